@@ -1,0 +1,157 @@
+"""Throughput benchmark of the PM-COLA time step on one MI355X.
+
+Workload (the single-box configuration): 256^3 particles, 768^3 mesh, 1000 Mpc/h box, 2LPT initial conditions at
+z = 9 from a seeded BBKS Gaussian field (generated on the GPU by lpc_init_ic, untimed), modified COLA stepping with
+nLPT = -2.5, CIC window deconvolved once.
+
+A "step" is one COLA time step: drift + full PM force (deposit, r2c FFT, Poisson/gradient, 3 c2r, gather) + kick.
+The timed region is ONE lpc_cola_step call over K + 1 scale factors spaced uniformly from a = 0.1 to 1.0: the opening
+force and half kick, K drift/force/kick iterations and the frame-velocity conversions (K + 1 force evaluations in
+all). value = N^3 * K / wall time (particle-steps/s), inputs resident in HBM before the clock starts.
+
+Also reported: the dominant kernel's achieved HBM bandwidth from HIP events recorded on the call's stream
+(roofline), and the FP64 CPU oracle's rate on a bounded sample (cpu_baseline).
+
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--workload single|small|large] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (COLA PM step), plain vs batched/learned at P(k) err <2%"
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes(stage, n_part, nm, ncomp_y=3):
+    """Algorithmic HBM bytes of one launch of each force-path stage (FP32 mesh, int64 density, SoA particles).
+
+    Half spectra are counted at nm * nm * (nm/2 + 1) complex values (8 B each)."""
+    M = nm**3
+    H = nm * nm * (nm // 2 + 1) * 8        # bytes of one half-spectrum complex mesh
+    corners = min(M, 8 * n_part)
+    return {
+        "fill density": 8 * M,
+        "deposit": 12 * n_part + 8 * M,     # read positions, the int64 mesh written once
+        "fft z r2c": 8 * M + H,             # read int64 density, write half spectrum
+        "fft y": 2 * H,
+        "fft x + poisson": H + 3 * H,       # read delta_hat, write three gradient spectra
+        "fft y inv": 2 * 3 * H,
+        "fft z c2r": 3 * H + 12 * M,        # read three spectra, write the AoS float3 force mesh
+        "gather kick drift": 72 * n_part + 12 * corners,
+        "frame velocity": 36 * n_part,
+    }.get(stage)
+
+
+def cpu_baseline_sample():
+    """The FP64 oracle, untuned, on one COLA step of the single-box workload at 1/8 of its volume: 128^3 particles,
+    384^3 mesh, 500 Mpc/h (same Nm/N = 3 and particle density). Returns particle-steps/s for that sample."""
+    import numpy as np
+
+    import synth
+    from oracle import cola as ocola
+    from oracle import ic as oic
+    n_side, nm, box = 128, 384, 500.0
+    init = oic.initial_conditions(7, n_side, box, 0.1, **synth.COSMOLOGY)
+    t0 = time.perf_counter()
+    ocola.cola_run(init["pos"], init["vel"], init["psi1"], init["psi2"], [0.1, 0.19], synth.COSMOLOGY["omega_m"],
+                   nm, box)
+    dt = time.perf_counter() - t0
+    # the run above is 1 drift and 2 force evaluations; count it as one step at the cost of (2 forces + 1 drift)
+    return {"value": n_side**3 / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one COLA step (2 force evaluations + 1 drift) of the FP64 NumPy oracle, 128^3 particles, "
+                      f"384^3 mesh, 500 Mpc/h (single-box workload at 1/8 volume), {dt:.1f} s, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="single", choices=["single", "small", "large"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path has no multi-GPU form (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1506_03737_amd import lpc
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = synth.WORKLOADS[args.workload]
+    n_side, nm, box = w["n_side"], w["n_mesh"], w["box"]
+    n = n_side**3
+    dev = torch.device("cuda:0")
+    geom = lpc.geometry(n_side, nm, box)
+    cosmo = lpc.cosmology(**synth.COSMOLOGY)
+    step = lpc.stepping(**synth.STEPPING)
+
+    ic = lpc.ParticleSet.empty(n, dev)
+    ws_ic = lpc.workspace(geom, lpc.LPC_OP_INIT_IC, dev)
+    lpc.lpc_init_ic(geom, cosmo, w["seed"], 0.1, ic, ws_ic)
+    del ws_ic
+    ps = lpc.ParticleSet.empty(n, dev)
+    ws = lpc.workspace(geom, lpc.LPC_OP_COLA_STEP, dev)
+
+    def reset():
+        for k in ("pos", "vel", "psi1", "psi2", "id"):
+            getattr(ps, k).copy_(getattr(ic, k))
+
+    if args.warmup > 0:
+        reset()
+        lpc.lpc_cola_step(geom, cosmo, step, np.linspace(0.1, 1.0, args.warmup + 1), ps, ws)
+    reset()
+    a_list = np.linspace(0.1, 1.0, args.steps + 1)
+    lpc.lpc_profile_reset()
+    lpc.lpc_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lpc.lpc_cola_step(geom, cosmo, step, a_list, ps, ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lpc.lpc_profile_enable(False)
+    stats = lpc.lpc_profile_stats()
+
+    value = n * args.steps / dt
+    stages = {}
+    for name, (launches, ms) in stats.items():
+        b = stage_bytes(name, n, nm)
+        avg = ms / launches
+        entry = {"launches": launches, "avg_ms": round(avg, 4), "share": round(ms / (dt * 1e3), 4)}
+        if b is not None:
+            entry["GB_per_s"] = round(b / (avg * 1e-3) / 1e9, 1)
+        stages[name] = entry
+    dom = max((k for k in stats if stage_bytes(k, n, nm) is not None), key=lambda k: stats[k][1])
+    dl, dms = stats[dom]
+    dbytes = stage_bytes(dom, n, nm)
+    achieved = dbytes / (dms / dl * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": dbytes}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n_side}^3 particles, {nm}^3 mesh, {box:g} Mpc/h, 2LPT ICs at z=9, "
+                               f"modified COLA nLPT=-2.5, plain form", "n_side": n_side, "n_mesh": nm, "box": box,
+                   "form": "plain", "force_evaluations": args.steps + 1},
+        "roofline": roofline,
+        "stages": stages,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_sample()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * lpc.h -- C ABI of liblpc.so: the particle-mesh COLA time step of L-PICOLA (Howlett, Manera & Percival 2015)
+ * on one AMD MI355X (gfx950).
+ *
+ * The problem statement follows Sec. 3 of the paper: N^3 particles, an Nm^3 mesh, a periodic box of side L (Mpc/h),
+ * a flat cosmology and a list of output times. Everything on the hot path runs in hand-written HIP kernels.
+ *
+ * Conventions shared by every call
+ *  - Units: lengths in Mpc/h, time is the scale factor a, H0 = 1. Momenta are p = a^2 dx/dt / H0 in Mpc/h
+ *    (peculiar velocity in km/s is 100 p / a).
+ *  - Particles are structure-of-arrays in device memory, each vector field as [3][n] floats
+ *    (x components, then y, then z). Particle order is preserved by every call; `id` is the lattice index.
+ *  - Meshes: node i of an axis sits at i L / Nm. Mesh sizes must factor into 2, 3 and 5, be even, and lie in
+ *    [8, 1024]. The initial-condition lattice side N obeys the same rule (its transforms use the same FFT).
+ *  - Memory: all device buffers (particles, outputs, workspace) are owned by the caller. The library allocates
+ *    no device memory. `ws` is a device buffer of at least lpc_workspace_bytes(geometry, op) bytes, 256-byte
+ *    aligned; its contents are scratch and may be overwritten.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream). Every call enqueues its work
+ *    on that stream and then waits for it once, to read back the device error flags; on return the outputs are
+ *    complete.
+ *  - Errors: every call returns an lpc_status; no C++ exception crosses this boundary. lpc_last_error() gives a
+ *    human-readable detail of the last failure on the calling thread. On an argument error nothing is enqueued.
+ *  - Concurrency: calls that share a workspace must not overlap.
+ */
+#ifndef LPC_H
+#define LPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LPC_OK = 0,
+  LPC_ERR_INVALID_ARG = -1,      /* null pointer, non-positive size, unordered time list, ... */
+  LPC_ERR_UNSUPPORTED_SIZE = -2, /* mesh or lattice size outside what the FFT supports */
+  LPC_ERR_WORKSPACE = -3,        /* workspace too small or misaligned */
+  LPC_ERR_HIP = -4,              /* a HIP runtime call failed (detail in lpc_last_error) */
+  LPC_ERR_FIXED_OVERFLOW = -5,   /* a density cell exceeded the 64-bit fixed-point headroom (>= 2^63) */
+  LPC_ERR_NONFINITE = -6         /* a particle coordinate was NaN/Inf or absurdly far outside the box */
+} lpc_status;
+
+/* Flat LCDM cosmology: Omega_Lambda = 1 - omega_m. The linear spectrum is A k^n_s T_BBKS(k)^2 with shape
+ * parameter Gamma = omega_m h, normalised to sigma8 (top-hat, 8 Mpc/h). */
+typedef struct {
+  double omega_m;
+  double h;
+  double sigma8;
+  double n_s;
+} lpc_cosmology;
+
+/* N = n_side particles per side (lattice), Nm = n_mesh cells per side, L = box in Mpc/h. */
+typedef struct {
+  int32_t n_side;
+  int32_t n_mesh;
+  double box;
+} lpc_geometry;
+
+/* Time stepping (Sec. 2.3). cola: 1 = integrate in the 2LPT frame (Eqs. 17-18), 0 = plain PM (Eqs. 14-15).
+ * modified: 1 = the modified kick/drift factors with nLPT (Eq. 19), 0 = the Quinn et al. factors (Eq. 16).
+ * deconv_power: divide the force spectrum by the CIC window this many times (0, 1 or 2); default 1. */
+typedef struct {
+  int32_t cola;
+  int32_t modified;
+  double n_lpt;
+  int32_t deconv_power;
+  int32_t reserved; /* must be 0 */
+} lpc_stepping;
+
+/* Device structure-of-arrays particle set: pos, vel, psi1, psi2 are float[3][n]; id is int32[n]. */
+typedef struct {
+  float* pos;
+  float* vel;
+  float* psi1;
+  float* psi2;
+  int32_t* id;
+  int64_t n;
+} lpc_particles;
+
+/* Operation codes for lpc_workspace_bytes. */
+enum {
+  LPC_OP_INIT_IC = 1,
+  LPC_OP_PM_FORCE = 2,
+  LPC_OP_COLA_STEP = 3,
+  LPC_OP_POWER_SPECTRUM = 4,
+  LPC_OP_FFT = 5
+};
+
+/* Number of columns of the per-time coefficient table written by lpc_cola_coefficients. */
+#define LPC_COEF_COLUMNS 12
+
+/* Workspace bytes needed by operation `op` for this geometry (0 on an invalid geometry or op). */
+size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op);
+
+/* 2LPT initial conditions at scale factor a_init (Sec. 2.1 Eqs. 5-10; Sec. 5).
+ * Draws a unit Gaussian per lattice point from SplitMix64 (Steele, Lea & Flood 2014) in counter mode:
+ *   u(c) = ((mix(seed + (c + 1) * 0x9E3779B97F4A7C15) >> 11) + 0.5) 2^-53,
+ *   noise(idx) = sqrt(-2 ln u(2 idx)) cos(2 pi u(2 idx + 1)), idx = (i N + j) N + l,
+ * scales its Fourier modes by sqrt(P(k) N^3 / L^3) (modes at k = 0 or on a Nyquist plane are zeroed), and solves
+ * lap(phi1) = delta_L, lap(phi2) = sum_{i>j} (phi1_ii phi1_jj - phi1_ij^2) spectrally. Outputs (all [3][n], n = N^3):
+ *   psi1 = -grad phi1, psi2 = grad phi2 (z = 0 displacements, D1(1) = 1),
+ *   pos  = q + D1(a) psi1 + D2(a) psi2 wrapped into [0, L), q = (i + 1/2, j + 1/2, l + 1/2) L / N,
+ *   vel  = a^3 E(a) (D1'(a) psi1 + D2'(a) psi2), id = idx.
+ * `out->n` must equal N^3. D2 is the Bouchet approximation of Eq. 7. */
+lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
+                       const lpc_particles* out, void* ws, size_t ws_bytes, void* stream);
+
+/* The particle-mesh force of Sec. 2.4 (Eqs. 20-21) at positions pos[3][n]:
+ *   fixed-point CIC deposit (16 fractional bits per axis, int64 counts, each particle adds exactly 2^48),
+ *   delta = C (Nm^3 / n) 2^-48 - 1, forward r2c FFT, g_hat_j = i k_j (-1/k^2) delta_hat / W^p
+ *   (W = prod sinc^2(pi n_d / Nm), p = step->deconv_power, zero at k = 0 and on the Nyquist plane of axis j),
+ *   three c2r FFTs, CIC gather with the deposit's own fixed-point fractions.
+ * grad_out[3][n] receives grad(psi) with lap(psi) = delta (Mpc/h). density_fixed_out, if not NULL, receives the
+ * int64 counts C[Nm][Nm][Nm] (x-major). Only step->deconv_power is read from `step`. geom->n_side is not used. */
+lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, const float* pos, int64_t n,
+                        float* grad_out, int64_t* density_fixed_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Advance particles from a_list[0] to a_list[n_a - 1] with the kick-drift-kick COLA integrator (Sec. 2.3):
+ * frame momentum removed at a_0 (Sec. 2.3), then for i = 0..n_a-1: force at a_i, kick a_{i-1/2} -> a_{i+1/2}
+ * (midpoints; a_{-1/2} = a_0, a_{N+1/2} = a_N), drift a_i -> a_{i+1} for i < n_a - 1; frame momentum added back at
+ * the last time. inout->vel holds the Eulerian momentum at a_list[0] on entry and at a_list[n_a-1] on exit.
+ * a_list is a host array, strictly increasing, positive, n_a >= 2. With cola = 0, psi1 and psi2 are not read. */
+lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, const lpc_stepping* step,
+                         const double* a_list, int32_t n_a, const lpc_particles* inout, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Binned power spectrum of the particles (periodic box; Sec. 7.1): fixed-point CIC deposit on the Nm mesh,
+ * r2c FFT, P = L^3 |delta_hat|^2 / (Nm^6 W^2) (one CIC window removed in amplitude), bins [b dk, (b+1) dk) of |k|
+ * with dk = k_max / n_bins, the k = 0 mode excluded, half-spectrum modes with 0 < n_z < Nm/2 counted twice.
+ * No shot-noise subtraction. k_mean, pk (double) and n_modes (int64) are HOST arrays of n_bins; empty bins give
+ * NaN for k_mean and pk. */
+lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_t n, double k_max, int32_t n_bins,
+                              double* k_mean, double* pk, int64_t* n_modes, void* ws, size_t ws_bytes, void* stream);
+
+/* The FP64 per-time coefficient table of one lpc_cola_step call (host only; for checking and inspection).
+ * out[n_a][LPC_COEF_COLUMNS] row i: a_i, D1, D2, dD1/da, dD2/da, E, K_i (kick factor), Q_i (drift factor, 0 in the
+ * last row), D1(a_{i+1}) - D1(a_i), D2(a_{i+1}) - D2(a_i) (0 in the last row), a^3 E D1', a^3 E D2'. */
+lpc_status lpc_cola_coefficients(const lpc_cosmology* cosmo, const lpc_stepping* step, const double* a_list,
+                                 int32_t n_a, double* out);
+
+/* Linear P(k) of the cosmology at host wavenumbers k[m] (h/Mpc) into host pk[m] (host only). */
+lpc_status lpc_linear_power(const lpc_cosmology* cosmo, const double* k, int32_t m, double* pk);
+
+/* Unnormalised forward r2c 3-D FFT of a real n^3 device mesh (x-major) into a complex half spectrum with
+ * row pitch lpc_fft_pitch(n) complex values: out[(kx * n + ky) * pitch + kz], kz = 0..n/2.
+ * X(k) = sum_x f(x) exp(-2 pi i k.x / n). (The same kernels as the force path; exposed for testing.) */
+lpc_status lpc_fft_r2c(int32_t n, const float* in, float* out_complex, void* ws, size_t ws_bytes, void* stream);
+
+/* Unnormalised inverse c2r 3-D FFT: f(x) = sum_k X(k) exp(+2 pi i k.x / n) over the Hermitian-completed spectrum.
+ * `in_complex` (pitch lpc_fft_pitch(n)) is overwritten. */
+lpc_status lpc_fft_c2r(int32_t n, float* in_complex, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Row pitch, in complex values, of the half-spectrum layout used by lpc_fft_r2c / lpc_fft_c2r. */
+int32_t lpc_fft_pitch(int32_t n);
+
+/* Per-stage profiling (measurement plumbing, not part of the method). When enabled, every kernel
+ * launch of the entry points above is bracketed by HIP events on the call's stream; the durations are read after the
+ * call's final synchronisation and accumulated per stage name ("deposit", "fft y inv", ...). Process-wide state,
+ * not thread safe. lpc_profile_get returns stage i's name (valid until lpc_profile_reset), its launch count and its
+ * total milliseconds. */
+lpc_status lpc_profile_enable(int32_t on);
+lpc_status lpc_profile_reset(void);
+int32_t lpc_profile_count(void);
+lpc_status lpc_profile_get(int32_t i, const char** name, int64_t* launches, double* total_ms);
+
+const char* lpc_status_string(lpc_status s);
+const char* lpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPC_H */

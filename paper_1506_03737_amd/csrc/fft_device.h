@@ -1,0 +1,196 @@
+// Device-side building blocks of liblpc's FFTs: complex helpers, radix-2/3/4/5/8 butterflies, one Stockham
+// autosort stage over an LDS tile, and the XCD-aware workgroup remap. Included by the .hip sources only.
+//
+// An LDS tile holds B = 2^lgB independent columns of one transform length n: element (j, b) at tile[j * BP + b]
+// (BP >= B is the padded column pitch; n * B <= kTileElems). Stage s with radix R and current sub-transform length p (product of the
+// earlier radices) reads x[i + r T] (T = n / R), multiplies by w^(r k) with w = exp(-+ 2 pi i / (p R)),
+// k = i mod p, takes the length-R DFT and writes it to ((i - k) R + k + r p): the Stockham autosort ordering,
+// so after the last stage the tile is in natural order. Each thread stages its butterflies in registers between two
+// barriers, which makes the update in place.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lpc_kernels.h"
+
+namespace lpc {
+namespace kern {
+
+constexpr int kEPT = kTileElems / kFftNT;  // complex values per thread per stage (16)
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    float2 t2 = cadd(v[1], v[3]), t3 = rot<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <bool INV>
+struct Dft<8, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, INV>::run(e);
+    Dft<4, INV>::run(o);
+    const float h = 0.70710678118654752f;
+    float2 o1 = cscale(cadd(o[1], rot<INV>(o[1])), h);   // w8^1 o1
+    float2 o2 = rot<INV>(o[2]);                           // w8^2 o2
+    float2 o3 = cscale(csub(rot<INV>(o[3]), o[3]), h);   // w8^3 o3
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    const float s3 = 0.86602540378443865f;
+    float2 t = cadd(v[1], v[2]);
+    float2 u = cscale(rot<INV>(csub(v[1], v[2])), s3);
+    float2 m = csub(v[0], cscale(t, 0.5f));
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(m, u);
+    v[2] = csub(m, u);
+  }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+    const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+    float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    float2 m1 = make_float2(v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y);
+    float2 m2 = make_float2(v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y);
+    float2 n1 = rot<INV>(make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+    float2 n2 = rot<INV>(make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(m1, n1);
+    v[4] = csub(m1, n1);
+    v[2] = cadd(m2, n2);
+    v[3] = csub(m2, n2);
+  }
+};
+
+// One Stockham stage over the tile (see the file comment). The tile has B = 2^lgB columns; thread t owns column
+// t mod B and butterflies i = t / B + m (kFftNT / B). tw holds exp(-2 pi i m / (n * tmul)) for m < n * tmul.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_stage(float2* tile, int BP, const float2* tw, int tmul, int n, int lgB, int p,
+                                          int tid) {
+  constexpr int MB = (kEPT + R - 1) / R;
+  const int T = n / R;
+  const int b = tid & ((1 << lgB) - 1);
+  const int i0 = tid >> lgB;
+  const int S = kFftNT >> lgB;
+  const int stride = (n / (p * R)) * tmul;
+  float2 v[MB][R];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      const float2* src = tile + i * BP + b;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[m][r] = src[r * T * BP];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      const int k = i % p;
+      if (p > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 t = tw[r * k * stride];
+          v[m][r] = INV ? cmulc(v[m][r], t) : cmul(v[m][r], t);
+        }
+      }
+      Dft<R, INV>::run(v[m]);
+      float2* dst = tile + ((i - k) * R + k) * BP + b;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * p * BP] = v[m][r];
+    }
+  }
+  __syncthreads();
+}
+
+// All stages of plan `pl` over the 2^lgB columns of the tile. The caller has synchronised after filling the tile.
+template <bool INV>
+__device__ void fft_tile(float2* tile, int BP, const float2* tw, int tmul, const Plan1D& pl, int lgB, int tid) {
+  const int n = pl.n;
+  int p = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.radix[s];
+    switch (R) {
+      case 8: fft_stage<8, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
+      case 4: fft_stage<4, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
+      case 2: fft_stage<2, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
+      case 3: fft_stage<3, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
+      default: fft_stage<5, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
+    }
+    p *= R;
+  }
+}
+
+// tw[m] = exp(-2 pi i m / len), m < len, rounded from FP64 (no barrier: the caller synchronises).
+__device__ __forceinline__ void fill_twiddles(float2* tw, int len, int tid) {
+  for (int m = tid; m < len; m += kFftNT) {
+    double s, c;
+    sincospi(-2.0 * m / len, &s, &c);
+    tw[m] = make_float2(static_cast<float>(c), static_cast<float>(s));
+  }
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Remap the hardware block index so
+// that each XCD receives a contiguous range of logical tiles: neighbouring tiles (which share cache lines at their
+// edges) then run on the same XCD.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int per = nblocks / 8, rem = nblocks % 8;
+  const int xcd = bid % 8, local = bid / 8;
+  return xcd * per + min(xcd, rem) + local;
+}
+
+}  // namespace kern
+}  // namespace lpc

@@ -1,0 +1,29 @@
+// Internal host-side declarations of liblpc (not part of the C ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lpc {
+namespace host {
+
+struct Cosmo {
+  double omega_m, h, sigma8, n_s;
+};
+
+// Column indices of the per-time coefficient table (same order as the ABI documents).
+enum { kA = 0, kD1, kD2, kdD1, kdD2, kE, kK, kQ, kDD1, kDD2, kF1, kF2, kCoefColumns };
+
+double hubble_E(const Cosmo& c, double a);
+double growth_D1(const Cosmo& c, double a);
+double growth_dD1(const Cosmo& c, double a);
+double growth_D2(const Cosmo& c, double a);
+double growth_dD2(const Cosmo& c, double a);
+double kick_factor(const Cosmo& c, double a_lo, double a_i, double a_hi, bool modified, double n_lpt);
+double drift_factor(const Cosmo& c, double a_i, double a_ip1, bool modified, double n_lpt);
+void coefficient_table(const Cosmo& c, bool modified, double n_lpt, const double* a, int n, double* out);
+double pk_amplitude(const Cosmo& c);
+double linear_pk(const Cosmo& c, double amplitude, double k);
+
+}  // namespace host
+}  // namespace lpc

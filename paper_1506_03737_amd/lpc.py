@@ -1,0 +1,235 @@
+"""Thin ctypes binding of liblpc.so (the C ABI in include/lpc.h).
+
+Argument marshalling only: every step of the method runs in liblpc's HIP kernels. PyTorch supplies device memory
+and the current stream. The functions keep the C names (lpc_init_ic, lpc_pm_force, lpc_cola_step,
+lpc_power_spectrum, ...). If liblpc.so is missing the import of this module fails loudly; there is no fallback.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblpc.so")
+
+LPC_OP_INIT_IC = 1
+LPC_OP_PM_FORCE = 2
+LPC_OP_COLA_STEP = 3
+LPC_OP_POWER_SPECTRUM = 4
+LPC_OP_FFT = 5
+COEF_COLUMNS = ("a", "D1", "D2", "dD1", "dD2", "E", "K", "Q", "dDD1", "dDD2", "f1", "f2")
+
+STATUS = {0: "LPC_OK", -1: "LPC_ERR_INVALID_ARG", -2: "LPC_ERR_UNSUPPORTED_SIZE", -3: "LPC_ERR_WORKSPACE",
+          -4: "LPC_ERR_HIP", -5: "LPC_ERR_FIXED_OVERFLOW", -6: "LPC_ERR_NONFINITE"}
+
+
+class LpcError(RuntimeError):
+    def __init__(self, status, detail):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_side", ctypes.c_int32), ("n_mesh", ctypes.c_int32), ("box", ctypes.c_double)]
+
+
+class Cosmology(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double), ("h", ctypes.c_double), ("sigma8", ctypes.c_double),
+                ("n_s", ctypes.c_double)]
+
+
+class Stepping(ctypes.Structure):
+    _fields_ = [("cola", ctypes.c_int32), ("modified", ctypes.c_int32), ("n_lpt", ctypes.c_double),
+                ("deconv_power", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Particles(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("psi1", ctypes.c_void_p),
+                ("psi2", ctypes.c_void_p), ("id", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"liblpc.so not found at {LIB_PATH}: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "lpc_workspace_bytes": (sz, [P(Geometry), i32]),
+        "lpc_init_ic": (i32, [P(Geometry), P(Cosmology), ctypes.c_uint64, dbl, P(Particles), vp, sz, vp]),
+        "lpc_pm_force": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp, sz, vp]),
+        "lpc_cola_step": (i32, [P(Geometry), P(Cosmology), P(Stepping), P(dbl), i32, P(Particles), vp, sz, vp]),
+        "lpc_power_spectrum": (i32, [P(Geometry), vp, i64, dbl, i32, P(dbl), P(dbl), P(i64), vp, sz, vp]),
+        "lpc_cola_coefficients": (i32, [P(Cosmology), P(Stepping), P(dbl), i32, P(dbl)]),
+        "lpc_linear_power": (i32, [P(Cosmology), P(dbl), i32, P(dbl)]),
+        "lpc_fft_r2c": (i32, [i32, vp, vp, vp, sz, vp]),
+        "lpc_fft_c2r": (i32, [i32, vp, vp, vp, sz, vp]),
+        "lpc_fft_pitch": (i32, [i32]),
+        "lpc_profile_enable": (i32, [i32]),
+        "lpc_profile_reset": (i32, []),
+        "lpc_profile_count": (i32, []),
+        "lpc_profile_get": (i32, [i32, P(ctypes.c_char_p), P(i64), P(dbl)]),
+        "lpc_status_string": (ctypes.c_char_p, [i32]),
+        "lpc_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_cola_step", "lpc_power_spectrum",
+            "lpc_cola_coefficients", "lpc_linear_power", "lpc_fft_r2c", "lpc_fft_c2r", "lpc_fft_pitch",
+            "lpc_profile_enable", "lpc_profile_reset", "lpc_profile_count", "lpc_profile_get",
+            "lpc_status_string", "lpc_last_error")
+
+
+def _check(status):
+    if status != 0:
+        raise LpcError(status, LIB.lpc_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def geometry(n_side, n_mesh, box):
+    return Geometry(int(n_side), int(n_mesh), float(box))
+
+
+def cosmology(omega_m=0.31, h=0.68, sigma8=0.8, n_s=0.96):
+    return Cosmology(omega_m, h, sigma8, n_s)
+
+
+def stepping(cola=1, modified=1, n_lpt=-2.5, deconv_power=1):
+    return Stepping(int(cola), int(modified), float(n_lpt), int(deconv_power), 0)
+
+
+def lpc_workspace_bytes(geom, op):
+    return int(LIB.lpc_workspace_bytes(ctypes.byref(geom), int(op)))
+
+
+def workspace(geom, op, device="cuda"):
+    """A caller-owned workspace tensor (uint8) for operation `op`."""
+    import torch
+    nbytes = lpc_workspace_bytes(geom, op)
+    if nbytes == 0:
+        raise LpcError(-2, f"unsupported geometry {geom.n_side}/{geom.n_mesh} for op {op}")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+class ParticleSet:
+    """Device SoA particles: pos/vel/psi1/psi2 float32 [3, n], id int32 [n] (torch tensors)."""
+
+    def __init__(self, pos, vel, psi1=None, psi2=None, id=None):
+        self.pos, self.vel, self.psi1, self.psi2, self.id = pos, vel, psi1, psi2, id
+
+    @classmethod
+    def empty(cls, n, device="cuda"):
+        import torch
+        f = lambda: torch.empty((3, n), dtype=torch.float32, device=device)
+        return cls(f(), f(), f(), f(), torch.empty(n, dtype=torch.int32, device=device))
+
+    @property
+    def n(self):
+        return int(self.pos.shape[1])
+
+    def c_struct(self):
+        for t in (self.pos, self.vel, self.psi1, self.psi2):
+            if t is not None and not t.is_contiguous():
+                raise ValueError("particle arrays must be contiguous")
+        return Particles(_ptr(self.pos), _ptr(self.vel), _ptr(self.psi1), _ptr(self.psi2), _ptr(self.id), self.n)
+
+
+def lpc_init_ic(geom, cosmo, seed, a_init, particles, ws, stream=None):
+    p = particles.c_struct()
+    _check(LIB.lpc_init_ic(ctypes.byref(geom), ctypes.byref(cosmo), ctypes.c_uint64(seed), float(a_init),
+                           ctypes.byref(p), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def lpc_pm_force(geom, step, pos, grad_out, ws, density_out=None, stream=None):
+    _check(LIB.lpc_pm_force(ctypes.byref(geom), ctypes.byref(step), _ptr(pos), int(pos.shape[1]), _ptr(grad_out),
+                            _ptr(density_out), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def lpc_cola_step(geom, cosmo, step, a_list, particles, ws, stream=None):
+    a = np.ascontiguousarray(a_list, dtype=np.float64)
+    p = particles.c_struct()
+    _check(LIB.lpc_cola_step(ctypes.byref(geom), ctypes.byref(cosmo), ctypes.byref(step),
+                             a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(a.size), ctypes.byref(p),
+                             _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def lpc_power_spectrum(geom, pos, k_max, n_bins, ws, stream=None):
+    k = np.empty(n_bins, dtype=np.float64)
+    pk = np.empty(n_bins, dtype=np.float64)
+    cnt = np.empty(n_bins, dtype=np.int64)
+    D = ctypes.POINTER(ctypes.c_double)
+    _check(LIB.lpc_power_spectrum(ctypes.byref(geom), _ptr(pos), int(pos.shape[1]), float(k_max), int(n_bins),
+                                  k.ctypes.data_as(D), pk.ctypes.data_as(D),
+                                  cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return k, pk, cnt
+
+
+def lpc_cola_coefficients(cosmo, step, a_list):
+    a = np.ascontiguousarray(a_list, dtype=np.float64)
+    out = np.empty((a.size, len(COEF_COLUMNS)), dtype=np.float64)
+    D = ctypes.POINTER(ctypes.c_double)
+    _check(LIB.lpc_cola_coefficients(ctypes.byref(cosmo), ctypes.byref(step), a.ctypes.data_as(D), int(a.size),
+                                     out.ctypes.data_as(D)))
+    return out
+
+
+def lpc_linear_power(cosmo, k):
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    out = np.empty_like(k)
+    D = ctypes.POINTER(ctypes.c_double)
+    _check(LIB.lpc_linear_power(ctypes.byref(cosmo), k.ctypes.data_as(D), int(k.size), out.ctypes.data_as(D)))
+    return out
+
+
+def lpc_fft_pitch(n):
+    return int(LIB.lpc_fft_pitch(int(n)))
+
+
+def lpc_fft_r2c(n, real_in, complex_out, ws, stream=None):
+    _check(LIB.lpc_fft_r2c(int(n), _ptr(real_in), _ptr(complex_out), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def lpc_fft_c2r(n, complex_in, real_out, ws, stream=None):
+    _check(LIB.lpc_fft_c2r(int(n), _ptr(complex_in), _ptr(real_out), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def lpc_status_string(status):
+    return LIB.lpc_status_string(int(status)).decode()
+
+
+def lpc_profile_enable(on=True):
+    _check(LIB.lpc_profile_enable(1 if on else 0))
+
+
+def lpc_profile_reset():
+    _check(LIB.lpc_profile_reset())
+
+
+def lpc_profile_stats():
+    """{stage name: (launches, total_ms)} accumulated since the last reset."""
+    out = {}
+    for i in range(LIB.lpc_profile_count()):
+        name = ctypes.c_char_p()
+        launches = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(LIB.lpc_profile_get(i, ctypes.byref(name), ctypes.byref(launches), ctypes.byref(ms)))
+        out[name.value.decode()] = (int(launches.value), float(ms.value))
+    return out

@@ -1,0 +1,115 @@
+"""CPU-only checks of the C ABI: the library loads, exports every symbol include/lpc.h declares, host-only entry
+points agree with the oracle, and argument errors come back as status codes (no GPU call is made)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cosmology as ocosmo
+from oracle import ic as oic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpc.h")
+LIBFILE = os.path.join(ROOT, "paper_1506_03737_amd", "liblpc.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIBFILE), reason="liblpc.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(lpc_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIBFILE)
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header():
+    from paper_1506_03737_amd import lpc
+    assert set(declared_functions()) == set(lpc.EXPORTED)
+
+
+@pytest.mark.parametrize("modified", [0, 1])
+def test_coefficients_match_oracle(modified):
+    from paper_1506_03737_amd import lpc
+    c = synth.COSMOLOGY
+    step = lpc.stepping(modified=modified)
+    got = lpc.lpc_cola_coefficients(lpc.cosmology(**c), step, synth.A_LIST)
+    ref = ocosmo.coefficient_table(synth.A_LIST, c["omega_m"], bool(modified), -2.5)
+    assert got.shape == ref.shape
+    assert np.allclose(got, ref, rtol=1e-11, atol=1e-14)
+
+
+def test_coefficients_eds_closed_form():
+    from paper_1506_03737_amd import lpc
+    got = lpc.lpc_cola_coefficients(lpc.cosmology(omega_m=1.0), lpc.stepping(modified=0), [0.25, 0.5, 1.0])
+    assert got[0, 7] == pytest.approx(2 * (0.25**-0.5 - 0.5**-0.5), rel=1e-13)       # Q
+    assert got[1, 6] == pytest.approx(2 * (0.75**0.5 - 0.375**0.5), rel=1e-13)      # K
+    assert got[2, 1] == pytest.approx(1.0, rel=1e-13)                               # D1(1)
+
+
+def test_linear_power_matches_oracle():
+    from paper_1506_03737_amd import lpc
+    c = synth.COSMOLOGY
+    k = np.logspace(-3, 1, 40)
+    got = lpc.lpc_linear_power(lpc.cosmology(**c), k)
+    ref = oic.linear_pk(k, **c)
+    assert np.allclose(got, ref, rtol=1e-9)
+
+
+def test_workspace_sizes_and_rejections():
+    from paper_1506_03737_amd import lpc
+    g = lpc.geometry(32, 64, 256.0)
+    assert lpc.lpc_workspace_bytes(g, lpc.LPC_OP_COLA_STEP) > 64**3 * 12
+    assert lpc.lpc_workspace_bytes(g, 99) == 0
+    assert lpc.lpc_workspace_bytes(lpc.geometry(32, 14, 256.0), lpc.LPC_OP_PM_FORCE) == 0   # 7 is not 2/3/5-smooth
+    assert lpc.lpc_workspace_bytes(lpc.geometry(32, 2048, 256.0), lpc.LPC_OP_PM_FORCE) == 0
+    assert lpc.lpc_fft_pitch(768) == 392 and lpc.lpc_fft_pitch(64) == 40
+
+
+def test_argument_errors_are_status_codes():
+    from paper_1506_03737_amd import lpc
+    c = lpc.cosmology()
+    with pytest.raises(lpc.LpcError) as e:
+        lpc.lpc_cola_coefficients(c, lpc.stepping(), [0.5, 0.4])
+    assert e.value.status == -1 and "increasing" in str(e.value)
+    with pytest.raises(lpc.LpcError) as e:
+        lpc.lpc_cola_coefficients(lpc.cosmology(omega_m=-1.0), lpc.stepping(), [0.1, 0.2])
+    assert e.value.status == -1
+    # unsupported mesh: rejected before any device work
+    lib = lpc.LIB
+    g = lpc.geometry(32, 14, 256.0)
+    st = lib.lpc_pm_force(ctypes.byref(g), ctypes.byref(lpc.stepping()), ctypes.c_void_p(8), 10,
+                          ctypes.c_void_p(8), None, ctypes.c_void_p(256), 1 << 20, None)
+    assert st == -2
+    # workspace too small / misaligned
+    g = lpc.geometry(32, 64, 256.0)
+    st = lib.lpc_pm_force(ctypes.byref(g), ctypes.byref(lpc.stepping()), ctypes.c_void_p(8), 10,
+                          ctypes.c_void_p(8), None, ctypes.c_void_p(256), 1024, None)
+    assert st == -3
+    st = lib.lpc_pm_force(ctypes.byref(g), ctypes.byref(lpc.stepping()), ctypes.c_void_p(8), 10,
+                          ctypes.c_void_p(8), None, ctypes.c_void_p(100), 1 << 30, None)
+    assert st == -3
+    # deconvolution power out of range, n = 0, NULL positions
+    st = lib.lpc_pm_force(ctypes.byref(g), ctypes.byref(lpc.stepping(deconv_power=3)), ctypes.c_void_p(8), 10,
+                          ctypes.c_void_p(8), None, ctypes.c_void_p(256), 1 << 30, None)
+    assert st == -1
+    st = lib.lpc_pm_force(ctypes.byref(g), ctypes.byref(lpc.stepping()), ctypes.c_void_p(8), 0,
+                          ctypes.c_void_p(8), None, ctypes.c_void_p(256), 1 << 30, None)
+    assert st == -1
+    st = lib.lpc_pm_force(ctypes.byref(g), ctypes.byref(lpc.stepping()), None, 10,
+                          ctypes.c_void_p(8), None, ctypes.c_void_p(256), 1 << 30, None)
+    assert st == -1
+    assert lpc.lpc_status_string(-5) == "LPC_ERR_FIXED_OVERFLOW"
+    # init_ic with mismatched particle count
+    p = lpc.Particles(8, 8, 8, 8, 8, 100)
+    st = lib.lpc_init_ic(ctypes.byref(g), ctypes.byref(c), 1, 0.1, ctypes.byref(p), ctypes.c_void_p(256), 1 << 30,
+                         None)
+    assert st == -1 and b"n_side^3" in lib.lpc_last_error()
