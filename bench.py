@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single", choices=["single", "small", "large"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path has no multi-GPU form (run with --gpus 1)", file=sys.stderr)
@@ -94,6 +96,13 @@ def main():
     geom = lpc.geometry(n_side, nm, box)
     cosmo = lpc.cosmology(**synth.COSMOLOGY)
     step = lpc.stepping(**synth.STEPPING)
+
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ic = lpc.ParticleSet.empty(n, dev)
     ws_ic = lpc.workspace(geom, lpc.LPC_OP_INIT_IC, dev)

@@ -9,6 +9,7 @@
 // read once and never written back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "fft_device.h"
@@ -19,11 +20,11 @@ namespace kern {
 bool make_plan(int n, Plan1D* p) {
   if (n < 1) return false;
   int m = n, ns = 0;
-  int radix[kMaxStages];
+  int odd[kMaxStages];
   for (int r : {5, 3}) {
     while (m % r == 0) {
       if (ns >= kMaxStages) return false;
-      radix[ns++] = r;
+      odd[ns++] = r;
       m /= r;
     }
   }
@@ -33,28 +34,30 @@ bool make_plan(int n, Plan1D* p) {
     ++k;
   }
   if (m != 1) return false;
-  // powers of two: as many radix-8 stages as possible, the remainder as one radix-4 or radix-2 stage
-  // (two radix-4 stages instead of 8 x 2 keep the work per stage even).
-  int n8 = k / 3, rem = k % 3;
-  if (rem == 1 && n8 > 0) {  // 8 x 2 -> 4 x 4
-    --n8;
-    rem = 4;
-  }
+  // powers of two: radix-8 stages, the remainder as one radix-4 or radix-2 stage (8 x 2 becomes 4 x 4)
   int pow2[kMaxStages], np = 0;
+  int n8 = k / 3, rem = k % 3;
+  if (rem == 1 && n8 > 0) {
+    --n8;
+    pow2[np++] = 4;
+    pow2[np++] = 4;
+    rem = 0;
+  }
   for (int i = 0; i < n8; ++i) pow2[np++] = 8;
   if (rem == 1) pow2[np++] = 2;
   if (rem == 2) pow2[np++] = 4;
-  if (rem == 4) {
-    pow2[np++] = 4;
-    pow2[np++] = 4;
-  }
   if (ns + np > kMaxStages) return false;
   p->n = n;
   p->nst = 0;
   for (int i = 0; i < np; ++i) p->radix[p->nst++] = pow2[i];
-  for (int i = 0; i < ns; ++i) p->radix[p->nst++] = radix[i];
-  if (n == 1) {  // length-1 transform: no stage
-    p->nst = 0;
+  for (int i = 0; i < ns; ++i) p->radix[p->nst++] = odd[i];
+  int prod = 1, off = 0;
+  for (int s = 0; s < p->nst; ++s) {
+    p->p[s] = prod;
+    p->pmask[s] = ((prod & (prod - 1)) == 0) ? prod - 1 : -1;
+    p->tw_off[s] = off;
+    off += prod * (p->radix[s] - 1);
+    prod *= p->radix[s];
   }
   return true;
 }
@@ -69,254 +72,347 @@ void allow_big_lds(K kernel) {
                       160 * 1024);
 }
 
-// log2 of the columns per tile of a strided pass of length n: B = 2^lgB <= 32 with n * B <= kTileElems.
-int strided_lg_cols(int n) {
-  int lg = 0;
-  while (lg < 5 && (2 << lg) * n <= kTileElems) ++lg;
-  return lg;
-}
-
-// log2 of the rows per workgroup of a z pass (transform length h = n/2) with `groups` column groups per row.
-int z_lg_rows(int n, int groups) {
-  int lg = 0;
-  while (lg < 4 && groups * (2 << lg) * (n / 2) <= kTileElems) ++lg;
-  return lg;
-}
-
 // ---------------------------------------------------------------------------------------------------------------
-// z pass, forward r2c. A workgroup transforms B = 2^lgB consecutive rows of n reals. Each row is read as n/2 complex
-// values z[m] = x[2m] + i x[2m+1]; after the length-n/2 FFT, X[k] = E[k] + exp(-2 pi i k / n) O[k] with
-// E[k] = (Z[k] + conj Z[n/2-k]) / 2 and O[k] = (Z[k] - conj Z[n/2-k]) / (2 i), for k = 0..n/2.
-template <bool FIXED>
-__global__ __launch_bounds__(kFftNT) void k_fft_z_r2c(const void* __restrict__ in, int n, int nrows,
-                                                      float2* __restrict__ out, int pitch, double mscale, Plan1D pl,
-                                                      int lgB, int* __restrict__ flags) {
+// Every kernel stages its global loads through registers in fully unrolled batches before writing the LDS tile: a
+// runtime-bounded load loop would wait out the HBM latency once per element.
+
+// z pass, forward r2c. A workgroup transforms B consecutive rows of n reals. Each row is read as h = n/2 complex
+// values z[m] = x[2m] + i x[2m+1]; after the length-h FFT, X[k] = E[k] + exp(-2 pi i k / n) O[k] with
+// E[k] = (Z[k] + conj Z[h-k]) / 2 and O[k] = (Z[k] - conj Z[h-k]) / (2 i), for k = 0..h.
+template <bool FIXED, int B>
+__global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const void* __restrict__ in, int n, int nrows,
+                                                         float2* __restrict__ out, int pitch, double mscale,
+                                                         Plan1D pl, int* __restrict__ flags) {
+  constexpr int BP = B + 1;
   extern __shared__ float2 smem[];
-  const int h = n / 2, B = 1 << lgB, BP = B + 1, tid = threadIdx.x;
+  const int h = n / 2, tid = threadIdx.x;
   float2* tile = smem;
-  float2* tw = smem + h * BP;
-  fill_twiddles(tw, n, tid);
+  float2* tw = tile + h * BP;
+  float2* roots = tw + h;
+  fill_stage_twiddles(tw, pl, tid);
+  fill_half_roots(roots, n, tid);
   const int row0 = blockIdx.x * B;
-  bool overflow = false;
-  for (int b = 0; b < B; ++b) {
-    const int row = row0 + b;
-    if (FIXED) {
-      const ulonglong2* src = reinterpret_cast<const ulonglong2*>(static_cast<const uint64_t*>(in) +
-                                                                  static_cast<size_t>(row) * n);
-      for (int j = tid; j < h; j += kFftNT) {
-        float2 v = make_float2(0.f, 0.f);
-        if (row < nrows) {
-          const ulonglong2 c = src[j];
-          overflow |= ((c.x | c.y) >> 63) != 0;
-          v.x = static_cast<float>(static_cast<double>(c.x) * mscale - 1.0);
-          v.y = static_cast<float>(static_cast<double>(c.y) * mscale - 1.0);
-        }
-        tile[j * BP + b] = v;
+  const int count = h * B;
+  if (FIXED) {
+    constexpr int H = kEPT / 2;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+      ulonglong2 raw[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const int e = tid + (half * H + m) * kFftNT;
+        const int b = e / h, j = e - b * h;
+        raw[m] = make_ulonglong2(0ull, 0ull);
+        if (e < count && row0 + b < nrows)
+          raw[m] = reinterpret_cast<const ulonglong2*>(static_cast<const uint64_t*>(in) +
+                                                       static_cast<size_t>(row0 + b) * n)[j];
       }
-    } else {
-      const float2* src = static_cast<const float2*>(in) + static_cast<size_t>(row) * h;
-      for (int j = tid; j < h; j += kFftNT) tile[j * BP + b] = (row < nrows) ? src[j] : make_float2(0.f, 0.f);
+      bool overflow = false;
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const int e = tid + (half * H + m) * kFftNT;
+        if (e < count) {
+          const int b = e / h, j = e - b * h;
+          overflow |= ((raw[m].x | raw[m].y) >> 63) != 0;
+          float2 v = make_float2(0.f, 0.f);
+          if (row0 + b < nrows) {
+            v.x = static_cast<float>(static_cast<double>(raw[m].x) * mscale - 1.0);
+            v.y = static_cast<float>(static_cast<double>(raw[m].y) * mscale - 1.0);
+          }
+          tile[j * BP + b] = v;
+        }
+      }
+      if (overflow) atomicOr(flags + kFlagOverflow, 1);
+    }
+  } else {
+    float2 v[kEPT];
+#pragma unroll
+    for (int m = 0; m < kEPT; ++m) {
+      const int e = tid + m * kFftNT;
+      const int b = e / h, j = e - b * h;
+      v[m] = make_float2(0.f, 0.f);
+      if (e < count && row0 + b < nrows) v[m] = static_cast<const float2*>(in)[static_cast<size_t>(row0 + b) * h + j];
+    }
+#pragma unroll
+    for (int m = 0; m < kEPT; ++m) {
+      const int e = tid + m * kFftNT;
+      if (e < count) {
+        const int b = e / h, j = e - b * h;
+        tile[j * BP + b] = v[m];
+      }
     }
   }
-  if (FIXED && overflow) atomicOr(flags + kFlagOverflow, 1);
   __syncthreads();
-  fft_tile<false>(tile, BP, tw, 2, pl, lgB, tid);
-  for (int b = 0; b < B; ++b) {
-    const int row = row0 + b;
-    if (row >= nrows) break;
-    float2* dst = out + static_cast<size_t>(row) * pitch;
-    for (int k = tid; k <= h; k += kFftNT) {
-      const float2 zk = tile[(k == h ? 0 : k) * BP + b];
-      const float2 zm = tile[(k == 0 ? 0 : h - k) * BP + b];
-      const float2 E = cscale(cadd(zk, cconj(zm)), 0.5f);
-      const float2 O = cscale(rot<false>(csub(zk, cconj(zm))), 0.5f);  // (zk - conj zm) / (2 i)
-      dst[k] = cadd(E, cmul(tw[k], O));
+  fft_tile<false>(tile, tw, pl, B, tid);
+  const int count2 = (h + 1) * B;
+#pragma unroll
+  for (int m = 0; m < kEPT + 1; ++m) {
+    const int e = tid + m * kFftNT;
+    if (e < count2) {
+      const int b = e / (h + 1), k = e - b * (h + 1);
+      const int row = row0 + b;
+      if (row < nrows) {
+        const float2 zk = tile[(k == h ? 0 : k) * BP + b];
+        const float2 zm = tile[(k == 0 ? 0 : h - k) * BP + b];
+        const float2 E = cscale(cadd(zk, cconj(zm)), 0.5f);
+        const float2 O = cscale(rot<false>(csub(zk, cconj(zm))), 0.5f);  // (zk - conj zm) / (2 i)
+        out[static_cast<size_t>(row) * pitch + k] = cadd(E, cmul(roots[k], O));
+      }
     }
   }
 }
 
-// Load/store of a strided tile: element (j, b) of the tile <-> ptr[j * astr + b], for b < bw.
-__device__ __forceinline__ void load_strided(float2* tile, int BP, const float2* __restrict__ ptr, int64_t astr, int n,
-                                             int lgB, int bw, int tid) {
-  const int b = tid & ((1 << lgB) - 1), S = kFftNT >> lgB;
-  const float2* p = ptr + b + static_cast<int64_t>(tid >> lgB) * astr;
-  const int64_t step = static_cast<int64_t>(S) * astr;
-  for (int j = tid >> lgB; j < n; j += S, p += step) tile[j * BP + b] = (b < bw) ? *p : make_float2(0.f, 0.f);
+// Load/store of a strided tile of B columns: element (j, b) <-> ptr[j * astr + b], for b < bw. Loads go out in two
+// unrolled batches of kEPT / 2 per thread (enough bytes in flight per CU to cover HBM latency at a register cost
+// that keeps four waves per SIMD). When `scale` is given, each loaded value is multiplied by scale(j, b) (a real
+// factor) and by i.
+template <int B>
+__device__ __forceinline__ void load_strided(float2* tile, const float2* __restrict__ ptr, int64_t astr, int n, int bw,
+                                             int tid) {
+  constexpr int BP = B + 1;
+  const int count = n * B;
+  constexpr int H = kEPT / 2;
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    float2 v[H];
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      const int e = tid + (half * H + m) * kFftNT;
+      const int j = e / B, b = e % B;
+      v[m] = make_float2(0.f, 0.f);
+      if (e < count && b < bw) v[m] = ptr[j * astr + b];
+    }
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      const int e = tid + (half * H + m) * kFftNT;
+      if (e < count) tile[(e / B) * BP + (e % B)] = v[m];
+    }
+  }
 }
 
-__device__ __forceinline__ void store_strided(const float2* tile, int BP, float2* __restrict__ ptr, int64_t astr,
-                                              int n, int lgB, int bw, int tid) {
-  const int b = tid & ((1 << lgB) - 1), S = kFftNT >> lgB;
-  if (b >= bw) return;
-  float2* p = ptr + b + static_cast<int64_t>(tid >> lgB) * astr;
-  const int64_t step = static_cast<int64_t>(S) * astr;
-  for (int j = tid >> lgB; j < n; j += S, p += step) *p = tile[j * BP + b];
+template <int B>
+__device__ __forceinline__ void store_strided(const float2* tile, float2* __restrict__ ptr, int64_t astr, int n,
+                                              int bw, int tid) {
+  constexpr int BP = B + 1;
+  const int count = n * B;
+#pragma unroll
+  for (int m = 0; m < kEPT; ++m) {
+    const int e = tid + m * kFftNT;
+    const int j = e / B, b = e % B;
+    if (e < count && b < bw) ptr[j * astr + b] = tile[j * BP + b];
+  }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
 // Strided complex pass (in place). Tile = B consecutive columns (contiguous in memory) x n points along the axis.
-template <bool INV>
-__global__ __launch_bounds__(kFftNT) void k_fft_axis(float2* __restrict__ base, int n, int64_t astr, int64_t ostr,
-                                                     int n_outer, int ncols, int64_t cstr, Plan1D pl, int lgB) {
+template <bool INV, int B>
+__global__ __launch_bounds__(kFftNT, 4) void k_fft_axis(float2* __restrict__ base, int n, int64_t astr, int64_t ostr,
+                                                        int n_outer, int ncols, int64_t cstr, Plan1D pl) {
   extern __shared__ float2 smem[];
-  const int B = 1 << lgB, BP = B + 1, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   float2* tile = smem;
-  float2* tw = smem + n * BP;
-  fill_twiddles(tw, n, tid);
-  const int ntc = (ncols + B - 1) >> lgB;
+  float2* tw = smem + n * (B + 1);
+  fill_stage_twiddles(tw, pl, tid);
+  const int ntc = (ncols + B - 1) / B;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int outer = logical / ntc, ct = logical - outer * ntc;
-  const int c0 = ct << lgB, bw = min(B, ncols - c0);
+  const int c0 = ct * B, bw = min(B, ncols - c0);
   float2* ptr = base + blockIdx.y * cstr + outer * ostr + c0;
-  load_strided(tile, BP, ptr, astr, n, lgB, bw, tid);
+  load_strided<B>(tile, ptr, astr, n, bw, tid);
   __syncthreads();
-  fft_tile<INV>(tile, BP, tw, 1, pl, lgB, tid);
-  store_strided(tile, BP, ptr, astr, n, lgB, bw, tid);
+  fft_tile<INV>(tile, tw, pl, B, tid);
+  store_strided<B>(tile, ptr, astr, n, bw, tid);
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Fused x pass of the force: forward FFT along x, then for each component j = x, y, z
+// Fused x pass of the force: forward FFT along x of a tile of delta_hat, then for each component j
 //   g_hat_j = i k_j (-1/k^2) delta_hat / W^p / Nm^3     (zero at k = 0 and on the Nyquist plane of axis j),
-// inverse FFT along x, store. W = prod_d sinc^2(pi n_d / Nm). The 1/Nm^3 of the inverse transform is folded in.
+// inverse FFT along x, store. W = prod_d sinc^2(pi n_d / Nm); the 1/Nm^3 of the inverse transform is folded in.
+// The x-transformed delta_hat stays in a second LDS tile across the three components.
+template <int B>
 __global__ __launch_bounds__(kFftNT) void k_fft_x_poisson(float2* __restrict__ A, float2* __restrict__ Bm,
                                                           float2* __restrict__ Cm, int nm, int pitch, float kf,
-                                                          float inv_m3, int deconv, Plan1D pl, int lgB) {
+                                                          float inv_m3, int deconv, Plan1D pl) {
+  constexpr int BP = B + 1;
   extern __shared__ float2 smem[];
-  const int n = nm, B = 1 << lgB, BP = B + 1, tid = threadIdx.x, nh = nm / 2 + 1;
+  const int n = nm, tid = threadIdx.x, nh = nm / 2 + 1;
   float2* tile = smem;
-  float2* tw = smem + n * BP;
-  float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m < n (even in m)
-  fill_twiddles(tw, n, tid);
-  for (int m = tid; m < n; m += kFftNT) {
-    const int mm = min(m, n - m);
+  float2* dh = tile + n * BP;
+  float2* tw = dh + n * BP;
+  float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
+  fill_stage_twiddles(tw, pl, tid);
+  for (int m = tid; m <= n / 2; m += kFftNT) {
     double w = 1.0;
-    if (mm != 0) {
-      const double x = static_cast<double>(mm) / n;
+    if (m != 0) {
+      const double x = static_cast<double>(m) / n;
       w = sinpi(x) / (M_PI * x);
       w = w * w;
     }
     win[m] = static_cast<float>(w);
   }
-  const int ntc = (nh + B - 1) >> lgB;
+  const int ntc = (nh + B - 1) / B;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int y = logical / ntc, ct = logical - y * ntc;
-  const int c0 = ct << lgB, bw = min(B, nh - c0);
+  const int c0 = ct * B, bw = min(B, nh - c0);
   const int64_t astr = static_cast<int64_t>(nm) * pitch;
   const int64_t off = static_cast<int64_t>(y) * pitch + c0;
-  load_strided(tile, BP, A + off, astr, n, lgB, bw, tid);
+  load_strided<B>(tile, A + off, astr, n, bw, tid);
   __syncthreads();
-  fft_tile<false>(tile, BP, tw, 1, pl, lgB, tid);
+  fft_tile<false>(tile, tw, pl, B, tid);
 
-  // This thread's elements (j = j0 + m S, column b): delta_hat stays in registers across the three components.
-  const int b = tid & (B - 1), S = kFftNT >> lgB, j0 = tid >> lgB;
+  // Each thread touches only its own elements (column b, rows j0 + m S) between the barriers that bracket the
+  // inverse transforms.
+  constexpr int S = kFftNT / B;
+  const int b = tid % B, j0 = tid / B;
   const int half = nm / 2;
   const int ny = (y <= half) ? y : y - nm;
   const int nz = c0 + b;
   const bool col_ok = b < bw;
-  const float wyz = win[y] * win[min(nz, n - 1)];
+  const float wyz = win[min(y, n - y)] * win[min(nz, half)];
   const int nyz2 = ny * ny + nz * nz;
-  float2 d[kEPT];
-#pragma unroll
-  for (int m = 0; m < kEPT; ++m) {
-    const int j = j0 + m * S;
-    d[m] = (j < n) ? tile[j * BP + b] : make_float2(0.f, 0.f);
-  }
-  float2* outs[3] = {A, Bm, Cm};
+  for (int j = j0; j < n; j += S) dh[j * BP + b] = tile[j * BP + b];
+#pragma unroll 1
   for (int comp = 0; comp < 3; ++comp) {
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < kEPT; ++m) {
-      const int j = j0 + m * S;
-      if (j < n) {
-        const int nx = (j <= half) ? j : j - nm;
-        const float k2 = kf * kf * static_cast<float>(nx * nx + nyz2);
-        const int nc = (comp == 0) ? nx : (comp == 1 ? ny : nz);
-        float s = 0.f;
-        if (k2 > 0.f && col_ok && nc != half && nc != -half) {
-          const float W = win[j] * wyz;
-          const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
-          s = -kf * static_cast<float>(nc) * inv_m3 / (k2 * wp);  // k_c * (-1 / (k^2 W^p Nm^3))
-        }
-        tile[j * BP + b] = make_float2(-s * d[m].y, s * d[m].x);  // i * s * delta_hat
+    for (int j = j0; j < n; j += S) {
+      const int nx = (j <= half) ? j : j - nm;
+      const float k2 = kf * kf * static_cast<float>(nx * nx + nyz2);
+      const int nc = (comp == 0) ? nx : (comp == 1 ? ny : nz);
+      float sc = 0.f;
+      if (k2 > 0.f && col_ok && nc != half && nc != -half) {
+        const float W = win[min(j, n - j)] * wyz;
+        const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
+        sc = -kf * static_cast<float>(nc) * inv_m3 / (k2 * wp);  // k_c * (-1 / (k^2 W^p Nm^3))
       }
+      const float2 d = dh[j * BP + b];
+      tile[j * BP + b] = make_float2(-sc * d.y, sc * d.x);  // i * sc * delta_hat
     }
     __syncthreads();
-    fft_tile<true>(tile, BP, tw, 1, pl, lgB, tid);
-    store_strided(tile, BP, outs[comp] + off, astr, n, lgB, bw, tid);
+    fft_tile<true>(tile, tw, pl, B, tid);
+    float2* dst = (comp == 0) ? A : (comp == 1 ? Bm : Cm);
+    store_strided<B>(tile, dst + off, astr, n, bw, tid);
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// z pass, inverse c2r. A workgroup transforms R = 2^lgR rows of each of NC spectra; the tile has G * R columns
-// (G = 1 for NC = 1, G = 4 for NC = 3: one column group stays zero so the column count is a power of two).
-// With X the half spectrum of a real row,
+// z pass, inverse c2r. A workgroup transforms R rows of each of NC spectra; tile column c R + r holds spectrum c of
+// row r (B = NC R columns). With X the half spectrum of a real row,
 //   Z[k] = (X[k] + conj X[h-k]) + i exp(+2 pi i k / n) (X[k] - conj X[h-k]),  h = n/2, k < h,
-// and the unnormalised length-h inverse FFT of Z gives x[2m] + i x[2m+1].
-template <int NC>
-__global__ __launch_bounds__(kFftNT) void k_fft_z_c2r(const float2* __restrict__ in0, const float2* __restrict__ in1,
-                                                      const float2* __restrict__ in2, int n, int nrows, int pitch,
-                                                      float* __restrict__ out, float scale, Plan1D pl, int lgR) {
-  constexpr int G = (NC == 1) ? 1 : 4;
+// and the unnormalised length-h inverse FFT of Z gives x[2m] + i x[2m+1]. Output rows are NC-interleaved.
+template <int NC, int R>
+__global__ __launch_bounds__(kFftNT, 4) void k_fft_z_c2r(const float2* __restrict__ in0, const float2* __restrict__ in1,
+                                                         const float2* __restrict__ in2, int n, int nrows, int pitch,
+                                                         float* __restrict__ out, float scale, Plan1D pl) {
+  constexpr int B = NC * R, BP = B + 1;
   extern __shared__ float2 smem[];
-  const int h = n / 2, R = 1 << lgR, ncol = G * R, BP = ncol + 1, tid = threadIdx.x;
-  int lgB = lgR + ((G == 4) ? 2 : 0);
+  const int h = n / 2, tid = threadIdx.x;
   float2* tile = smem;                 // (h + 1) x BP
-  float2* tw = smem + (h + 1) * BP;    // n-th roots
-  fill_twiddles(tw, n, tid);
+  float2* tw = tile + (h + 1) * BP;    // stage twiddles (h)
+  float2* roots = tw + h;              // exp(-2 pi i k / n), k <= h
+  fill_stage_twiddles(tw, pl, tid);
+  fill_half_roots(roots, n, tid);
   const int row0 = blockIdx.x * R;
   const float2* ins[3] = {in0, in1, in2};
-  for (int col = 0; col < ncol; ++col) {
-    const int c = col >> lgR, r = col & (R - 1);
-    const int row = row0 + r;
-    const bool live = (c < NC) && (row < nrows);
-    const float2* src = ins[c < NC ? c : 0] + static_cast<size_t>(row) * pitch;
-    for (int k = tid; k <= h; k += kFftNT) tile[k * BP + col] = live ? src[k] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  for (int col = 0; col < NC * R; ++col) {
-    for (int k = tid; k <= h / 2; k += kFftNT) {
-      const float2 xk = tile[k * BP + col];
-      const float2 xm = tile[(h - k) * BP + col];
-      const float2 t = tw[k];
-      // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm)
-      const float2 zk = cadd(cadd(xk, cconj(xm)), rot<true>(cmulc(csub(xk, cconj(xm)), t)));
-      if (k != 0 && 2 * k != h) {
-        // Z[h-k] = (xm + conj xk) - i t (xm - conj xk)
-        const float2 zm = csub(cadd(xm, cconj(xk)), rot<true>(cmul(csub(xm, cconj(xk)), t)));
-        tile[(h - k) * BP + col] = zm;
+  const int count = B * (h + 1);
+  {
+    float2 v[kEPT + 1];
+#pragma unroll
+    for (int m = 0; m < kEPT + 1; ++m) {
+      const int e = tid + m * kFftNT;
+      const int col = e / (h + 1), k = e - col * (h + 1);
+      const int c = col / R, row = row0 + col % R;
+      v[m] = make_float2(0.f, 0.f);
+      if (e < count && row < nrows) v[m] = ins[c][static_cast<size_t>(row) * pitch + k];
+    }
+#pragma unroll
+    for (int m = 0; m < kEPT + 1; ++m) {
+      const int e = tid + m * kFftNT;
+      if (e < count) {
+        const int col = e / (h + 1), k = e - col * (h + 1);
+        tile[k * BP + col] = v[m];
       }
-      tile[k * BP + col] = zk;
     }
   }
   __syncthreads();
-  fft_tile<true>(tile, BP, tw, 2, pl, lgB, tid);
+  const int hk = h / 2 + 1;
+  for (int e = tid; e < hk * B; e += kFftNT) {
+    const int col = e / hk, k = e - col * hk;
+    const float2 xk = tile[k * BP + col];
+    const float2 xm = tile[(h - k) * BP + col];
+    const float2 t = roots[k];
+    // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm)
+    const float2 zk = cadd(cadd(xk, cconj(xm)), rot<true>(cmulc(csub(xk, cconj(xm)), t)));
+    if (k != 0 && 2 * k != h) {
+      // Z[h-k] = (xm + conj xk) - i t (xm - conj xk)
+      const float2 zm = csub(cadd(xm, cconj(xk)), rot<true>(cmul(csub(xm, cconj(xk)), t)));
+      tile[(h - k) * BP + col] = zm;
+    }
+    tile[k * BP + col] = zk;
+  }
+  __syncthreads();
+  fft_tile<true>(tile, tw, pl, B, tid);
   const int rowlen = NC * n;
-  for (int r = 0; r < R; ++r) {
+#pragma unroll 4
+  for (int f = tid; f < R * rowlen; f += kFftNT) {
+    const int r = f / rowlen, q = f - r * rowlen;
     const int row = row0 + r;
-    if (row >= nrows) break;
-    float* dst = out + static_cast<size_t>(row) * rowlen;
-    for (int q = tid; q < rowlen; q += kFftNT) {
+    if (row < nrows) {
       const int jj = q / NC, c = q - jj * NC;
       const float2 z = tile[(jj >> 1) * BP + c * R + r];
-      dst[q] = ((jj & 1) ? z.y : z.x) * scale;
+      out[static_cast<size_t>(row) * rowlen + q] = ((jj & 1) ? z.y : z.x) * scale;
     }
   }
 }
 
-size_t lds_z_r2c(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n / 2) * (B + 1) + n); }
+size_t lds_z_r2c(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n / 2) * (B + 1) + n / 2 + n / 2 + 1); }
 size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) * (B + 1) + n); }
-size_t lds_x_poisson(int n, int B) { return lds_axis(n, B) + sizeof(float) * n; }
-size_t lds_z_c2r(int n, int ncol) { return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (ncol + 1) + n); }
+size_t lds_x_poisson(int n, int B) {
+  return sizeof(float2) * (2 * static_cast<size_t>(n) * (B + 1) + n) + sizeof(float) * (n / 2 + 1);
+}
+size_t lds_z_c2r(int n, int B) {
+  return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (B + 1) + n / 2 + n / 2 + 1);
+}
+
+// Columns of a strided tile: the most of 8, 16, 32 with n * B <= kTileElems (8 for n > 512).
+int strided_cols(int n) { return (n <= 256) ? 32 : (n <= 512 ? 16 : 8); }
+// Rows of a z-pass tile for NC interleaved spectra: the largest of 1, 2, 4, 8, 16, 32 (/ NC-dependent cap) with
+// NC R (h + 1) <= kTileElems + kFftNT and NC R h <= kEPT (kFftNT / (NC R)) (NC R).
+int z_rows(int n, int nc) {
+  const int h = n / 2;
+  int best = 1;
+  for (int r = 1; r <= 32; r *= 2) {
+    const int B = nc * r;
+    if (B > kFftNT) break;
+    if (B * (h + 1) > kTileElems + kFftNT) break;
+    if (static_cast<long>(h) * B > static_cast<long>(kEPT) * (kFftNT / B) * B) break;
+    best = r;
+  }
+  return best;
+}
 
 struct Init {
   Init() {
-    allow_big_lds(k_fft_z_r2c<true>);
-    allow_big_lds(k_fft_z_r2c<false>);
-    allow_big_lds(k_fft_axis<true>);
-    allow_big_lds(k_fft_axis<false>);
-    allow_big_lds(k_fft_x_poisson);
-    allow_big_lds(k_fft_z_c2r<1>);
-    allow_big_lds(k_fft_z_c2r<3>);
+    allow_big_lds(k_fft_z_r2c<true, 8>);
+    allow_big_lds(k_fft_z_r2c<true, 16>);
+    allow_big_lds(k_fft_z_r2c<true, 32>);
+    allow_big_lds(k_fft_z_r2c<false, 8>);
+    allow_big_lds(k_fft_z_r2c<false, 16>);
+    allow_big_lds(k_fft_z_r2c<false, 32>);
+    allow_big_lds(k_fft_axis<true, 8>);
+    allow_big_lds(k_fft_axis<true, 16>);
+    allow_big_lds(k_fft_axis<true, 32>);
+    allow_big_lds(k_fft_axis<false, 8>);
+    allow_big_lds(k_fft_axis<false, 16>);
+    allow_big_lds(k_fft_axis<false, 32>);
+    allow_big_lds(k_fft_x_poisson<8>);
+    allow_big_lds(k_fft_x_poisson<16>);
+    allow_big_lds(k_fft_x_poisson<32>);
+    allow_big_lds(k_fft_z_c2r<1, 8>);
+    allow_big_lds(k_fft_z_c2r<1, 16>);
+    allow_big_lds(k_fft_z_c2r<1, 32>);
+    allow_big_lds(k_fft_z_c2r<3, 4>);
+    allow_big_lds(k_fft_z_c2r<3, 8>);
+    allow_big_lds(k_fft_z_c2r<3, 16>);
   }
 };
 
@@ -329,9 +425,12 @@ hipError_t fft_z_r2c_fixed(const uint64_t* C, int nm, double mscale, float2* out
   ensure_init();
   Plan1D pl;
   if (!make_plan(nm / 2, &pl)) return hipErrorInvalidValue;
-  const int lgB = z_lg_rows(nm, 1), B = 1 << lgB, nrows = nm * nm;
-  k_fft_z_r2c<true><<<(nrows + B - 1) / B, kFftNT, lds_z_r2c(nm, B), s>>>(C, nm, nrows, out, pitch, mscale, pl, lgB,
-                                                                            flags);
+  const int B = std::max(8, z_rows(nm, 1)), nrows = nm * nm;
+  const unsigned grid = (nrows + B - 1) / B;
+  const size_t lds = lds_z_r2c(nm, B);
+  if (B == 8) k_fft_z_r2c<true, 8><<<grid, kFftNT, lds, s>>>(C, nm, nrows, out, pitch, mscale, pl, flags);
+  else if (B == 16) k_fft_z_r2c<true, 16><<<grid, kFftNT, lds, s>>>(C, nm, nrows, out, pitch, mscale, pl, flags);
+  else k_fft_z_r2c<true, 32><<<grid, kFftNT, lds, s>>>(C, nm, nrows, out, pitch, mscale, pl, flags);
   return hipGetLastError();
 }
 
@@ -339,9 +438,12 @@ hipError_t fft_z_r2c_real(const float* in, int n, float2* out, int pitch, hipStr
   ensure_init();
   Plan1D pl;
   if (!make_plan(n / 2, &pl)) return hipErrorInvalidValue;
-  const int lgB = z_lg_rows(n, 1), B = 1 << lgB, nrows = n * n;
-  k_fft_z_r2c<false><<<(nrows + B - 1) / B, kFftNT, lds_z_r2c(n, B), s>>>(in, n, nrows, out, pitch, 0.0, pl, lgB,
-                                                                            nullptr);
+  const int B = std::max(8, z_rows(n, 1)), nrows = n * n;
+  const unsigned grid = (nrows + B - 1) / B;
+  const size_t lds = lds_z_r2c(n, B);
+  if (B == 8) k_fft_z_r2c<false, 8><<<grid, kFftNT, lds, s>>>(in, n, nrows, out, pitch, 0.0, pl, nullptr);
+  else if (B == 16) k_fft_z_r2c<false, 16><<<grid, kFftNT, lds, s>>>(in, n, nrows, out, pitch, 0.0, pl, nullptr);
+  else k_fft_z_r2c<false, 32><<<grid, kFftNT, lds, s>>>(in, n, nrows, out, pitch, 0.0, pl, nullptr);
   return hipGetLastError();
 }
 
@@ -350,15 +452,18 @@ hipError_t fft_axis(float2* base, int n, int64_t axis_stride, int64_t outer_stri
   ensure_init();
   Plan1D pl;
   if (!make_plan(n, &pl)) return hipErrorInvalidValue;
-  const int lgB = strided_lg_cols(n), B = 1 << lgB;
+  const int B = strided_cols(n);
   const int ntc = (ncols + B - 1) / B;
   dim3 grid(n_outer * ntc, ncomp);
-  if (inverse)
-    k_fft_axis<true><<<grid, kFftNT, lds_axis(n, B), s>>>(base, n, axis_stride, outer_stride, n_outer, ncols,
-                                                            comp_stride, pl, lgB);
-  else
-    k_fft_axis<false><<<grid, kFftNT, lds_axis(n, B), s>>>(base, n, axis_stride, outer_stride, n_outer, ncols,
-                                                             comp_stride, pl, lgB);
+  const size_t lds = lds_axis(n, B);
+#define LPC_AXIS(INV, BB) \
+  k_fft_axis<INV, BB><<<grid, kFftNT, lds, s>>>(base, n, axis_stride, outer_stride, n_outer, ncols, comp_stride, pl)
+  if (inverse) {
+    if (B == 8) LPC_AXIS(true, 8); else if (B == 16) LPC_AXIS(true, 16); else LPC_AXIS(true, 32);
+  } else {
+    if (B == 8) LPC_AXIS(false, 8); else if (B == 16) LPC_AXIS(false, 16); else LPC_AXIS(false, 32);
+  }
+#undef LPC_AXIS
   return hipGetLastError();
 }
 
@@ -367,12 +472,15 @@ hipError_t fft_x_poisson(float2* A, float2* B, float2* C, int nm, int pitch, dou
   ensure_init();
   Plan1D pl;
   if (!make_plan(nm, &pl)) return hipErrorInvalidValue;
-  const int lgB = strided_lg_cols(nm), Bc = 1 << lgB;
+  const int Bc = strided_cols(nm);
   const int nh = nm / 2 + 1, ntc = (nh + Bc - 1) / Bc;
   const float kf = static_cast<float>(2.0 * M_PI / box);
   const float inv_m3 = static_cast<float>(1.0 / (static_cast<double>(nm) * nm * nm));
-  k_fft_x_poisson<<<nm * ntc, kFftNT, lds_x_poisson(nm, Bc), s>>>(A, B, C, nm, pitch, kf, inv_m3, deconv_power, pl,
-                                                                    lgB);
+  const size_t lds = lds_x_poisson(nm, Bc);
+  const unsigned grid = nm * ntc;
+  if (Bc == 8) k_fft_x_poisson<8><<<grid, kFftNT, lds, s>>>(A, B, C, nm, pitch, kf, inv_m3, deconv_power, pl);
+  else if (Bc == 16) k_fft_x_poisson<16><<<grid, kFftNT, lds, s>>>(A, B, C, nm, pitch, kf, inv_m3, deconv_power, pl);
+  else k_fft_x_poisson<32><<<grid, kFftNT, lds, s>>>(A, B, C, nm, pitch, kf, inv_m3, deconv_power, pl);
   return hipGetLastError();
 }
 
@@ -381,9 +489,12 @@ hipError_t fft_z_c2r_aos3(const float2* A, const float2* B, const float2* C, int
   ensure_init();
   Plan1D pl;
   if (!make_plan(nm / 2, &pl)) return hipErrorInvalidValue;
-  const int lgR = z_lg_rows(nm, 4), R = 1 << lgR, nrows = nm * nm;
-  k_fft_z_c2r<3><<<(nrows + R - 1) / R, kFftNT, lds_z_c2r(nm, 4 * R), s>>>(A, B, C, nm, nrows, pitch, out, 1.0f, pl,
-                                                                             lgR);
+  const int R = std::max(4, std::min(16, z_rows(nm, 3))), nrows = nm * nm;
+  const unsigned grid = (nrows + R - 1) / R;
+  const size_t lds = lds_z_c2r(nm, 3 * R);
+  if (R == 4) k_fft_z_c2r<3, 4><<<grid, kFftNT, lds, s>>>(A, B, C, nm, nrows, pitch, out, 1.0f, pl);
+  else if (R == 8) k_fft_z_c2r<3, 8><<<grid, kFftNT, lds, s>>>(A, B, C, nm, nrows, pitch, out, 1.0f, pl);
+  else k_fft_z_c2r<3, 16><<<grid, kFftNT, lds, s>>>(A, B, C, nm, nrows, pitch, out, 1.0f, pl);
   return hipGetLastError();
 }
 
@@ -391,9 +502,12 @@ hipError_t fft_z_c2r_real(const float2* in, int n, int pitch, float* out, float 
   ensure_init();
   Plan1D pl;
   if (!make_plan(n / 2, &pl)) return hipErrorInvalidValue;
-  const int lgR = z_lg_rows(n, 1), R = 1 << lgR, nrows = n * n;
-  k_fft_z_c2r<1><<<(nrows + R - 1) / R, kFftNT, lds_z_c2r(n, R), s>>>(in, in, in, n, nrows, pitch, out, scale, pl,
-                                                                        lgR);
+  const int R = std::max(8, z_rows(n, 1)), nrows = n * n;
+  const unsigned grid = (nrows + R - 1) / R;
+  const size_t lds = lds_z_c2r(n, R);
+  if (R == 8) k_fft_z_c2r<1, 8><<<grid, kFftNT, lds, s>>>(in, in, in, n, nrows, pitch, out, scale, pl);
+  else if (R == 16) k_fft_z_c2r<1, 16><<<grid, kFftNT, lds, s>>>(in, in, in, n, nrows, pitch, out, scale, pl);
+  else k_fft_z_c2r<1, 32><<<grid, kFftNT, lds, s>>>(in, in, in, n, nrows, pitch, out, scale, pl);
   return hipGetLastError();
 }
 

@@ -1,8 +1,8 @@
-// Device-side building blocks of liblpc's FFTs: complex helpers, radix-2/3/4/5/8 butterflies, one Stockham
+// Device-side building blocks of liblpc's FFTs: complex helpers, radix-2/3/4/5/8/16 butterflies, one Stockham
 // autosort stage over an LDS tile, and the XCD-aware workgroup remap. Included by the .hip sources only.
 //
-// An LDS tile holds B = 2^lgB independent columns of one transform length n: element (j, b) at tile[j * BP + b]
-// (BP >= B is the padded column pitch; n * B <= kTileElems). Stage s with radix R and current sub-transform length p (product of the
+// An LDS tile holds B independent columns of one transform length n: element (j, b) at tile[j * BP + b] with
+// BP = B + 1 (n * B <= kTileElems). Stage s with radix R and current sub-transform length p (product of the
 // earlier radices) reads x[i + r T] (T = n / R), multiplies by w^(r k) with w = exp(-+ 2 pi i / (p R)),
 // k = i mod p, takes the length-R DFT and writes it to ((i - k) R + k + r p): the Stockham autosort ordering,
 // so after the last stage the tile is in natural order. Each thread stages its butterflies in registers between two
@@ -113,73 +113,130 @@ struct Dft<5, INV> {
   }
 };
 
-// One Stockham stage over the tile (see the file comment). The tile has B = 2^lgB columns; thread t owns column
-// t mod B and butterflies i = t / B + m (kFftNT / B). tw holds exp(-2 pi i m / (n * tmul)) for m < n * tmul.
+template <bool INV>
+struct Dft<16, INV> {
+  // 16 = 4 x 4: DFT4 over stride-4 subsequences, twiddle by w16^(c q), DFT4 across; output index q + 4 d.
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 y[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float2 t[4] = {v[c], v[c + 4], v[c + 8], v[c + 12]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) y[c][q] = t[q];
+    }
+    const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
+    const float sg = INV ? 1.f : -1.f;  // w16 = cos(2 pi / 16) + sg i sin(2 pi / 16)
+    const float2 w1 = make_float2(c1, sg * s1), w2 = make_float2(h, sg * h), w3 = make_float2(s1, sg * c1);
+    y[1][1] = cmul(y[1][1], w1);
+    y[1][2] = cmul(y[1][2], w2);
+    y[1][3] = cmul(y[1][3], w3);
+    y[2][1] = cmul(y[2][1], w2);
+    y[2][2] = rot<INV>(y[2][2]);                                 // w16^4
+    y[2][3] = cmul(y[2][3], make_float2(-h, sg * h));           // w16^6
+    y[3][1] = cmul(y[3][1], w3);
+    y[3][2] = cmul(y[3][2], make_float2(-h, sg * h));           // w16^6
+    y[3][3] = cmul(y[3][3], make_float2(-c1, -sg * s1));        // w16^9 = -w16^1
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float2 t[4] = {y[0][q], y[1][q], y[2][q], y[3][q]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[q + 4 * d] = t[d];
+    }
+  }
+};
+
+// Thread geometry of a tile with B columns (row pitch BP = B + 1): threads t < S B (S = kFftNT / B) own column
+// b = t mod B and butterflies i = i0 + m S with i0 = t / B; the others idle during the stages.
+struct TileGeom {
+  int B, BP, S, b, i0;
+  __device__ TileGeom(int B_, int tid) : B(B_), BP(B_ + 1), S(kFftNT / B_) {
+    b = tid % B_;
+    i0 = (tid < S * B_) ? tid / B_ : (1 << 30);
+  }
+};
+
+// One Stockham stage over the tile (see the file comment). tws points at this stage's twiddles (k (R - 1) + r - 1).
+// Requires n B <= kEPT S B.
 template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(float2* tile, int BP, const float2* tw, int tmul, int n, int lgB, int p,
-                                          int tid) {
+__device__ __forceinline__ void fft_stage(float2* tile, const float2* tws, int n, int p, int pmask, const TileGeom& g) {
   constexpr int MB = (kEPT + R - 1) / R;
   const int T = n / R;
-  const int b = tid & ((1 << lgB) - 1);
-  const int i0 = tid >> lgB;
-  const int S = kFftNT >> lgB;
-  const int stride = (n / (p * R)) * tmul;
   float2 v[MB][R];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
-    const int i = i0 + m * S;
+    const int i = g.i0 + m * g.S;
     if (i < T) {
-      const float2* src = tile + i * BP + b;
+      const float2* src = tile + i * g.BP + g.b;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[m][r] = src[r * T * BP];
+      for (int r = 0; r < R; ++r) v[m][r] = src[r * T * g.BP];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
-    const int i = i0 + m * S;
+    const int i = g.i0 + m * g.S;
     if (i < T) {
-      const int k = i % p;
+      const int k = (pmask >= 0) ? (i & pmask) : (i % p);
       if (p > 1) {
+        const float2* w = tws + k * (R - 1) - 1;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          const float2 t = tw[r * k * stride];
+          const float2 t = w[r];
           v[m][r] = INV ? cmulc(v[m][r], t) : cmul(v[m][r], t);
         }
       }
       Dft<R, INV>::run(v[m]);
-      float2* dst = tile + ((i - k) * R + k) * BP + b;
+      float2* dst = tile + ((i - k) * R + k) * g.BP + g.b;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * p * BP] = v[m][r];
+      for (int r = 0; r < R; ++r) dst[r * p * g.BP] = v[m][r];
     }
   }
   __syncthreads();
 }
 
-// All stages of plan `pl` over the 2^lgB columns of the tile. The caller has synchronised after filling the tile.
+// All stages of plan `pl` over the B columns of the tile (row pitch B + 1). tw is the plan's per-stage twiddle
+// table. The caller has synchronised after filling the tile.
 template <bool INV>
-__device__ void fft_tile(float2* tile, int BP, const float2* tw, int tmul, const Plan1D& pl, int lgB, int tid) {
+__device__ void fft_tile(float2* tile, const float2* tw, const Plan1D& pl, int B, int tid) {
+  const TileGeom g(B, tid);
   const int n = pl.n;
-  int p = 1;
   for (int s = 0; s < pl.nst; ++s) {
-    const int R = pl.radix[s];
-    switch (R) {
-      case 8: fft_stage<8, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
-      case 4: fft_stage<4, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
-      case 2: fft_stage<2, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
-      case 3: fft_stage<3, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
-      default: fft_stage<5, INV>(tile, BP, tw, tmul, n, lgB, p, tid); break;
+    const float2* tws = tw + pl.tw_off[s];
+    const int p = pl.p[s], pm = pl.pmask[s];
+    switch (pl.radix[s]) {
+      case 16: fft_stage<16, INV>(tile, tws, n, p, pm, g); break;
+      case 8: fft_stage<8, INV>(tile, tws, n, p, pm, g); break;
+      case 4: fft_stage<4, INV>(tile, tws, n, p, pm, g); break;
+      case 2: fft_stage<2, INV>(tile, tws, n, p, pm, g); break;
+      case 3: fft_stage<3, INV>(tile, tws, n, p, pm, g); break;
+      default: fft_stage<5, INV>(tile, tws, n, p, pm, g); break;
     }
-    p *= R;
   }
 }
 
-// tw[m] = exp(-2 pi i m / len), m < len, rounded from FP64 (no barrier: the caller synchronises).
-__device__ __forceinline__ void fill_twiddles(float2* tw, int len, int tid) {
-  for (int m = tid; m < len; m += kFftNT) {
-    double s, c;
-    sincospi(-2.0 * m / len, &s, &c);
-    tw[m] = make_float2(static_cast<float>(c), static_cast<float>(s));
+// Fill the per-stage twiddle table of plan `pl` (n - 1 entries), rounded from FP64. No barrier.
+__device__ __forceinline__ void fill_stage_twiddles(float2* tw, const Plan1D& pl, int tid) {
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.radix[s], p = pl.p[s], cnt = p * (R - 1);
+    if (p == 1) continue;
+    const double inv = 1.0 / (static_cast<double>(p) * R);
+    for (int idx = tid; idx < cnt; idx += kFftNT) {
+      const int k = idx / (R - 1), r = idx - k * (R - 1) + 1;
+      double sn, cs;
+      sincospi(-2.0 * (r * k) * inv, &sn, &cs);
+      tw[pl.tw_off[s] + idx] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
+    }
+  }
+}
+
+// roots[k] = exp(-2 pi i k / n) for k <= n / 2 (the real-transform split), rounded from FP64. No barrier.
+__device__ __forceinline__ void fill_half_roots(float2* roots, int n, int tid) {
+  for (int k = tid; k <= n / 2; k += kFftNT) {
+    double sn, cs;
+    sincospi(-2.0 * k / n, &sn, &cs);
+    roots[k] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
   }
 }
 

@@ -14,16 +14,22 @@ constexpr int kNT = 256;           // threads per workgroup of the particle and 
 constexpr int kFftNT = 512;        // threads per workgroup of the FFT kernels
 constexpr int kTileElems = 8192;   // complex values per LDS FFT tile (64 KiB)
 constexpr int kFracBits = 16;      // fixed-point fractional bits per axis of the CIC deposit
-constexpr int kMaxStages = 10;
+constexpr int kMaxStages = 7;
 
 // Device error flags, one int each, at the start of every workspace.
 enum { kFlagOverflow = 0, kFlagNonfinite = 1, kNumFlags = 2 };
 
-// One 1-D transform length factored into radix stages (applied in order; radices 2, 3, 4, 5, 8).
+// One 1-D transform length factored into radix stages (applied in order; radices 2, 3, 4, 5, 8). For stage s,
+// p[s] is the product of the earlier radices, pmask[s] = p[s] - 1 when p[s] is a power of two (else -1), and the
+// stage's twiddles W_{p R}^{r k} (k < p, 1 <= r < R) sit at tw_off[s] + k (R - 1) + r - 1 of the twiddle table
+// (n - 1 entries in all).
 struct Plan1D {
   int n;
   int nst;
   int radix[kMaxStages];
+  int p[kMaxStages];
+  int pmask[kMaxStages];
+  int tw_off[kMaxStages];
 };
 
 bool make_plan(int n, Plan1D* p);        // false if n has a prime factor > 5 or n < 1
