@@ -126,6 +126,33 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
                          const double* a_list, int32_t n_a, const lpc_particles* inout, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* One box of a batched run: its geometry (n_side unused) and its device particles (pos, vel, psi1, psi2). */
+typedef struct {
+  lpc_geometry geom;
+  lpc_particles particles;
+} lpc_batch_entry;
+
+/* Workspace bytes of lpc_cola_step_batched for these n_real entries (0 if any mesh size is unsupported):
+ * flags, the job tables and, per entry in order, its own int64/force mesh and three half-spectrum meshes. */
+size_t lpc_workspace_bytes_batched(const lpc_batch_entry* entries, int32_t n_real);
+
+/* The run of lpc_cola_step (Sec. 2.3 integrator, Sec. 2.4 force) for n_real independent boxes at once: the many
+ * independent realisations (mocks) that a covariance estimate needs (Sec. 1). The boxes may differ in mesh
+ * size, box side and particle count; they share the cosmology, the stepping options and the time list. Every stage
+ * (deposit, each FFT pass, Poisson, gather/kick/drift) is ONE launch over all boxes, whose workgroups take the
+ * (box, tile) items of a work table; the results equal n_real separate lpc_cola_step calls bit for bit.
+ * `entries` is a host array of 1..4096 entries; `ws` holds lpc_workspace_bytes_batched(entries, n_real) bytes.
+ * The enqueued kernels are recorded once into a HIP graph and replayed while every argument (entries, cosmology,
+ * stepping, time list, workspace pointer) repeats; lpc_graph_enable(0) launches them directly instead. The graph
+ * cache is process-wide: batched calls must not overlap across threads. */
+lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real, const lpc_cosmology* cosmo,
+                                 const lpc_stepping* step, const double* a_list, int32_t n_a, void* ws,
+                                 size_t ws_bytes, void* stream);
+
+/* Switch graph replay of lpc_cola_step_batched on (default) or off. Profiling (lpc_profile_enable) also turns it
+ * off, since per-stage events are recorded between launches. */
+lpc_status lpc_graph_enable(int32_t on);
+
 /* Binned power spectrum of the particles (periodic box; Sec. 7.1): fixed-point CIC deposit on the Nm mesh,
  * r2c FFT, P = L^3 |delta_hat|^2 / (Nm^6 W^2) (one CIC window removed in amplitude), bins [b dk, (b+1) dk) of |k|
  * with dk = k_max / n_bins, the k = 0 mode excluded, half-spectrum modes with 0 < n_z < Nm/2 counted twice.

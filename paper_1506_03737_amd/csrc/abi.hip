@@ -2,6 +2,7 @@
 // the sequence of kernel launches for each entry point. No C++ exception crosses this boundary.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -105,6 +106,7 @@ void stage(const char* name, hipStream_t s, F f) {
 
 constexpr size_t kAlign = 256;
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int round8(int x) { return (x + 7) / 8 * 8; }
 
 bool fft_size_ok(int n) {
   if (n < 8 || n > 1024 || (n % 2) != 0) return false;
@@ -112,23 +114,24 @@ bool fft_size_ok(int n) {
   return kern::make_plan(n, &p) && kern::make_plan(n / 2, &p);
 }
 
-// Workspace plan of one operation on an n^3 mesh: flags first, then 256-byte aligned regions.
+constexpr size_t kJobRegion = size_t(1) << 20;  // device bytes reserved for the job tables of one call
+
+// Workspace plan of one operation on an n^3 mesh: flags, the job-table region, then 256-byte aligned regions.
 struct Plan {
-  size_t flags = 0, dens = 0, A = 0, B = 0, C = 0, bins = 0, total = 0;
-  size_t complex_elems = 0;  // float2 per complex mesh
+  size_t flags = 0, jobs = 0, dens = 0, A = 0, B = 0, C = 0, bins = 0, total = 0;
 };
 
-Plan make_ws_plan(int n, int op, int n_bins = 0) {
+Plan make_ws_plan(int n, int op) {
   Plan p;
   const size_t M = static_cast<size_t>(n) * n * n;
-  p.complex_elems = static_cast<size_t>(n) * n * kern::mesh_pitch(n);
-  const size_t cbytes = round_up(p.complex_elems * sizeof(float2));
+  const size_t cbytes = round_up(static_cast<size_t>(n) * n * kern::mesh_pitch(n) * sizeof(float2));
   size_t off = round_up(sizeof(int) * kern::kNumFlags);
   auto take = [&off](size_t bytes) {
     size_t at = off;
     off += round_up(bytes);
     return at;
   };
+  p.jobs = take(kJobRegion);
   switch (op) {
     case LPC_OP_PM_FORCE:
     case LPC_OP_COLA_STEP:
@@ -144,7 +147,7 @@ Plan make_ws_plan(int n, int op, int n_bins = 0) {
     case LPC_OP_POWER_SPECTRUM:
       p.dens = take(M * 8);
       p.A = take(cbytes);
-      p.bins = take(static_cast<size_t>(n_bins > 0 ? n_bins : 2048) * 3 * sizeof(double));
+      p.bins = take(static_cast<size_t>(2048) * 3 * sizeof(double));
       break;
     case LPC_OP_FFT:
       break;
@@ -206,45 +209,325 @@ lpc_status guarded(F body) {
 
 char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
-// Forward r2c of an FP32 real mesh, then y and x passes (in place on `out`).
-void r2c_real(const float* in, int n, float2* out, hipStream_t s) {
-  const int pitch = kern::mesh_pitch(n), nh = n / 2 + 1;
-  stage("fft z r2c", s, [&] { return kern::fft_z_r2c_real(in, n, out, pitch, s); });
-  stage("fft y", s, [&] { return kern::fft_axis(out, n, pitch, static_cast<int64_t>(n) * pitch, n, nh, 1, 0, false, s); });
-  stage("fft x", s, [&] { return kern::fft_axis(out, n, static_cast<int64_t>(n) * pitch, pitch, n, nh, 1, 0, false, s); });
+// ---------------------------------------------------------------------------------------------------------------
+// Job tables. A call collects the jobs of every launch it will make into one host buffer, uploads it once into the
+// workspace's job region (stream ordered), and then launches with device pointers into that region.
+struct Section {
+  size_t jobs_off = 0, offs_off = 0;
+  int njob = 0, total = 0;
+};
+
+class JobPack {
+ public:
+  // Append `jobs` with `items[i]` work items each (rounded up to multiples of 8); returns the section handle.
+  template <class J>
+  Section add(const std::vector<J>& jobs, const std::vector<int>& items) {
+    Section s;
+    s.njob = static_cast<int>(jobs.size());
+    std::vector<int> offs(jobs.size() + 1, 0);
+    for (size_t i = 0; i < jobs.size(); ++i) offs[i + 1] = offs[i] + round8(items[i]);
+    s.total = offs.back();
+    s.jobs_off = append(jobs.data(), jobs.size() * sizeof(J));
+    s.offs_off = append(offs.data(), offs.size() * sizeof(int));
+    return s;
+  }
+  template <class J>
+  Section add1(const J& job, int items) {
+    return add(std::vector<J>{job}, std::vector<int>{items});
+  }
+  size_t bytes() const { return host_.size(); }
+  void upload(char* dev, hipStream_t s) {
+    if (host_.size() > kJobRegion) throw HipError{hipErrorInvalidValue, "job tables exceed the workspace job region"};
+    dev_ = dev;
+    check(hipMemcpyAsync(dev, host_.data(), host_.size(), hipMemcpyHostToDevice, s), "upload job tables");
+  }
+  template <class J>
+  const J* jobs(const Section& s) const {
+    return reinterpret_cast<const J*>(dev_ + s.jobs_off);
+  }
+  kern::WorkTable table(const Section& s) const {
+    return kern::WorkTable{reinterpret_cast<const int*>(dev_ + s.offs_off), s.njob, s.total};
+  }
+
+ private:
+  size_t append(const void* p, size_t n) {
+    const size_t at = (host_.size() + 63) / 64 * 64;
+    host_.resize(at + n);
+    std::memcpy(host_.data() + at, p, n);
+    return at;
+  }
+  std::vector<char> host_;
+  char* dev_ = nullptr;
+};
+
+Plan1D plan_of(int n) {
+  Plan1D p;
+  if (!kern::make_plan(n, &p)) throw HipError{hipErrorInvalidValue, "unsupported FFT length"};
+  return p;
 }
 
-// Inverse x and y passes in place on `spec`, then c2r into `out` times `scale`.
-void c2r_real(float2* spec, int n, float* out, float scale, hipStream_t s) {
-  const int pitch = kern::mesh_pitch(n), nh = n / 2 + 1;
-  stage("fft x inv", s, [&] { return kern::fft_axis(spec, n, static_cast<int64_t>(n) * pitch, pitch, n, nh, 1, 0, true, s); });
-  stage("fft y inv", s, [&] { return kern::fft_axis(spec, n, pitch, static_cast<int64_t>(n) * pitch, n, nh, 1, 0, true, s); });
-  stage("fft z c2r", s, [&] { return kern::fft_z_c2r_real(spec, n, pitch, out, scale, s); });
+// One 3-D transform on an n^3 mesh: the jobs of its passes.
+struct R2CSections {
+  Section z, y, x;
+  int Bz, Bax;
+  size_t lds_z, lds_ax;
+};
+struct C2RSections {
+  Section x, y, z;
+  int Bax, R;
+  size_t lds_ax, lds_z;
+};
+
+kern::AxisJob axis_job(float2* base, int n, int64_t astr, int64_t ostr, int64_t cstr, int B) {
+  kern::AxisJob a{};
+  a.base = base;
+  a.astr = astr;
+  a.ostr = ostr;
+  a.cstr = cstr;
+  a.n = n;
+  a.ncols = n / 2 + 1;
+  a.ntc = (a.ncols + B - 1) / B;
+  a.per_comp = round8(n * a.ntc);
+  a.pl = plan_of(n);
+  return a;
 }
 
-// The mesh part of the PM force: deposit -> delta -> FFT -> Poisson/gradient -> 3 inverse FFTs -> AoS force mesh.
-// Returns the force mesh (float[nm^3][3]) in the workspace.
-float* force_mesh(const float* pos, int64_t n, int nm, double box, int deconv, void* ws, const Plan& p,
-                  uint64_t* dens_override, int* flags, hipStream_t s) {
-  const size_t M = static_cast<size_t>(nm) * nm * nm;
-  const int pitch = kern::mesh_pitch(nm), nh = nm / 2 + 1;
-  uint64_t* dens = dens_override ? dens_override : reinterpret_cast<uint64_t*>(at(ws, p.dens));
-  float2* A = reinterpret_cast<float2*>(at(ws, p.A));
-  float2* B = reinterpret_cast<float2*>(at(ws, p.B));
-  float2* C = reinterpret_cast<float2*>(at(ws, p.C));
-  float* force = reinterpret_cast<float*>(at(ws, p.dens));
-  const double scale = (static_cast<double>(nm) * 65536.0) / box;
-  const double mscale = (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48;
-  stage("fill density", s, [&] { return kern::fill_u64(dens, M, s); });
-  stage("deposit", s, [&] { return kern::deposit(pos, n, nm, scale, dens, flags, s); });
-  stage("fft z r2c", s, [&] { return kern::fft_z_r2c_fixed(dens, nm, mscale, A, pitch, flags, s); });
-  stage("fft y", s, [&] { return kern::fft_axis(A, nm, pitch, static_cast<int64_t>(nm) * pitch, nm, nh, 1, 0, false, s); });
-  stage("fft x + poisson", s, [&] { return kern::fft_x_poisson(A, B, C, nm, pitch, box, deconv, s); });
-  const int64_t cstride = static_cast<int64_t>(B - A);
-  if (C - B != B - A) throw HipError{hipErrorInvalidValue, "workspace layout"};
-  stage("fft y inv", s, [&] { return kern::fft_axis(A, nm, pitch, static_cast<int64_t>(nm) * pitch, nm, nh, 3, cstride, true, s); });
-  stage("fft z c2r", s, [&] { return kern::fft_z_c2r_aos3(A, B, C, nm, pitch, force, s); });
-  return force;
+// forward r2c of a real FP32 mesh (fixed = false) or of int64 counts (fixed = true, delta = C mscale - 1)
+R2CSections add_r2c(JobPack& jp, const void* in, bool fixed, double mscale, int n, float2* out) {
+  R2CSections r;
+  const int pitch = kern::mesh_pitch(n);
+  r.Bz = std::max(8, kern::z_rows(n, 1));
+  r.Bax = kern::strided_cols(n);
+  r.lds_z = kern::lds_z_r2c(n, r.Bz);
+  r.lds_ax = kern::lds_axis(n, r.Bax);
+  kern::ZR2CJob z{};
+  z.in = in;
+  z.out = out;
+  z.mscale = mscale;
+  z.n = n;
+  z.nrows = n * n;
+  z.pitch = pitch;
+  z.pl = plan_of(n / 2);
+  r.z = jp.add1(z, (z.nrows + r.Bz - 1) / r.Bz);
+  kern::AxisJob y = axis_job(out, n, pitch, static_cast<int64_t>(n) * pitch, 0, r.Bax);
+  r.y = jp.add1(y, y.per_comp);
+  kern::AxisJob x = axis_job(out, n, static_cast<int64_t>(n) * pitch, pitch, 0, r.Bax);
+  r.x = jp.add1(x, x.per_comp);
+  (void)fixed;
+  return r;
+}
+
+C2RSections add_c2r(JobPack& jp, float2* spec, int n, float* out, float scale) {
+  C2RSections c;
+  const int pitch = kern::mesh_pitch(n);
+  c.Bax = kern::strided_cols(n);
+  c.R = std::max(8, kern::z_rows(n, 1));
+  c.lds_ax = kern::lds_axis(n, c.Bax);
+  c.lds_z = kern::lds_z_c2r(n, c.R);
+  kern::AxisJob x = axis_job(spec, n, static_cast<int64_t>(n) * pitch, pitch, 0, c.Bax);
+  c.x = jp.add1(x, x.per_comp);
+  kern::AxisJob y = axis_job(spec, n, pitch, static_cast<int64_t>(n) * pitch, 0, c.Bax);
+  c.y = jp.add1(y, y.per_comp);
+  kern::ZC2RJob z{};
+  z.in0 = z.in1 = z.in2 = spec;
+  z.out = out;
+  z.n = n;
+  z.nrows = n * n;
+  z.pitch = pitch;
+  z.scale = scale;
+  z.pl = plan_of(n / 2);
+  c.z = jp.add1(z, (z.nrows + c.R - 1) / c.R);
+  return c;
+}
+
+void run_r2c(const JobPack& jp, const R2CSections& r, bool fixed, int* flags, hipStream_t s) {
+  stage("fft z r2c", s, [&] {
+    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(r.z), jp.table(r.z), fixed, r.Bz, r.lds_z, flags, s);
+  });
+  stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.y), jp.table(r.y), false, r.Bax, r.lds_ax, s); });
+  stage("fft x", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.x), jp.table(r.x), false, r.Bax, r.lds_ax, s); });
+}
+
+void run_c2r(const JobPack& jp, const C2RSections& c, hipStream_t s) {
+  stage("fft x inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(c.x), jp.table(c.x), true, c.Bax, c.lds_ax, s); });
+  stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(c.y), jp.table(c.y), true, c.Bax, c.lds_ax, s); });
+  stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(c.z), jp.table(c.z), 1, c.R, c.lds_z, s); });
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// The PM force of a batch of boxes: every stage is one launch over all boxes.
+struct ForceBox {
+  int nm;
+  double box;
+  int64_t n;
+  float* pos;
+  float* vel;
+  const float* psi1;
+  const float* psi2;
+  float* grad;        // pm_force output (or NULL)
+  uint64_t* dens;     // int64 counts
+  float2 *A, *B, *C;  // three half-spectrum meshes (contiguous: B = A + stride, C = B + stride)
+  float* force;       // AoS float3 force mesh
+};
+
+struct ForceProgram {
+  Section fill, parts, frame, zr2c, yfwd, pois, yinv, zc2r;
+  int Bz = 32, Bax = 32, Bp = 16, R3 = 16;
+  size_t lds_z = 0, lds_ax = 0, lds_p = 0, lds_c = 0;
+};
+
+ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, int deconv) {
+  ForceProgram f;
+  for (const ForceBox& b : boxes) {
+    f.Bz = std::min(f.Bz, std::max(8, kern::z_rows(b.nm, 1)));
+    f.Bax = std::min(f.Bax, kern::strided_cols(b.nm));
+    f.Bp = std::min(f.Bp, std::min(16, kern::strided_cols(b.nm)));
+    f.R3 = std::min(f.R3, std::max(4, std::min(16, kern::z_rows(b.nm, 3))));
+  }
+  std::vector<kern::FillJob> fills;
+  std::vector<kern::PartJob> parts;
+  std::vector<kern::ZR2CJob> zs;
+  std::vector<kern::AxisJob> ys, yis;
+  std::vector<kern::PoissonJob> ps;
+  std::vector<kern::ZC2RJob> cs;
+  std::vector<int> i_fill, i_part, i_frame, i_z, i_y, i_yi, i_p, i_c;
+  for (const ForceBox& b : boxes) {
+    const int nm = b.nm, pitch = kern::mesh_pitch(nm), nh = nm / 2 + 1;
+    const int64_t M = static_cast<int64_t>(nm) * nm * nm;
+    fills.push_back(kern::FillJob{b.dens, M});
+    i_fill.push_back(kern::fill_items(M));
+    kern::PartJob pj{};
+    pj.pos = b.pos;
+    pj.vel = b.vel;
+    pj.psi1 = b.psi1;
+    pj.psi2 = b.psi2;
+    pj.n = b.n;
+    pj.dens = b.dens;
+    pj.force = b.force;
+    pj.grad = b.grad;
+    pj.nm = nm;
+    pj.box = static_cast<float>(b.box);
+    pj.scale = (static_cast<double>(nm) * 65536.0) / b.box;
+    parts.push_back(pj);
+    i_part.push_back(static_cast<int>((b.n + kern::kNT - 1) / kern::kNT));
+    i_frame.push_back(static_cast<int>((3 * b.n + kern::kNT - 1) / kern::kNT));
+    kern::ZR2CJob z{};
+    z.in = b.dens;
+    z.out = b.A;
+    z.mscale = (static_cast<double>(M) / static_cast<double>(b.n)) * 0x1.0p-48;
+    z.n = nm;
+    z.nrows = nm * nm;
+    z.pitch = pitch;
+    z.pl = plan_of(nm / 2);
+    zs.push_back(z);
+    i_z.push_back((z.nrows + f.Bz - 1) / f.Bz);
+    kern::AxisJob y = axis_job(b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, 0, f.Bax);
+    ys.push_back(y);
+    i_y.push_back(y.per_comp);
+    kern::AxisJob yi = axis_job(b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, static_cast<int64_t>(b.B - b.A), f.Bax);
+    yis.push_back(yi);
+    i_yi.push_back(3 * yi.per_comp);
+    kern::PoissonJob p{};
+    p.A = b.A;
+    p.B = b.B;
+    p.C = b.C;
+    p.nm = nm;
+    p.pitch = pitch;
+    p.ntc = (nh + f.Bp - 1) / f.Bp;
+    p.deconv = deconv;
+    p.kf = static_cast<float>(2.0 * M_PI / b.box);
+    p.inv_m3 = static_cast<float>(1.0 / static_cast<double>(M));
+    p.pl = plan_of(nm);
+    ps.push_back(p);
+    i_p.push_back(nm * p.ntc);
+    kern::ZC2RJob c{};
+    c.in0 = b.A;
+    c.in1 = b.B;
+    c.in2 = b.C;
+    c.out = b.force;
+    c.n = nm;
+    c.nrows = nm * nm;
+    c.pitch = pitch;
+    c.scale = 1.0f;
+    c.pl = plan_of(nm / 2);
+    cs.push_back(c);
+    i_c.push_back((c.nrows + f.R3 - 1) / f.R3);
+    f.lds_z = std::max(f.lds_z, kern::lds_z_r2c(nm, f.Bz));
+    f.lds_ax = std::max(f.lds_ax, kern::lds_axis(nm, f.Bax));
+    f.lds_p = std::max(f.lds_p, kern::lds_x_poisson(nm, f.Bp));
+    f.lds_c = std::max(f.lds_c, kern::lds_z_c2r(nm, 3 * f.R3));
+  }
+  f.fill = jp.add(fills, i_fill);
+  f.parts = jp.add(parts, i_part);
+  f.frame = jp.add(parts, i_frame);
+  f.zr2c = jp.add(zs, i_z);
+  f.yfwd = jp.add(ys, i_y);
+  f.pois = jp.add(ps, i_p);
+  f.yinv = jp.add(yis, i_yi);
+  f.zc2r = jp.add(cs, i_c);
+  return f;
+}
+
+// deposit -> delta -> forward FFT -> Poisson/gradient -> inverse FFTs -> AoS force meshes, for every box
+void run_force_mesh(const JobPack& jp, const ForceProgram& f, int* flags, hipStream_t s) {
+  stage("fill density", s, [&] { return kern::launch_fill(jp.jobs<kern::FillJob>(f.fill), jp.table(f.fill), s); });
+  stage("deposit", s, [&] { return kern::launch_deposit(jp.jobs<kern::PartJob>(f.parts), jp.table(f.parts), flags, s); });
+  stage("fft z r2c", s, [&] {
+    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), true, f.Bz, f.lds_z, flags, s);
+  });
+  stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.lds_ax, s); });
+  stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.lds_p, s); });
+  stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yinv), jp.table(f.yinv), true, f.Bax, f.lds_ax, s); });
+  stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(f.zc2r), jp.table(f.zc2r), 3, f.R3, f.lds_c, s); });
+}
+
+// The whole COLA run over a_list for every box (all boxes share cosmology, stepping and time list).
+void run_cola(const JobPack& jp, const ForceProgram& f, const std::vector<double>& tab, int n_a, double om, bool cola,
+              int* flags, hipStream_t s) {
+  auto row = [&tab](int i) { return tab.data() + static_cast<size_t>(i) * host::kCoefColumns; };
+  const kern::PartJob* pj = jp.jobs<kern::PartJob>(f.parts);
+  if (cola) {
+    const float f1 = static_cast<float>(-row(0)[host::kF1]), f2 = static_cast<float>(-row(0)[host::kF2]);
+    stage("frame velocity", s, [&] { return kern::launch_frame(jp.jobs<kern::PartJob>(f.frame), jp.table(f.frame), f1, f2, s); });
+  }
+  for (int i = 0; i < n_a; ++i) {
+    const double* r = row(i);
+    run_force_mesh(jp, f, flags, s);
+    kern::KickDrift kd;
+    kd.kick = static_cast<float>(r[host::kK] * (-1.5 * om));
+    kd.d1 = static_cast<float>(r[host::kD1]);
+    kd.d2m = static_cast<float>(r[host::kD2] - r[host::kD1] * r[host::kD1]);
+    kd.drift = static_cast<float>(r[host::kQ]);
+    kd.dd1 = static_cast<float>(r[host::kDD1]);
+    kd.dd2 = static_cast<float>(r[host::kDD2]);
+    kd.do_drift = (i + 1 < n_a) ? 1 : 0;
+    kd.cola = cola ? 1 : 0;
+    stage("gather kick drift", s, [&] { return kern::launch_gather_kick_drift(pj, jp.table(f.parts), kd, flags, s); });
+  }
+  if (cola) {
+    const double* r = row(n_a - 1);
+    const float f1 = static_cast<float>(r[host::kF1]), f2 = static_cast<float>(r[host::kF2]);
+    stage("frame velocity", s, [&] { return kern::launch_frame(jp.jobs<kern::PartJob>(f.frame), jp.table(f.frame), f1, f2, s); });
+  }
+}
+
+ForceBox force_box(void* ws, const Plan& p, int nm, double box, int64_t n, float* pos, float* vel, const float* psi1,
+                   const float* psi2, float* grad, uint64_t* dens_override) {
+  ForceBox b{};
+  b.nm = nm;
+  b.box = box;
+  b.n = n;
+  b.pos = pos;
+  b.vel = vel;
+  b.psi1 = psi1;
+  b.psi2 = psi2;
+  b.grad = grad;
+  b.dens = dens_override ? dens_override : reinterpret_cast<uint64_t*>(at(ws, p.dens));
+  b.A = reinterpret_cast<float2*>(at(ws, p.A));
+  b.B = reinterpret_cast<float2*>(at(ws, p.B));
+  b.C = reinterpret_cast<float2*>(at(ws, p.C));
+  b.force = reinterpret_cast<float*>(at(ws, p.dens));
+  return b;
 }
 
 lpc_status check_geom_mesh(const lpc_geometry* g) {
@@ -260,6 +543,31 @@ lpc_status check_particles(const lpc_particles* p, bool need_psi) {
   if (p->n > 0 && need_psi && (!p->psi1 || !p->psi2)) return fail(LPC_ERR_INVALID_ARG, "psi1/psi2 is NULL");
   if (p->n > (int64_t(1) << 31) - 1) return fail(LPC_ERR_INVALID_ARG, "n exceeds 2^31 - 1");
   return LPC_OK;
+}
+
+lpc_status check_stepping(const lpc_stepping* step) {
+  if (!step) return fail(LPC_ERR_INVALID_ARG, "stepping is NULL");
+  if (step->deconv_power < 0 || step->deconv_power > 2) return fail(LPC_ERR_INVALID_ARG, "deconv_power not in 0..2");
+  if (step->reserved != 0) return fail(LPC_ERR_INVALID_ARG, "stepping.reserved must be 0");
+  return LPC_OK;
+}
+
+// Cached hipGraph of one batched run: replayed while the call's arguments stay the same.
+struct GraphCache {
+  std::vector<char> key;
+  hipGraphExec_t exec = nullptr;
+};
+GraphCache g_graph;
+bool g_graph_on = true;
+
+// The stream batched runs are captured on (capture only records launches; the graph runs on the caller's stream).
+hipStream_t capture_stream() {
+  static hipStream_t cs = [] {
+    hipStream_t st;
+    check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    return st;
+  }();
+  return cs;
 }
 
 }  // namespace
@@ -353,11 +661,13 @@ lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, cons
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    const int nm = geom->n_mesh;
-    float* F = force_mesh(pos, n, nm, geom->box, step->deconv_power, ws, p,
-                          reinterpret_cast<uint64_t*>(density_fixed_out), flags, s);
-    const double scale = (static_cast<double>(nm) * 65536.0) / geom->box;
-    stage("gather", s, [&] { return kern::gather(pos, n, F, nm, scale, grad_out, flags, s); });
+    JobPack jp;
+    const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, n, const_cast<float*>(pos), nullptr, nullptr, nullptr,
+                                 grad_out, reinterpret_cast<uint64_t*>(density_fixed_out));
+    const ForceProgram f = add_force(jp, {b}, step->deconv_power);
+    jp.upload(at(ws, p.jobs), s);
+    run_force_mesh(jp, f, flags, s);
+    stage("gather", s, [&] { return kern::launch_gather(jp.jobs<kern::PartJob>(f.parts), jp.table(f.parts), flags, s); });
     return finish(flags, s);
   });
 }
@@ -367,9 +677,7 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
                          void* stream) {
   if (lpc_status st = check_geom_mesh(geom)) return st;
   if (lpc_status st = check_cosmo(cosmo)) return st;
-  if (!step) return fail(LPC_ERR_INVALID_ARG, "stepping is NULL");
-  if (step->deconv_power < 0 || step->deconv_power > 2) return fail(LPC_ERR_INVALID_ARG, "deconv_power not in 0..2");
-  if (step->reserved != 0) return fail(LPC_ERR_INVALID_ARG, "stepping.reserved must be 0");
+  if (lpc_status st = check_stepping(step)) return st;
   if (lpc_status st = check_particles(inout, step->cola != 0)) return st;
   if (inout->n == 0) return fail(LPC_ERR_INVALID_ARG, "no particles");
   std::vector<double> tab(static_cast<size_t>(n_a > 0 ? n_a : 0) * host::kCoefColumns);
@@ -380,35 +688,134 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    const int nm = geom->n_mesh;
-    const int64_t n = inout->n;
+    JobPack jp;
+    const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, inout->n, inout->pos, inout->vel, inout->psi1,
+                                 inout->psi2, nullptr, nullptr);
+    const ForceProgram f = add_force(jp, {b}, step->deconv_power);
+    jp.upload(at(ws, p.jobs), s);
+    run_cola(jp, f, tab, n_a, cosmo->omega_m, step->cola != 0, flags, s);
+    return finish(flags, s);
+  });
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Batched form: workspace = flags, job region, then per box its int64/force mesh and three half spectra.
+static bool batch_layout(const lpc_batch_entry* e, int32_t n_real, std::vector<size_t>* offs, size_t* total) {
+  if (!e || n_real < 1) return false;
+  size_t off = round_up(sizeof(int) * kern::kNumFlags) + round_up(kJobRegion);
+  if (offs) offs->clear();
+  for (int i = 0; i < n_real; ++i) {
+    const int nm = e[i].geom.n_mesh;
+    if (!fft_size_ok(nm)) return false;
+    const size_t M = static_cast<size_t>(nm) * nm * nm;
+    const size_t cbytes = round_up(static_cast<size_t>(nm) * nm * kern::mesh_pitch(nm) * sizeof(float2));
+    if (offs) offs->push_back(off);
+    off += round_up(M * 12) + 3 * cbytes;
+  }
+  *total = off;
+  return true;
+}
+
+size_t lpc_workspace_bytes_batched(const lpc_batch_entry* entries, int32_t n_real) {
+  size_t total = 0;
+  return batch_layout(entries, n_real, nullptr, &total) ? total : 0;
+}
+
+lpc_status lpc_graph_enable(int32_t on) {
+  g_graph_on = (on != 0);
+  return LPC_OK;
+}
+
+lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real, const lpc_cosmology* cosmo,
+                                 const lpc_stepping* step, const double* a_list, int32_t n_a, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  if (!entries || n_real < 1 || n_real > 4096) return fail(LPC_ERR_INVALID_ARG, "need 1..4096 batch entries");
+  if (lpc_status st = check_cosmo(cosmo)) return st;
+  if (lpc_status st = check_stepping(step)) return st;
+  for (int i = 0; i < n_real; ++i) {
+    if (lpc_status st = check_geom_mesh(&entries[i].geom)) return fail(st, "entry %d: %s", i, g_error.c_str());
+    if (lpc_status st = check_particles(&entries[i].particles, step->cola != 0))
+      return fail(st, "entry %d: %s", i, g_error.c_str());
+    if (entries[i].particles.n == 0) return fail(LPC_ERR_INVALID_ARG, "entry %d has no particles", i);
+  }
+  std::vector<double> tab(static_cast<size_t>(n_a > 0 ? n_a : 0) * host::kCoefColumns);
+  if (lpc_status st = lpc_cola_coefficients(cosmo, step, a_list, n_a, tab.data())) return st;
+  std::vector<size_t> offs;
+  size_t need = 0;
+  batch_layout(entries, n_real, &offs, &need);
+  if (lpc_status st = check_ws(ws, ws_bytes, need)) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() {
+    int* flags = reinterpret_cast<int*>(ws);
+    stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
+    JobPack jp;
+    std::vector<ForceBox> boxes;
+    for (int i = 0; i < n_real; ++i) {
+      const lpc_batch_entry& e = entries[i];
+      const int nm = e.geom.n_mesh;
+      const size_t M = static_cast<size_t>(nm) * nm * nm;
+      const size_t cbytes = round_up(static_cast<size_t>(nm) * nm * kern::mesh_pitch(nm) * sizeof(float2));
+      char* base = at(ws, offs[i]);
+      ForceBox b{};
+      b.nm = nm;
+      b.box = e.geom.box;
+      b.n = e.particles.n;
+      b.pos = e.particles.pos;
+      b.vel = e.particles.vel;
+      b.psi1 = e.particles.psi1;
+      b.psi2 = e.particles.psi2;
+      b.dens = reinterpret_cast<uint64_t*>(base);
+      b.force = reinterpret_cast<float*>(base);
+      b.A = reinterpret_cast<float2*>(base + round_up(M * 12));
+      b.B = reinterpret_cast<float2*>(base + round_up(M * 12) + cbytes);
+      b.C = reinterpret_cast<float2*>(base + round_up(M * 12) + 2 * cbytes);
+      boxes.push_back(b);
+    }
+    const ForceProgram f = add_force(jp, boxes, step->deconv_power);
+    char* jobs_dev = at(ws, round_up(sizeof(int) * kern::kNumFlags));
+    jp.upload(jobs_dev, s);
     const bool cola = step->cola != 0;
-    const double om = cosmo->omega_m;
-    const double scale = (static_cast<double>(nm) * 65536.0) / geom->box;
-    auto row = [&tab](int i) { return tab.data() + static_cast<size_t>(i) * host::kCoefColumns; };
-    if (cola)
-      stage("frame velocity", s, [&] { return kern::frame_velocity(inout->vel, inout->psi1, inout->psi2, n, static_cast<float>(-row(0)[host::kF1]),
-                                 static_cast<float>(-row(0)[host::kF2]), s); });
-    for (int i = 0; i < n_a; ++i) {
-      const double* r = row(i);
-      float* F = force_mesh(inout->pos, n, nm, geom->box, step->deconv_power, ws, p, nullptr, flags, s);
-      kern::KickDrift kd;
-      kd.kick = static_cast<float>(r[host::kK] * (-1.5 * om));
-      kd.d1 = static_cast<float>(r[host::kD1]);
-      kd.d2m = static_cast<float>(r[host::kD2] - r[host::kD1] * r[host::kD1]);
-      kd.drift = static_cast<float>(r[host::kQ]);
-      kd.dd1 = static_cast<float>(r[host::kDD1]);
-      kd.dd2 = static_cast<float>(r[host::kDD2]);
-      kd.do_drift = (i + 1 < n_a) ? 1 : 0;
-      kd.cola = cola ? 1 : 0;
-      stage("gather kick drift", s, [&] { return kern::gather_kick_drift(inout->pos, inout->vel, inout->psi1, inout->psi2, n, F, nm, scale,
-                                    static_cast<float>(geom->box), kd, flags, s); });
+    if (!g_graph_on || g_prof.on) {
+      run_cola(jp, f, tab, n_a, cosmo->omega_m, cola, flags, s);
+      return finish(flags, s);
     }
-    if (cola) {
-      const double* r = row(n_a - 1);
-      stage("frame velocity", s, [&] { return kern::frame_velocity(inout->vel, inout->psi1, inout->psi2, n, static_cast<float>(r[host::kF1]),
-                                 static_cast<float>(r[host::kF2]), s); });
+    // Graph of the whole run, keyed by every argument that shapes the launches; replayed while they repeat.
+    std::vector<char> key;
+    auto put = [&key](const void* p, size_t n) {
+      const char* c = static_cast<const char*>(p);
+      key.insert(key.end(), c, c + n);
+    };
+    put(entries, sizeof(lpc_batch_entry) * n_real);
+    put(cosmo, sizeof(*cosmo));
+    put(step, sizeof(*step));
+    put(a_list, sizeof(double) * n_a);
+    put(&ws, sizeof(ws));
+    if (g_graph.exec == nullptr || g_graph.key != key) {
+      if (g_graph.exec) {
+        check(hipGraphExecDestroy(g_graph.exec), "hipGraphExecDestroy");
+        g_graph.exec = nullptr;
+      }
+      kern::init_kernels();
+      hipStream_t cap = capture_stream();
+      hipGraph_t graph;
+      check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      try {
+        run_cola(jp, f, tab, n_a, cosmo->omega_m, cola, flags, cap);
+      } catch (...) {
+        hipGraph_t dropped;
+        hipStreamEndCapture(cap, &dropped);
+        if (dropped) hipGraphDestroy(dropped);
+        throw;
+      }
+      check(hipStreamEndCapture(cap, &graph), "hipStreamEndCapture");
+      hipGraphExec_t exec;
+      const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      check(e, "hipGraphInstantiate");
+      g_graph.exec = exec;
+      g_graph.key = key;
     }
+    check(hipGraphLaunch(g_graph.exec, s), "hipGraphLaunch");
     return finish(flags, s);
   });
 }
@@ -441,29 +848,42 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
     float* r1 = out->psi2 + n;
     float* r2 = out->psi2 + 2 * n;
     const float inv_n3 = static_cast<float>(1.0 / static_cast<double>(n));
-    stage("noise", s, [&] { return kern::ic_noise(seed, N, r0, s); });
-    r2c_real(r0, N, dhat, s);
-    stage("scale spectrum", s, [&] { return kern::ic_scale_spectrum(dhat, N, pitch, geom->box, A, c.omega_m, c.h, c.n_s, s); });
-    auto derived = [&](const float2* src, int kind, float* dst) {
-      stage("spectral factor", s, [&] { return kern::ic_spectral_factor(src, spec, N, pitch, geom->box, kind, s); });
-      c2r_real(spec, N, dst, inv_n3, s);
+    // the transforms of the whole construction, in order: r2c(noise), 12 derived fields, r2c(source), and the 2LPT
+    // displacement fields; kinds 0..2 Psi1, 3..8 phi1_ij, 9..11 Psi2
+    float* dst[12] = {out->psi1, out->psi1 + n, out->psi1 + 2 * n, r0, r1, r2, r1, r1, r1, r0, r1, r2};
+    JobPack jp;
+    const R2CSections noise = add_r2c(jp, r0, false, 0.0, N, dhat);
+    C2RSections der[12];
+    for (int k = 0; k < 12; ++k) der[k] = add_c2r(jp, spec, N, dst[k], inv_n3);
+    const R2CSections source = add_r2c(jp, r0, false, 0.0, N, dhat);
+    jp.upload(at(ws, p.jobs), s);
+    auto derived = [&](int kind) {
+      stage("spectral factor", s, [&] { return kern::ic_spectral_factor(dhat, spec, N, pitch, geom->box, kind, s); });
+      run_c2r(jp, der[kind], s);
     };
-    for (int j = 0; j < 3; ++j) derived(dhat, j, out->psi1 + j * n);
-    derived(dhat, 3, r0);  // phi_xx
-    derived(dhat, 4, r1);  // phi_yy
-    derived(dhat, 5, r2);  // phi_zz
+    stage("noise", s, [&] { return kern::ic_noise(seed, N, r0, s); });
+    run_r2c(jp, noise, false, flags, s);
+    stage("scale spectrum", s, [&] { return kern::ic_scale_spectrum(dhat, N, pitch, geom->box, A, c.omega_m, c.h, c.n_s, s); });
+    for (int k = 0; k < 3; ++k) derived(k);  // Psi1
+    for (int k = 3; k < 6; ++k) derived(k);  // phi_xx, phi_yy, phi_zz
     stage("source", s, [&] { return kern::ic_source_init(r0, r1, r2, n, s); });
-    for (int kind = 6; kind < 9; ++kind) {  // phi_xy, phi_xz, phi_yz
-      derived(dhat, kind, r1);
+    for (int k = 6; k < 9; ++k) {            // phi_xy, phi_xz, phi_yz
+      derived(k);
       stage("source", s, [&] { return kern::ic_sub_square(r0, r1, n, s); });
     }
-    r2c_real(r0, N, dhat, s);  // source spectrum replaces delta_hat
-    for (int j = 0; j < 3; ++j) derived(dhat, 9 + j, out->psi2 + j * n);
+    run_r2c(jp, source, false, flags, s);    // source spectrum replaces delta_hat
+    // Psi2 = i k phi2_hat; kinds 9..11 read the source spectrum in dhat
+    for (int j = 0; j < 3; ++j) {
+      stage("spectral factor", s, [&] { return kern::ic_spectral_factor(dhat, spec, N, pitch, geom->box, 9 + j, s); });
+      run_c2r(jp, der[9 + j], s);
+    }
     const double d1 = host::growth_D1(c, a_init), d2 = host::growth_D2(c, a_init);
     const double E = host::hubble_E(c, a_init), a3 = a_init * a_init * a_init;
     const double f1 = a3 * E * host::growth_dD1(c, a_init), f2 = a3 * E * host::growth_dD2(c, a_init);
-    stage("assemble", s, [&] { return kern::ic_assemble(out->pos, out->vel, out->id, out->psi1, out->psi2, N, geom->box, static_cast<float>(d1),
-                            static_cast<float>(d2), static_cast<float>(f1), static_cast<float>(f2), s); });
+    stage("assemble", s, [&] {
+      return kern::ic_assemble(out->pos, out->vel, out->id, out->psi1, out->psi2, N, geom->box, static_cast<float>(d1),
+                               static_cast<float>(d2), static_cast<float>(f1), static_cast<float>(f2), s);
+    });
     return finish(flags, s);
   });
 }
@@ -479,22 +899,32 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
-    const int nm = geom->n_mesh, pitch = kern::mesh_pitch(nm), nh = nm / 2 + 1;
-    const size_t M = static_cast<size_t>(nm) * nm * nm;
+    const int nm = geom->n_mesh, pitch = kern::mesh_pitch(nm);
+    const int64_t M = static_cast<int64_t>(nm) * nm * nm;
     int* flags = reinterpret_cast<int*>(ws);
     uint64_t* dens = reinterpret_cast<uint64_t*>(at(ws, p.dens));
     float2* A = reinterpret_cast<float2*>(at(ws, p.A));
     double* sums = reinterpret_cast<double*>(at(ws, p.bins));
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(sums + 2 * n_bins);
-    const double scale = (static_cast<double>(nm) * 65536.0) / geom->box;
-    const double mscale = (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48;
+    JobPack jp;
+    const Section fill = jp.add1(kern::FillJob{dens, M}, kern::fill_items(M));
+    kern::PartJob pj{};
+    pj.pos = const_cast<float*>(pos);
+    pj.n = n;
+    pj.dens = dens;
+    pj.nm = nm;
+    pj.box = static_cast<float>(geom->box);
+    pj.scale = (static_cast<double>(nm) * 65536.0) / geom->box;
+    const Section dep = jp.add1(pj, static_cast<int>((n + kern::kNT - 1) / kern::kNT));
+    const R2CSections r = add_r2c(jp, dens, true, (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48, nm, A);
+    jp.upload(at(ws, p.jobs), s);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    stage("clear bins", s, [&] { return kern::fill_u64(reinterpret_cast<uint64_t*>(sums), static_cast<size_t>(3) * n_bins, s); });
-    stage("fill density", s, [&] { return kern::fill_u64(dens, M, s); });
-    stage("deposit", s, [&] { return kern::deposit(pos, n, nm, scale, dens, flags, s); });
-    stage("fft z r2c", s, [&] { return kern::fft_z_r2c_fixed(dens, nm, mscale, A, pitch, flags, s); });
-    stage("fft y", s, [&] { return kern::fft_axis(A, nm, pitch, static_cast<int64_t>(nm) * pitch, nm, nh, 1, 0, false, s); });
-    stage("fft x", s, [&] { return kern::fft_axis(A, nm, static_cast<int64_t>(nm) * pitch, pitch, nm, nh, 1, 0, false, s); });
+    stage("clear bins", s, [&] {
+      return kern::fill_i32(reinterpret_cast<int*>(sums), static_cast<size_t>(6) * n_bins, 0, s);
+    });
+    stage("fill density", s, [&] { return kern::launch_fill(jp.jobs<kern::FillJob>(fill), jp.table(fill), s); });
+    stage("deposit", s, [&] { return kern::launch_deposit(jp.jobs<kern::PartJob>(dep), jp.table(dep), flags, s); });
+    run_r2c(jp, r, true, flags, s);
     const double V = geom->box * geom->box * geom->box;
     const double pscale = V / (static_cast<double>(M) * static_cast<double>(M));
     stage("pk bin", s, [&] { return kern::pk_bin(A, nm, pitch, geom->box, k_max, n_bins, pscale, sums, counts, s); });
@@ -525,7 +955,10 @@ lpc_status lpc_fft_r2c(int32_t n, const float* in, float* out_complex, void* ws,
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    r2c_real(in, n, reinterpret_cast<float2*>(out_complex), s);
+    JobPack jp;
+    const R2CSections r = add_r2c(jp, in, false, 0.0, n, reinterpret_cast<float2*>(out_complex));
+    jp.upload(at(ws, p.jobs), s);
+    run_r2c(jp, r, false, flags, s);
     return finish(flags, s);
   });
 }
@@ -539,7 +972,10 @@ lpc_status lpc_fft_c2r(int32_t n, float* in_complex, float* out, void* ws, size_
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    c2r_real(reinterpret_cast<float2*>(in_complex), n, out, 1.0f, s);
+    JobPack jp;
+    const C2RSections c = add_c2r(jp, reinterpret_cast<float2*>(in_complex), n, out, 1.0f);
+    jp.upload(at(ws, p.jobs), s);
+    run_c2r(jp, c, s);
     return finish(flags, s);
   });
 }

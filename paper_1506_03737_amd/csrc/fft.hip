@@ -7,6 +7,10 @@
 // Inverse: x pass, y pass, z pass (c2r via the same split). The force path fuses the forward x pass, the Poisson /
 // deconvolution / gradient multiply and the three inverse x passes into one kernel, so the density spectrum is
 // read once and never written back.
+//
+// Every kernel is batched: workgroup w takes item w of a work table of (job, tile) items, where a job is one mesh of
+// one box, so one launch per pass serves any number of boxes of uneven sizes (see WorkTable). (A persistent
+// grid-stride loop over the items measured slower: it raised register pressure past the four-waves-per-SIMD limit.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -72,91 +76,117 @@ void allow_big_lds(K kernel) {
                       160 * 1024);
 }
 
+// Job of work item w: the last j with offs[j] <= w (binary search; offs is uniform, so scalar loads).
+__device__ __forceinline__ int find_job(const LPC_CONST int* __restrict__ offs, int njob, int w) {
+  int lo = 0, hi = njob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------------------------------------------------------
 // Every kernel stages its global loads through registers in fully unrolled batches before writing the LDS tile: a
 // runtime-bounded load loop would wait out the HBM latency once per element.
 
-// z pass, forward r2c. A workgroup transforms B consecutive rows of n reals. Each row is read as h = n/2 complex
-// values z[m] = x[2m] + i x[2m+1]; after the length-h FFT, X[k] = E[k] + exp(-2 pi i k / n) O[k] with
+// z pass, forward r2c. An item transforms B consecutive rows of n reals. Each row is read as h = n/2 complex values
+// z[m] = x[2m] + i x[2m+1]; after the length-h FFT, X[k] = E[k] + exp(-2 pi i k / n) O[k] with
 // E[k] = (Z[k] + conj Z[h-k]) / 2 and O[k] = (Z[k] - conj Z[h-k]) / (2 i), for k = 0..h.
 template <bool FIXED, int B>
-__global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const void* __restrict__ in, int n, int nrows,
-                                                         float2* __restrict__ out, int pitch, double mscale,
-                                                         Plan1D pl, int* __restrict__ flags) {
+__global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restrict__ jobs,
+                                                         const int* __restrict__ offs, int njob, int total,
+                                                         int* __restrict__ flags) {
   constexpr int BP = B + 1;
   extern __shared__ float2 smem[];
-  const int h = n / 2, tid = threadIdx.x;
-  float2* tile = smem;
-  float2* tw = tile + h * BP;
-  float2* roots = tw + h;
-  fill_stage_twiddles(tw, pl, tid);
-  fill_half_roots(roots, n, tid);
-  const int row0 = blockIdx.x * B;
-  const int count = h * B;
-  if (FIXED) {
-    constexpr int H = kEPT / 2;
+  {
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (w >= total) return;
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST ZR2CJob& J = to_const(jobs)[jb];
+    const int n = J.n, h = n / 2, nrows = J.nrows;
+    const int row0 = (w - offs[jb]) * B;
+    if (row0 >= nrows) return;  // padding item (uniform; no LDS touched)
+    float2* tile = smem;
+    float2* tw = tile + h * BP;
+    float2* roots = tw + h;
+    {
+      fill_stage_twiddles(tw, J.pl, tid);
+      fill_half_roots(roots, n, tid);
+    }
+    const int count = h * B;
+    if (FIXED) {
+      LPC_GLOBAL const uint64_t* in = to_global(static_cast<const uint64_t*>(J.in));
+      constexpr int H = kEPT / 2;
 #pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-      ulonglong2 raw[H];
+      for (int half = 0; half < 2; ++half) {
+        ulonglong2 raw[H];
 #pragma unroll
-      for (int m = 0; m < H; ++m) {
-        const int e = tid + (half * H + m) * kFftNT;
-        const int b = e / h, j = e - b * h;
-        raw[m] = make_ulonglong2(0ull, 0ull);
-        if (e < count && row0 + b < nrows)
-          raw[m] = reinterpret_cast<const ulonglong2*>(static_cast<const uint64_t*>(in) +
-                                                       static_cast<size_t>(row0 + b) * n)[j];
+        for (int m = 0; m < H; ++m) {
+          const int e = tid + (half * H + m) * kFftNT;
+          const int b = e / h, j = e - b * h;
+          raw[m] = make_ulonglong2(0ull, 0ull);
+          if (e < count && row0 + b < nrows)
+            raw[m] = reinterpret_cast<LPC_GLOBAL const ulonglong2*>(in + static_cast<size_t>(row0 + b) * n)[j];
+        }
+        bool overflow = false;
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+          const int e = tid + (half * H + m) * kFftNT;
+          if (e < count) {
+            const int b = e / h, j = e - b * h;
+            overflow |= ((raw[m].x | raw[m].y) >> 63) != 0;
+            float2 v = make_float2(0.f, 0.f);
+            if (row0 + b < nrows) {
+              v.x = static_cast<float>(static_cast<double>(raw[m].x) * J.mscale - 1.0);
+              v.y = static_cast<float>(static_cast<double>(raw[m].y) * J.mscale - 1.0);
+            }
+            tile[j * BP + b] = v;
+          }
+        }
+        if (overflow) atomicOr(flags + kFlagOverflow, 1);
       }
-      bool overflow = false;
+    } else {
+      LPC_GLOBAL const float2* in = to_global(static_cast<const float2*>(J.in));
+      float2 v[kEPT];
 #pragma unroll
-      for (int m = 0; m < H; ++m) {
-        const int e = tid + (half * H + m) * kFftNT;
+      for (int m = 0; m < kEPT; ++m) {
+        const int e = tid + m * kFftNT;
+        const int b = e / h, j = e - b * h;
+        v[m] = make_float2(0.f, 0.f);
+        if (e < count && row0 + b < nrows) v[m] = in[static_cast<size_t>(row0 + b) * h + j];
+      }
+#pragma unroll
+      for (int m = 0; m < kEPT; ++m) {
+        const int e = tid + m * kFftNT;
         if (e < count) {
           const int b = e / h, j = e - b * h;
-          overflow |= ((raw[m].x | raw[m].y) >> 63) != 0;
-          float2 v = make_float2(0.f, 0.f);
-          if (row0 + b < nrows) {
-            v.x = static_cast<float>(static_cast<double>(raw[m].x) * mscale - 1.0);
-            v.y = static_cast<float>(static_cast<double>(raw[m].y) * mscale - 1.0);
-          }
-          tile[j * BP + b] = v;
+          tile[j * BP + b] = v[m];
         }
       }
-      if (overflow) atomicOr(flags + kFlagOverflow, 1);
     }
-  } else {
-    float2 v[kEPT];
+    __syncthreads();
+    fft_tile<false>(tile, tw, J.pl, B, tid);
+    const int count2 = (h + 1) * B;
+    LPC_GLOBAL float2* out = to_global(J.out);
+    const int pitch = J.pitch;
 #pragma unroll
-    for (int m = 0; m < kEPT; ++m) {
+    for (int m = 0; m < kEPT + 1; ++m) {
       const int e = tid + m * kFftNT;
-      const int b = e / h, j = e - b * h;
-      v[m] = make_float2(0.f, 0.f);
-      if (e < count && row0 + b < nrows) v[m] = static_cast<const float2*>(in)[static_cast<size_t>(row0 + b) * h + j];
-    }
-#pragma unroll
-    for (int m = 0; m < kEPT; ++m) {
-      const int e = tid + m * kFftNT;
-      if (e < count) {
-        const int b = e / h, j = e - b * h;
-        tile[j * BP + b] = v[m];
-      }
-    }
-  }
-  __syncthreads();
-  fft_tile<false>(tile, tw, pl, B, tid);
-  const int count2 = (h + 1) * B;
-#pragma unroll
-  for (int m = 0; m < kEPT + 1; ++m) {
-    const int e = tid + m * kFftNT;
-    if (e < count2) {
-      const int b = e / (h + 1), k = e - b * (h + 1);
-      const int row = row0 + b;
-      if (row < nrows) {
-        const float2 zk = tile[(k == h ? 0 : k) * BP + b];
-        const float2 zm = tile[(k == 0 ? 0 : h - k) * BP + b];
-        const float2 E = cscale(cadd(zk, cconj(zm)), 0.5f);
-        const float2 O = cscale(rot<false>(csub(zk, cconj(zm))), 0.5f);  // (zk - conj zm) / (2 i)
-        out[static_cast<size_t>(row) * pitch + k] = cadd(E, cmul(roots[k], O));
+      if (e < count2) {
+        const int b = e / (h + 1), k = e - b * (h + 1);
+        const int row = row0 + b;
+        if (row < nrows) {
+          const float2 zk = tile[(k == h ? 0 : k) * BP + b];
+          const float2 zm = tile[(k == 0 ? 0 : h - k) * BP + b];
+          const float2 E = cscale(cadd(zk, cconj(zm)), 0.5f);
+          const float2 O = cscale(rot<false>(csub(zk, cconj(zm))), 0.5f);  // (zk - conj zm) / (2 i)
+          out[static_cast<size_t>(row) * pitch + k] = cadd(E, cmul(roots[k], O));
+        }
       }
     }
   }
@@ -164,10 +194,9 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const void* __restrict_
 
 // Load/store of a strided tile of B columns: element (j, b) <-> ptr[j * astr + b], for b < bw. Loads go out in two
 // unrolled batches of kEPT / 2 per thread (enough bytes in flight per CU to cover HBM latency at a register cost
-// that keeps four waves per SIMD). When `scale` is given, each loaded value is multiplied by scale(j, b) (a real
-// factor) and by i.
+// that keeps four waves per SIMD).
 template <int B>
-__device__ __forceinline__ void load_strided(float2* tile, const float2* __restrict__ ptr, int64_t astr, int n, int bw,
+__device__ __forceinline__ void load_strided(float2* tile, LPC_GLOBAL const float2* __restrict__ ptr, int64_t astr, int n, int bw,
                                              int tid) {
   constexpr int BP = B + 1;
   const int count = n * B;
@@ -191,7 +220,7 @@ __device__ __forceinline__ void load_strided(float2* tile, const float2* __restr
 }
 
 template <int B>
-__device__ __forceinline__ void store_strided(const float2* tile, float2* __restrict__ ptr, int64_t astr, int n,
+__device__ __forceinline__ void store_strided(const float2* tile, LPC_GLOBAL float2* __restrict__ ptr, int64_t astr, int n,
                                               int bw, int tid) {
   constexpr int BP = B + 1;
   const int count = n * B;
@@ -204,24 +233,37 @@ __device__ __forceinline__ void store_strided(const float2* tile, float2* __rest
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Strided complex pass (in place). Tile = B consecutive columns (contiguous in memory) x n points along the axis.
+// Strided complex pass (in place). A tile is B consecutive columns (contiguous in memory) x n points along the
+// axis. Within a component, tiles are XCD-remapped so that neighbouring tiles (which share cache lines at their
+// edges) run on the same XCD.
 template <bool INV, int B>
-__global__ __launch_bounds__(kFftNT, 4) void k_fft_axis(float2* __restrict__ base, int n, int64_t astr, int64_t ostr,
-                                                        int n_outer, int ncols, int64_t cstr, Plan1D pl) {
+__global__ __launch_bounds__(kFftNT, 4) void k_fft_axis(const AxisJob* __restrict__ jobs,
+                                                        const int* __restrict__ offs, int njob, int total) {
   extern __shared__ float2 smem[];
-  const int tid = threadIdx.x;
-  float2* tile = smem;
-  float2* tw = smem + n * (B + 1);
-  fill_stage_twiddles(tw, pl, tid);
-  const int ntc = (ncols + B - 1) / B;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int outer = logical / ntc, ct = logical - outer * ntc;
-  const int c0 = ct * B, bw = min(B, ncols - c0);
-  float2* ptr = base + blockIdx.y * cstr + outer * ostr + c0;
-  load_strided<B>(tile, ptr, astr, n, bw, tid);
-  __syncthreads();
-  fft_tile<INV>(tile, tw, pl, B, tid);
-  store_strided<B>(tile, ptr, astr, n, bw, tid);
+  {
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (w >= total) return;
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST AxisJob& J = to_const(jobs)[jb];
+    const int local = w - offs[jb];
+    const int comp = local / J.per_comp;
+    const int t = xcd_remap(local - comp * J.per_comp, J.per_comp);
+    const int outer = t / J.ntc, ct = t - outer * J.ntc;
+    const int n = J.n;
+    if (outer >= n) return;  // padding item
+    const int c0 = ct * B, bw = min(B, J.ncols - c0);
+    float2* tile = smem;
+    float2* tw = smem + n * (B + 1);
+    {
+      fill_stage_twiddles(tw, J.pl, tid);
+    }
+    LPC_GLOBAL float2* ptr = to_global(J.base + comp * J.cstr + outer * J.ostr + c0);
+    load_strided<B>(tile, ptr, J.astr, n, bw, tid);
+    __syncthreads();
+    fft_tile<INV>(tile, tw, J.pl, B, tid);
+    store_strided<B>(tile, ptr, J.astr, n, bw, tid);
+  }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -230,164 +272,161 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_axis(float2* __restrict__ bas
 // inverse FFT along x, store. W = prod_d sinc^2(pi n_d / Nm); the 1/Nm^3 of the inverse transform is folded in.
 // The x-transformed delta_hat stays in a second LDS tile across the three components.
 template <int B>
-__global__ __launch_bounds__(kFftNT) void k_fft_x_poisson(float2* __restrict__ A, float2* __restrict__ Bm,
-                                                          float2* __restrict__ Cm, int nm, int pitch, float kf,
-                                                          float inv_m3, int deconv, Plan1D pl) {
-  constexpr int BP = B + 1;
+__global__ __launch_bounds__(kFftNT) void k_fft_x_poisson(const PoissonJob* __restrict__ jobs,
+                                                          const int* __restrict__ offs, int njob, int total) {
+  constexpr int BP = B + 1, S = kFftNT / B;
   extern __shared__ float2 smem[];
-  const int n = nm, tid = threadIdx.x, nh = nm / 2 + 1;
-  float2* tile = smem;
-  float2* dh = tile + n * BP;
-  float2* tw = dh + n * BP;
-  float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
-  fill_stage_twiddles(tw, pl, tid);
-  for (int m = tid; m <= n / 2; m += kFftNT) {
-    double w = 1.0;
-    if (m != 0) {
-      const double x = static_cast<double>(m) / n;
-      w = sinpi(x) / (M_PI * x);
-      w = w * w;
-    }
-    win[m] = static_cast<float>(w);
-  }
-  const int ntc = (nh + B - 1) / B;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int y = logical / ntc, ct = logical - y * ntc;
-  const int c0 = ct * B, bw = min(B, nh - c0);
-  const int64_t astr = static_cast<int64_t>(nm) * pitch;
-  const int64_t off = static_cast<int64_t>(y) * pitch + c0;
-  load_strided<B>(tile, A + off, astr, n, bw, tid);
-  __syncthreads();
-  fft_tile<false>(tile, tw, pl, B, tid);
-
-  // Each thread touches only its own elements (column b, rows j0 + m S) between the barriers that bracket the
-  // inverse transforms.
-  constexpr int S = kFftNT / B;
-  const int b = tid % B, j0 = tid / B;
-  const int half = nm / 2;
-  const int ny = (y <= half) ? y : y - nm;
-  const int nz = c0 + b;
-  const bool col_ok = b < bw;
-  const float wyz = win[min(y, n - y)] * win[min(nz, half)];
-  const int nyz2 = ny * ny + nz * nz;
-  for (int j = j0; j < n; j += S) dh[j * BP + b] = tile[j * BP + b];
-#pragma unroll 1
-  for (int comp = 0; comp < 3; ++comp) {
-    for (int j = j0; j < n; j += S) {
-      const int nx = (j <= half) ? j : j - nm;
-      const float k2 = kf * kf * static_cast<float>(nx * nx + nyz2);
-      const int nc = (comp == 0) ? nx : (comp == 1 ? ny : nz);
-      float sc = 0.f;
-      if (k2 > 0.f && col_ok && nc != half && nc != -half) {
-        const float W = win[min(j, n - j)] * wyz;
-        const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
-        sc = -kf * static_cast<float>(nc) * inv_m3 / (k2 * wp);  // k_c * (-1 / (k^2 W^p Nm^3))
+  {
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (w >= total) return;
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST PoissonJob& J = to_const(jobs)[jb];
+    const int n = J.nm, nm = J.nm, nh = nm / 2 + 1, pitch = J.pitch;
+    const int t = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]);
+    const int y = t / J.ntc, ct = t - y * J.ntc;
+    if (y >= n) return;  // padding item
+    float2* tile = smem;
+    float2* dh = tile + n * BP;
+    float2* tw = dh + n * BP;
+    float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
+    {
+      fill_stage_twiddles(tw, J.pl, tid);
+      for (int m = tid; m <= n / 2; m += kFftNT) {
+        double wv = 1.0;
+        if (m != 0) {
+          const double x = static_cast<double>(m) / n;
+          wv = sinpi(x) / (M_PI * x);
+          wv = wv * wv;
+        }
+        win[m] = static_cast<float>(wv);
       }
-      const float2 d = dh[j * BP + b];
-      tile[j * BP + b] = make_float2(-sc * d.y, sc * d.x);  // i * sc * delta_hat
     }
+    const int c0 = ct * B, bw = min(B, nh - c0);
+    const int64_t astr = static_cast<int64_t>(nm) * pitch;
+    const int64_t off = static_cast<int64_t>(y) * pitch + c0;
+    load_strided<B>(tile, to_global(J.A + off), astr, n, bw, tid);
     __syncthreads();
-    fft_tile<true>(tile, tw, pl, B, tid);
-    float2* dst = (comp == 0) ? A : (comp == 1 ? Bm : Cm);
-    store_strided<B>(tile, dst + off, astr, n, bw, tid);
-    __syncthreads();
+    fft_tile<false>(tile, tw, J.pl, B, tid);
+
+    // Each thread touches only its own elements (column b, rows j0 + m S) between the barriers that bracket the
+    // inverse transforms.
+    const int b = tid % B, j0 = tid / B;
+    const int half = nm / 2;
+    const int ny = (y <= half) ? y : y - nm;
+    const int nz = c0 + b;
+    const bool col_ok = b < bw;
+    const float wyz = win[min(y, n - y)] * win[min(nz, half)];
+    const int nyz2 = ny * ny + nz * nz;
+    const float kf = J.kf, inv_m3 = J.inv_m3;
+    const int deconv = J.deconv;
+    for (int j = j0; j < n; j += S) dh[j * BP + b] = tile[j * BP + b];
+#pragma unroll 1
+    for (int comp = 0; comp < 3; ++comp) {
+      for (int j = j0; j < n; j += S) {
+        const int nx = (j <= half) ? j : j - nm;
+        const float k2 = kf * kf * static_cast<float>(nx * nx + nyz2);
+        const int nc = (comp == 0) ? nx : (comp == 1 ? ny : nz);
+        float sc = 0.f;
+        if (k2 > 0.f && col_ok && nc != half && nc != -half) {
+          const float W = win[min(j, n - j)] * wyz;
+          const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
+          sc = -kf * static_cast<float>(nc) * inv_m3 / (k2 * wp);  // k_c * (-1 / (k^2 W^p Nm^3))
+        }
+        const float2 d = dh[j * BP + b];
+        tile[j * BP + b] = make_float2(-sc * d.y, sc * d.x);  // i * sc * delta_hat
+      }
+      __syncthreads();
+      fft_tile<true>(tile, tw, J.pl, B, tid);
+      float2* dst = (comp == 0) ? J.A : (comp == 1 ? J.B : J.C);
+      store_strided<B>(tile, to_global(dst + off), astr, n, bw, tid);
+      __syncthreads();
+    }
   }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// z pass, inverse c2r. A workgroup transforms R rows of each of NC spectra; tile column c R + r holds spectrum c of
+// z pass, inverse c2r. An item transforms R rows of each of NC spectra; tile column c R + r holds spectrum c of
 // row r (B = NC R columns). With X the half spectrum of a real row,
 //   Z[k] = (X[k] + conj X[h-k]) + i exp(+2 pi i k / n) (X[k] - conj X[h-k]),  h = n/2, k < h,
 // and the unnormalised length-h inverse FFT of Z gives x[2m] + i x[2m+1]. Output rows are NC-interleaved.
 template <int NC, int R>
-__global__ __launch_bounds__(kFftNT, 4) void k_fft_z_c2r(const float2* __restrict__ in0, const float2* __restrict__ in1,
-                                                         const float2* __restrict__ in2, int n, int nrows, int pitch,
-                                                         float* __restrict__ out, float scale, Plan1D pl) {
+__global__ __launch_bounds__(kFftNT, 4) void k_fft_z_c2r(const ZC2RJob* __restrict__ jobs,
+                                                         const int* __restrict__ offs, int njob, int total) {
   constexpr int B = NC * R, BP = B + 1;
   extern __shared__ float2 smem[];
-  const int h = n / 2, tid = threadIdx.x;
-  float2* tile = smem;                 // (h + 1) x BP
-  float2* tw = tile + (h + 1) * BP;    // stage twiddles (h)
-  float2* roots = tw + h;              // exp(-2 pi i k / n), k <= h
-  fill_stage_twiddles(tw, pl, tid);
-  fill_half_roots(roots, n, tid);
-  const int row0 = blockIdx.x * R;
-  const float2* ins[3] = {in0, in1, in2};
-  const int count = B * (h + 1);
   {
-    float2 v[kEPT + 1];
-#pragma unroll
-    for (int m = 0; m < kEPT + 1; ++m) {
-      const int e = tid + m * kFftNT;
-      const int col = e / (h + 1), k = e - col * (h + 1);
-      const int c = col / R, row = row0 + col % R;
-      v[m] = make_float2(0.f, 0.f);
-      if (e < count && row < nrows) v[m] = ins[c][static_cast<size_t>(row) * pitch + k];
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (w >= total) return;
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST ZC2RJob& J = to_const(jobs)[jb];
+    const int n = J.n, h = n / 2, nrows = J.nrows, pitch = J.pitch;
+    const int row0 = (w - offs[jb]) * R;
+    if (row0 >= nrows) return;  // padding item
+    float2* tile = smem;                 // (h + 1) x BP
+    float2* tw = tile + (h + 1) * BP;    // stage twiddles (h)
+    float2* roots = tw + h;              // exp(-2 pi i k / n), k <= h
+    {
+      fill_stage_twiddles(tw, J.pl, tid);
+      fill_half_roots(roots, n, tid);
     }
+    LPC_GLOBAL const float2* in0 = to_global(J.in0);
+    LPC_GLOBAL const float2* in1 = to_global(J.in1);
+    LPC_GLOBAL const float2* in2 = to_global(J.in2);
+    const int count = B * (h + 1);
+    {
+      float2 v[kEPT + 1];
 #pragma unroll
-    for (int m = 0; m < kEPT + 1; ++m) {
-      const int e = tid + m * kFftNT;
-      if (e < count) {
+      for (int m = 0; m < kEPT + 1; ++m) {
+        const int e = tid + m * kFftNT;
         const int col = e / (h + 1), k = e - col * (h + 1);
-        tile[k * BP + col] = v[m];
+        const int c = col / R, row = row0 + col % R;
+        v[m] = make_float2(0.f, 0.f);
+        LPC_GLOBAL const float2* src = (c == 0) ? in0 : (c == 1 ? in1 : in2);
+        if (e < count && row < nrows) v[m] = src[static_cast<size_t>(row) * pitch + k];
+      }
+#pragma unroll
+      for (int m = 0; m < kEPT + 1; ++m) {
+        const int e = tid + m * kFftNT;
+        if (e < count) {
+          const int col = e / (h + 1), k = e - col * (h + 1);
+          tile[k * BP + col] = v[m];
+        }
+      }
+    }
+    __syncthreads();
+    const int hk = h / 2 + 1;
+    for (int e = tid; e < hk * B; e += kFftNT) {
+      const int col = e / hk, k = e - col * hk;
+      const float2 xk = tile[k * BP + col];
+      const float2 xm = tile[(h - k) * BP + col];
+      const float2 t = roots[k];
+      // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm)
+      const float2 zk = cadd(cadd(xk, cconj(xm)), rot<true>(cmulc(csub(xk, cconj(xm)), t)));
+      if (k != 0 && 2 * k != h) {
+        // Z[h-k] = (xm + conj xk) - i t (xm - conj xk)
+        const float2 zm = csub(cadd(xm, cconj(xk)), rot<true>(cmul(csub(xm, cconj(xk)), t)));
+        tile[(h - k) * BP + col] = zm;
+      }
+      tile[k * BP + col] = zk;
+    }
+    __syncthreads();
+    fft_tile<true>(tile, tw, J.pl, B, tid);
+    const int rowlen = NC * n;
+    LPC_GLOBAL float* out = to_global(J.out);
+    const float scale = J.scale;
+#pragma unroll 4
+    for (int f = tid; f < R * rowlen; f += kFftNT) {
+      const int r = f / rowlen, q = f - r * rowlen;
+      const int row = row0 + r;
+      if (row < nrows) {
+        const int jj = q / NC, c = q - jj * NC;
+        const float2 z = tile[(jj >> 1) * BP + c * R + r];
+        out[static_cast<size_t>(row) * rowlen + q] = ((jj & 1) ? z.y : z.x) * scale;
       }
     }
   }
-  __syncthreads();
-  const int hk = h / 2 + 1;
-  for (int e = tid; e < hk * B; e += kFftNT) {
-    const int col = e / hk, k = e - col * hk;
-    const float2 xk = tile[k * BP + col];
-    const float2 xm = tile[(h - k) * BP + col];
-    const float2 t = roots[k];
-    // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm)
-    const float2 zk = cadd(cadd(xk, cconj(xm)), rot<true>(cmulc(csub(xk, cconj(xm)), t)));
-    if (k != 0 && 2 * k != h) {
-      // Z[h-k] = (xm + conj xk) - i t (xm - conj xk)
-      const float2 zm = csub(cadd(xm, cconj(xk)), rot<true>(cmul(csub(xm, cconj(xk)), t)));
-      tile[(h - k) * BP + col] = zm;
-    }
-    tile[k * BP + col] = zk;
-  }
-  __syncthreads();
-  fft_tile<true>(tile, tw, pl, B, tid);
-  const int rowlen = NC * n;
-#pragma unroll 4
-  for (int f = tid; f < R * rowlen; f += kFftNT) {
-    const int r = f / rowlen, q = f - r * rowlen;
-    const int row = row0 + r;
-    if (row < nrows) {
-      const int jj = q / NC, c = q - jj * NC;
-      const float2 z = tile[(jj >> 1) * BP + c * R + r];
-      out[static_cast<size_t>(row) * rowlen + q] = ((jj & 1) ? z.y : z.x) * scale;
-    }
-  }
-}
-
-size_t lds_z_r2c(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n / 2) * (B + 1) + n / 2 + n / 2 + 1); }
-size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) * (B + 1) + n); }
-size_t lds_x_poisson(int n, int B) {
-  return sizeof(float2) * (2 * static_cast<size_t>(n) * (B + 1) + n) + sizeof(float) * (n / 2 + 1);
-}
-size_t lds_z_c2r(int n, int B) {
-  return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (B + 1) + n / 2 + n / 2 + 1);
-}
-
-// Columns of a strided tile: the most of 8, 16, 32 with n * B <= kTileElems (8 for n > 512).
-int strided_cols(int n) { return (n <= 256) ? 32 : (n <= 512 ? 16 : 8); }
-// Rows of a z-pass tile for NC interleaved spectra: the largest of 1, 2, 4, 8, 16, 32 (/ NC-dependent cap) with
-// NC R (h + 1) <= kTileElems + kFftNT and NC R h <= kEPT (kFftNT / (NC R)) (NC R).
-int z_rows(int n, int nc) {
-  const int h = n / 2;
-  int best = 1;
-  for (int r = 1; r <= 32; r *= 2) {
-    const int B = nc * r;
-    if (B > kFftNT) break;
-    if (B * (h + 1) > kTileElems + kFftNT) break;
-    if (static_cast<long>(h) * B > static_cast<long>(kEPT) * (kFftNT / B) * B) break;
-    best = r;
-  }
-  return best;
 }
 
 struct Init {
@@ -404,9 +443,9 @@ struct Init {
     allow_big_lds(k_fft_axis<false, 8>);
     allow_big_lds(k_fft_axis<false, 16>);
     allow_big_lds(k_fft_axis<false, 32>);
+    allow_big_lds(k_fft_x_poisson<4>);
     allow_big_lds(k_fft_x_poisson<8>);
     allow_big_lds(k_fft_x_poisson<16>);
-    allow_big_lds(k_fft_x_poisson<32>);
     allow_big_lds(k_fft_z_c2r<1, 8>);
     allow_big_lds(k_fft_z_c2r<1, 16>);
     allow_big_lds(k_fft_z_c2r<1, 32>);
@@ -418,96 +457,99 @@ struct Init {
 
 void ensure_init() { static Init once; }
 
+// One workgroup per work item (the table's total is a multiple of 8, so blockIdx.x % 8 is the item's XCD slot).
+unsigned item_grid(int total) { return total > 0 ? static_cast<unsigned>(total) : 0u; }
+
+
 }  // namespace
 
-hipError_t fft_z_r2c_fixed(const uint64_t* C, int nm, double mscale, float2* out, int pitch, int* flags,
-                           hipStream_t s) {
-  ensure_init();
-  Plan1D pl;
-  if (!make_plan(nm / 2, &pl)) return hipErrorInvalidValue;
-  const int B = std::max(8, z_rows(nm, 1)), nrows = nm * nm;
-  const unsigned grid = (nrows + B - 1) / B;
-  const size_t lds = lds_z_r2c(nm, B);
-  if (B == 8) k_fft_z_r2c<true, 8><<<grid, kFftNT, lds, s>>>(C, nm, nrows, out, pitch, mscale, pl, flags);
-  else if (B == 16) k_fft_z_r2c<true, 16><<<grid, kFftNT, lds, s>>>(C, nm, nrows, out, pitch, mscale, pl, flags);
-  else k_fft_z_r2c<true, 32><<<grid, kFftNT, lds, s>>>(C, nm, nrows, out, pitch, mscale, pl, flags);
-  return hipGetLastError();
+size_t lds_z_r2c(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n / 2) * (B + 1) + n / 2 + n / 2 + 1); }
+size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) * (B + 1) + n); }
+size_t lds_x_poisson(int n, int B) {
+  return sizeof(float2) * (2 * static_cast<size_t>(n) * (B + 1) + n) + sizeof(float) * (n / 2 + 1);
+}
+size_t lds_z_c2r(int n, int B) {
+  return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (B + 1) + n / 2 + n / 2 + 1);
 }
 
-hipError_t fft_z_r2c_real(const float* in, int n, float2* out, int pitch, hipStream_t s) {
-  ensure_init();
-  Plan1D pl;
-  if (!make_plan(n / 2, &pl)) return hipErrorInvalidValue;
-  const int B = std::max(8, z_rows(n, 1)), nrows = n * n;
-  const unsigned grid = (nrows + B - 1) / B;
-  const size_t lds = lds_z_r2c(n, B);
-  if (B == 8) k_fft_z_r2c<false, 8><<<grid, kFftNT, lds, s>>>(in, n, nrows, out, pitch, 0.0, pl, nullptr);
-  else if (B == 16) k_fft_z_r2c<false, 16><<<grid, kFftNT, lds, s>>>(in, n, nrows, out, pitch, 0.0, pl, nullptr);
-  else k_fft_z_r2c<false, 32><<<grid, kFftNT, lds, s>>>(in, n, nrows, out, pitch, 0.0, pl, nullptr);
-  return hipGetLastError();
+// Columns of a strided tile: the most of 8, 16, 32 with n * B <= kTileElems (8 for n > 512).
+int strided_cols(int n) { return (n <= 256) ? 32 : (n <= 512 ? 16 : 8); }
+
+// Rows of a z-pass tile for NC interleaved spectra: the largest power of two up to 32 with
+// NC R (h + 1) <= kTileElems + kFftNT (load capacity) and NC R h <= kEPT S (NC R) (stage capacity).
+int z_rows(int n, int nc) {
+  const int h = n / 2;
+  int best = 1;
+  for (int r = 1; r <= 32; r *= 2) {
+    const int B = nc * r;
+    if (B > kFftNT) break;
+    if (B * (h + 1) > kTileElems + kFftNT) break;
+    if (static_cast<long>(h) * B > static_cast<long>(kEPT) * (kFftNT / B) * B) break;
+    best = r;
+  }
+  return best;
 }
 
-hipError_t fft_axis(float2* base, int n, int64_t axis_stride, int64_t outer_stride, int n_outer, int ncols, int ncomp,
-                    int64_t comp_stride, bool inverse, hipStream_t s) {
+void init_kernels() { ensure_init(); }
+
+hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, size_t lds, int* flags, hipStream_t s) {
   ensure_init();
-  Plan1D pl;
-  if (!make_plan(n, &pl)) return hipErrorInvalidValue;
-  const int B = strided_cols(n);
-  const int ntc = (ncols + B - 1) / B;
-  dim3 grid(n_outer * ntc, ncomp);
-  const size_t lds = lds_axis(n, B);
-#define LPC_AXIS(INV, BB) \
-  k_fft_axis<INV, BB><<<grid, kFftNT, lds, s>>>(base, n, axis_stride, outer_stride, n_outer, ncols, comp_stride, pl)
-  if (inverse) {
-    if (B == 8) LPC_AXIS(true, 8); else if (B == 16) LPC_AXIS(true, 16); else LPC_AXIS(true, 32);
+  const unsigned g = item_grid(wt.total);
+  if (g == 0) return hipSuccess;
+#define LPC_ZR2C(F, BB) k_fft_z_r2c<F, BB><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total, flags)
+  if (fixed) {
+    if (B == 8) LPC_ZR2C(true, 8); else if (B == 16) LPC_ZR2C(true, 16); else if (B == 32) LPC_ZR2C(true, 32);
+    else return hipErrorInvalidValue;
   } else {
-    if (B == 8) LPC_AXIS(false, 8); else if (B == 16) LPC_AXIS(false, 16); else LPC_AXIS(false, 32);
+    if (B == 8) LPC_ZR2C(false, 8); else if (B == 16) LPC_ZR2C(false, 16); else if (B == 32) LPC_ZR2C(false, 32);
+    else return hipErrorInvalidValue;
+  }
+#undef LPC_ZR2C
+  return hipGetLastError();
+}
+
+hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, size_t lds, hipStream_t s) {
+  ensure_init();
+  const unsigned g = item_grid(wt.total);
+  if (g == 0) return hipSuccess;
+#define LPC_AXIS(INV, BB) k_fft_axis<INV, BB><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+  if (inverse) {
+    if (B == 8) LPC_AXIS(true, 8); else if (B == 16) LPC_AXIS(true, 16); else if (B == 32) LPC_AXIS(true, 32);
+    else return hipErrorInvalidValue;
+  } else {
+    if (B == 8) LPC_AXIS(false, 8); else if (B == 16) LPC_AXIS(false, 16); else if (B == 32) LPC_AXIS(false, 32);
+    else return hipErrorInvalidValue;
   }
 #undef LPC_AXIS
   return hipGetLastError();
 }
 
-hipError_t fft_x_poisson(float2* A, float2* B, float2* C, int nm, int pitch, double box, int deconv_power,
-                         hipStream_t s) {
+hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, size_t lds, hipStream_t s) {
   ensure_init();
-  Plan1D pl;
-  if (!make_plan(nm, &pl)) return hipErrorInvalidValue;
-  const int Bc = strided_cols(nm);
-  const int nh = nm / 2 + 1, ntc = (nh + Bc - 1) / Bc;
-  const float kf = static_cast<float>(2.0 * M_PI / box);
-  const float inv_m3 = static_cast<float>(1.0 / (static_cast<double>(nm) * nm * nm));
-  const size_t lds = lds_x_poisson(nm, Bc);
-  const unsigned grid = nm * ntc;
-  if (Bc == 8) k_fft_x_poisson<8><<<grid, kFftNT, lds, s>>>(A, B, C, nm, pitch, kf, inv_m3, deconv_power, pl);
-  else if (Bc == 16) k_fft_x_poisson<16><<<grid, kFftNT, lds, s>>>(A, B, C, nm, pitch, kf, inv_m3, deconv_power, pl);
-  else k_fft_x_poisson<32><<<grid, kFftNT, lds, s>>>(A, B, C, nm, pitch, kf, inv_m3, deconv_power, pl);
+  const unsigned g = item_grid(wt.total);
+  if (g == 0) return hipSuccess;
+  if (B == 4) k_fft_x_poisson<4><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total);
+  else if (B == 8) k_fft_x_poisson<8><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total);
+  else if (B == 16) k_fft_x_poisson<16><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t fft_z_c2r_aos3(const float2* A, const float2* B, const float2* C, int nm, int pitch, float* out,
-                          hipStream_t s) {
+hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, size_t lds, hipStream_t s) {
   ensure_init();
-  Plan1D pl;
-  if (!make_plan(nm / 2, &pl)) return hipErrorInvalidValue;
-  const int R = std::max(4, std::min(16, z_rows(nm, 3))), nrows = nm * nm;
-  const unsigned grid = (nrows + R - 1) / R;
-  const size_t lds = lds_z_c2r(nm, 3 * R);
-  if (R == 4) k_fft_z_c2r<3, 4><<<grid, kFftNT, lds, s>>>(A, B, C, nm, nrows, pitch, out, 1.0f, pl);
-  else if (R == 8) k_fft_z_c2r<3, 8><<<grid, kFftNT, lds, s>>>(A, B, C, nm, nrows, pitch, out, 1.0f, pl);
-  else k_fft_z_c2r<3, 16><<<grid, kFftNT, lds, s>>>(A, B, C, nm, nrows, pitch, out, 1.0f, pl);
-  return hipGetLastError();
-}
-
-hipError_t fft_z_c2r_real(const float2* in, int n, int pitch, float* out, float scale, hipStream_t s) {
-  ensure_init();
-  Plan1D pl;
-  if (!make_plan(n / 2, &pl)) return hipErrorInvalidValue;
-  const int R = std::max(8, z_rows(n, 1)), nrows = n * n;
-  const unsigned grid = (nrows + R - 1) / R;
-  const size_t lds = lds_z_c2r(n, R);
-  if (R == 8) k_fft_z_c2r<1, 8><<<grid, kFftNT, lds, s>>>(in, in, in, n, nrows, pitch, out, scale, pl);
-  else if (R == 16) k_fft_z_c2r<1, 16><<<grid, kFftNT, lds, s>>>(in, in, in, n, nrows, pitch, out, scale, pl);
-  else k_fft_z_c2r<1, 32><<<grid, kFftNT, lds, s>>>(in, in, in, n, nrows, pitch, out, scale, pl);
+  const unsigned g = item_grid(wt.total);
+  if (g == 0) return hipSuccess;
+#define LPC_ZC2R(NC, RR) k_fft_z_c2r<NC, RR><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+  if (nc == 3) {
+    if (R == 4) LPC_ZC2R(3, 4); else if (R == 8) LPC_ZC2R(3, 8); else if (R == 16) LPC_ZC2R(3, 16);
+    else return hipErrorInvalidValue;
+  } else if (nc == 1) {
+    if (R == 8) LPC_ZC2R(1, 8); else if (R == 16) LPC_ZC2R(1, 16); else if (R == 32) LPC_ZC2R(1, 32);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef LPC_ZC2R
   return hipGetLastError();
 }
 

@@ -198,8 +198,8 @@ __device__ __forceinline__ void fft_stage(float2* tile, const float2* tws, int n
 
 // All stages of plan `pl` over the B columns of the tile (row pitch B + 1). tw is the plan's per-stage twiddle
 // table. The caller has synchronised after filling the tile.
-template <bool INV>
-__device__ void fft_tile(float2* tile, const float2* tw, const Plan1D& pl, int B, int tid) {
+template <bool INV, class PL>
+__device__ __forceinline__ void fft_tile(float2* tile, const float2* tw, const PL& pl, int B, int tid) {
   const TileGeom g(B, tid);
   const int n = pl.n;
   for (int s = 0; s < pl.nst; ++s) {
@@ -217,7 +217,8 @@ __device__ void fft_tile(float2* tile, const float2* tw, const Plan1D& pl, int B
 }
 
 // Fill the per-stage twiddle table of plan `pl` (n - 1 entries), rounded from FP64. No barrier.
-__device__ __forceinline__ void fill_stage_twiddles(float2* tw, const Plan1D& pl, int tid) {
+template <class PL>
+__device__ __forceinline__ void fill_stage_twiddles(float2* tw, const PL& pl, int tid) {
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.radix[s], p = pl.p[s], cnt = p * (R - 1);
     if (p == 1) continue;

@@ -46,45 +46,106 @@ struct KickDrift {
   int cola;
 };
 
-hipError_t fill_u64(uint64_t* p, size_t count, hipStream_t s);
 hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s);
 
-// Fixed-point CIC deposit into C[nm^3] (must be zeroed). scale = nm 2^16 / box in FP64.
-hipError_t deposit(const float* pos, int64_t n, int nm, double scale, uint64_t* C, int* flags, hipStream_t s);
+// ---------------------------------------------------------------------------------------------------------------
+// Batched stage launches. Every stage kernel runs over the items of a work table: FFT kernels take one item per
+// workgroup (w = blockIdx.x); the light particle kernels walk w = blockIdx.x, blockIdx.x + G, ... with a capped grid
+// of G workgroups. Item w belongs to job j with offs[j] <= w < offs[j + 1]
+// (offs has njob + 1 entries, offs[0] = 0, offs[njob] = total, every offs[j] a multiple of 8 so that items keep their
+// XCD position within a job). A single box is a batch of one job. Job arrays and offsets live in device memory.
+// Pointers read from job tables are generic; casting them to the global address space lets the compiler issue
+// global (not flat) memory instructions for them, as it does for pointer kernel arguments.
+// (The host pass of hipcc also parses kernel bodies; there the qualifiers are dropped.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LPC_GLOBAL __attribute__((address_space(1)))
+#define LPC_CONST __attribute__((address_space(4)))
+#else
+#define LPC_GLOBAL
+#define LPC_CONST
+#endif
+template <class T>
+__device__ __forceinline__ LPC_GLOBAL T* to_global(T* p) {
+  return (LPC_GLOBAL T*)p;
+}
+// Job tables are written before a launch and only read by it: reading them through the constant address space
+// lets the compiler use scalar loads and reload fields instead of holding them in registers across a work loop.
+template <class T>
+__device__ __forceinline__ const LPC_CONST T* to_const(const T* p) {
+  return (const LPC_CONST T*)p;
+}
 
-// z-pass of the forward r2c 3-D FFT.
-//   from fixed point: delta = C * mscale - 1 (FP64, rounded to FP32), rows of nm reals, nrows = nm^2
-hipError_t fft_z_r2c_fixed(const uint64_t* C, int nm, double mscale, float2* out, int pitch, int* flags,
-                           hipStream_t s);
-//   from an FP32 real mesh (rows of n reals)
-hipError_t fft_z_r2c_real(const float* in, int n, float2* out, int pitch, hipStream_t s);
+struct WorkTable {
+  const int* offs;
+  int njob;
+  int total;
+};
 
-// Complex FFT along a strided axis of `ncomp` meshes (in place). Element (axis j, outer o, column c, comp q) is at
-// base + q*comp_stride + o*outer_stride + j*axis_stride + c.
-hipError_t fft_axis(float2* base, int n, int64_t axis_stride, int64_t outer_stride, int n_outer, int ncols, int ncomp,
-                    int64_t comp_stride, bool inverse, hipStream_t s);
+struct FillJob {        // zero `count` 64-bit words
+  uint64_t* p;
+  int64_t count;
+};
+struct PartJob {        // one box's particles and meshes
+  float* pos;
+  float* vel;
+  const float* psi1;
+  const float* psi2;
+  int64_t n;
+  uint64_t* dens;       // fixed-point counts (deposit)
+  const float* force;   // AoS float3 force mesh (gather)
+  float* grad;          // gather output [3][n] (pm force only)
+  int nm;
+  float box;
+  double scale;         // nm 2^16 / box
+};
+struct ZR2CJob {        // forward z pass of one mesh
+  const void* in;       // uint64 counts (fixed) or FP32 reals
+  float2* out;
+  double mscale;        // fixed point: delta = C mscale - 1
+  int n, nrows, pitch;
+  Plan1D pl;            // length n / 2
+};
+struct AxisJob {        // complex FFT along a strided axis, ncomp meshes
+  float2* base;
+  int64_t astr, ostr, cstr;
+  int n, ncols, ntc, per_comp;  // per_comp = n_outer * ntc tiles (rounded up to 8)
+  Plan1D pl;
+};
+struct PoissonJob {     // fused forward x / Poisson-gradient / inverse x of one box
+  float2 *A, *B, *C;
+  int nm, pitch, ntc, deconv;
+  float kf, inv_m3;
+  Plan1D pl;
+};
+struct ZC2RJob {        // inverse z pass of NC spectra of one mesh
+  const float2 *in0, *in1, *in2;
+  float* out;
+  int n, nrows, pitch;
+  float scale;
+  Plan1D pl;            // length n / 2
+};
 
-// Fused x-pass: forward FFT along x of the half spectrum in A (after z and y passes), Poisson/deconvolution/
-// gradient multiply for the three components, inverse FFT along x; outputs into A (x comp), B (y), C (z).
-hipError_t fft_x_poisson(float2* A, float2* B, float2* C, int nm, int pitch, double box, int deconv_power,
-                         hipStream_t s);
+// Tile geometry chosen for one transform length (shared by the host builder and the launchers).
+int strided_cols(int n);          // B of strided passes
+int z_rows(int n, int nc);        // rows per z-pass tile for nc interleaved spectra
+size_t lds_z_r2c(int n, int B);
+size_t lds_axis(int n, int B);
+size_t lds_x_poisson(int n, int B);
+size_t lds_z_c2r(int n, int B);
 
-// z-pass of the inverse c2r 3-D FFT: three component spectra -> AoS float3 real mesh out[nm^3][3].
-hipError_t fft_z_c2r_aos3(const float2* A, const float2* B, const float2* C, int nm, int pitch, float* out,
-                          hipStream_t s);
-//   one spectrum -> planar real mesh out[n^3] times `scale`
-hipError_t fft_z_c2r_real(const float2* in, int n, int pitch, float* out, float scale, hipStream_t s);
-
-// Fused CIC gather of the AoS force mesh + COLA kick (+ drift) per particle.
-hipError_t gather_kick_drift(float* pos, float* vel, const float* psi1, const float* psi2, int64_t n,
-                             const float* force, int nm, double scale, float box, KickDrift kd, int* flags,
-                             hipStream_t s);
-// CIC gather only: grad[3][n].
-hipError_t gather(const float* pos, int64_t n, const float* force, int nm, double scale, float* grad, int* flags,
-                  hipStream_t s);
-// vel += sign * (f1 psi1 + f2 psi2)
-hipError_t frame_velocity(float* vel, const float* psi1, const float* psi2, int64_t n, float f1, float f2,
-                          hipStream_t s);
+int fill_items(int64_t count);    // items of a fill job
+hipError_t launch_fill(const FillJob* jobs, WorkTable wt, hipStream_t s);
+hipError_t launch_deposit(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s);
+hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, hipStream_t s);
+hipError_t launch_gather(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s);
+hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, hipStream_t s);
+// B: tile columns (rows for z passes); lds: dynamic LDS bytes (the max over the jobs).
+// One-time kernel attribute set-up (large dynamic LDS); launches do it themselves, graph capture calls it first.
+void init_kernels();
+hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, size_t lds, int* flags, hipStream_t s);
+hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, size_t lds, hipStream_t s);
+hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, size_t lds, hipStream_t s);
+hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, size_t lds, hipStream_t s);
 
 // Initial conditions on an N^3 lattice.
 hipError_t ic_noise(uint64_t seed, int N, float* out, hipStream_t s);

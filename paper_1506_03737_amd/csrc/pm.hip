@@ -6,6 +6,9 @@
 // fraction f = u & 0xffff. The deposit adds prod_d (2^16 - f_d or f_d) to the 8 corners with 64-bit integer atomics,
 // so every particle adds exactly 2^48 and the mesh does not depend on the order of the additions. The gather uses
 // the same u, with weights f 2^-16 and 1 - f 2^-16 (exact in FP32), so it is the transpose of the deposit.
+//
+// The kernels are batched over the jobs (boxes) of a work table, with a capped grid that strides over the items;
+// an item is kNT particles of one box.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -31,9 +34,32 @@ __device__ __forceinline__ bool fixed_coord(float x, double scale, int64_t perio
   return true;
 }
 
-__global__ __launch_bounds__(kNT) void k_fill_u64(uint64_t* __restrict__ p, size_t count) {
-  const size_t stride = static_cast<size_t>(gridDim.x) * kNT;
-  for (size_t i = static_cast<size_t>(blockIdx.x) * kNT + threadIdx.x; i < count; i += stride) p[i] = 0;
+__device__ __forceinline__ int find_job(const LPC_CONST int* __restrict__ offs, int njob, int w) {
+  int lo = 0, hi = njob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+constexpr int kFillChunk = kNT * 16;  // words per fill item
+
+__global__ __launch_bounds__(kNT) void k_fill(const FillJob* __restrict__ jobs, const int* __restrict__ offs, int njob,
+                                              int total) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST FillJob& J = to_const(jobs)[jb];
+    const int64_t base = static_cast<int64_t>(w - offs[jb]) * kFillChunk;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int64_t i = base + m * kNT + threadIdx.x;
+      if (i < J.count) to_global(J.p)[i] = 0;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kNT) void k_fill_i32(int* __restrict__ p, size_t count, int value) {
@@ -41,23 +67,25 @@ __global__ __launch_bounds__(kNT) void k_fill_i32(int* __restrict__ p, size_t co
   for (size_t i = static_cast<size_t>(blockIdx.x) * kNT + threadIdx.x; i < count; i += stride) p[i] = value;
 }
 
-__global__ __launch_bounds__(kNT) void k_deposit(const float* __restrict__ pos, int64_t n, int nm, double scale,
-                                                 uint64_t* __restrict__ C, int* __restrict__ flags) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (i >= n) return;
+template <class PJ>
+__device__ __forceinline__ void deposit_one(const PJ& J, int64_t i, int* flags) {
+  const int64_t n = J.n;
+  const int nm = J.nm;
   const int64_t period = static_cast<int64_t>(nm) << kFracBits;
   uint32_t c[3], f[3];
   bool ok = true;
+  LPC_GLOBAL const float* pos = to_global(J.pos);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], scale, period, &c[d], &f[d]);
+  for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], J.scale, period, &c[d], &f[d]);
   if (!ok) {
     atomicOr(flags + kFlagNonfinite, 1);
     return;
   }
-  uint64_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
+  const uint64_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
   const uint32_t xs[2] = {c[0], (c[0] + 1 == static_cast<uint32_t>(nm)) ? 0u : c[0] + 1};
   const uint32_t ys[2] = {c[1], (c[1] + 1 == static_cast<uint32_t>(nm)) ? 0u : c[1] + 1};
   const uint32_t zs[2] = {c[2], (c[2] + 1 == static_cast<uint32_t>(nm)) ? 0u : c[2] + 1};
+  LPC_GLOBAL unsigned long long* C = to_global(reinterpret_cast<unsigned long long*>(J.dens));
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
 #pragma unroll
@@ -68,14 +96,25 @@ __global__ __launch_bounds__(kNT) void k_deposit(const float* __restrict__ pos, 
       for (int e = 0; e < 2; ++e) {
         const uint64_t w = wab * wz[e];
         if (w != 0)
-          atomicAdd(reinterpret_cast<unsigned long long*>(C + rowbase + zs[e]), static_cast<unsigned long long>(w));
+          __hip_atomic_fetch_add(C + rowbase + zs[e], static_cast<unsigned long long>(w), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }
 }
 
+__global__ __launch_bounds__(kNT) void k_deposit(const PartJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                 int njob, int total, int* __restrict__ flags) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST PartJob& J = to_const(jobs)[jb];
+    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    if (i < J.n) deposit_one(J, i, flags);
+  }
+}
+
 // Interpolate the AoS float3 mesh to one particle; false if the position is not usable.
-__device__ __forceinline__ bool cic_gather(const float* __restrict__ F, int nm, double scale, float x, float y,
+__device__ __forceinline__ bool cic_gather(LPC_GLOBAL const float* __restrict__ F, int nm, double scale, float x, float y,
                                            float z, float g[3]) {
   const int64_t period = static_cast<int64_t>(nm) << kFracBits;
   uint32_t c[3], f[3];
@@ -100,7 +139,7 @@ __device__ __forceinline__ bool cic_gather(const float* __restrict__ F, int nm, 
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const float w = wab * wz[e];
-        const float* p = F + 3 * (rowbase + zs[e]);
+        LPC_GLOBAL const float* p = F + 3 * (rowbase + zs[e]);
         gx += w * p[0];
         gy += w * p[1];
         gz += w * p[2];
@@ -113,73 +152,90 @@ __device__ __forceinline__ bool cic_gather(const float* __restrict__ F, int nm, 
   return true;
 }
 
-__global__ __launch_bounds__(kNT) void k_gather_kick_drift(float* __restrict__ pos, float* __restrict__ vel,
-                                                           const float* __restrict__ psi1,
-                                                           const float* __restrict__ psi2, int64_t n,
-                                                           const float* __restrict__ F, int nm, double scale,
-                                                           float box, KickDrift kd, int* __restrict__ flags) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (i >= n) return;
-  float x[3] = {pos[i], pos[n + i], pos[2 * n + i]};
-  float g[3];
-  if (!cic_gather(F, nm, scale, x[0], x[1], x[2], g)) {
-    atomicOr(flags + kFlagNonfinite, 1);
-    return;
-  }
+__global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __restrict__ jobs,
+                                                           const int* __restrict__ offs, int njob, int total,
+                                                           KickDrift kd, int* __restrict__ flags) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST PartJob& J = to_const(jobs)[jb];
+    const int64_t n = J.n;
+    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    if (i >= n) continue;
+    LPC_GLOBAL float* pos = to_global(J.pos);
+    LPC_GLOBAL float* vel = to_global(J.vel);
+    LPC_GLOBAL const float* psi1 = to_global(J.psi1);
+    LPC_GLOBAL const float* psi2 = to_global(J.psi2);
+    float x[3] = {pos[i], pos[n + i], pos[2 * n + i]};
+    float g[3];
+    if (!cic_gather(to_global(J.force), J.nm, J.scale, x[0], x[1], x[2], g)) {
+      atomicOr(flags + kFlagNonfinite, 1);
+      continue;
+    }
+    const float box = J.box;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    float acc = g[d];
-    float p1 = 0.f, p2 = 0.f;
-    if (kd.cola) {
-      p1 = psi1[d * n + i];
-      p2 = psi2[d * n + i];
-      acc += kd.d1 * p1 + kd.d2m * p2;
-    }
-    float v = vel[d * n + i] + kd.kick * acc;
-    vel[d * n + i] = v;
-    if (kd.do_drift) {
-      float xn = x[d] + kd.drift * v;
-      if (kd.cola) xn += kd.dd1 * p1 + kd.dd2 * p2;
-      if (xn >= box) xn -= box;
-      if (xn < 0.f) xn += box;
-      pos[d * n + i] = xn;
+    for (int d = 0; d < 3; ++d) {
+      float acc = g[d];
+      float p1 = 0.f, p2 = 0.f;
+      if (kd.cola) {
+        p1 = psi1[d * n + i];
+        p2 = psi2[d * n + i];
+        acc += kd.d1 * p1 + kd.d2m * p2;
+      }
+      const float v = vel[d * n + i] + kd.kick * acc;
+      vel[d * n + i] = v;
+      if (kd.do_drift) {
+        float xn = x[d] + kd.drift * v;
+        if (kd.cola) xn += kd.dd1 * p1 + kd.dd2 * p2;
+        if (xn >= box) xn -= box;
+        if (xn < 0.f) xn += box;
+        pos[d * n + i] = xn;
+      }
     }
   }
 }
 
-__global__ __launch_bounds__(kNT) void k_gather(const float* __restrict__ pos, int64_t n, const float* __restrict__ F,
-                                                int nm, double scale, float* __restrict__ grad,
-                                                int* __restrict__ flags) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (i >= n) return;
-  float g[3];
-  if (!cic_gather(F, nm, scale, pos[i], pos[n + i], pos[2 * n + i], g)) {
-    atomicOr(flags + kFlagNonfinite, 1);
-    g[0] = g[1] = g[2] = 0.f;
+__global__ __launch_bounds__(kNT) void k_gather(const PartJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                int njob, int total, int* __restrict__ flags) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST PartJob& J = to_const(jobs)[jb];
+    const int64_t n = J.n;
+    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    if (i >= n) continue;
+    float g[3];
+    LPC_GLOBAL const float* pos = to_global(J.pos);
+    LPC_GLOBAL float* grad = to_global(J.grad);
+    if (!cic_gather(to_global(J.force), J.nm, J.scale, pos[i], pos[n + i], pos[2 * n + i], g)) {
+      atomicOr(flags + kFlagNonfinite, 1);
+      g[0] = g[1] = g[2] = 0.f;
+    }
+    grad[i] = g[0];
+    grad[n + i] = g[1];
+    grad[2 * n + i] = g[2];
   }
-  grad[i] = g[0];
-  grad[n + i] = g[1];
-  grad[2 * n + i] = g[2];
 }
 
-__global__ __launch_bounds__(kNT) void k_frame_velocity(float* __restrict__ vel, const float* __restrict__ psi1,
-                                                        const float* __restrict__ psi2, int64_t count, float f1,
-                                                        float f2) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (i < count) vel[i] += f1 * psi1[i] + f2 * psi2[i];
+// vel += f1 psi1 + f2 psi2 over the 3 n components (items of kNT values)
+__global__ __launch_bounds__(kNT) void k_frame_velocity(const PartJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                        int njob, int total, float f1, float f2) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST PartJob& J = to_const(jobs)[jb];
+    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    if (i < 3 * J.n) to_global(J.vel)[i] += f1 * to_global(J.psi1)[i] + f2 * to_global(J.psi2)[i];
+  }
 }
 
-unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kNT - 1) / kNT); }
+constexpr int kPartGridCap = 256 * 8 * 4;
+
+unsigned grid_of(const WorkTable& wt, int cap) {
+  return static_cast<unsigned>(wt.total < cap ? wt.total : cap);
+}
 
 }  // namespace
 
-hipError_t fill_u64(uint64_t* p, size_t count, hipStream_t s) {
-  if (count == 0) return hipSuccess;
-  size_t blocks = (count + kNT - 1) / kNT;
-  if (blocks > 65536) blocks = 65536;
-  k_fill_u64<<<static_cast<unsigned>(blocks), kNT, 0, s>>>(p, count);
-  return hipGetLastError();
-}
+// items of a particle stage per job: ceil(n / kNT) (ceil(3n / kNT) for the frame velocity)
+int fill_items(int64_t count) { return static_cast<int>((count + kFillChunk - 1) / kFillChunk); }
 
 hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s) {
   if (count == 0) return hipSuccess;
@@ -189,31 +245,33 @@ hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t deposit(const float* pos, int64_t n, int nm, double scale, uint64_t* C, int* flags, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_deposit<<<grid_for(n), kNT, 0, s>>>(pos, n, nm, scale, C, flags);
+hipError_t launch_fill(const FillJob* jobs, WorkTable wt, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  k_fill<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total);
   return hipGetLastError();
 }
 
-hipError_t gather_kick_drift(float* pos, float* vel, const float* psi1, const float* psi2, int64_t n,
-                             const float* force, int nm, double scale, float box, KickDrift kd, int* flags,
-                             hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_gather_kick_drift<<<grid_for(n), kNT, 0, s>>>(pos, vel, psi1, psi2, n, force, nm, scale, box, kd, flags);
+hipError_t launch_deposit(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  k_deposit<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, flags);
   return hipGetLastError();
 }
 
-hipError_t gather(const float* pos, int64_t n, const float* force, int nm, double scale, float* grad, int* flags,
-                  hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_gather<<<grid_for(n), kNT, 0, s>>>(pos, n, force, nm, scale, grad, flags);
+hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  k_gather_kick_drift<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd, flags);
   return hipGetLastError();
 }
 
-hipError_t frame_velocity(float* vel, const float* psi1, const float* psi2, int64_t n, float f1, float f2,
-                          hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  k_frame_velocity<<<grid_for(3 * n), kNT, 0, s>>>(vel, psi1, psi2, 3 * n, f1, f2);
+hipError_t launch_gather(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  k_gather<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  k_frame_velocity<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, f1, f2);
   return hipGetLastError();
 }
 

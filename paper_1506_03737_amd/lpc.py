@@ -49,6 +49,10 @@ class Particles(ctypes.Structure):
                 ("psi2", ctypes.c_void_p), ("id", ctypes.c_void_p), ("n", ctypes.c_int64)]
 
 
+class BatchEntry(ctypes.Structure):
+    _fields_ = [("geom", Geometry), ("particles", Particles)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"liblpc.so not found at {LIB_PATH}: run __graft_entry__.build() first")
@@ -60,6 +64,9 @@ def _load():
         "lpc_init_ic": (i32, [P(Geometry), P(Cosmology), ctypes.c_uint64, dbl, P(Particles), vp, sz, vp]),
         "lpc_pm_force": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp, sz, vp]),
         "lpc_cola_step": (i32, [P(Geometry), P(Cosmology), P(Stepping), P(dbl), i32, P(Particles), vp, sz, vp]),
+        "lpc_workspace_bytes_batched": (sz, [P(BatchEntry), i32]),
+        "lpc_cola_step_batched": (i32, [P(BatchEntry), i32, P(Cosmology), P(Stepping), P(dbl), i32, vp, sz, vp]),
+        "lpc_graph_enable": (i32, [i32]),
         "lpc_power_spectrum": (i32, [P(Geometry), vp, i64, dbl, i32, P(dbl), P(dbl), P(i64), vp, sz, vp]),
         "lpc_cola_coefficients": (i32, [P(Cosmology), P(Stepping), P(dbl), i32, P(dbl)]),
         "lpc_linear_power": (i32, [P(Cosmology), P(dbl), i32, P(dbl)]),
@@ -81,7 +88,8 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_cola_step", "lpc_power_spectrum",
+EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_cola_step", "lpc_workspace_bytes_batched",
+            "lpc_cola_step_batched", "lpc_graph_enable", "lpc_power_spectrum",
             "lpc_cola_coefficients", "lpc_linear_power", "lpc_fft_r2c", "lpc_fft_c2r", "lpc_fft_pitch",
             "lpc_profile_enable", "lpc_profile_reset", "lpc_profile_count", "lpc_profile_get",
             "lpc_status_string", "lpc_last_error")
@@ -168,6 +176,41 @@ def lpc_cola_step(geom, cosmo, step, a_list, particles, ws, stream=None):
     _check(LIB.lpc_cola_step(ctypes.byref(geom), ctypes.byref(cosmo), ctypes.byref(step),
                              a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(a.size), ctypes.byref(p),
                              _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def _entries(boxes):
+    """boxes: sequence of (geometry, ParticleSet) -> ctypes array of BatchEntry (the particle sets stay referenced
+    by the caller)."""
+    arr = (BatchEntry * len(boxes))()
+    for i, (g, ps) in enumerate(boxes):
+        arr[i].geom = g
+        arr[i].particles = ps.c_struct()
+    return arr
+
+
+def lpc_workspace_bytes_batched(boxes):
+    return int(LIB.lpc_workspace_bytes_batched(_entries(boxes), len(boxes)))
+
+
+def workspace_batched(boxes, device="cuda"):
+    import torch
+    nbytes = lpc_workspace_bytes_batched(boxes)
+    if nbytes == 0:
+        raise LpcError(-2, "unsupported geometry in batch")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def lpc_cola_step_batched(boxes, cosmo, step, a_list, ws, stream=None):
+    """One lpc_cola_step run for every (geometry, ParticleSet) in `boxes`, all stages batched across boxes."""
+    a = np.ascontiguousarray(a_list, dtype=np.float64)
+    e = _entries(boxes)
+    _check(LIB.lpc_cola_step_batched(e, len(boxes), ctypes.byref(cosmo), ctypes.byref(step),
+                                     a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(a.size), _ptr(ws),
+                                     ws.numel(), _stream(stream)))
+
+
+def lpc_graph_enable(on=True):
+    _check(LIB.lpc_graph_enable(1 if on else 0))
 
 
 def lpc_power_spectrum(geom, pos, k_max, n_bins, ws, stream=None):

@@ -14,7 +14,7 @@ uniform in a from 0.1 to 1.0, modified COLA stepping with nLPT = -2.5, CIC windo
 import numpy as np
 
 COSMOLOGY = {"omega_m": 0.31, "h": 0.68, "sigma8": 0.8, "n_s": 0.96}
-STEPPING = {"cola": 1, "modified": 1, "n_lpt": -2.5, "deconv_power": 2}
+STEPPING = {"cola": 1, "modified": 1, "n_lpt": -2.5, "deconv_power": 1}
 A_LIST = [0.1 + 0.09 * i for i in range(11)]
 
 WORKLOADS = {

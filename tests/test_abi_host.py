@@ -74,6 +74,32 @@ def test_workspace_sizes_and_rejections():
     assert lpc.lpc_fft_pitch(768) == 392 and lpc.lpc_fft_pitch(64) == 40
 
 
+def test_batched_workspace_layout():
+    """Flags + job region, then per box 12 Nm^3 bytes (int64 counts / AoS float3 force) and three half spectra,
+    each region 256-byte aligned; an unsupported mesh anywhere in the batch gives 0."""
+    from paper_1506_03737_amd import lpc
+
+    def entry(nm, box=100.0):
+        e = lpc.BatchEntry()
+        e.geom = lpc.geometry(0, nm, box)
+        return e
+
+    def r256(x):
+        return (x + 255) // 256 * 256
+
+    def per_box(nm):
+        return r256(12 * nm**3) + 3 * r256(nm * nm * lpc.lpc_fft_pitch(nm) * 8)
+
+    one = (lpc.BatchEntry * 1)(entry(64))
+    base = lpc.LIB.lpc_workspace_bytes_batched(one, 1) - per_box(64)
+    assert base == 256 + (1 << 20)
+    arr = (lpc.BatchEntry * 3)(entry(192), entry(40), entry(320))
+    assert lpc.LIB.lpc_workspace_bytes_batched(arr, 3) == base + per_box(192) + per_box(40) + per_box(320)
+    arr[1] = entry(14)
+    assert lpc.LIB.lpc_workspace_bytes_batched(arr, 3) == 0
+    assert lpc.LIB.lpc_workspace_bytes_batched(arr, 0) == 0
+
+
 def test_argument_errors_are_status_codes():
     from paper_1506_03737_amd import lpc
     c = lpc.cosmology()

@@ -17,7 +17,7 @@ def gpu_r2c(lpc, f):
     n = f.shape[0]
     pitch = lpc.lpc_fft_pitch(n)
     out = torch.empty((n, n, pitch, 2), dtype=torch.float32, device="cuda")
-    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    ws = lpc.workspace(lpc.geometry(n, n, 1.0), lpc.LPC_OP_FFT)
     lpc.lpc_fft_r2c(n, to_dev(f.astype(np.float32)), out, ws)
     o = to_np(out)
     return o.view(np.complex64)[..., 0][:, :, : n // 2 + 1]
@@ -30,7 +30,7 @@ def gpu_c2r(lpc, F):
     buf[:, :, : n // 2 + 1, 0] = F.real
     buf[:, :, : n // 2 + 1, 1] = F.imag
     out = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
-    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    ws = lpc.workspace(lpc.geometry(n, n, 1.0), lpc.LPC_OP_FFT)
     lpc.lpc_fft_c2r(n, to_dev(buf), out, ws)
     return to_np(out)
 
