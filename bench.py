@@ -10,9 +10,11 @@ force and half kick, K drift/force/kick iterations and the frame-velocity conver
 all). value = N^3 * K / wall time (particle-steps/s), inputs resident in HBM before the clock starts.
 
 Also reported: the dominant kernel's achieved HBM bandwidth from HIP events recorded on the call's stream
-(roofline), and the FP64 CPU oracle's rate on a bounded sample (cpu_baseline).
+(roofline), the FP64 CPU oracle's rate on a bounded sample (cpu_baseline), and the batched form on 48 uneven boxes
+(96^3/128^3/160^3 particles, Nm = 2N, L = 300..600 Mpc/h, one lpc_cola_step_batched call replaying its recorded HIP
+graph; aggregate particle-steps/s, in "batched").
 
-Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--workload single|small|large] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--workload single|small|large] [--no-cpu] [--no-batched]
 """
 import argparse
 import json
@@ -26,6 +28,12 @@ if ROOT not in sys.path:
 
 METRIC = "particle-steps/s (COLA PM step), plain vs batched/learned at P(k) err <2%"
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes (read scaled by 2.0, write by 1.0, from
+# a 1 GiB copy), by (stage, mesh size); profiles/force_path_768_hbm_traffic.md. Must be re-measured (or removed) when
+# the kernel changes.
+MEASURED_TRAFFIC = {("fft x + poisson", 768): 7.345e9, ("fft y inv", 768): 11.137e9, ("fft z c2r", 768): 10.985e9,
+                    ("deposit", 768): 4.153e9, ("gather kick drift", 768): 7.505e9}
 
 
 def stage_bytes(stage, n_part, nm, ncomp_y=3):
@@ -44,8 +52,85 @@ def stage_bytes(stage, n_part, nm, ncomp_y=3):
         "fft y inv": 2 * 3 * H,
         "fft z c2r": 3 * H + 12 * M,        # read three spectra, write the AoS float3 force mesh
         "gather kick drift": 72 * n_part + 12 * corners,
-        "frame velocity": 36 * n_part,
+        "frame velocity": 48 * n_part,      # read vel, psi1, psi2; write vel
     }.get(stage)
+
+
+def stage_table(stats, n_part, nm, wall_ms):
+    stages = {}
+    for name, (launches, ms) in stats.items():
+        b = stage_bytes(name, n_part, nm)
+        avg = ms / launches
+        entry = {"launches": launches, "avg_ms": round(avg, 4), "share": round(ms / wall_ms, 4)}
+        if b is not None:
+            entry["GB_per_s"] = round(b / (avg * 1e-3) / 1e9, 1)
+        stages[name] = entry
+    return stages
+
+
+def batched_bench(lpc, synth, torch, steps):
+    """The 48-box batched form: ICs per box (untimed), one recording call, then one timed replay of the graph over
+    steps + 1 scale factors. Returns the "batched" object of the JSON line."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    cosmo = lpc.cosmology(**synth.COSMOLOGY)
+    step = lpc.stepping(**synth.STEPPING)
+    boxes = synth.batch_workload()
+    ics, sets, entries = [], [], []
+    for b in boxes:
+        n = b["n_side"] ** 3
+        geom = lpc.geometry(b["n_side"], b["n_mesh"], b["box"])
+        ic = lpc.ParticleSet.empty(n, dev)
+        ws_ic = lpc.workspace(geom, lpc.LPC_OP_INIT_IC, dev)
+        lpc.lpc_init_ic(geom, cosmo, b["seed"], 0.1, ic, ws_ic)
+        del ws_ic
+        ps = lpc.ParticleSet.empty(n, dev)
+        ics.append(ic)
+        sets.append(ps)
+        entries.append((geom, ps))
+    ws = lpc.workspace_batched(entries, dev)
+    n_total = sum(b["n_side"] ** 3 for b in boxes)
+
+    def reset():
+        for ps, ic in zip(sets, ics):
+            for k in ("pos", "vel", "psi1", "psi2", "id"):
+                getattr(ps, k).copy_(getattr(ic, k))
+
+    a_list = np.linspace(0.1, 1.0, steps + 1)
+    reset()
+    lpc.lpc_cola_step_batched(entries, cosmo, step, a_list, ws)  # records the graph (untimed)
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lpc.lpc_cola_step_batched(entries, cosmo, step, a_list, ws)  # replays it
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # per-stage times from one more (direct-launch, event-bracketed) run
+    reset()
+    lpc.lpc_profile_reset()
+    lpc.lpc_profile_enable(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lpc.lpc_cola_step_batched(entries, cosmo, step, a_list, ws)
+    torch.cuda.synchronize()
+    dt_prof = time.perf_counter() - t1
+    lpc.lpc_profile_enable(False)
+    stats = lpc.lpc_profile_stats()
+    # algorithmic bytes of a batched launch: the sum over boxes of each box's bytes
+    stages = {}
+    for name, (launches, ms) in stats.items():
+        per = [stage_bytes(name, b["n_side"] ** 3, b["n_mesh"]) for b in boxes]
+        avg = ms / launches
+        entry = {"launches": launches, "avg_ms": round(avg, 4), "share": round(ms / (dt_prof * 1e3), 4)}
+        if per[0] is not None:
+            entry["GB_per_s"] = round(sum(per) / (avg * 1e-3) / 1e9, 1)
+        stages[name] = entry
+    return {"value": n_total * steps / dt, "unit": "particle-steps/s", "ms_per_step": dt * 1e3 / steps,
+            "steps": steps, "boxes": len(boxes), "particles": n_total,
+            "workload": "48 boxes, N in {96,128,160} cycling, Nm = 2N, L = 300 + 300 j/47 Mpc/h, seeds 1000 + j, "
+                        "2LPT ICs at z=9, modified COLA nLPT=-2.5; one graph replay (graph recorded by an untimed "
+                        "identical call)",
+            "stages_direct_launch": stages}
 
 
 def cpu_baseline_sample():
@@ -75,6 +160,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single", choices=["single", "small", "large"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 48-box batched measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -131,20 +217,13 @@ def main():
     stats = lpc.lpc_profile_stats()
 
     value = n * args.steps / dt
-    stages = {}
-    for name, (launches, ms) in stats.items():
-        b = stage_bytes(name, n, nm)
-        avg = ms / launches
-        entry = {"launches": launches, "avg_ms": round(avg, 4), "share": round(ms / (dt * 1e3), 4)}
-        if b is not None:
-            entry["GB_per_s"] = round(b / (avg * 1e-3) / 1e9, 1)
-        stages[name] = entry
+    stages = stage_table(stats, n, nm, dt * 1e3)
     dom = max((k for k in stats if stage_bytes(k, n, nm) is not None), key=lambda k: stats[k][1])
     dl, dms = stats[dom]
     dbytes = stage_bytes(dom, n, nm)
     achieved = dbytes / (dms / dl * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": MEASURED_TRAFFIC.get((dom, nm)),
                 "algorithmic_bytes_per_launch": dbytes}
 
     out = {
@@ -157,6 +236,10 @@ def main():
         "roofline": roofline,
         "stages": stages,
     }
+    if not args.no_batched and args.workload == "single":
+        del ps, ic, ws
+        torch.cuda.empty_cache()
+        out["batched"] = batched_bench(lpc, synth, torch, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_sample()
     print(json.dumps(out), flush=True)
