@@ -91,8 +91,11 @@ enum {
 /* Number of columns of the per-time coefficient table written by lpc_cola_coefficients. */
 #define LPC_COEF_COLUMNS 12
 
-/* Workspace bytes needed by operation `op` for this geometry (0 on an invalid geometry or op). */
-size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op);
+/* Workspace bytes needed by operation `op` for this geometry and n_particles particles (0 on an invalid geometry,
+ * op or count). PM_FORCE, COLA_STEP and POWER_SPECTRUM need 1 <= n_particles <= 2^31 - 1: their workspace holds
+ * tile-sorted copies of the particles (about 16 B per particle for a force or spectrum, 112 B for a COLA run) next
+ * to the meshes; INIT_IC and FFT ignore n_particles. */
+size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op, int64_t n_particles);
 
 /* 2LPT initial conditions at scale factor a_init (Sec. 2.1 Eqs. 5-10; Sec. 5).
  * Draws a unit Gaussian per lattice point from SplitMix64 (Steele, Lea & Flood 2014) in counter mode:
@@ -108,7 +111,9 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
                        const lpc_particles* out, void* ws, size_t ws_bytes, void* stream);
 
 /* The particle-mesh force of Sec. 2.4 (Eqs. 20-21) at positions pos[3][n]:
- *   fixed-point CIC deposit (16 fractional bits per axis, int64 counts, each particle adds exactly 2^48),
+ *   particles sorted by mesh tile (16^3 cells) into the workspace (the single-GPU counterpart of moving particles
+ *   to the process that owns their slab, Sec. 3.3), fixed-point CIC deposit by one workgroup per tile
+ *   (16 fractional bits per axis, int64 counts, each particle adds exactly 2^48),
  *   delta = C (Nm^3 / n) 2^-48 - 1, forward r2c FFT, g_hat_j = i k_j (-1/k^2) delta_hat / W^p
  *   (W = prod sinc^2(pi n_d / Nm), p = step->deconv_power, zero at k = 0 and on the Nyquist plane of axis j),
  *   three c2r FFTs, CIC gather with the deposit's own fixed-point fractions.
@@ -121,7 +126,9 @@ lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, cons
  * frame momentum removed at a_0 (Sec. 2.3), then for i = 0..n_a-1: force at a_i, kick a_{i-1/2} -> a_{i+1/2}
  * (midpoints; a_{-1/2} = a_0, a_{N+1/2} = a_N), drift a_i -> a_{i+1} for i < n_a - 1; frame momentum added back at
  * the last time. inout->vel holds the Eulerian momentum at a_list[0] on entry and at a_list[n_a-1] on exit.
- * a_list is a host array, strictly increasing, positive, n_a >= 2. With cola = 0, psi1 and psi2 are not read. */
+ * a_list is a host array, strictly increasing, positive, n_a >= 2. With cola = 0, psi1 and psi2 are not read.
+ * The run works on tile-sorted copies of the particles in the workspace (re-sorted before every force evaluation)
+ * and writes pos and vel back in the caller's order at the end; psi1, psi2 and id are not modified. */
 lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, const lpc_stepping* step,
                          const double* a_list, int32_t n_a, const lpc_particles* inout, void* ws, size_t ws_bytes,
                          void* stream);

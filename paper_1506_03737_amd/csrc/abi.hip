@@ -116,12 +116,73 @@ bool fft_size_ok(int n) {
 
 constexpr size_t kJobRegion = size_t(1) << 20;  // device bytes reserved for the job tables of one call
 
-// Workspace plan of one operation on an n^3 mesh: flags, the job-table region, then 256-byte aligned regions.
-struct Plan {
-  size_t flags = 0, jobs = 0, dens = 0, A = 0, B = 0, C = 0, bins = 0, total = 0;
+// Particle storage of a call (after the meshes): tile-sorted copies of every box's particles (two copies for a COLA
+// run, ping-ponged by the per-step re-sort, with pos, vel, psi1, psi2 and the caller's index; one copy with pos and
+// the caller's index for a single force or spectrum), sort keys and ranks, and the tile counts and starts.
+struct BoxParts {
+  float *pos = nullptr, *vel = nullptr, *psi1 = nullptr, *psi2 = nullptr;
+  int* orig = nullptr;
+};
+struct SortSpace {
+  std::vector<BoxParts> copy[2];
+  std::vector<int64_t> pbase;
+  std::vector<int> tbase, nt;
+  int *key = nullptr, *rank = nullptr, *cnt = nullptr, *start = nullptr, *block_sums = nullptr;
+  int G = 0;  // buckets over all boxes (2 nt^3 + 1 each)
 };
 
-Plan make_ws_plan(int n, int op) {
+// Lays out the sort space of boxes with particle counts n[] and meshes nm[] from workspace offset `off` (base NULL:
+// sizes only) and returns the end offset.
+size_t layout_sort(char* base, size_t off, const std::vector<int64_t>& n, const std::vector<int>& nm, bool cola,
+                   SortSpace* out) {
+  auto take = [&off](size_t bytes) {
+    const size_t at = off;
+    off += round_up(bytes);
+    return at;
+  };
+  auto ptr = [base](size_t at) { return base ? base + at : nullptr; };
+  SortSpace ss;
+  int64_t ptot = 0;
+  int G = 0;
+  for (size_t b = 0; b < n.size(); ++b) {
+    ss.pbase.push_back(ptot);
+    ss.tbase.push_back(G);
+    const int nt = kern::tiles_per_side(nm[b]);
+    ss.nt.push_back(nt);
+    ptot += n[b];
+    G += 2 * nt * nt * nt + 1;
+  }
+  for (int c = 0; c < (cola ? 2 : 1); ++c) {
+    for (size_t b = 0; b < n.size(); ++b) {
+      const size_t v3 = sizeof(float) * 3 * static_cast<size_t>(n[b]);
+      BoxParts bp;
+      bp.pos = reinterpret_cast<float*>(ptr(take(v3)));
+      if (cola) {
+        bp.vel = reinterpret_cast<float*>(ptr(take(v3)));
+        bp.psi1 = reinterpret_cast<float*>(ptr(take(v3)));
+        bp.psi2 = reinterpret_cast<float*>(ptr(take(v3)));
+      }
+      bp.orig = reinterpret_cast<int*>(ptr(take(sizeof(int) * static_cast<size_t>(n[b]))));
+      ss.copy[c].push_back(bp);
+    }
+  }
+  ss.key = reinterpret_cast<int*>(ptr(take(sizeof(int) * static_cast<size_t>(ptot))));
+  ss.rank = reinterpret_cast<int*>(ptr(take(sizeof(int) * static_cast<size_t>(ptot))));
+  ss.cnt = reinterpret_cast<int*>(ptr(take(sizeof(int) * static_cast<size_t>(G))));
+  ss.start = reinterpret_cast<int*>(ptr(take(sizeof(int) * (static_cast<size_t>(G) + 1))));
+  ss.block_sums = reinterpret_cast<int*>(ptr(take(sizeof(int) * static_cast<size_t>(kern::scan_blocks(G)))));
+  ss.G = G;
+  if (out) *out = ss;
+  return off;
+}
+
+// Workspace plan of one operation on an n^3 mesh with np particles: flags, the job-table region, the meshes, then
+// the sort space, every region 256-byte aligned.
+struct Plan {
+  size_t flags = 0, jobs = 0, dens = 0, A = 0, B = 0, C = 0, bins = 0, sort = 0, total = 0;
+};
+
+Plan make_ws_plan(int n, int op, int64_t np) {
   Plan p;
   const size_t M = static_cast<size_t>(n) * n * n;
   const size_t cbytes = round_up(static_cast<size_t>(n) * n * kern::mesh_pitch(n) * sizeof(float2));
@@ -154,8 +215,18 @@ Plan make_ws_plan(int n, int op) {
     default:
       return Plan{};
   }
+  if (op == LPC_OP_PM_FORCE || op == LPC_OP_COLA_STEP || op == LPC_OP_POWER_SPECTRUM) {
+    p.sort = off;
+    off = layout_sort(nullptr, off, {np}, {n}, op == LPC_OP_COLA_STEP, nullptr);
+  }
   p.total = off;
   return p;
+}
+
+SortSpace sort_space(void* ws, const Plan& p, int n, int op, int64_t np) {
+  SortSpace ss;
+  layout_sort(static_cast<char*>(ws), p.sort, {np}, {n}, op == LPC_OP_COLA_STEP, &ss);
+  return ss;
 }
 
 lpc_status check_ws(void* ws, size_t ws_bytes, size_t need) {
@@ -360,7 +431,7 @@ struct ForceBox {
   int nm;
   double box;
   int64_t n;
-  float* pos;
+  float* pos;         // caller's arrays
   float* vel;
   const float* psi1;
   const float* psi2;
@@ -371,46 +442,108 @@ struct ForceBox {
 };
 
 struct ForceProgram {
-  Section fill, parts, frame, zr2c, yfwd, pois, yinv, zc2r;
+  // sorting: user -> copy 0; copy c -> copy 1 - c; per-copy particle stages
+  Section sort_user, sort_next[2], dep[2], parts[2], frame[2], unsort[2];
+  Section zr2c, yfwd, pois, yinv, zc2r;
   int Bz = 32, Bax = 32, Bp = 16, R3 = 16;
   size_t lds_z = 0, lds_ax = 0, lds_p = 0, lds_c = 0;
+  SortSpace ss;
+  bool cola_run = false;
 };
 
-ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, int deconv) {
+ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const SortSpace& ss, int deconv,
+                       bool cola_run) {
   ForceProgram f;
+  f.ss = ss;
+  f.cola_run = cola_run;
   for (const ForceBox& b : boxes) {
     f.Bz = std::min(f.Bz, std::max(8, kern::z_rows(b.nm, 1)));
     f.Bax = std::min(f.Bax, kern::strided_cols(b.nm));
     f.Bp = std::min(f.Bp, std::min(16, kern::strided_cols(b.nm)));
     f.R3 = std::min(f.R3, std::max(4, std::min(16, kern::z_rows(b.nm, 3))));
   }
-  std::vector<kern::FillJob> fills;
-  std::vector<kern::PartJob> parts;
+  const int ncopy = cola_run ? 2 : 1;
+  std::vector<kern::SortJob> su, sn[2];
+  std::vector<kern::DepJob> dj[2];
+  std::vector<kern::PartJob> pj[2];
+  std::vector<kern::UnsortJob> uj[2];
   std::vector<kern::ZR2CJob> zs;
   std::vector<kern::AxisJob> ys, yis;
   std::vector<kern::PoissonJob> ps;
   std::vector<kern::ZC2RJob> cs;
-  std::vector<int> i_fill, i_part, i_frame, i_z, i_y, i_yi, i_p, i_c;
-  for (const ForceBox& b : boxes) {
+  std::vector<int> i_part, i_frame, i_tile, i_z, i_y, i_yi, i_p, i_c;
+  for (size_t ib = 0; ib < boxes.size(); ++ib) {
+    const ForceBox& b = boxes[ib];
     const int nm = b.nm, pitch = kern::mesh_pitch(nm), nh = nm / 2 + 1;
     const int64_t M = static_cast<int64_t>(nm) * nm * nm;
-    fills.push_back(kern::FillJob{b.dens, M});
-    i_fill.push_back(kern::fill_items(M));
-    kern::PartJob pj{};
-    pj.pos = b.pos;
-    pj.vel = b.vel;
-    pj.psi1 = b.psi1;
-    pj.psi2 = b.psi2;
-    pj.n = b.n;
-    pj.dens = b.dens;
-    pj.force = b.force;
-    pj.grad = b.grad;
-    pj.nm = nm;
-    pj.box = static_cast<float>(b.box);
-    pj.scale = (static_cast<double>(nm) * 65536.0) / b.box;
-    parts.push_back(pj);
+    const double scale = (static_cast<double>(nm) * 65536.0) / b.box;
+    const int nt = ss.nt[ib];
     i_part.push_back(static_cast<int>((b.n + kern::kNT - 1) / kern::kNT));
     i_frame.push_back(static_cast<int>((3 * b.n + kern::kNT - 1) / kern::kNT));
+    i_tile.push_back(nt * nt * nt);
+    auto sort_job = [&](const BoxParts* src, const BoxParts& dst) {
+      kern::SortJob j{};
+      if (src) {
+        j.pos = src->pos;
+        j.vel = src->vel;
+        j.psi1 = src->psi1;
+        j.psi2 = src->psi2;
+        j.orig = src->orig;
+      } else {
+        j.pos = b.pos;
+        j.vel = b.vel;
+        j.psi1 = b.psi1;
+        j.psi2 = b.psi2;
+      }
+      j.dpos = dst.pos;
+      j.dvel = dst.vel;
+      j.dpsi1 = (j.psi1 && j.psi2) ? dst.psi1 : nullptr;  // a plain PM run may pass no displacements
+      j.dpsi2 = (j.psi1 && j.psi2) ? dst.psi2 : nullptr;
+      j.dorig = dst.orig;
+      j.n = b.n;
+      j.pbase = ss.pbase[ib];
+      j.tbase = ss.tbase[ib];
+      j.nt = nt;
+      j.nm = nm;
+      j.scale = scale;
+      return j;
+    };
+    su.push_back(sort_job(nullptr, ss.copy[0][ib]));
+    for (int c = 0; c < ncopy; ++c) {
+      const BoxParts& cp = ss.copy[c][ib];
+      if (cola_run) sn[c].push_back(sort_job(&cp, ss.copy[1 - c][ib]));
+      kern::DepJob d{};
+      d.pos = cp.pos;
+      d.n = b.n;
+      d.pbase = ss.pbase[ib];
+      d.tbase = ss.tbase[ib];
+      d.nt = nt;
+      d.nm = nm;
+      d.scale = scale;
+      d.dens = b.dens;
+      dj[c].push_back(d);
+      kern::PartJob p{};
+      p.pos = cp.pos;
+      p.vel = cp.vel;
+      p.psi1 = cp.psi1;
+      p.psi2 = cp.psi2;
+      p.n = b.n;
+      p.force = b.force;
+      p.grad = b.grad;
+      p.orig = cp.orig;
+      p.nm = nm;
+      p.box = static_cast<float>(b.box);
+      p.scale = scale;
+      pj[c].push_back(p);
+      kern::UnsortJob u{};
+      u.spos = cp.pos;
+      u.svel = cp.vel;
+      u.orig = cp.orig;
+      u.pos = b.pos;
+      u.vel = b.vel;
+      u.n = b.n;
+      uj[c].push_back(u);
+    }
     kern::ZR2CJob z{};
     z.in = b.dens;
     z.out = b.A;
@@ -457,9 +590,14 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, int deco
     f.lds_p = std::max(f.lds_p, kern::lds_x_poisson(nm, f.Bp));
     f.lds_c = std::max(f.lds_c, kern::lds_z_c2r(nm, 3 * f.R3));
   }
-  f.fill = jp.add(fills, i_fill);
-  f.parts = jp.add(parts, i_part);
-  f.frame = jp.add(parts, i_frame);
+  f.sort_user = jp.add(su, i_part);
+  for (int c = 0; c < ncopy; ++c) {
+    if (cola_run) f.sort_next[c] = jp.add(sn[c], i_part);
+    f.dep[c] = jp.add(dj[c], i_tile);
+    f.parts[c] = jp.add(pj[c], i_part);
+    f.frame[c] = jp.add(pj[c], i_frame);
+    f.unsort[c] = jp.add(uj[c], i_part);
+  }
   f.zr2c = jp.add(zs, i_z);
   f.yfwd = jp.add(ys, i_y);
   f.pois = jp.add(ps, i_p);
@@ -468,10 +606,23 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, int deco
   return f;
 }
 
-// deposit -> delta -> forward FFT -> Poisson/gradient -> inverse FFTs -> AoS force meshes, for every box
-void run_force_mesh(const JobPack& jp, const ForceProgram& f, int* flags, hipStream_t s) {
-  stage("fill density", s, [&] { return kern::launch_fill(jp.jobs<kern::FillJob>(f.fill), jp.table(f.fill), s); });
-  stage("deposit", s, [&] { return kern::launch_deposit(jp.jobs<kern::PartJob>(f.parts), jp.table(f.parts), flags, s); });
+// Tile sort of every box (counts cleared by a kernel, so the sequence may be recorded in a graph).
+void run_sort(const JobPack& jp, const SortSpace& ss, const Section& sec, int* flags, hipStream_t s) {
+  stage("sort keys", s, [&] { return kern::fill_i32(ss.cnt, static_cast<size_t>(ss.G), 0, s); });
+  stage("sort keys", s, [&] {
+    return kern::launch_tile_key(jp.jobs<kern::SortJob>(sec), jp.table(sec), ss.cnt, ss.key, ss.rank, flags, s);
+  });
+  stage("sort scan", s, [&] { return kern::launch_scan(ss.cnt, ss.start, ss.G, ss.block_sums, s); });
+  stage("sort scatter", s, [&] {
+    return kern::launch_scatter(jp.jobs<kern::SortJob>(sec), jp.table(sec), ss.key, ss.rank, ss.start, s);
+  });
+}
+
+// deposit (from sorted copy c) -> delta -> forward FFT -> Poisson/gradient -> inverse FFTs -> AoS force meshes
+void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags, hipStream_t s) {
+  stage("deposit", s, [&] {
+    return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(f.dep[c]), jp.table(f.dep[c]), f.ss.start, s);
+  });
   stage("fft z r2c", s, [&] {
     return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), true, f.Bz, f.lds_z, flags, s);
   });
@@ -481,18 +632,25 @@ void run_force_mesh(const JobPack& jp, const ForceProgram& f, int* flags, hipStr
   stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(f.zc2r), jp.table(f.zc2r), 3, f.R3, f.lds_c, s); });
 }
 
-// The whole COLA run over a_list for every box (all boxes share cosmology, stepping and time list).
+// The whole COLA run over a_list for every box (all boxes share cosmology, stepping and time list). Particles are
+// tile-sorted into workspace copy 0 first, re-sorted into the other copy before every later force evaluation, and
+// copied back to the caller's order at the end.
 void run_cola(const JobPack& jp, const ForceProgram& f, const std::vector<double>& tab, int n_a, double om, bool cola,
               int* flags, hipStream_t s) {
   auto row = [&tab](int i) { return tab.data() + static_cast<size_t>(i) * host::kCoefColumns; };
-  const kern::PartJob* pj = jp.jobs<kern::PartJob>(f.parts);
+  int c = 0;
+  run_sort(jp, f.ss, f.sort_user, flags, s);
   if (cola) {
     const float f1 = static_cast<float>(-row(0)[host::kF1]), f2 = static_cast<float>(-row(0)[host::kF2]);
-    stage("frame velocity", s, [&] { return kern::launch_frame(jp.jobs<kern::PartJob>(f.frame), jp.table(f.frame), f1, f2, s); });
+    stage("frame velocity", s, [&] { return kern::launch_frame(jp.jobs<kern::PartJob>(f.frame[c]), jp.table(f.frame[c]), f1, f2, s); });
   }
   for (int i = 0; i < n_a; ++i) {
+    if (i > 0) {
+      run_sort(jp, f.ss, f.sort_next[c], flags, s);
+      c = 1 - c;
+    }
     const double* r = row(i);
-    run_force_mesh(jp, f, flags, s);
+    run_force_mesh(jp, f, c, flags, s);
     kern::KickDrift kd;
     kd.kick = static_cast<float>(r[host::kK] * (-1.5 * om));
     kd.d1 = static_cast<float>(r[host::kD1]);
@@ -502,13 +660,16 @@ void run_cola(const JobPack& jp, const ForceProgram& f, const std::vector<double
     kd.dd2 = static_cast<float>(r[host::kDD2]);
     kd.do_drift = (i + 1 < n_a) ? 1 : 0;
     kd.cola = cola ? 1 : 0;
-    stage("gather kick drift", s, [&] { return kern::launch_gather_kick_drift(pj, jp.table(f.parts), kd, flags, s); });
+    stage("gather kick drift", s, [&] {
+      return kern::launch_gather_kick_drift(jp.jobs<kern::PartJob>(f.parts[c]), jp.table(f.parts[c]), kd, flags, s);
+    });
   }
   if (cola) {
     const double* r = row(n_a - 1);
     const float f1 = static_cast<float>(r[host::kF1]), f2 = static_cast<float>(r[host::kF2]);
-    stage("frame velocity", s, [&] { return kern::launch_frame(jp.jobs<kern::PartJob>(f.frame), jp.table(f.frame), f1, f2, s); });
+    stage("frame velocity", s, [&] { return kern::launch_frame(jp.jobs<kern::PartJob>(f.frame[c]), jp.table(f.frame[c]), f1, f2, s); });
   }
+  stage("unsort", s, [&] { return kern::launch_unsort(jp.jobs<kern::UnsortJob>(f.unsort[c]), jp.table(f.unsort[c]), s); });
 }
 
 ForceBox force_box(void* ws, const Plan& p, int nm, double box, int64_t n, float* pos, float* vel, const float* psi1,
@@ -574,11 +735,13 @@ hipStream_t capture_stream() {
 
 extern "C" {
 
-size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op) {
+size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op, int64_t n_particles) {
   if (!geom) return 0;
   const int n = (op == LPC_OP_INIT_IC) ? geom->n_side : geom->n_mesh;
   if (!fft_size_ok(n)) return 0;
-  return make_ws_plan(n, op).total;
+  const bool takes_particles = (op == LPC_OP_PM_FORCE || op == LPC_OP_COLA_STEP || op == LPC_OP_POWER_SPECTRUM);
+  if (takes_particles && (n_particles < 1 || n_particles > (int64_t(1) << 31) - 1)) return 0;
+  return make_ws_plan(n, op, n_particles).total;
 }
 
 int32_t lpc_fft_pitch(int32_t n) { return (n >= 2) ? kern::mesh_pitch(n) : 0; }
@@ -655,7 +818,7 @@ lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, cons
   if (step->deconv_power < 0 || step->deconv_power > 2) return fail(LPC_ERR_INVALID_ARG, "deconv_power not in 0..2");
   if (n <= 0 || n > (int64_t(1) << 31) - 1) return fail(LPC_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
   if (!pos || !grad_out) return fail(LPC_ERR_INVALID_ARG, "pos/grad_out is NULL");
-  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_PM_FORCE);
+  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_PM_FORCE, n);
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
@@ -664,10 +827,12 @@ lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, cons
     JobPack jp;
     const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, n, const_cast<float*>(pos), nullptr, nullptr, nullptr,
                                  grad_out, reinterpret_cast<uint64_t*>(density_fixed_out));
-    const ForceProgram f = add_force(jp, {b}, step->deconv_power);
+    const ForceProgram f = add_force(jp, {b}, sort_space(ws, p, geom->n_mesh, LPC_OP_PM_FORCE, n), step->deconv_power,
+                                     false);
     jp.upload(at(ws, p.jobs), s);
-    run_force_mesh(jp, f, flags, s);
-    stage("gather", s, [&] { return kern::launch_gather(jp.jobs<kern::PartJob>(f.parts), jp.table(f.parts), flags, s); });
+    run_sort(jp, f.ss, f.sort_user, flags, s);
+    run_force_mesh(jp, f, 0, flags, s);
+    stage("gather", s, [&] { return kern::launch_gather(jp.jobs<kern::PartJob>(f.parts[0]), jp.table(f.parts[0]), flags, s); });
     return finish(flags, s);
   });
 }
@@ -682,7 +847,7 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
   if (inout->n == 0) return fail(LPC_ERR_INVALID_ARG, "no particles");
   std::vector<double> tab(static_cast<size_t>(n_a > 0 ? n_a : 0) * host::kCoefColumns);
   if (lpc_status st = lpc_cola_coefficients(cosmo, step, a_list, n_a, tab.data())) return st;
-  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_COLA_STEP);
+  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_COLA_STEP, inout->n);
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
@@ -691,7 +856,8 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
     JobPack jp;
     const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, inout->n, inout->pos, inout->vel, inout->psi1,
                                  inout->psi2, nullptr, nullptr);
-    const ForceProgram f = add_force(jp, {b}, step->deconv_power);
+    const ForceProgram f = add_force(jp, {b}, sort_space(ws, p, geom->n_mesh, LPC_OP_COLA_STEP, inout->n),
+                                     step->deconv_power, true);
     jp.upload(at(ws, p.jobs), s);
     run_cola(jp, f, tab, n_a, cosmo->omega_m, step->cola != 0, flags, s);
     return finish(flags, s);
@@ -699,26 +865,38 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Batched form: workspace = flags, job region, then per box its int64/force mesh and three half spectra.
-static bool batch_layout(const lpc_batch_entry* e, int32_t n_real, std::vector<size_t>* offs, size_t* total) {
+// Batched form: workspace = flags, job region, then per box its int64/force mesh and three half spectra, then the
+// sort space of all boxes (two tile-sorted copies of every box's particles, keys, ranks, tile counts and starts).
+static bool batch_layout(const lpc_batch_entry* e, int32_t n_real, std::vector<size_t>* offs, size_t* total,
+                         SortSpace* ss, void* ws) {
   if (!e || n_real < 1) return false;
   size_t off = round_up(sizeof(int) * kern::kNumFlags) + round_up(kJobRegion);
   if (offs) offs->clear();
+  std::vector<int64_t> np;
+  std::vector<int> nms;
   for (int i = 0; i < n_real; ++i) {
     const int nm = e[i].geom.n_mesh;
     if (!fft_size_ok(nm)) return false;
+    const int64_t n = e[i].particles.n;
+    if (n < 1 || n > (int64_t(1) << 31) - 1) return false;
     const size_t M = static_cast<size_t>(nm) * nm * nm;
     const size_t cbytes = round_up(static_cast<size_t>(nm) * nm * kern::mesh_pitch(nm) * sizeof(float2));
     if (offs) offs->push_back(off);
     off += round_up(M * 12) + 3 * cbytes;
+    np.push_back(n);
+    nms.push_back(nm);
   }
+  int64_t ptot = 0;
+  for (int64_t n : np) ptot += n;
+  if (ptot > (int64_t(1) << 31) - 1) return false;
+  off = layout_sort(static_cast<char*>(ws), off, np, nms, true, ss);
   *total = off;
   return true;
 }
 
 size_t lpc_workspace_bytes_batched(const lpc_batch_entry* entries, int32_t n_real) {
   size_t total = 0;
-  return batch_layout(entries, n_real, nullptr, &total) ? total : 0;
+  return batch_layout(entries, n_real, nullptr, &total, nullptr, nullptr) ? total : 0;
 }
 
 lpc_status lpc_graph_enable(int32_t on) {
@@ -742,7 +920,9 @@ lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real,
   if (lpc_status st = lpc_cola_coefficients(cosmo, step, a_list, n_a, tab.data())) return st;
   std::vector<size_t> offs;
   size_t need = 0;
-  batch_layout(entries, n_real, &offs, &need);
+  SortSpace ss;
+  if (!batch_layout(entries, n_real, &offs, &need, &ss, ws))
+    return fail(LPC_ERR_INVALID_ARG, "batch has more than 2^31 - 1 particles in all");
   if (lpc_status st = check_ws(ws, ws_bytes, need)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
@@ -771,7 +951,7 @@ lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real,
       b.C = reinterpret_cast<float2*>(base + round_up(M * 12) + 2 * cbytes);
       boxes.push_back(b);
     }
-    const ForceProgram f = add_force(jp, boxes, step->deconv_power);
+    const ForceProgram f = add_force(jp, boxes, ss, step->deconv_power, true);
     char* jobs_dev = at(ws, round_up(sizeof(int) * kern::kNumFlags));
     jp.upload(jobs_dev, s);
     const bool cola = step->cola != 0;
@@ -833,7 +1013,7 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
   const int64_t n = static_cast<int64_t>(N) * N * N;
   if (out->n != n) return fail(LPC_ERR_INVALID_ARG, "particles.n = %lld but n_side^3 = %lld",
                                static_cast<long long>(out->n), static_cast<long long>(n));
-  const Plan p = make_ws_plan(N, LPC_OP_INIT_IC);
+  const Plan p = make_ws_plan(N, LPC_OP_INIT_IC, 0);
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
@@ -895,7 +1075,7 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
   if (!pos || !k_mean || !pk || !n_modes) return fail(LPC_ERR_INVALID_ARG, "NULL array");
   if (n_bins < 1 || n_bins > 2048) return fail(LPC_ERR_INVALID_ARG, "n_bins must be in [1, 2048]");
   if (!(k_max > 0.0) || !std::isfinite(k_max)) return fail(LPC_ERR_INVALID_ARG, "k_max must be positive");
-  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_POWER_SPECTRUM);
+  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_POWER_SPECTRUM, n);
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
@@ -907,23 +1087,33 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
     double* sums = reinterpret_cast<double*>(at(ws, p.bins));
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(sums + 2 * n_bins);
     JobPack jp;
-    const Section fill = jp.add1(kern::FillJob{dens, M}, kern::fill_items(M));
-    kern::PartJob pj{};
-    pj.pos = const_cast<float*>(pos);
-    pj.n = n;
-    pj.dens = dens;
-    pj.nm = nm;
-    pj.box = static_cast<float>(geom->box);
-    pj.scale = (static_cast<double>(nm) * 65536.0) / geom->box;
-    const Section dep = jp.add1(pj, static_cast<int>((n + kern::kNT - 1) / kern::kNT));
+    const SortSpace ss = sort_space(ws, p, nm, LPC_OP_POWER_SPECTRUM, n);
+    const int nt = ss.nt[0];
+    kern::SortJob sj{};
+    sj.pos = pos;
+    sj.dpos = ss.copy[0][0].pos;
+    sj.dorig = ss.copy[0][0].orig;
+    sj.n = n;
+    sj.nt = nt;
+    sj.nm = nm;
+    sj.scale = (static_cast<double>(nm) * 65536.0) / geom->box;
+    const Section sort = jp.add1(sj, static_cast<int>((n + kern::kNT - 1) / kern::kNT));
+    kern::DepJob dj{};
+    dj.pos = sj.dpos;
+    dj.n = n;
+    dj.nt = nt;
+    dj.nm = nm;
+    dj.scale = sj.scale;
+    dj.dens = dens;
+    const Section dep = jp.add1(dj, nt * nt * nt);
     const R2CSections r = add_r2c(jp, dens, true, (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48, nm, A);
     jp.upload(at(ws, p.jobs), s);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
     stage("clear bins", s, [&] {
       return kern::fill_i32(reinterpret_cast<int*>(sums), static_cast<size_t>(6) * n_bins, 0, s);
     });
-    stage("fill density", s, [&] { return kern::launch_fill(jp.jobs<kern::FillJob>(fill), jp.table(fill), s); });
-    stage("deposit", s, [&] { return kern::launch_deposit(jp.jobs<kern::PartJob>(dep), jp.table(dep), flags, s); });
+    run_sort(jp, ss, sort, flags, s);
+    stage("deposit", s, [&] { return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(dep), jp.table(dep), ss.start, s); });
     run_r2c(jp, r, true, flags, s);
     const double V = geom->box * geom->box * geom->box;
     const double pscale = V / (static_cast<double>(M) * static_cast<double>(M));
@@ -949,7 +1139,7 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
 lpc_status lpc_fft_r2c(int32_t n, const float* in, float* out_complex, void* ws, size_t ws_bytes, void* stream) {
   if (lpc_status st = check_mesh(n, "n")) return st;
   if (!in || !out_complex) return fail(LPC_ERR_INVALID_ARG, "NULL array");
-  const Plan p = make_ws_plan(n, LPC_OP_FFT);
+  const Plan p = make_ws_plan(n, LPC_OP_FFT, 0);
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
@@ -966,7 +1156,7 @@ lpc_status lpc_fft_r2c(int32_t n, const float* in, float* out_complex, void* ws,
 lpc_status lpc_fft_c2r(int32_t n, float* in_complex, float* out, void* ws, size_t ws_bytes, void* stream) {
   if (lpc_status st = check_mesh(n, "n")) return st;
   if (!in_complex || !out) return fail(LPC_ERR_INVALID_ARG, "NULL array");
-  const Plan p = make_ws_plan(n, LPC_OP_FFT);
+  const Plan p = make_ws_plan(n, LPC_OP_FFT, 0);
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {

@@ -81,9 +81,42 @@ struct WorkTable {
   int total;
 };
 
-struct FillJob {        // zero `count` 64-bit words
-  uint64_t* p;
-  int64_t count;
+// Mesh tiles of the particle sort and of the tiled deposit: kTile^3 cells (narrower at the end of an axis when
+// kTile does not divide Nm); a box has nt = ceil(Nm / kTile) tiles per side, tile (tx, ty, tz) has index
+// t = (tx nt + ty) nt + tz and two buckets, 2 t (interior) and 2 t + 1 (boundary: the particle's cell is in the
+// tile's last layer along some axis); one extra bucket (2 nt^3) collects particles whose position is unusable.
+constexpr int kTile = 16;
+inline int tiles_per_side(int nm) { return (nm + kTile - 1) / kTile; }
+
+struct SortJob {        // key pass and scatter of one box: src (SoA [3][n]) -> dst in tile order
+  const float* pos;
+  const float* vel;     // vel / psi1 / psi2 are carried only when the dst pointer is not NULL
+  const float* psi1;
+  const float* psi2;
+  const int* orig;      // index in the caller's arrays; NULL when src is the caller's arrays (orig = i)
+  float* dpos;
+  float* dvel;
+  float* dpsi1;
+  float* dpsi2;
+  int* dorig;
+  int64_t n, pbase;     // particles; first global particle index of the box (key / rank arrays)
+  int tbase, nt, nm;    // first global tile index; tiles per side; mesh size
+  double scale;         // nm 2^16 / box
+};
+struct DepJob {         // tiled deposit of one box from its tile-sorted positions
+  const float* pos;
+  int64_t n, pbase;
+  int tbase, nt, nm;
+  double scale;
+  uint64_t* dens;
+};
+struct UnsortJob {      // sorted pos / vel back to the caller's order
+  const float* spos;
+  const float* svel;
+  const int* orig;
+  float* pos;
+  float* vel;
+  int64_t n;
 };
 struct PartJob {        // one box's particles and meshes
   float* pos;
@@ -93,7 +126,8 @@ struct PartJob {        // one box's particles and meshes
   int64_t n;
   uint64_t* dens;       // fixed-point counts (deposit)
   const float* force;   // AoS float3 force mesh (gather)
-  float* grad;          // gather output [3][n] (pm force only)
+  float* grad;          // gather output [3][n] (pm force only), written at index orig[i]
+  const int* orig;      // caller's index of each (sorted) particle; NULL = identity
   int nm;
   float box;
   double scale;         // nm 2^16 / box
@@ -133,9 +167,14 @@ size_t lds_axis(int n, int B);
 size_t lds_x_poisson(int n, int B);
 size_t lds_z_c2r(int n, int B);
 
-int fill_items(int64_t count);    // items of a fill job
-hipError_t launch_fill(const FillJob* jobs, WorkTable wt, hipStream_t s);
-hipError_t launch_deposit(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s);
+hipError_t launch_tile_key(const SortJob* jobs, WorkTable wt, int* cnt, int* key, int* rank, int* flags,
+                           hipStream_t s);
+int scan_blocks(int count);  // entries of the block-sum scratch of launch_scan
+hipError_t launch_scan(const int* cnt, int* start, int count, int* block_sums, hipStream_t s);  // start: count + 1
+hipError_t launch_scatter(const SortJob* jobs, WorkTable wt, const int* key, const int* rank, const int* start,
+                          hipStream_t s);
+hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* start, hipStream_t s);
+hipError_t launch_unsort(const UnsortJob* jobs, WorkTable wt, hipStream_t s);
 hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, hipStream_t s);
 hipError_t launch_gather(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s);
 hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, hipStream_t s);

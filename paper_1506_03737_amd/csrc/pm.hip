@@ -46,70 +46,300 @@ __device__ __forceinline__ int find_job(const LPC_CONST int* __restrict__ offs, 
   return lo;
 }
 
-constexpr int kFillChunk = kNT * 16;  // words per fill item
-
-__global__ __launch_bounds__(kNT) void k_fill(const FillJob* __restrict__ jobs, const int* __restrict__ offs, int njob,
-                                              int total) {
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
-    const LPC_CONST FillJob& J = to_const(jobs)[jb];
-    const int64_t base = static_cast<int64_t>(w - offs[jb]) * kFillChunk;
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int64_t i = base + m * kNT + threadIdx.x;
-      if (i < J.count) to_global(J.p)[i] = 0;
-    }
-  }
-}
-
 __global__ __launch_bounds__(kNT) void k_fill_i32(int* __restrict__ p, size_t count, int value) {
   const size_t stride = static_cast<size_t>(gridDim.x) * kNT;
   for (size_t i = static_cast<size_t>(blockIdx.x) * kNT + threadIdx.x; i < count; i += stride) p[i] = value;
 }
 
-template <class PJ>
-__device__ __forceinline__ void deposit_one(const PJ& J, int64_t i, int* flags) {
-  const int64_t n = J.n;
-  const int nm = J.nm;
-  const int64_t period = static_cast<int64_t>(nm) << kFracBits;
-  uint32_t c[3], f[3];
-  bool ok = true;
-  LPC_GLOBAL const float* pos = to_global(J.pos);
-#pragma unroll
-  for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], J.scale, period, &c[d], &f[d]);
-  if (!ok) {
-    atomicOr(flags + kFlagNonfinite, 1);
-    return;
+// ---------------------------------------------------------------------------------------------------------------
+// Tile sort. A box's mesh is cut into tiles of kTile^3 cells (the last tile of an axis may be narrower); a particle
+// belongs to the tile of its floor cell, and within it to one of two buckets: interior, or boundary when its cell is
+// in the last layer of the tile along any axis (only boundary particles can reach the next tile's cells). Bucket
+// 2 t + boundary; the box's last bucket (2 nt^3) holds particles whose position is unusable.
+// Key pass: bucket and rank among the bucket's particles. Scan: bucket starts. Scatter: copy each record to
+// start[bucket] + rank. The order within a bucket is not deterministic, but nothing downstream depends on it: the
+// deposit is integer and the other particle stages act per particle.
+
+__device__ __forceinline__ int bucket_of(uint32_t cx, uint32_t cy, uint32_t cz, int nt, int nm) {
+  const int t = (static_cast<int>(cx / kTile) * nt + static_cast<int>(cy / kTile)) * nt + static_cast<int>(cz / kTile);
+  auto last = [nm](uint32_t c) { return (c % kTile == kTile - 1) || (static_cast<int>(c) == nm - 1); };
+  return 2 * t + ((last(cx) || last(cy) || last(cz)) ? 1 : 0);
+}
+
+// Rank of each active lane among the lanes of its wave with the same bucket g, with one counter atomic per distinct
+// bucket in the wave (sorted input puts long runs of one bucket in a wave). Called by all lanes of the wave.
+__device__ __forceinline__ int wave_rank(int* __restrict__ cnt, int g, bool active) {
+  const int lane = __lane_id();
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long pending = __ballot(active);
+  int rank = 0;
+  while (pending) {
+    const int leader = __ffsll(static_cast<long long>(pending)) - 1;
+    const int lg = __shfl(g, leader);
+    const unsigned long long same = __ballot(active && g == lg);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt + lg, __popcll(same));
+    base = __shfl(base, leader);
+    if (active && g == lg) rank = base + __popcll(same & below);
+    pending &= ~same;
   }
-  const uint64_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
-  const uint32_t xs[2] = {c[0], (c[0] + 1 == static_cast<uint32_t>(nm)) ? 0u : c[0] + 1};
-  const uint32_t ys[2] = {c[1], (c[1] + 1 == static_cast<uint32_t>(nm)) ? 0u : c[1] + 1};
-  const uint32_t zs[2] = {c[2], (c[2] + 1 == static_cast<uint32_t>(nm)) ? 0u : c[2] + 1};
-  LPC_GLOBAL unsigned long long* C = to_global(reinterpret_cast<unsigned long long*>(J.dens));
+  return rank;
+}
+
+__global__ __launch_bounds__(kNT) void k_tile_key(const SortJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                  int njob, int total, int* __restrict__ cnt, int* __restrict__ key,
+                                                  int* __restrict__ rank, int* __restrict__ flags) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST SortJob& J = to_const(jobs)[jb];
+    const int64_t n = J.n;
+    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    const bool active = i < n;
+    int g = 0;
+    if (active) {
+      LPC_GLOBAL const float* pos = to_global(J.pos);
+      const int64_t period = static_cast<int64_t>(J.nm) << kFracBits;
+      uint32_t c[3], f[3];
+      bool ok = true;
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const uint64_t wab = wx[a] * wy[b];
-      const size_t rowbase = (static_cast<size_t>(xs[a]) * nm + ys[b]) * nm;
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const uint64_t w = wab * wz[e];
-        if (w != 0)
-          __hip_atomic_fetch_add(C + rowbase + zs[e], static_cast<unsigned long long>(w), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-      }
+      for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], J.scale, period, &c[d], &f[d]);
+      int b = 2 * J.nt * J.nt * J.nt;
+      if (ok)
+        b = bucket_of(c[0], c[1], c[2], J.nt, J.nm);
+      else
+        atomicOr(flags + kFlagNonfinite, 1);
+      g = J.tbase + b;
+    }
+    const int r = wave_rank(cnt, g, active);
+    if (active) {
+      key[J.pbase + i] = g;
+      rank[J.pbase + i] = r;
     }
   }
 }
 
-__global__ __launch_bounds__(kNT) void k_deposit(const PartJob* __restrict__ jobs, const int* __restrict__ offs,
-                                                 int njob, int total, int* __restrict__ flags) {
+// Exclusive scan of cnt[0..count) into start[0..count] in three launches: block-local scans of kScanBlock elements
+// (writing block totals), a scan of the block totals, and the add of each block's offset.
+constexpr int kScanPer = 8;
+constexpr int kScanBlock = kNT * kScanPer;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+  // sh: kNT ints of LDS; Hillis-Steele over the workgroup
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kNT; off <<= 1) {
+    const int u = (tid >= off) ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += u;
+    __syncthreads();
+  }
+  const int incl = sh[tid];
+  *total = sh[kNT - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kNT) void k_scan_local(const int* __restrict__ cnt, int* __restrict__ start, int count,
+                                                    int* __restrict__ block_sums) {
+  __shared__ int sh[kNT];
+  const int base = blockIdx.x * kScanBlock + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < count) ? cnt[base + k] : 0;
+    sum += v[k];
+  }
+  int total;
+  int run = block_exclusive_scan(sum, sh, &total);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < count) start[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the block totals in place, and start[count] = the grand total.
+__global__ __launch_bounds__(kNT) void k_scan_sums(int* __restrict__ block_sums, int nblocks, int* __restrict__ start,
+                                                   int count) {
+  __shared__ int sh[kNT];
+  int carry = 0;
+  for (int b0 = 0; b0 < nblocks; b0 += kNT) {
+    const int b = b0 + threadIdx.x;
+    const int v = (b < nblocks) ? block_sums[b] : 0;
+    int total;
+    const int ex = block_exclusive_scan(v, sh, &total);
+    if (b < nblocks) block_sums[b] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) start[count] = carry;
+}
+
+__global__ __launch_bounds__(kNT) void k_scan_add(int* __restrict__ start, int count,
+                                                  const int* __restrict__ block_sums) {
+  const int base = blockIdx.x * kScanBlock;
+  const int add = block_sums[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanBlock; k += kNT)
+    if (base + k < count) start[base + k] += add;
+}
+
+__global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                 int njob, int total, const int* __restrict__ key,
+                                                 const int* __restrict__ rank, const int* __restrict__ start) {
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
-    const LPC_CONST PartJob& J = to_const(jobs)[jb];
+    const LPC_CONST SortJob& J = to_const(jobs)[jb];
+    const int64_t n = J.n;
     const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
-    if (i < J.n) deposit_one(J, i, flags);
+    if (i >= n) continue;
+    const int64_t gi = J.pbase + i;
+    const int64_t dst = static_cast<int64_t>(start[key[gi]]) + rank[gi] - J.pbase;
+    LPC_GLOBAL const float* pos = to_global(J.pos);
+    LPC_GLOBAL float* dpos = to_global(J.dpos);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dpos[d * n + dst] = pos[d * n + i];
+    if (J.dvel) {
+      LPC_GLOBAL const float* vel = to_global(J.vel);
+      LPC_GLOBAL float* dvel = to_global(J.dvel);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) dvel[d * n + dst] = vel[d * n + i];
+    }
+    if (J.dpsi1) {
+      LPC_GLOBAL const float* p1 = to_global(J.psi1);
+      LPC_GLOBAL const float* p2 = to_global(J.psi2);
+      LPC_GLOBAL float* d1 = to_global(J.dpsi1);
+      LPC_GLOBAL float* d2 = to_global(J.dpsi2);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        d1[d * n + dst] = p1[d * n + i];
+        d2[d * n + dst] = p2[d * n + i];
+      }
+    }
+    to_global(J.dorig)[dst] = J.orig ? to_global(J.orig)[i] : static_cast<int>(i);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Tiled deposit: one workgroup per mesh tile. It reads the sorted particles of its own tile (both buckets) and the
+// boundary buckets of the (up to 7) lower neighbour tiles, whose particles can reach its cells; accumulates the
+// integer weights of the corners that fall inside its tile with 64-bit LDS atomics; and writes every cell of the
+// tile once with plain stores (so the mesh needs no clearing and sees no global atomics). The up to 8 particle
+// ranges are walked as one index space, so a workgroup needs few rounds of loads.
+constexpr int kTileCells = kTile * kTile * kTile;
+
+__global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                       int njob, int total, const int* __restrict__ start) {
+  __shared__ unsigned long long acc[kTileCells];
+  const int w = blockIdx.x;
+  if (w >= total) return;
+  const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+  const LPC_CONST DepJob& J = to_const(jobs)[jb];
+  const int nt = J.nt, nm = J.nm;
+  const int t = w - offs[jb];
+  if (t >= nt * nt * nt) return;  // padding item
+  const int tid = threadIdx.x;
+  for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
+  const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
+  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  // the particle ranges (local indices): own tile, then the boundary bucket of each distinct lower neighbour
+  int64_t rb[8], rlen[8];
+  int nr = 0;
+  const int lo = (nt > 1) ? -1 : 0;  // an axis with one tile has no distinct lower neighbour
+  for (int dx = lo; dx <= 0; ++dx) {
+    for (int dy = lo; dy <= 0; ++dy) {
+      for (int dz = lo; dz <= 0; ++dz) {
+        const int sx = (tx + dx + nt) % nt, sy = (ty + dy + nt) % nt, sz = (tz + dz + nt) % nt;
+        const int g = J.tbase + 2 * ((sx * nt + sy) * nt + sz);
+        const bool own = (dx == 0 && dy == 0 && dz == 0);
+        const int64_t b = start[own ? g : g + 1] - J.pbase, e = start[g + 2] - J.pbase;
+        rb[nr] = b;
+        rlen[nr] = e - b;
+        ++nr;
+      }
+    }
+  }
+  int64_t tot = 0;
+  for (int r = 0; r < nr; ++r) tot += rlen[r];
+  __syncthreads();
+  const int64_t n = J.n;
+  const int64_t period = static_cast<int64_t>(nm) << kFracBits;
+  LPC_GLOBAL const float* pos = to_global(J.pos);
+  for (int64_t q = tid; q < tot; q += kNT) {
+    int64_t rem = q;
+    int r = 0;
+    while (rem >= rlen[r]) {  // uniform bounds: at most 8 ranges
+      rem -= rlen[r];
+      ++r;
+    }
+    const int64_t i = rb[r] + rem;
+    uint32_t c[3], f[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], J.scale, period, &c[d], &f[d]);
+    if (!ok) continue;  // cannot happen for a bucketed particle; kept as a guard
+    // corner offsets relative to the tile origin (periodic), in [0, kTile) when inside
+    int lx[2], ly[2], lz[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      int cx = static_cast<int>(c[0]) + a, cy = static_cast<int>(c[1]) + a, cz = static_cast<int>(c[2]) + a;
+      if (cx == nm) cx = 0;
+      if (cy == nm) cy = 0;
+      if (cz == nm) cz = 0;
+      lx[a] = cx - x0;
+      ly[a] = cy - y0;
+      lz[a] = cz - z0;
+    }
+    const uint64_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      if (static_cast<unsigned>(lx[a]) >= static_cast<unsigned>(kTile)) continue;
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) {
+        if (static_cast<unsigned>(ly[bb]) >= static_cast<unsigned>(kTile)) continue;
+        const uint64_t wab = wx[a] * wy[bb];
+#pragma unroll
+        for (int e2 = 0; e2 < 2; ++e2) {
+          if (static_cast<unsigned>(lz[e2]) >= static_cast<unsigned>(kTile)) continue;
+          const uint64_t wt = wab * wz[e2];
+          if (wt != 0)
+            __hip_atomic_fetch_add(&acc[(lx[a] * kTile + ly[bb]) * kTile + lz[e2]], static_cast<unsigned long long>(wt),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // write the tile (cells outside the mesh on a narrow last tile are skipped)
+  LPC_GLOBAL unsigned long long* C = to_global(reinterpret_cast<unsigned long long*>(J.dens));
+  const int wx_ = min(kTile, nm - x0), wy_ = min(kTile, nm - y0), wz_ = min(kTile, nm - z0);
+  for (int c = tid; c < kTileCells; c += kNT) {
+    const int i = c / (kTile * kTile), j = (c / kTile) % kTile, k = c % kTile;
+    if (i < wx_ && j < wy_ && k < wz_)
+      C[(static_cast<size_t>(x0 + i) * nm + (y0 + j)) * nm + (z0 + k)] = acc[c];
+  }
+}
+
+// Copy sorted positions and momenta back to the caller's order.
+__global__ __launch_bounds__(kNT) void k_unsort(const UnsortJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                int njob, int total) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+    const LPC_CONST UnsortJob& J = to_const(jobs)[jb];
+    const int64_t n = J.n;
+    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    if (i >= n) continue;
+    const int64_t o = to_global(J.orig)[i];
+    LPC_GLOBAL const float* sp = to_global(J.spos);
+    LPC_GLOBAL const float* sv = to_global(J.svel);
+    LPC_GLOBAL float* p = to_global(J.pos);
+    LPC_GLOBAL float* v = to_global(J.vel);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d * n + o] = sp[d * n + i];
+      v[d * n + o] = sv[d * n + i];
+    }
   }
 }
 
@@ -209,9 +439,10 @@ __global__ __launch_bounds__(kNT) void k_gather(const PartJob* __restrict__ jobs
       atomicOr(flags + kFlagNonfinite, 1);
       g[0] = g[1] = g[2] = 0.f;
     }
-    grad[i] = g[0];
-    grad[n + i] = g[1];
-    grad[2 * n + i] = g[2];
+    const int64_t o = J.orig ? to_global(J.orig)[i] : i;  // output in the caller's order
+    grad[o] = g[0];
+    grad[n + o] = g[1];
+    grad[2 * n + o] = g[2];
   }
 }
 
@@ -234,9 +465,6 @@ unsigned grid_of(const WorkTable& wt, int cap) {
 
 }  // namespace
 
-// items of a particle stage per job: ceil(n / kNT) (ceil(3n / kNT) for the frame velocity)
-int fill_items(int64_t count) { return static_cast<int>((count + kFillChunk - 1) / kFillChunk); }
-
 hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s) {
   if (count == 0) return hipSuccess;
   size_t blocks = (count + kNT - 1) / kNT;
@@ -245,15 +473,40 @@ hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_fill(const FillJob* jobs, WorkTable wt, hipStream_t s) {
+hipError_t launch_tile_key(const SortJob* jobs, WorkTable wt, int* cnt, int* key, int* rank, int* flags,
+                           hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_fill<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total);
+  k_tile_key<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, cnt, key, rank, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_deposit(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s) {
+int scan_blocks(int count) { return (count + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_scan(const int* cnt, int* start, int count, int* block_sums, hipStream_t s) {
+  const int nb = scan_blocks(count);
+  if (nb == 0) return hipErrorInvalidValue;
+  k_scan_local<<<nb, kNT, 0, s>>>(cnt, start, count, block_sums);
+  k_scan_sums<<<1, kNT, 0, s>>>(block_sums, nb, start, count);
+  k_scan_add<<<nb, kNT, 0, s>>>(start, count, block_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const SortJob* jobs, WorkTable wt, const int* key, const int* rank, const int* start,
+                          hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_deposit<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, flags);
+  k_scatter<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, key, rank, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* start, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  k_deposit_tiles<<<static_cast<unsigned>(wt.total), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_unsort(const UnsortJob* jobs, WorkTable wt, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  k_unsort<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total);
   return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ def _load():
     P = ctypes.POINTER
     vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     sig = {
-        "lpc_workspace_bytes": (sz, [P(Geometry), i32]),
+        "lpc_workspace_bytes": (sz, [P(Geometry), i32, i64]),
         "lpc_init_ic": (i32, [P(Geometry), P(Cosmology), ctypes.c_uint64, dbl, P(Particles), vp, sz, vp]),
         "lpc_pm_force": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp, sz, vp]),
         "lpc_cola_step": (i32, [P(Geometry), P(Cosmology), P(Stepping), P(dbl), i32, P(Particles), vp, sz, vp]),
@@ -123,14 +123,16 @@ def stepping(cola=1, modified=1, n_lpt=-2.5, deconv_power=1):
     return Stepping(int(cola), int(modified), float(n_lpt), int(deconv_power), 0)
 
 
-def lpc_workspace_bytes(geom, op):
-    return int(LIB.lpc_workspace_bytes(ctypes.byref(geom), int(op)))
+def lpc_workspace_bytes(geom, op, n_particles=0):
+    return int(LIB.lpc_workspace_bytes(ctypes.byref(geom), int(op), int(n_particles)))
 
 
-def workspace(geom, op, device="cuda"):
-    """A caller-owned workspace tensor (uint8) for operation `op`."""
+def workspace(geom, op, device="cuda", n_particles=None):
+    """A caller-owned workspace tensor (uint8) for operation `op`; n_particles defaults to n_side^3."""
     import torch
-    nbytes = lpc_workspace_bytes(geom, op)
+    if n_particles is None:
+        n_particles = int(geom.n_side) ** 3
+    nbytes = lpc_workspace_bytes(geom, op, n_particles)
     if nbytes == 0:
         raise LpcError(-2, f"unsupported geometry {geom.n_side}/{geom.n_mesh} for op {op}")
     return torch.empty(nbytes, dtype=torch.uint8, device=device)

@@ -67,21 +67,29 @@ def test_linear_power_matches_oracle():
 def test_workspace_sizes_and_rejections():
     from paper_1506_03737_amd import lpc
     g = lpc.geometry(32, 64, 256.0)
-    assert lpc.lpc_workspace_bytes(g, lpc.LPC_OP_COLA_STEP) > 64**3 * 12
-    assert lpc.lpc_workspace_bytes(g, 99) == 0
-    assert lpc.lpc_workspace_bytes(lpc.geometry(32, 14, 256.0), lpc.LPC_OP_PM_FORCE) == 0   # 7 is not 2/3/5-smooth
-    assert lpc.lpc_workspace_bytes(lpc.geometry(32, 2048, 256.0), lpc.LPC_OP_PM_FORCE) == 0
+    n = 32**3
+    cola = lpc.lpc_workspace_bytes(g, lpc.LPC_OP_COLA_STEP, n)
+    force = lpc.lpc_workspace_bytes(g, lpc.LPC_OP_PM_FORCE, n)
+    assert force > 64**3 * 12 + 3 * 64 * 64 * 40 * 8 + 16 * n      # meshes + one sorted copy (pos, index)
+    assert cola - force == 2 * 52 * n - 16 * n                       # two full sorted copies instead of one
+    assert lpc.lpc_workspace_bytes(g, lpc.LPC_OP_COLA_STEP, 0) == 0  # a particle op needs a particle count
+    assert lpc.lpc_workspace_bytes(g, lpc.LPC_OP_FFT, 0) > 0
+    assert lpc.lpc_workspace_bytes(g, 99, n) == 0
+    assert lpc.lpc_workspace_bytes(lpc.geometry(32, 14, 256.0), lpc.LPC_OP_PM_FORCE, n) == 0   # 7 is not 2/3/5-smooth
+    assert lpc.lpc_workspace_bytes(lpc.geometry(32, 2048, 256.0), lpc.LPC_OP_PM_FORCE, n) == 0
     assert lpc.lpc_fft_pitch(768) == 392 and lpc.lpc_fft_pitch(64) == 40
 
 
 def test_batched_workspace_layout():
-    """Flags + job region, then per box 12 Nm^3 bytes (int64 counts / AoS float3 force) and three half spectra,
-    each region 256-byte aligned; an unsupported mesh anywhere in the batch gives 0."""
+    """Flags + job region, then per box 12 Nm^3 bytes (int64 counts / AoS float3 force) and three half spectra, then
+    the sort space (two tile-sorted copies of every box's pos/vel/psi1/psi2/index, keys, ranks, tile counts and
+    starts), each array 256-byte aligned; an unsupported mesh anywhere in the batch gives 0."""
     from paper_1506_03737_amd import lpc
 
-    def entry(nm, box=100.0):
+    def entry(nm, n, box=100.0):
         e = lpc.BatchEntry()
         e.geom = lpc.geometry(0, nm, box)
+        e.particles.n = n
         return e
 
     def r256(x):
@@ -90,12 +98,20 @@ def test_batched_workspace_layout():
     def per_box(nm):
         return r256(12 * nm**3) + 3 * r256(nm * nm * lpc.lpc_fft_pitch(nm) * 8)
 
-    one = (lpc.BatchEntry * 1)(entry(64))
-    base = lpc.LIB.lpc_workspace_bytes_batched(one, 1) - per_box(64)
+    def sort_space(nms, ns):
+        copies = 2 * sum(4 * r256(12 * n) + r256(4 * n) for n in ns)
+        G = sum(2 * (-(-nm // 16)) ** 3 + 1 for nm in nms)
+        return copies + 2 * r256(4 * sum(ns)) + r256(4 * G) + r256(4 * (G + 1)) + r256(4 * -(-G // 2048))
+
+    one = (lpc.BatchEntry * 1)(entry(64, 1000))
+    base = lpc.LIB.lpc_workspace_bytes_batched(one, 1) - per_box(64) - sort_space([64], [1000])
     assert base == 256 + (1 << 20)
-    arr = (lpc.BatchEntry * 3)(entry(192), entry(40), entry(320))
-    assert lpc.LIB.lpc_workspace_bytes_batched(arr, 3) == base + per_box(192) + per_box(40) + per_box(320)
-    arr[1] = entry(14)
+    arr = (lpc.BatchEntry * 3)(entry(192, 96**3), entry(40, 777), entry(320, 160**3))
+    want = base + per_box(192) + per_box(40) + per_box(320) + sort_space([192, 40, 320], [96**3, 777, 160**3])
+    assert lpc.LIB.lpc_workspace_bytes_batched(arr, 3) == want
+    arr[1] = entry(14, 777)
+    assert lpc.LIB.lpc_workspace_bytes_batched(arr, 3) == 0
+    arr[1] = entry(40, 0)
     assert lpc.LIB.lpc_workspace_bytes_batched(arr, 3) == 0
     assert lpc.LIB.lpc_workspace_bytes_batched(arr, 0) == 0
 

@@ -40,7 +40,7 @@ def test_power_spectrum_matches_oracle(nm, n_bins):
     box = 256.0
     pos = synth.clustered_positions(nm, 60000, box)
     geom = lpc.geometry(0, nm, box)
-    ws = lpc.workspace(geom, lpc.LPC_OP_POWER_SPECTRUM)
+    ws = lpc.workspace(geom, lpc.LPC_OP_POWER_SPECTRUM, n_particles=pos.shape[1])
     k_max = 0.9 * np.pi * nm / box
     k, pk, cnt = lpc.lpc_power_spectrum(geom, to_dev(pos), k_max, n_bins, ws)
     kr, pr, cr = ospec.power_spectrum(pos, nm, box, k_max, n_bins)

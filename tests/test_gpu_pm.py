@@ -24,7 +24,7 @@ def exact_sum(C):
 def run_force(lpc, pos32, nm, box, p=1, want_density=True):
     n = pos32.shape[1]
     geom = lpc.geometry(0, nm, box)
-    ws = lpc.workspace(geom, lpc.LPC_OP_PM_FORCE)
+    ws = lpc.workspace(geom, lpc.LPC_OP_PM_FORCE, n_particles=n)
     grad = torch.empty((3, n), dtype=torch.float32, device="cuda")
     dens = torch.empty((nm, nm, nm), dtype=torch.int64, device="cuda") if want_density else None
     lpc.lpc_pm_force(geom, lpc.stepping(deconv_power=p), to_dev(pos32), grad, ws, density_out=dens)
