@@ -17,6 +17,8 @@ Modules:
   cola       -- the kick-drift-kick COLA integrator about the stored 2LPT displacements (Sec. 2.2, 2.3)
   spectrum   -- binned power spectrum of a periodic box (Sec. 7.1)
   dft        -- brute-force discrete Fourier transform, used only to pin the FFT-based steps
+  net        -- the learned displacement correction: a 3-level 3-D U-Net, its backpropagation and Adam
+  bispectrum -- reduced bispectrum Q(k1, k2, k3) with the FFT shell estimator and a brute-force triangle sum (Sec. 7)
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test against a closed form, an invariant or brute
 force, except the BBKS transfer-function constants (parity unpinned: retyped from Bardeen et al. 1986, no printed
