@@ -189,6 +189,57 @@ lpc_status lpc_fft_c2r(int32_t n, float* in_complex, float* out, void* ws, size_
 /* Row pitch, in complex values, of the half-spectrum layout used by lpc_fft_r2c / lpc_fft_c2r. */
 int32_t lpc_fft_pitch(int32_t n);
 
+/* ---------------------------------------------------------------------------------------------------------------
+ * Learned displacement correction (not in the paper: a learned stand-in for the small-scale accuracy that a finer PM
+ * mesh buys, Sec. 2.4). A coarse run (Nm = N) is corrected toward a fine run (Nm = 3N) by a 3-D convolutional
+ * network on the N^3 particle lattice, trained only on pairs of runs of this library.
+ *
+ * Grid: voxel v = (i N + j) N + l is the lattice site of particle id v. Feature grid: FP32 [N^3][3], the particle's
+ * minimal-image displacement from its lattice point q = (i + 1/2, j + 1/2, l + 1/2) L / N, in units of L / N. Output:
+ * FP32 [N^3][3], the residual displacement (same units) added to the coarse positions.
+ * Network (3^3 convolutions with periodic wrap; "down" = 2^3 stride-2 convolution, "up" = 2^3 stride-2 transposed
+ * convolution; every layer but the last followed by leaky ReLU, slope 0.1):
+ *   a0 = conv(in: 3 -> 16); s0 = conv(a0: 16 -> 16); a1 = down(s0: 16 -> 32) at N/2; s1 = conv(a1: 32 -> 32);
+ *   a2 = down(s1: 32 -> 64) at N/4; b2 = conv(a2: 64 -> 64); u1 = up(b2: 64 -> 32) at N/2;
+ *   c1 = conv([u1, s1]: 64 -> 32); u0 = up(c1: 32 -> 16) at N; c0 = conv([u0, s0]: 32 -> 16); out = conv(c0: 16 -> 3).
+ * Parameters: one FP32 vector (lpc_net_param_count() values); per layer in the order above, W[Cout][taps][Cin] with
+ * taps x-major (t = (tx K + ty) K + tz, K = 3 or 2), then b[Cout]. Loss: mean over voxels and channels of
+ * (out - target)^2. Precision: activations and their gradients BF16, 3^3 convolutions and their data gradients on
+ * BF16 MFMA with FP32 accumulation, weight gradients FP32 sums of BF16 products, master weights and Adam state FP32.
+ * n_side must be a multiple of 4 in [8, 512]. Device buffers are caller-owned; ws holds lpc_net_workspace_bytes()
+ * bytes (256-byte aligned) and is scratch for every call below. */
+int64_t lpc_net_param_count(void);
+
+/* Host-side initialisation of params[lpc_net_param_count()] (host FP32): W uniform in +-sqrt(6 / (taps Cin))
+ * (0.1 x that for the last layer), b = 0, from SplitMix64 seeded with `seed`. */
+lpc_status lpc_net_init(float* params, uint64_t seed);
+
+size_t lpc_net_workspace_bytes(int32_t n_side);
+
+/* Feature (ref_pos NULL) or target grid of N^3 particles pos[3][n] with lattice ids id[n]: out[id][d] = minimal
+ * image (pos - base) / (L / N), base = the lattice point of id, or ref_pos[3][n] (the same particles in another run,
+ * e.g. target = fine - coarse). An id outside [0, N^3) gives LPC_ERR_INVALID_ARG. */
+lpc_status lpc_net_features(const lpc_geometry* geom, const float* pos, const int32_t* id, int64_t n,
+                            const float* ref_pos, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* out[N^3][3] = network(feat[N^3][3]) with device params. */
+lpc_status lpc_net_forward(int32_t n_side, const float* params, const float* feat, float* out, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* Loss of the network on one sample and its gradient grad[lpc_net_param_count()] (device, overwritten) by
+ * backpropagation; *loss (host) receives the loss. */
+lpc_status lpc_net_loss_grad(int32_t n_side, const float* params, const float* feat, const float* target,
+                             float* grad, double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step counts from 1) on the
+ * device vectors params, m, v with gradient grad. */
+lpc_status lpc_net_adam(float* params, float* m, float* v, const float* grad, int64_t step, float lr, void* stream);
+
+/* Corrects a coarse run in place: pos += network(features(pos, id)) L / N, wrapped into [0, L). inout->n must be
+ * n_side^3 (one particle per lattice site); only pos and id are used. */
+lpc_status lpc_net_apply(const lpc_geometry* geom, const float* params, const lpc_particles* inout, void* ws,
+                         size_t ws_bytes, void* stream);
+
 /* Per-stage profiling (measurement plumbing, not part of the method). When enabled, every kernel
  * launch of the entry points above is bracketed by HIP events on the call's stream; the durations are read after the
  * call's final synchronisation and accumulated per stage name ("deposit", "fft y inv", ...). Process-wide state,

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "liblpc.so")
 
-HIP_SOURCES = ["fft.hip", "pm.hip", "ic.hip", "pk.hip", "abi.hip"]
+HIP_SOURCES = ["fft.hip", "pm.hip", "ic.hip", "pk.hip", "abi.hip", "net.hip", "net_abi.hip"]
 CPP_SOURCES = ["cosmo.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -12,16 +12,16 @@
 #include <vector>
 
 #include "../../include/lpc.h"
+#include "abi_common.h"
 #include "lpc_host.h"
 #include "lpc_kernels.h"
 
 namespace {
-
-using lpc::kern::Plan1D;
-namespace kern = lpc::kern;
-namespace host = lpc::host;
-
 thread_local std::string g_error;
+}  // namespace
+
+namespace lpc {
+namespace abi {
 
 lpc_status fail(lpc_status s, const char* fmt, ...) {
   char buf[512];
@@ -33,14 +33,20 @@ lpc_status fail(lpc_status s, const char* fmt, ...) {
   return s;
 }
 
-struct HipError {
-  hipError_t e;
-  const char* what;
-};
+const char* last_error() { return g_error.c_str(); }
 
-void check(hipError_t e, const char* what) {
-  if (e != hipSuccess) throw HipError{e, what};
-}
+}  // namespace abi
+}  // namespace lpc
+
+namespace {
+
+using lpc::abi::HipError;
+using lpc::abi::check;
+using lpc::abi::fail;
+using lpc::abi::guarded;
+using lpc::kern::Plan1D;
+namespace kern = lpc::kern;
+namespace host = lpc::host;
 
 // Optional per-stage timing: when enabled, every kernel launch of an entry point is bracketed by HIP events on the
 // call's stream; the durations are read after the call's final synchronisation and accumulated per stage name.
@@ -265,18 +271,6 @@ lpc_status finish(int* flags, hipStream_t s) {
   return LPC_OK;
 }
 
-template <class F>
-lpc_status guarded(F body) {
-  try {
-    return body();
-  } catch (const HipError& e) {
-    return fail(LPC_ERR_HIP, "%s failed: %s", e.what, hipGetErrorString(e.e));
-  } catch (const std::exception& e) {
-    return fail(LPC_ERR_HIP, "internal error: %s", e.what());
-  } catch (...) {
-    return fail(LPC_ERR_HIP, "unknown internal error");
-  }
-}
 
 char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
@@ -781,7 +775,7 @@ const char* lpc_status_string(lpc_status s) {
   return "unknown lpc_status";
 }
 
-const char* lpc_last_error(void) { return g_error.c_str(); }
+const char* lpc_last_error(void) { return lpc::abi::last_error(); }
 
 lpc_status lpc_cola_coefficients(const lpc_cosmology* cosmo, const lpc_stepping* step, const double* a_list,
                                  int32_t n_a, double* out) {

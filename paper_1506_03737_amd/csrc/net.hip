@@ -1,0 +1,525 @@
+// Kernels of the learned displacement correction (declared in net_kernels.h). The 3^3 convolutions, forward and
+// data gradient, run on BF16 MFMA with FP32 accumulation; the 2^3 down/up layers, the weight gradients (FP32
+// partial sums per voxel chunk, reduced in a fixed order) and the element-wise steps run on the vector ALUs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "net_kernels.h"
+
+namespace lpc {
+namespace net {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kNT = 256;
+constexpr float kSlope = 0.1f;
+
+__device__ __forceinline__ int wrapi(int a, int D) { return a < 0 ? a + D : (a >= D ? a - D : a); }
+__device__ __forceinline__ float leaky(float v) { return v > 0.f ? v : kSlope * v; }
+__device__ __forceinline__ float f(bf16 v) { return static_cast<float>(v); }
+
+unsigned blocks_for(int64_t count, int per = kNT) { return static_cast<unsigned>((count + per - 1) / per); }
+
+// ---------------------------------------------------------------------------------------------------------------
+// 3^3 convolution, implicit GEMM on v_mfma_f32_16x16x32_bf16. A wave owns 64 consecutive output voxels (4 row
+// tiles of 16) and all 16 NB output channels; a workgroup is 4 waves. Operand layout of the instruction: lane l
+// supplies row (l % 16) of A and column (l % 16) of B with k = 8 (l / 16) + [0, 8), and receives column (l % 16),
+// rows 4 (l / 16) + [0, 4) of the 16 x 16 result.
+template <int CIN, int NB>
+__global__ __launch_bounds__(kNT) void k_conv3(View in, const bf16* __restrict__ w, int kpad,
+                                               const float* __restrict__ bias, int act, View out,
+                                               float* __restrict__ outf, int cout, int D) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int V = D * D * D;
+  const int vw = (blockIdx.x * 4 + wave) * 64;
+  if (vw >= V) return;
+  const int r = lane & 15, g = lane >> 4;
+  int vx[4], vy[4], vz[4];
+  bool ok[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const int v = vw + mt * 16 + r;
+    ok[mt] = v < V;
+    const int vv = ok[mt] ? v : 0;
+    vx[mt] = vv / (D * D);
+    vy[mt] = (vv / D) % D;
+    vz[mt] = vv % D;
+  }
+  f32x4 acc[4][NB];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mt][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16* inb = in.p + in.off;
+  const int nk = kpad / 32;
+  for (int s = 0; s < nk; ++s) {
+    const int k0 = s * 32 + g * 8;
+    const int tap = k0 / CIN, ci = k0 - tap * CIN;
+    const bool tap_ok = tap < 27;
+    const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
+    bf16x8 A[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      bf16x8 a;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j] = static_cast<bf16>(0.f);
+      if (tap_ok && ok[mt]) {
+        const int x = wrapi(vx[mt] + dx, D), y = wrapi(vy[mt] + dy, D), z = wrapi(vz[mt] + dz, D);
+        a = *reinterpret_cast<const bf16x8*>(inb + static_cast<size_t>((x * D + y) * D + z) * in.ld + ci);
+      }
+      A[mt] = a;
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const bf16x8 B = *reinterpret_cast<const bf16x8*>(w + static_cast<size_t>(nb * 16 + r) * kpad + k0);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B, acc[mt][nb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int co = nb * 16 + r;
+    if (co >= cout) continue;
+    const float b = bias ? bias[co] : 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int v = vw + mt * 16 + g * 4 + j;
+        if (v >= V) continue;
+        const float val = acc[mt][nb][j] + b;
+        if (outf)
+          outf[static_cast<size_t>(v) * cout + co] = val;
+        else
+          out.p[static_cast<size_t>(v) * out.ld + out.off + co] = static_cast<bf16>(act ? leaky(val) : val);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// 2^3 down / up layers and their data gradients (one thread per output element).
+__global__ __launch_bounds__(kNT) void k_down2(View x, int cin, const float* __restrict__ W,
+                                               const float* __restrict__ b, int cout, View out, int D) {
+  const int Dc = D / 2;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (idx >= static_cast<int64_t>(Dc) * Dc * Dc * cout) return;
+  const int o = static_cast<int>(idx % cout);
+  const int y = static_cast<int>(idx / cout);
+  const int yx = y / (Dc * Dc), yy = (y / Dc) % Dc, yz = y % Dc;
+  float acc = b[o];
+  for (int t = 0; t < 8; ++t) {
+    const int xv = ((2 * yx + (t >> 2)) * D + 2 * yy + ((t >> 1) & 1)) * D + 2 * yz + (t & 1);
+    const bf16* xp = x.p + static_cast<size_t>(xv) * x.ld + x.off;
+    const float* wp = W + (o * 8 + t) * cin;
+    for (int i = 0; i < cin; ++i) acc += wp[i] * f(xp[i]);
+  }
+  out.p[static_cast<size_t>(y) * out.ld + out.off + o] = static_cast<bf16>(leaky(acc));
+}
+
+__global__ __launch_bounds__(kNT) void k_up2(View x, int cin, const float* __restrict__ W,
+                                             const float* __restrict__ b, int cout, View out, int D) {
+  const int Df = 2 * D;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (idx >= static_cast<int64_t>(Df) * Df * Df * cout) return;
+  const int o = static_cast<int>(idx % cout);
+  const int q = static_cast<int>(idx / cout);
+  const int qx = q / (Df * Df), qy = (q / Df) % Df, qz = q % Df;
+  const int t = ((qx & 1) * 2 + (qy & 1)) * 2 + (qz & 1);
+  const int y = ((qx >> 1) * D + (qy >> 1)) * D + (qz >> 1);
+  const bf16* xp = x.p + static_cast<size_t>(y) * x.ld + x.off;
+  const float* wp = W + (o * 8 + t) * cin;
+  float acc = b[o];
+  for (int i = 0; i < cin; ++i) acc += wp[i] * f(xp[i]);
+  out.p[static_cast<size_t>(q) * out.ld + out.off + o] = static_cast<bf16>(leaky(acc));
+}
+
+// dx[2y + t][i] (+)= sum_o W[o][t][i] dz[y][o]   (x on D^3)
+__global__ __launch_bounds__(kNT) void k_down2_dgrad(View dz, int cout, const float* __restrict__ W, int cin, View dx,
+                                                     int D, int accumulate) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (idx >= static_cast<int64_t>(D) * D * D * cin) return;
+  const int i = static_cast<int>(idx % cin);
+  const int xv = static_cast<int>(idx / cin);
+  const int xx = xv / (D * D), xy = (xv / D) % D, xz = xv % D;
+  const int Dc = D / 2;
+  const int t = ((xx & 1) * 2 + (xy & 1)) * 2 + (xz & 1);
+  const int y = ((xx >> 1) * Dc + (xy >> 1)) * Dc + (xz >> 1);
+  const bf16* zp = dz.p + static_cast<size_t>(y) * dz.ld + dz.off;
+  float acc = 0.f;
+  for (int o = 0; o < cout; ++o) acc += W[(o * 8 + t) * cin + i] * f(zp[o]);
+  bf16* dst = dx.p + static_cast<size_t>(xv) * dx.ld + dx.off + i;
+  if (accumulate) acc += f(*dst);
+  *dst = static_cast<bf16>(acc);
+}
+
+// dx[y][i] = sum_{t, o} W[o][t][i] dz[2y + t][o]   (x on D^3, dz on (2D)^3)
+__global__ __launch_bounds__(kNT) void k_up2_dgrad(View dz, int cout, const float* __restrict__ W, int cin, View dx,
+                                                   int D) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (idx >= static_cast<int64_t>(D) * D * D * cin) return;
+  const int i = static_cast<int>(idx % cin);
+  const int y = static_cast<int>(idx / cin);
+  const int yx = y / (D * D), yy = (y / D) % D, yz = y % D;
+  const int Df = 2 * D;
+  float acc = 0.f;
+  for (int t = 0; t < 8; ++t) {
+    const int q = ((2 * yx + (t >> 2)) * Df + 2 * yy + ((t >> 1) & 1)) * Df + 2 * yz + (t & 1);
+    const bf16* zp = dz.p + static_cast<size_t>(q) * dz.ld + dz.off;
+    for (int o = 0; o < cout; ++o) acc += W[(o * 8 + t) * cin + i] * f(zp[o]);
+  }
+  dx.p[static_cast<size_t>(y) * dx.ld + dx.off + i] = static_cast<bf16>(acc);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Weight gradients. Workgroup (chunk, tap) sums dz[zv(b, tap)][o] x[xv(b, tap)][i] over the base voxels b of its
+// chunk, for every (o, i); tap 0 also sums dz[..][o] for the bias. Base voxels, tiles of kTV, are staged in LDS as
+// FP32; thread groups take interleaved voxels of a tile and are reduced in LDS at the end.
+constexpr int kTV = 64;
+constexpr int kMaxC = 64;
+
+__device__ __forceinline__ void wgrad_voxels(int kind, int b, int tap, int D, int* xv, int* zv) {
+  if (kind == 0) {  // conv3: base = output voxel p on D^3; x at p + tap - 1
+    const int px = b / (D * D), py = (b / D) % D, pz = b % D;
+    const int x = wrapi(px + tap / 9 - 1, D), y = wrapi(py + (tap / 3) % 3 - 1, D), z = wrapi(pz + tap % 3 - 1, D);
+    *xv = (x * D + y) * D + z;
+    *zv = b;
+  } else if (kind == 1) {  // down2: base = output voxel y on (D/2)^3; x at 2y + t on D^3
+    const int Dc = D / 2;
+    const int yx = b / (Dc * Dc), yy = (b / Dc) % Dc, yz = b % Dc;
+    *xv = ((2 * yx + (tap >> 2)) * D + 2 * yy + ((tap >> 1) & 1)) * D + 2 * yz + (tap & 1);
+    *zv = b;
+  } else {  // up2: base = input voxel y on D^3; dz at 2y + t on (2D)^3
+    const int Df = 2 * D;
+    const int yx = b / (D * D), yy = (b / D) % D, yz = b % D;
+    *xv = b;
+    *zv = ((2 * yx + (tap >> 2)) * Df + 2 * yy + ((tap >> 1) & 1)) * Df + 2 * yz + (tap & 1);
+  }
+}
+
+template <int CI>
+__global__ __launch_bounds__(kNT) void k_wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int D,
+                                               int ntap, int nbase, float* __restrict__ partial) {
+  __shared__ float sdz[kTV * kMaxC];
+  __shared__ float sx[kTV * kMaxC];
+  const int chunk = blockIdx.x, tap = blockIdx.y, nchunk = gridDim.x;
+  const int tid = threadIdx.x;
+  const int ncb = cin / CI;
+  const int npb = cout * ncb;           // (o, ci-block) pairs
+  const int G = kNT / npb;              // thread groups over voxels
+  const int pb = tid % npb, grp = tid / npb;
+  const bool active = grp < G;
+  const int o = pb / ncb, cb = pb % ncb;
+  float acc[CI];
+#pragma unroll
+  for (int c = 0; c < CI; ++c) acc[c] = 0.f;
+  float accb = 0.f;
+  const int64_t per = (static_cast<int64_t>(nbase) + nchunk - 1) / nchunk;
+  const int b0 = static_cast<int>(per * chunk);
+  const int b1 = static_cast<int>(std::min<int64_t>(nbase, per * (chunk + 1)));
+  for (int t0 = b0; t0 < b1; t0 += kTV) {
+    const int nv = min(kTV, b1 - t0);
+    __syncthreads();
+    for (int e = tid; e < nv * kMaxC; e += kNT) {
+      const int v = e / kMaxC, c = e % kMaxC;
+      int xv, zv;
+      wgrad_voxels(kind, t0 + v, tap, D, &xv, &zv);
+      if (c < cout) sdz[v * kMaxC + c] = f(dz.p[static_cast<size_t>(zv) * dz.ld + dz.off + c]);
+      if (c < cin) sx[v * kMaxC + c] = f(x.p[static_cast<size_t>(xv) * x.ld + x.off + c]);
+    }
+    __syncthreads();
+    if (active) {
+      for (int v = grp; v < nv; v += G) {
+        const float z = sdz[v * kMaxC + o];
+        const float* xp = sx + v * kMaxC + cb * CI;
+#pragma unroll
+        for (int c = 0; c < CI; ++c) acc[c] += z * xp[c];
+        accb += z;
+      }
+    }
+  }
+  // reduce the thread groups one after another into the (no longer needed) staging buffers
+  __syncthreads();
+  float* red = sx;
+  const int slice = npb * CI;
+  for (int gg = 0; gg < G; ++gg) {
+    if (active && grp == gg) {
+#pragma unroll
+      for (int c = 0; c < CI; ++c) red[pb * CI + c] = (gg == 0 ? 0.f : red[pb * CI + c]) + acc[c];
+      sdz[pb] = (gg == 0 ? 0.f : sdz[pb]) + accb;
+    }
+    __syncthreads();
+  }
+  // canonical layout W[o][t][i] over the real input channels, then the bias (each (o, cb) pair summed dz[o]; take
+  // the cb == 0 one). For up2 every tap sees a different set of dz voxels, so each tap has its own bias slot.
+  const int nW = cout * ntap * cin_real;
+  const int nslot = (kind == 2) ? ntap : 1;
+  float* dst = partial + static_cast<size_t>(chunk) * (nW + nslot * cout);
+  for (int e = tid; e < slice; e += kNT) {
+    const int p = e / CI, c = e % CI;
+    const int oo = p / ncb, ci = (p % ncb) * CI + c;
+    if (ci < cin_real) dst[(oo * ntap + tap) * cin_real + ci] = red[e];
+  }
+  if (kind == 2 || tap == 0)
+    for (int e = tid; e < cout; e += kNT) dst[nW + (kind == 2 ? tap : 0) * cout + e] = sdz[e * ncb];
+}
+
+// grad[j] = sum over chunks (and, for the bias, over its nslot slots) of the partial sums, in a fixed order.
+__global__ __launch_bounds__(kNT) void k_reduce(const float* __restrict__ partial, int nchunk, int nW, int cout,
+                                                int nslot, float* __restrict__ grad) {
+  const int j = blockIdx.x * kNT + threadIdx.x;
+  if (j >= nW + cout) return;
+  const size_t stride = static_cast<size_t>(nW) + static_cast<size_t>(nslot) * cout;
+  float s = 0.f;
+  if (j < nW) {
+    for (int c = 0; c < nchunk; ++c) s += partial[c * stride + j];
+  } else {
+    for (int c = 0; c < nchunk; ++c)
+      for (int k = 0; k < nslot; ++k) s += partial[c * stride + nW + k * cout + (j - nW)];
+  }
+  grad[j] = s;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kNT) void k_leaky_dgrad(View a, View da, int c, int V) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (idx >= static_cast<int64_t>(V) * c) return;
+  const int v = static_cast<int>(idx / c), ch = static_cast<int>(idx % c);
+  bf16* d = da.p + static_cast<size_t>(v) * da.ld + da.off + ch;
+  if (!(f(a.p[static_cast<size_t>(v) * a.ld + a.off + ch]) > 0.f)) *d = static_cast<bf16>(kSlope * f(*d));
+}
+
+__global__ __launch_bounds__(kNT) void k_convert_conv3(const float* __restrict__ W, int cout, int cin,
+                                                       bf16* __restrict__ wf, int cinp, int nbo, int kpad,
+                                                       bf16* __restrict__ wb, int coutp, int nbi, int kpadb) {
+  const int64_t nf = static_cast<int64_t>(16 * nbo) * kpad, nbk = static_cast<int64_t>(16 * nbi) * kpadb;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (idx < nf) {
+    const int row = static_cast<int>(idx / kpad), k = static_cast<int>(idx % kpad);
+    const int t = k / cinp, ci = k % cinp;
+    float v = 0.f;
+    if (row < cout && t < 27 && ci < cin) v = W[(row * 27 + t) * cin + ci];
+    wf[idx] = static_cast<bf16>(v);
+  } else if (idx < nf + nbk) {
+    const int64_t j = idx - nf;
+    const int row = static_cast<int>(j / kpadb), k = static_cast<int>(j % kpadb);
+    const int t = k / coutp, o = k % coutp;
+    float v = 0.f;
+    if (row < cin && t < 27 && o < cout) v = W[(o * 27 + (26 - t)) * cin + row];
+    wb[j] = static_cast<bf16>(v);
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_pack_input(const float* __restrict__ feat, bf16* __restrict__ x, int V) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (idx >= static_cast<int64_t>(V) * 8) return;
+  const int64_t v = idx / 8;
+  const int c = static_cast<int>(idx % 8);
+  x[idx] = static_cast<bf16>(c < 3 ? feat[v * 3 + c] : 0.f);
+}
+
+__global__ __launch_bounds__(kNT) void k_loss_grad(const float* __restrict__ out, const float* __restrict__ target,
+                                                   bf16* __restrict__ dout, double* __restrict__ part, int V) {
+  __shared__ double sh[kNT];
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  double sq = 0.0;
+  if (idx < static_cast<int64_t>(V) * 8) {
+    const int64_t v = idx / 8;
+    const int c = static_cast<int>(idx % 8);
+    float g = 0.f;
+    if (c < 3) {
+      const float e = out[v * 3 + c] - target[v * 3 + c];
+      sq = static_cast<double>(e) * e;
+      g = 2.0f * e / (3.0f * static_cast<float>(V));
+    }
+    dout[idx] = static_cast<bf16>(g);
+  }
+  sh[threadIdx.x] = sq;
+  __syncthreads();
+  for (int off = kNT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// omb1 = 1 - beta1 and omb2 = 1 - beta2 come rounded from FP64 (1 - 0.999f in FP32 would be 1.3e-5 off).
+__global__ __launch_bounds__(kNT) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, int64_t count, float lr, float b1,
+                                              float omb1, float b2, float omb2, float eps, float c1, float c2) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ __launch_bounds__(kNT) void k_features(const float* __restrict__ pos, const int32_t* __restrict__ id,
+                                                  int64_t n, const float* __restrict__ ref, int N, double box,
+                                                  float* __restrict__ out, int* __restrict__ flags) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (p >= n) return;
+  const int64_t q = id[p];
+  const int64_t V = static_cast<int64_t>(N) * N * N;
+  if (q < 0 || q >= V) {
+    atomicOr(flags, 1);
+    return;
+  }
+  const double dp = box / N;
+  const int64_t ijk[3] = {q / (static_cast<int64_t>(N) * N), (q / N) % N, q % N};
+  for (int d = 0; d < 3; ++d) {
+    const double base = ref ? static_cast<double>(ref[d * n + p]) : (static_cast<double>(ijk[d]) + 0.5) * dp;
+    double dd = static_cast<double>(pos[d * n + p]) - base;
+    dd -= box * rint(dd / box);
+    out[q * 3 + d] = static_cast<float>(dd / dp);
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_apply(float* __restrict__ pos, const int32_t* __restrict__ id, int64_t n,
+                                               const float* __restrict__ r, int N, float dp, float box,
+                                               int* __restrict__ flags) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (p >= n) return;
+  const int64_t q = id[p];
+  if (q < 0 || q >= static_cast<int64_t>(N) * N * N) {
+    atomicOr(flags, 1);
+    return;
+  }
+  for (int d = 0; d < 3; ++d) {
+    float x = pos[d * n + p] + r[q * 3 + d] * dp;
+    if (x >= box) x -= box;
+    if (x < 0.f) x += box;
+    pos[d * n + p] = x;
+  }
+}
+
+}  // namespace
+
+hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float* bias, int leaky_act, View out,
+                 float* outf, int cout, int D, hipStream_t s) {
+  const int V = D * D * D;
+  const unsigned grid = blocks_for(V, kNT);
+#define LPC_CONV(CI, NBV) k_conv3<CI, NBV><<<grid, kNT, 0, s>>>(in, w, kpad, bias, leaky_act, out, outf, cout, D)
+  if (cin == 8 && nb == 1) LPC_CONV(8, 1);
+  else if (cin == 8 && nb == 2) LPC_CONV(8, 2);
+  else if (cin == 8 && nb == 4) LPC_CONV(8, 4);
+  else if (cin == 16 && nb == 1) LPC_CONV(16, 1);
+  else if (cin == 16 && nb == 2) LPC_CONV(16, 2);
+  else if (cin == 16 && nb == 4) LPC_CONV(16, 4);
+  else if (cin == 32 && nb == 1) LPC_CONV(32, 1);
+  else if (cin == 32 && nb == 2) LPC_CONV(32, 2);
+  else if (cin == 32 && nb == 4) LPC_CONV(32, 4);
+  else if (cin == 64 && nb == 1) LPC_CONV(64, 1);
+  else if (cin == 64 && nb == 2) LPC_CONV(64, 2);
+  else if (cin == 64 && nb == 4) LPC_CONV(64, 4);
+  else return hipErrorInvalidValue;
+#undef LPC_CONV
+  return hipGetLastError();
+}
+
+hipError_t down2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(D / 2) * (D / 2) * (D / 2) * cout;
+  k_down2<<<blocks_for(n), kNT, 0, s>>>(x, cin, W, b, cout, out, D);
+  return hipGetLastError();
+}
+
+hipError_t up2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(8) * D * D * D * cout;
+  k_up2<<<blocks_for(n), kNT, 0, s>>>(x, cin, W, b, cout, out, D);
+  return hipGetLastError();
+}
+
+hipError_t down2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D, int accumulate, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(D) * D * D * cin;
+  k_down2_dgrad<<<blocks_for(n), kNT, 0, s>>>(dz, cout, W, cin, dx, D, accumulate);
+  return hipGetLastError();
+}
+
+hipError_t up2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(D) * D * D * cin;
+  k_up2_dgrad<<<blocks_for(n), kNT, 0, s>>>(dz, cout, W, cin, dx, D);
+  return hipGetLastError();
+}
+
+int wgrad_chunks(int nbase) {
+  const int c = nbase / 4096;
+  return c < 1 ? 1 : (c > 64 ? 64 : c);
+}
+
+hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int D, float* partial, hipStream_t s) {
+  if (cin > kMaxC || cout > kMaxC || (cin % 8) != 0) return hipErrorInvalidValue;
+  const int ntap = (kind == 0) ? 27 : 8;
+  const int nbase = (kind == 1) ? (D / 2) * (D / 2) * (D / 2) : D * D * D;
+  const dim3 grid(static_cast<unsigned>(wgrad_chunks(nbase)), static_cast<unsigned>(ntap));
+  if (cin == 8)
+    k_wgrad<8><<<grid, kNT, 0, s>>>(kind, x, cin, cin_real, dz, cout, D, ntap, nbase, partial);
+  else if ((cin % 16) == 0 && cout * (cin / 16) <= kNT)
+    k_wgrad<16><<<grid, kNT, 0, s>>>(kind, x, cin, cin_real, dz, cout, D, ntap, nbase, partial);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t reduce_partials(const float* partial, int nchunk, int nW, int cout, int nslot, float* grad,
+                           hipStream_t s) {
+  k_reduce<<<blocks_for(nW + cout), kNT, 0, s>>>(partial, nchunk, nW, cout, nslot, grad);
+  return hipGetLastError();
+}
+
+hipError_t leaky_dgrad(View a, View da, int c, int V, hipStream_t s) {
+  k_leaky_dgrad<<<blocks_for(static_cast<int64_t>(V) * c), kNT, 0, s>>>(a, da, c, V);
+  return hipGetLastError();
+}
+
+hipError_t convert_conv3(const float* W, int cout, int cin, bf16* wf, int cinp, int nbo, int kpad, bf16* wb,
+                         int coutp, int nbi, int kpadb, hipStream_t s) {
+  const int64_t n = static_cast<int64_t>(16 * nbo) * kpad + static_cast<int64_t>(16 * nbi) * kpadb;
+  k_convert_conv3<<<blocks_for(n), kNT, 0, s>>>(W, cout, cin, wf, cinp, nbo, kpad, wb, coutp, nbi, kpadb);
+  return hipGetLastError();
+}
+
+hipError_t pack_input(const float* feat, bf16* x, int V, hipStream_t s) {
+  k_pack_input<<<blocks_for(static_cast<int64_t>(V) * 8), kNT, 0, s>>>(feat, x, V);
+  return hipGetLastError();
+}
+
+int loss_blocks(int V) { return static_cast<int>(blocks_for(static_cast<int64_t>(V) * 8)); }
+
+hipError_t loss_grad(const float* out, const float* target, bf16* dout, double* loss_part, int V, hipStream_t s) {
+  k_loss_grad<<<static_cast<unsigned>(loss_blocks(V)), kNT, 0, s>>>(out, target, dout, loss_part, V);
+  return hipGetLastError();
+}
+
+hipError_t adam(float* p, float* m, float* v, const float* g, int64_t count, float lr, double beta1, double beta2,
+                float eps, int64_t t, hipStream_t s) {
+  const float c1 = static_cast<float>(1.0 - std::pow(beta1, static_cast<double>(t)));
+  const float c2 = static_cast<float>(1.0 - std::pow(beta2, static_cast<double>(t)));
+  k_adam<<<blocks_for(count), kNT, 0, s>>>(p, m, v, g, count, lr, static_cast<float>(beta1),
+                                           static_cast<float>(1.0 - beta1), static_cast<float>(beta2),
+                                           static_cast<float>(1.0 - beta2), eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t features(const float* pos, const int32_t* id, int64_t n, const float* ref, int N, double box, float* out,
+                    int* flags, hipStream_t s) {
+  k_features<<<blocks_for(n), kNT, 0, s>>>(pos, id, n, ref, N, box, out, flags);
+  return hipGetLastError();
+}
+
+hipError_t apply_residual(float* pos, const int32_t* id, int64_t n, const float* r, int N, double box, int* flags,
+                          hipStream_t s) {
+  k_apply<<<blocks_for(n), kNT, 0, s>>>(pos, id, n, r, N, static_cast<float>(box / N), static_cast<float>(box),
+                                        flags);
+  return hipGetLastError();
+}
+
+}  // namespace net
+}  // namespace lpc

@@ -1,0 +1,108 @@
+"""Training and use of the learned displacement correction (the network of include/lpc.h), on top of the C ABI.
+
+A pair is two runs of lpc_cola_step from the same 2LPT initial conditions: a coarse one with the PM mesh equal to the
+particle lattice (Nm = N) and a fine one with Nm = 3 N. The network learns the per-particle displacement that moves
+the coarse result onto the fine one (in lattice units, as a field on the N^3 lattice), so that a coarse run plus one
+network pass stands in for the fine run. Every numerical step runs in liblpc's kernels; this module only sequences
+calls and holds device buffers (torch tensors).
+"""
+import time
+
+import numpy as np
+
+from paper_1506_03737_amd import lpc
+
+
+def run_pair(seed, n_side, box, a_list, cosmo, step, device, fine_factor=3):
+    """(coarse, fine) particle sets evolved over a_list from the same initial conditions (lattice-ordered ids)."""
+    import torch
+    n = n_side**3
+    geom_ic = lpc.geometry(n_side, n_side, box)
+    ic = lpc.ParticleSet.empty(n, device)
+    ws = lpc.workspace(geom_ic, lpc.LPC_OP_INIT_IC, device)
+    lpc.lpc_init_ic(geom_ic, cosmo, seed, a_list[0], ic, ws)
+    del ws
+    out = []
+    for nm in (n_side, fine_factor * n_side):
+        ps = lpc.ParticleSet(*(torch.clone(getattr(ic, k)) for k in ("pos", "vel", "psi1", "psi2", "id")))
+        geom = lpc.geometry(n_side, nm, box)
+        ws = lpc.workspace(geom, lpc.LPC_OP_COLA_STEP, device)
+        lpc.lpc_cola_step(geom, cosmo, step, a_list, ps, ws)
+        del ws
+        out.append(ps)
+    return out[0], out[1]
+
+
+def pair_grids(coarse, fine, n_side, box, ws, device):
+    """Feature grid (coarse displacement from the lattice) and target grid (fine - coarse), FP32 [N^3][3] each."""
+    import torch
+    geom = lpc.geometry(n_side, n_side, box)
+    feat = torch.empty((n_side**3, 3), dtype=torch.float32, device=device)
+    target = torch.empty_like(feat)
+    lpc.lpc_net_features(geom, coarse.pos, coarse.id, feat, ws)
+    lpc.lpc_net_features(geom, fine.pos, fine.id, target, ws, ref_pos=coarse.pos)
+    return feat, target
+
+
+def symmetry(grid, n_side, k):
+    """The k-th (0..47) symmetry of the cube applied to a vector field [N^3][3]: an axis permutation with sign flips,
+    acting on both the grid positions and the vector components (the equations of motion are invariant under it)."""
+    import torch
+    perms = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+    perm, flips = perms[k // 8], k % 8
+    g = grid.reshape(n_side, n_side, n_side, 3).permute(*perm, 3)[..., list(perm)]
+    for ax in range(3):
+        if flips >> ax & 1:
+            # reflection x -> -x of a periodic, cell-centred lattice maps site i to N - 1 - i
+            g = torch.flip(g, dims=(ax,))
+            g[..., ax] = -g[..., ax]
+    return g.reshape(-1, 3).contiguous()
+
+
+def train(samples, n_side, epochs, lr, seed=1, device="cuda", augment=True, log=None):
+    """Adam on (feature, target) grid pairs; returns (params on device, per-epoch mean losses)."""
+    import torch
+    params = torch.from_numpy(lpc.lpc_net_init(seed)).to(device)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    ws = lpc.net_workspace(n_side, device)
+    rng = np.random.default_rng(seed)
+    t = 0
+    history = []
+    for ep in range(epochs):
+        order = rng.permutation(len(samples))
+        losses = []
+        for i in order:
+            feat, target = samples[i]
+            if augment:
+                k = int(rng.integers(48))
+                feat, target = symmetry(feat, n_side, k), symmetry(target, n_side, k)
+            t += 1
+            losses.append(lpc.lpc_net_loss_grad(n_side, params, feat, target, grad, ws))
+            lpc.lpc_net_adam(params, m, v, grad, t, lr)
+        history.append(float(np.mean(losses)))
+        if log:
+            log(f"epoch {ep}: mean loss {history[-1]:.4e}")
+    return params, history
+
+
+def validation_loss(params, samples, n_side, device="cuda"):
+    """Mean loss of the network and of the zero correction (target^2) over held-out samples."""
+    import torch
+    ws = lpc.net_workspace(n_side, device)
+    grad = torch.empty_like(params)
+    net, zero = [], []
+    for feat, target in samples:
+        net.append(lpc.lpc_net_loss_grad(n_side, params, feat, target, grad, ws))
+        zero.append(float(torch.mean(target.double() ** 2)))
+    return float(np.mean(net)), float(np.mean(zero))
+
+
+def timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0

@@ -67,6 +67,14 @@ def _load():
         "lpc_workspace_bytes_batched": (sz, [P(BatchEntry), i32]),
         "lpc_cola_step_batched": (i32, [P(BatchEntry), i32, P(Cosmology), P(Stepping), P(dbl), i32, vp, sz, vp]),
         "lpc_graph_enable": (i32, [i32]),
+        "lpc_net_param_count": (i64, []),
+        "lpc_net_init": (i32, [P(ctypes.c_float), ctypes.c_uint64]),
+        "lpc_net_workspace_bytes": (sz, [i32]),
+        "lpc_net_features": (i32, [P(Geometry), vp, vp, i64, vp, vp, vp, sz, vp]),
+        "lpc_net_forward": (i32, [i32, vp, vp, vp, vp, sz, vp]),
+        "lpc_net_loss_grad": (i32, [i32, vp, vp, vp, vp, P(dbl), vp, sz, vp]),
+        "lpc_net_adam": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, vp]),
+        "lpc_net_apply": (i32, [P(Geometry), vp, P(Particles), vp, sz, vp]),
         "lpc_power_spectrum": (i32, [P(Geometry), vp, i64, dbl, i32, P(dbl), P(dbl), P(i64), vp, sz, vp]),
         "lpc_cola_coefficients": (i32, [P(Cosmology), P(Stepping), P(dbl), i32, P(dbl)]),
         "lpc_linear_power": (i32, [P(Cosmology), P(dbl), i32, P(dbl)]),
@@ -90,6 +98,8 @@ def _load():
 LIB = _load()
 EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_cola_step", "lpc_workspace_bytes_batched",
             "lpc_cola_step_batched", "lpc_graph_enable", "lpc_power_spectrum",
+            "lpc_net_param_count", "lpc_net_init", "lpc_net_workspace_bytes", "lpc_net_features", "lpc_net_forward",
+            "lpc_net_loss_grad", "lpc_net_adam", "lpc_net_apply",
             "lpc_cola_coefficients", "lpc_linear_power", "lpc_fft_r2c", "lpc_fft_c2r", "lpc_fft_pitch",
             "lpc_profile_enable", "lpc_profile_reset", "lpc_profile_count", "lpc_profile_get",
             "lpc_status_string", "lpc_last_error")
@@ -254,6 +264,59 @@ def lpc_fft_r2c(n, real_in, complex_out, ws, stream=None):
 
 def lpc_fft_c2r(n, complex_in, real_out, ws, stream=None):
     _check(LIB.lpc_fft_c2r(int(n), _ptr(complex_in), _ptr(real_out), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+# --- learned correction ---------------------------------------------------------------------------------------
+
+def lpc_net_param_count():
+    return int(LIB.lpc_net_param_count())
+
+
+def lpc_net_init(seed):
+    """Initial parameters (host NumPy float32)."""
+    p = np.empty(lpc_net_param_count(), dtype=np.float32)
+    _check(LIB.lpc_net_init(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.c_uint64(seed)))
+    return p
+
+
+def lpc_net_workspace_bytes(n_side):
+    return int(LIB.lpc_net_workspace_bytes(int(n_side)))
+
+
+def net_workspace(n_side, device="cuda"):
+    import torch
+    nbytes = lpc_net_workspace_bytes(n_side)
+    if nbytes == 0:
+        raise LpcError(-2, f"unsupported n_side {n_side} for the network")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def lpc_net_features(geom, pos, ids, out, ws, ref_pos=None, stream=None):
+    _check(LIB.lpc_net_features(ctypes.byref(geom), _ptr(pos), _ptr(ids), int(pos.shape[1]), _ptr(ref_pos), _ptr(out),
+                                _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def lpc_net_forward(n_side, params, feat, out, ws, stream=None):
+    _check(LIB.lpc_net_forward(int(n_side), _ptr(params), _ptr(feat), _ptr(out), _ptr(ws), ws.numel(),
+                               _stream(stream)))
+
+
+def lpc_net_loss_grad(n_side, params, feat, target, grad, ws, stream=None):
+    loss = ctypes.c_double()
+    _check(LIB.lpc_net_loss_grad(int(n_side), _ptr(params), _ptr(feat), _ptr(target), _ptr(grad),
+                                 ctypes.byref(loss), _ptr(ws), ws.numel(), _stream(stream)))
+    return float(loss.value)
+
+
+def lpc_net_adam(params, m, v, grad, step, lr, stream=None):
+    _check(LIB.lpc_net_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), ctypes.c_float(lr),
+                            _stream(stream)))
+
+
+def lpc_net_apply(geom, params, particles, ws, stream=None):
+    p = particles.c_struct()
+    _check(LIB.lpc_net_apply(ctypes.byref(geom), _ptr(params), ctypes.byref(p), _ptr(ws), ws.numel(),
+                             _stream(stream)))
 
 
 def lpc_status_string(status):

@@ -155,3 +155,17 @@ def test_argument_errors_are_status_codes():
     st = lib.lpc_init_ic(ctypes.byref(g), ctypes.byref(c), 1, 0.1, ctypes.byref(p), ctypes.c_void_p(256), 1 << 30,
                          None)
     assert st == -1 and b"n_side^3" in lib.lpc_last_error()
+
+
+def test_net_parameter_count_and_workspace_sizes():
+    from oracle import net as onet
+    from paper_1506_03737_amd import lpc
+    assert lpc.lpc_net_param_count() == onet.param_count()
+    p = lpc.lpc_net_init(7)
+    assert p.shape == (onet.param_count(),) and np.all(np.isfinite(p))
+    sl = onet.layer_slices()
+    assert np.all(p[sl["e0b"][1]] == 0.0)                          # biases start at zero
+    assert np.abs(p[sl["e0b"][0]]).max() <= np.sqrt(6.0 / (27 * 16)) + 1e-7
+    assert np.array_equal(p, lpc.lpc_net_init(7)) and not np.array_equal(p, lpc.lpc_net_init(8))
+    assert lpc.lpc_net_workspace_bytes(16) > 0 and lpc.lpc_net_workspace_bytes(6) == 0
+    assert lpc.lpc_net_workspace_bytes(18) == 0 and lpc.lpc_net_workspace_bytes(1024) == 0
