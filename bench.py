@@ -12,9 +12,11 @@ all). value = N^3 * K / wall time (particle-steps/s), inputs resident in HBM bef
 Also reported: the dominant kernel's achieved HBM bandwidth from HIP events recorded on the call's stream
 (roofline), the FP64 CPU oracle's rate on a bounded sample (cpu_baseline), and the batched form on 48 uneven boxes
 (96^3/128^3/160^3 particles, Nm = 2N, L = 300..600 Mpc/h, one lpc_cola_step_batched call replaying its recorded HIP
-graph; aggregate particle-steps/s, in "batched").
+graph; aggregate particle-steps/s, in "batched"), and the learned form (a coarse Nm = N run plus the trained
+correction network against the fine Nm = 3N run, with its P(k) error, in "learned").
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--workload single|small|large] [--no-cpu] [--no-batched]
+                      [--no-learned]
 """
 import argparse
 import json
@@ -133,6 +135,66 @@ def batched_bench(lpc, synth, torch, steps):
             "stages_direct_launch": stages}
 
 
+def learned_bench(lpc, synth, torch, steps):
+    """The learned form: a coarse run (Nm = N) plus one network pass, against the fine run (Nm = 3N) it stands in
+    for. Training data: 64 coarse/fine pairs of 128^3 particles in 500 Mpc/h boxes (seeds 5000..5063) made by
+    lpc_cola_step, 8 more held out; 12 epochs of Adam (lr 1e-3 -> 5e-5, cosine), random cube symmetries. Applied to
+    the single-box workload (256^3 particles, 1000 Mpc/h, seed 2015): coarse Nm = 256 + network vs fine Nm = 768.
+    Throughput counts the coarse run and the network pass; P(k) errors are against the fine run, k <= 0.5 h/Mpc."""
+    import numpy as np
+    from paper_1506_03737_amd import learned
+    dev = torch.device("cuda:0")
+    cosmo = lpc.cosmology(**synth.COSMOLOGY)
+    step = lpc.stepping(**synth.STEPPING)
+    a_list = np.linspace(0.1, 1.0, steps + 1)
+    n_tr, box_tr = 128, 500.0
+    ws = lpc.net_workspace(n_tr, dev)
+    t0 = time.perf_counter()
+    train_s, val_s = [], []
+    for seed in range(5000, 5072):
+        c, f = learned.run_pair(seed, n_tr, box_tr, a_list, cosmo, step, dev)
+        (train_s if seed < 5064 else val_s).append(learned.pair_grids(c, f, n_tr, box_tr, ws, dev))
+        del c, f
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    (params, hist), t_train = learned.timed(
+        lambda: learned.train(train_s, n_tr, epochs=12, lr=1e-3, lr_final=5e-5, seed=3, device=dev))
+    net_loss, zero_loss = learned.validation_loss(params, val_s, n_tr, dev)
+    del train_s, val_s, ws
+    # apply to the single-box workload
+    N, box = 256, 1000.0
+    n = N**3
+    geom_ic = lpc.geometry(N, N, box)
+    ic = lpc.ParticleSet.empty(n, dev)
+    ws_ic = lpc.workspace(geom_ic, lpc.LPC_OP_INIT_IC, dev)
+    lpc.lpc_init_ic(geom_ic, cosmo, 2015, 0.1, ic, ws_ic)
+    del ws_ic
+    runs = {}
+    for name, nm in (("coarse", N), ("fine", 3 * N)):
+        ps = lpc.ParticleSet(*(torch.clone(getattr(ic, k)) for k in ("pos", "vel", "psi1", "psi2", "id")))
+        geom = lpc.geometry(N, nm, box)
+        wsr = lpc.workspace(geom, lpc.LPC_OP_COLA_STEP, dev)
+        _, dt = learned.timed(lambda: lpc.lpc_cola_step(geom, cosmo, step, a_list, ps, wsr))
+        del wsr
+        runs[name] = (ps, dt)
+    corrected = lpc.ParticleSet(torch.clone(runs["coarse"][0].pos), None, ic.psi1, None, ic.id)
+    ws_net = lpc.net_workspace(N, dev)
+    _, t_apply = learned.timed(lambda: lpc.lpc_net_apply(lpc.geometry(N, N, box), params, corrected, ws_net))
+    k, p_fine, cnt = learned.power_spectrum(runs["fine"][0].pos, n, box, dev)
+    _, p_coarse, _ = learned.power_spectrum(runs["coarse"][0].pos, n, box, dev)
+    _, p_corr, _ = learned.power_spectrum(corrected.pos, n, box, dev)
+    sel = (k <= 0.5) & (cnt > 0)
+    err = lambda p: float(np.max(np.abs(p[sel] / p_fine[sel] - 1.0)))
+    t_learned = runs["coarse"][1] + t_apply
+    return {"value": n * steps / t_learned, "unit": "particle-steps/s", "ms_per_step": t_learned * 1e3 / steps,
+            "fine_value": n * steps / runs["fine"][1], "speedup_vs_fine": runs["fine"][1] / t_learned,
+            "coarse_run_ms": runs["coarse"][1] * 1e3, "net_apply_ms": t_apply * 1e3, "fine_run_ms": runs["fine"][1] * 1e3,
+            "pk_max_rel_err_k_le_0.5": {"coarse": err(p_coarse), "coarse+net": err(p_corr)},
+            "validation_loss_ratio": net_loss / zero_loss, "train_s": t_train, "pairs_s": t_gen,
+            "workload": "256^3 particles, 1000 Mpc/h, seed 2015: coarse Nm=256 + network vs fine Nm=768; network "
+                        "trained on 64 pairs of 128^3 / 500 Mpc/h (coarse Nm=128, fine Nm=384), 12 epochs"}
+
+
 def cpu_baseline_sample():
     """The FP64 oracle, untuned, on one COLA step of the single-box workload at 1/8 of its volume: 128^3 particles,
     384^3 mesh, 500 Mpc/h (same Nm/N = 3 and particle density). Returns particle-steps/s for that sample."""
@@ -161,6 +223,7 @@ def main():
     ap.add_argument("--workload", default="single", choices=["single", "small", "large"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-box batched measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -240,6 +303,9 @@ def main():
         del ps, ic, ws
         torch.cuda.empty_cache()
         out["batched"] = batched_bench(lpc, synth, torch, args.steps)
+    if not args.no_learned and args.workload == "single":
+        torch.cuda.empty_cache()
+        out["learned"] = learned_bench(lpc, synth, torch, args.steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_sample()
     print(json.dumps(out), flush=True)

@@ -194,12 +194,13 @@ int32_t lpc_fft_pitch(int32_t n);
  * mesh buys, Sec. 2.4). A coarse run (Nm = N) is corrected toward a fine run (Nm = 3N) by a 3-D convolutional
  * network on the N^3 particle lattice, trained only on pairs of runs of this library.
  *
- * Grid: voxel v = (i N + j) N + l is the lattice site of particle id v. Feature grid: FP32 [N^3][3], the particle's
- * minimal-image displacement from its lattice point q = (i + 1/2, j + 1/2, l + 1/2) L / N, in units of L / N. Output:
- * FP32 [N^3][3], the residual displacement (same units) added to the coarse positions.
+ * Grid: voxel v = (i N + j) N + l is the lattice site of particle id v. Input grid: FP32 [N^3][6]: channels 0..2
+ * the particle's minimal-image displacement from its lattice point q = (i + 1/2, j + 1/2, l + 1/2) L / N, channels
+ * 3..5 its first-order 2LPT displacement Psi1 (Sec. 2.1), both in units of L / N. Output: FP32 [N^3][3], the
+ * residual displacement (same units) added to the coarse positions.
  * Network (3^3 convolutions with periodic wrap; "down" = 2^3 stride-2 convolution, "up" = 2^3 stride-2 transposed
  * convolution; every layer but the last followed by leaky ReLU, slope 0.1):
- *   a0 = conv(in: 3 -> 16); s0 = conv(a0: 16 -> 16); a1 = down(s0: 16 -> 32) at N/2; s1 = conv(a1: 32 -> 32);
+ *   a0 = conv(in: 6 -> 16); s0 = conv(a0: 16 -> 16); a1 = down(s0: 16 -> 32) at N/2; s1 = conv(a1: 32 -> 32);
  *   a2 = down(s1: 32 -> 64) at N/4; b2 = conv(a2: 64 -> 64); u1 = up(b2: 64 -> 32) at N/2;
  *   c1 = conv([u1, s1]: 64 -> 32); u0 = up(c1: 32 -> 16) at N; c0 = conv([u0, s0]: 32 -> 16); out = conv(c0: 16 -> 3).
  * Parameters: one FP32 vector (lpc_net_param_count() values); per layer in the order above, W[Cout][taps][Cin] with
@@ -216,13 +217,16 @@ lpc_status lpc_net_init(float* params, uint64_t seed);
 
 size_t lpc_net_workspace_bytes(int32_t n_side);
 
-/* Feature (ref_pos NULL) or target grid of N^3 particles pos[3][n] with lattice ids id[n]: out[id][d] = minimal
- * image (pos - base) / (L / N), base = the lattice point of id, or ref_pos[3][n] (the same particles in another run,
- * e.g. target = fine - coarse). An id outside [0, N^3) gives LPC_ERR_INVALID_ARG. */
+/* Input grid (psi1 given, ref_pos NULL: out is [N^3][6]) or target grid (ref_pos given, psi1 NULL: out is [N^3][3])
+ * of N^3 particles pos[3][n] with lattice ids id[n]: out[id][d] = minimal image (pos - base) / (L / N) with base the
+ * lattice point of id, or ref_pos[3][n] (the same particles in another run: target = fine - coarse); and
+ * out[id][3 + d] = psi1[d][p] / (L / N). With neither, out is the displacement alone ([N^3][3]). An id outside
+ * [0, N^3) gives LPC_ERR_INVALID_ARG. */
 lpc_status lpc_net_features(const lpc_geometry* geom, const float* pos, const int32_t* id, int64_t n,
-                            const float* ref_pos, float* out, void* ws, size_t ws_bytes, void* stream);
+                            const float* ref_pos, const float* psi1, float* out, void* ws, size_t ws_bytes,
+                            void* stream);
 
-/* out[N^3][3] = network(feat[N^3][3]) with device params. */
+/* out[N^3][3] = network(feat[N^3][6]) with device params. */
 lpc_status lpc_net_forward(int32_t n_side, const float* params, const float* feat, float* out, void* ws,
                            size_t ws_bytes, void* stream);
 
@@ -235,8 +239,8 @@ lpc_status lpc_net_loss_grad(int32_t n_side, const float* params, const float* f
  * device vectors params, m, v with gradient grad. */
 lpc_status lpc_net_adam(float* params, float* m, float* v, const float* grad, int64_t step, float lr, void* stream);
 
-/* Corrects a coarse run in place: pos += network(features(pos, id)) L / N, wrapped into [0, L). inout->n must be
- * n_side^3 (one particle per lattice site); only pos and id are used. */
+/* Corrects a coarse run in place: pos += network(input grid(pos, psi1, id)) L / N, wrapped into [0, L). inout->n must
+ * be n_side^3 (one particle per lattice site); only pos, psi1 and id are used. */
 lpc_status lpc_net_apply(const lpc_geometry* geom, const float* params, const lpc_particles* inout, void* ws,
                          size_t ws_bytes, void* stream);
 

@@ -9,7 +9,8 @@ Tensors are channels-first NumPy arrays (C, D, D, D) on a periodic D^3 grid. Lay
   down2(x, W, b)  out[o, y] = b[o] + sum_{i, t} W[o, t, i] x[i, 2y + t]      (t in {0,1}^3)
   up2(x, W, b)    out[o, 2y + t] = b[o] + sum_i W[o, t, i] x[i, y]
   leaky(z)        z if z > 0 else 0.1 z
-Network (input 3 channels: the coarse displacement in lattice units; output 3 channels: the residual):
+Network (input 6 channels: the coarse run's displacement from the lattice and the first-order 2LPT displacement Psi1,
+both in lattice units; output 3 channels: the residual displacement):
   a0 = leaky(conv3(in))            16 @ D
   s0 = leaky(conv3(a0))            16 @ D
   a1 = leaky(down2(s0))            32 @ D/2
@@ -29,7 +30,7 @@ import numpy as np
 SLOPE = 0.1
 # (name, kind, cin, cout)
 LAYERS = (
-    ("e0a", "conv3", 3, 16),
+    ("e0a", "conv3", 6, 16),
     ("e0b", "conv3", 16, 16),
     ("d1", "down2", 16, 32),
     ("e1", "conv3", 32, 32),
@@ -226,6 +227,14 @@ def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 # --- features ------------------------------------------------------------------------------------------------------
+
+def input_grid(pos, psi1, ids, n_side, box):
+    """Network input (6, N, N, N): the displacement from the lattice (displacement_grid) and Psi1 / (L / N)."""
+    dp = box / n_side
+    g = np.zeros((3, n_side**3))
+    g[:, np.asarray(ids)] = np.asarray(psi1, dtype=np.float64) / dp
+    return np.concatenate([displacement_grid(pos, ids, n_side, box), g.reshape(3, n_side, n_side, n_side)])
+
 
 def displacement_grid(pos, ids, n_side, box, ref=None):
     """Lagrangian displacement field on the lattice, in lattice units, channels-first (3, N, N, N).

@@ -55,8 +55,12 @@ __global__ __launch_bounds__(kNT) void k_conv3(View in, const bf16* __restrict__
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mt][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const bf16* inb = in.p + in.off;
-  const int nk = kpad / 32;
-  for (int s = 0; s < nk; ++s) {
+  // K steps of 32 (27 taps x CIN channels, padded): a compile-time count, unrolled so that the loads of several
+  // steps are in flight before their MFMAs need them (the kernel is latency-bound otherwise)
+  constexpr int NK = (27 * CIN + 31) / 32;
+  (void)kpad;
+#pragma unroll 4
+  for (int s = 0; s < NK; ++s) {
     const int k0 = s * 32 + g * 8;
     const int tap = k0 / CIN, ci = k0 - tap * CIN;
     const bool tap_ok = tap < 27;
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(kNT) void k_conv3(View in, const bf16* __restrict__
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const bf16x8 B = *reinterpret_cast<const bf16x8*>(w + static_cast<size_t>(nb * 16 + r) * kpad + k0);
+      const bf16x8 B = *reinterpret_cast<const bf16x8*>(w + static_cast<size_t>(nb * 16 + r) * (NK * 32) + k0);
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
         acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B, acc[mt][nb], 0, 0, 0);
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(kNT) void k_pack_input(const float* __restrict__ fe
   if (idx >= static_cast<int64_t>(V) * 8) return;
   const int64_t v = idx / 8;
   const int c = static_cast<int>(idx % 8);
-  x[idx] = static_cast<bf16>(c < 3 ? feat[v * 3 + c] : 0.f);
+  x[idx] = static_cast<bf16>(c < kInputChannels ? feat[v * kInputChannels + c] : 0.f);
 }
 
 __global__ __launch_bounds__(kNT) void k_loss_grad(const float* __restrict__ out, const float* __restrict__ target,
@@ -363,8 +367,9 @@ __global__ __launch_bounds__(kNT) void k_adam(float* __restrict__ p, float* __re
 }
 
 __global__ __launch_bounds__(kNT) void k_features(const float* __restrict__ pos, const int32_t* __restrict__ id,
-                                                  int64_t n, const float* __restrict__ ref, int N, double box,
-                                                  float* __restrict__ out, int* __restrict__ flags) {
+                                                  int64_t n, const float* __restrict__ ref,
+                                                  const float* __restrict__ psi1, int N, double box,
+                                                  float* __restrict__ out, int ld, int* __restrict__ flags) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
   if (p >= n) return;
   const int64_t q = id[p];
@@ -379,7 +384,8 @@ __global__ __launch_bounds__(kNT) void k_features(const float* __restrict__ pos,
     const double base = ref ? static_cast<double>(ref[d * n + p]) : (static_cast<double>(ijk[d]) + 0.5) * dp;
     double dd = static_cast<double>(pos[d * n + p]) - base;
     dd -= box * rint(dd / box);
-    out[q * 3 + d] = static_cast<float>(dd / dp);
+    out[q * ld + d] = static_cast<float>(dd / dp);
+    if (psi1) out[q * ld + 3 + d] = static_cast<float>(static_cast<double>(psi1[d * n + p]) / dp);
   }
 }
 
@@ -508,9 +514,9 @@ hipError_t adam(float* p, float* m, float* v, const float* g, int64_t count, flo
   return hipGetLastError();
 }
 
-hipError_t features(const float* pos, const int32_t* id, int64_t n, const float* ref, int N, double box, float* out,
-                    int* flags, hipStream_t s) {
-  k_features<<<blocks_for(n), kNT, 0, s>>>(pos, id, n, ref, N, box, out, flags);
+hipError_t features(const float* pos, const int32_t* id, int64_t n, const float* ref, const float* psi1, int N,
+                    double box, float* out, int* flags, hipStream_t s) {
+  k_features<<<blocks_for(n), kNT, 0, s>>>(pos, id, n, ref, psi1, N, box, out, psi1 ? kInputChannels : 3, flags);
   return hipGetLastError();
 }
 

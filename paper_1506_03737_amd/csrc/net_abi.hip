@@ -29,7 +29,7 @@ struct LayerDef {
 // The network of include/lpc.h, in parameter order.
 enum { E0A, E0B, DOWN1, E1, DOWN2, B2, UP1, C1, UP0, C0, OUT, kNumLayers };
 constexpr LayerDef kLayers[kNumLayers] = {
-    {kConv3, 3, 16},  {kConv3, 16, 16}, {kDown2, 16, 32}, {kConv3, 32, 32}, {kDown2, 32, 64}, {kConv3, 64, 64},
+    {kConv3, net::kInputChannels, 16},  {kConv3, 16, 16}, {kDown2, 16, 32}, {kConv3, 32, 32}, {kDown2, 32, 64}, {kConv3, 64, 64},
     {kUp2, 64, 32},   {kConv3, 64, 32}, {kUp2, 32, 16},   {kConv3, 32, 16}, {kConv3, 16, 3},
 };
 
@@ -128,7 +128,7 @@ NetWs layout(void* base, int D) {
   w.db2 = act(V2, 64);
   w.da2 = act(V2, 64);
   w.out = reinterpret_cast<float*>(take(V * 3 * sizeof(float)));
-  w.feat = reinterpret_cast<float*>(take(V * 3 * sizeof(float)));
+  w.feat = reinterpret_cast<float*>(take(V * net::kInputChannels * sizeof(float)));
   w.loss_part = reinterpret_cast<double*>(take(static_cast<size_t>(net::loss_blocks(static_cast<int>(V))) * 8));
   w.partial = reinterpret_cast<float*>(take(static_cast<size_t>(partial_floats(D)) * sizeof(float)));
   for (int l = 0; l < kNumLayers; ++l) {
@@ -303,8 +303,10 @@ lpc_status lpc_net_init(float* params, uint64_t seed) {
 size_t lpc_net_workspace_bytes(int32_t n_side) { return size_ok(n_side) ? layout(nullptr, n_side).total : 0; }
 
 lpc_status lpc_net_features(const lpc_geometry* geom, const float* pos, const int32_t* id, int64_t n,
-                            const float* ref_pos, float* out, void* ws, size_t ws_bytes, void* stream) {
+                            const float* ref_pos, const float* psi1, float* out, void* ws, size_t ws_bytes,
+                            void* stream) {
   if (!geom || !pos || !id || !out) return fail(LPC_ERR_INVALID_ARG, "NULL argument");
+  if (ref_pos && psi1) return fail(LPC_ERR_INVALID_ARG, "give ref_pos (a target grid) or psi1 (an input grid), not both");
   if (!(geom->box > 0.0) || !std::isfinite(geom->box)) return fail(LPC_ERR_INVALID_ARG, "box must be positive");
   if (n < 1 || n > (int64_t(1) << 31) - 1) return fail(LPC_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
   NetWs w;
@@ -312,7 +314,7 @@ lpc_status lpc_net_features(const lpc_geometry* geom, const float* pos, const in
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
     check(hipMemsetAsync(w.flags, 0, 4 * sizeof(int), s), "hipMemsetAsync");
-    check(net::features(pos, id, n, ref_pos, geom->n_side, geom->box, out, w.flags, s), "features");
+    check(net::features(pos, id, n, ref_pos, psi1, geom->n_side, geom->box, out, w.flags, s), "features");
     return sync_flags(w.flags, s);
   });
 }
@@ -324,10 +326,11 @@ lpc_status lpc_net_forward(int32_t n_side, const float* params, const float* fea
   if (lpc_status st = check_net_ws(n_side, ws, ws_bytes, &w)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
-    const size_t bytes = static_cast<size_t>(n_side) * n_side * n_side * 3 * sizeof(float);
-    check(hipMemcpyAsync(w.feat, feat, bytes, hipMemcpyDeviceToDevice, s), "copy features");
+    const size_t V = static_cast<size_t>(n_side) * n_side * n_side;
+    check(hipMemcpyAsync(w.feat, feat, V * net::kInputChannels * sizeof(float), hipMemcpyDeviceToDevice, s),
+          "copy features");
     forward(w, params, s);
-    check(hipMemcpyAsync(out, w.out, bytes, hipMemcpyDeviceToDevice, s), "copy output");
+    check(hipMemcpyAsync(out, w.out, V * 3 * sizeof(float), hipMemcpyDeviceToDevice, s), "copy output");
     check(hipStreamSynchronize(s), "hipStreamSynchronize");
     return LPC_OK;
   });
@@ -341,7 +344,8 @@ lpc_status lpc_net_loss_grad(int32_t n_side, const float* params, const float* f
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
     const int V = n_side * n_side * n_side;
-    check(hipMemcpyAsync(w.feat, feat, static_cast<size_t>(V) * 3 * sizeof(float), hipMemcpyDeviceToDevice, s),
+    check(hipMemcpyAsync(w.feat, feat, static_cast<size_t>(V) * net::kInputChannels * sizeof(float),
+                         hipMemcpyDeviceToDevice, s),
           "copy features");
     forward(w, params, s);
     backward(w, params, target, grad, s);
@@ -370,7 +374,8 @@ lpc_status lpc_net_adam(float* params, float* m, float* v, const float* grad, in
 
 lpc_status lpc_net_apply(const lpc_geometry* geom, const float* params, const lpc_particles* inout, void* ws,
                          size_t ws_bytes, void* stream) {
-  if (!geom || !params || !inout || !inout->pos || !inout->id) return fail(LPC_ERR_INVALID_ARG, "NULL argument");
+  if (!geom || !params || !inout || !inout->pos || !inout->psi1 || !inout->id)
+    return fail(LPC_ERR_INVALID_ARG, "NULL argument (params, pos, psi1 and id are needed)");
   if (!(geom->box > 0.0) || !std::isfinite(geom->box)) return fail(LPC_ERR_INVALID_ARG, "box must be positive");
   const int N = geom->n_side;
   NetWs w;
@@ -380,8 +385,10 @@ lpc_status lpc_net_apply(const lpc_geometry* geom, const float* params, const lp
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
     check(hipMemsetAsync(w.flags, 0, 4 * sizeof(int), s), "hipMemsetAsync");
-    check(hipMemsetAsync(w.feat, 0, static_cast<size_t>(V) * 3 * sizeof(float), s), "hipMemsetAsync");
-    check(net::features(inout->pos, inout->id, inout->n, nullptr, N, geom->box, w.feat, w.flags, s), "features");
+    check(hipMemsetAsync(w.feat, 0, static_cast<size_t>(V) * net::kInputChannels * sizeof(float), s),
+          "hipMemsetAsync");
+    check(net::features(inout->pos, inout->id, inout->n, nullptr, inout->psi1, N, geom->box, w.feat, w.flags, s),
+          "features");
     forward(w, params, s);
     check(net::apply_residual(inout->pos, inout->id, inout->n, w.out, N, geom->box, w.flags, s), "apply");
     return sync_flags(w.flags, s);

@@ -14,6 +14,9 @@ namespace net {
 
 typedef __bf16 bf16;
 
+// Network input channels: the displacement from the lattice and Psi1, both in lattice units.
+constexpr int kInputChannels = 6;
+
 struct View {        // a BF16 tensor view: base[v * ld + off + c]
   bf16* p;
   int ld, off;
@@ -55,7 +58,7 @@ hipError_t leaky_dgrad(View a, View da, int c, int V, hipStream_t s);
 hipError_t convert_conv3(const float* W, int cout, int cin, bf16* wf, int cinp, int nbo, int kpad, bf16* wb,
                          int coutp, int nbi, int kpadb, hipStream_t s);
 
-// Net input: FP32 features [V][3] -> BF16 [V][8] (channels 3..7 zero).
+// Net input: FP32 features [V][6] -> BF16 [V][8] (channels 6, 7 zero).
 hipError_t pack_input(const float* feat, bf16* x, int V, hipStream_t s);
 // Loss gradient: dout BF16 [V][8] = 2 (out - target) / (3 V) (channels 3..7 zero); per-block sums of squared
 // errors (double) in loss_part[nblocks].
@@ -67,9 +70,10 @@ hipError_t adam(float* p, float* m, float* v, const float* g, int64_t count, flo
                 float eps, int64_t t, hipStream_t s);
 
 // Lattice features of particles pos[3][n] with lattice ids: out[id][d] = minimal image (pos - base) / (L / N), base
-// the lattice point of id (ref == NULL) or ref[3][n]. flags[0] is set if an id is out of range.
-hipError_t features(const float* pos, const int32_t* id, int64_t n, const float* ref, int N, double box, float* out,
-                    int* flags, hipStream_t s);
+// the lattice point of id (ref == NULL) or ref[3][n]; with psi1, also out[id][3 + d] = psi1[d][p] / (L / N) (row
+// stride 6, else 3). flags[0] is set if an id is out of range.
+hipError_t features(const float* pos, const int32_t* id, int64_t n, const float* ref, const float* psi1, int N,
+                    double box, float* out, int* flags, hipStream_t s);
 // pos = wrap(pos + r[id] L / N) for every particle.
 hipError_t apply_residual(float* pos, const int32_t* id, int64_t n, const float* r, int N, double box, int* flags,
                           hipStream_t s);

@@ -34,33 +34,38 @@ def run_pair(seed, n_side, box, a_list, cosmo, step, device, fine_factor=3):
 
 
 def pair_grids(coarse, fine, n_side, box, ws, device):
-    """Feature grid (coarse displacement from the lattice) and target grid (fine - coarse), FP32 [N^3][3] each."""
+    """Input grid (coarse displacement from the lattice and Psi1, FP32 [N^3][6]) and target grid (fine - coarse,
+    FP32 [N^3][3])."""
     import torch
     geom = lpc.geometry(n_side, n_side, box)
-    feat = torch.empty((n_side**3, 3), dtype=torch.float32, device=device)
-    target = torch.empty_like(feat)
-    lpc.lpc_net_features(geom, coarse.pos, coarse.id, feat, ws)
+    feat = torch.empty((n_side**3, lpc.NET_INPUT_CHANNELS), dtype=torch.float32, device=device)
+    target = torch.empty((n_side**3, 3), dtype=torch.float32, device=device)
+    lpc.lpc_net_features(geom, coarse.pos, coarse.id, feat, ws, psi1=coarse.psi1)
     lpc.lpc_net_features(geom, fine.pos, fine.id, target, ws, ref_pos=coarse.pos)
     return feat, target
 
 
 def symmetry(grid, n_side, k):
-    """The k-th (0..47) symmetry of the cube applied to a vector field [N^3][3]: an axis permutation with sign flips,
-    acting on both the grid positions and the vector components (the equations of motion are invariant under it)."""
+    """The k-th (0..47) symmetry of the cube applied to a field of 3-vectors [N^3][3 m] (m vectors per site): an axis
+    permutation with sign flips, acting on both the grid positions and every vector's components (the equations of
+    motion are invariant under it)."""
     import torch
     perms = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
     perm, flips = perms[k // 8], k % 8
-    g = grid.reshape(n_side, n_side, n_side, 3).permute(*perm, 3)[..., list(perm)]
+    c = grid.shape[1]
+    comp = [3 * (j // 3) + perm[j % 3] for j in range(c)]
+    g = grid.reshape(n_side, n_side, n_side, c).permute(*perm, 3)[..., comp]
     for ax in range(3):
         if flips >> ax & 1:
             # reflection x -> -x of a periodic, cell-centred lattice maps site i to N - 1 - i
             g = torch.flip(g, dims=(ax,))
-            g[..., ax] = -g[..., ax]
-    return g.reshape(-1, 3).contiguous()
+            g[..., ax::3] = -g[..., ax::3]
+    return g.reshape(-1, c).contiguous()
 
 
-def train(samples, n_side, epochs, lr, seed=1, device="cuda", augment=True, log=None):
-    """Adam on (feature, target) grid pairs; returns (params on device, per-epoch mean losses)."""
+def train(samples, n_side, epochs, lr, seed=1, device="cuda", augment=True, lr_final=None, log=None):
+    """Adam on (feature, target) grid pairs, with the learning rate decaying from lr to lr_final (cosine) when
+    lr_final is given; returns (params on device, per-epoch mean losses)."""
     import torch
     params = torch.from_numpy(lpc.lpc_net_init(seed)).to(device)
     m = torch.zeros_like(params)
@@ -79,8 +84,12 @@ def train(samples, n_side, epochs, lr, seed=1, device="cuda", augment=True, log=
                 k = int(rng.integers(48))
                 feat, target = symmetry(feat, n_side, k), symmetry(target, n_side, k)
             t += 1
+            rate = lr
+            if lr_final is not None:
+                frac = (t - 1) / max(1, epochs * len(samples) - 1)
+                rate = lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * frac))
             losses.append(lpc.lpc_net_loss_grad(n_side, params, feat, target, grad, ws))
-            lpc.lpc_net_adam(params, m, v, grad, t, lr)
+            lpc.lpc_net_adam(params, m, v, grad, t, rate)
         history.append(float(np.mean(losses)))
         if log:
             log(f"epoch {ep}: mean loss {history[-1]:.4e}")
@@ -97,6 +106,13 @@ def validation_loss(params, samples, n_side, device="cuda"):
         net.append(lpc.lpc_net_loss_grad(n_side, params, feat, target, grad, ws))
         zero.append(float(torch.mean(target.double() ** 2)))
     return float(np.mean(net)), float(np.mean(zero))
+
+
+def power_spectrum(pos, n, box, device, nm_est=512, k_max=1.0, n_bins=100):
+    """Binned P(k) of particles on an nm_est^3 estimator mesh (lpc_power_spectrum)."""
+    g = lpc.geometry(0, nm_est, box)
+    ws = lpc.workspace(g, lpc.LPC_OP_POWER_SPECTRUM, device, n_particles=n)
+    return lpc.lpc_power_spectrum(g, pos, k_max, n_bins, ws)
 
 
 def timed(fn):

@@ -70,7 +70,7 @@ def _load():
         "lpc_net_param_count": (i64, []),
         "lpc_net_init": (i32, [P(ctypes.c_float), ctypes.c_uint64]),
         "lpc_net_workspace_bytes": (sz, [i32]),
-        "lpc_net_features": (i32, [P(Geometry), vp, vp, i64, vp, vp, vp, sz, vp]),
+        "lpc_net_features": (i32, [P(Geometry), vp, vp, i64, vp, vp, vp, vp, sz, vp]),
         "lpc_net_forward": (i32, [i32, vp, vp, vp, vp, sz, vp]),
         "lpc_net_loss_grad": (i32, [i32, vp, vp, vp, vp, P(dbl), vp, sz, vp]),
         "lpc_net_adam": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, vp]),
@@ -291,9 +291,13 @@ def net_workspace(n_side, device="cuda"):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def lpc_net_features(geom, pos, ids, out, ws, ref_pos=None, stream=None):
-    _check(LIB.lpc_net_features(ctypes.byref(geom), _ptr(pos), _ptr(ids), int(pos.shape[1]), _ptr(ref_pos), _ptr(out),
-                                _ptr(ws), ws.numel(), _stream(stream)))
+NET_INPUT_CHANNELS = 6
+
+
+def lpc_net_features(geom, pos, ids, out, ws, ref_pos=None, psi1=None, stream=None):
+    """Input grid [N^3][6] (psi1 given) or target grid [N^3][3] (ref_pos given) into the device tensor out."""
+    _check(LIB.lpc_net_features(ctypes.byref(geom), _ptr(pos), _ptr(ids), int(pos.shape[1]), _ptr(ref_pos), _ptr(psi1),
+                                _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def lpc_net_forward(n_side, params, feat, out, ws, stream=None):

@@ -16,17 +16,19 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 
 
 def grid_to_cf(a, D):
-    """GPU channels-last [V][3] -> oracle channels-first (3, D, D, D)."""
-    return np.asarray(a, dtype=np.float64).reshape(D, D, D, 3).transpose(3, 0, 1, 2)
+    """GPU channels-last [V][C] -> oracle channels-first (C, D, D, D)."""
+    a = np.asarray(a, dtype=np.float64)
+    return a.reshape(D, D, D, a.shape[-1]).transpose(3, 0, 1, 2)
 
 
 def cf_to_grid(a):
-    return np.ascontiguousarray(np.asarray(a).transpose(1, 2, 3, 0).reshape(-1, 3)).astype(np.float32)
+    a = np.asarray(a)
+    return np.ascontiguousarray(a.transpose(1, 2, 3, 0).reshape(-1, a.shape[0])).astype(np.float32)
 
 
 def sample(D, seed):
     rng = np.random.default_rng(seed)
-    feat = (0.5 * rng.standard_normal((3, D, D, D))).astype(np.float32)
+    feat = (0.5 * rng.standard_normal((6, D, D, D))).astype(np.float32)
     target = (0.1 * rng.standard_normal((3, D, D, D))).astype(np.float32)
     return feat, target
 
@@ -40,7 +42,7 @@ def test_forward_matches_oracle(D):
     feat, _ = sample(D, 1)
     ws = lpc.net_workspace(D)
     out = torch.empty((D**3, 3), dtype=torch.float32, device="cuda")
-    lpc.lpc_net_forward(D, to_dev(params), to_dev(cf_to_grid(feat)), out, ws)
+    lpc.lpc_net_forward(D, to_dev(params), to_dev(cf_to_grid(feat)), out, ws)  # feat: 6 channels
     ref, _ = onet.forward(params.astype(np.float64), feat.astype(np.float64))
     err = rel_l2(grid_to_cf(to_np(out), D), ref)
     say(f"  rel L2 = {err:.3e}")
@@ -116,13 +118,18 @@ def test_features_and_apply():
     tgt = torch.empty_like(feat)
     lpc.lpc_net_features(geom, to_dev(pos_p), to_dev(ids_p), tgt, ws, ref_pos=to_dev(ref))
     assert np.abs(grid_to_cf(to_np(tgt), N) - onet.displacement_grid(pos_p, ids_p, N, box, ref=ref)).max() < 1e-5
-    # apply = features -> forward -> pos += r dp
+    # the 6-channel input grid: displacement and Psi1 / dp
+    psi1 = rng.normal(0, 2.0 * dp, pos_p.shape).astype(np.float32)
+    inp = torch.empty((N**3, 6), dtype=torch.float32, device="cuda")
+    lpc.lpc_net_features(geom, to_dev(pos_p), to_dev(ids_p), inp, ws, psi1=to_dev(psi1))
+    assert np.abs(grid_to_cf(to_np(inp), N) - onet.input_grid(pos_p, psi1, ids_p, N, box)).max() < 1e-5
+    # apply = input grid -> forward -> pos += r dp
     params = lpc.lpc_net_init(5)
     params[onet.layer_slices()["out"][0]] *= 10.0
     pd = to_dev(params)
     out = torch.empty_like(feat)
-    lpc.lpc_net_forward(N, pd, feat, out, ws)
-    ps = lpc.ParticleSet(to_dev(pos_p), None, None, None, to_dev(ids_p))
+    lpc.lpc_net_forward(N, pd, inp, out, ws)
+    ps = lpc.ParticleSet(to_dev(pos_p), None, to_dev(psi1), None, to_dev(ids_p))
     lpc.lpc_net_apply(geom, pd, ps, ws)
     r = to_np(out)[ids_p].T
     expect = (pos_p.astype(np.float64) + r * dp) % box
@@ -141,7 +148,7 @@ def test_training_reduces_loss():
     say("net: training on one sample")
     D = 16
     feat, _ = sample(D, 6)
-    target = (0.3 * np.tanh(feat) - 0.1 * np.roll(feat, 1, axis=1)).astype(np.float32)
+    target = (0.3 * np.tanh(feat[:3]) - 0.1 * np.roll(feat[3:], 1, axis=1)).astype(np.float32)
     params = to_dev(lpc.lpc_net_init(9))
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)

@@ -19,7 +19,7 @@ def rand(seed, *shape):
 
 def test_param_count_and_layout():
     # 3-level U-Net of the header: 16/32/64 channels
-    want = (16 * 27 * 3 + 16) + (16 * 27 * 16 + 16) + (32 * 8 * 16 + 32) + (32 * 27 * 32 + 32) + (64 * 8 * 32 + 64) \
+    want = (16 * 27 * 6 + 16) + (16 * 27 * 16 + 16) + (32 * 8 * 16 + 32) + (32 * 27 * 32 + 32) + (64 * 8 * 32 + 64) \
         + (64 * 27 * 64 + 64) + (32 * 8 * 64 + 32) + (32 * 27 * 64 + 32) + (16 * 8 * 32 + 16) + (16 * 27 * 32 + 16) \
         + (3 * 27 * 16 + 3)
     assert net.param_count() == want
@@ -79,7 +79,7 @@ def test_network_gradient_matches_finite_differences():
         fan_in = net.TAPS[kind] * cin
         params[ws] = rng.uniform(-1, 1, ws.stop - ws.start) * np.sqrt(6.0 / fan_in)
         params[bs] = rng.uniform(-0.1, 0.1, cout)
-    x = rand(6, 3, 8, 8, 8)
+    x = rand(6, 6, 8, 8, 8)
     target = rand(7, 3, 8, 8, 8) * 0.5
     L, g = net.loss_and_grad(params, x, target)
     assert np.isclose(L, net.loss(net.forward(params, x)[0], target))
@@ -119,6 +119,10 @@ def test_displacement_grid_features():
     assert np.allclose(net.displacement_grid(pos[:, perm], ids[perm], n, box), g)
     ref = (pos + 0.1 * dp) % box
     assert np.allclose(net.displacement_grid(pos, ids, n, box, ref=ref), -0.1)
+    psi1 = np.stack([np.full(n**3, 2.0 * dp), np.zeros(n**3), -0.5 * dp * np.ones(n**3)])
+    inp = net.input_grid(pos[:, perm], psi1[:, perm], ids[perm], n, box)
+    assert inp.shape == (6, n, n, n)
+    assert np.allclose(inp[:3], g) and np.allclose(inp[3], 2.0) and np.allclose(inp[5], -0.5)
 
 
 def test_bispectrum_fft_estimator_equals_brute_force():
