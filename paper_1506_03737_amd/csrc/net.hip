@@ -13,6 +13,15 @@ namespace net {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Weights read by every thread of a wave at the same address go through the constant address space, so the
+// compiler loads them with scalar instructions. (The host pass of hipcc also parses kernel bodies; there the
+// qualifier is dropped.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define LPC_NET_CONST __attribute__((address_space(4)))
+#else
+#define LPC_NET_CONST
+#endif
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNT = 256;
@@ -25,66 +34,86 @@ __device__ __forceinline__ float f(bf16 v) { return static_cast<float>(v); }
 unsigned blocks_for(int64_t count, int per = kNT) { return static_cast<unsigned>((count + per - 1) / per); }
 
 // ---------------------------------------------------------------------------------------------------------------
-// 3^3 convolution, implicit GEMM on v_mfma_f32_16x16x32_bf16. A wave owns 64 consecutive output voxels (4 row
-// tiles of 16) and all 16 NB output channels; a workgroup is 4 waves. Operand layout of the instruction: lane l
-// supplies row (l % 16) of A and column (l % 16) of B with k = 8 (l / 16) + [0, 8), and receives column (l % 16),
-// rows 4 (l / 16) + [0, 4) of the 16 x 16 result.
+// 3^3 convolution, implicit GEMM on v_mfma_f32_16x16x32_bf16. Operand layout of the instruction: lane l supplies row
+// (l % 16) of A and column (l % 16) of B with k = 8 (l / 16) + [0, 8), and receives column (l % 16), rows
+// 4 (l / 16) + [0, 4) of the 16 x 16 result.
+// A workgroup (4 waves) computes a 4 x 4 x 16 tile of output voxels: wave w takes x = x0 + w, its 4 row tiles are
+// y = y0 + mt, and a row tile's 16 rows are z = z0 + [0, 16). The input halo of the tile (6 x 6 x 18 voxels, periodic)
+// is staged in LDS one chunk of CC = min(CIN, 32) channels at a time, so every K step reads its A operands from LDS
+// at a fixed offset per tap: no wrap-around arithmetic in the inner loop. B (weights) comes from global memory
+// (a few hundred KB at most, cache resident).
+constexpr int kHX = 6, kHY = 6, kHZ = 18, kHalo = kHX * kHY * kHZ;
+
+__device__ __forceinline__ int modi(int a, int D) {
+  const int m = a % D;
+  return m < 0 ? m + D : m;
+}
+
 template <int CIN, int NB>
 __global__ __launch_bounds__(kNT) void k_conv3(View in, const bf16* __restrict__ w, int kpad,
                                                const float* __restrict__ bias, int act, View out,
                                                float* __restrict__ outf, int cout, int D) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int V = D * D * D;
-  const int vw = (blockIdx.x * 4 + wave) * 64;
-  if (vw >= V) return;
+  constexpr int CC = CIN < 32 ? CIN : 32;   // channels per staged chunk
+  constexpr int NCH = CIN / CC;             // chunks
+  constexpr int VS = CC + 8;                // LDS voxel stride (bf16), padded against bank conflicts
+  constexpr int TPS = 32 / CC;              // taps per K step (4, 2 or 1)
+  constexpr int NS = (27 + TPS - 1) / TPS;  // K steps per chunk
+  __shared__ bf16 halo[kHalo * VS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
   const int r = lane & 15, g = lane >> 4;
-  int vx[4], vy[4], vz[4];
-  bool ok[4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    const int v = vw + mt * 16 + r;
-    ok[mt] = v < V;
-    const int vv = ok[mt] ? v : 0;
-    vx[mt] = vv / (D * D);
-    vy[mt] = (vv / D) % D;
-    vz[mt] = vv % D;
-  }
+  const int ntxy = (D + 3) / 4, ntz = (D + 15) / 16;
+  const int bz = blockIdx.x % ntz, by = (blockIdx.x / ntz) % ntxy, bx = blockIdx.x / (ntz * ntxy);
+  const int x0 = bx * 4, y0 = by * 4, z0 = bz * 16;
+  const bool wave_on = (x0 + wave) < D;
   f32x4 acc[4][NB];
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mt][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const bf16* inb = in.p + in.off;
-  // K steps of 32 (27 taps x CIN channels, padded): a compile-time count, unrolled so that the loads of several
-  // steps are in flight before their MFMAs need them (the kernel is latency-bound otherwise)
-  constexpr int NK = (27 * CIN + 31) / 32;
-  (void)kpad;
-#pragma unroll 4
-  for (int s = 0; s < NK; ++s) {
-    const int k0 = s * 32 + g * 8;
-    const int tap = k0 / CIN, ci = k0 - tap * CIN;
-    const bool tap_ok = tap < 27;
-    const int dx = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dz = tap % 3 - 1;
-    bf16x8 A[4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      bf16x8 a;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) a[j] = static_cast<bf16>(0.f);
-      if (tap_ok && ok[mt]) {
-        const int x = wrapi(vx[mt] + dx, D), y = wrapi(vy[mt] + dy, D), z = wrapi(vz[mt] + dz, D);
-        a = *reinterpret_cast<const bf16x8*>(inb + static_cast<size_t>((x * D + y) * D + z) * in.ld + ci);
-      }
-      A[mt] = a;
+  // this lane's tap slot within a K step and its channel offset within the chunk
+  const int tsub = g / (CC / 8), cio = 8 * (g % (CC / 8));
+  for (int ch = 0; ch < NCH; ++ch) {
+    __syncthreads();  // the previous chunk's reads are done
+    for (int e = tid; e < kHalo * (CC / 8); e += kNT) {
+      const int hv = e / (CC / 8), grp = e % (CC / 8);
+      const int hx = hv / (kHY * kHZ), hy = (hv / kHZ) % kHY, hz = hv % kHZ;
+      const int gx = modi(x0 - 1 + hx, D), gy = modi(y0 - 1 + hy, D), gz = modi(z0 - 1 + hz, D);
+      const bf16* src = in.p + static_cast<size_t>((gx * D + gy) * D + gz) * in.ld + in.off + ch * CC + grp * 8;
+      *reinterpret_cast<bf16x8*>(halo + hv * VS + grp * 8) = *reinterpret_cast<const bf16x8*>(src);
     }
+    __syncthreads();
+    if (wave_on) {
+#pragma unroll 3
+      for (int s = 0; s < NS; ++s) {
+        const int tap = s * TPS + tsub;
+        const bool tap_ok = tap < 27;
+        const int tt = tap_ok ? tap : 26;
+        const int tx = tt / 9, ty = (tt / 3) % 3, tz = tt % 3;
+        const bf16* abase = halo + ((wave + tx) * kHY * kHZ + ty * kHZ + r + tz) * VS + cio;
+        bf16x8 A[4];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const bf16x8 B = *reinterpret_cast<const bf16x8*>(w + static_cast<size_t>(nb * 16 + r) * (NK * 32) + k0);
+        for (int mt = 0; mt < 4; ++mt) {
+          bf16x8 a = *reinterpret_cast<const bf16x8*>(abase + mt * kHZ * VS);
+          if (!tap_ok) {
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B, acc[mt][nb], 0, 0, 0);
+            for (int j = 0; j < 8; ++j) a[j] = static_cast<bf16>(0.f);
+          }
+          A[mt] = a;
+        }
+        // k of this lane's 8 values: tap * CIN + ch * CC + cio (a padding tap points into the zero tail of the row)
+        const int k0 = tap * CIN + ch * CC + cio;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bf16x8 B = *reinterpret_cast<const bf16x8*>(w + static_cast<size_t>(nb * 16 + r) * kpad + k0);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+            acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B, acc[mt][nb], 0, 0, 0);
+        }
+      }
     }
   }
+  if (!wave_on) return;
+  const int x = x0 + wave;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int co = nb * 16 + r;
@@ -92,55 +121,97 @@ __global__ __launch_bounds__(kNT) void k_conv3(View in, const bf16* __restrict__
     const float b = bias ? bias[co] : 0.f;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
+      const int y = y0 + mt;
+      if (y >= D) continue;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int v = vw + mt * 16 + g * 4 + j;
-        if (v >= V) continue;
+        const int z = z0 + g * 4 + j;
+        if (z >= D) continue;
+        const size_t v = static_cast<size_t>((x * D + y) * D + z);
         const float val = acc[mt][nb][j] + b;
         if (outf)
-          outf[static_cast<size_t>(v) * cout + co] = val;
+          outf[v * cout + co] = val;
         else
-          out.p[static_cast<size_t>(v) * out.ld + out.off + co] = static_cast<bf16>(act ? leaky(val) : val);
+          out.p[v * out.ld + out.off + co] = static_cast<bf16>(act ? leaky(val) : val);
       }
     }
   }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// 2^3 down / up layers and their data gradients (one thread per output element).
-__global__ __launch_bounds__(kNT) void k_down2(View x, int cin, const float* __restrict__ W,
-                                               const float* __restrict__ b, int cout, View out, int D) {
-  const int Dc = D / 2;
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (idx >= static_cast<int64_t>(Dc) * Dc * Dc * cout) return;
-  const int o = static_cast<int>(idx % cout);
-  const int y = static_cast<int>(idx / cout);
-  const int yx = y / (Dc * Dc), yy = (y / Dc) % Dc, yz = y % Dc;
-  float acc = b[o];
-  for (int t = 0; t < 8; ++t) {
-    const int xv = ((2 * yx + (t >> 2)) * D + 2 * yy + ((t >> 1) & 1)) * D + 2 * yz + (t & 1);
-    const bf16* xp = x.p + static_cast<size_t>(xv) * x.ld + x.off;
-    const float* wp = W + (o * 8 + t) * cin;
-    for (int i = 0; i < cin; ++i) acc += wp[i] * f(xp[i]);
+// 2^3 down / up layers: one thread per coarse voxel computes every output channel, reading its input rows as 16-byte
+// vectors; the weights are read through the constant address space (wave-uniform addresses: scalar loads).
+template <int CIN>
+__device__ __forceinline__ void load_row(const bf16* p, float* v) {
+#pragma unroll
+  for (int q = 0; q < CIN / 8; ++q) {
+    const bf16x8 u = *reinterpret_cast<const bf16x8*>(p + 8 * q);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[8 * q + j] = f(u[j]);
   }
-  out.p[static_cast<size_t>(y) * out.ld + out.off + o] = static_cast<bf16>(leaky(acc));
 }
 
-__global__ __launch_bounds__(kNT) void k_up2(View x, int cin, const float* __restrict__ W,
-                                             const float* __restrict__ b, int cout, View out, int D) {
+template <int COUT>
+__device__ __forceinline__ void store_row(bf16* p, const float* acc) {
+#pragma unroll
+  for (int q = 0; q < COUT / 8; ++q) {
+    bf16x8 u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) u[j] = static_cast<bf16>(leaky(acc[8 * q + j]));
+    *reinterpret_cast<bf16x8*>(p + 8 * q) = u;
+  }
+}
+
+// out[y][o] = leaky(b[o] + sum_{t, i} W[o][t][i] x[2y + t][i])   (x on D^3, y on (D/2)^3)
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__ Wg, const float* __restrict__ bg,
+                                               View out, int D) {
+  const int Dc = D / 2;
+  const int y = blockIdx.x * kNT + threadIdx.x;
+  if (y >= Dc * Dc * Dc) return;
+  const LPC_NET_CONST float* W = (const LPC_NET_CONST float*)(Wg);
+  const LPC_NET_CONST float* b = (const LPC_NET_CONST float*)(bg);
+  const int yx = y / (Dc * Dc), yy = (y / Dc) % Dc, yz = y % Dc;
+  float acc[COUT];
+#pragma unroll
+  for (int o = 0; o < COUT; ++o) acc[o] = b[o];
+#pragma unroll 1
+  for (int t = 0; t < 8; ++t) {
+    const int xv = ((2 * yx + (t >> 2)) * D + 2 * yy + ((t >> 1) & 1)) * D + 2 * yz + (t & 1);
+    float xr[CIN];
+    load_row<CIN>(x.p + static_cast<size_t>(xv) * x.ld + x.off, xr);
+#pragma unroll
+    for (int i = 0; i < CIN; ++i)
+#pragma unroll
+      for (int o = 0; o < COUT; ++o) acc[o] += W[(o * 8 + t) * CIN + i] * xr[i];
+  }
+  store_row<COUT>(out.p + static_cast<size_t>(y) * out.ld + out.off, acc);
+}
+
+// out[2y + t][o] = leaky(b[o] + sum_i W[o][t][i] x[y][i])   (x on D^3, out on (2D)^3)
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ Wg, const float* __restrict__ bg,
+                                             View out, int D) {
+  const int y = blockIdx.x * kNT + threadIdx.x;
+  if (y >= D * D * D) return;
+  const LPC_NET_CONST float* W = (const LPC_NET_CONST float*)(Wg);
+  const LPC_NET_CONST float* b = (const LPC_NET_CONST float*)(bg);
+  const int yx = y / (D * D), yy = (y / D) % D, yz = y % D;
   const int Df = 2 * D;
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (idx >= static_cast<int64_t>(Df) * Df * Df * cout) return;
-  const int o = static_cast<int>(idx % cout);
-  const int q = static_cast<int>(idx / cout);
-  const int qx = q / (Df * Df), qy = (q / Df) % Df, qz = q % Df;
-  const int t = ((qx & 1) * 2 + (qy & 1)) * 2 + (qz & 1);
-  const int y = ((qx >> 1) * D + (qy >> 1)) * D + (qz >> 1);
-  const bf16* xp = x.p + static_cast<size_t>(y) * x.ld + x.off;
-  const float* wp = W + (o * 8 + t) * cin;
-  float acc = b[o];
-  for (int i = 0; i < cin; ++i) acc += wp[i] * f(xp[i]);
-  out.p[static_cast<size_t>(q) * out.ld + out.off + o] = static_cast<bf16>(leaky(acc));
+  float xr[CIN];
+  load_row<CIN>(x.p + static_cast<size_t>(y) * x.ld + x.off, xr);
+#pragma unroll 1
+  for (int t = 0; t < 8; ++t) {
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) acc[o] = b[o];
+#pragma unroll
+    for (int i = 0; i < CIN; ++i)
+#pragma unroll
+      for (int o = 0; o < COUT; ++o) acc[o] += W[(o * 8 + t) * CIN + i] * xr[i];
+    const int q = ((2 * yx + (t >> 2)) * Df + 2 * yy + ((t >> 1) & 1)) * Df + 2 * yz + (t & 1);
+    store_row<COUT>(out.p + static_cast<size_t>(q) * out.ld + out.off, acc);
+  }
 }
 
 // dx[2y + t][i] (+)= sum_o W[o][t][i] dz[y][o]   (x on D^3)
@@ -211,6 +282,7 @@ __global__ __launch_bounds__(kNT) void k_wgrad(int kind, View x, int cin, int ci
                                                int ntap, int nbase, float* __restrict__ partial) {
   __shared__ float sdz[kTV * kMaxC];
   __shared__ float sx[kTV * kMaxC];
+  __shared__ int sxv[kTV], szv[kTV];
   const int chunk = blockIdx.x, tap = blockIdx.y, nchunk = gridDim.x;
   const int tid = threadIdx.x;
   const int ncb = cin / CI;
@@ -226,15 +298,29 @@ __global__ __launch_bounds__(kNT) void k_wgrad(int kind, View x, int cin, int ci
   const int64_t per = (static_cast<int64_t>(nbase) + nchunk - 1) / nchunk;
   const int b0 = static_cast<int>(per * chunk);
   const int b1 = static_cast<int>(std::min<int64_t>(nbase, per * (chunk + 1)));
+  const int gz = (cout + 7) / 8, gx = cin / 8;  // 16-byte groups per voxel (dz views are zero-padded to 8 channels)
   for (int t0 = b0; t0 < b1; t0 += kTV) {
     const int nv = min(kTV, b1 - t0);
     __syncthreads();
-    for (int e = tid; e < nv * kMaxC; e += kNT) {
-      const int v = e / kMaxC, c = e % kMaxC;
+    if (tid < nv) {
       int xv, zv;
-      wgrad_voxels(kind, t0 + v, tap, D, &xv, &zv);
-      if (c < cout) sdz[v * kMaxC + c] = f(dz.p[static_cast<size_t>(zv) * dz.ld + dz.off + c]);
-      if (c < cin) sx[v * kMaxC + c] = f(x.p[static_cast<size_t>(xv) * x.ld + x.off + c]);
+      wgrad_voxels(kind, t0 + tid, tap, D, &xv, &zv);
+      sxv[tid] = xv;
+      szv[tid] = zv;
+    }
+    __syncthreads();
+    for (int e = tid; e < nv * (gz + gx); e += kNT) {
+      const int v = e / (gz + gx), q = e % (gz + gx);
+      if (q < gz) {
+        const bf16x8 u = *reinterpret_cast<const bf16x8*>(dz.p + static_cast<size_t>(szv[v]) * dz.ld + dz.off + 8 * q);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sdz[v * kMaxC + 8 * q + j] = f(u[j]);
+      } else {
+        const int qq = q - gz;
+        const bf16x8 u = *reinterpret_cast<const bf16x8*>(x.p + static_cast<size_t>(sxv[v]) * x.ld + x.off + 8 * qq);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sx[v * kMaxC + 8 * qq + j] = f(u[j]);
+      }
     }
     __syncthreads();
     if (active) {
@@ -411,8 +497,7 @@ __global__ __launch_bounds__(kNT) void k_apply(float* __restrict__ pos, const in
 
 hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float* bias, int leaky_act, View out,
                  float* outf, int cout, int D, hipStream_t s) {
-  const int V = D * D * D;
-  const unsigned grid = blocks_for(V, kNT);
+  const unsigned grid = static_cast<unsigned>(((D + 3) / 4) * ((D + 3) / 4) * ((D + 15) / 16));
 #define LPC_CONV(CI, NBV) k_conv3<CI, NBV><<<grid, kNT, 0, s>>>(in, w, kpad, bias, leaky_act, out, outf, cout, D)
   if (cin == 8 && nb == 1) LPC_CONV(8, 1);
   else if (cin == 8 && nb == 2) LPC_CONV(8, 2);
@@ -432,14 +517,18 @@ hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float*
 }
 
 hipError_t down2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
-  const int64_t n = static_cast<int64_t>(D / 2) * (D / 2) * (D / 2) * cout;
-  k_down2<<<blocks_for(n), kNT, 0, s>>>(x, cin, W, b, cout, out, D);
+  const unsigned grid = blocks_for(static_cast<int64_t>(D / 2) * (D / 2) * (D / 2));
+  if (cin == 16 && cout == 32) k_down2<16, 32><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  else if (cin == 32 && cout == 64) k_down2<32, 64><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t up2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
-  const int64_t n = static_cast<int64_t>(8) * D * D * D * cout;
-  k_up2<<<blocks_for(n), kNT, 0, s>>>(x, cin, W, b, cout, out, D);
+  const unsigned grid = blocks_for(static_cast<int64_t>(D) * D * D);
+  if (cin == 64 && cout == 32) k_up2<64, 32><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  else if (cin == 32 && cout == 16) k_up2<32, 16><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
