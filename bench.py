@@ -15,8 +15,11 @@ Also reported: the dominant kernel's achieved HBM bandwidth from HIP events reco
 graph; aggregate particle-steps/s, in "batched"), and the learned form (a coarse Nm = N run plus the trained
 correction network against the fine Nm = 3N run, with its P(k) error, in "learned").
 
+Before the clock starts, the FFT tile widths of every mesh size measured here are autotuned (paper_1506_03737_amd/
+autotune.py; --no-tune keeps the built-in widths); the widths used are reported in config.fft_tiling.
+
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--workload single|small|large] [--no-cpu] [--no-batched]
-                      [--no-learned]
+                      [--no-learned] [--no-tune] [--tiling-cache PATH]
 """
 import argparse
 import json
@@ -32,9 +35,10 @@ METRIC = "particle-steps/s (COLA PM step), plain vs batched/learned at P(k) err 
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes (read scaled by 2.0, write by 1.0, from
-# a 1 GiB copy), by (stage, mesh size); profiles/force_path_768_hbm_traffic.md. Must be re-measured (or removed) when
-# the kernel changes.
-MEASURED_TRAFFIC = {("fft x + poisson", 768): 7.345e9, ("fft y inv", 768): 11.137e9, ("fft z c2r", 768): 10.985e9}
+# a 1 GiB copy), by (stage, mesh size, tile width of the stage); profiles/force_path_768_hbm_traffic.md. Must be
+# re-measured (or removed) when the kernel changes.
+MEASURED_TRAFFIC = {("fft x + poisson", 768, 8): 7.345e9, ("fft y inv", 768, 8): 11.137e9,
+                    ("fft z c2r", 768, 4): 10.985e9}
 
 
 def stage_bytes(stage, n_part, nm, ncomp_y=3):
@@ -223,6 +227,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-box batched measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT tile widths (no autotuning)")
+    ap.add_argument("--tiling-cache", default=None,
+                    help="JSON cache of tuned FFT tile widths: applied if present, written with new results")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a known-size kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -234,11 +241,21 @@ def main():
     import torch
 
     import synth
-    from paper_1506_03737_amd import lpc
+    from paper_1506_03737_amd import autotune, lpc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.WORKLOADS[args.workload]
     n_side, nm, box = w["n_side"], w["n_mesh"], w["box"]
+    # FFT tile widths: tuned (untimed) for the single-box mesh and the batched form's meshes
+    tune_sizes = [nm]
+    if not args.no_batched and args.workload == "single":
+        tune_sizes += sorted({b["n_mesh"] for b in synth.batch_workload()})
+    t_tune = time.perf_counter()
+    if not args.no_tune:
+        autotune.tune_sizes(tune_sizes, "cuda", path=args.tiling_cache,
+                            log=lambda m: print(m, file=sys.stderr, flush=True))
+    t_tune = time.perf_counter() - t_tune
+    tilings = {str(s): lpc.lpc_fft_tiling_get(s) for s in tune_sizes}
     n = n_side**3
     dev = torch.device("cuda:0")
     geom = lpc.geometry(n_side, nm, box)
@@ -284,9 +301,10 @@ def main():
     dl, dms = stats[dom]
     dbytes = stage_bytes(dom, n, nm)
     achieved = dbytes / (dms / dl * 1e-3) / 1e9
+    width = next((tilings[str(nm)][f] for f, (st, _) in autotune.FIELDS.items() if dom in st), None)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": MEASURED_TRAFFIC.get((dom, nm)),
-                "algorithmic_bytes_per_launch": dbytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": MEASURED_TRAFFIC.get((dom, nm, width)),
+                "algorithmic_bytes_per_launch": dbytes, "tile_width": width}
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -294,7 +312,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n_side}^3 particles, {nm}^3 mesh, {box:g} Mpc/h, 2LPT ICs at z=9, "
                                f"modified COLA nLPT=-2.5, plain form", "n_side": n_side, "n_mesh": nm, "box": box,
-                   "form": "plain", "force_evaluations": args.steps + 1},
+                   "form": "plain", "force_evaluations": args.steps + 1, "fft_tiling": tilings,
+                   "fft_tiling_source": "built-in" if args.no_tune else "autotuned",
+                   "autotune_s": round(t_tune, 2)},
         "roofline": roofline,
         "stages": stages,
     }

@@ -189,6 +189,34 @@ lpc_status lpc_fft_c2r(int32_t n, float* in_complex, float* out, void* ws, size_
 /* Row pitch, in complex values, of the half-spectrum layout used by lpc_fft_r2c / lpc_fft_c2r. */
 int32_t lpc_fft_pitch(int32_t n);
 
+/* FFT tile shape of one mesh size (measurement and tuning plumbing; the transforms' results do not depend on it).
+ * Each pass of a 3-D transform stages a tile of independent 1-D transforms through LDS; these are the tile widths.
+ *   z_rows:       rows per tile of the forward z (r2c) pass and of single-spectrum inverse z passes: 8, 16 or 32
+ *   axis_cols:    columns per tile of the strided y and x passes (forward and inverse): 8, 16 or 32
+ *   poisson_cols: columns per tile of the force path's fused x + Poisson pass: 4, 8 or 16
+ *   c2r_rows:     rows per tile of the force path's three-component inverse z pass: 4, 8 or 16
+ * A width fits mesh size n when its tile's loads and FFT stages fit one 512-thread workgroup and its LDS is at most
+ * 160 KiB. A batched call uses, per pass, the smallest width over its boxes. */
+typedef struct {
+  int32_t z_rows;
+  int32_t axis_cols;
+  int32_t poisson_cols;
+  int32_t c2r_rows;
+} lpc_fft_tiling;
+
+/* The built-in tiling of mesh size n (the widest widths that fit, with the fused pass at most 16 and 8 above
+ * n = 512): host only. LPC_ERR_UNSUPPORTED_SIZE for a mesh size the FFTs do not take. */
+lpc_status lpc_fft_tiling_default(int32_t n_mesh, lpc_fft_tiling* out);
+/* The tiling in effect for mesh size n: the override set by lpc_fft_tiling_set, else the built-in one. */
+lpc_status lpc_fft_tiling_get(int32_t n_mesh, lpc_fft_tiling* out);
+/* Override the tiling of mesh size n for every later call of this process (t = NULL removes the override).
+ * LPC_ERR_INVALID_ARG, with the field named in lpc_last_error(), if a width is not an instantiated one or does not
+ * fit n; nothing changes then. Process-wide state, guarded by a mutex; a recorded batched graph is re-recorded on its
+ * next call. An autotuner (paper_1506_03737_amd/autotune.py) measures the widths per mesh size and sets them here. */
+lpc_status lpc_fft_tiling_set(int32_t n_mesh, const lpc_fft_tiling* t);
+/* Remove every override. */
+lpc_status lpc_fft_tiling_reset(void);
+
 /* ---------------------------------------------------------------------------------------------------------------
  * Learned displacement correction (not in the paper: a learned stand-in for the small-scale accuracy that a finer PM
  * mesh buys, Sec. 2.4). A coarse run (Nm = N) is corrected toward a fine run (Nm = 3N) by a 3-D convolutional

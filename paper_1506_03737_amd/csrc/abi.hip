@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -250,6 +252,50 @@ lpc_status check_mesh(int nm, const char* what) {
   return LPC_OK;
 }
 
+// FFT tile widths per mesh size: the built-in rule, and overrides set through lpc_fft_tiling_set.
+lpc_fft_tiling default_tiling(int n) {
+  lpc_fft_tiling t;
+  t.z_rows = std::max(8, kern::z_rows(n, 1));
+  t.axis_cols = kern::strided_cols(n);
+  t.poisson_cols = std::min(16, kern::strided_cols(n));
+  t.c2r_rows = std::max(4, std::min(16, kern::z_rows(n, 3)));
+  return t;
+}
+
+struct TilingTable {
+  std::mutex mu;
+  std::map<int, lpc_fft_tiling> over;
+  uint64_t generation = 0;  // bumped on every change, part of the batched graph's key
+};
+TilingTable g_tiling;
+
+lpc_fft_tiling tiling_of(int n) {
+  std::lock_guard<std::mutex> lock(g_tiling.mu);
+  const auto it = g_tiling.over.find(n);
+  return it != g_tiling.over.end() ? it->second : default_tiling(n);
+}
+
+uint64_t tiling_generation() {
+  std::lock_guard<std::mutex> lock(g_tiling.mu);
+  return g_tiling.generation;
+}
+
+lpc_status check_tiling(int n, const lpc_fft_tiling& t) {
+  const struct {
+    kern::TileKind kind;
+    int w;
+    const char* name;
+  } fields[] = {{kern::TileKind::kZRows, t.z_rows, "z_rows"},
+                {kern::TileKind::kAxisCols, t.axis_cols, "axis_cols"},
+                {kern::TileKind::kPoissonCols, t.poisson_cols, "poisson_cols"},
+                {kern::TileKind::kForceC2RRows, t.c2r_rows, "c2r_rows"}};
+  for (const auto& f : fields)
+    if (!kern::tile_ok(f.kind, n, f.w))
+      return fail(LPC_ERR_INVALID_ARG, "%s = %d is not an instantiated tile width that fits mesh size %d", f.name, f.w,
+                  n);
+  return LPC_OK;
+}
+
 lpc_status check_cosmo(const lpc_cosmology* c) {
   if (!c) return fail(LPC_ERR_INVALID_ARG, "cosmology is NULL");
   if (!(c->omega_m > 0.0 && c->omega_m <= 1.0)) return fail(LPC_ERR_INVALID_ARG, "omega_m must be in (0, 1]");
@@ -361,8 +407,9 @@ kern::AxisJob axis_job(float2* base, int n, int64_t astr, int64_t ostr, int64_t 
 R2CSections add_r2c(JobPack& jp, const void* in, bool fixed, double mscale, int n, float2* out) {
   R2CSections r;
   const int pitch = kern::mesh_pitch(n);
-  r.Bz = std::max(8, kern::z_rows(n, 1));
-  r.Bax = kern::strided_cols(n);
+  const lpc_fft_tiling t = tiling_of(n);
+  r.Bz = t.z_rows;
+  r.Bax = t.axis_cols;
   r.lds_z = kern::lds_z_r2c(n, r.Bz);
   r.lds_ax = kern::lds_axis(n, r.Bax);
   kern::ZR2CJob z{};
@@ -385,8 +432,9 @@ R2CSections add_r2c(JobPack& jp, const void* in, bool fixed, double mscale, int 
 C2RSections add_c2r(JobPack& jp, float2* spec, int n, float* out, float scale) {
   C2RSections c;
   const int pitch = kern::mesh_pitch(n);
-  c.Bax = kern::strided_cols(n);
-  c.R = std::max(8, kern::z_rows(n, 1));
+  const lpc_fft_tiling t = tiling_of(n);
+  c.Bax = t.axis_cols;
+  c.R = t.z_rows;
   c.lds_ax = kern::lds_axis(n, c.Bax);
   c.lds_z = kern::lds_z_c2r(n, c.R);
   kern::AxisJob x = axis_job(spec, n, static_cast<int64_t>(n) * pitch, pitch, 0, c.Bax);
@@ -440,6 +488,7 @@ struct ForceProgram {
   Section sort_user, sort_next[2], dep[2], parts[2], frame[2], unsort[2];
   Section zr2c, yfwd, pois, yinv, zc2r;
   int Bz = 32, Bax = 32, Bp = 16, R3 = 16;
+  int Mp = 8;  // points per thread of the fused x + Poisson tiles: the largest over the boxes
   size_t lds_z = 0, lds_ax = 0, lds_p = 0, lds_c = 0;
   SortSpace ss;
   bool cola_run = false;
@@ -451,11 +500,14 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
   f.ss = ss;
   f.cola_run = cola_run;
   for (const ForceBox& b : boxes) {
-    f.Bz = std::min(f.Bz, std::max(8, kern::z_rows(b.nm, 1)));
-    f.Bax = std::min(f.Bax, kern::strided_cols(b.nm));
-    f.Bp = std::min(f.Bp, std::min(16, kern::strided_cols(b.nm)));
-    f.R3 = std::min(f.R3, std::max(4, std::min(16, kern::z_rows(b.nm, 3))));
+    // widths fit every smaller size too, so the smallest over the boxes fits all of them
+    const lpc_fft_tiling t = tiling_of(b.nm);
+    f.Bz = std::min(f.Bz, t.z_rows);
+    f.Bax = std::min(f.Bax, t.axis_cols);
+    f.Bp = std::min(f.Bp, t.poisson_cols);
+    f.R3 = std::min(f.R3, t.c2r_rows);
   }
+  for (const ForceBox& b : boxes) f.Mp = std::max(f.Mp, kern::poisson_points(b.nm, f.Bp));
   const int ncopy = cola_run ? 2 : 1;
   std::vector<kern::SortJob> su, sn[2];
   std::vector<kern::DepJob> dj[2];
@@ -581,7 +633,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     i_c.push_back((c.nrows + f.R3 - 1) / f.R3);
     f.lds_z = std::max(f.lds_z, kern::lds_z_r2c(nm, f.Bz));
     f.lds_ax = std::max(f.lds_ax, kern::lds_axis(nm, f.Bax));
-    f.lds_p = std::max(f.lds_p, kern::lds_x_poisson(nm, f.Bp));
+    f.lds_p = std::max(f.lds_p, kern::lds_x_poisson(nm, f.Bp, f.Mp));
     f.lds_c = std::max(f.lds_c, kern::lds_z_c2r(nm, 3 * f.R3));
   }
   f.sort_user = jp.add(su, i_part);
@@ -621,7 +673,7 @@ void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags,
     return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), true, f.Bz, f.lds_z, flags, s);
   });
   stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.lds_ax, s); });
-  stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.lds_p, s); });
+  stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.Mp, f.lds_p, s); });
   stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yinv), jp.table(f.yinv), true, f.Bax, f.lds_ax, s); });
   stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(f.zc2r), jp.table(f.zc2r), 3, f.R3, f.lds_c, s); });
 }
@@ -739,6 +791,40 @@ size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op, int64_t n_parti
 }
 
 int32_t lpc_fft_pitch(int32_t n) { return (n >= 2) ? kern::mesh_pitch(n) : 0; }
+
+lpc_status lpc_fft_tiling_default(int32_t n_mesh, lpc_fft_tiling* out) {
+  if (lpc_status st = check_mesh(n_mesh, "n_mesh")) return st;
+  if (!out) return fail(LPC_ERR_INVALID_ARG, "out is NULL");
+  *out = default_tiling(n_mesh);
+  return LPC_OK;
+}
+
+lpc_status lpc_fft_tiling_get(int32_t n_mesh, lpc_fft_tiling* out) {
+  if (lpc_status st = check_mesh(n_mesh, "n_mesh")) return st;
+  if (!out) return fail(LPC_ERR_INVALID_ARG, "out is NULL");
+  *out = tiling_of(n_mesh);
+  return LPC_OK;
+}
+
+lpc_status lpc_fft_tiling_set(int32_t n_mesh, const lpc_fft_tiling* t) {
+  if (lpc_status st = check_mesh(n_mesh, "n_mesh")) return st;
+  if (t)
+    if (lpc_status st = check_tiling(n_mesh, *t)) return st;
+  std::lock_guard<std::mutex> lock(g_tiling.mu);
+  if (t)
+    g_tiling.over[n_mesh] = *t;
+  else
+    g_tiling.over.erase(n_mesh);
+  ++g_tiling.generation;
+  return LPC_OK;
+}
+
+lpc_status lpc_fft_tiling_reset(void) {
+  std::lock_guard<std::mutex> lock(g_tiling.mu);
+  g_tiling.over.clear();
+  ++g_tiling.generation;
+  return LPC_OK;
+}
 
 lpc_status lpc_profile_enable(int32_t on) {
   g_prof.on = (on != 0);
@@ -964,6 +1050,8 @@ lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real,
     put(step, sizeof(*step));
     put(a_list, sizeof(double) * n_a);
     put(&ws, sizeof(ws));
+    const uint64_t tgen = tiling_generation();
+    put(&tgen, sizeof(tgen));
     if (g_graph.exec == nullptr || g_graph.key != key) {
       if (g_graph.exec) {
         check(hipGraphExecDestroy(g_graph.exec), "hipGraphExecDestroy");

@@ -270,11 +270,16 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_axis(const AxisJob* __restric
 // Fused x pass of the force: forward FFT along x of a tile of delta_hat, then for each component j
 //   g_hat_j = i k_j (-1/k^2) delta_hat / W^p / Nm^3     (zero at k = 0 and on the Nyquist plane of axis j),
 // inverse FFT along x, store. W = prod_d sinc^2(pi n_d / Nm); the 1/Nm^3 of the inverse transform is folded in.
-// The x-transformed delta_hat stays in a second LDS tile across the three components.
-template <int B>
-__global__ __launch_bounds__(kFftNT) void k_fft_x_poisson(const PoissonJob* __restrict__ jobs,
-                                                          const int* __restrict__ offs, int njob, int total) {
+// The x-transformed delta_hat is kept across the three components. Each thread owns the points of column b at rows
+// j0 + m S, at most M of them (M = n B / kFftNT rounded up to 8, 12 or 16): with M <= 12 they stay in the thread's
+// registers, so the workgroup needs one LDS tile and two workgroups fit on a CU; with M = 16 a second LDS tile holds
+// them (the registers would spill).
+template <int B, int M>
+__global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(const PoissonJob* __restrict__ jobs,
+                                                                            const int* __restrict__ offs, int njob,
+                                                                            int total) {
   constexpr int BP = B + 1, S = kFftNT / B;
+  constexpr bool kRegs = M <= 12;
   extern __shared__ float2 smem[];
   {
     const int w = blockIdx.x;
@@ -287,8 +292,8 @@ __global__ __launch_bounds__(kFftNT) void k_fft_x_poisson(const PoissonJob* __re
     const int y = t / J.ntc, ct = t - y * J.ntc;
     if (y >= n) return;  // padding item
     float2* tile = smem;
-    float2* dh = tile + n * BP;
-    float2* tw = dh + n * BP;
+    float2* dh_lds = tile + n * BP;  // used when !kRegs
+    float2* tw = tile + (kRegs ? 1 : 2) * n * BP;
     float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
     {
       fill_stage_twiddles(tw, J.pl, tid);
@@ -307,23 +312,43 @@ __global__ __launch_bounds__(kFftNT) void k_fft_x_poisson(const PoissonJob* __re
     const int64_t off = static_cast<int64_t>(y) * pitch + c0;
     load_strided<B>(tile, to_global(J.A + off), astr, n, bw, tid);
     __syncthreads();
-    fft_tile<false>(tile, tw, J.pl, B, tid);
+    fft_tile<false, M>(tile, tw, J.pl, B, tid);
 
-    // Each thread touches only its own elements (column b, rows j0 + m S) between the barriers that bracket the
-    // inverse transforms.
-    const int b = tid % B, j0 = tid / B;
+    // Each thread touches only its own points between the barriers that bracket the inverse transforms.
     const int half = nm / 2;
     const int ny = (y <= half) ? y : y - nm;
-    const int nz = c0 + b;
-    const bool col_ok = b < bw;
-    const float wyz = win[min(y, n - y)] * win[min(nz, half)];
-    const int nyz2 = ny * ny + nz * nz;
     const float kf = J.kf, inv_m3 = J.inv_m3;
     const int deconv = J.deconv;
-    for (int j = j0; j < n; j += S) dh[j * BP + b] = tile[j * BP + b];
+    float2 dh[kRegs ? M : 1];
+    {
+      const int b = tid % B, j0 = tid / B;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int j = j0 + m * S;
+        if (j < n) {
+          if (kRegs)
+            dh[kRegs ? m : 0] = tile[j * BP + b];
+          else
+            dh_lds[j * BP + b] = tile[j * BP + b];
+        }
+      }
+    }
 #pragma unroll 1
     for (int comp = 0; comp < 3; ++comp) {
-      for (int j = j0; j < n; j += S) {
+      // The thread's indices are derived anew in every pass (the empty asm hides that they repeat), so that the
+      // compiler does not hoist the component-independent addresses and factors and keep them live across the
+      // inverse transform.
+      int ltid = tid;
+      asm volatile("" : "+v"(ltid));
+      const int b = ltid % B, j0 = ltid / B;
+      const int nz = c0 + b;
+      const bool col_ok = b < bw;
+      const float wyz = win[min(y, n - y)] * win[min(nz, half)];
+      const int nyz2 = ny * ny + nz * nz;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int j = j0 + m * S;
+        if (j >= n) continue;
         const int nx = (j <= half) ? j : j - nm;
         const float k2 = kf * kf * static_cast<float>(nx * nx + nyz2);
         const int nc = (comp == 0) ? nx : (comp == 1 ? ny : nz);
@@ -333,13 +358,13 @@ __global__ __launch_bounds__(kFftNT) void k_fft_x_poisson(const PoissonJob* __re
           const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
           sc = -kf * static_cast<float>(nc) * inv_m3 / (k2 * wp);  // k_c * (-1 / (k^2 W^p Nm^3))
         }
-        const float2 d = dh[j * BP + b];
+        const float2 d = kRegs ? dh[kRegs ? m : 0] : dh_lds[j * BP + b];
         tile[j * BP + b] = make_float2(-sc * d.y, sc * d.x);  // i * sc * delta_hat
       }
       __syncthreads();
-      fft_tile<true>(tile, tw, J.pl, B, tid);
+      fft_tile<true, M>(tile, tw, J.pl, B, ltid);
       float2* dst = (comp == 0) ? J.A : (comp == 1 ? J.B : J.C);
-      store_strided<B>(tile, to_global(dst + off), astr, n, bw, tid);
+      store_strided<B>(tile, to_global(dst + off), astr, n, bw, ltid);
       __syncthreads();
     }
   }
@@ -443,9 +468,13 @@ struct Init {
     allow_big_lds(k_fft_axis<false, 8>);
     allow_big_lds(k_fft_axis<false, 16>);
     allow_big_lds(k_fft_axis<false, 32>);
-    allow_big_lds(k_fft_x_poisson<4>);
-    allow_big_lds(k_fft_x_poisson<8>);
-    allow_big_lds(k_fft_x_poisson<16>);
+    allow_big_lds(k_fft_x_poisson<4, 8>);
+    allow_big_lds(k_fft_x_poisson<8, 8>);
+    allow_big_lds(k_fft_x_poisson<8, 12>);
+    allow_big_lds(k_fft_x_poisson<8, 16>);
+    allow_big_lds(k_fft_x_poisson<16, 8>);
+    allow_big_lds(k_fft_x_poisson<16, 12>);
+    allow_big_lds(k_fft_x_poisson<16, 16>);
     allow_big_lds(k_fft_z_c2r<1, 8>);
     allow_big_lds(k_fft_z_c2r<1, 16>);
     allow_big_lds(k_fft_z_c2r<1, 32>);
@@ -465,8 +494,15 @@ unsigned item_grid(int total) { return total > 0 ? static_cast<unsigned>(total) 
 
 size_t lds_z_r2c(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n / 2) * (B + 1) + n / 2 + n / 2 + 1); }
 size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) * (B + 1) + n); }
-size_t lds_x_poisson(int n, int B) {
-  return sizeof(float2) * (2 * static_cast<size_t>(n) * (B + 1) + n) + sizeof(float) * (n / 2 + 1);
+// Points per thread of the fused x + Poisson tile, n B / kFftNT rounded up to 8, 12 or 16 (the kernel's M).
+int poisson_points(int n, int B) {
+  const long pts = (static_cast<long>(n) * B + kFftNT - 1) / kFftNT;
+  return pts <= 8 ? 8 : (pts <= 12 ? 12 : 16);
+}
+
+size_t lds_x_poisson(int n, int B, int M) {
+  const size_t tiles = M <= 12 ? 1 : 2;
+  return sizeof(float2) * (tiles * static_cast<size_t>(n) * (B + 1) + n) + sizeof(float) * (n / 2 + 1);
 }
 size_t lds_z_c2r(int n, int B) {
   return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (B + 1) + n / 2 + n / 2 + 1);
@@ -475,19 +511,48 @@ size_t lds_z_c2r(int n, int B) {
 // Columns of a strided tile: the most of 8, 16, 32 with n * B <= kTileElems (8 for n > 512).
 int strided_cols(int n) { return (n <= 256) ? 32 : (n <= 512 ? 16 : 8); }
 
-// Rows of a z-pass tile for NC interleaved spectra: the largest power of two up to 32 with
-// NC R (h + 1) <= kTileElems + kFftNT (load capacity) and NC R h <= kEPT S (NC R) (stage capacity).
+namespace {
+
+// A z-pass tile of B interleaved columns (rows times spectra) at length n: the loads cover B (h + 1) values with
+// kEPT + 1 per thread, and each of the S = kFftNT / B threads of a column takes at most kEPT points per stage.
+bool rows_fit(int n, int B) {
+  const long h = n / 2;
+  return B >= 1 && B <= kFftNT && B * (h + 1) <= kTileElems + kFftNT &&
+         h * B <= static_cast<long>(kEPT) * (kFftNT / B) * B;
+}
+
+// A strided tile of B columns at length n: n B values loaded with kEPT per thread, kEPT points per thread per stage.
+bool cols_fit(int n, int B) {
+  return B >= 1 && B <= kFftNT && static_cast<long>(n) * B <= static_cast<long>(kEPT) * (kFftNT / B) * B;
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+}  // namespace
+
+// Rows of a z-pass tile for NC interleaved spectra: the largest power of two up to 32 that fits (rows_fit).
 int z_rows(int n, int nc) {
-  const int h = n / 2;
   int best = 1;
   for (int r = 1; r <= 32; r *= 2) {
-    const int B = nc * r;
-    if (B > kFftNT) break;
-    if (B * (h + 1) > kTileElems + kFftNT) break;
-    if (static_cast<long>(h) * B > static_cast<long>(kEPT) * (kFftNT / B) * B) break;
+    if (!rows_fit(n, nc * r)) break;
     best = r;
   }
   return best;
+}
+
+bool tile_ok(TileKind kind, int n, int w) {
+  switch (kind) {
+    case TileKind::kZRows:  // forward r2c and single-spectrum c2r z passes (instances 8, 16, 32)
+      return (w == 8 || w == 16 || w == 32) && rows_fit(n, w) && lds_z_r2c(n, w) <= kMaxLds &&
+             lds_z_c2r(n, w) <= kMaxLds;
+    case TileKind::kAxisCols:  // strided y / x passes (instances 8, 16, 32)
+      return (w == 8 || w == 16 || w == 32) && cols_fit(n, w) && lds_axis(n, w) <= kMaxLds;
+    case TileKind::kPoissonCols:  // fused x + Poisson pass (instances 4, 8, 16)
+      return (w == 4 || w == 8 || w == 16) && cols_fit(n, w) && lds_x_poisson(n, w, poisson_points(n, w)) <= kMaxLds;
+    case TileKind::kForceC2RRows:  // three-component c2r z pass (instances 4, 8, 16)
+      return (w == 4 || w == 8 || w == 16) && rows_fit(n, 3 * w) && lds_z_c2r(n, 3 * w) <= kMaxLds;
+  }
+  return false;
 }
 
 void init_kernels() { ensure_init(); }
@@ -524,14 +589,20 @@ hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, s
   return hipGetLastError();
 }
 
-hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, size_t lds, hipStream_t s) {
+hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, size_t lds, hipStream_t s) {
   ensure_init();
   const unsigned g = item_grid(wt.total);
   if (g == 0) return hipSuccess;
-  if (B == 4) k_fft_x_poisson<4><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total);
-  else if (B == 8) k_fft_x_poisson<8><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total);
-  else if (B == 16) k_fft_x_poisson<16><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total);
+#define LPC_POIS(BB, MM) k_fft_x_poisson<BB, MM><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+  if (B == 4 && M == 8) LPC_POIS(4, 8);
+  else if (B == 8 && M == 8) LPC_POIS(8, 8);
+  else if (B == 8 && M == 12) LPC_POIS(8, 12);
+  else if (B == 8 && M == 16) LPC_POIS(8, 16);
+  else if (B == 16 && M == 8) LPC_POIS(16, 8);
+  else if (B == 16 && M == 12) LPC_POIS(16, 12);
+  else if (B == 16 && M == 16) LPC_POIS(16, 16);
   else return hipErrorInvalidValue;
+#undef LPC_POIS
   return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-// Device-side building blocks of liblpc's FFTs: complex helpers, radix-2/3/4/5/8/16 butterflies, one Stockham
+// Device-side building blocks of liblpc's FFTs: complex helpers, radix-2/3/4/5/8 butterflies, one Stockham
 // autosort stage over an LDS tile, and the XCD-aware workgroup remap. Included by the .hip sources only.
 //
 // An LDS tile holds B independent columns of one transform length n: element (j, b) at tile[j * BP + b] with
@@ -113,40 +113,6 @@ struct Dft<5, INV> {
   }
 };
 
-template <bool INV>
-struct Dft<16, INV> {
-  // 16 = 4 x 4: DFT4 over stride-4 subsequences, twiddle by w16^(c q), DFT4 across; output index q + 4 d.
-  static __device__ __forceinline__ void run(float2* v) {
-    float2 y[4][4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      float2 t[4] = {v[c], v[c + 4], v[c + 8], v[c + 12]};
-      Dft<4, INV>::run(t);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) y[c][q] = t[q];
-    }
-    const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f, h = 0.70710678118654752f;
-    const float sg = INV ? 1.f : -1.f;  // w16 = cos(2 pi / 16) + sg i sin(2 pi / 16)
-    const float2 w1 = make_float2(c1, sg * s1), w2 = make_float2(h, sg * h), w3 = make_float2(s1, sg * c1);
-    y[1][1] = cmul(y[1][1], w1);
-    y[1][2] = cmul(y[1][2], w2);
-    y[1][3] = cmul(y[1][3], w3);
-    y[2][1] = cmul(y[2][1], w2);
-    y[2][2] = rot<INV>(y[2][2]);                                 // w16^4
-    y[2][3] = cmul(y[2][3], make_float2(-h, sg * h));           // w16^6
-    y[3][1] = cmul(y[3][1], w3);
-    y[3][2] = cmul(y[3][2], make_float2(-h, sg * h));           // w16^6
-    y[3][3] = cmul(y[3][3], make_float2(-c1, -sg * s1));        // w16^9 = -w16^1
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float2 t[4] = {y[0][q], y[1][q], y[2][q], y[3][q]};
-      Dft<4, INV>::run(t);
-#pragma unroll
-      for (int d = 0; d < 4; ++d) v[q + 4 * d] = t[d];
-    }
-  }
-};
-
 // Thread geometry of a tile with B columns (row pitch BP = B + 1): threads t < S B (S = kFftNT / B) own column
 // b = t mod B and butterflies i = i0 + m S with i0 = t / B; the others idle during the stages.
 struct TileGeom {
@@ -158,10 +124,11 @@ struct TileGeom {
 };
 
 // One Stockham stage over the tile (see the file comment). tws points at this stage's twiddles (k (R - 1) + r - 1).
-// Requires n B <= kEPT S B.
-template <int R, bool INV>
+// Requires n <= EPT S: each thread owns at most EPT points of its column, so ceil(EPT / R) butterflies (a kernel
+// that knows a smaller bound than kEPT passes it, which sizes the register arrays down).
+template <int R, bool INV, int EPT>
 __device__ __forceinline__ void fft_stage(float2* tile, const float2* tws, int n, int p, int pmask, const TileGeom& g) {
-  constexpr int MB = (kEPT + R - 1) / R;
+  constexpr int MB = (EPT + R - 1) / R;
   const int T = n / R;
   float2 v[MB][R];
 #pragma unroll
@@ -198,20 +165,19 @@ __device__ __forceinline__ void fft_stage(float2* tile, const float2* tws, int n
 
 // All stages of plan `pl` over the B columns of the tile (row pitch B + 1). tw is the plan's per-stage twiddle
 // table. The caller has synchronised after filling the tile.
-template <bool INV, class PL>
+template <bool INV, int EPT = kEPT, class PL>
 __device__ __forceinline__ void fft_tile(float2* tile, const float2* tw, const PL& pl, int B, int tid) {
   const TileGeom g(B, tid);
   const int n = pl.n;
   for (int s = 0; s < pl.nst; ++s) {
     const float2* tws = tw + pl.tw_off[s];
     const int p = pl.p[s], pm = pl.pmask[s];
-    switch (pl.radix[s]) {
-      case 16: fft_stage<16, INV>(tile, tws, n, p, pm, g); break;
-      case 8: fft_stage<8, INV>(tile, tws, n, p, pm, g); break;
-      case 4: fft_stage<4, INV>(tile, tws, n, p, pm, g); break;
-      case 2: fft_stage<2, INV>(tile, tws, n, p, pm, g); break;
-      case 3: fft_stage<3, INV>(tile, tws, n, p, pm, g); break;
-      default: fft_stage<5, INV>(tile, tws, n, p, pm, g); break;
+    switch (pl.radix[s]) {  // the plans use radices 8, 4, 2, 3 and 5 (make_plan)
+      case 8: fft_stage<8, INV, EPT>(tile, tws, n, p, pm, g); break;
+      case 4: fft_stage<4, INV, EPT>(tile, tws, n, p, pm, g); break;
+      case 2: fft_stage<2, INV, EPT>(tile, tws, n, p, pm, g); break;
+      case 3: fft_stage<3, INV, EPT>(tile, tws, n, p, pm, g); break;
+      default: fft_stage<5, INV, EPT>(tile, tws, n, p, pm, g); break;
     }
   }
 }

@@ -162,9 +162,14 @@ struct ZC2RJob {        // inverse z pass of NC spectra of one mesh
 // Tile geometry chosen for one transform length (shared by the host builder and the launchers).
 int strided_cols(int n);          // B of strided passes
 int z_rows(int n, int nc);        // rows per z-pass tile for nc interleaved spectra
+// Tile widths the FFT kernels are instantiated for, and whether width w fits length n (stage and load capacity of a
+// tile, 160 KiB of LDS).
+enum class TileKind { kZRows, kAxisCols, kPoissonCols, kForceC2RRows };
+bool tile_ok(TileKind kind, int n, int w);
 size_t lds_z_r2c(int n, int B);
 size_t lds_axis(int n, int B);
-size_t lds_x_poisson(int n, int B);
+int poisson_points(int n, int B);  // points per thread of a fused x + Poisson tile (8, 12 or 16)
+size_t lds_x_poisson(int n, int B, int M);
 size_t lds_z_c2r(int n, int B);
 
 hipError_t launch_tile_key(const SortJob* jobs, WorkTable wt, int* cnt, int* key, int* rank, int* flags,
@@ -183,7 +188,7 @@ hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, h
 void init_kernels();
 hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, size_t lds, int* flags, hipStream_t s);
 hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, size_t lds, hipStream_t s);
-hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, size_t lds, hipStream_t s);
+hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, size_t lds, hipStream_t s);
 hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, size_t lds, hipStream_t s);
 
 // Initial conditions on an N^3 lattice.

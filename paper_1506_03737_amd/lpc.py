@@ -53,6 +53,14 @@ class BatchEntry(ctypes.Structure):
     _fields_ = [("geom", Geometry), ("particles", Particles)]
 
 
+class FftTiling(ctypes.Structure):
+    _fields_ = [("z_rows", ctypes.c_int32), ("axis_cols", ctypes.c_int32), ("poisson_cols", ctypes.c_int32),
+                ("c2r_rows", ctypes.c_int32)]
+
+
+TILING_FIELDS = tuple(f for f, _ in FftTiling._fields_)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"liblpc.so not found at {LIB_PATH}: run __graft_entry__.build() first")
@@ -81,6 +89,10 @@ def _load():
         "lpc_fft_r2c": (i32, [i32, vp, vp, vp, sz, vp]),
         "lpc_fft_c2r": (i32, [i32, vp, vp, vp, sz, vp]),
         "lpc_fft_pitch": (i32, [i32]),
+        "lpc_fft_tiling_default": (i32, [i32, P(FftTiling)]),
+        "lpc_fft_tiling_get": (i32, [i32, P(FftTiling)]),
+        "lpc_fft_tiling_set": (i32, [i32, P(FftTiling)]),
+        "lpc_fft_tiling_reset": (i32, []),
         "lpc_profile_enable": (i32, [i32]),
         "lpc_profile_reset": (i32, []),
         "lpc_profile_count": (i32, []),
@@ -101,6 +113,7 @@ EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_cola_step
             "lpc_net_param_count", "lpc_net_init", "lpc_net_workspace_bytes", "lpc_net_features", "lpc_net_forward",
             "lpc_net_loss_grad", "lpc_net_adam", "lpc_net_apply",
             "lpc_cola_coefficients", "lpc_linear_power", "lpc_fft_r2c", "lpc_fft_c2r", "lpc_fft_pitch",
+            "lpc_fft_tiling_default", "lpc_fft_tiling_get", "lpc_fft_tiling_set", "lpc_fft_tiling_reset",
             "lpc_profile_enable", "lpc_profile_reset", "lpc_profile_count", "lpc_profile_get",
             "lpc_status_string", "lpc_last_error")
 
@@ -264,6 +277,36 @@ def lpc_fft_r2c(n, real_in, complex_out, ws, stream=None):
 
 def lpc_fft_c2r(n, complex_in, real_out, ws, stream=None):
     _check(LIB.lpc_fft_c2r(int(n), _ptr(complex_in), _ptr(real_out), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def _tiling_dict(t):
+    return {f: int(getattr(t, f)) for f in TILING_FIELDS}
+
+
+def lpc_fft_tiling_default(n_mesh):
+    """Built-in FFT tile widths of mesh size n_mesh, as a dict of the lpc_fft_tiling fields."""
+    t = FftTiling()
+    _check(LIB.lpc_fft_tiling_default(int(n_mesh), ctypes.byref(t)))
+    return _tiling_dict(t)
+
+
+def lpc_fft_tiling_get(n_mesh):
+    t = FftTiling()
+    _check(LIB.lpc_fft_tiling_get(int(n_mesh), ctypes.byref(t)))
+    return _tiling_dict(t)
+
+
+def lpc_fft_tiling_set(n_mesh, tiling):
+    """Override the tile widths of n_mesh (a dict with every lpc_fft_tiling field), or remove the override (None)."""
+    if tiling is None:
+        _check(LIB.lpc_fft_tiling_set(int(n_mesh), None))
+        return
+    t = FftTiling(*(int(tiling[f]) for f in TILING_FIELDS))
+    _check(LIB.lpc_fft_tiling_set(int(n_mesh), ctypes.byref(t)))
+
+
+def lpc_fft_tiling_reset():
+    _check(LIB.lpc_fft_tiling_reset())
 
 
 # --- learned correction ---------------------------------------------------------------------------------------

@@ -169,3 +169,75 @@ def test_net_parameter_count_and_workspace_sizes():
     assert np.array_equal(p, lpc.lpc_net_init(7)) and not np.array_equal(p, lpc.lpc_net_init(8))
     assert lpc.lpc_net_workspace_bytes(16) > 0 and lpc.lpc_net_workspace_bytes(6) == 0
     assert lpc.lpc_net_workspace_bytes(18) == 0 and lpc.lpc_net_workspace_bytes(1024) == 0
+
+
+def _supported_meshes():
+    def smooth(n):
+        for r in (2, 3, 5):
+            while n % r == 0:
+                n //= r
+        return n == 1
+    return [n for n in range(8, 1025, 2) if smooth(n)]
+
+
+def _fits(field, n, w):
+    """Capacity of the FFT tiles, restated from the kernels' limits: 512 threads, 16 complex values per thread per
+    stage (8192 per tile), one extra value per thread in the z passes' loads, 160 KiB of LDS (8-byte complex)."""
+    h = n // 2
+    lds = 160 * 1024
+
+    def rows(B):
+        return B * (h + 1) <= 8192 + 512 and h * B <= 16 * (512 // B) * B
+
+    if field == "z_rows":
+        return (w in (8, 16, 32) and rows(w) and 8 * (h * (w + 1) + 2 * h + 1) <= lds
+                and 8 * ((h + 1) * (w + 1) + 2 * h + 1) <= lds)
+    if field == "axis_cols":
+        return w in (8, 16, 32) and n * w <= 8192 and 8 * (n * (w + 1) + n) <= lds
+    if field == "poisson_cols":
+        # the transformed delta_hat stays in registers (one LDS tile) up to 12 points per thread, else a second tile
+        tiles = 1 if -(-n * w // 512) <= 12 else 2
+        return w in (4, 8, 16) and n * w <= 8192 and 8 * (tiles * n * (w + 1) + n) + 4 * (h + 1) <= lds
+    return w in (4, 8, 16) and rows(3 * w) and 8 * ((h + 1) * (3 * w + 1) + 2 * h + 1) <= lds
+
+
+def test_fft_tiling_defaults_overrides_and_rejections():
+    from paper_1506_03737_amd import lpc
+    lpc.lpc_fft_tiling_reset()
+    fields = lpc.TILING_FIELDS
+    try:
+        for n in _supported_meshes():
+            d = lpc.lpc_fft_tiling_default(n)
+            assert lpc.lpc_fft_tiling_get(n) == d
+            for f in fields:
+                assert _fits(f, n, d[f]), (n, f, d[f])
+                for w in (0, 2, 4, 8, 12, 16, 32, 64):
+                    ok = _fits(f, n, w)
+                    try:
+                        lpc.lpc_fft_tiling_set(n, dict(d, **{f: w}))
+                        accepted = True
+                    except lpc.LpcError as e:
+                        accepted = False
+                        assert e.status == -1 and f in str(e)
+                    assert accepted == ok, (n, f, w)
+                lpc.lpc_fft_tiling_set(n, None)
+        # the largest widths that fit the single-box mesh
+        assert lpc.lpc_fft_tiling_default(768) == dict(z_rows=16, axis_cols=8, poisson_cols=8, c2r_rows=4)
+        # an override sticks, a rejected one leaves it in place, None and reset remove it
+        t = dict(z_rows=8, axis_cols=8, poisson_cols=4, c2r_rows=4)
+        lpc.lpc_fft_tiling_set(768, t)
+        with pytest.raises(lpc.LpcError):
+            lpc.lpc_fft_tiling_set(768, dict(t, axis_cols=16))
+        assert lpc.lpc_fft_tiling_get(768) == t
+        assert lpc.lpc_fft_tiling_get(384) == lpc.lpc_fft_tiling_default(384)
+        lpc.lpc_fft_tiling_set(768, None)
+        assert lpc.lpc_fft_tiling_get(768) == lpc.lpc_fft_tiling_default(768)
+        lpc.lpc_fft_tiling_set(768, t)
+        lpc.lpc_fft_tiling_reset()
+        assert lpc.lpc_fft_tiling_get(768) == lpc.lpc_fft_tiling_default(768)
+        for bad in (7, 14, 1026, 0, -8):
+            with pytest.raises(lpc.LpcError) as e:
+                lpc.lpc_fft_tiling_default(bad)
+            assert e.value.status == -2
+    finally:
+        lpc.lpc_fft_tiling_reset()
