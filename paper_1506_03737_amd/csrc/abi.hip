@@ -380,12 +380,12 @@ Plan1D plan_of(int n) {
 // One 3-D transform on an n^3 mesh: the jobs of its passes.
 struct R2CSections {
   Section z, y, x;
-  int Bz, Bax;
+  int Bz, Bax, Pax;
   size_t lds_z, lds_ax;
 };
 struct C2RSections {
   Section x, y, z;
-  int Bax, R;
+  int Bax, R, Pax;
   size_t lds_ax, lds_z;
 };
 
@@ -410,6 +410,7 @@ R2CSections add_r2c(JobPack& jp, const void* in, bool fixed, double mscale, int 
   const lpc_fft_tiling t = tiling_of(n);
   r.Bz = t.z_rows;
   r.Bax = t.axis_cols;
+  r.Pax = kern::axis_points(n, r.Bax);
   r.lds_z = kern::lds_z_r2c(n, r.Bz);
   r.lds_ax = kern::lds_axis(n, r.Bax);
   kern::ZR2CJob z{};
@@ -435,6 +436,7 @@ C2RSections add_c2r(JobPack& jp, float2* spec, int n, float* out, float scale) {
   const lpc_fft_tiling t = tiling_of(n);
   c.Bax = t.axis_cols;
   c.R = t.z_rows;
+  c.Pax = kern::axis_points(n, c.Bax);
   c.lds_ax = kern::lds_axis(n, c.Bax);
   c.lds_z = kern::lds_z_c2r(n, c.R);
   kern::AxisJob x = axis_job(spec, n, static_cast<int64_t>(n) * pitch, pitch, 0, c.Bax);
@@ -457,14 +459,14 @@ void run_r2c(const JobPack& jp, const R2CSections& r, bool fixed, int* flags, hi
   stage("fft z r2c", s, [&] {
     return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(r.z), jp.table(r.z), fixed, r.Bz, r.lds_z, flags, s);
   });
-  stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.y), jp.table(r.y), false, r.Bax, r.lds_ax, s); });
-  stage("fft x", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.x), jp.table(r.x), false, r.Bax, r.lds_ax, s); });
+  stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.y), jp.table(r.y), false, r.Bax, r.Pax, r.lds_ax, s); });
+  stage("fft x", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.x), jp.table(r.x), false, r.Bax, r.Pax, r.lds_ax, s); });
 }
 
 void run_c2r(const JobPack& jp, const C2RSections& c, hipStream_t s) {
-  stage("fft x inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(c.x), jp.table(c.x), true, c.Bax, c.lds_ax, s); });
-  stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(c.y), jp.table(c.y), true, c.Bax, c.lds_ax, s); });
-  stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(c.z), jp.table(c.z), 1, c.R, c.lds_z, s); });
+  stage("fft x inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(c.x), jp.table(c.x), true, c.Bax, c.Pax, c.lds_ax, s); });
+  stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(c.y), jp.table(c.y), true, c.Bax, c.Pax, c.lds_ax, s); });
+  stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(c.z), jp.table(c.z), 1, c.R, 0, c.lds_z, s); });
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -489,6 +491,8 @@ struct ForceProgram {
   Section zr2c, yfwd, pois, yinv, zc2r;
   int Bz = 32, Bax = 32, Bp = 16, R3 = 16;
   int Mp = 8;  // points per thread of the fused x + Poisson tiles: the largest over the boxes
+  int P3 = 8;  // points per thread of the three-spectrum c2r tiles: the largest over the boxes
+  int Pax = 8;  // points per thread of the strided y tiles: the largest over the boxes
   size_t lds_z = 0, lds_ax = 0, lds_p = 0, lds_c = 0;
   SortSpace ss;
   bool cola_run = false;
@@ -507,7 +511,11 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     f.Bp = std::min(f.Bp, t.poisson_cols);
     f.R3 = std::min(f.R3, t.c2r_rows);
   }
-  for (const ForceBox& b : boxes) f.Mp = std::max(f.Mp, kern::poisson_points(b.nm, f.Bp));
+  for (const ForceBox& b : boxes) {
+    f.Mp = std::max(f.Mp, kern::poisson_points(b.nm, f.Bp));
+    f.P3 = std::max(f.P3, kern::c2r_points(b.nm, f.R3));
+    f.Pax = std::max(f.Pax, kern::axis_points(b.nm, f.Bax));
+  }
   const int ncopy = cola_run ? 2 : 1;
   std::vector<kern::SortJob> su, sn[2];
   std::vector<kern::DepJob> dj[2];
@@ -672,10 +680,10 @@ void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags,
   stage("fft z r2c", s, [&] {
     return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), true, f.Bz, f.lds_z, flags, s);
   });
-  stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.lds_ax, s); });
+  stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.Pax, f.lds_ax, s); });
   stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.Mp, f.lds_p, s); });
-  stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yinv), jp.table(f.yinv), true, f.Bax, f.lds_ax, s); });
-  stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(f.zc2r), jp.table(f.zc2r), 3, f.R3, f.lds_c, s); });
+  stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yinv), jp.table(f.yinv), true, f.Bax, f.Pax, f.lds_ax, s); });
+  stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(f.zc2r), jp.table(f.zc2r), 3, f.R3, f.P3, f.lds_c, s); });
 }
 
 // The whole COLA run over a_list for every box (all boxes share cosmology, stepping and time list). Particles are

@@ -192,15 +192,15 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
   }
 }
 
-// Load/store of a strided tile of B columns: element (j, b) <-> ptr[j * astr + b], for b < bw. Loads go out in two
-// unrolled batches of kEPT / 2 per thread (enough bytes in flight per CU to cover HBM latency at a register cost
-// that keeps four waves per SIMD).
-template <int B>
+// Load/store of a strided tile of B columns: element (j, b) <-> ptr[j * astr + b], for b < bw, with n B <= EPT kFftNT.
+// Loads go out in two unrolled batches of EPT / 2 per thread (enough bytes in flight per CU to cover HBM latency at
+// a register cost that keeps four waves per SIMD).
+template <int B, int EPT = kEPT>
 __device__ __forceinline__ void load_strided(float2* tile, LPC_GLOBAL const float2* __restrict__ ptr, int64_t astr, int n, int bw,
                                              int tid) {
   constexpr int BP = B + 1;
   const int count = n * B;
-  constexpr int H = kEPT / 2;
+  constexpr int H = EPT / 2;
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
     float2 v[H];
@@ -219,13 +219,13 @@ __device__ __forceinline__ void load_strided(float2* tile, LPC_GLOBAL const floa
   }
 }
 
-template <int B>
+template <int B, int EPT = kEPT>
 __device__ __forceinline__ void store_strided(const float2* tile, LPC_GLOBAL float2* __restrict__ ptr, int64_t astr, int n,
                                               int bw, int tid) {
   constexpr int BP = B + 1;
   const int count = n * B;
 #pragma unroll
-  for (int m = 0; m < kEPT; ++m) {
+  for (int m = 0; m < EPT; ++m) {
     const int e = tid + m * kFftNT;
     const int j = e / B, b = e % B;
     if (e < count && b < bw) ptr[j * astr + b] = tile[j * BP + b];
@@ -235,9 +235,10 @@ __device__ __forceinline__ void store_strided(const float2* tile, LPC_GLOBAL flo
 // ---------------------------------------------------------------------------------------------------------------
 // Strided complex pass (in place). A tile is B consecutive columns (contiguous in memory) x n points along the
 // axis. Within a component, tiles are XCD-remapped so that neighbouring tiles (which share cache lines at their
-// edges) run on the same XCD.
-template <bool INV, int B>
-__global__ __launch_bounds__(kFftNT, 4) void k_fft_axis(const AxisJob* __restrict__ jobs,
+// edges) run on the same XCD. Each thread owns at most EPT points of its column (n B <= EPT kFftNT); with EPT <= 12
+// the kernel fits in 80 VGPRs (three workgroups per CU where the LDS tile allows it).
+template <bool INV, int B, int EPT>
+__global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_axis(const AxisJob* __restrict__ jobs,
                                                         const int* __restrict__ offs, int njob, int total) {
   extern __shared__ float2 smem[];
   {
@@ -259,10 +260,10 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_axis(const AxisJob* __restric
       fill_stage_twiddles(tw, J.pl, tid);
     }
     LPC_GLOBAL float2* ptr = to_global(J.base + comp * J.cstr + outer * J.ostr + c0);
-    load_strided<B>(tile, ptr, J.astr, n, bw, tid);
+    load_strided<B, EPT>(tile, ptr, J.astr, n, bw, tid);
     __syncthreads();
-    fft_tile<INV>(tile, tw, J.pl, B, tid);
-    store_strided<B>(tile, ptr, J.astr, n, bw, tid);
+    fft_tile<INV, EPT>(tile, tw, J.pl, B, tid);
+    store_strided<B, EPT>(tile, ptr, J.astr, n, bw, tid);
   }
 }
 
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
     const int c0 = ct * B, bw = min(B, nh - c0);
     const int64_t astr = static_cast<int64_t>(nm) * pitch;
     const int64_t off = static_cast<int64_t>(y) * pitch + c0;
-    load_strided<B>(tile, to_global(J.A + off), astr, n, bw, tid);
+    load_strided<B, M>(tile, to_global(J.A + off), astr, n, bw, tid);
     __syncthreads();
     fft_tile<false, M>(tile, tw, J.pl, B, tid);
 
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
       __syncthreads();
       fft_tile<true, M>(tile, tw, J.pl, B, ltid);
       float2* dst = (comp == 0) ? J.A : (comp == 1 ? J.B : J.C);
-      store_strided<B>(tile, to_global(dst + off), astr, n, bw, ltid);
+      store_strided<B, M>(tile, to_global(dst + off), astr, n, bw, ltid);
       __syncthreads();
     }
   }
@@ -375,8 +376,10 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
 // row r (B = NC R columns). With X the half spectrum of a real row,
 //   Z[k] = (X[k] + conj X[h-k]) + i exp(+2 pi i k / n) (X[k] - conj X[h-k]),  h = n/2, k < h,
 // and the unnormalised length-h inverse FFT of Z gives x[2m] + i x[2m+1]. Output rows are NC-interleaved.
-template <int NC, int R>
-__global__ __launch_bounds__(kFftNT, 4) void k_fft_z_c2r(const ZC2RJob* __restrict__ jobs,
+// Each thread owns at most EPT points of a column (h <= EPT S); with EPT <= 12 the kernel fits in 80 VGPRs, so
+// LDS-light tiles run three workgroups per CU.
+template <int NC, int R, int EPT>
+__global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const ZC2RJob* __restrict__ jobs,
                                                          const int* __restrict__ offs, int njob, int total) {
   constexpr int B = NC * R, BP = B + 1;
   extern __shared__ float2 smem[];
@@ -401,9 +404,9 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_c2r(const ZC2RJob* __restri
     LPC_GLOBAL const float2* in2 = to_global(J.in2);
     const int count = B * (h + 1);
     {
-      float2 v[kEPT + 1];
+      float2 v[EPT + 1];  // B (h + 1) <= B (EPT S + 1) <= (EPT + 1) kFftNT
 #pragma unroll
-      for (int m = 0; m < kEPT + 1; ++m) {
+      for (int m = 0; m < EPT + 1; ++m) {
         const int e = tid + m * kFftNT;
         const int col = e / (h + 1), k = e - col * (h + 1);
         const int c = col / R, row = row0 + col % R;
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_c2r(const ZC2RJob* __restri
         if (e < count && row < nrows) v[m] = src[static_cast<size_t>(row) * pitch + k];
       }
 #pragma unroll
-      for (int m = 0; m < kEPT + 1; ++m) {
+      for (int m = 0; m < EPT + 1; ++m) {
         const int e = tid + m * kFftNT;
         if (e < count) {
           const int col = e / (h + 1), k = e - col * (h + 1);
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_c2r(const ZC2RJob* __restri
       tile[k * BP + col] = zk;
     }
     __syncthreads();
-    fft_tile<true>(tile, tw, J.pl, B, tid);
+    fft_tile<true, EPT>(tile, tw, J.pl, B, tid);
     const int rowlen = NC * n;
     LPC_GLOBAL float* out = to_global(J.out);
     const float scale = J.scale;
@@ -462,12 +465,24 @@ struct Init {
     allow_big_lds(k_fft_z_r2c<false, 8>);
     allow_big_lds(k_fft_z_r2c<false, 16>);
     allow_big_lds(k_fft_z_r2c<false, 32>);
-    allow_big_lds(k_fft_axis<true, 8>);
-    allow_big_lds(k_fft_axis<true, 16>);
-    allow_big_lds(k_fft_axis<true, 32>);
-    allow_big_lds(k_fft_axis<false, 8>);
-    allow_big_lds(k_fft_axis<false, 16>);
-    allow_big_lds(k_fft_axis<false, 32>);
+    allow_big_lds(k_fft_axis<true, 8, 8>);
+    allow_big_lds(k_fft_axis<true, 8, 12>);
+    allow_big_lds(k_fft_axis<true, 8, 16>);
+    allow_big_lds(k_fft_axis<true, 16, 8>);
+    allow_big_lds(k_fft_axis<true, 16, 12>);
+    allow_big_lds(k_fft_axis<true, 16, 16>);
+    allow_big_lds(k_fft_axis<true, 32, 8>);
+    allow_big_lds(k_fft_axis<true, 32, 12>);
+    allow_big_lds(k_fft_axis<true, 32, 16>);
+    allow_big_lds(k_fft_axis<false, 8, 8>);
+    allow_big_lds(k_fft_axis<false, 8, 12>);
+    allow_big_lds(k_fft_axis<false, 8, 16>);
+    allow_big_lds(k_fft_axis<false, 16, 8>);
+    allow_big_lds(k_fft_axis<false, 16, 12>);
+    allow_big_lds(k_fft_axis<false, 16, 16>);
+    allow_big_lds(k_fft_axis<false, 32, 8>);
+    allow_big_lds(k_fft_axis<false, 32, 12>);
+    allow_big_lds(k_fft_axis<false, 32, 16>);
     allow_big_lds(k_fft_x_poisson<4, 8>);
     allow_big_lds(k_fft_x_poisson<8, 8>);
     allow_big_lds(k_fft_x_poisson<8, 12>);
@@ -475,12 +490,18 @@ struct Init {
     allow_big_lds(k_fft_x_poisson<16, 8>);
     allow_big_lds(k_fft_x_poisson<16, 12>);
     allow_big_lds(k_fft_x_poisson<16, 16>);
-    allow_big_lds(k_fft_z_c2r<1, 8>);
-    allow_big_lds(k_fft_z_c2r<1, 16>);
-    allow_big_lds(k_fft_z_c2r<1, 32>);
-    allow_big_lds(k_fft_z_c2r<3, 4>);
-    allow_big_lds(k_fft_z_c2r<3, 8>);
-    allow_big_lds(k_fft_z_c2r<3, 16>);
+    allow_big_lds(k_fft_z_c2r<1, 8, kEPT>);
+    allow_big_lds(k_fft_z_c2r<1, 16, kEPT>);
+    allow_big_lds(k_fft_z_c2r<1, 32, kEPT>);
+    allow_big_lds(k_fft_z_c2r<3, 4, 8>);
+    allow_big_lds(k_fft_z_c2r<3, 4, 12>);
+    allow_big_lds(k_fft_z_c2r<3, 4, 16>);
+    allow_big_lds(k_fft_z_c2r<3, 8, 8>);
+    allow_big_lds(k_fft_z_c2r<3, 8, 12>);
+    allow_big_lds(k_fft_z_c2r<3, 8, 16>);
+    allow_big_lds(k_fft_z_c2r<3, 16, 8>);
+    allow_big_lds(k_fft_z_c2r<3, 16, 12>);
+    allow_big_lds(k_fft_z_c2r<3, 16, 16>);
   }
 };
 
@@ -494,6 +515,20 @@ unsigned item_grid(int total) { return total > 0 ? static_cast<unsigned>(total) 
 
 size_t lds_z_r2c(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n / 2) * (B + 1) + n / 2 + n / 2 + 1); }
 size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) * (B + 1) + n); }
+// Points per thread of a strided tile of B columns at length n (n B / kFftNT), rounded up to 8, 12 or 16.
+int axis_points(int n, int B) {
+  const long pts = (static_cast<long>(n) * B + kFftNT - 1) / kFftNT;
+  return pts <= 8 ? 8 : (pts <= 12 ? 12 : 16);
+}
+
+// Points per thread of a three-spectrum c2r z tile of R rows (B = 3 R columns of length n / 2, S = kFftNT / B
+// threads per column), rounded up to 8, 12 or 16 (the kernel's EPT).
+int c2r_points(int n, int R) {
+  const int S = kFftNT / (3 * R);
+  const int pts = (n / 2 + S - 1) / S;
+  return pts <= 8 ? 8 : (pts <= 12 ? 12 : 16);
+}
+
 // Points per thread of the fused x + Poisson tile, n B / kFftNT rounded up to 8, 12 or 16 (the kernel's M).
 int poisson_points(int n, int B) {
   const long pts = (static_cast<long>(n) * B + kFftNT - 1) / kFftNT;
@@ -573,18 +608,22 @@ hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, si
   return hipGetLastError();
 }
 
-hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, size_t lds, hipStream_t s) {
+hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, int P, size_t lds, hipStream_t s) {
   ensure_init();
   const unsigned g = item_grid(wt.total);
   if (g == 0) return hipSuccess;
-#define LPC_AXIS(INV, BB) k_fft_axis<INV, BB><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+#define LPC_AXIS(INV, BB, PP) k_fft_axis<INV, BB, PP><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+#define LPC_AXIS_P(INV, BB) \
+  if (P == 8) LPC_AXIS(INV, BB, 8); else if (P == 12) LPC_AXIS(INV, BB, 12); else if (P == 16) LPC_AXIS(INV, BB, 16); \
+  else return hipErrorInvalidValue
   if (inverse) {
-    if (B == 8) LPC_AXIS(true, 8); else if (B == 16) LPC_AXIS(true, 16); else if (B == 32) LPC_AXIS(true, 32);
+    if (B == 8) { LPC_AXIS_P(true, 8); } else if (B == 16) { LPC_AXIS_P(true, 16); } else if (B == 32) { LPC_AXIS_P(true, 32); }
     else return hipErrorInvalidValue;
   } else {
-    if (B == 8) LPC_AXIS(false, 8); else if (B == 16) LPC_AXIS(false, 16); else if (B == 32) LPC_AXIS(false, 32);
+    if (B == 8) { LPC_AXIS_P(false, 8); } else if (B == 16) { LPC_AXIS_P(false, 16); } else if (B == 32) { LPC_AXIS_P(false, 32); }
     else return hipErrorInvalidValue;
   }
+#undef LPC_AXIS_P
 #undef LPC_AXIS
   return hipGetLastError();
 }
@@ -606,16 +645,24 @@ hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, si
   return hipGetLastError();
 }
 
-hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, size_t lds, hipStream_t s) {
+hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, int P, size_t lds, hipStream_t s) {
   ensure_init();
   const unsigned g = item_grid(wt.total);
   if (g == 0) return hipSuccess;
-#define LPC_ZC2R(NC, RR) k_fft_z_c2r<NC, RR><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
-  if (nc == 3) {
-    if (R == 4) LPC_ZC2R(3, 4); else if (R == 8) LPC_ZC2R(3, 8); else if (R == 16) LPC_ZC2R(3, 16);
+#define LPC_ZC2R(NC, RR, PP) k_fft_z_c2r<NC, RR, PP><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+  if (nc == 1) {
+    if (R == 8) LPC_ZC2R(1, 8, kEPT); else if (R == 16) LPC_ZC2R(1, 16, kEPT); else if (R == 32) LPC_ZC2R(1, 32, kEPT);
     else return hipErrorInvalidValue;
-  } else if (nc == 1) {
-    if (R == 8) LPC_ZC2R(1, 8); else if (R == 16) LPC_ZC2R(1, 16); else if (R == 32) LPC_ZC2R(1, 32);
+  } else if (nc == 3) {
+    if (R == 4 && P == 8) LPC_ZC2R(3, 4, 8);
+    else if (R == 4 && P == 12) LPC_ZC2R(3, 4, 12);
+    else if (R == 4 && P == 16) LPC_ZC2R(3, 4, 16);
+    else if (R == 8 && P == 8) LPC_ZC2R(3, 8, 8);
+    else if (R == 8 && P == 12) LPC_ZC2R(3, 8, 12);
+    else if (R == 8 && P == 16) LPC_ZC2R(3, 8, 16);
+    else if (R == 16 && P == 8) LPC_ZC2R(3, 16, 8);
+    else if (R == 16 && P == 12) LPC_ZC2R(3, 16, 12);
+    else if (R == 16 && P == 16) LPC_ZC2R(3, 16, 16);
     else return hipErrorInvalidValue;
   } else {
     return hipErrorInvalidValue;
