@@ -444,16 +444,41 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     const int rowlen = NC * n;
     LPC_GLOBAL float* out = to_global(J.out);
     const float scale = J.scale;
-#pragma unroll 4
-    for (int f = tid; f < R * rowlen; f += kFftNT) {
-      const int r = f / rowlen, q = f - r * rowlen;
-      const int row = row0 + r;
-      if (row < nrows) {
-        const int jj = q / NC, c = q - jj * NC;
-        const float2 z = tile[(jj >> 1) * BP + c * R + r];
-        out[static_cast<size_t>(row) * rowlen + q] = ((jj & 1) ? z.y : z.x) * scale;
+    // Output value (r, q): row row0 + r, position q of the NC-interleaved row (tile column c R + r, point jj / 2).
+#define LPC_C2R_VALUE(r, q, val)                              \
+  do {                                                        \
+    const int jj_ = (q) / NC, c_ = (q) - jj_ * NC;            \
+    const float2 z_ = tile[(jj_ >> 1) * BP + c_ * R + (r)];   \
+    (val) = ((jj_ & 1) ? z_.y : z_.x) * scale;                \
+  } while (0)
+    const int nval = min(R, nrows - row0) * rowlen;  // the item's rows are contiguous in the output
+    LPC_GLOBAL float* dst = out + static_cast<size_t>(row0) * rowlen;
+    // (the empty asm keeps the store loop's per-thread indices from being computed before the transform)
+    int stid = tid;
+    asm volatile("" : "+v"(stid));
+    if (nval == R * rowlen && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
+      // R rowlen is a multiple of 4 (R >= 4), so a whole item of a 16-byte aligned mesh starts 16-byte aligned.
+#pragma unroll 1
+      for (int f4 = stid; f4 < R * rowlen / 4; f4 += kFftNT) {
+        int r = (4 * f4) / rowlen, q = 4 * f4 - r * rowlen;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          LPC_C2R_VALUE(r, q, v[i]);
+          if (++q == rowlen) {
+            q = 0;
+            ++r;
+          }
+        }
+        reinterpret_cast<LPC_GLOBAL float4*>(dst)[f4] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    } else {
+      for (int f = stid; f < nval; f += kFftNT) {
+        const int r = f / rowlen, q = f - r * rowlen;
+        LPC_C2R_VALUE(r, q, dst[f]);
       }
     }
+#undef LPC_C2R_VALUE
   }
 }
 
