@@ -268,13 +268,14 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_axis(const 
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Fused x pass of the force: forward FFT along x of a tile of delta_hat, then for each component j
-//   g_hat_j = i k_j (-1/k^2) delta_hat / W^p / Nm^3     (zero at k = 0 and on the Nyquist plane of axis j),
-// inverse FFT along x, store. W = prod_d sinc^2(pi n_d / Nm); the 1/Nm^3 of the inverse transform is folded in.
-// The x-transformed delta_hat is kept across the three components. Each thread owns the points of column b at rows
-// j0 + m S, at most M of them (M = n B / kFftNT rounded up to 8, 12 or 16): with M <= 12 they stay in the thread's
-// registers, so the workgroup needs one LDS tile and two workgroups fit on a CU; with M = 16 a second LDS tile holds
-// them (the registers would spill).
+// Fused x pass of the force. With psi_hat = -delta_hat / (k^2 W^p Nm^3) (zero at k = 0; W = prod_d sinc^2(pi n_d /
+// Nm); the 1/Nm^3 of the inverse transform folded in), the gradient spectra are g_hat_j = i k_j psi_hat, zero on the
+// Nyquist plane of axis j. Along the x transform k_y and k_z are constant (per tile and per column), so
+//   IFFT_x(g_hat_x) = IFFT_x(i k_x psi_hat),   IFFT_x(g_hat_{y,z}) = i k_{y,z} IFFT_x(psi_hat):
+// one forward and two inverse transforms per tile. psi_hat is kept between them. Each thread owns the points of column
+// b at rows j0 + m S, at most M of them (M = n B / kFftNT rounded up to 8, 12 or 16): with M <= 12 they stay in the
+// thread's registers, so the workgroup needs one LDS tile and two workgroups fit on a CU; with M = 16 a second LDS
+// tile holds them (the registers would spill).
 template <int B, int M>
 __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(const PoissonJob* __restrict__ jobs,
                                                                             const int* __restrict__ offs, int njob,
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
     const int y = t / J.ntc, ct = t - y * J.ntc;
     if (y >= n) return;  // padding item
     float2* tile = smem;
-    float2* dh_lds = tile + n * BP;  // used when !kRegs
+    float2* ph_lds = tile + n * BP;  // psi_hat when !kRegs
     float2* tw = tile + (kRegs ? 1 : 2) * n * BP;
     float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
     {
@@ -320,28 +321,9 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
     const int ny = (y <= half) ? y : y - nm;
     const float kf = J.kf, inv_m3 = J.inv_m3;
     const int deconv = J.deconv;
-    float2 dh[kRegs ? M : 1];
+    float2 ph[kRegs ? M : 1];
     {
       const int b = tid % B, j0 = tid / B;
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const int j = j0 + m * S;
-        if (j < n) {
-          if (kRegs)
-            dh[kRegs ? m : 0] = tile[j * BP + b];
-          else
-            dh_lds[j * BP + b] = tile[j * BP + b];
-        }
-      }
-    }
-#pragma unroll 1
-    for (int comp = 0; comp < 3; ++comp) {
-      // The thread's indices are derived anew in every pass (the empty asm hides that they repeat), so that the
-      // compiler does not hoist the component-independent addresses and factors and keep them live across the
-      // inverse transform.
-      int ltid = tid;
-      asm volatile("" : "+v"(ltid));
-      const int b = ltid % B, j0 = ltid / B;
       const int nz = c0 + b;
       const bool col_ok = b < bw;
       const float wyz = win[min(y, n - y)] * win[min(nz, half)];
@@ -352,21 +334,55 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
         if (j >= n) continue;
         const int nx = (j <= half) ? j : j - nm;
         const float k2 = kf * kf * static_cast<float>(nx * nx + nyz2);
-        const int nc = (comp == 0) ? nx : (comp == 1 ? ny : nz);
         float sc = 0.f;
-        if (k2 > 0.f && col_ok && nc != half && nc != -half) {
+        if (k2 > 0.f && col_ok) {
           const float W = win[min(j, n - j)] * wyz;
           const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
-          sc = -kf * static_cast<float>(nc) * inv_m3 / (k2 * wp);  // k_c * (-1 / (k^2 W^p Nm^3))
+          sc = -inv_m3 / (k2 * wp);
         }
-        const float2 d = kRegs ? dh[kRegs ? m : 0] : dh_lds[j * BP + b];
-        tile[j * BP + b] = make_float2(-sc * d.y, sc * d.x);  // i * sc * delta_hat
+        const float2 d = tile[j * BP + b];
+        const float2 psi = make_float2(sc * d.x, sc * d.y);
+        if (kRegs)
+          ph[kRegs ? m : 0] = psi;
+        else
+          ph_lds[j * BP + b] = psi;
+        const float kx = (nx == half) ? 0.f : kf * static_cast<float>(nx);
+        tile[j * BP + b] = make_float2(-kx * psi.y, kx * psi.x);  // i k_x psi_hat
+      }
+    }
+    __syncthreads();
+    fft_tile<true, M>(tile, tw, J.pl, B, tid);
+    store_strided<B, M>(tile, to_global(J.A + off), astr, n, bw, tid);
+    __syncthreads();
+    {
+      // (the empty asm keeps the comp-invariant indices of the first inverse transform from staying live)
+      int ltid = tid;
+      asm volatile("" : "+v"(ltid));
+      const int b = ltid % B, j0 = ltid / B;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int j = j0 + m * S;
+        if (j < n) tile[j * BP + b] = kRegs ? ph[kRegs ? m : 0] : ph_lds[j * BP + b];
       }
       __syncthreads();
       fft_tile<true, M>(tile, tw, J.pl, B, ltid);
-      float2* dst = (comp == 0) ? J.A : (comp == 1 ? J.B : J.C);
-      store_strided<B, M>(tile, to_global(dst + off), astr, n, bw, ltid);
-      __syncthreads();
+      // y and z components: i k_y and i k_z times the transformed potential, zero on their Nyquist planes
+      const float ky = (ny == half) ? 0.f : kf * static_cast<float>(ny);
+      LPC_GLOBAL float2* gy = to_global(J.B + off);
+      LPC_GLOBAL float2* gz = to_global(J.C + off);
+      const int count = n * B;
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const int e = ltid + m * kFftNT;
+        const int jr = e / B, bc = e % B;
+        if (e < count && bc < bw) {
+          const int nzc = c0 + bc;
+          const float kz = (nzc == half) ? 0.f : kf * static_cast<float>(nzc);
+          const float2 v = tile[jr * BP + bc];
+          gy[jr * astr + bc] = make_float2(-ky * v.y, ky * v.x);
+          gz[jr * astr + bc] = make_float2(-kz * v.y, kz * v.x);
+        }
+      }
     }
   }
 }
