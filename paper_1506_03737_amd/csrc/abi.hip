@@ -328,8 +328,19 @@ struct Section {
   int njob = 0, total = 0;
 };
 
+// exp(-2 pi i num / den) rounded to FP32 (num / den reduced exactly to [0, 1) first).
+float2 unit_root(int64_t num, int64_t den) {
+  int64_t r = num % den;
+  if (r < 0) r += den;
+  const double a = 2.0 * M_PI * static_cast<double>(r) / static_cast<double>(den);
+  return make_float2(static_cast<float>(std::cos(a)), static_cast<float>(-std::sin(a)));
+}
+
+// The job tables and FFT tables of one call, built on the host and uploaded in one copy to the workspace's job
+// region at `dev`.
 class JobPack {
  public:
+  explicit JobPack(char* dev) : dev_(dev) {}
   // Append `jobs` with `items[i]` work items each (rounded up to multiples of 8); returns the section handle.
   template <class J>
   Section add(const std::vector<J>& jobs, const std::vector<int>& items) {
@@ -347,10 +358,49 @@ class JobPack {
     return add(std::vector<J>{job}, std::vector<int>{items});
   }
   size_t bytes() const { return host_.size(); }
-  void upload(char* dev, hipStream_t s) {
+  void upload(hipStream_t s) {
     if (host_.size() > kJobRegion) throw HipError{hipErrorInvalidValue, "job tables exceed the workspace job region"};
-    dev_ = dev;
-    check(hipMemcpyAsync(dev, host_.data(), host_.size(), hipMemcpyHostToDevice, s), "upload job tables");
+    check(hipMemcpyAsync(dev_, host_.data(), host_.size(), hipMemcpyHostToDevice, s), "upload job tables");
+  }
+  // Stage twiddles of plan pl (Plan1D layout, pl.n entries): W_{pR}^{r k} at tw_off[s] + k (R - 1) + r - 1.
+  const float2* twiddles(const Plan1D& pl) {
+    auto it = tw_.find(pl.n);
+    if (it == tw_.end()) {
+      std::vector<float2> t(static_cast<size_t>(pl.n), make_float2(1.f, 0.f));
+      for (int st = 0; st < pl.nst; ++st) {
+        const int R = pl.radix[st], p = pl.p[st];
+        for (int k = 0; k < p; ++k)
+          for (int r = 1; r < R; ++r)
+            t[static_cast<size_t>(pl.tw_off[st] + k * (R - 1) + r - 1)] =
+                unit_root(static_cast<int64_t>(r) * k, static_cast<int64_t>(p) * R);
+      }
+      it = tw_.emplace(pl.n, append(t.data(), t.size() * sizeof(float2))).first;
+    }
+    return reinterpret_cast<const float2*>(dev_ + it->second);
+  }
+  // exp(-2 pi i k / n) for k <= n / 2
+  const float2* half_roots(int n) {
+    auto it = roots_.find(n);
+    if (it == roots_.end()) {
+      std::vector<float2> t(static_cast<size_t>(n / 2 + 1));
+      for (int k = 0; k <= n / 2; ++k) t[static_cast<size_t>(k)] = unit_root(k, n);
+      it = roots_.emplace(n, append(t.data(), t.size() * sizeof(float2))).first;
+    }
+    return reinterpret_cast<const float2*>(dev_ + it->second);
+  }
+  // sinc^2(pi m / n) for m <= n / 2 (the CIC window along one axis)
+  const float* sinc2(int n) {
+    auto it = win_.find(n);
+    if (it == win_.end()) {
+      std::vector<float> t(static_cast<size_t>(n / 2 + 1), 1.f);
+      for (int m = 1; m <= n / 2; ++m) {
+        const double x = M_PI * static_cast<double>(m) / n;
+        const double v = std::sin(x) / x;
+        t[static_cast<size_t>(m)] = static_cast<float>(v * v);
+      }
+      it = win_.emplace(n, append(t.data(), t.size() * sizeof(float))).first;
+    }
+    return reinterpret_cast<const float*>(dev_ + it->second);
   }
   template <class J>
   const J* jobs(const Section& s) const {
@@ -368,7 +418,8 @@ class JobPack {
     return at;
   }
   std::vector<char> host_;
-  char* dev_ = nullptr;
+  char* dev_;
+  std::map<int, size_t> tw_, roots_, win_;
 };
 
 Plan1D plan_of(int n) {
@@ -389,7 +440,7 @@ struct C2RSections {
   size_t lds_ax, lds_z;
 };
 
-kern::AxisJob axis_job(float2* base, int n, int64_t astr, int64_t ostr, int64_t cstr, int B) {
+kern::AxisJob axis_job(JobPack& jp, float2* base, int n, int64_t astr, int64_t ostr, int64_t cstr, int B) {
   kern::AxisJob a{};
   a.base = base;
   a.astr = astr;
@@ -400,6 +451,7 @@ kern::AxisJob axis_job(float2* base, int n, int64_t astr, int64_t ostr, int64_t 
   a.ntc = (a.ncols + B - 1) / B;
   a.per_comp = round8(n * a.ntc);
   a.pl = plan_of(n);
+  a.tw = jp.twiddles(a.pl);
   return a;
 }
 
@@ -421,10 +473,12 @@ R2CSections add_r2c(JobPack& jp, const void* in, bool fixed, double mscale, int 
   z.nrows = n * n;
   z.pitch = pitch;
   z.pl = plan_of(n / 2);
+  z.tw = jp.twiddles(z.pl);
+  z.roots = jp.half_roots(n);
   r.z = jp.add1(z, (z.nrows + r.Bz - 1) / r.Bz);
-  kern::AxisJob y = axis_job(out, n, pitch, static_cast<int64_t>(n) * pitch, 0, r.Bax);
+  kern::AxisJob y = axis_job(jp, out, n, pitch, static_cast<int64_t>(n) * pitch, 0, r.Bax);
   r.y = jp.add1(y, y.per_comp);
-  kern::AxisJob x = axis_job(out, n, static_cast<int64_t>(n) * pitch, pitch, 0, r.Bax);
+  kern::AxisJob x = axis_job(jp, out, n, static_cast<int64_t>(n) * pitch, pitch, 0, r.Bax);
   r.x = jp.add1(x, x.per_comp);
   (void)fixed;
   return r;
@@ -439,9 +493,9 @@ C2RSections add_c2r(JobPack& jp, float2* spec, int n, float* out, float scale) {
   c.Pax = kern::axis_points(n, c.Bax);
   c.lds_ax = kern::lds_axis(n, c.Bax);
   c.lds_z = kern::lds_z_c2r(n, c.R);
-  kern::AxisJob x = axis_job(spec, n, static_cast<int64_t>(n) * pitch, pitch, 0, c.Bax);
+  kern::AxisJob x = axis_job(jp, spec, n, static_cast<int64_t>(n) * pitch, pitch, 0, c.Bax);
   c.x = jp.add1(x, x.per_comp);
-  kern::AxisJob y = axis_job(spec, n, pitch, static_cast<int64_t>(n) * pitch, 0, c.Bax);
+  kern::AxisJob y = axis_job(jp, spec, n, pitch, static_cast<int64_t>(n) * pitch, 0, c.Bax);
   c.y = jp.add1(y, y.per_comp);
   kern::ZC2RJob z{};
   z.in0 = z.in1 = z.in2 = spec;
@@ -451,6 +505,8 @@ C2RSections add_c2r(JobPack& jp, float2* spec, int n, float* out, float scale) {
   z.pitch = pitch;
   z.scale = scale;
   z.pl = plan_of(n / 2);
+  z.tw = jp.twiddles(z.pl);
+  z.roots = jp.half_roots(n);
   c.z = jp.add1(z, (z.nrows + c.R - 1) / c.R);
   return c;
 }
@@ -606,12 +662,14 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     z.nrows = nm * nm;
     z.pitch = pitch;
     z.pl = plan_of(nm / 2);
+    z.tw = jp.twiddles(z.pl);
+    z.roots = jp.half_roots(nm);
     zs.push_back(z);
     i_z.push_back((z.nrows + f.Bz - 1) / f.Bz);
-    kern::AxisJob y = axis_job(b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, 0, f.Bax);
+    kern::AxisJob y = axis_job(jp, b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, 0, f.Bax);
     ys.push_back(y);
     i_y.push_back(y.per_comp);
-    kern::AxisJob yi = axis_job(b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, static_cast<int64_t>(b.B - b.A), f.Bax);
+    kern::AxisJob yi = axis_job(jp, b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, static_cast<int64_t>(b.B - b.A), f.Bax);
     yis.push_back(yi);
     i_yi.push_back(3 * yi.per_comp);
     kern::PoissonJob p{};
@@ -625,6 +683,8 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     p.kf = static_cast<float>(2.0 * M_PI / b.box);
     p.inv_m3 = static_cast<float>(1.0 / static_cast<double>(M));
     p.pl = plan_of(nm);
+    p.tw = jp.twiddles(p.pl);
+    p.win = jp.sinc2(nm);
     ps.push_back(p);
     i_p.push_back(nm * p.ntc);
     kern::ZC2RJob c{};
@@ -637,6 +697,8 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     c.pitch = pitch;
     c.scale = 1.0f;
     c.pl = plan_of(nm / 2);
+    c.tw = jp.twiddles(c.pl);
+    c.roots = jp.half_roots(nm);
     cs.push_back(c);
     i_c.push_back((c.nrows + f.R3 - 1) / f.R3);
     f.lds_z = std::max(f.lds_z, kern::lds_z_r2c(nm, f.Bz));
@@ -912,12 +974,12 @@ lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, cons
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    JobPack jp;
+    JobPack jp(at(ws, p.jobs));
     const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, n, const_cast<float*>(pos), nullptr, nullptr, nullptr,
                                  grad_out, reinterpret_cast<uint64_t*>(density_fixed_out));
     const ForceProgram f = add_force(jp, {b}, sort_space(ws, p, geom->n_mesh, LPC_OP_PM_FORCE, n), step->deconv_power,
                                      false);
-    jp.upload(at(ws, p.jobs), s);
+    jp.upload(s);
     run_sort(jp, f.ss, f.sort_user, flags, s);
     run_force_mesh(jp, f, 0, flags, s);
     stage("gather", s, [&] { return kern::launch_gather(jp.jobs<kern::PartJob>(f.parts[0]), jp.table(f.parts[0]), flags, s); });
@@ -941,12 +1003,12 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    JobPack jp;
+    JobPack jp(at(ws, p.jobs));
     const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, inout->n, inout->pos, inout->vel, inout->psi1,
                                  inout->psi2, nullptr, nullptr);
     const ForceProgram f = add_force(jp, {b}, sort_space(ws, p, geom->n_mesh, LPC_OP_COLA_STEP, inout->n),
                                      step->deconv_power, true);
-    jp.upload(at(ws, p.jobs), s);
+    jp.upload(s);
     run_cola(jp, f, tab, n_a, cosmo->omega_m, step->cola != 0, flags, s);
     return finish(flags, s);
   });
@@ -1016,7 +1078,7 @@ lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real,
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    JobPack jp;
+    JobPack jp(at(ws, round_up(sizeof(int) * kern::kNumFlags)));  // the job region follows the flags
     std::vector<ForceBox> boxes;
     for (int i = 0; i < n_real; ++i) {
       const lpc_batch_entry& e = entries[i];
@@ -1040,8 +1102,7 @@ lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real,
       boxes.push_back(b);
     }
     const ForceProgram f = add_force(jp, boxes, ss, step->deconv_power, true);
-    char* jobs_dev = at(ws, round_up(sizeof(int) * kern::kNumFlags));
-    jp.upload(jobs_dev, s);
+    jp.upload(s);
     const bool cola = step->cola != 0;
     if (!g_graph_on || g_prof.on) {
       run_cola(jp, f, tab, n_a, cosmo->omega_m, cola, flags, s);
@@ -1121,12 +1182,12 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
     // the transforms of the whole construction, in order: r2c(noise), 12 derived fields, r2c(source), and the 2LPT
     // displacement fields; kinds 0..2 Psi1, 3..8 phi1_ij, 9..11 Psi2
     float* dst[12] = {out->psi1, out->psi1 + n, out->psi1 + 2 * n, r0, r1, r2, r1, r1, r1, r0, r1, r2};
-    JobPack jp;
+    JobPack jp(at(ws, p.jobs));
     const R2CSections noise = add_r2c(jp, r0, false, 0.0, N, dhat);
     C2RSections der[12];
     for (int k = 0; k < 12; ++k) der[k] = add_c2r(jp, spec, N, dst[k], inv_n3);
     const R2CSections source = add_r2c(jp, r0, false, 0.0, N, dhat);
-    jp.upload(at(ws, p.jobs), s);
+    jp.upload(s);
     auto derived = [&](int kind) {
       stage("spectral factor", s, [&] { return kern::ic_spectral_factor(dhat, spec, N, pitch, geom->box, kind, s); });
       run_c2r(jp, der[kind], s);
@@ -1176,7 +1237,7 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
     float2* A = reinterpret_cast<float2*>(at(ws, p.A));
     double* sums = reinterpret_cast<double*>(at(ws, p.bins));
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(sums + 2 * n_bins);
-    JobPack jp;
+    JobPack jp(at(ws, p.jobs));
     const SortSpace ss = sort_space(ws, p, nm, LPC_OP_POWER_SPECTRUM, n);
     const int nt = ss.nt[0];
     kern::SortJob sj{};
@@ -1197,7 +1258,7 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
     dj.dens = dens;
     const Section dep = jp.add1(dj, nt * nt * nt);
     const R2CSections r = add_r2c(jp, dens, true, (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48, nm, A);
-    jp.upload(at(ws, p.jobs), s);
+    jp.upload(s);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
     stage("clear bins", s, [&] {
       return kern::fill_i32(reinterpret_cast<int*>(sums), static_cast<size_t>(6) * n_bins, 0, s);
@@ -1235,9 +1296,9 @@ lpc_status lpc_fft_r2c(int32_t n, const float* in, float* out_complex, void* ws,
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    JobPack jp;
+    JobPack jp(at(ws, p.jobs));
     const R2CSections r = add_r2c(jp, in, false, 0.0, n, reinterpret_cast<float2*>(out_complex));
-    jp.upload(at(ws, p.jobs), s);
+    jp.upload(s);
     run_r2c(jp, r, false, flags, s);
     return finish(flags, s);
   });
@@ -1252,9 +1313,9 @@ lpc_status lpc_fft_c2r(int32_t n, float* in_complex, float* out, void* ws, size_
   return guarded([&]() {
     int* flags = reinterpret_cast<int*>(ws);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    JobPack jp;
+    JobPack jp(at(ws, p.jobs));
     const C2RSections c = add_c2r(jp, reinterpret_cast<float2*>(in_complex), n, out, 1.0f);
-    jp.upload(at(ws, p.jobs), s);
+    jp.upload(s);
     run_c2r(jp, c, s);
     return finish(flags, s);
   });

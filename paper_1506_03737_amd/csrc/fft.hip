@@ -114,31 +114,44 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     float2* tile = smem;
     float2* tw = tile + h * BP;
     float2* roots = tw + h;
-    {
-      fill_stage_twiddles(tw, J.pl, tid);
-      fill_half_roots(roots, n, tid);
-    }
     const int count = h * B;
+    // Element e = tid + m kFftNT of the tile is (row b, point j) = divmod(e, h): one division per thread, then steps
+    // of kFftNT = dq h + dr.
+    const int dq = kFftNT / h, dr = kFftNT - dq * h;
+    const int b0 = tid / h, j0 = tid - b0 * h;
+    // The global loads are issued before the twiddle tables are computed, so the tables overlap their latency.
     if (FIXED) {
       LPC_GLOBAL const uint64_t* in = to_global(static_cast<const uint64_t*>(J.in));
       constexpr int H = kEPT / 2;
+      int bb = b0, jj = j0;
 #pragma unroll 1
       for (int half = 0; half < 2; ++half) {
         ulonglong2 raw[H];
+        int b = bb, j = jj;
 #pragma unroll
         for (int m = 0; m < H; ++m) {
           const int e = tid + (half * H + m) * kFftNT;
-          const int b = e / h, j = e - b * h;
           raw[m] = make_ulonglong2(0ull, 0ull);
           if (e < count && row0 + b < nrows)
             raw[m] = reinterpret_cast<LPC_GLOBAL const ulonglong2*>(in + static_cast<size_t>(row0 + b) * n)[j];
+          b += dq;
+          j += dr;
+          if (j >= h) {
+            j -= h;
+            ++b;
+          }
+        }
+        if (half == 0) {
+          copy_table(tw, J.tw, h, tid);
+          copy_table(roots, J.roots, h + 1, tid);
         }
         bool overflow = false;
+        b = bb;
+        j = jj;
 #pragma unroll
         for (int m = 0; m < H; ++m) {
           const int e = tid + (half * H + m) * kFftNT;
           if (e < count) {
-            const int b = e / h, j = e - b * h;
             overflow |= ((raw[m].x | raw[m].y) >> 63) != 0;
             float2 v = make_float2(0.f, 0.f);
             if (row0 + b < nrows) {
@@ -147,25 +160,46 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
             }
             tile[j * BP + b] = v;
           }
+          b += dq;
+          j += dr;
+          if (j >= h) {
+            j -= h;
+            ++b;
+          }
         }
+        bb = b;
+        jj = j;
         if (overflow) atomicOr(flags + kFlagOverflow, 1);
       }
     } else {
       LPC_GLOBAL const float2* in = to_global(static_cast<const float2*>(J.in));
       float2 v[kEPT];
+      int b = b0, j = j0;
 #pragma unroll
       for (int m = 0; m < kEPT; ++m) {
         const int e = tid + m * kFftNT;
-        const int b = e / h, j = e - b * h;
         v[m] = make_float2(0.f, 0.f);
         if (e < count && row0 + b < nrows) v[m] = in[static_cast<size_t>(row0 + b) * h + j];
+        b += dq;
+        j += dr;
+        if (j >= h) {
+          j -= h;
+          ++b;
+        }
       }
+      copy_table(tw, J.tw, h, tid);
+      copy_table(roots, J.roots, h + 1, tid);
+      b = b0;
+      j = j0;
 #pragma unroll
       for (int m = 0; m < kEPT; ++m) {
         const int e = tid + m * kFftNT;
-        if (e < count) {
-          const int b = e / h, j = e - b * h;
-          tile[j * BP + b] = v[m];
+        if (e < count) tile[j * BP + b] = v[m];
+        b += dq;
+        j += dr;
+        if (j >= h) {
+          j -= h;
+          ++b;
         }
       }
     }
@@ -174,11 +208,13 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     const int count2 = (h + 1) * B;
     LPC_GLOBAL float2* out = to_global(J.out);
     const int pitch = J.pitch;
+    // output element e = (row b, frequency k) = divmod(e, h + 1), stepped the same way
+    const int h1 = h + 1, dq1 = kFftNT / h1, dr1 = kFftNT - dq1 * h1;
+    int b = tid / h1, k = tid - (tid / h1) * h1;
 #pragma unroll
     for (int m = 0; m < kEPT + 1; ++m) {
       const int e = tid + m * kFftNT;
       if (e < count2) {
-        const int b = e / (h + 1), k = e - b * (h + 1);
         const int row = row0 + b;
         if (row < nrows) {
           const float2 zk = tile[(k == h ? 0 : k) * BP + b];
@@ -188,34 +224,41 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
           out[static_cast<size_t>(row) * pitch + k] = cadd(E, cmul(roots[k], O));
         }
       }
+      b += dq1;
+      k += dr1;
+      if (k >= h1) {
+        k -= h1;
+        ++b;
+      }
     }
   }
 }
 
 // Load/store of a strided tile of B columns: element (j, b) <-> ptr[j * astr + b], for b < bw, with n B <= EPT kFftNT.
 // Loads go out in two unrolled batches of EPT / 2 per thread (enough bytes in flight per CU to cover HBM latency at
-// a register cost that keeps four waves per SIMD).
-template <int B, int EPT = kEPT>
-__device__ __forceinline__ void load_strided(float2* tile, LPC_GLOBAL const float2* __restrict__ ptr, int64_t astr, int n, int bw,
-                                             int tid) {
+// a register cost that keeps four waves per SIMD): strided_issue loads batch `half` into registers, strided_put
+// writes it to the tile, so a kernel can do other work (its twiddle tables) while the first batch is in flight.
+template <int B, int H>
+__device__ __forceinline__ void strided_issue(float2 (&v)[H], LPC_GLOBAL const float2* __restrict__ ptr, int64_t astr,
+                                              int n, int bw, int tid, int half) {
+  const int count = n * B;
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    const int e = tid + (half * H + m) * kFftNT;
+    const int j = e / B, b = e % B;
+    v[m] = make_float2(0.f, 0.f);
+    if (e < count && b < bw) v[m] = ptr[j * astr + b];
+  }
+}
+
+template <int B, int H>
+__device__ __forceinline__ void strided_put(float2* tile, const float2 (&v)[H], int n, int tid, int half) {
   constexpr int BP = B + 1;
   const int count = n * B;
-  constexpr int H = EPT / 2;
-#pragma unroll 1
-  for (int half = 0; half < 2; ++half) {
-    float2 v[H];
 #pragma unroll
-    for (int m = 0; m < H; ++m) {
-      const int e = tid + (half * H + m) * kFftNT;
-      const int j = e / B, b = e % B;
-      v[m] = make_float2(0.f, 0.f);
-      if (e < count && b < bw) v[m] = ptr[j * astr + b];
-    }
-#pragma unroll
-    for (int m = 0; m < H; ++m) {
-      const int e = tid + (half * H + m) * kFftNT;
-      if (e < count) tile[(e / B) * BP + (e % B)] = v[m];
-    }
+  for (int m = 0; m < H; ++m) {
+    const int e = tid + (half * H + m) * kFftNT;
+    if (e < count) tile[(e / B) * BP + (e % B)] = v[m];
   }
 }
 
@@ -235,10 +278,10 @@ __device__ __forceinline__ void store_strided(const float2* tile, LPC_GLOBAL flo
 // ---------------------------------------------------------------------------------------------------------------
 // Strided complex pass (in place). A tile is B consecutive columns (contiguous in memory) x n points along the
 // axis. Within a component, tiles are XCD-remapped so that neighbouring tiles (which share cache lines at their
-// edges) run on the same XCD. Each thread owns at most EPT points of its column (n B <= EPT kFftNT); with EPT <= 12
-// the kernel fits in 80 VGPRs (three workgroups per CU where the LDS tile allows it).
+// edges) run on the same XCD. Each thread owns at most EPT points of its column (n B <= EPT kFftNT); with EPT <= 8
+// the kernel fits in 80 VGPRs (three workgroups per CU where the LDS tile allows it), with EPT = 12 in 96.
 template <bool INV, int B, int EPT>
-__global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_axis(const AxisJob* __restrict__ jobs,
+__global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : (EPT <= 12 ? 5 : 4)) void k_fft_axis(const AxisJob* __restrict__ jobs,
                                                         const int* __restrict__ offs, int njob, int total) {
   extern __shared__ float2 smem[];
   {
@@ -256,11 +299,17 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_axis(const 
     const int c0 = ct * B, bw = min(B, J.ncols - c0);
     float2* tile = smem;
     float2* tw = smem + n * (B + 1);
-    {
-      fill_stage_twiddles(tw, J.pl, tid);
-    }
     LPC_GLOBAL float2* ptr = to_global(J.base + comp * J.cstr + outer * J.ostr + c0);
-    load_strided<B, EPT>(tile, ptr, J.astr, n, bw, tid);
+    {
+      constexpr int H = EPT / 2;
+      float2 v[H];
+      const TableRegs<float2> t = table_load(J.tw, n, tid);
+      strided_issue<B, H>(v, ptr, J.astr, n, bw, tid, 0);
+      table_store(tw, t, n, tid);
+      strided_put<B, H>(tile, v, n, tid, 0);
+      strided_issue<B, H>(v, ptr, J.astr, n, bw, tid, 1);
+      strided_put<B, H>(tile, v, n, tid, 1);
+    }
     __syncthreads();
     fft_tile<INV, EPT>(tile, tw, J.pl, B, tid);
     store_strided<B, EPT>(tile, ptr, J.astr, n, bw, tid);
@@ -297,22 +346,20 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
     float2* ph_lds = tile + n * BP;  // psi_hat when !kRegs
     float2* tw = tile + (kRegs ? 1 : 2) * n * BP;
     float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
-    {
-      fill_stage_twiddles(tw, J.pl, tid);
-      for (int m = tid; m <= n / 2; m += kFftNT) {
-        double wv = 1.0;
-        if (m != 0) {
-          const double x = static_cast<double>(m) / n;
-          wv = sinpi(x) / (M_PI * x);
-          wv = wv * wv;
-        }
-        win[m] = static_cast<float>(wv);
-      }
-    }
     const int c0 = ct * B, bw = min(B, nh - c0);
     const int64_t astr = static_cast<int64_t>(nm) * pitch;
     const int64_t off = static_cast<int64_t>(y) * pitch + c0;
-    load_strided<B, M>(tile, to_global(J.A + off), astr, n, bw, tid);
+    {
+      constexpr int H = M / 2;
+      float2 v[H];
+      strided_issue<B, H>(v, to_global(J.A + off), astr, n, bw, tid, 0);
+      // the tables are copied while the first batch is in flight
+      copy_table(tw, J.tw, n, tid);
+      copy_table(win, J.win, n / 2 + 1, tid);
+      strided_put<B, H>(tile, v, n, tid, 0);
+      strided_issue<B, H>(v, to_global(J.A + off), astr, n, bw, tid, 1);
+      strided_put<B, H>(tile, v, n, tid, 1);
+    }
     __syncthreads();
     fft_tile<false, M>(tile, tw, J.pl, B, tid);
 
@@ -411,49 +458,72 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     float2* tile = smem;                 // (h + 1) x BP
     float2* tw = tile + (h + 1) * BP;    // stage twiddles (h)
     float2* roots = tw + h;              // exp(-2 pi i k / n), k <= h
-    {
-      fill_stage_twiddles(tw, J.pl, tid);
-      fill_half_roots(roots, n, tid);
-    }
     LPC_GLOBAL const float2* in0 = to_global(J.in0);
     LPC_GLOBAL const float2* in1 = to_global(J.in1);
     LPC_GLOBAL const float2* in2 = to_global(J.in2);
-    const int count = B * (h + 1);
+    const int h1 = h + 1, count = B * h1;
+    // Element e = tid + m kFftNT is (tile column col, frequency k) = divmod(e, h + 1): one division per thread, then
+    // steps of kFftNT = dq (h + 1) + dr.
+    const int dq = kFftNT / h1, dr = kFftNT - dq * h1;
+    const int col0 = tid / h1, k0 = tid - col0 * h1;
     {
       float2 v[EPT + 1];  // B (h + 1) <= B (EPT S + 1) <= (EPT + 1) kFftNT
+      int col = col0, k = k0;
 #pragma unroll
       for (int m = 0; m < EPT + 1; ++m) {
         const int e = tid + m * kFftNT;
-        const int col = e / (h + 1), k = e - col * (h + 1);
         const int c = col / R, row = row0 + col % R;
         v[m] = make_float2(0.f, 0.f);
         LPC_GLOBAL const float2* src = (c == 0) ? in0 : (c == 1 ? in1 : in2);
         if (e < count && row < nrows) v[m] = src[static_cast<size_t>(row) * pitch + k];
+        col += dq;
+        k += dr;
+        if (k >= h1) {
+          k -= h1;
+          ++col;
+        }
       }
+      // the tables are copied while the loads are in flight
+      copy_table(tw, J.tw, h, tid);
+      copy_table(roots, J.roots, h + 1, tid);
+      col = col0;
+      k = k0;
 #pragma unroll
       for (int m = 0; m < EPT + 1; ++m) {
         const int e = tid + m * kFftNT;
-        if (e < count) {
-          const int col = e / (h + 1), k = e - col * (h + 1);
-          tile[k * BP + col] = v[m];
+        if (e < count) tile[k * BP + col] = v[m];
+        col += dq;
+        k += dr;
+        if (k >= h1) {
+          k -= h1;
+          ++col;
         }
       }
     }
     __syncthreads();
-    const int hk = h / 2 + 1;
-    for (int e = tid; e < hk * B; e += kFftNT) {
-      const int col = e / hk, k = e - col * hk;
-      const float2 xk = tile[k * BP + col];
-      const float2 xm = tile[(h - k) * BP + col];
-      const float2 t = roots[k];
-      // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm)
-      const float2 zk = cadd(cadd(xk, cconj(xm)), rot<true>(cmulc(csub(xk, cconj(xm)), t)));
-      if (k != 0 && 2 * k != h) {
-        // Z[h-k] = (xm + conj xk) - i t (xm - conj xk)
-        const float2 zm = csub(cadd(xm, cconj(xk)), rot<true>(cmul(csub(xm, cconj(xk)), t)));
-        tile[(h - k) * BP + col] = zm;
+    {
+      const int hk = h / 2 + 1;
+      const int dqk = kFftNT / hk, drk = kFftNT - dqk * hk;
+      int col = tid / hk, k = tid - (tid / hk) * hk;
+      for (int e = tid; e < hk * B; e += kFftNT) {
+        const float2 xk = tile[k * BP + col];
+        const float2 xm = tile[(h - k) * BP + col];
+        const float2 t = roots[k];
+        // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm)
+        const float2 zk = cadd(cadd(xk, cconj(xm)), rot<true>(cmulc(csub(xk, cconj(xm)), t)));
+        if (k != 0 && 2 * k != h) {
+          // Z[h-k] = (xm + conj xk) - i t (xm - conj xk)
+          const float2 zm = csub(cadd(xm, cconj(xk)), rot<true>(cmul(csub(xm, cconj(xk)), t)));
+          tile[(h - k) * BP + col] = zm;
+        }
+        tile[k * BP + col] = zk;
+        col += dqk;
+        k += drk;
+        if (k >= hk) {
+          k -= hk;
+          ++col;
+        }
       }
-      tile[k * BP + col] = zk;
     }
     __syncthreads();
     fft_tile<true, EPT>(tile, tw, J.pl, B, tid);
@@ -474,9 +544,13 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     asm volatile("" : "+v"(stid));
     if (nval == R * rowlen && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
       // R rowlen is a multiple of 4 (R >= 4), so a whole item of a 16-byte aligned mesh starts 16-byte aligned.
+      // value f = 4 f4 + i is (row r, position q) = divmod(f, rowlen): one division per thread, then steps of
+      // 4 kFftNT = dq4 rowlen + dr4 (rowlen = NC n >= 8)
+      const int dq4 = (4 * kFftNT) / rowlen, dr4 = 4 * kFftNT - dq4 * rowlen;
+      int r0 = (4 * stid) / rowlen, q0 = 4 * stid - r0 * rowlen;
 #pragma unroll 1
       for (int f4 = stid; f4 < R * rowlen / 4; f4 += kFftNT) {
-        int r = (4 * f4) / rowlen, q = 4 * f4 - r * rowlen;
+        int r = r0, q = q0;
         float v[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -487,6 +561,12 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
           }
         }
         reinterpret_cast<LPC_GLOBAL float4*>(dst)[f4] = make_float4(v[0], v[1], v[2], v[3]);
+        r0 += dq4;
+        q0 += dr4;
+        if (q0 >= rowlen) {
+          q0 -= rowlen;
+          ++r0;
+        }
       }
     } else {
       for (int f = stid; f < nval; f += kFftNT) {

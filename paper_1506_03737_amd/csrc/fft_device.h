@@ -182,28 +182,36 @@ __device__ __forceinline__ void fft_tile(float2* tile, const float2* tw, const P
   }
 }
 
-// Fill the per-stage twiddle table of plan `pl` (n - 1 entries), rounded from FP64. No barrier.
-template <class PL>
-__device__ __forceinline__ void fill_stage_twiddles(float2* tw, const PL& pl, int tid) {
-  for (int s = 0; s < pl.nst; ++s) {
-    const int R = pl.radix[s], p = pl.p[s], cnt = p * (R - 1);
-    if (p == 1) continue;
-    const double inv = 1.0 / (static_cast<double>(p) * R);
-    for (int idx = tid; idx < cnt; idx += kFftNT) {
-      const int k = idx / (R - 1), r = idx - k * (R - 1) + 1;
-      double sn, cs;
-      sincospi(-2.0 * (r * k) * inv, &sn, &cs);
-      tw[pl.tw_off[s] + idx] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
-    }
-  }
+// Copy `count` entries of a precomputed table from global memory to LDS. No barrier.
+template <class T>
+__device__ __forceinline__ void copy_table(T* dst, const T* __restrict__ src, int count, int tid) {
+  LPC_GLOBAL const T* g = to_global(src);
+  for (int i = tid; i < count; i += kFftNT) dst[i] = g[i];
 }
 
-// roots[k] = exp(-2 pi i k / n) for k <= n / 2 (the real-transform split), rounded from FP64. No barrier.
-__device__ __forceinline__ void fill_half_roots(float2* roots, int n, int tid) {
-  for (int k = tid; k <= n / 2; k += kFftNT) {
-    double sn, cs;
-    sincospi(-2.0 * k / n, &sn, &cs);
-    roots[k] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
+// The same in two steps, for count <= 2 kFftNT (tables of lengths up to 1024): table_load issues the loads into
+// registers, table_store writes them, so other loads can be issued in between.
+template <class T>
+struct TableRegs {
+  T v[2];
+};
+template <class T>
+__device__ __forceinline__ TableRegs<T> table_load(const T* __restrict__ src, int count, int tid) {
+  LPC_GLOBAL const T* g = to_global(src);
+  TableRegs<T> r;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int i = tid + m * kFftNT;
+    if (i < count) r.v[m] = g[i];
+  }
+  return r;
+}
+template <class T>
+__device__ __forceinline__ void table_store(T* dst, const TableRegs<T>& r, int count, int tid) {
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int i = tid + m * kFftNT;
+    if (i < count) dst[i] = r.v[m];
   }
 }
 

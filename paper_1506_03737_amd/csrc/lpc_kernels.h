@@ -132,21 +132,28 @@ struct PartJob {        // one box's particles and meshes
   float box;
   double scale;         // nm 2^16 / box
 };
+// FFT tables (device, built once per call on the host in FP64 and rounded to FP32): tw = the plan's stage twiddles
+// (Plan1D), roots[k] = exp(-2 pi i k / n) for k <= n / 2 (real-transform split), win[m] = sinc^2(pi m / n) for
+// m <= n / 2 (CIC window).
 struct ZR2CJob {        // forward z pass of one mesh
   const void* in;       // uint64 counts (fixed) or FP32 reals
   float2* out;
+  const float2 *tw, *roots;
   double mscale;        // fixed point: delta = C mscale - 1
   int n, nrows, pitch;
   Plan1D pl;            // length n / 2
 };
 struct AxisJob {        // complex FFT along a strided axis, ncomp meshes
   float2* base;
+  const float2* tw;
   int64_t astr, ostr, cstr;
   int n, ncols, ntc, per_comp;  // per_comp = n_outer * ntc tiles (rounded up to 8)
   Plan1D pl;
 };
 struct PoissonJob {     // fused forward x / Poisson-gradient / inverse x of one box
   float2 *A, *B, *C;
+  const float2* tw;
+  const float* win;
   int nm, pitch, ntc, deconv;
   float kf, inv_m3;
   Plan1D pl;
@@ -154,6 +161,7 @@ struct PoissonJob {     // fused forward x / Poisson-gradient / inverse x of one
 struct ZC2RJob {        // inverse z pass of NC spectra of one mesh
   const float2 *in0, *in1, *in2;
   float* out;
+  const float2 *tw, *roots;
   int n, nrows, pitch;
   float scale;
   Plan1D pl;            // length n / 2
