@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
       }
     }
     __syncthreads();
-    fft_tile<false>(tile, tw, J.pl, B, tid);
+    fft_tile<false>(tile, tw, J.pl, B, BP, tid);
     const int count2 = (h + 1) * B;
     LPC_GLOBAL float2* out = to_global(J.out);
     const int pitch = J.pitch;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void strided_issue(float2 (&v)[H], LPC_GLOBAL const f
 
 template <int B, int H>
 __device__ __forceinline__ void strided_put(float2* tile, const float2 (&v)[H], int n, int tid, int half) {
-  constexpr int BP = B + 1;
+  constexpr int BP = strided_pitch(B);
   const int count = n * B;
 #pragma unroll
   for (int m = 0; m < H; ++m) {
@@ -265,7 +265,7 @@ __device__ __forceinline__ void strided_put(float2* tile, const float2 (&v)[H], 
 template <int B, int EPT = kEPT>
 __device__ __forceinline__ void store_strided(const float2* tile, LPC_GLOBAL float2* __restrict__ ptr, int64_t astr, int n,
                                               int bw, int tid) {
-  constexpr int BP = B + 1;
+  constexpr int BP = strided_pitch(B);
   const int count = n * B;
 #pragma unroll
   for (int m = 0; m < EPT; ++m) {
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : (EPT <= 12 ? 5 : 4)) void 
     if (outer >= n) return;  // padding item
     const int c0 = ct * B, bw = min(B, J.ncols - c0);
     float2* tile = smem;
-    float2* tw = smem + n * (B + 1);
+    float2* tw = smem + n * strided_pitch(B);
     LPC_GLOBAL float2* ptr = to_global(J.base + comp * J.cstr + outer * J.ostr + c0);
     {
       constexpr int H = EPT / 2;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : (EPT <= 12 ? 5 : 4)) void 
       strided_put<B, H>(tile, v, n, tid, 1);
     }
     __syncthreads();
-    fft_tile<INV, EPT>(tile, tw, J.pl, B, tid);
+    fft_tile<INV, EPT>(tile, tw, J.pl, B, strided_pitch(B), tid);
     store_strided<B, EPT>(tile, ptr, J.astr, n, bw, tid);
   }
 }
@@ -329,7 +329,7 @@ template <int B, int M>
 __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(const PoissonJob* __restrict__ jobs,
                                                                             const int* __restrict__ offs, int njob,
                                                                             int total) {
-  constexpr int BP = B + 1, S = kFftNT / B;
+  constexpr int BP = strided_pitch(B), S = kFftNT / B;
   constexpr bool kRegs = M <= 12;
   extern __shared__ float2 smem[];
   {
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
       strided_put<B, H>(tile, v, n, tid, 1);
     }
     __syncthreads();
-    fft_tile<false, M>(tile, tw, J.pl, B, tid);
+    fft_tile<false, M>(tile, tw, J.pl, B, BP, tid);
 
     // Each thread touches only its own points between the barriers that bracket the inverse transforms.
     const int half = nm / 2;
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
       }
     }
     __syncthreads();
-    fft_tile<true, M>(tile, tw, J.pl, B, tid);
+    fft_tile<true, M>(tile, tw, J.pl, B, BP, tid);
     store_strided<B, M>(tile, to_global(J.A + off), astr, n, bw, tid);
     __syncthreads();
     {
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
         if (j < n) tile[j * BP + b] = kRegs ? ph[kRegs ? m : 0] : ph_lds[j * BP + b];
       }
       __syncthreads();
-      fft_tile<true, M>(tile, tw, J.pl, B, ltid);
+      fft_tile<true, M>(tile, tw, J.pl, B, BP, ltid);
       // y and z components: i k_y and i k_z times the transformed potential, zero on their Nyquist planes
       const float ky = (ny == half) ? 0.f : kf * static_cast<float>(ny);
       LPC_GLOBAL float2* gy = to_global(J.B + off);
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
       }
     }
     __syncthreads();
-    fft_tile<true, EPT>(tile, tw, J.pl, B, tid);
+    fft_tile<true, EPT>(tile, tw, J.pl, B, BP, tid);
     const int rowlen = NC * n;
     LPC_GLOBAL float* out = to_global(J.out);
     const float scale = J.scale;
@@ -635,7 +635,7 @@ unsigned item_grid(int total) { return total > 0 ? static_cast<unsigned>(total) 
 }  // namespace
 
 size_t lds_z_r2c(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n / 2) * (B + 1) + n / 2 + n / 2 + 1); }
-size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) * (B + 1) + n); }
+size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) * strided_pitch(B) + n); }
 // Points per thread of a strided tile of B columns at length n (n B / kFftNT), rounded up to 8, 12 or 16.
 int axis_points(int n, int B) {
   const long pts = (static_cast<long>(n) * B + kFftNT - 1) / kFftNT;
@@ -658,7 +658,7 @@ int poisson_points(int n, int B) {
 
 size_t lds_x_poisson(int n, int B, int M) {
   const size_t tiles = M <= 12 ? 1 : 2;
-  return sizeof(float2) * (tiles * static_cast<size_t>(n) * (B + 1) + n) + sizeof(float) * (n / 2 + 1);
+  return sizeof(float2) * (tiles * static_cast<size_t>(n) * strided_pitch(B) + n) + sizeof(float) * (n / 2 + 1);
 }
 size_t lds_z_c2r(int n, int B) {
   return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (B + 1) + n / 2 + n / 2 + 1);

@@ -2,7 +2,7 @@
 // autosort stage over an LDS tile, and the XCD-aware workgroup remap. Included by the .hip sources only.
 //
 // An LDS tile holds B independent columns of one transform length n: element (j, b) at tile[j * BP + b] with
-// BP = B + 1 (n * B <= kTileElems). Stage s with radix R and current sub-transform length p (product of the
+// BP >= B (n * B <= kTileElems). Stage s with radix R and current sub-transform length p (product of the
 // earlier radices) reads x[i + r T] (T = n / R), multiplies by w^(r k) with w = exp(-+ 2 pi i / (p R)),
 // k = i mod p, takes the length-R DFT and writes it to ((i - k) R + k + r p): the Stockham autosort ordering,
 // so after the last stage the tile is in natural order. Each thread stages its butterflies in registers between two
@@ -113,11 +113,11 @@ struct Dft<5, INV> {
   }
 };
 
-// Thread geometry of a tile with B columns (row pitch BP = B + 1): threads t < S B (S = kFftNT / B) own column
+// Thread geometry of a tile with B columns and row pitch BP: threads t < S B (S = kFftNT / B) own column
 // b = t mod B and butterflies i = i0 + m S with i0 = t / B; the others idle during the stages.
 struct TileGeom {
   int B, BP, S, b, i0;
-  __device__ TileGeom(int B_, int tid) : B(B_), BP(B_ + 1), S(kFftNT / B_) {
+  __device__ TileGeom(int B_, int BP_, int tid) : B(B_), BP(BP_), S(kFftNT / B_) {
     b = tid % B_;
     i0 = (tid < S * B_) ? tid / B_ : (1 << 30);
   }
@@ -163,11 +163,11 @@ __device__ __forceinline__ void fft_stage(float2* tile, const float2* tws, int n
   __syncthreads();
 }
 
-// All stages of plan `pl` over the B columns of the tile (row pitch B + 1). tw is the plan's per-stage twiddle
+// All stages of plan `pl` over the B columns of the tile (row pitch BP). tw is the plan's per-stage twiddle
 // table. The caller has synchronised after filling the tile.
 template <bool INV, int EPT = kEPT, class PL>
-__device__ __forceinline__ void fft_tile(float2* tile, const float2* tw, const PL& pl, int B, int tid) {
-  const TileGeom g(B, tid);
+__device__ __forceinline__ void fft_tile(float2* tile, const float2* tw, const PL& pl, int B, int BP, int tid) {
+  const TileGeom g(B, BP, tid);
   const int n = pl.n;
   for (int s = 0; s < pl.nst; ++s) {
     const float2* tws = tw + pl.tw_off[s];
@@ -191,6 +191,11 @@ __device__ __forceinline__ void copy_table(T* dst, const T* __restrict__ src, in
 
 // The same in two steps, for count <= 2 kFftNT (tables of lengths up to 1024): table_load issues the loads into
 // registers, table_store writes them, so other loads can be issued in between.
+// Row pitch of a strided tile of B columns, whose lanes run along the columns: 8-column tiles are left unpadded
+// (with a pitch of 9, two rows met in one 16-lane group of a 64-bit LDS access share banks; a model of the stage
+// accesses gives 1.9x the conflict-free cycles for pitch 9 and 1.1x for pitch 8), wider tiles take B + 1.
+__host__ __device__ constexpr int strided_pitch(int B) { return B == 8 ? 8 : B + 1; }
+
 template <class T>
 struct TableRegs {
   T v[2];

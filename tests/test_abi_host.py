@@ -192,12 +192,13 @@ def _fits(field, n, w):
     if field == "z_rows":
         return (w in (8, 16, 32) and rows(w) and 8 * (h * (w + 1) + 2 * h + 1) <= lds
                 and 8 * ((h + 1) * (w + 1) + 2 * h + 1) <= lds)
+    pitch = w if w == 8 else w + 1  # row pitch of a strided tile (8-column tiles unpadded)
     if field == "axis_cols":
-        return w in (8, 16, 32) and n * w <= 8192 and 8 * (n * (w + 1) + n) <= lds
+        return w in (8, 16, 32) and n * w <= 8192 and 8 * (n * pitch + n) <= lds
     if field == "poisson_cols":
         # the transformed delta_hat stays in registers (one LDS tile) up to 12 points per thread, else a second tile
         tiles = 1 if -(-n * w // 512) <= 12 else 2
-        return w in (4, 8, 16) and n * w <= 8192 and 8 * (tiles * n * (w + 1) + n) + 4 * (h + 1) <= lds
+        return w in (4, 8, 16) and n * w <= 8192 and 8 * (tiles * n * pitch + n) + 4 * (h + 1) <= lds
     return w in (4, 8, 16) and rows(3 * w) and 8 * ((h + 1) * (3 * w + 1) + 2 * h + 1) <= lds
 
 
