@@ -48,9 +48,8 @@ def stage_bytes(stage, n_part, nm, ncomp_y=3):
     H = nm * nm * (nm // 2 + 1) * 8        # bytes of one half-spectrum complex mesh
     corners = min(M, 8 * n_part)
     return {
-        "fill density": 8 * M,
-        "deposit": 12 * n_part + 8 * M,     # read positions, the int64 mesh written once
-        "fft z r2c": 8 * M + H,             # read int64 density, write half spectrum
+        "deposit": 12 * n_part + 4 * M,     # read positions, the FP32 density contrast written once
+        "fft z r2c": 4 * M + H,             # read the FP32 contrast, write half spectrum
         "fft y": 2 * H,
         "fft x + poisson": H + 3 * H,       # read delta_hat, write three gradient spectra
         "fft y inv": 2 * 3 * H,

@@ -536,7 +536,8 @@ struct ForceBox {
   const float* psi1;
   const float* psi2;
   float* grad;        // pm_force output (or NULL)
-  uint64_t* dens;     // int64 counts
+  uint64_t* dens;     // int64 counts (written only when the caller asks for them)
+  bool keep_counts;   // the caller asked for the int64 counts
   float2 *A, *B, *C;  // three half-spectrum meshes (contiguous: B = A + stride, C = B + stride)
   float* force;       // AoS float3 force mesh
 };
@@ -552,6 +553,7 @@ struct ForceProgram {
   size_t lds_z = 0, lds_ax = 0, lds_p = 0, lds_c = 0;
   SortSpace ss;
   bool cola_run = false;
+  bool fixed_in = false;  // the deposit writes int64 counts for the forward transform (else the FP32 contrast)
 };
 
 ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const SortSpace& ss, int deconv,
@@ -559,6 +561,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
   ForceProgram f;
   f.ss = ss;
   f.cola_run = cola_run;
+  for (const ForceBox& b : boxes) f.fixed_in |= b.keep_counts;
   for (const ForceBox& b : boxes) {
     // widths fit every smaller size too, so the smallest over the boxes fits all of them
     const lpc_fft_tiling t = tiling_of(b.nm);
@@ -630,7 +633,9 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
       d.nt = nt;
       d.nm = nm;
       d.scale = scale;
-      d.dens = b.dens;
+      d.mscale = (static_cast<double>(M) / static_cast<double>(b.n)) * 0x1.0p-48;
+      d.dens = f.fixed_in ? b.dens : nullptr;
+      d.delta = f.fixed_in ? nullptr : b.force;  // the contrast takes the start of the density / force region
       dj[c].push_back(d);
       kern::PartJob p{};
       p.pos = cp.pos;
@@ -655,7 +660,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
       uj[c].push_back(u);
     }
     kern::ZR2CJob z{};
-    z.in = b.dens;
+    z.in = f.fixed_in ? static_cast<const void*>(b.dens) : static_cast<const void*>(b.force);
     z.out = b.A;
     z.mscale = (static_cast<double>(M) / static_cast<double>(b.n)) * 0x1.0p-48;
     z.n = nm;
@@ -737,10 +742,10 @@ void run_sort(const JobPack& jp, const SortSpace& ss, const Section& sec, int* f
 // deposit (from sorted copy c) -> delta -> forward FFT -> Poisson/gradient -> inverse FFTs -> AoS force meshes
 void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags, hipStream_t s) {
   stage("deposit", s, [&] {
-    return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(f.dep[c]), jp.table(f.dep[c]), f.ss.start, s);
+    return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(f.dep[c]), jp.table(f.dep[c]), f.ss.start, flags, s);
   });
   stage("fft z r2c", s, [&] {
-    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), true, f.Bz, f.lds_z, flags, s);
+    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), f.fixed_in, f.Bz, f.lds_z, flags, s);
   });
   stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.Pax, f.lds_ax, s); });
   stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.Mp, f.lds_p, s); });
@@ -800,6 +805,7 @@ ForceBox force_box(void* ws, const Plan& p, int nm, double box, int64_t n, float
   b.psi2 = psi2;
   b.grad = grad;
   b.dens = dens_override ? dens_override : reinterpret_cast<uint64_t*>(at(ws, p.dens));
+  b.keep_counts = dens_override != nullptr;
   b.A = reinterpret_cast<float2*>(at(ws, p.A));
   b.B = reinterpret_cast<float2*>(at(ws, p.B));
   b.C = reinterpret_cast<float2*>(at(ws, p.C));
@@ -1255,17 +1261,20 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
     dj.nt = nt;
     dj.nm = nm;
     dj.scale = sj.scale;
-    dj.dens = dens;
+    dj.delta = reinterpret_cast<float*>(dens);  // the FP32 contrast, in the density region
+    dj.mscale = (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48;
     const Section dep = jp.add1(dj, nt * nt * nt);
-    const R2CSections r = add_r2c(jp, dens, true, (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48, nm, A);
+    const R2CSections r = add_r2c(jp, dj.delta, false, 0.0, nm, A);
     jp.upload(s);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
     stage("clear bins", s, [&] {
       return kern::fill_i32(reinterpret_cast<int*>(sums), static_cast<size_t>(6) * n_bins, 0, s);
     });
     run_sort(jp, ss, sort, flags, s);
-    stage("deposit", s, [&] { return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(dep), jp.table(dep), ss.start, s); });
-    run_r2c(jp, r, true, flags, s);
+    stage("deposit", s, [&] {
+      return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(dep), jp.table(dep), ss.start, flags, s);
+    });
+    run_r2c(jp, r, false, flags, s);
     const double V = geom->box * geom->box * geom->box;
     const double pscale = V / (static_cast<double>(M) * static_cast<double>(M));
     stage("pk bin", s, [&] { return kern::pk_bin(A, nm, pitch, geom->box, k_max, n_bins, pscale, sums, counts, s); });

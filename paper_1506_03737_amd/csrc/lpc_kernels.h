@@ -108,7 +108,9 @@ struct DepJob {         // tiled deposit of one box from its tile-sorted positio
   int64_t n, pbase;
   int tbase, nt, nm;
   double scale;
-  uint64_t* dens;
+  uint64_t* dens;       // int64 counts, or NULL
+  float* delta;         // FP32 density contrast C mscale - 1, or NULL
+  double mscale;
 };
 struct UnsortJob {      // sorted pos / vel back to the caller's order
   const float* spos;
@@ -188,7 +190,7 @@ int scan_blocks(int count);  // entries of the block-sum scratch of launch_scan
 hipError_t launch_scan(const int* cnt, int* start, int count, int* block_sums, hipStream_t s);  // start: count + 1
 hipError_t launch_scatter(const SortJob* jobs, WorkTable wt, const int* key, const int* rank, const int* start,
                           hipStream_t s);
-hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* start, hipStream_t s);
+hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* start, int* flags, hipStream_t s);
 hipError_t launch_unsort(const UnsortJob* jobs, WorkTable wt, hipStream_t s);
 hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, hipStream_t s);
 hipError_t launch_gather(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s);

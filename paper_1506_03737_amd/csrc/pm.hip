@@ -230,7 +230,8 @@ __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ job
 constexpr int kTileCells = kTile * kTile * kTile;
 
 __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict__ jobs, const int* __restrict__ offs,
-                                                       int njob, int total, const int* __restrict__ start) {
+                                                       int njob, int total, const int* __restrict__ start,
+                                                       int* __restrict__ flags) {
   __shared__ unsigned long long acc[kTileCells];
   const int w = blockIdx.x;
   if (w >= total) return;
@@ -311,14 +312,27 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
     }
   }
   __syncthreads();
-  // write the tile (cells outside the mesh on a narrow last tile are skipped)
+  // write the tile (cells outside the mesh on a narrow last tile are skipped): the exact int64 counts, and/or the
+  // FP32 density contrast C mscale - 1 that the forward transform takes (a cell whose count passed 2^63 raises the
+  // overflow flag)
   LPC_GLOBAL unsigned long long* C = to_global(reinterpret_cast<unsigned long long*>(J.dens));
+  LPC_GLOBAL float* D = to_global(J.delta);
+  const double mscale = J.mscale;
   const int wx_ = min(kTile, nm - x0), wy_ = min(kTile, nm - y0), wz_ = min(kTile, nm - z0);
+  bool overflow = false;
   for (int c = tid; c < kTileCells; c += kNT) {
     const int i = c / (kTile * kTile), j = (c / kTile) % kTile, k = c % kTile;
-    if (i < wx_ && j < wy_ && k < wz_)
-      C[(static_cast<size_t>(x0 + i) * nm + (y0 + j)) * nm + (z0 + k)] = acc[c];
+    if (i < wx_ && j < wy_ && k < wz_) {
+      const size_t cell = (static_cast<size_t>(x0 + i) * nm + (y0 + j)) * nm + (z0 + k);
+      const unsigned long long v = acc[c];
+      if (C) C[cell] = v;
+      if (D) {
+        overflow |= (v >> 63) != 0;
+        D[cell] = static_cast<float>(static_cast<double>(v) * mscale - 1.0);
+      }
+    }
   }
+  if (overflow) atomicOr(flags + kFlagOverflow, 1);
 }
 
 // Copy sorted positions and momenta back to the caller's order.
@@ -498,9 +512,9 @@ hipError_t launch_scatter(const SortJob* jobs, WorkTable wt, const int* key, con
   return hipGetLastError();
 }
 
-hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* start, hipStream_t s) {
+hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* start, int* flags, hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_deposit_tiles<<<static_cast<unsigned>(wt.total), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, start);
+  k_deposit_tiles<<<static_cast<unsigned>(wt.total), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, start, flags);
   return hipGetLastError();
 }
 
