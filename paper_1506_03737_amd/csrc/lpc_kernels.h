@@ -75,6 +75,15 @@ __device__ __forceinline__ const LPC_CONST T* to_const(const T* p) {
   return (const LPC_CONST T*)p;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Remap the hardware block index so
+// that each XCD receives a contiguous range of logical tiles: neighbouring tiles (which share cache lines at their
+// edges) then run on the same XCD.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int per = nblocks / 8, rem = nblocks % 8;
+  const int xcd = bid % 8, local = bid / 8;
+  return xcd * per + min(xcd, rem) + local;
+}
+
 struct WorkTable {
   const int* offs;
   int njob;

@@ -238,7 +238,8 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
   const LPC_CONST DepJob& J = to_const(jobs)[jb];
   const int nt = J.nt, nm = J.nm;
-  const int t = w - offs[jb];
+  // neighbouring tiles (which write the two halves of shared 128-byte lines) run on the same XCD
+  const int t = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]);
   if (t >= nt * nt * nt) return;  // padding item
   const int tid = threadIdx.x;
   for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
