@@ -50,7 +50,7 @@ __device__ __forceinline__ int modi(int a, int D) {
 }
 
 template <int CIN, int NB>
-__global__ __launch_bounds__(kNT) void k_conv3(View in, const bf16* __restrict__ w, int kpad,
+__global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(View in, const bf16* __restrict__ w, int kpad,
                                                const float* __restrict__ bias, int act, View out,
                                                float* __restrict__ outf, int cout, int D) {
   constexpr int CC = CIN < 32 ? CIN : 32;   // channels per staged chunk
@@ -74,12 +74,44 @@ __global__ __launch_bounds__(kNT) void k_conv3(View in, const bf16* __restrict__
   const int tsub = g / (CC / 8), cio = 8 * (g % (CC / 8));
   for (int ch = 0; ch < NCH; ++ch) {
     __syncthreads();  // the previous chunk's reads are done
-    for (int e = tid; e < kHalo * (CC / 8); e += kNT) {
-      const int hv = e / (CC / 8), grp = e % (CC / 8);
-      const int hx = hv / (kHY * kHZ), hy = (hv / kHZ) % kHY, hz = hv % kHZ;
-      const int gx = modi(x0 - 1 + hx, D), gy = modi(y0 - 1 + hy, D), gz = modi(z0 - 1 + hz, D);
-      const bf16* src = in.p + static_cast<size_t>((gx * D + gy) * D + gz) * in.ld + in.off + ch * CC + grp * 8;
-      *reinterpret_cast<bf16x8*>(halo + hv * VS + grp * 8) = *reinterpret_cast<const bf16x8*>(src);
+    {
+      // the chunk's loads are issued in at most two batches before they are written to LDS (one or two memory
+      // latencies per chunk; a single batch of 11 loads for 32 channels would not fit the register budget)
+      constexpr int NE = (kHalo * (CC / 8) + kNT - 1) / kNT;
+      constexpr int NB1 = NE > 6 ? (NE + 1) / 2 : NE;
+#pragma unroll
+      for (int m0 = 0; m0 < NE; m0 += NB1) {
+        bf16x8 hbuf[NB1];
+#pragma unroll
+        for (int m = 0; m < NB1; ++m) {
+          const int e = tid + (m0 + m) * kNT;
+          if (m0 + m < NE && e < kHalo * (CC / 8)) {
+            const int hv = e / (CC / 8), grp = e % (CC / 8);
+            const int hx = hv / (kHY * kHZ), hy = (hv / kHZ) % kHY, hz = hv % kHZ;
+            int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+            if (D >= kHZ) {  // one wrap at most (uniform branch)
+              gx = gx < 0 ? gx + D : (gx >= D ? gx - D : gx);
+              gy = gy < 0 ? gy + D : (gy >= D ? gy - D : gy);
+              gz = gz < 0 ? gz + D : (gz >= D ? gz - D : gz);
+            } else {
+              gx = modi(gx, D);
+              gy = modi(gy, D);
+              gz = modi(gz, D);
+            }
+            const bf16* src =
+                in.p + static_cast<size_t>((gx * D + gy) * D + gz) * in.ld + in.off + ch * CC + grp * 8;
+            hbuf[m] = *reinterpret_cast<const bf16x8*>(src);
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < NB1; ++m) {
+          const int e = tid + (m0 + m) * kNT;
+          if (m0 + m < NE && e < kHalo * (CC / 8)) {
+            const int hv = e / (CC / 8), grp = e % (CC / 8);
+            *reinterpret_cast<bf16x8*>(halo + hv * VS + grp * 8) = hbuf[m];
+          }
+        }
+      }
     }
     __syncthreads();
     if (wave_on) {
@@ -405,12 +437,15 @@ __global__ __launch_bounds__(kNT) void k_convert_conv3(const float* __restrict__
   }
 }
 
+// one thread per voxel: six FP32 features in, one 16-byte row of eight BF16 channels out
 __global__ __launch_bounds__(kNT) void k_pack_input(const float* __restrict__ feat, bf16* __restrict__ x, int V) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (idx >= static_cast<int64_t>(V) * 8) return;
-  const int64_t v = idx / 8;
-  const int c = static_cast<int>(idx % 8);
-  x[idx] = static_cast<bf16>(c < kInputChannels ? feat[v * kInputChannels + c] : 0.f);
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (v >= V) return;
+  const float* src = feat + v * kInputChannels;
+  bf16x8 u;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) u[c] = static_cast<bf16>(c < kInputChannels ? src[c] : 0.f);
+  *reinterpret_cast<bf16x8*>(x + v * 8) = u;
 }
 
 __global__ __launch_bounds__(kNT) void k_loss_grad(const float* __restrict__ out, const float* __restrict__ target,
@@ -582,7 +617,7 @@ hipError_t convert_conv3(const float* W, int cout, int cin, bf16* wf, int cinp, 
 }
 
 hipError_t pack_input(const float* feat, bf16* x, int V, hipStream_t s) {
-  k_pack_input<<<blocks_for(static_cast<int64_t>(V) * 8), kNT, 0, s>>>(feat, x, V);
+  k_pack_input<<<blocks_for(V), kNT, 0, s>>>(feat, x, V);
   return hipGetLastError();
 }
 

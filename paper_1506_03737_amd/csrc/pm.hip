@@ -27,8 +27,11 @@ constexpr uint32_t kMask = kOne - 1u;
 __device__ __forceinline__ bool fixed_coord(float x, double scale, int64_t period, uint32_t* cell, uint32_t* frac) {
   const double xs = static_cast<double>(x) * scale;
   if (!(fabs(xs) < 4.0e18)) return false;  // also catches NaN
-  int64_t u = static_cast<int64_t>(floor(xs)) % period;
-  if (u < 0) u += period;
+  int64_t u = static_cast<int64_t>(floor(xs));
+  if (u < 0 || u >= period) {  // positions are normally wrapped already: the 64-bit remainder is rarely needed
+    u %= period;
+    if (u < 0) u += period;
+  }
   *cell = static_cast<uint32_t>(u >> kFracBits);
   *frac = static_cast<uint32_t>(u) & kMask;
   return true;
@@ -268,46 +271,63 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   const int64_t n = J.n;
   const int64_t period = static_cast<int64_t>(nm) << kFracBits;
   LPC_GLOBAL const float* pos = to_global(J.pos);
-  for (int64_t q = tid; q < tot; q += kNT) {
-    int64_t rem = q;
-    int r = 0;
-    while (rem >= rlen[r]) {  // uniform bounds: at most 8 ranges
-      rem -= rlen[r];
-      ++r;
+  // kUnroll particles per thread per round: all their position loads are issued before any is used
+  constexpr int kUnroll = 4;
+  for (int64_t q0 = tid; q0 < tot; q0 += kUnroll * kNT) {
+    float px[kUnroll][3];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t q = q0 + u * kNT;
+      px[u][0] = px[u][1] = px[u][2] = 0.f;
+      if (q < tot) {
+        int64_t rem = q;
+        int r = 0;
+        while (rem >= rlen[r]) {  // at most 8 ranges
+          rem -= rlen[r];
+          ++r;
+        }
+        const int64_t i = rb[r] + rem;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) px[u][d] = pos[d * n + i];
+      }
     }
-    const int64_t i = rb[r] + rem;
-    uint32_t c[3], f[3];
-    bool ok = true;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], J.scale, period, &c[d], &f[d]);
-    if (!ok) continue;  // cannot happen for a bucketed particle; kept as a guard
-    // corner offsets relative to the tile origin (periodic), in [0, kTile) when inside
-    int lx[2], ly[2], lz[2];
+    for (int u = 0; u < kUnroll; ++u) {
+      if (q0 + u * kNT >= tot) continue;
+      uint32_t c[3], f[3];
+      bool ok = true;
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      int cx = static_cast<int>(c[0]) + a, cy = static_cast<int>(c[1]) + a, cz = static_cast<int>(c[2]) + a;
-      if (cx == nm) cx = 0;
-      if (cy == nm) cy = 0;
-      if (cz == nm) cz = 0;
-      lx[a] = cx - x0;
-      ly[a] = cy - y0;
-      lz[a] = cz - z0;
-    }
-    const uint64_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
+      for (int d = 0; d < 3; ++d) ok &= fixed_coord(px[u][d], J.scale, period, &c[d], &f[d]);
+      if (!ok) continue;  // cannot happen for a bucketed particle; kept as a guard
+      // corner offsets relative to the tile origin (periodic), in [0, kTile) when inside
+      int lx[2], ly[2], lz[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      if (static_cast<unsigned>(lx[a]) >= static_cast<unsigned>(kTile)) continue;
+      for (int a = 0; a < 2; ++a) {
+        int cx = static_cast<int>(c[0]) + a, cy = static_cast<int>(c[1]) + a, cz = static_cast<int>(c[2]) + a;
+        if (cx == nm) cx = 0;
+        if (cy == nm) cy = 0;
+        if (cz == nm) cz = 0;
+        lx[a] = cx - x0;
+        ly[a] = cy - y0;
+        lz[a] = cz - z0;
+      }
+      const uint64_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
 #pragma unroll
-      for (int bb = 0; bb < 2; ++bb) {
-        if (static_cast<unsigned>(ly[bb]) >= static_cast<unsigned>(kTile)) continue;
-        const uint64_t wab = wx[a] * wy[bb];
+      for (int a = 0; a < 2; ++a) {
+        if (static_cast<unsigned>(lx[a]) >= static_cast<unsigned>(kTile)) continue;
 #pragma unroll
-        for (int e2 = 0; e2 < 2; ++e2) {
-          if (static_cast<unsigned>(lz[e2]) >= static_cast<unsigned>(kTile)) continue;
-          const uint64_t wt = wab * wz[e2];
-          if (wt != 0)
-            __hip_atomic_fetch_add(&acc[(lx[a] * kTile + ly[bb]) * kTile + lz[e2]], static_cast<unsigned long long>(wt),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int bb = 0; bb < 2; ++bb) {
+          if (static_cast<unsigned>(ly[bb]) >= static_cast<unsigned>(kTile)) continue;
+          const uint64_t wab = wx[a] * wy[bb];
+#pragma unroll
+          for (int e2 = 0; e2 < 2; ++e2) {
+            if (static_cast<unsigned>(lz[e2]) >= static_cast<unsigned>(kTile)) continue;
+            const uint64_t wt = wab * wz[e2];
+            if (wt != 0)
+              __hip_atomic_fetch_add(&acc[(lx[a] * kTile + ly[bb]) * kTile + lz[e2]],
+                                     static_cast<unsigned long long>(wt), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
         }
       }
     }
