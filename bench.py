@@ -38,8 +38,7 @@ HBM_PEAK_GBS = 8000.0
 # a 1 GiB copy), by (stage, mesh size, tile width of the stage); profiles/force_path_768_hbm_traffic.md. Must be
 # re-measured (or removed) when the kernel changes.
 MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 11.145e9, ("fft x + poisson", 768, 8): 7.674e9,
-                    ("fft y", 768, 8): 3.715e9, ("fft z r2c", 768, 16): 3.643e9, ("deposit", 768, None): 2.095e9,
-                    ("gather kick drift", 768, None): 6.537e9}
+                    ("fft y", 768, 8): 3.715e9, ("fft z r2c", 768, 16): 3.643e9}
 
 
 def stage_bytes(stage, n_part, nm, ncomp_y=3):
