@@ -233,10 +233,11 @@ lpc_status lpc_fft_tiling_reset(void);
  *   c1 = conv([u1, s1]: 64 -> 32); u0 = up(c1: 32 -> 16) at N; c0 = conv([u0, s0]: 32 -> 16); out = conv(c0: 16 -> 3).
  * Parameters: one FP32 vector (lpc_net_param_count() values); per layer in the order above, W[Cout][taps][Cin] with
  * taps x-major (t = (tx K + ty) K + tz, K = 3 or 2), then b[Cout]. Loss: mean over voxels and channels of
- * (out - target)^2. Precision: activations and their gradients BF16, 3^3 convolutions and their data gradients on
- * BF16 MFMA with FP32 accumulation, weight gradients FP32 sums of BF16 products, master weights and Adam state FP32.
- * n_side must be a multiple of 4 in [8, 512]. Device buffers are caller-owned; ws holds lpc_net_workspace_bytes()
- * bytes (256-byte aligned) and is scratch for every call below. */
+ * (out - target)^2. Precision: activations and their gradients BF16, 3^3 convolutions (forward and data gradient) and
+ * the forward down/up layers on BF16 MFMA with FP32 accumulation (weights rounded to BF16), weight gradients FP32 sums
+ * of BF16 products, master weights and Adam state FP32. n_side must be a multiple of 4 in [8, 512]. Device buffers
+ * are caller-owned; device params must be 16-byte aligned (LPC_ERR_INVALID_ARG otherwise); ws holds
+ * lpc_net_workspace_bytes() bytes (256-byte aligned) and is scratch for every call below. */
 int64_t lpc_net_param_count(void);
 
 /* Host-side initialisation of params[lpc_net_param_count()] (host FP32): W uniform in +-sqrt(6 / (taps Cin))

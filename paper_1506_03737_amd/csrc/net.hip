@@ -1,6 +1,7 @@
-// Kernels of the learned displacement correction (declared in net_kernels.h). The 3^3 convolutions, forward and
-// data gradient, run on BF16 MFMA with FP32 accumulation; the 2^3 down/up layers, the weight gradients (FP32
-// partial sums per voxel chunk, reduced in a fixed order) and the element-wise steps run on the vector ALUs.
+// Kernels of the learned displacement correction (declared in net_kernels.h). The 3^3 convolutions (forward and data
+// gradient) and the forward 2^3 down/up layers run on BF16 MFMA with FP32 accumulation; the 2^3 data gradients, the
+// weight gradients (FP32 partial sums per voxel chunk, reduced in a fixed order) and the element-wise steps run on
+// the vector ALUs.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -14,14 +15,6 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// Weights read by every thread of a wave at the same address go through the constant address space, so the
-// compiler loads them with scalar instructions. (The host pass of hipcc also parses kernel bodies; there the
-// qualifier is dropped.)
-#if defined(__HIP_DEVICE_COMPILE__)
-#define LPC_NET_CONST __attribute__((address_space(4)))
-#else
-#define LPC_NET_CONST
-#endif
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNT = 256;
@@ -171,78 +164,123 @@ __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(V
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// 2^3 down / up layers: one thread per coarse voxel computes every output channel, reading its input rows as 16-byte
-// vectors; the weights are read through the constant address space (wave-uniform addresses: scalar loads).
-template <int CIN>
-__device__ __forceinline__ void load_row(const bf16* p, float* v) {
-#pragma unroll
-  for (int q = 0; q < CIN / 8; ++q) {
-    const bf16x8 u = *reinterpret_cast<const bf16x8*>(p + 8 * q);
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[8 * q + j] = f(u[j]);
-  }
+// 2^3 down / up layers as GEMMs on v_mfma_f32_16x16x32_bf16 (FP32 accumulation): a wave takes 16 coarse voxels (the
+// rows). The FP32 canonical weights W[o][t][i] are rounded to BF16 as each B fragment is loaded (8 consecutive input
+// channels of one (o, t) per lane). Outputs get the bias and the leaky ReLU and are stored as BF16.
+__device__ __forceinline__ bf16x8 weight_frag(const float* __restrict__ w) {
+  const float4 u = *reinterpret_cast<const float4*>(w), v = *reinterpret_cast<const float4*>(w + 4);
+  bf16x8 r;
+  r[0] = static_cast<bf16>(u.x);
+  r[1] = static_cast<bf16>(u.y);
+  r[2] = static_cast<bf16>(u.z);
+  r[3] = static_cast<bf16>(u.w);
+  r[4] = static_cast<bf16>(v.x);
+  r[5] = static_cast<bf16>(v.y);
+  r[6] = static_cast<bf16>(v.z);
+  r[7] = static_cast<bf16>(v.w);
+  return r;
 }
 
-template <int COUT>
-__device__ __forceinline__ void store_row(bf16* p, const float* acc) {
-#pragma unroll
-  for (int q = 0; q < COUT / 8; ++q) {
-    bf16x8 u;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) u[j] = static_cast<bf16>(leaky(acc[8 * q + j]));
-    *reinterpret_cast<bf16x8*>(p + 8 * q) = u;
-  }
+__device__ __forceinline__ int fine_voxel(int y, int Dc, int t) {  // voxel 2 y + t of the (2 Dc)^3 grid
+  const int yx = y / (Dc * Dc), yy = (y / Dc) % Dc, yz = y % Dc, Df = 2 * Dc;
+  return ((2 * yx + (t >> 2)) * Df + 2 * yy + ((t >> 1) & 1)) * Df + 2 * yz + (t & 1);
 }
 
-// out[y][o] = leaky(b[o] + sum_{t, i} W[o][t][i] x[2y + t][i])   (x on D^3, y on (D/2)^3)
+// Each wave stages its BF16 outputs in its own LDS region and then writes them as 16-byte rows of 8 channels (a lane
+// of the MFMA result holds one channel of four voxels). The kernels keep every wave to the barriers: a wave past the
+// end of the grid only skips its loads and stores.
+
+// out[y][o] = leaky(b[o] + sum_{t, i} W[o][t][i] x[2y + t][i])   (x on D^3, y on (D/2)^3): K = 8 CIN as (t, i).
 template <int CIN, int COUT>
-__global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__ Wg, const float* __restrict__ bg,
+__global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__ W, const float* __restrict__ b,
                                                View out, int D) {
-  const int Dc = D / 2;
-  const int y = blockIdx.x * kNT + threadIdx.x;
-  if (y >= Dc * Dc * Dc) return;
-  const LPC_NET_CONST float* W = (const LPC_NET_CONST float*)(Wg);
-  const LPC_NET_CONST float* b = (const LPC_NET_CONST float*)(bg);
-  const int yx = y / (Dc * Dc), yy = (y / Dc) % Dc, yz = y % Dc;
-  float acc[COUT];
+  static_assert(CIN % 8 == 0 && COUT % 16 == 0, "fragment shapes");
+  constexpr int KS = 8 * CIN / 32, NBLK = COUT / 16;
+  __shared__ bf16 stage[4][16 * COUT];
+  const int Dc = D / 2, Vc = Dc * Dc * Dc;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int y0 = (blockIdx.x * 4 + wave) * 16;
+  const int y = y0 + r;
+  const bool row_ok = y < Vc;
+  f32x4 acc[NBLK];
 #pragma unroll
-  for (int o = 0; o < COUT; ++o) acc[o] = b[o];
-#pragma unroll 1
-  for (int t = 0; t < 8; ++t) {
-    const int xv = ((2 * yx + (t >> 2)) * D + 2 * yy + ((t >> 1) & 1)) * D + 2 * yz + (t & 1);
-    float xr[CIN];
-    load_row<CIN>(x.p + static_cast<size_t>(xv) * x.ld + x.off, xr);
+  for (int nb = 0; nb < NBLK; ++nb) acc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < CIN; ++i)
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = 32 * ks + 8 * g, t = k / CIN, i0 = k % CIN;
+    bf16x8 a;
 #pragma unroll
-      for (int o = 0; o < COUT; ++o) acc[o] += W[(o * 8 + t) * CIN + i] * xr[i];
+    for (int j = 0; j < 8; ++j) a[j] = static_cast<bf16>(0.f);
+    if (row_ok)
+      a = *reinterpret_cast<const bf16x8*>(x.p + static_cast<size_t>(fine_voxel(y, Dc, t)) * x.ld + x.off + i0);
+#pragma unroll
+    for (int nb = 0; nb < NBLK; ++nb) {
+      const int o = nb * 16 + r;
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, weight_frag(W + (o * 8 + t) * CIN + i0), acc[nb], 0, 0, 0);
+    }
   }
-  store_row<COUT>(out.p + static_cast<size_t>(y) * out.ld + out.off, acc);
+  bf16* st = stage[wave];
+#pragma unroll
+  for (int nb = 0; nb < NBLK; ++nb) {
+    const int o = nb * 16 + r;
+    const float bo = b[o];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st[(4 * g + j) * COUT + o] = static_cast<bf16>(leaky(acc[nb][j] + bo));
+  }
+  __syncthreads();
+  constexpr int NCH = 16 * COUT / 8;  // 16-byte chunks of the wave's rows
+#pragma unroll
+  for (int c = lane; c < NCH; c += 64) {
+    const int row = c / (COUT / 8), q8 = c % (COUT / 8);
+    const int yr = y0 + row;
+    if (yr < Vc)
+      *reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>(yr) * out.ld + out.off + 8 * q8) =
+          *reinterpret_cast<const bf16x8*>(st + row * COUT + 8 * q8);
+  }
 }
 
-// out[2y + t][o] = leaky(b[o] + sum_i W[o][t][i] x[y][i])   (x on D^3, out on (2D)^3)
+// out[2y + t][o] = leaky(b[o] + sum_i W[o][t][i] x[y][i])   (x on D^3, out on (2D)^3): N = 8 COUT as (t, o).
 template <int CIN, int COUT>
-__global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ Wg, const float* __restrict__ bg,
+__global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ W, const float* __restrict__ b,
                                              View out, int D) {
-  const int y = blockIdx.x * kNT + threadIdx.x;
-  if (y >= D * D * D) return;
-  const LPC_NET_CONST float* W = (const LPC_NET_CONST float*)(Wg);
-  const LPC_NET_CONST float* b = (const LPC_NET_CONST float*)(bg);
-  const int yx = y / (D * D), yy = (y / D) % D, yz = y % D;
-  const int Df = 2 * D;
-  float xr[CIN];
-  load_row<CIN>(x.p + static_cast<size_t>(y) * x.ld + x.off, xr);
-#pragma unroll 1
-  for (int t = 0; t < 8; ++t) {
-    float acc[COUT];
+  static_assert(CIN % 32 == 0 && COUT % 16 == 0, "fragment shapes");
+  constexpr int KS = CIN / 32, NBLK = 8 * COUT / 16;
+  __shared__ bf16 stage[4][16 * 8 * COUT];  // [coarse row][tap][channel] per wave
+  const int V = D * D * D;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const int y0 = (blockIdx.x * 4 + wave) * 16;
+  const int y = y0 + r;
+  bf16x8 A[KS];
 #pragma unroll
-    for (int o = 0; o < COUT; ++o) acc[o] = b[o];
+  for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-    for (int i = 0; i < CIN; ++i)
+    for (int j = 0; j < 8; ++j) A[ks][j] = static_cast<bf16>(0.f);
+    if (y < V) A[ks] = *reinterpret_cast<const bf16x8*>(x.p + static_cast<size_t>(y) * x.ld + x.off + 32 * ks + 8 * g);
+  }
+  bf16* st = stage[wave];
+#pragma unroll 2
+  for (int nb = 0; nb < NBLK; ++nb) {
+    const int n = nb * 16 + r, t = n / COUT, o = n % COUT;  // t is uniform over the block (COUT >= 16)
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int o = 0; o < COUT; ++o) acc[o] += W[(o * 8 + t) * CIN + i] * xr[i];
-    const int q = ((2 * yx + (t >> 2)) * Df + 2 * yy + ((t >> 1) & 1)) * Df + 2 * yz + (t & 1);
-    store_row<COUT>(out.p + static_cast<size_t>(q) * out.ld + out.off, acc);
+    for (int ks = 0; ks < KS; ++ks)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks], weight_frag(W + (o * 8 + t) * CIN + 32 * ks + 8 * g), acc,
+                                                    0, 0, 0);
+    const float bo = b[o];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st[((4 * g + j) * 8 + t) * COUT + o] = static_cast<bf16>(leaky(acc[j] + bo));
+  }
+  __syncthreads();
+  constexpr int NCH = 16 * 8 * COUT / 8;  // 16-byte chunks: (coarse row, tap, channel group)
+#pragma unroll
+  for (int c = lane; c < NCH; c += 64) {
+    const int row = c / (8 * COUT / 8), rest = c % (8 * COUT / 8), t = rest / (COUT / 8), q8 = rest % (COUT / 8);
+    const int yr = y0 + row;
+    if (yr < V)
+      *reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>(fine_voxel(yr, D, t)) * out.ld + out.off + 8 * q8) =
+          *reinterpret_cast<const bf16x8*>(st + (row * 8 + t) * COUT + 8 * q8);
   }
 }
 
@@ -552,7 +590,7 @@ hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float*
 }
 
 hipError_t down2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
-  const unsigned grid = blocks_for(static_cast<int64_t>(D / 2) * (D / 2) * (D / 2));
+  const unsigned grid = blocks_for(static_cast<int64_t>(D / 2) * (D / 2) * (D / 2), 64);  // 64 coarse voxels per block
   if (cin == 16 && cout == 32) k_down2<16, 32><<<grid, kNT, 0, s>>>(x, W, b, out, D);
   else if (cin == 32 && cout == 64) k_down2<32, 64><<<grid, kNT, 0, s>>>(x, W, b, out, D);
   else return hipErrorInvalidValue;
@@ -560,7 +598,7 @@ hipError_t down2(View x, int cin, const float* W, const float* b, int cout, View
 }
 
 hipError_t up2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
-  const unsigned grid = blocks_for(static_cast<int64_t>(D) * D * D);
+  const unsigned grid = blocks_for(static_cast<int64_t>(D) * D * D, 64);  // 64 coarse voxels per block
   if (cin == 64 && cout == 32) k_up2<64, 32><<<grid, kNT, 0, s>>>(x, W, b, out, D);
   else if (cin == 32 && cout == 16) k_up2<32, 16><<<grid, kNT, 0, s>>>(x, W, b, out, D);
   else return hipErrorInvalidValue;

@@ -143,6 +143,12 @@ NetWs layout(void* base, int D) {
 
 bool size_ok(int D) { return D >= 8 && D <= 512 && (D % 4) == 0; }
 
+// The down/up layers read weights as 16-byte vectors (every layer's W starts at a multiple of 8 values).
+lpc_status check_params(const float* params) {
+  if (reinterpret_cast<uintptr_t>(params) % 16 != 0) return fail(LPC_ERR_INVALID_ARG, "params must be 16-byte aligned");
+  return LPC_OK;
+}
+
 lpc_status check_net_ws(int D, void* ws, size_t ws_bytes, NetWs* out) {
   if (!size_ok(D)) return fail(LPC_ERR_UNSUPPORTED_SIZE, "n_side = %d: need a multiple of 4 in [8, 512]", D);
   if (!ws) return fail(LPC_ERR_INVALID_ARG, "workspace pointer is NULL");
@@ -322,6 +328,7 @@ lpc_status lpc_net_features(const lpc_geometry* geom, const float* pos, const in
 lpc_status lpc_net_forward(int32_t n_side, const float* params, const float* feat, float* out, void* ws,
                            size_t ws_bytes, void* stream) {
   if (!params || !feat || !out) return fail(LPC_ERR_INVALID_ARG, "NULL argument");
+  if (lpc_status st = check_params(params)) return st;
   NetWs w;
   if (lpc_status st = check_net_ws(n_side, ws, ws_bytes, &w)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -339,6 +346,7 @@ lpc_status lpc_net_forward(int32_t n_side, const float* params, const float* fea
 lpc_status lpc_net_loss_grad(int32_t n_side, const float* params, const float* feat, const float* target,
                              float* grad, double* loss, void* ws, size_t ws_bytes, void* stream) {
   if (!params || !feat || !target || !grad || !loss) return fail(LPC_ERR_INVALID_ARG, "NULL argument");
+  if (lpc_status st = check_params(params)) return st;
   NetWs w;
   if (lpc_status st = check_net_ws(n_side, ws, ws_bytes, &w)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -377,6 +385,7 @@ lpc_status lpc_net_apply(const lpc_geometry* geom, const float* params, const lp
   if (!geom || !params || !inout || !inout->pos || !inout->psi1 || !inout->id)
     return fail(LPC_ERR_INVALID_ARG, "NULL argument (params, pos, psi1 and id are needed)");
   if (!(geom->box > 0.0) || !std::isfinite(geom->box)) return fail(LPC_ERR_INVALID_ARG, "box must be positive");
+  if (lpc_status st = check_params(params)) return st;
   const int N = geom->n_side;
   NetWs w;
   if (lpc_status st = check_net_ws(N, ws, ws_bytes, &w)) return st;

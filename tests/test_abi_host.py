@@ -242,3 +242,18 @@ def test_fft_tiling_defaults_overrides_and_rejections():
             assert e.value.status == -2
     finally:
         lpc.lpc_fft_tiling_reset()
+
+
+def test_net_entry_points_reject_misaligned_params():
+    """The network's down/up layers read weights as 16-byte vectors: a params pointer off a 16-byte boundary is an
+    argument error, reported before any device work (the fake pointers below are never dereferenced)."""
+    from paper_1506_03737_amd import lpc
+    lib = lpc.LIB
+    loss = ctypes.c_double()
+    vp = ctypes.c_void_p
+    bad = vp(0x100004)
+    ok = vp(0x100000)
+    st = lib.lpc_net_forward(16, bad, ok, ok, ok, 1 << 20, None)
+    assert st == -1 and b"16-byte" in lib.lpc_last_error()
+    st = lib.lpc_net_loss_grad(16, bad, ok, ok, ok, ctypes.byref(loss), ok, 1 << 20, None)
+    assert st == -1 and b"16-byte" in lib.lpc_last_error()
