@@ -108,6 +108,13 @@ __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(V
     }
     __syncthreads();
     if (wave_on) {
+      // k of this lane's 8 values at step s: tap * CIN + ch * CC + cio (a padding tap points into the zero tail of the
+      // row). The weight fragments of step s + 1 are loaded (from global memory) while step s runs.
+      const bf16* wlane = w + static_cast<size_t>(r) * kpad + ch * CC + cio;
+      bf16x8 Bn[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        Bn[nb] = *reinterpret_cast<const bf16x8*>(wlane + static_cast<size_t>(nb * 16) * kpad + tsub * CIN);
 #pragma unroll 3
       for (int s = 0; s < NS; ++s) {
         const int tap = s * TPS + tsub;
@@ -115,6 +122,14 @@ __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(V
         const int tt = tap_ok ? tap : 26;
         const int tx = tt / 9, ty = (tt / 3) % 3, tz = tt % 3;
         const bf16* abase = halo + ((wave + tx) * kHY * kHZ + ty * kHZ + r + tz) * VS + cio;
+        bf16x8 B[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) B[nb] = Bn[nb];
+        if (s + 1 < NS) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            Bn[nb] = *reinterpret_cast<const bf16x8*>(wlane + static_cast<size_t>(nb * 16) * kpad + (tap + TPS) * CIN);
+        }
         bf16x8 A[4];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
@@ -125,14 +140,11 @@ __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(V
           }
           A[mt] = a;
         }
-        // k of this lane's 8 values: tap * CIN + ch * CC + cio (a padding tap points into the zero tail of the row)
-        const int k0 = tap * CIN + ch * CC + cio;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          const bf16x8 B = *reinterpret_cast<const bf16x8*>(w + static_cast<size_t>(nb * 16 + r) * kpad + k0);
 #pragma unroll
           for (int mt = 0; mt < 4; ++mt)
-            acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B, acc[mt][nb], 0, 0, 0);
+            acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nb], acc[mt][nb], 0, 0, 0);
         }
       }
     }
