@@ -37,8 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes (read scaled by 2.0, write by 1.0, from
 # a 1 GiB copy), by (stage, mesh size, tile width of the stage); profiles/force_path_768_hbm_traffic.md. Must be
 # re-measured (or removed) when the kernel changes.
-MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 11.145e9, ("fft x + poisson", 768, 8): 7.674e9,
-                    ("fft y", 768, 8): 3.715e9, ("fft z r2c", 768, 16): 3.643e9}
+MEASURED_TRAFFIC = {("fft y", 768, 8): 3.715e9, ("fft z r2c", 768, 16): 3.643e9}
 
 
 def stage_bytes(stage, n_part, nm, ncomp_y=3):
@@ -52,8 +51,8 @@ def stage_bytes(stage, n_part, nm, ncomp_y=3):
         "deposit": 12 * n_part + 4 * M,     # read positions, the FP32 density contrast written once
         "fft z r2c": 4 * M + H,             # read the FP32 contrast, write half spectrum
         "fft y": 2 * H,
-        "fft x + poisson": H + 3 * H,       # read delta_hat, write three gradient spectra
-        "fft y inv": 2 * 3 * H,
+        "fft x + poisson": H + 2 * H,       # read delta_hat, write the x gradient and the potential
+        "fft y inv": 2 * H + 3 * H,         # x gradient in place; read the potential, write its y gradient and itself
         "fft z c2r": 3 * H + 12 * M,        # read three spectra, write the AoS float3 force mesh
         "gather kick drift": 72 * n_part + 12 * corners,
         "frame velocity": 48 * n_part,      # read vel, psi1, psi2; write vel

@@ -581,7 +581,8 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
   std::vector<kern::PartJob> pj[2];
   std::vector<kern::UnsortJob> uj[2];
   std::vector<kern::ZR2CJob> zs;
-  std::vector<kern::AxisJob> ys, yis;
+  std::vector<kern::AxisJob> ys;
+  std::vector<kern::YGradJob> yis;
   std::vector<kern::PoissonJob> ps;
   std::vector<kern::ZC2RJob> cs;
   std::vector<int> i_part, i_frame, i_tile, i_z, i_y, i_yi, i_p, i_c;
@@ -674,9 +675,21 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     kern::AxisJob y = axis_job(jp, b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, 0, f.Bax);
     ys.push_back(y);
     i_y.push_back(y.per_comp);
-    kern::AxisJob yi = axis_job(jp, b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, static_cast<int64_t>(b.B - b.A), f.Bax);
+    kern::YGradJob yi{};
+    yi.A = b.A;
+    yi.B = b.B;
+    yi.C = b.C;
+    yi.astr = pitch;
+    yi.ostr = static_cast<int64_t>(nm) * pitch;
+    yi.n = nm;
+    yi.ncols = nh;
+    yi.ntc = (nh + f.Bax - 1) / f.Bax;
+    yi.per_comp = round8(nm * yi.ntc);
+    yi.kf = static_cast<float>(2.0 * M_PI / b.box);
+    yi.pl = plan_of(nm);
+    yi.tw = jp.twiddles(yi.pl);
     yis.push_back(yi);
-    i_yi.push_back(3 * yi.per_comp);
+    i_yi.push_back(2 * yi.per_comp);  // component 0: the x gradient; 1: the potential (y and z gradients)
     kern::PoissonJob p{};
     p.A = b.A;
     p.B = b.B;
@@ -701,6 +714,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     c.nrows = nm * nm;
     c.pitch = pitch;
     c.scale = 1.0f;
+    c.kz3 = static_cast<float>(2.0 * M_PI / b.box);  // C holds the potential: i k_z applied on load
     c.pl = plan_of(nm / 2);
     c.tw = jp.twiddles(c.pl);
     c.roots = jp.half_roots(nm);
@@ -749,7 +763,7 @@ void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags,
   });
   stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.Pax, f.lds_ax, s); });
   stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.Mp, f.lds_p, s); });
-  stage("fft y inv", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yinv), jp.table(f.yinv), true, f.Bax, f.Pax, f.lds_ax, s); });
+  stage("fft y inv", s, [&] { return kern::launch_y_grad(jp.jobs<kern::YGradJob>(f.yinv), jp.table(f.yinv), f.Bax, f.Pax, f.lds_ax, s); });
   stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(f.zc2r), jp.table(f.zc2r), 3, f.R3, f.P3, f.lds_c, s); });
 }
 

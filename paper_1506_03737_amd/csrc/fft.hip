@@ -317,11 +317,99 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : (EPT <= 12 ? 5 : 4)) void 
 }
 
 // ---------------------------------------------------------------------------------------------------------------
+// Inverse y pass of the force. Items of component 0 transform A (the x gradient) in place. Items of component 1 read
+// the x-transformed potential psi from C once, transform i k_y psi into B and psi itself back into C (k_z is constant
+// along y; the z pass applies i k_z as it loads C). With EPT <= 12 each thread keeps its own points of psi (column b,
+// rows j0 + m S) in registers between the two transforms; with EPT = 16 (the registers would spill) psi is loaded
+// again from C, which this item has not yet overwritten.
+template <int B, int EPT>
+__global__ __launch_bounds__(kFftNT, EPT <= 12 ? 4 : 2) void k_fft_y_grad(const YGradJob* __restrict__ jobs,
+                                                          const int* __restrict__ offs, int njob, int total) {
+  constexpr int BP = strided_pitch(B), S = kFftNT / B, H = EPT / 2;
+  extern __shared__ float2 smem[];
+  const int w = blockIdx.x;
+  const int tid = threadIdx.x;
+  if (w >= total) return;
+  const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+  const LPC_CONST YGradJob& J = to_const(jobs)[jb];
+  const int local = w - offs[jb];
+  const int comp = local / J.per_comp;
+  const int t = xcd_remap(local - comp * J.per_comp, J.per_comp);
+  const int outer = t / J.ntc, ct = t - outer * J.ntc;
+  const int n = J.n;
+  if (outer >= n) return;  // padding item
+  const int c0 = ct * B, bw = min(B, J.ncols - c0);
+  float2* tile = smem;
+  float2* tw = smem + n * BP;
+  const int64_t off = static_cast<int64_t>(outer) * J.ostr + c0;
+  {
+    LPC_GLOBAL const float2* src = to_global(comp == 0 ? J.A + off : J.C + off);
+    float2 v[H];
+    const TableRegs<float2> tt = table_load(J.tw, n, tid);
+    strided_issue<B, H>(v, src, J.astr, n, bw, tid, 0);
+    table_store(tw, tt, n, tid);
+    strided_put<B, H>(tile, v, n, tid, 0);
+    strided_issue<B, H>(v, src, J.astr, n, bw, tid, 1);
+    strided_put<B, H>(tile, v, n, tid, 1);
+  }
+  __syncthreads();
+  if (comp == 0) {  // uniform
+    fft_tile<true, EPT>(tile, tw, J.pl, B, BP, tid);
+    store_strided<B, EPT>(tile, to_global(J.A + off), J.astr, n, bw, tid);
+    return;
+  }
+  constexpr bool kRegs = EPT <= 12;
+  const int half = n / 2;
+  const float kf = J.kf;
+  float2 ph[kRegs ? EPT : 1];  // n B <= EPT kFftNT, so n / S <= EPT
+  {
+    const int b = tid % B, j0 = tid / B;
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int j = j0 + m * S;
+      if (j < n) {
+        const float2 v = tile[j * BP + b];
+        if (kRegs) ph[kRegs ? m : 0] = v;
+        const float ky = (j == half) ? 0.f : kf * static_cast<float>(j <= half ? j : j - n);
+        tile[j * BP + b] = make_float2(-ky * v.y, ky * v.x);  // i k_y psi
+      }
+    }
+  }
+  __syncthreads();
+  fft_tile<true, EPT>(tile, tw, J.pl, B, BP, tid);
+  store_strided<B, EPT>(tile, to_global(J.B + off), J.astr, n, bw, tid);
+  __syncthreads();
+  {
+    // (the empty asm keeps the first transform's thread-dependent addresses from staying live across the second)
+    int ltid = tid;
+    asm volatile("" : "+v"(ltid));
+    if (kRegs) {
+      const int b = ltid % B, j0 = ltid / B;
+#pragma unroll
+      for (int m = 0; m < EPT; ++m) {
+        const int j = j0 + m * S;
+        if (j < n) tile[j * BP + b] = ph[kRegs ? m : 0];
+      }
+    } else {
+      LPC_GLOBAL const float2* src = to_global(J.C + off);
+      float2 v[H];
+      strided_issue<B, H>(v, src, J.astr, n, bw, ltid, 0);
+      strided_put<B, H>(tile, v, n, ltid, 0);
+      strided_issue<B, H>(v, src, J.astr, n, bw, ltid, 1);
+      strided_put<B, H>(tile, v, n, ltid, 1);
+    }
+    __syncthreads();
+    fft_tile<true, EPT>(tile, tw, J.pl, B, BP, ltid);
+    store_strided<B, EPT>(tile, to_global(J.C + off), J.astr, n, bw, ltid);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
 // Fused x pass of the force. With psi_hat = -delta_hat / (k^2 W^p Nm^3) (zero at k = 0; W = prod_d sinc^2(pi n_d /
 // Nm); the 1/Nm^3 of the inverse transform folded in), the gradient spectra are g_hat_j = i k_j psi_hat, zero on the
 // Nyquist plane of axis j. Along the x transform k_y and k_z are constant (per tile and per column), so
-//   IFFT_x(g_hat_x) = IFFT_x(i k_x psi_hat),   IFFT_x(g_hat_{y,z}) = i k_{y,z} IFFT_x(psi_hat):
-// one forward and two inverse transforms per tile. psi_hat is kept between them. Each thread owns the points of column
+//   IFFT_x(g_hat_x) = IFFT_x(i k_x psi_hat) -> A,   IFFT_x(g_hat_{y,z}) = i k_{y,z} IFFT_x(psi_hat), IFFT_x(psi_hat) -> C:
+// one forward and two inverse transforms per tile, two spectra written. psi_hat is kept between them. Each thread owns the points of column
 // b at rows j0 + m S, at most M of them (M = n B / kFftNT rounded up to 8, 12 or 16): with M <= 12 they stay in the
 // thread's registers, so the workgroup needs one LDS tile and two workgroups fit on a CU; with M = 16 a second LDS
 // tile holds them (the registers would spill).
@@ -413,23 +501,8 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
       }
       __syncthreads();
       fft_tile<true, M>(tile, tw, J.pl, B, BP, ltid);
-      // y and z components: i k_y and i k_z times the transformed potential, zero on their Nyquist planes
-      const float ky = (ny == half) ? 0.f : kf * static_cast<float>(ny);
-      LPC_GLOBAL float2* gy = to_global(J.B + off);
-      LPC_GLOBAL float2* gz = to_global(J.C + off);
-      const int count = n * B;
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const int e = ltid + m * kFftNT;
-        const int jr = e / B, bc = e % B;
-        if (e < count && bc < bw) {
-          const int nzc = c0 + bc;
-          const float kz = (nzc == half) ? 0.f : kf * static_cast<float>(nzc);
-          const float2 v = tile[jr * BP + bc];
-          gy[jr * astr + bc] = make_float2(-ky * v.y, ky * v.x);
-          gz[jr * astr + bc] = make_float2(-kz * v.y, kz * v.x);
-        }
-      }
+      // the x-transformed potential: the y and z gradients are i k_y and i k_z times it (applied by the y and z passes)
+      store_strided<B, M>(tile, to_global(J.C + off), astr, n, bw, ltid);
     }
   }
 }
@@ -462,6 +535,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     LPC_GLOBAL const float2* in1 = to_global(J.in1);
     LPC_GLOBAL const float2* in2 = to_global(J.in2);
     const int h1 = h + 1, count = B * h1;
+    const float kz3 = J.kz3;
     // Element e = tid + m kFftNT is (tile column col, frequency k) = divmod(e, h + 1): one division per thread, then
     // steps of kFftNT = dq (h + 1) + dr.
     const int dq = kFftNT / h1, dr = kFftNT - dq * h1;
@@ -491,7 +565,13 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
 #pragma unroll
       for (int m = 0; m < EPT + 1; ++m) {
         const int e = tid + m * kFftNT;
-        if (e < count) tile[k * BP + col] = v[m];
+        float2 x = v[m];
+        // the third spectrum is psi: i k_z psi, zero on the Nyquist plane (applied here, once every load is issued)
+        if (NC == 3 && col >= 2 * R && kz3 != 0.f) {
+          const float kz = (k == h) ? 0.f : kz3 * static_cast<float>(k);
+          x = make_float2(-kz * x.y, kz * x.x);
+        }
+        if (e < count) tile[k * BP + col] = x;
         col += dq;
         k += dr;
         if (k >= h1) {
@@ -604,6 +684,15 @@ struct Init {
     allow_big_lds(k_fft_axis<false, 32, 8>);
     allow_big_lds(k_fft_axis<false, 32, 12>);
     allow_big_lds(k_fft_axis<false, 32, 16>);
+    allow_big_lds(k_fft_y_grad<8, 8>);
+    allow_big_lds(k_fft_y_grad<8, 12>);
+    allow_big_lds(k_fft_y_grad<8, 16>);
+    allow_big_lds(k_fft_y_grad<16, 8>);
+    allow_big_lds(k_fft_y_grad<16, 12>);
+    allow_big_lds(k_fft_y_grad<16, 16>);
+    allow_big_lds(k_fft_y_grad<32, 8>);
+    allow_big_lds(k_fft_y_grad<32, 12>);
+    allow_big_lds(k_fft_y_grad<32, 16>);
     allow_big_lds(k_fft_x_poisson<4, 8>);
     allow_big_lds(k_fft_x_poisson<8, 8>);
     allow_big_lds(k_fft_x_poisson<8, 12>);
@@ -746,6 +835,21 @@ hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, i
   }
 #undef LPC_AXIS_P
 #undef LPC_AXIS
+  return hipGetLastError();
+}
+
+hipError_t launch_y_grad(const YGradJob* jobs, WorkTable wt, int B, int P, size_t lds, hipStream_t s) {
+  ensure_init();
+  const unsigned g = item_grid(wt.total);
+  if (g == 0) return hipSuccess;
+#define LPC_YG(BB, PP) k_fft_y_grad<BB, PP><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+#define LPC_YG_P(BB) \
+  if (P == 8) LPC_YG(BB, 8); else if (P == 12) LPC_YG(BB, 12); else if (P == 16) LPC_YG(BB, 16); \
+  else return hipErrorInvalidValue
+  if (B == 8) { LPC_YG_P(8); } else if (B == 16) { LPC_YG_P(16); } else if (B == 32) { LPC_YG_P(32); }
+  else return hipErrorInvalidValue;
+#undef LPC_YG_P
+#undef LPC_YG
   return hipGetLastError();
 }
 

@@ -169,10 +169,19 @@ struct PoissonJob {     // fused forward x / Poisson-gradient / inverse x of one
   float kf, inv_m3;
   Plan1D pl;
 };
+struct YGradJob {       // inverse y pass of the force: A in place; i k_y psi (from C) into B, psi back into C
+  float2 *A, *B, *C;
+  const float2* tw;
+  int64_t astr, ostr;   // stride along y, stride of the outer (x) index
+  int n, ncols, ntc, per_comp;
+  float kf;             // 2 pi / L
+  Plan1D pl;
+};
 struct ZC2RJob {        // inverse z pass of NC spectra of one mesh
   const float2 *in0, *in1, *in2;
   float* out;
   const float2 *tw, *roots;
+  float kz3;            // if nonzero (NC = 3): the third spectrum is psi, taken as i k_z psi with k_z = kz3 k
   int n, nrows, pitch;
   float scale;
   Plan1D pl;            // length n / 2
@@ -209,6 +218,7 @@ hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, h
 void init_kernels();
 hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, size_t lds, int* flags, hipStream_t s);
 hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, int P, size_t lds, hipStream_t s);
+hipError_t launch_y_grad(const YGradJob* jobs, WorkTable wt, int B, int P, size_t lds, hipStream_t s);
 hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, size_t lds, hipStream_t s);
 hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, int P, size_t lds, hipStream_t s);
 
