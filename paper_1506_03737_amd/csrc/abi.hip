@@ -364,7 +364,10 @@ class JobPack {
   }
   // Stage twiddles of plan pl (Plan1D layout, pl.n entries): W_{pR}^{r k} at tw_off[s] + k (R - 1) + r - 1.
   const float2* twiddles(const Plan1D& pl) {
-    auto it = tw_.find(pl.n);
+    // keyed by the radix sequence as well: two plans of one length may differ
+    int64_t key = pl.n;
+    for (int st = 0; st < pl.nst; ++st) key = key * 16 + pl.radix[st];
+    auto it = tw_.find(key);
     if (it == tw_.end()) {
       std::vector<float2> t(static_cast<size_t>(pl.n), make_float2(1.f, 0.f));
       for (int st = 0; st < pl.nst; ++st) {
@@ -374,7 +377,7 @@ class JobPack {
             t[static_cast<size_t>(pl.tw_off[st] + k * (R - 1) + r - 1)] =
                 unit_root(static_cast<int64_t>(r) * k, static_cast<int64_t>(p) * R);
       }
-      it = tw_.emplace(pl.n, append(t.data(), t.size() * sizeof(float2))).first;
+      it = tw_.emplace(key, append(t.data(), t.size() * sizeof(float2))).first;
     }
     return reinterpret_cast<const float2*>(dev_ + it->second);
   }
@@ -419,12 +422,13 @@ class JobPack {
   }
   std::vector<char> host_;
   char* dev_;
-  std::map<int, size_t> tw_, roots_, win_;
+  std::map<int64_t, size_t> tw_;
+  std::map<int, size_t> roots_, win_;
 };
 
-Plan1D plan_of(int n) {
+Plan1D plan_of(int n, bool radix12 = true) {
   Plan1D p;
-  if (!kern::make_plan(n, &p)) throw HipError{hipErrorInvalidValue, "unsupported FFT length"};
+  if (!kern::make_plan(n, &p, radix12)) throw HipError{hipErrorInvalidValue, "unsupported FFT length"};
   return p;
 }
 
@@ -715,7 +719,8 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     c.pitch = pitch;
     c.scale = 1.0f;
     c.kz3 = static_cast<float>(2.0 * M_PI / b.box);  // C holds the potential: i k_z applied on load
-    c.pl = plan_of(nm / 2);
+    // this pass sits at its register cap (six waves per SIMD); the radix-12 stage would push it into scratch
+    c.pl = plan_of(nm / 2, false);
     c.tw = jp.twiddles(c.pl);
     c.roots = jp.half_roots(nm);
     cs.push_back(c);

@@ -21,7 +21,7 @@
 namespace lpc {
 namespace kern {
 
-bool make_plan(int n, Plan1D* p) {
+bool make_plan(int n, Plan1D* p, bool radix12) {
   if (n < 1) return false;
   int m = n, ns = 0;
   int odd[kMaxStages];
@@ -50,11 +50,21 @@ bool make_plan(int n, Plan1D* p) {
   for (int i = 0; i < n8; ++i) pow2[np++] = 8;
   if (rem == 1) pow2[np++] = 2;
   if (rem == 2) pow2[np++] = 4;
-  if (ns + np > kMaxStages) return false;
+  // a radix-4 and a radix-3 stage merge into one radix-12 stage (one LDS round trip fewer)
+  int i4 = -1, i3 = -1;
+  for (int i = 0; i < np; ++i)
+    if (pow2[i] == 4) i4 = i;
+  for (int i = 0; i < ns; ++i)
+    if (odd[i] == 3) i3 = i;
+  const bool r12 = radix12 && i4 >= 0 && i3 >= 0;
+  if (ns + np - (r12 ? 1 : 0) > kMaxStages) return false;
   p->n = n;
   p->nst = 0;
-  for (int i = 0; i < np; ++i) p->radix[p->nst++] = pow2[i];
-  for (int i = 0; i < ns; ++i) p->radix[p->nst++] = odd[i];
+  for (int i = 0; i < np; ++i)
+    if (!(r12 && i == i4)) p->radix[p->nst++] = pow2[i];
+  if (r12) p->radix[p->nst++] = 12;
+  for (int i = 0; i < ns; ++i)
+    if (!(r12 && i == i3)) p->radix[p->nst++] = odd[i];
   int prod = 1, off = 0;
   for (int s = 0; s < p->nst; ++s) {
     p->p[s] = prod;
@@ -606,7 +616,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
       }
     }
     __syncthreads();
-    fft_tile<true, EPT>(tile, tw, J.pl, B, BP, tid);
+    fft_tile<true, EPT, NC != 3>(tile, tw, J.pl, B, BP, tid);  // NC = 3: plans without radix 12
     const int rowlen = NC * n;
     LPC_GLOBAL float* out = to_global(J.out);
     const float scale = J.scale;

@@ -113,6 +113,29 @@ struct Dft<5, INV> {
   }
 };
 
+// 12 points as 4 x 3 by the prime-factor (Good-Thomas) mapping, which needs no twiddles because 4 and 3 are coprime:
+// input n = (3 a + 4 b) mod 12 and output k = (9 a + 4 b) mod 12 for a < 4, b < 3, since n k = 3 a a' + 4 b b' mod 12.
+// Four-point transforms over a for each b, then three-point transforms over b for each a.
+template <bool INV>
+struct Dft<12, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 y[3][4];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) y[b][a] = v[(3 * a + 4 * b) % 12];
+      Dft<4, INV>::run(y[b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      float2 z[3] = {y[0][a], y[1][a], y[2][a]};
+      Dft<3, INV>::run(z);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) v[(9 * a + 4 * b) % 12] = z[b];
+    }
+  }
+};
+
 // Thread geometry of a tile with B columns and row pitch BP: threads t < S B (S = kFftNT / B) own column
 // b = t mod B and butterflies i = i0 + m S with i0 = t / B; the others idle during the stages.
 struct TileGeom {
@@ -164,16 +187,20 @@ __device__ __forceinline__ void fft_stage(float2* tile, const float2* tws, int n
 }
 
 // All stages of plan `pl` over the B columns of the tile (row pitch BP). tw is the plan's per-stage twiddle
-// table. The caller has synchronised after filling the tile.
-template <bool INV, int EPT = kEPT, class PL>
+// table. The caller has synchronised after filling the tile. With R12 false the radix-12 stage is not compiled in
+// (for a kernel at its register cap): the plan must then come from make_plan(n, p, false).
+template <bool INV, int EPT = kEPT, bool R12 = true, class PL>
 __device__ __forceinline__ void fft_tile(float2* tile, const float2* tw, const PL& pl, int B, int BP, int tid) {
   const TileGeom g(B, BP, tid);
   const int n = pl.n;
   for (int s = 0; s < pl.nst; ++s) {
     const float2* tws = tw + pl.tw_off[s];
     const int p = pl.p[s], pm = pl.pmask[s];
-    switch (pl.radix[s]) {  // the plans use radices 8, 4, 2, 3 and 5 (make_plan)
+    switch (pl.radix[s]) {  // the plans use radices 8, 4, 2, 12, 3 and 5 (make_plan)
       case 8: fft_stage<8, INV, EPT>(tile, tws, n, p, pm, g); break;
+      case 12:
+        if constexpr (R12) fft_stage<12, INV, EPT>(tile, tws, n, p, pm, g);
+        break;
       case 4: fft_stage<4, INV, EPT>(tile, tws, n, p, pm, g); break;
       case 2: fft_stage<2, INV, EPT>(tile, tws, n, p, pm, g); break;
       case 3: fft_stage<3, INV, EPT>(tile, tws, n, p, pm, g); break;

@@ -32,7 +32,9 @@ struct Plan1D {
   int tw_off[kMaxStages];
 };
 
-bool make_plan(int n, Plan1D* p);        // false if n has a prime factor > 5 or n < 1
+// Stages of a length-n transform: radix 8 (2, 4 for the rest of the power of two), 3 and 5; with radix12 a radix-4
+// and a radix-3 stage become one radix-12 stage. False if n has a prime factor > 5 or n < 1.
+bool make_plan(int n, Plan1D* p, bool radix12 = true);
 int mesh_pitch(int n);                   // complex row pitch of the half-spectrum layout, >= n/2 + 1
 
 // Per-kick scalars (FP64 table rows reduced to FP32 products).
