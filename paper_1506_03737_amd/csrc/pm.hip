@@ -248,9 +248,12 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
   const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
   const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
-  // the particle ranges (local indices): own tile, then the boundary bucket of each distinct lower neighbour
-  int64_t rb[8], rlen[8];
+  // the particle ranges (local indices, uniform): own tile, then the boundary bucket of each distinct lower
+  // neighbour; logical particle q lies in range r when cum[r] <= q < cum[r + 1], at index rb[r] + q - cum[r]
+  int rb[8], cum[9];
   int nr = 0;
+  cum[0] = 0;
+  const int pbase = static_cast<int>(J.pbase);  // sort positions are int
   const int lo = (nt > 1) ? -1 : 0;  // an axis with one tile has no distinct lower neighbour
   for (int dx = lo; dx <= 0; ++dx) {
     for (int dy = lo; dy <= 0; ++dy) {
@@ -258,35 +261,33 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
         const int sx = (tx + dx + nt) % nt, sy = (ty + dy + nt) % nt, sz = (tz + dz + nt) % nt;
         const int g = J.tbase + 2 * ((sx * nt + sy) * nt + sz);
         const bool own = (dx == 0 && dy == 0 && dz == 0);
-        const int64_t b = start[own ? g : g + 1] - J.pbase, e = start[g + 2] - J.pbase;
+        const int b = __builtin_amdgcn_readfirstlane(start[own ? g : g + 1] - pbase);
+        const int e = __builtin_amdgcn_readfirstlane(start[g + 2] - pbase);
         rb[nr] = b;
-        rlen[nr] = e - b;
+        cum[nr + 1] = cum[nr] + (e - b);
         ++nr;
       }
     }
   }
-  int64_t tot = 0;
-  for (int r = 0; r < nr; ++r) tot += rlen[r];
+  const int tot = cum[nr];
   __syncthreads();
   const int64_t n = J.n;
   const int64_t period = static_cast<int64_t>(nm) << kFracBits;
   LPC_GLOBAL const float* pos = to_global(J.pos);
   // kUnroll particles per thread per round: all their position loads are issued before any is used
   constexpr int kUnroll = 4;
-  for (int64_t q0 = tid; q0 < tot; q0 += kUnroll * kNT) {
+  for (int q0 = tid; q0 < tot; q0 += kUnroll * kNT) {
     float px[kUnroll][3];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t q = q0 + u * kNT;
+      const int q = q0 + u * kNT;
       px[u][0] = px[u][1] = px[u][2] = 0.f;
       if (q < tot) {
-        int64_t rem = q;
-        int r = 0;
-        while (rem >= rlen[r]) {  // at most 8 ranges
-          rem -= rlen[r];
-          ++r;
-        }
-        const int64_t i = rb[r] + rem;
+        int off = rb[0];
+#pragma unroll
+        for (int r = 1; r < 8; ++r)
+          if (r < nr && q >= cum[r]) off = rb[r] - cum[r];
+        const int64_t i = off + q;
 #pragma unroll
         for (int d = 0; d < 3; ++d) px[u][d] = pos[d * n + i];
       }
