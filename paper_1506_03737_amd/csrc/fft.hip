@@ -518,7 +518,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// z pass, inverse c2r. An item transforms R rows of each of NC spectra; tile column c R + r holds spectrum c of
+// z pass, inverse c2r. An item transforms R rows of each of NC spectra; tile column r NC + c holds spectrum c of
 // row r (B = NC R columns). With X the half spectrum of a real row,
 //   Z[k] = (X[k] + conj X[h-k]) + i exp(+2 pi i k / n) (X[k] - conj X[h-k]),  h = n/2, k < h,
 // and the unnormalised length-h inverse FFT of Z gives x[2m] + i x[2m+1]. Output rows are NC-interleaved.
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
 #pragma unroll
       for (int m = 0; m < EPT + 1; ++m) {
         const int e = tid + m * kFftNT;
-        const int c = col / R, row = row0 + col % R;
+        const int c = col % NC, row = row0 + col / NC;
         v[m] = make_float2(0.f, 0.f);
         LPC_GLOBAL const float2* src = (c == 0) ? in0 : (c == 1 ? in1 : in2);
         if (e < count && row < nrows) v[m] = src[static_cast<size_t>(row) * pitch + k];
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
         const int e = tid + m * kFftNT;
         float2 x = v[m];
         // the third spectrum is psi: i k_z psi, zero on the Nyquist plane (applied here, once every load is issued)
-        if (NC == 3 && col >= 2 * R && kz3 != 0.f) {
+        if (NC == 3 && col % NC == 2 && kz3 != 0.f) {
           const float kz = (k == h) ? 0.f : kz3 * static_cast<float>(k);
           x = make_float2(-kz * x.y, kz * x.x);
         }
@@ -617,54 +617,49 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     }
     __syncthreads();
     fft_tile<true, EPT, NC != 3>(tile, tw, J.pl, B, BP, tid);  // NC = 3: plans without radix 12
-    const int rowlen = NC * n;
-    LPC_GLOBAL float* out = to_global(J.out);
+    // Output: tile row m of row r holds points 2m and 2m + 1 of every spectrum (columns r NC .. r NC + NC - 1),
+    // i.e. 2 NC consecutive floats of the NC-interleaved output row. One (row, m) unit per thread: NC 8-byte LDS
+    // reads at a stride of BP float2 between lanes (conflict-free for odd BP) and NC 8-byte stores, contiguous across
+    // lanes.
+    const int rowlen = NC * n, hm = n / 2;
     const float scale = J.scale;
-    // Output value (r, q): row row0 + r, position q of the NC-interleaved row (tile column c R + r, point jj / 2).
-#define LPC_C2R_VALUE(r, q, val)                              \
-  do {                                                        \
-    const int jj_ = (q) / NC, c_ = (q) - jj_ * NC;            \
-    const float2 z_ = tile[(jj_ >> 1) * BP + c_ * R + (r)];   \
-    (val) = ((jj_ & 1) ? z_.y : z_.x) * scale;                \
-  } while (0)
-    const int nval = min(R, nrows - row0) * rowlen;  // the item's rows are contiguous in the output
-    LPC_GLOBAL float* dst = out + static_cast<size_t>(row0) * rowlen;
+    const int units = min(R, nrows - row0) * hm;
+    LPC_GLOBAL float* dst = to_global(J.out) + static_cast<size_t>(row0) * rowlen;
     // (the empty asm keeps the store loop's per-thread indices from being computed before the transform)
     int stid = tid;
     asm volatile("" : "+v"(stid));
-    if (nval == R * rowlen && (reinterpret_cast<uintptr_t>(J.out) & 15) == 0) {
-      // R rowlen is a multiple of 4 (R >= 4), so a whole item of a 16-byte aligned mesh starts 16-byte aligned.
-      // value f = 4 f4 + i is (row r, position q) = divmod(f, rowlen): one division per thread, then steps of
-      // 4 kFftNT = dq4 rowlen + dr4 (rowlen = NC n >= 8)
-      const int dq4 = (4 * kFftNT) / rowlen, dr4 = 4 * kFftNT - dq4 * rowlen;
-      int r0 = (4 * stid) / rowlen, q0 = 4 * stid - r0 * rowlen;
+    if ((reinterpret_cast<uintptr_t>(J.out) & 7) == 0) {
+      // unit u = r hm + m: one division per thread, then steps of kFftNT = dqs hm + drs
+      const int dqs = kFftNT / hm, drs = kFftNT - dqs * hm;
+      int r = stid / hm, m = stid - r * hm;
 #pragma unroll 1
-      for (int f4 = stid; f4 < R * rowlen / 4; f4 += kFftNT) {
-        int r = r0, q = q0;
-        float v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          LPC_C2R_VALUE(r, q, v[i]);
-          if (++q == rowlen) {
-            q = 0;
-            ++r;
-          }
+      for (int u = stid; u < units; u += kFftNT) {
+        const float2* src = tile + m * BP + r * NC;
+        LPC_GLOBAL float2* o = reinterpret_cast<LPC_GLOBAL float2*>(dst + static_cast<size_t>(r) * rowlen + 2 * NC * m);
+        if (NC == 3) {
+          const float2 a = src[0], b = src[1], c = src[2];
+          o[0] = make_float2(a.x * scale, b.x * scale);
+          o[1] = make_float2(c.x * scale, a.y * scale);
+          o[2] = make_float2(b.y * scale, c.y * scale);
+        } else {
+          const float2 a = src[0];
+          o[0] = make_float2(a.x * scale, a.y * scale);
         }
-        reinterpret_cast<LPC_GLOBAL float4*>(dst)[f4] = make_float4(v[0], v[1], v[2], v[3]);
-        r0 += dq4;
-        q0 += dr4;
-        if (q0 >= rowlen) {
-          q0 -= rowlen;
-          ++r0;
+        r += dqs;
+        m += drs;
+        if (m >= hm) {
+          m -= hm;
+          ++r;
         }
       }
     } else {
-      for (int f = stid; f < nval; f += kFftNT) {
+      for (int f = stid; f < units * 2 * NC; f += kFftNT) {
         const int r = f / rowlen, q = f - r * rowlen;
-        LPC_C2R_VALUE(r, q, dst[f]);
+        const int jj = q / NC, c = q - jj * NC;
+        const float2 z = tile[(jj >> 1) * BP + r * NC + c];
+        dst[f] = ((jj & 1) ? z.y : z.x) * scale;
       }
     }
-#undef LPC_C2R_VALUE
   }
 }
 
