@@ -435,7 +435,7 @@ Plan1D plan_of(int n, bool radix12 = true) {
 // One 3-D transform on an n^3 mesh: the jobs of its passes.
 struct R2CSections {
   Section z, y, x;
-  int Bz, Bax, Pax;
+  int Bz, Pz, Bax, Pax;
   size_t lds_z, lds_ax;
 };
 struct C2RSections {
@@ -467,6 +467,7 @@ R2CSections add_r2c(JobPack& jp, const void* in, bool fixed, double mscale, int 
   r.Bz = t.z_rows;
   r.Bax = t.axis_cols;
   r.Pax = kern::axis_points(n, r.Bax);
+  r.Pz = kern::r2c_points(n, r.Bz);
   r.lds_z = kern::lds_z_r2c(n, r.Bz);
   r.lds_ax = kern::lds_axis(n, r.Bax);
   kern::ZR2CJob z{};
@@ -517,7 +518,7 @@ C2RSections add_c2r(JobPack& jp, float2* spec, int n, float* out, float scale) {
 
 void run_r2c(const JobPack& jp, const R2CSections& r, bool fixed, int* flags, hipStream_t s) {
   stage("fft z r2c", s, [&] {
-    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(r.z), jp.table(r.z), fixed, r.Bz, r.lds_z, flags, s);
+    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(r.z), jp.table(r.z), fixed, r.Bz, r.Pz, r.lds_z, flags, s);
   });
   stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.y), jp.table(r.y), false, r.Bax, r.Pax, r.lds_ax, s); });
   stage("fft x", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(r.x), jp.table(r.x), false, r.Bax, r.Pax, r.lds_ax, s); });
@@ -554,6 +555,7 @@ struct ForceProgram {
   int Mp = 8;  // points per thread of the fused x + Poisson tiles: the largest over the boxes
   int P3 = 8;  // points per thread of the three-spectrum c2r tiles: the largest over the boxes
   int Pax = 8;  // points per thread of the strided y tiles: the largest over the boxes
+  int Pz = 8;   // points per thread of the forward z tiles: the largest over the boxes
   size_t lds_z = 0, lds_ax = 0, lds_p = 0, lds_c = 0;
   SortSpace ss;
   bool cola_run = false;
@@ -578,6 +580,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     f.Mp = std::max(f.Mp, kern::poisson_points(b.nm, f.Bp));
     f.P3 = std::max(f.P3, kern::c2r_points(b.nm, f.R3));
     f.Pax = std::max(f.Pax, kern::axis_points(b.nm, f.Bax));
+    f.Pz = std::max(f.Pz, kern::r2c_points(b.nm, f.Bz));
   }
   const int ncopy = cola_run ? 2 : 1;
   std::vector<kern::SortJob> su, sn[2];
@@ -764,7 +767,8 @@ void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags,
     return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(f.dep[c]), jp.table(f.dep[c]), f.ss.start, flags, s);
   });
   stage("fft z r2c", s, [&] {
-    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), f.fixed_in, f.Bz, f.lds_z, flags, s);
+    return kern::launch_z_r2c(jp.jobs<kern::ZR2CJob>(f.zr2c), jp.table(f.zr2c), f.fixed_in, f.Bz, f.Pz, f.lds_z, flags,
+                              s);
   });
   stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.Pax, f.lds_ax, s); });
   stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.Mp, f.lds_p, s); });

@@ -106,7 +106,7 @@ __device__ __forceinline__ int find_job(const LPC_CONST int* __restrict__ offs, 
 // z pass, forward r2c. An item transforms B consecutive rows of n reals. Each row is read as h = n/2 complex values
 // z[m] = x[2m] + i x[2m+1]; after the length-h FFT, X[k] = E[k] + exp(-2 pi i k / n) O[k] with
 // E[k] = (Z[k] + conj Z[h-k]) / 2 and O[k] = (Z[k] - conj Z[h-k]) / (2 i), for k = 0..h.
-template <bool FIXED, int B>
+template <bool FIXED, int B, int EPT>
 __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restrict__ jobs,
                                                          const int* __restrict__ offs, int njob, int total,
                                                          int* __restrict__ flags) {
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     // The global loads are issued before the twiddle tables are computed, so the tables overlap their latency.
     if (FIXED) {
       LPC_GLOBAL const uint64_t* in = to_global(static_cast<const uint64_t*>(J.in));
-      constexpr int H = kEPT / 2;
+      constexpr int H = EPT / 2;
       int bb = b0, jj = j0;
 #pragma unroll 1
       for (int half = 0; half < 2; ++half) {
@@ -183,10 +183,10 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
       }
     } else {
       LPC_GLOBAL const float2* in = to_global(static_cast<const float2*>(J.in));
-      float2 v[kEPT];
+      float2 v[EPT];
       int b = b0, j = j0;
 #pragma unroll
-      for (int m = 0; m < kEPT; ++m) {
+      for (int m = 0; m < EPT; ++m) {
         const int e = tid + m * kFftNT;
         v[m] = make_float2(0.f, 0.f);
         if (e < count && row0 + b < nrows) v[m] = in[static_cast<size_t>(row0 + b) * h + j];
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
       b = b0;
       j = j0;
 #pragma unroll
-      for (int m = 0; m < kEPT; ++m) {
+      for (int m = 0; m < EPT; ++m) {
         const int e = tid + m * kFftNT;
         if (e < count) tile[j * BP + b] = v[m];
         b += dq;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
       }
     }
     __syncthreads();
-    fft_tile<false>(tile, tw, J.pl, B, BP, tid);
+    fft_tile<false, EPT>(tile, tw, J.pl, B, BP, tid);
     const int count2 = (h + 1) * B;
     LPC_GLOBAL float2* out = to_global(J.out);
     const int pitch = J.pitch;
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     const int h1 = h + 1, dq1 = kFftNT / h1, dr1 = kFftNT - dq1 * h1;
     int b = tid / h1, k = tid - (tid / h1) * h1;
 #pragma unroll
-    for (int m = 0; m < kEPT + 1; ++m) {
+    for (int m = 0; m < EPT + 1; ++m) {
       const int e = tid + m * kFftNT;
       if (e < count2) {
         const int row = row0 + b;
@@ -665,12 +665,24 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
 
 struct Init {
   Init() {
-    allow_big_lds(k_fft_z_r2c<true, 8>);
-    allow_big_lds(k_fft_z_r2c<true, 16>);
-    allow_big_lds(k_fft_z_r2c<true, 32>);
-    allow_big_lds(k_fft_z_r2c<false, 8>);
-    allow_big_lds(k_fft_z_r2c<false, 16>);
-    allow_big_lds(k_fft_z_r2c<false, 32>);
+    allow_big_lds(k_fft_z_r2c<true, 8, 8>);
+    allow_big_lds(k_fft_z_r2c<true, 8, 12>);
+    allow_big_lds(k_fft_z_r2c<true, 8, 16>);
+    allow_big_lds(k_fft_z_r2c<true, 16, 8>);
+    allow_big_lds(k_fft_z_r2c<true, 16, 12>);
+    allow_big_lds(k_fft_z_r2c<true, 16, 16>);
+    allow_big_lds(k_fft_z_r2c<true, 32, 8>);
+    allow_big_lds(k_fft_z_r2c<true, 32, 12>);
+    allow_big_lds(k_fft_z_r2c<true, 32, 16>);
+    allow_big_lds(k_fft_z_r2c<false, 8, 8>);
+    allow_big_lds(k_fft_z_r2c<false, 8, 12>);
+    allow_big_lds(k_fft_z_r2c<false, 8, 16>);
+    allow_big_lds(k_fft_z_r2c<false, 16, 8>);
+    allow_big_lds(k_fft_z_r2c<false, 16, 12>);
+    allow_big_lds(k_fft_z_r2c<false, 16, 16>);
+    allow_big_lds(k_fft_z_r2c<false, 32, 8>);
+    allow_big_lds(k_fft_z_r2c<false, 32, 12>);
+    allow_big_lds(k_fft_z_r2c<false, 32, 16>);
     allow_big_lds(k_fft_axis<true, 8, 8>);
     allow_big_lds(k_fft_axis<true, 8, 12>);
     allow_big_lds(k_fft_axis<true, 8, 16>);
@@ -733,6 +745,12 @@ size_t lds_axis(int n, int B) { return sizeof(float2) * (static_cast<size_t>(n) 
 // Points per thread of a strided tile of B columns at length n (n B / kFftNT), rounded up to 8, 12 or 16.
 int axis_points(int n, int B) {
   const long pts = (static_cast<long>(n) * B + kFftNT - 1) / kFftNT;
+  return pts <= 8 ? 8 : (pts <= 12 ? 12 : 16);
+}
+
+// Points per thread of a forward r2c z tile of B rows (B columns of length n / 2), rounded up to 8, 12 or 16.
+int r2c_points(int n, int B) {
+  const long pts = (static_cast<long>(n / 2) * B + kFftNT - 1) / kFftNT;
   return pts <= 8 ? 8 : (pts <= 12 ? 12 : 16);
 }
 
@@ -807,18 +825,21 @@ bool tile_ok(TileKind kind, int n, int w) {
 
 void init_kernels() { ensure_init(); }
 
-hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, size_t lds, int* flags, hipStream_t s) {
+hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, int P, size_t lds, int* flags,
+                        hipStream_t s) {
   ensure_init();
   const unsigned g = item_grid(wt.total);
   if (g == 0) return hipSuccess;
-#define LPC_ZR2C(F, BB) k_fft_z_r2c<F, BB><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total, flags)
+  if ((B != 8 && B != 16 && B != 32) || (P != 8 && P != 12 && P != 16)) return hipErrorInvalidValue;
+#define LPC_ZR2C(F, BB, PP) k_fft_z_r2c<F, BB, PP><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total, flags)
+#define LPC_ZR2C_P(F, BB) \
+  if (P == 8) LPC_ZR2C(F, BB, 8); else if (P == 12) LPC_ZR2C(F, BB, 12); else LPC_ZR2C(F, BB, 16)
   if (fixed) {
-    if (B == 8) LPC_ZR2C(true, 8); else if (B == 16) LPC_ZR2C(true, 16); else if (B == 32) LPC_ZR2C(true, 32);
-    else return hipErrorInvalidValue;
+    if (B == 8) { LPC_ZR2C_P(true, 8); } else if (B == 16) { LPC_ZR2C_P(true, 16); } else { LPC_ZR2C_P(true, 32); }
   } else {
-    if (B == 8) LPC_ZR2C(false, 8); else if (B == 16) LPC_ZR2C(false, 16); else if (B == 32) LPC_ZR2C(false, 32);
-    else return hipErrorInvalidValue;
+    if (B == 8) { LPC_ZR2C_P(false, 8); } else if (B == 16) { LPC_ZR2C_P(false, 16); } else { LPC_ZR2C_P(false, 32); }
   }
+#undef LPC_ZR2C_P
 #undef LPC_ZR2C
   return hipGetLastError();
 }

@@ -199,6 +199,7 @@ bool tile_ok(TileKind kind, int n, int w);
 size_t lds_z_r2c(int n, int B);
 size_t lds_axis(int n, int B);
 int axis_points(int n, int B);     // points per thread of a strided tile of B columns (8, 12 or 16)
+int r2c_points(int n, int B);      // points per thread of a forward r2c z tile of B rows (8, 12 or 16)
 int c2r_points(int n, int R);      // points per thread of a three-spectrum c2r z tile of R rows (8, 12 or 16)
 int poisson_points(int n, int B);  // points per thread of a fused x + Poisson tile (8, 12 or 16)
 size_t lds_x_poisson(int n, int B, int M);
@@ -218,7 +219,8 @@ hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, h
 // B: tile columns (rows for z passes); lds: dynamic LDS bytes (the max over the jobs).
 // One-time kernel attribute set-up (large dynamic LDS); launches do it themselves, graph capture calls it first.
 void init_kernels();
-hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, size_t lds, int* flags, hipStream_t s);
+hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, int P, size_t lds, int* flags,
+                        hipStream_t s);
 hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, int P, size_t lds, hipStream_t s);
 hipError_t launch_y_grad(const YGradJob* jobs, WorkTable wt, int B, int P, size_t lds, hipStream_t s);
 hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, size_t lds, hipStream_t s);
