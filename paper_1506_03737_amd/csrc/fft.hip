@@ -544,51 +544,71 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     LPC_GLOBAL const float2* in0 = to_global(J.in0);
     LPC_GLOBAL const float2* in1 = to_global(J.in1);
     LPC_GLOBAL const float2* in2 = to_global(J.in2);
-    const int h1 = h + 1, count = B * h1;
     const float kz3 = J.kz3;
-    // Element e = tid + m kFftNT is (tile column col, frequency k) = divmod(e, h + 1): one division per thread, then
-    // steps of kFftNT = dq (h + 1) + dr.
-    const int dq = kFftNT / h1, dr = kFftNT - dq * h1;
-    const int col0 = tid / h1, k0 = tid - col0 * h1;
+    // Loads, spectrum by spectrum: element e = tid + m kFftNT of a spectrum's R rows below the Nyquist point is
+    // (row r, frequency k) = divmod(e, h), the same for every spectrum, so the offsets are stepped once (one division
+    // per thread, then steps of kFftNT = dq h + dr) and each spectrum's base pointer is a compile-time choice. R h <=
+    // B h / NC <= EPT kFftNT / NC, so MC loads per thread and spectrum cover it. The R NC Nyquist points (k = h) are
+    // one load each for the first R NC threads. Tile column of (row r, spectrum c): r NC + c.
+    constexpr int MC = (EPT + NC - 1) / NC;
+    const int per = R * h;
+    const int dq = kFftNT / h, dr = kFftNT - dq * h;
     {
-      float2 v[EPT + 1];  // B (h + 1) <= B (EPT S + 1) <= (EPT + 1) kFftNT
-      int col = col0, k = k0;
+      int64_t goff[MC];  // global element offset (row0 + r) pitch + k, or -1 for no element
+      int loff[MC];      // tile offset k BP + r NC
+      int kk[MC];
+      {
+        int r = tid / h, k = tid - (tid / h) * h;
 #pragma unroll
-      for (int m = 0; m < EPT + 1; ++m) {
-        const int e = tid + m * kFftNT;
-        const int c = col % NC, row = row0 + col / NC;
-        v[m] = make_float2(0.f, 0.f);
-        LPC_GLOBAL const float2* src = (c == 0) ? in0 : (c == 1 ? in1 : in2);
-        if (e < count && row < nrows) v[m] = src[static_cast<size_t>(row) * pitch + k];
-        col += dq;
-        k += dr;
-        if (k >= h1) {
-          k -= h1;
-          ++col;
+        for (int m = 0; m < MC; ++m) {
+          const bool ok = tid + m * kFftNT < per && row0 + r < nrows;
+          goff[m] = ok ? static_cast<int64_t>(row0 + r) * pitch + k : -1;
+          loff[m] = k * BP + r * NC;
+          kk[m] = k;
+          r += dq;
+          k += dr;
+          if (k >= h) {
+            k -= h;
+            ++r;
+          }
         }
+      }
+      float2 v[NC][MC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        LPC_GLOBAL const float2* src = (c == 0) ? in0 : (c == 1 ? in1 : in2);
+#pragma unroll
+        for (int m = 0; m < MC; ++m) {
+          v[c][m] = make_float2(0.f, 0.f);
+          if (goff[m] >= 0) v[c][m] = src[goff[m]];
+        }
+      }
+      const int nyq_r = tid / NC, nyq_c = tid - nyq_r * NC;  // Nyquist point of tile column tid
+      float2 nyq = make_float2(0.f, 0.f);
+      if (tid < B && row0 + nyq_r < nrows) {
+        LPC_GLOBAL const float2* src = (nyq_c == 0) ? in0 : (nyq_c == 1 ? in1 : in2);
+        nyq = src[static_cast<size_t>(row0 + nyq_r) * pitch + h];
       }
       // the tables are copied while the loads are in flight
       copy_table(tw, J.tw, h, tid);
       copy_table(roots, J.roots, h + 1, tid);
-      col = col0;
-      k = k0;
 #pragma unroll
-      for (int m = 0; m < EPT + 1; ++m) {
-        const int e = tid + m * kFftNT;
-        float2 x = v[m];
-        // the third spectrum is psi: i k_z psi, zero on the Nyquist plane (applied here, once every load is issued)
-        if (NC == 3 && col % NC == 2 && kz3 != 0.f) {
-          const float kz = (k == h) ? 0.f : kz3 * static_cast<float>(k);
-          x = make_float2(-kz * x.y, kz * x.x);
-        }
-        if (e < count) tile[k * BP + col] = x;
-        col += dq;
-        k += dr;
-        if (k >= h1) {
-          k -= h1;
-          ++col;
+      for (int c = 0; c < NC; ++c) {
+#pragma unroll
+        for (int m = 0; m < MC; ++m) {
+          if (tid + m * kFftNT < per) {
+            float2 x = v[c][m];
+            // the third spectrum is psi: i k_z psi (applied here, once every load is issued)
+            if (NC == 3 && c == 2 && kz3 != 0.f) {
+              const float kz = kz3 * static_cast<float>(kk[m]);
+              x = make_float2(-kz * x.y, kz * x.x);
+            }
+            tile[loff[m] + c] = x;
+          }
         }
       }
+      // i k_z psi is zero on the Nyquist plane
+      if (tid < B) tile[h * BP + tid] = (NC == 3 && nyq_c == 2 && kz3 != 0.f) ? make_float2(0.f, 0.f) : nyq;
     }
     __syncthreads();
     {
