@@ -130,8 +130,13 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     const int dq = kFftNT / h, dr = kFftNT - dq * h;
     const int b0 = tid / h, j0 = tid - b0 * h;
     // The global loads are issued before the twiddle tables are computed, so the tables overlap their latency.
+    // The item's rows are contiguous in the input, so element e is at offset row0 h + e (in complex values); rows past
+    // the last are not read.
+    const int valid = min(count, (nrows - row0) * h);
     if (FIXED) {
-      LPC_GLOBAL const uint64_t* in = to_global(static_cast<const uint64_t*>(J.in));
+      LPC_GLOBAL const ulonglong2* in =
+          reinterpret_cast<LPC_GLOBAL const ulonglong2*>(to_global(static_cast<const uint64_t*>(J.in))) +
+          static_cast<size_t>(row0) * h;
       constexpr int H = EPT / 2;
       int bb = b0, jj = j0;
 #pragma unroll 1
@@ -142,14 +147,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
         for (int m = 0; m < H; ++m) {
           const int e = tid + (half * H + m) * kFftNT;
           raw[m] = make_ulonglong2(0ull, 0ull);
-          if (e < count && row0 + b < nrows)
-            raw[m] = reinterpret_cast<LPC_GLOBAL const ulonglong2*>(in + static_cast<size_t>(row0 + b) * n)[j];
-          b += dq;
-          j += dr;
-          if (j >= h) {
-            j -= h;
-            ++b;
-          }
+          if (e < valid) raw[m] = in[e];
         }
         if (half == 0) {
           copy_table(tw, J.tw, h, tid);
@@ -182,25 +180,17 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
         if (overflow) atomicOr(flags + kFlagOverflow, 1);
       }
     } else {
-      LPC_GLOBAL const float2* in = to_global(static_cast<const float2*>(J.in));
+      LPC_GLOBAL const float2* in = to_global(static_cast<const float2*>(J.in)) + static_cast<size_t>(row0) * h;
       float2 v[EPT];
-      int b = b0, j = j0;
 #pragma unroll
       for (int m = 0; m < EPT; ++m) {
         const int e = tid + m * kFftNT;
         v[m] = make_float2(0.f, 0.f);
-        if (e < count && row0 + b < nrows) v[m] = in[static_cast<size_t>(row0 + b) * h + j];
-        b += dq;
-        j += dr;
-        if (j >= h) {
-          j -= h;
-          ++b;
-        }
+        if (e < valid) v[m] = in[e];
       }
       copy_table(tw, J.tw, h, tid);
       copy_table(roots, J.roots, h + 1, tid);
-      b = b0;
-      j = j0;
+      int b = b0, j = j0;
 #pragma unroll
       for (int m = 0; m < EPT; ++m) {
         const int e = tid + m * kFftNT;
@@ -215,29 +205,30 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     }
     __syncthreads();
     fft_tile<false, EPT>(tile, tw, J.pl, B, BP, tid);
-    const int count2 = (h + 1) * B;
     LPC_GLOBAL float2* out = to_global(J.out);
     const int pitch = J.pitch;
-    // output element e = (row b, frequency k) = divmod(e, h + 1), stepped the same way
-    const int h1 = h + 1, dq1 = kFftNT / h1, dr1 = kFftNT - dq1 * h1;
-    int b = tid / h1, k = tid - (tid / h1) * h1;
-#pragma unroll
-    for (int m = 0; m < EPT + 1; ++m) {
-      const int e = tid + m * kFftNT;
-      if (e < count2) {
-        const int row = row0 + b;
-        if (row < nrows) {
-          const float2 zk = tile[(k == h ? 0 : k) * BP + b];
-          const float2 zm = tile[(k == 0 ? 0 : h - k) * BP + b];
-          const float2 E = cscale(cadd(zk, cconj(zm)), 0.5f);
-          const float2 O = cscale(rot<false>(csub(zk, cconj(zm))), 0.5f);  // (zk - conj zm) / (2 i)
-          out[static_cast<size_t>(row) * pitch + k] = cadd(E, cmul(roots[k], O));
-        }
+    // Output in pairs (k, h - k), k <= h / 2, of each row: with E = (Z[k] + conj Z[h-k]) / 2,
+    // O = (Z[k] - conj Z[h-k]) / (2 i) and t = exp(-2 pi i k / n) O, X[k] = E + t and X[h-k] = conj(E - t)
+    // (Z[h] = Z[0]). Unit u = (row b, pair k) = divmod(u, h / 2 + 1): one division per thread, then steps.
+    const int hk = h / 2 + 1, npair = B * hk;
+    const int dqp = kFftNT / hk, drp = kFftNT - dqp * hk;
+    int b = tid / hk, k = tid - (tid / hk) * hk;
+    for (int u = tid; u < npair; u += kFftNT) {
+      const int row = row0 + b;
+      if (row < nrows) {
+        const float2 zk = tile[k * BP + b];
+        const float2 zm = tile[(k == 0 ? 0 : h - k) * BP + b];
+        const float2 E = cscale(cadd(zk, cconj(zm)), 0.5f);
+        const float2 O = cscale(rot<false>(csub(zk, cconj(zm))), 0.5f);  // (zk - conj zm) / (2 i)
+        const float2 t = cmul(roots[k], O);
+        LPC_GLOBAL float2* o = out + static_cast<size_t>(row) * pitch;
+        o[k] = cadd(E, t);
+        if (2 * k != h) o[h - k] = cconj(csub(E, t));
       }
-      b += dq1;
-      k += dr1;
-      if (k >= h1) {
-        k -= h1;
+      b += dqp;
+      k += drp;
+      if (k >= hk) {
+        k -= hk;
         ++b;
       }
     }
