@@ -342,11 +342,16 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   const double mscale = J.mscale;
   const int wx_ = min(kTile, nm - x0), wy_ = min(kTile, nm - y0), wz_ = min(kTile, nm - z0);
   bool overflow = false;
-  for (int c = tid; c < kTileCells; c += kNT) {
-    const int i = c / (kTile * kTile), j = (c / kTile) % kTile, k = c % kTile;
-    if (i < wx_ && j < wy_ && k < wz_) {
-      const size_t cell = (static_cast<size_t>(x0 + i) * nm + (y0 + j)) * nm + (z0 + k);
-      const unsigned long long v = acc[c];
+  // kNT = kTile^2 threads: thread (j, k) writes its cell of every x-plane i, stepping one plane (nm^2 cells) at a time
+  static_assert(kNT == kTile * kTile, "one thread per (y, z) cell of a tile plane");
+  const int j = tid / kTile, k = tid % kTile;
+  if (j < wy_ && k < wz_) {
+    const size_t plane = static_cast<size_t>(nm) * nm;
+    size_t cell = (static_cast<size_t>(x0) * nm + (y0 + j)) * nm + (z0 + k);
+#pragma unroll
+    for (int i = 0; i < kTile; ++i, cell += plane) {
+      if (i >= wx_) break;  // uniform: a narrow last tile along x
+      const unsigned long long v = acc[i * kNT + tid];
       if (C) C[cell] = v;
       if (D) {
         overflow |= (v >> 63) != 0;
