@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
         if (k2 > 0.f && col_ok) {
           const float W = win[min(j, n - j)] * wyz;
           const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
-          sc = -inv_m3 / (k2 * wp);
+          sc = -inv_m3 * __builtin_amdgcn_rcpf(k2 * wp);  // hardware reciprocal (1 ulp) instead of a division
         }
         const float2 d = tile[j * BP + b];
         const float2 psi = make_float2(sc * d.x, sc * d.y);
