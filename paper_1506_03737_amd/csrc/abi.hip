@@ -692,11 +692,13 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     yi.ncols = nh;
     yi.ntc = (nh + f.Bax - 1) / f.Bax;
     yi.per_comp = round8(nm * yi.ntc);
+    yi.ntc1 = (nh + f.Bax / 2 - 1) / (f.Bax / 2);
+    yi.per_comp1 = round8(nm * yi.ntc1);
     yi.kf = static_cast<float>(2.0 * M_PI / b.box);
     yi.pl = plan_of(nm);
     yi.tw = jp.twiddles(yi.pl);
     yis.push_back(yi);
-    i_yi.push_back(2 * yi.per_comp);  // component 0: the x gradient; 1: the potential (y and z gradients)
+    i_yi.push_back(yi.per_comp + yi.per_comp1);  // component 0: the x gradient; 1: the potential (y and z gradients)
     kern::PoissonJob p{};
     p.A = b.A;
     p.B = b.B;

@@ -280,9 +280,10 @@ __device__ __forceinline__ void store_strided(const float2* tile, LPC_GLOBAL flo
 // Strided complex pass (in place). A tile is B consecutive columns (contiguous in memory) x n points along the
 // axis. Within a component, tiles are XCD-remapped so that neighbouring tiles (which share cache lines at their
 // edges) run on the same XCD. Each thread owns at most EPT points of its column (n B <= EPT kFftNT); with EPT <= 8
-// the kernel fits in 80 VGPRs (three workgroups per CU where the LDS tile allows it), with EPT = 12 in 96.
+// the kernel fits in 80 VGPRs (three workgroups of 8 waves per CU where the LDS tile allows it); larger EPT gets
+// 128 (a cap of 96 would also give two workgroups per CU, and spills).
 template <bool INV, int B, int EPT>
-__global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : (EPT <= 12 ? 5 : 4)) void k_fft_axis(const AxisJob* __restrict__ jobs,
+__global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : 4) void k_fft_axis(const AxisJob* __restrict__ jobs,
                                                         const int* __restrict__ offs, int njob, int total) {
   extern __shared__ float2 smem[];
   {
@@ -318,15 +319,15 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : (EPT <= 12 ? 5 : 4)) void 
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Inverse y pass of the force. Items of component 0 transform A (the x gradient) in place. Items of component 1 read
-// the x-transformed potential psi from C once, transform i k_y psi into B and psi itself back into C (k_z is constant
-// along y; the z pass applies i k_z as it loads C). With EPT <= 12 each thread keeps its own points of psi (column b,
-// rows j0 + m S) in registers between the two transforms; with EPT = 16 (the registers would spill) psi is loaded
-// again from C, which this item has not yet overwritten.
+// Inverse y pass of the force. Items of component 0 transform a tile of B columns of A (the x gradient) in place.
+// Items of component 1 take B / 2 columns of the x-transformed potential psi from C and stack them twice in their
+// tile, as i k_y psi (columns b) and as psi (columns B / 2 + b): one B-column transform gives the y gradient, stored
+// to B, and psi, stored back to C (k_z is constant along y; the z pass applies i k_z as it loads C). An item reads and
+// writes only its own columns, so items do not race.
 template <int B, int EPT>
-__global__ __launch_bounds__(kFftNT, EPT <= 12 ? 4 : 2) void k_fft_y_grad(const YGradJob* __restrict__ jobs,
-                                                          const int* __restrict__ offs, int njob, int total) {
-  constexpr int BP = strided_pitch(B), S = kFftNT / B, H = EPT / 2;
+__global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
+    const YGradJob* __restrict__ jobs, const int* __restrict__ offs, int njob, int total) {
+  constexpr int BP = strided_pitch(B), H = EPT / 2, BH = B / 2;
   extern __shared__ float2 smem[];
   const int w = blockIdx.x;
   const int tid = threadIdx.x;
@@ -334,74 +335,73 @@ __global__ __launch_bounds__(kFftNT, EPT <= 12 ? 4 : 2) void k_fft_y_grad(const 
   const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
   const LPC_CONST YGradJob& J = to_const(jobs)[jb];
   const int local = w - offs[jb];
-  const int comp = local / J.per_comp;
-  const int t = xcd_remap(local - comp * J.per_comp, J.per_comp);
-  const int outer = t / J.ntc, ct = t - outer * J.ntc;
   const int n = J.n;
-  if (outer >= n) return;  // padding item
-  const int c0 = ct * B, bw = min(B, J.ncols - c0);
   float2* tile = smem;
   float2* tw = smem + n * BP;
-  const int64_t off = static_cast<int64_t>(outer) * J.ostr + c0;
-  {
-    LPC_GLOBAL const float2* src = to_global(comp == 0 ? J.A + off : J.C + off);
-    float2 v[H];
-    const TableRegs<float2> tt = table_load(J.tw, n, tid);
-    strided_issue<B, H>(v, src, J.astr, n, bw, tid, 0);
-    table_store(tw, tt, n, tid);
-    strided_put<B, H>(tile, v, n, tid, 0);
-    strided_issue<B, H>(v, src, J.astr, n, bw, tid, 1);
-    strided_put<B, H>(tile, v, n, tid, 1);
-  }
-  __syncthreads();
-  if (comp == 0) {  // uniform
+  if (local < J.per_comp) {  // component 0 (uniform)
+    const int t = xcd_remap(local, J.per_comp);
+    const int outer = t / J.ntc, ct = t - outer * J.ntc;
+    if (outer >= n) return;  // padding item
+    const int c0 = ct * B, bw = min(B, J.ncols - c0);
+    const int64_t off = static_cast<int64_t>(outer) * J.ostr + c0;
+    {
+      LPC_GLOBAL const float2* src = to_global(J.A + off);
+      float2 v[H];
+      const TableRegs<float2> tt = table_load(J.tw, n, tid);
+      strided_issue<B, H>(v, src, J.astr, n, bw, tid, 0);
+      table_store(tw, tt, n, tid);
+      strided_put<B, H>(tile, v, n, tid, 0);
+      strided_issue<B, H>(v, src, J.astr, n, bw, tid, 1);
+      strided_put<B, H>(tile, v, n, tid, 1);
+    }
+    __syncthreads();
     fft_tile<true, EPT>(tile, tw, J.pl, B, BP, tid);
     store_strided<B, EPT>(tile, to_global(J.A + off), J.astr, n, bw, tid);
     return;
   }
-  constexpr bool kRegs = EPT <= 12;
-  const int half = n / 2;
-  const float kf = J.kf;
-  float2 ph[kRegs ? EPT : 1];  // n B <= EPT kFftNT, so n / S <= EPT
+  const int t = xcd_remap(local - J.per_comp, J.per_comp1);
+  const int outer = t / J.ntc1, ct = t - outer * J.ntc1;
+  if (outer >= n) return;  // padding item
+  const int c0 = ct * BH, bw = min(BH, J.ncols - c0);
+  const int64_t off = static_cast<int64_t>(outer) * J.ostr + c0;
   {
-    const int b = tid % B, j0 = tid / B;
+    // n BH <= H kFftNT values, H per thread; column bh = tid % BH is the same for all of a thread's values
+    constexpr int SH = kFftNT / BH;
+    const int bh = tid % BH, j0 = tid / BH;
+    LPC_GLOBAL const float2* src = to_global(J.C + off) + bh;
+    const TableRegs<float2> tt = table_load(J.tw, n, tid);
+    float2 v[H];
 #pragma unroll
-    for (int m = 0; m < EPT; ++m) {
-      const int j = j0 + m * S;
+    for (int m = 0; m < H; ++m) {
+      const int j = j0 + m * SH;
+      v[m] = make_float2(0.f, 0.f);
+      if (j < n && bh < bw) v[m] = src[j * J.astr];
+    }
+    table_store(tw, tt, n, tid);
+    const int half = n / 2;
+    const float kf = J.kf;
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      const int j = j0 + m * SH;
       if (j < n) {
-        const float2 v = tile[j * BP + b];
-        if (kRegs) ph[kRegs ? m : 0] = v;
         const float ky = (j == half) ? 0.f : kf * static_cast<float>(j <= half ? j : j - n);
-        tile[j * BP + b] = make_float2(-ky * v.y, ky * v.x);  // i k_y psi
+        tile[j * BP + bh] = make_float2(-ky * v[m].y, ky * v[m].x);  // i k_y psi
+        tile[j * BP + BH + bh] = v[m];                               // psi
       }
     }
   }
   __syncthreads();
   fft_tile<true, EPT>(tile, tw, J.pl, B, BP, tid);
-  store_strided<B, EPT>(tile, to_global(J.B + off), J.astr, n, bw, tid);
-  __syncthreads();
   {
-    // (the empty asm keeps the first transform's thread-dependent addresses from staying live across the second)
-    int ltid = tid;
-    asm volatile("" : "+v"(ltid));
-    if (kRegs) {
-      const int b = ltid % B, j0 = ltid / B;
+    // tile column b: b < BH -> B (y gradient), else C (psi); b = tid % B is fixed per thread
+    constexpr int S = kFftNT / B;
+    const int b = tid % B, j0 = tid / B, bh = b % BH;
+    LPC_GLOBAL float2* dst = to_global((b < BH ? J.B : J.C) + off) + bh;
 #pragma unroll
-      for (int m = 0; m < EPT; ++m) {
-        const int j = j0 + m * S;
-        if (j < n) tile[j * BP + b] = ph[kRegs ? m : 0];
-      }
-    } else {
-      LPC_GLOBAL const float2* src = to_global(J.C + off);
-      float2 v[H];
-      strided_issue<B, H>(v, src, J.astr, n, bw, ltid, 0);
-      strided_put<B, H>(tile, v, n, ltid, 0);
-      strided_issue<B, H>(v, src, J.astr, n, bw, ltid, 1);
-      strided_put<B, H>(tile, v, n, ltid, 1);
+    for (int m = 0; m < EPT; ++m) {
+      const int j = j0 + m * S;
+      if (j < n && bh < bw) dst[j * J.astr] = tile[j * BP + b];
     }
-    __syncthreads();
-    fft_tile<true, EPT>(tile, tw, J.pl, B, BP, ltid);
-    store_strided<B, EPT>(tile, to_global(J.C + off), J.astr, n, bw, ltid);
   }
 }
 

@@ -175,7 +175,9 @@ struct YGradJob {       // inverse y pass of the force: A in place; i k_y psi (f
   float2 *A, *B, *C;
   const float2* tw;
   int64_t astr, ostr;   // stride along y, stride of the outer (x) index
-  int n, ncols, ntc, per_comp;
+  int n, ncols;
+  int ntc, per_comp;    // component 0: column tiles of B per row, items (a multiple of 8)
+  int ntc1, per_comp1;  // component 1: column tiles of B / 2 per row, items (a multiple of 8)
   float kf;             // 2 pi / L
   Plan1D pl;
 };
