@@ -610,14 +610,12 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
         const float2 xk = tile[k * BP + col];
         const float2 xm = tile[(h - k) * BP + col];
         const float2 t = roots[k];
-        // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm)
-        const float2 zk = cadd(cadd(xk, cconj(xm)), rot<true>(cmulc(csub(xk, cconj(xm)), t)));
-        if (k != 0 && 2 * k != h) {
-          // Z[h-k] = (xm + conj xk) - i t (xm - conj xk)
-          const float2 zm = csub(cadd(xm, cconj(xk)), rot<true>(cmul(csub(xm, cconj(xk)), t)));
-          tile[(h - k) * BP + col] = zm;
-        }
-        tile[k * BP + col] = zk;
+        // Z[k] = (xk + conj xm) + i conj(t) (xk - conj xm) = S + u, and
+        // Z[h-k] = (xm + conj xk) - i t (xm - conj xk) = conj(S - u)
+        const float2 S = cadd(xk, cconj(xm));
+        const float2 u = rot<true>(cmulc(csub(xk, cconj(xm)), t));
+        if (k != 0 && 2 * k != h) tile[(h - k) * BP + col] = cconj(csub(S, u));
+        tile[k * BP + col] = cadd(S, u);
         col += dqk;
         k += drk;
         if (k >= hk) {
