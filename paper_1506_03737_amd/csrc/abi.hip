@@ -1164,15 +1164,14 @@ lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real,
       try {
         run_cola(jp, f, tab, n_a, cosmo->omega_m, cola, flags, cap);
       } catch (...) {
-        hipGraph_t dropped;
-        hipStreamEndCapture(cap, &dropped);
-        if (dropped) hipGraphDestroy(dropped);
+        hipGraph_t dropped = nullptr;  // end the capture so the stream is usable again; the error is the one thrown
+        if (hipStreamEndCapture(cap, &dropped) == hipSuccess && dropped) (void)hipGraphDestroy(dropped);
         throw;
       }
       check(hipStreamEndCapture(cap, &graph), "hipStreamEndCapture");
       hipGraphExec_t exec;
       const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       check(e, "hipGraphInstantiate");
       g_graph.exec = exec;
       g_graph.key = key;

@@ -80,10 +80,12 @@ int mesh_pitch(int n) { return ((n / 2 + 1) + 7) / 8 * 8; }
 
 namespace {
 
+// Lets the kernel take up to 160 KB of dynamic LDS. If the attribute cannot be set, a launch that asks for more than
+// the default fails, and the launcher reports it through hipGetLastError.
 template <class K>
 void allow_big_lds(K kernel) {
-  hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                      160 * 1024);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
 }
 
 // Job of work item w: the last j with offs[j] <= w (binary search; offs is uniform, so scalar loads).

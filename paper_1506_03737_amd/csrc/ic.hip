@@ -40,7 +40,7 @@ struct Mode {
   bool zero;  // k = 0 or a Nyquist index on any axis
 };
 
-__device__ __forceinline__ bool mode_of(int64_t e, int N, int nh, int pitch, Mode* m) {
+__device__ __forceinline__ void mode_of(int64_t e, int N, int nh, Mode* m) {
   const int kz = static_cast<int>(e % nh);
   const int64_t r = e / nh;
   const int ky = static_cast<int>(r % N), kx = static_cast<int>(r / N);
@@ -50,10 +50,9 @@ __device__ __forceinline__ bool mode_of(int64_t e, int N, int nh, int pitch, Mod
   const int h = N / 2;
   m->zero = (m->nx == 0 && m->ny == 0 && kz == 0) || m->nx == h || m->nx == -h || m->ny == h || m->ny == -h ||
             kz == h;
-  return true;
 }
 
-__device__ __forceinline__ int64_t spec_index(int64_t e, int N, int nh, int pitch) {
+__device__ __forceinline__ int64_t spec_index(int64_t e, int nh, int pitch) {
   const int kz = static_cast<int>(e % nh);
   const int64_t r = e / nh;
   return r * pitch + kz;
@@ -74,8 +73,8 @@ __global__ __launch_bounds__(kNT) void k_ic_scale(float2* __restrict__ spec, int
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
   if (e >= count) return;
   Mode m;
-  mode_of(e, N, nh, pitch, &m);
-  const int64_t idx = spec_index(e, N, nh, pitch);
+  mode_of(e, N, nh, &m);
+  const int64_t idx = spec_index(e, nh, pitch);
   if (m.zero) {
     spec[idx] = make_float2(0.f, 0.f);
     return;
@@ -94,8 +93,8 @@ __global__ __launch_bounds__(kNT) void k_ic_factor(const float2* __restrict__ in
   const int64_t e = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
   if (e >= count) return;
   Mode m;
-  mode_of(e, N, nh, pitch, &m);
-  const int64_t idx = spec_index(e, N, nh, pitch);
+  mode_of(e, N, nh, &m);
+  const int64_t idx = spec_index(e, nh, pitch);
   if (m.zero) {
     out[idx] = make_float2(0.f, 0.f);
     return;

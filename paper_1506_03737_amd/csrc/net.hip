@@ -517,7 +517,7 @@ __global__ __launch_bounds__(kNT) void k_loss_grad(const float* __restrict__ out
   sh[threadIdx.x] = sq;
   __syncthreads();
   for (int off = kNT / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    if (static_cast<int>(threadIdx.x) < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
