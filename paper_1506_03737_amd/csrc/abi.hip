@@ -657,6 +657,9 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
       p.nm = nm;
       p.box = static_cast<float>(b.box);
       p.scale = scale;
+      p.pbase = ss.pbase[ib];
+      p.tbase = ss.tbase[ib];
+      p.nt = nt;
       pj[c].push_back(p);
       kern::UnsortJob u{};
       u.spos = cp.pos;
@@ -752,11 +755,15 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
 }
 
 // Tile sort of every box (counts cleared by a kernel, so the sequence may be recorded in a graph).
-void run_sort(const JobPack& jp, const SortSpace& ss, const Section& sec, int* flags, hipStream_t s) {
-  stage("sort keys", s, [&] { return kern::fill_i32(ss.cnt, static_cast<size_t>(ss.G), 0, s); });
-  stage("sort keys", s, [&] {
-    return kern::launch_tile_key(jp.jobs<kern::SortJob>(sec), jp.table(sec), ss.cnt, ss.key, ss.rank, flags, s);
-  });
+// keys_done: the key pass already ran (folded into the previous drift), so only the scan and the scatter remain
+void run_sort(const JobPack& jp, const SortSpace& ss, const Section& sec, int* flags, hipStream_t s,
+              bool keys_done = false) {
+  if (!keys_done) {
+    stage("sort keys", s, [&] { return kern::fill_i32(ss.cnt, static_cast<size_t>(ss.G), 0, s); });
+    stage("sort keys", s, [&] {
+      return kern::launch_tile_key(jp.jobs<kern::SortJob>(sec), jp.table(sec), ss.cnt, ss.key, ss.rank, flags, s);
+    });
+  }
   stage("sort scan", s, [&] { return kern::launch_scan(ss.cnt, ss.start, ss.G, ss.block_sums, s); });
   stage("sort scatter", s, [&] {
     return kern::launch_scatter(jp.jobs<kern::SortJob>(sec), jp.table(sec), ss.key, ss.rank, ss.start, s);
@@ -792,7 +799,7 @@ void run_cola(const JobPack& jp, const ForceProgram& f, const std::vector<double
   }
   for (int i = 0; i < n_a; ++i) {
     if (i > 0) {
-      run_sort(jp, f.ss, f.sort_next[c], flags, s);
+      run_sort(jp, f.ss, f.sort_next[c], flags, s, true);
       c = 1 - c;
     }
     const double* r = row(i);
@@ -806,8 +813,13 @@ void run_cola(const JobPack& jp, const ForceProgram& f, const std::vector<double
     kd.dd2 = static_cast<float>(r[host::kDD2]);
     kd.do_drift = (i + 1 < n_a) ? 1 : 0;
     kd.cola = cola ? 1 : 0;
+    // a drift is followed by a re-sort: its key pass runs inside this kernel, on zeroed bucket counts
+    const bool keys = kd.do_drift != 0;
+    if (keys) stage("sort keys", s, [&] { return kern::fill_i32(f.ss.cnt, static_cast<size_t>(f.ss.G), 0, s); });
     stage("gather kick drift", s, [&] {
-      return kern::launch_gather_kick_drift(jp.jobs<kern::PartJob>(f.parts[c]), jp.table(f.parts[c]), kd, flags, s);
+      return kern::launch_gather_kick_drift(jp.jobs<kern::PartJob>(f.parts[c]), jp.table(f.parts[c]), kd, flags,
+                                            keys ? f.ss.cnt : nullptr, keys ? f.ss.key : nullptr,
+                                            keys ? f.ss.rank : nullptr, s);
     });
   }
   if (cola) {

@@ -144,6 +144,8 @@ struct PartJob {        // one box's particles and meshes
   int nm;
   float box;
   double scale;         // nm 2^16 / box
+  int64_t pbase;        // first global particle index of the box (key / rank arrays of the next sort)
+  int tbase, nt;        // first global tile index of the box; tiles per side
 };
 // FFT tables (device, built once per call on the host in FP64 and rounded to FP32): tw = the plan's stage twiddles
 // (Plan1D), roots[k] = exp(-2 pi i k / n) for k <= n / 2 (real-transform split), win[m] = sinc^2(pi m / n) for
@@ -215,7 +217,10 @@ hipError_t launch_scatter(const SortJob* jobs, WorkTable wt, const int* key, con
                           hipStream_t s);
 hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* start, int* flags, hipStream_t s);
 hipError_t launch_unsort(const UnsortJob* jobs, WorkTable wt, hipStream_t s);
-hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, hipStream_t s);
+// With key != NULL the kernel also does the next sort's key pass on the positions it writes (bucket, rank via cnt,
+// which must be zero): the key pass of k_tile_key folded into the drift.
+hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, int* cnt, int* key,
+                                    int* rank, hipStream_t s);
 hipError_t launch_gather(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s);
 hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, hipStream_t s);
 // B: tile columns (rows for z passes); lds: dynamic LDS bytes (the max over the jobs).

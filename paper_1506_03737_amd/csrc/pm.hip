@@ -425,41 +425,69 @@ __device__ __forceinline__ bool cic_gather(LPC_GLOBAL const float* __restrict__ 
 
 __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __restrict__ jobs,
                                                            const int* __restrict__ offs, int njob, int total,
-                                                           KickDrift kd, int* __restrict__ flags) {
+                                                           KickDrift kd, int* __restrict__ flags, int* __restrict__ cnt,
+                                                           int* __restrict__ key, int* __restrict__ rank) {
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST PartJob& J = to_const(jobs)[jb];
     const int64_t n = J.n;
     const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
-    if (i >= n) continue;
-    LPC_GLOBAL float* pos = to_global(J.pos);
-    LPC_GLOBAL float* vel = to_global(J.vel);
-    LPC_GLOBAL const float* psi1 = to_global(J.psi1);
-    LPC_GLOBAL const float* psi2 = to_global(J.psi2);
-    float x[3] = {pos[i], pos[n + i], pos[2 * n + i]};
-    float g[3];
-    if (!cic_gather(to_global(J.force), J.nm, J.scale, x[0], x[1], x[2], g)) {
-      atomicOr(flags + kFlagNonfinite, 1);
-      continue;
-    }
-    const float box = J.box;
+    const bool active = i < n;
+    float x[3] = {0.f, 0.f, 0.f};
+    if (active) {
+      LPC_GLOBAL float* pos = to_global(J.pos);
+      LPC_GLOBAL float* vel = to_global(J.vel);
+      LPC_GLOBAL const float* psi1 = to_global(J.psi1);
+      LPC_GLOBAL const float* psi2 = to_global(J.psi2);
+      x[0] = pos[i];
+      x[1] = pos[n + i];
+      x[2] = pos[2 * n + i];
+      float g[3];
+      if (!cic_gather(to_global(J.force), J.nm, J.scale, x[0], x[1], x[2], g)) {
+        atomicOr(flags + kFlagNonfinite, 1);  // the particle is left as it is
+      } else {
+        const float box = J.box;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      float acc = g[d];
-      float p1 = 0.f, p2 = 0.f;
-      if (kd.cola) {
-        p1 = psi1[d * n + i];
-        p2 = psi2[d * n + i];
-        acc += kd.d1 * p1 + kd.d2m * p2;
+        for (int d = 0; d < 3; ++d) {
+          float acc = g[d];
+          float p1 = 0.f, p2 = 0.f;
+          if (kd.cola) {
+            p1 = psi1[d * n + i];
+            p2 = psi2[d * n + i];
+            acc += kd.d1 * p1 + kd.d2m * p2;
+          }
+          const float v = vel[d * n + i] + kd.kick * acc;
+          vel[d * n + i] = v;
+          if (kd.do_drift) {
+            float xn = x[d] + kd.drift * v;
+            if (kd.cola) xn += kd.dd1 * p1 + kd.dd2 * p2;
+            if (xn >= box) xn -= box;
+            if (xn < 0.f) xn += box;
+            pos[d * n + i] = xn;
+            x[d] = xn;
+          }
+        }
       }
-      const float v = vel[d * n + i] + kd.kick * acc;
-      vel[d * n + i] = v;
-      if (kd.do_drift) {
-        float xn = x[d] + kd.drift * v;
-        if (kd.cola) xn += kd.dd1 * p1 + kd.dd2 * p2;
-        if (xn >= box) xn -= box;
-        if (xn < 0.f) xn += box;
-        pos[d * n + i] = xn;
+    }
+    if (key) {  // uniform: the next sort's key pass on the positions as stored (k_tile_key's arithmetic)
+      int g = 0;
+      if (active) {
+        const int64_t period = static_cast<int64_t>(J.nm) << kFracBits;
+        uint32_t c[3], f[3];
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ok &= fixed_coord(x[d], J.scale, period, &c[d], &f[d]);
+        int b = 2 * J.nt * J.nt * J.nt;
+        if (ok)
+          b = bucket_of(c[0], c[1], c[2], J.nt, J.nm);
+        else
+          atomicOr(flags + kFlagNonfinite, 1);
+        g = J.tbase + b;
+      }
+      const int r = wave_rank(cnt, g, active);
+      if (active) {
+        key[J.pbase + i] = g;
+        rank[J.pbase + i] = r;
       }
     }
   }
@@ -551,9 +579,12 @@ hipError_t launch_unsort(const UnsortJob* jobs, WorkTable wt, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, hipStream_t s) {
+hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, int* cnt, int* key,
+                                    int* rank, hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_gather_kick_drift<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd, flags);
+  if (key && (!cnt || !rank)) return hipErrorInvalidValue;
+  k_gather_kick_drift<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd, flags, cnt, key,
+                                                                 rank);
   return hipGetLastError();
 }
 
