@@ -55,7 +55,8 @@ def stage_bytes(stage, n_part, nm, ncomp_y=3):
         "fft x + poisson": H + 2 * H,       # read delta_hat, write the x gradient and the potential
         "fft y inv": 2 * H + 3 * H,         # x gradient in place; read the potential, write its y gradient and itself
         "fft z c2r": 3 * H + 12 * M,        # read three spectra, write the AoS float3 force mesh
-        "gather kick drift": 72 * n_part + 12 * corners,
+        # pos, vel, psi1, psi2 in, vel and pos out, the next sort's key and rank out (on the launches that drift)
+        "gather kick drift": 80 * n_part + 12 * corners,
         "frame velocity": 48 * n_part,      # read vel, psi1, psi2; write vel
     }.get(stage)
 
