@@ -69,29 +69,61 @@ __device__ __forceinline__ int bucket_of(uint32_t cx, uint32_t cy, uint32_t cz, 
   return 2 * t + ((last(cx) || last(cy) || last(cz)) ? 1 : 0);
 }
 
-// Rank of each active lane among the lanes of its wave with the same bucket g, with one counter atomic per distinct
-// bucket in the wave (sorted input puts long runs of one bucket in a wave). Called by all lanes of the wave.
-__device__ __forceinline__ int wave_rank(int* __restrict__ cnt, int g, bool active) {
+// Rank of each active thread among the threads of its workgroup with the same bucket g, with one counter atomic per
+// distinct bucket in the workgroup: longer runs of one bucket in the sorted copy than a wave's (fewer partial cache
+// lines written by the scatter). Wave runs of one bucket are merged through an LDS hash of the block's buckets
+// (kRankSlots >= 2 kNT slots, linear probing, so an insert always finds a slot); LDS atomics give each run its offset
+// in the block, and the leader thread of each slot takes the block's range from cnt. Called by all threads of the
+// workgroup (it has barriers); sh holds 3 kRankSlots ints.
+constexpr int kRankSlots = 2 * kNT;
+__device__ int block_rank(int* __restrict__ cnt, int g, bool active, int* sh) {
+  int* s_key = sh;
+  int* s_cnt = sh + kRankSlots;
+  int* s_base = sh + 2 * kRankSlots;
+  for (int t = threadIdx.x; t < kRankSlots; t += kNT) {
+    s_key[t] = -1;
+    s_cnt[t] = 0;
+  }
+  __syncthreads();
   const int lane = __lane_id();
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   unsigned long long pending = __ballot(active);
-  int rank = 0;
+  int slot = 0, local = 0;
   while (pending) {
     const int leader = __ffsll(static_cast<long long>(pending)) - 1;
     const int lg = __shfl(g, leader);
     const unsigned long long same = __ballot(active && g == lg);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(cnt + lg, __popcll(same));
-    base = __shfl(base, leader);
-    if (active && g == lg) rank = base + __popcll(same & below);
+    int sl = 0, off = 0;
+    if (lane == leader) {
+      sl = static_cast<int>((static_cast<unsigned>(lg) * 2654435761u) % kRankSlots);
+      while (true) {
+        const int prev = atomicCAS(s_key + sl, -1, lg);
+        if (prev == -1 || prev == lg) break;
+        sl = (sl + 1) % kRankSlots;
+      }
+      off = atomicAdd(s_cnt + sl, __popcll(same));
+    }
+    sl = __shfl(sl, leader);
+    off = __shfl(off, leader);
+    if (active && g == lg) {
+      slot = sl;
+      local = off + __popcll(same & below);
+    }
     pending &= ~same;
   }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kRankSlots; t += kNT)
+    if (s_key[t] >= 0) s_base[t] = atomicAdd(cnt + s_key[t], s_cnt[t]);
+  __syncthreads();
+  const int rank = active ? s_base[slot] + local : 0;
+  __syncthreads();  // sh is reused by the next call
   return rank;
 }
 
 __global__ __launch_bounds__(kNT) void k_tile_key(const SortJob* __restrict__ jobs, const int* __restrict__ offs,
                                                   int njob, int total, int* __restrict__ cnt, int* __restrict__ key,
                                                   int* __restrict__ rank, int* __restrict__ flags) {
+  __shared__ int sh[3 * kRankSlots];
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST SortJob& J = to_const(jobs)[jb];
@@ -113,7 +145,7 @@ __global__ __launch_bounds__(kNT) void k_tile_key(const SortJob* __restrict__ jo
         atomicOr(flags + kFlagNonfinite, 1);
       g = J.tbase + b;
     }
-    const int r = wave_rank(cnt, g, active);
+    const int r = block_rank(cnt, g, active, sh);
     if (active) {
       key[J.pbase + i] = g;
       rank[J.pbase + i] = r;
@@ -427,6 +459,7 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
                                                            const int* __restrict__ offs, int njob, int total,
                                                            KickDrift kd, int* __restrict__ flags, int* __restrict__ cnt,
                                                            int* __restrict__ key, int* __restrict__ rank) {
+  __shared__ int sh[3 * kRankSlots];  // block_rank, when key != NULL
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST PartJob& J = to_const(jobs)[jb];
@@ -484,7 +517,7 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
           atomicOr(flags + kFlagNonfinite, 1);
         g = J.tbase + b;
       }
-      const int r = wave_rank(cnt, g, active);
+      const int r = block_rank(cnt, g, active, sh);
       if (active) {
         key[J.pbase + i] = g;
         rank[J.pbase + i] = r;
