@@ -5,8 +5,8 @@
 // (pitch = n/2 + 1 rounded up to 8 complex values, 64 bytes, so every row starts on a 64-byte boundary).
 // Forward: z pass (r2c of each row via a length-n/2 complex FFT and the even/odd split), y pass, x pass.
 // Inverse: x pass, y pass, z pass (c2r via the same split). The force path fuses the forward x pass, the Poisson /
-// deconvolution / gradient multiply and the three inverse x passes into one kernel, so the density spectrum is
-// read once and never written back.
+// deconvolution multiply and the inverse x transforms into one kernel, so the density spectrum is read once and never
+// written back; it stores the x gradient and the potential, whose y and z gradients the y and z passes apply.
 //
 // Every kernel is batched: workgroup w takes item w of a work table of (job, tile) items, where a job is one mesh of
 // one box, so one launch per pass serves any number of boxes of uneven sizes (see WorkTable). (A persistent

@@ -1,4 +1,4 @@
-// Device-side building blocks of liblpc's FFTs: complex helpers, radix-2/3/4/5/8 butterflies, one Stockham
+// Device-side building blocks of liblpc's FFTs: complex helpers, radix-2/3/4/5/8/12 butterflies, one Stockham
 // autosort stage over an LDS tile, and the XCD-aware workgroup remap. Included by the .hip sources only.
 //
 // An LDS tile holds B independent columns of one transform length n: element (j, b) at tile[j * BP + b] with

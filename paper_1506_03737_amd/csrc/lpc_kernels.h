@@ -19,7 +19,7 @@ constexpr int kMaxStages = 7;
 // Device error flags, one int each, at the start of every workspace.
 enum { kFlagOverflow = 0, kFlagNonfinite = 1, kNumFlags = 2 };
 
-// One 1-D transform length factored into radix stages (applied in order; radices 2, 3, 4, 5, 8). For stage s,
+// One 1-D transform length factored into radix stages (applied in order; radices 2, 3, 4, 5, 8, 12). For stage s,
 // p[s] is the product of the earlier radices, pmask[s] = p[s] - 1 when p[s] is a power of two (else -1), and the
 // stage's twiddles W_{p R}^{r k} (k < p, 1 <= r < R) sit at tw_off[s] + k (R - 1) + r - 1 of the twiddle table
 // (n - 1 entries in all).
