@@ -115,3 +115,20 @@ def test_gather_of_linear_ramp_is_exact_inside():
     out = pm.gather(field, pos, n, box)
     frac_pos = np.floor(pos[0] * 2**16) / 2**16
     assert np.allclose(out[0], frac_pos, atol=1e-12)
+
+
+def test_plane_wave_sampled_force_equals_oracle():
+    """The separable lattice input of tests/plane_wave.py: its factored counts equal deposit_fixed bit for bit, and the
+    mode sum over the density's support equals pm.pm_force (full FFTs) at every sampled particle (N = 32, Nm = 96)."""
+    from tests import plane_wave as pw
+    N, nm = 32, 96
+    box = float(nm)
+    pos = pw.lattice_plane_wave(N, box, 0.4 * box / N, 3)
+    X, Y, Z = pw.factors(pos, N, nm, box)
+    C = pm.deposit_fixed(pos.astype(np.float64), nm, box)
+    assert np.array_equal(C, X[:, None, None] * Y[None, :, None] * Z[None, None, :])
+    sample = np.random.default_rng(5).choice(N**3, 300, replace=False)
+    for p in (1, 2):
+        ref = pm.pm_force(pos.astype(np.float64), nm, box, deconv_power=p)[:, sample]
+        got = pw.force_at(pos, N, nm, box, sample, deconv_power=p)
+        assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
