@@ -186,6 +186,79 @@ __device__ __forceinline__ void fft_stage(float2* tile, const float2* tws, int n
   __syncthreads();
 }
 
+// The same stage with the transform length N, the sub-transform length P and the tile geometry (B columns, pitch BP)
+// known at compile time: the LDS offsets r T BP and r P BP become immediates and the twiddle index a constant mask.
+template <int R, bool INV, int EPT, int N, int P, int B, int BP>
+__device__ __forceinline__ void fft_stage_c(float2* tile, const float2* tws, int tid) {
+  constexpr int MB = (EPT + R - 1) / R, T = N / R, S = kFftNT / B;
+  const int b = tid % B;
+  const int i0 = (tid < S * B) ? tid / B : (1 << 30);
+  float2 v[MB][R];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      const float2* src = tile + i * BP + b;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[m][r] = src[r * T * BP];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      const int k = ((P & (P - 1)) == 0) ? (i & (P - 1)) : (i % P);
+      if (P > 1) {
+        const float2* w = tws + k * (R - 1) - 1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 t = w[r];
+          v[m][r] = INV ? cmulc(v[m][r], t) : cmul(v[m][r], t);
+        }
+      }
+      Dft<R, INV>::run(v[m]);
+      float2* dst = tile + ((i - k) * R + k) * BP + b;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * P * BP] = v[m][r];
+    }
+  }
+  __syncthreads();
+}
+
+// A transform whose plan (radices Rs..., applied in order) and tile geometry are fixed at compile time. matches()
+// tells whether a job's run-time plan is this one (then run() computes exactly what fft_tile computes, with the same
+// twiddle table) and whether the tile geometry can hold it; kernels use it for the mesh sizes they are tuned for and
+// fall back to fft_tile otherwise.
+template <bool INV, int EPT, int B, int BP, int... Rs>
+struct FixedFFT {
+  static constexpr int kN = (Rs * ...);
+  static constexpr int kNst = sizeof...(Rs);
+  static constexpr bool kFits = kN <= EPT * (kFftNT / B) && kNst <= kMaxStages;
+  template <class PL>
+  static __device__ __forceinline__ bool matches(const PL& pl) {
+    if constexpr (!kFits) {
+      return false;
+    } else {
+      constexpr int radix[kNst] = {Rs...};
+      if (pl.n != kN || pl.nst != kNst) return false;
+#pragma unroll
+      for (int s = 0; s < kNst; ++s)
+        if (pl.radix[s] != radix[s]) return false;
+      return true;
+    }
+  }
+  template <int P, int R, int... More>
+  static __device__ __forceinline__ void stages(float2* tile, const float2* tw, int tid) {
+    fft_stage_c<R, INV, EPT, kN, P, B, BP>(tile, tw, tid);
+    if constexpr (sizeof...(More) > 0) stages<P * R, More...>(tile, tw + P * (R - 1), tid);
+  }
+  // The caller has synchronised after filling the tile.
+  static __device__ __forceinline__ void run(float2* tile, const float2* tw, int tid) {
+    if constexpr (kFits) stages<1, Rs...>(tile, tw, tid);
+  }
+};
+
 // All stages of plan `pl` over the B columns of the tile (row pitch BP). tw is the plan's per-stage twiddle
 // table. The caller has synchronised after filling the tile. With R12 false the radix-12 stage is not compiled in
 // (for a kernel at its register cap): the plan must then come from make_plan(n, p, false).
