@@ -88,19 +88,21 @@ void allow_big_lds(K kernel) {
                             160 * 1024);
 }
 
-// The transforms of the single-box workload's mesh with compile-time plans (768 = 8 x 8 x 12 along x and y; the
-// half-length z transforms 384 = 4 x 8 x 12, or 4 x 4 x 8 x 3 where radix 12 is left out) when the job's plan is one
-// of them and the tile can hold it; fft_tile otherwise. Both compute the same stages with the same twiddle table.
-template <bool INV, int EPT, int B, int BP, bool R12 = true, class PL>
+// The transforms of the single-box workload's mesh with compile-time plans when the job's plan is one of them and
+// the tile can hold it, fft_tile otherwise; both compute the same stages with the same twiddle table. HALF selects
+// the plans of the half-length z transforms (384 = 4 x 8 x 12, or 4 x 4 x 8 x 3 where radix 12 is left out);
+// otherwise the full-length x and y transforms (768 = 8 x 8 x 12). A kernel carries only its own kind.
+template <bool INV, int EPT, int B, int BP, bool HALF, bool R12 = true, class PL>
 __device__ __forceinline__ void fft_tile_fast(float2* tile, const float2* tw, const PL& pl, int tid) {
   using F768 = FixedFFT<INV, EPT, B, BP, 8, 8, 12>;
   using F384 = FixedFFT<INV, EPT, B, BP, 4, 8, 12>;
   using F384b = FixedFFT<INV, EPT, B, BP, 4, 4, 8, 3>;
-  if constexpr (R12) {
+  if constexpr (!HALF) {
     if (F768::matches(pl)) {
       F768::run(tile, tw, tid);
       return;
     }
+  } else if constexpr (R12) {
     if (F384::matches(pl)) {
       F384::run(tile, tw, tid);
       return;
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
       }
     }
     __syncthreads();
-    fft_tile_fast<false, EPT, B, BP>(tile, tw, J.pl, tid);
+    fft_tile_fast<false, EPT, B, BP, true>(tile, tw, J.pl, tid);
     LPC_GLOBAL float2* out = to_global(J.out);
     const int pitch = J.pitch;
     // Output in pairs (k, h - k), k <= h / 2, of each row: with E = (Z[k] + conj Z[h-k]) / 2,
@@ -341,7 +343,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : 4) void k_fft_axis(const A
       strided_put<B, H>(tile, v, n, tid, 1);
     }
     __syncthreads();
-    fft_tile_fast<INV, EPT, B, strided_pitch(B)>(tile, tw, J.pl, tid);
+    fft_tile_fast<INV, EPT, B, strided_pitch(B), false>(tile, tw, J.pl, tid);
     store_strided<B, EPT>(tile, ptr, J.astr, n, bw, tid);
   }
 }
@@ -383,7 +385,7 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
       strided_put<B, H>(tile, v, n, tid, 1);
     }
     __syncthreads();
-    fft_tile_fast<true, EPT, B, BP>(tile, tw, J.pl, tid);
+    fft_tile_fast<true, EPT, B, BP, false>(tile, tw, J.pl, tid);
     store_strided<B, EPT>(tile, to_global(J.A + off), J.astr, n, bw, tid);
     return;
   }
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
     }
   }
   __syncthreads();
-  fft_tile_fast<true, EPT, B, BP>(tile, tw, J.pl, tid);
+  fft_tile_fast<true, EPT, B, BP, false>(tile, tw, J.pl, tid);
   {
     // tile column b: b < BH -> B (y gradient), else C (psi); b = tid % B is fixed per thread
     constexpr int S = kFftNT / B;
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
       strided_put<B, H>(tile, v, n, tid, 1);
     }
     __syncthreads();
-    fft_tile_fast<false, M, B, BP>(tile, tw, J.pl, tid);
+    fft_tile_fast<false, M, B, BP, false>(tile, tw, J.pl, tid);
 
     // Each thread touches only its own points between the barriers that bracket the inverse transforms.
     const int half = nm / 2;
@@ -515,7 +517,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
       }
     }
     __syncthreads();
-    fft_tile_fast<true, M, B, BP>(tile, tw, J.pl, tid);
+    fft_tile_fast<true, M, B, BP, false>(tile, tw, J.pl, tid);
     store_strided<B, M>(tile, to_global(J.A + off), astr, n, bw, tid);
     __syncthreads();
     {
@@ -529,7 +531,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
         if (j < n) tile[j * BP + b] = kRegs ? ph[kRegs ? m : 0] : ph_lds[j * BP + b];
       }
       __syncthreads();
-      fft_tile_fast<true, M, B, BP>(tile, tw, J.pl, ltid);
+      fft_tile_fast<true, M, B, BP, false>(tile, tw, J.pl, ltid);
       // the x-transformed potential: the y and z gradients are i k_y and i k_z times it (applied by the y and z passes)
       store_strided<B, M>(tile, to_global(J.C + off), astr, n, bw, ltid);
     }
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
       }
     }
     __syncthreads();
-    fft_tile_fast<true, EPT, B, BP, NC != 3>(tile, tw, J.pl, tid);  // NC = 3: plans without radix 12
+    fft_tile_fast<true, EPT, B, BP, true, NC != 3>(tile, tw, J.pl, tid);  // NC = 3: plans without radix 12
     // Output: tile row m of row r holds points 2m and 2m + 1 of every spectrum (columns r NC .. r NC + NC - 1),
     // i.e. 2 NC consecutive floats of the NC-interleaved output row. One (row, m) unit per thread: NC 8-byte LDS
     // reads at a stride of BP float2 between lanes (conflict-free for odd BP) and NC 8-byte stores, contiguous across
