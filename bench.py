@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes (read scaled by 2.0, write by 1.0, from
 # a 1 GiB copy), by (stage, mesh size, tile width of the stage); profiles/force_path_768_hbm_traffic.md. Must be
 # re-measured (or removed) when the kernel changes.
-MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 9.255e9, ("fft x + poisson", 768, 8): 5.672e9,
+MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 9.255e9, ("fft x + poisson", 768, 8): 5.664e9,
                     ("fft y", 768, 8): 3.713e9, ("fft z r2c", 768, 16): 3.643e9}
 
 
