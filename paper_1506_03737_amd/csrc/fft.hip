@@ -88,30 +88,37 @@ void allow_big_lds(K kernel) {
                             160 * 1024);
 }
 
-// The transforms of the single-box workload's mesh with compile-time plans when the job's plan is one of them and
-// the tile can hold it, fft_tile otherwise; both compute the same stages with the same twiddle table. HALF selects
-// the plans of the half-length z transforms (384 = 4 x 8 x 12, or 4 x 4 x 8 x 3 where radix 12 is left out);
-// otherwise the full-length x and y transforms (768 = 8 x 8 x 12). A kernel carries only its own kind.
+// The transforms of the workloads' meshes (768 for the single box and the learned form's fine run, 192 / 256 / 320 for
+// the batched form and the coarse run) with compile-time plans when the job's plan is one of them and the tile can
+// hold it, fft_tile otherwise; both compute the same stages with the same twiddle table. HALF selects the plans of the
+// half-length z transforms, otherwise those of the full-length x and y transforms; a kernel carries only its own kind.
+template <class F, class PL>
+__device__ __forceinline__ bool try_fixed(float2* tile, const float2* tw, const PL& pl, int tid) {
+  if (!F::matches(pl)) return false;
+  F::run(tile, tw, tid);
+  return true;
+}
+
 template <bool INV, int EPT, int B, int BP, bool HALF, bool R12 = true, class PL>
 __device__ __forceinline__ void fft_tile_fast(float2* tile, const float2* tw, const PL& pl, int tid) {
-  using F768 = FixedFFT<INV, EPT, B, BP, 8, 8, 12>;
-  using F384 = FixedFFT<INV, EPT, B, BP, 4, 8, 12>;
-  using F384b = FixedFFT<INV, EPT, B, BP, 4, 4, 8, 3>;
+  // full-length plans (make_plan): 768 = 8 x 8 x 12, 320 = 8 x 8 x 5, 256 = 8 x 8 x 4, 192 = 8 x 8 x 3;
+  // half-length with radix 12: 384 = 4 x 8 x 12, 160 = 8 x 4 x 5, 128 = 4 x 4 x 8, 96 = 8 x 12;
+  // half-length without radix 12: 384 = 4 x 4 x 8 x 3, 160, 128 as above, 96 = 8 x 4 x 3
   if constexpr (!HALF) {
-    if (F768::matches(pl)) {
-      F768::run(tile, tw, tid);
-      return;
-    }
-  } else if constexpr (R12) {
-    if (F384::matches(pl)) {
-      F384::run(tile, tw, tid);
-      return;
-    }
+    if (try_fixed<FixedFFT<INV, EPT, B, BP, 8, 8, 12>>(tile, tw, pl, tid)) return;
+    if (try_fixed<FixedFFT<INV, EPT, B, BP, 8, 8, 5>>(tile, tw, pl, tid)) return;
+    if (try_fixed<FixedFFT<INV, EPT, B, BP, 8, 8, 4>>(tile, tw, pl, tid)) return;
+    if (try_fixed<FixedFFT<INV, EPT, B, BP, 8, 8, 3>>(tile, tw, pl, tid)) return;
   } else {
-    if (F384b::matches(pl)) {
-      F384b::run(tile, tw, tid);
-      return;
+    if constexpr (R12) {
+      if (try_fixed<FixedFFT<INV, EPT, B, BP, 4, 8, 12>>(tile, tw, pl, tid)) return;
+      if (try_fixed<FixedFFT<INV, EPT, B, BP, 8, 12>>(tile, tw, pl, tid)) return;
+    } else {
+      if (try_fixed<FixedFFT<INV, EPT, B, BP, 4, 4, 8, 3>>(tile, tw, pl, tid)) return;
+      if (try_fixed<FixedFFT<INV, EPT, B, BP, 8, 4, 3>>(tile, tw, pl, tid)) return;
     }
+    if (try_fixed<FixedFFT<INV, EPT, B, BP, 8, 4, 5>>(tile, tw, pl, tid)) return;
+    if (try_fixed<FixedFFT<INV, EPT, B, BP, 4, 4, 8>>(tile, tw, pl, tid)) return;
   }
   fft_tile<INV, EPT, R12>(tile, tw, pl, B, BP, tid);
 }
