@@ -1,9 +1,10 @@
-// Kernels of the learned displacement correction (declared in net_kernels.h). The 3^3 convolutions (forward and data
-// gradient) and the forward 2^3 down/up layers run on BF16 MFMA with FP32 accumulation; the 2^3 data gradients, the
-// weight gradients (FP32 partial sums per voxel chunk, reduced in a fixed order) and the element-wise steps run on
-// the vector ALUs.
+// Kernels of the learned displacement correction (declared in net_kernels.h). The 3^3 convolutions (forward, data
+// gradient, and weight gradient on grids a multiple of 32 per side) and the forward 2^3 down/up layers run on BF16
+// MFMA with FP32 accumulation; the 2^3 data gradients, the other weight gradients and the element-wise steps run on
+// the vector ALUs. Weight gradients are FP32 partial sums per voxel chunk, reduced in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "net_kernels.h"
@@ -441,6 +442,136 @@ __global__ __launch_bounds__(kNT) void k_wgrad(int kind, View x, int cin, int ci
     for (int e = tid; e < cout; e += kNT) dst[nW + (kind == 2 ? tap : 0) * cout + e] = sdz[e * ncb];
 }
 
+// Weight gradient of a 3^3 layer on v_mfma_f32_16x16x32_bf16, for D a multiple of 32: dW[o][t][i] =
+// sum_p dz[p][o] x[p + d_t][i] is a product whose k index is the voxel p. A workgroup takes one 16 (o) x 16 (i) tile
+// of all 27 taps over a range of bricks of 4 x 4 x 32 output voxels. Per brick it stages dz (16 rows of 32 z) and the
+// periodic x halo (6 x 6 rows of 34 z) in LDS channel-major with z contiguous, two BF16 of neighbouring z per dword,
+// so a lane's 8 consecutive k (8 consecutive z of one row) are one 16-byte read. A tap's z offset (0, 1 or 2 halo
+// elements) is applied in registers: the lane reads halo z 8 g .. 8 g + 9 once per (x, y) offset and takes its 8
+// values by dword selection (offsets 0 and 2) or a 16-bit funnel shift (offset 1), so the three z taps share the
+// reads. Wave w takes the brick rows at x = x0 + w (y = y0 + 0..3) and holds all 27 16 x 16 FP32 tiles; the four waves
+// and, for the bias, the four lane groups are summed in a fixed order at the end.
+constexpr int kWB = 32;                    // z extent of a brick: one K step
+constexpr int kWRow = 20;                  // halo row pitch in dwords (17 used; a multiple of 4 for 16-byte reads)
+constexpr int kWXC = 36 * kWRow + 20;      // halo channel pitch in dwords, = 4 mod 32: 8 lanes' 16-byte reads hit
+constexpr int kWZC = 16 * 16 + 4;          // dz channel pitch in dwords (16 rows x 16), = 4 mod 32   distinct banks
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned half16(const u32x4& w, int j) {
+  return (j & 1) ? (w[j >> 1] >> 16) : (w[j >> 1] & 0xffffu);
+}
+__device__ __forceinline__ unsigned funnel16(unsigned lo, unsigned hi) { return (lo >> 16) | (hi << 16); }
+__device__ __forceinline__ float bf16_bits(unsigned h) { return __uint_as_float(h << 16); }
+
+bool wgrad3_mfma(int kind, int D) { return kind == 0 && D >= kWB && D % kWB == 0; }
+
+__global__ __launch_bounds__(kNT, 2) void k_wgrad3(View x, int cin, int cin_real, View dz, int cout, int D, int nchunk,
+                                                   float* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) unsigned sx[16 * kWXC];
+  __shared__ __attribute__((aligned(16))) unsigned sz[16 * kWZC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c16 = lane & 15, g = lane >> 4;
+  const int chunk = blockIdx.x;
+  const int nib = (cin + 15) / 16;
+  const int ob = blockIdx.y / nib, ib = blockIdx.y % nib;
+  const int coutp = (cout + 7) & ~7;
+  const int nb4 = D / 4, nbz = D / kWB;
+  const int nbrick = nb4 * nb4 * nbz;
+  const int per = (nbrick + nchunk - 1) / nchunk;
+  const int k0 = per * chunk, k1 = min(nbrick, k0 + per);
+  f32x4 acc[27];
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  const bool do_bias = ib == 0;
+  for (int k = k0; k < k1; ++k) {
+    const int bzi = k % nbz, byi = (k / nbz) % nb4, bxi = k / (nbz * nb4);
+    const int x0 = 4 * bxi, y0 = 4 * byi, z0 = kWB * bzi;
+    __syncthreads();  // the previous brick's reads are done
+    // dz rows: (8-channel group q, row r, z pair p); channels at or past coutp are zero
+    for (int e = tid; e < 2 * 16 * 16; e += kNT) {
+      const int q = e >> 8, r = (e >> 4) & 15, p = e & 15;
+      const int ch = 16 * ob + 8 * q;
+      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
+      if (ch < coutp) {
+        const size_t vox = (static_cast<size_t>(x0 + (r >> 2)) * D + (y0 + (r & 3))) * D + z0 + 2 * p;
+        u0 = *reinterpret_cast<const u32x4*>(dz.p + vox * dz.ld + dz.off + ch);
+        u1 = *reinterpret_cast<const u32x4*>(dz.p + (vox + 1) * dz.ld + dz.off + ch);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sz[(8 * q + j) * kWZC + r * 16 + p] = half16(u0, j) | (half16(u1, j) << 16);
+    }
+    // x halo rows: (group q, halo row hr = 6 hx + hy, z pair p) for halo z 2 p, 2 p + 1 (voxel z0 - 1 + halo z)
+    for (int e = tid; e < 2 * 36 * 17; e += kNT) {
+      const int q = e / (36 * 17), rem = e - q * (36 * 17), hr = rem / 17, p = rem - hr * 17;
+      const int ch = 16 * ib + 8 * q;
+      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
+      if (ch < cin) {
+        const int gx = wrapi(x0 - 1 + hr / 6, D), gy = wrapi(y0 - 1 + hr % 6, D);
+        const size_t row = (static_cast<size_t>(gx) * D + gy) * D;
+        const size_t v0 = row + wrapi(z0 - 1 + 2 * p, D), v1 = row + wrapi(z0 + 2 * p, D);
+        u0 = *reinterpret_cast<const u32x4*>(x.p + v0 * x.ld + x.off + ch);
+        u1 = *reinterpret_cast<const u32x4*>(x.p + v1 * x.ld + x.off + ch);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sx[(8 * q + j) * kWXC + hr * kWRow + p] = half16(u0, j) | (half16(u1, j) << 16);
+    }
+    __syncthreads();
+    for (int ry = 0; ry < 4; ++ry) {
+      const int r = wave * 4 + ry;
+      const u32x4 a = *reinterpret_cast<const u32x4*>(sz + c16 * kWZC + r * 16 + 4 * g);
+      if (do_bias) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) bsum += bf16_bits(a[d] & 0xffffu) + bf16_bits(a[d] >> 16);
+      }
+      const bf16x8 A = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+      for (int txy = 0; txy < 9; ++txy) {
+        const int tx = txy / 3, ty = txy % 3;
+        const unsigned* src = sx + c16 * kWXC + ((wave + tx) * 6 + ry + ty) * kWRow + 4 * g;
+        const u32x4 q0 = *reinterpret_cast<const u32x4*>(src);
+        const unsigned q4 = src[4];
+        const u32x4 b1 = u32x4{funnel16(q0[0], q0[1]), funnel16(q0[1], q0[2]), funnel16(q0[2], q0[3]),
+                               funnel16(q0[3], q4)};
+        const u32x4 b2 = u32x4{q0[1], q0[2], q0[3], q4};
+        acc[3 * txy + 0] =
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, q0), acc[3 * txy + 0], 0, 0, 0);
+        acc[3 * txy + 1] =
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, b1), acc[3 * txy + 1], 0, 0, 0);
+        acc[3 * txy + 2] =
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, b2), acc[3 * txy + 2], 0, 0, 0);
+      }
+    }
+  }
+  // sum the waves in order into LDS (the staging buffers are free now), then write this tile of the chunk's partial
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(sx);
+  float* rb = reinterpret_cast<float*>(sz);
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < 27; ++t) {
+        f32x4* cell = reinterpret_cast<f32x4*>(red + (t * 64 + lane) * 4);
+        *cell = (w == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : *cell) + acc[t];
+      }
+      rb[lane] = (w == 0 ? 0.f : rb[lane]) + bsum;
+    }
+    __syncthreads();
+  }
+  const int nW = cout * 27 * cin_real;
+  float* dst = partial + static_cast<size_t>(chunk) * (nW + cout);
+  for (int e = tid; e < 27 * 256; e += kNT) {
+    const int t = e >> 8, ln = (e >> 2) & 63, j = e & 3;
+    const int o = 16 * ob + 4 * (ln >> 4) + j, i = 16 * ib + (ln & 15);
+    if (o < cout && i < cin_real) dst[(o * 27 + t) * cin_real + i] = red[e];
+  }
+  if (do_bias && tid < 16) {
+    const int o = 16 * ob + tid;
+    if (o < cout) dst[nW + o] = ((rb[tid] + rb[16 + tid]) + rb[32 + tid]) + rb[48 + tid];
+  }
+}
+
 // grad[j] = sum over chunks (and, for the bias, over its nslot slots) of the partial sums, in a fixed order.
 __global__ __launch_bounds__(kNT) void k_reduce(const float* __restrict__ partial, int nchunk, int nW, int cout,
                                                 int nslot, float* __restrict__ grad) {
@@ -629,16 +760,29 @@ hipError_t up2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D,
   return hipGetLastError();
 }
 
-int wgrad_chunks(int nbase) {
+int wgrad_chunks(int kind, int cin, int cout, int D) {
+  if (wgrad3_mfma(kind, D)) {  // about 512 workgroups over the chunks and the (o, i) tiles
+    const int ntile = ((cout + 15) / 16) * ((cin + 15) / 16);
+    const int nbrick = (D / 4) * (D / 4) * (D / kWB);
+    const int c = std::max(1, 512 / ntile);
+    return std::min(c, nbrick);
+  }
+  const int nbase = (kind == 1) ? (D / 2) * (D / 2) * (D / 2) : D * D * D;
   const int c = nbase / 4096;
   return c < 1 ? 1 : (c > 64 ? 64 : c);
 }
 
 hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int D, float* partial, hipStream_t s) {
   if (cin > kMaxC || cout > kMaxC || (cin % 8) != 0) return hipErrorInvalidValue;
+  if (wgrad3_mfma(kind, D)) {
+    const int nchunk = wgrad_chunks(kind, cin, cout, D);
+    const dim3 grid(static_cast<unsigned>(nchunk), static_cast<unsigned>(((cout + 15) / 16) * ((cin + 15) / 16)));
+    k_wgrad3<<<grid, kNT, 0, s>>>(x, cin, cin_real, dz, cout, D, nchunk, partial);
+    return hipGetLastError();
+  }
   const int ntap = (kind == 0) ? 27 : 8;
   const int nbase = (kind == 1) ? (D / 2) * (D / 2) * (D / 2) : D * D * D;
-  const dim3 grid(static_cast<unsigned>(wgrad_chunks(nbase)), static_cast<unsigned>(ntap));
+  const dim3 grid(static_cast<unsigned>(wgrad_chunks(kind, cin, cout, D)), static_cast<unsigned>(ntap));
   if (cin == 8)
     k_wgrad<8><<<grid, kNT, 0, s>>>(kind, x, cin, cin_real, dz, cout, D, ntap, nbase, partial);
   else if ((cin % 16) == 0 && cout * (cin / 16) <= kNT)

@@ -89,8 +89,7 @@ int64_t partial_floats(int D) {
   Dl[UP0] = D / 2;
   for (int l = 0; l < kNumLayers; ++l) {
     const LayerDef& L = kLayers[l];
-    const int Db = (L.kind == kDown2) ? Dl[l] / 2 : Dl[l];
-    const int nchunk = net::wgrad_chunks(Db * Db * Db);
+    const int nchunk = net::wgrad_chunks(L.kind, round_to(L.cin, 8), L.cout, Dl[l]);
     const int nslot = (L.kind == kUp2) ? 8 : 1;
     best = std::max<int64_t>(best, static_cast<int64_t>(nchunk) * (weight_count(L) + nslot * L.cout));
   }
@@ -193,8 +192,7 @@ void conv_dgrad(const NetWs& w, int l, View dz, View dx, int D, hipStream_t s) {
 void weight_grad(const NetWs& w, int l, View x, int cin, View dz, int D, float* grad, hipStream_t s) {
   const LayerDef& L = kLayers[l];
   check(net::wgrad(L.kind, x, cin, L.cin, dz, L.cout, D, w.partial, s), "weight grad");
-  const int Db = (L.kind == kDown2) ? D / 2 : D;
-  const int nchunk = net::wgrad_chunks(Db * Db * Db);
+  const int nchunk = net::wgrad_chunks(L.kind, cin, L.cout, D);
   const int nslot = (L.kind == kUp2) ? 8 : 1;
   check(net::reduce_partials(w.partial, nchunk, static_cast<int>(weight_count(L)), L.cout, nslot, grad + layer_offset(l),
                              s),

@@ -44,7 +44,8 @@ hipError_t up2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D,
 // then nslot bias slots of cout] with nslot = 8 for up2 (one per tap) and 1 otherwise. x has cin (a multiple of 8)
 // channels of which the first cin_real are real.
 //   kind 0: conv3 (x and dz on D^3), 1: down2 (x on D^3, dz on (D/2)^3), 2: up2 (x on D^3, dz on (2D)^3)
-int wgrad_chunks(int nbase);
+// wgrad_chunks gives the number of chunks (partial rows) that wgrad writes for these arguments.
+int wgrad_chunks(int kind, int cin, int cout, int D);
 hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int D, float* partial, hipStream_t s);
 // grad[0..nW) = sum over chunks; grad[nW + o] = sum over chunks and slots (over wgrad_chunks(...) chunks)
 hipError_t reduce_partials(const float* partial, int nchunk, int nW, int cout, int nslot, float* grad,

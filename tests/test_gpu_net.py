@@ -49,7 +49,10 @@ def test_forward_matches_oracle(D):
     assert err < 3e-2
 
 
-@pytest.mark.parametrize("D", [8, 16])
+# D = 8, 16: every weight gradient on the vector-ALU kernels; D = 32, 64: the 3^3 layers on grids of 32 and 64 per
+# side take the MFMA weight-gradient kernel (bricks of 4 x 4 x 32; at D = 64 the (cin, cout) pairs (8, 16), (16, 16),
+# (32, 16), (16, 3), (32, 32) and (64, 32); the 64 x 64 layer is at D / 4 = 16 and stays on the vector ALUs)
+@pytest.mark.parametrize("D", [8, 16, 32, 64])
 def test_gradient_matches_oracle(D):
     from paper_1506_03737_amd import lpc
     say(f"net: loss and gradient D={D}")
