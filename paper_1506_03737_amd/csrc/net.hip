@@ -204,7 +204,8 @@ __device__ __forceinline__ int fine_voxel(int y, int Dc, int t) {  // voxel 2 y 
 // end of the grid only skips its loads and stores.
 
 // out[y][o] = leaky(b[o] + sum_{t, i} W[o][t][i] x[2y + t][i])   (x on D^3, y on (D/2)^3): K = 8 CIN as (t, i).
-template <int CIN, int COUT>
+// DG: the data gradient of a 2^3 up layer, the same product without bias and activation (W its weights transposed).
+template <int CIN, int COUT, bool DG>
 __global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__ W, const float* __restrict__ b,
                                                View out, int D) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "fragment shapes");
@@ -237,9 +238,10 @@ __global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__
 #pragma unroll
   for (int nb = 0; nb < NBLK; ++nb) {
     const int o = nb * 16 + r;
-    const float bo = b[o];
+    const float bo = DG ? 0.f : b[o];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) st[(4 * g + j) * COUT + o] = static_cast<bf16>(leaky(acc[nb][j] + bo));
+    for (int j = 0; j < 4; ++j)
+      st[(4 * g + j) * COUT + o] = static_cast<bf16>(DG ? acc[nb][j] : leaky(acc[nb][j] + bo));
   }
   __syncthreads();
   constexpr int NCH = 16 * COUT / 8;  // 16-byte chunks of the wave's rows
@@ -254,9 +256,11 @@ __global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__
 }
 
 // out[2y + t][o] = leaky(b[o] + sum_i W[o][t][i] x[y][i])   (x on D^3, out on (2D)^3): N = 8 COUT as (t, o).
-template <int CIN, int COUT>
+// DG: the data gradient of a 2^3 down layer, the same product without bias and activation (W its weights transposed),
+// added to what out holds when accumulate is set.
+template <int CIN, int COUT, bool DG>
 __global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ W, const float* __restrict__ b,
-                                             View out, int D) {
+                                             View out, int D, int accumulate) {
   static_assert(CIN % 32 == 0 && COUT % 16 == 0, "fragment shapes");
   constexpr int KS = CIN / 32, NBLK = 8 * COUT / 16;
   __shared__ bf16 stage[4][16 * 8 * COUT];  // [coarse row][tap][channel] per wave
@@ -281,9 +285,10 @@ __global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ W
     for (int ks = 0; ks < KS; ++ks)
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks], weight_frag(W + (o * 8 + t) * CIN + 32 * ks + 8 * g), acc,
                                                     0, 0, 0);
-    const float bo = b[o];
+    const float bo = DG ? 0.f : b[o];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) st[((4 * g + j) * 8 + t) * COUT + o] = static_cast<bf16>(leaky(acc[j] + bo));
+    for (int j = 0; j < 4; ++j)
+      st[((4 * g + j) * 8 + t) * COUT + o] = static_cast<bf16>(DG ? acc[j] : leaky(acc[j] + bo));
   }
   __syncthreads();
   constexpr int NCH = 16 * 8 * COUT / 8;  // 16-byte chunks: (coarse row, tap, channel group)
@@ -291,47 +296,27 @@ __global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ W
   for (int c = lane; c < NCH; c += 64) {
     const int row = c / (8 * COUT / 8), rest = c % (8 * COUT / 8), t = rest / (COUT / 8), q8 = rest % (COUT / 8);
     const int yr = y0 + row;
-    if (yr < V)
-      *reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>(fine_voxel(yr, D, t)) * out.ld + out.off + 8 * q8) =
-          *reinterpret_cast<const bf16x8*>(st + (row * 8 + t) * COUT + 8 * q8);
+    if (yr < V) {
+      bf16x8* dst =
+          reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>(fine_voxel(yr, D, t)) * out.ld + out.off + 8 * q8);
+      bf16x8 val = *reinterpret_cast<const bf16x8*>(st + (row * 8 + t) * COUT + 8 * q8);
+      if (DG && accumulate) {
+        const bf16x8 old = *dst;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) val[j] = static_cast<bf16>(f(old[j]) + f(val[j]));
+      }
+      *dst = val;
+    }
   }
 }
 
-// dx[2y + t][i] (+)= sum_o W[o][t][i] dz[y][o]   (x on D^3)
-__global__ __launch_bounds__(kNT) void k_down2_dgrad(View dz, int cout, const float* __restrict__ W, int cin, View dx,
-                                                     int D, int accumulate) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (idx >= static_cast<int64_t>(D) * D * D * cin) return;
-  const int i = static_cast<int>(idx % cin);
-  const int xv = static_cast<int>(idx / cin);
-  const int xx = xv / (D * D), xy = (xv / D) % D, xz = xv % D;
-  const int Dc = D / 2;
-  const int t = ((xx & 1) * 2 + (xy & 1)) * 2 + (xz & 1);
-  const int y = ((xx >> 1) * Dc + (xy >> 1)) * Dc + (xz >> 1);
-  const bf16* zp = dz.p + static_cast<size_t>(y) * dz.ld + dz.off;
-  float acc = 0.f;
-  for (int o = 0; o < cout; ++o) acc += W[(o * 8 + t) * cin + i] * f(zp[o]);
-  bf16* dst = dx.p + static_cast<size_t>(xv) * dx.ld + dx.off + i;
-  if (accumulate) acc += f(*dst);
-  *dst = static_cast<bf16>(acc);
-}
-
-// dx[y][i] = sum_{t, o} W[o][t][i] dz[2y + t][o]   (x on D^3, dz on (2D)^3)
-__global__ __launch_bounds__(kNT) void k_up2_dgrad(View dz, int cout, const float* __restrict__ W, int cin, View dx,
-                                                   int D) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (idx >= static_cast<int64_t>(D) * D * D * cin) return;
-  const int i = static_cast<int>(idx % cin);
-  const int y = static_cast<int>(idx / cin);
-  const int yx = y / (D * D), yy = (y / D) % D, yz = y % D;
-  const int Df = 2 * D;
-  float acc = 0.f;
-  for (int t = 0; t < 8; ++t) {
-    const int q = ((2 * yx + (t >> 2)) * Df + 2 * yy + ((t >> 1) & 1)) * Df + 2 * yz + (t & 1);
-    const bf16* zp = dz.p + static_cast<size_t>(q) * dz.ld + dz.off;
-    for (int o = 0; o < cout; ++o) acc += W[(o * 8 + t) * cin + i] * f(zp[o]);
-  }
-  dx.p[static_cast<size_t>(y) * dx.ld + dx.off + i] = static_cast<bf16>(acc);
+// Wt[i][t][o] = W[o][t][i] for a 2^3 layer (the weights of its data gradient)
+__global__ __launch_bounds__(kNT) void k_transpose2(const float* __restrict__ W, int cout, int cin,
+                                                    float* __restrict__ Wt) {
+  const int e = blockIdx.x * kNT + threadIdx.x;
+  if (e >= cout * 8 * cin) return;
+  const int o = e / (8 * cin), t = (e / cin) % 8, i = e % cin;
+  Wt[(i * 8 + t) * cout + o] = W[e];
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -572,29 +557,40 @@ __global__ __launch_bounds__(kNT, 2) void k_wgrad3(View x, int cin, int cin_real
   }
 }
 
-// grad[j] = sum over chunks (and, for the bias, over its nslot slots) of the partial sums, in a fixed order.
+// grad[j] = sum over chunks (and, for the bias, over its nslot slots) of the partial sums, in a fixed order: a block
+// takes 64 outputs, wave q sums the chunks c = q mod 4, and the four wave sums are added in order.
 __global__ __launch_bounds__(kNT) void k_reduce(const float* __restrict__ partial, int nchunk, int nW, int cout,
                                                 int nslot, float* __restrict__ grad) {
-  const int j = blockIdx.x * kNT + threadIdx.x;
-  if (j >= nW + cout) return;
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   const size_t stride = static_cast<size_t>(nW) + static_cast<size_t>(nslot) * cout;
   float s = 0.f;
   if (j < nW) {
-    for (int c = 0; c < nchunk; ++c) s += partial[c * stride + j];
-  } else {
-    for (int c = 0; c < nchunk; ++c)
+    for (int c = q; c < nchunk; c += 4) s += partial[c * stride + j];
+  } else if (j < nW + cout) {
+    for (int c = q; c < nchunk; c += 4)
       for (int k = 0; k < nslot; ++k) s += partial[c * stride + nW + k * cout + (j - nW)];
   }
-  grad[j] = s;
+  part[q][lane] = s;
+  __syncthreads();
+  if (q == 0 && j < nW + cout) grad[j] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // ---------------------------------------------------------------------------------------------------------------
+// one thread per 8 channels of a voxel (16-byte loads and store; c, ld and off are multiples of 8)
 __global__ __launch_bounds__(kNT) void k_leaky_dgrad(View a, View da, int c, int V) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  if (idx >= static_cast<int64_t>(V) * c) return;
-  const int v = static_cast<int>(idx / c), ch = static_cast<int>(idx % c);
-  bf16* d = da.p + static_cast<size_t>(v) * da.ld + da.off + ch;
-  if (!(f(a.p[static_cast<size_t>(v) * a.ld + a.off + ch]) > 0.f)) *d = static_cast<bf16>(kSlope * f(*d));
+  const int c8 = c / 8;
+  if (idx >= static_cast<int64_t>(V) * c8) return;
+  const int v = static_cast<int>(idx / c8), ch = 8 * static_cast<int>(idx % c8);
+  bf16x8* d = reinterpret_cast<bf16x8*>(da.p + static_cast<size_t>(v) * da.ld + da.off + ch);
+  const bf16x8 av = *reinterpret_cast<const bf16x8*>(a.p + static_cast<size_t>(v) * a.ld + a.off + ch);
+  bf16x8 dv = *d;
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (!(f(av[j]) > 0.f)) dv[j] = static_cast<bf16>(kSlope * f(dv[j]));
+  *d = dv;
 }
 
 __global__ __launch_bounds__(kNT) void k_convert_conv3(const float* __restrict__ W, int cout, int cin,
@@ -734,29 +730,41 @@ hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float*
 
 hipError_t down2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
   const unsigned grid = blocks_for(static_cast<int64_t>(D / 2) * (D / 2) * (D / 2), 64);  // 64 coarse voxels per block
-  if (cin == 16 && cout == 32) k_down2<16, 32><<<grid, kNT, 0, s>>>(x, W, b, out, D);
-  else if (cin == 32 && cout == 64) k_down2<32, 64><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  if (cin == 16 && cout == 32) k_down2<16, 32, false><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  else if (cin == 32 && cout == 64) k_down2<32, 64, false><<<grid, kNT, 0, s>>>(x, W, b, out, D);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t up2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
   const unsigned grid = blocks_for(static_cast<int64_t>(D) * D * D, 64);  // 64 coarse voxels per block
-  if (cin == 64 && cout == 32) k_up2<64, 32><<<grid, kNT, 0, s>>>(x, W, b, out, D);
-  else if (cin == 32 && cout == 16) k_up2<32, 16><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  if (cin == 64 && cout == 32) k_up2<64, 32, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, 0);
+  else if (cin == 32 && cout == 16) k_up2<32, 16, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, 0);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t down2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D, int accumulate, hipStream_t s) {
-  const int64_t n = static_cast<int64_t>(D) * D * D * cin;
-  k_down2_dgrad<<<blocks_for(n), kNT, 0, s>>>(dz, cout, W, cin, dx, D, accumulate);
+// The data gradient of a 2^3 down layer has the form of an up layer from dz's grid, and that of an up layer the
+// form of a down layer onto dx's grid, both with the transposed weights Wt[i][t][o].
+hipError_t down2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, int accumulate, hipStream_t s) {
+  const int Dc = D / 2;
+  const unsigned grid = blocks_for(static_cast<int64_t>(Dc) * Dc * Dc, 64);
+  if (cin == 16 && cout == 32) k_up2<32, 16, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, Dc, accumulate);
+  else if (cin == 32 && cout == 64) k_up2<64, 32, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, Dc, accumulate);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t up2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D, hipStream_t s) {
-  const int64_t n = static_cast<int64_t>(D) * D * D * cin;
-  k_up2_dgrad<<<blocks_for(n), kNT, 0, s>>>(dz, cout, W, cin, dx, D);
+hipError_t up2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, hipStream_t s) {
+  const unsigned grid = blocks_for(static_cast<int64_t>(D) * D * D, 64);
+  if (cin == 32 && cout == 16) k_down2<16, 32, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, 2 * D);
+  else if (cin == 64 && cout == 32) k_down2<32, 64, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, 2 * D);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t transpose2(const float* W, int cout, int cin, float* Wt, hipStream_t s) {
+  k_transpose2<<<blocks_for(static_cast<int64_t>(cout) * 8 * cin), kNT, 0, s>>>(W, cout, cin, Wt);
   return hipGetLastError();
 }
 
@@ -794,12 +802,13 @@ hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int
 
 hipError_t reduce_partials(const float* partial, int nchunk, int nW, int cout, int nslot, float* grad,
                            hipStream_t s) {
-  k_reduce<<<blocks_for(nW + cout), kNT, 0, s>>>(partial, nchunk, nW, cout, nslot, grad);
+  k_reduce<<<blocks_for(nW + cout, 64), kNT, 0, s>>>(partial, nchunk, nW, cout, nslot, grad);
   return hipGetLastError();
 }
 
 hipError_t leaky_dgrad(View a, View da, int c, int V, hipStream_t s) {
-  k_leaky_dgrad<<<blocks_for(static_cast<int64_t>(V) * c), kNT, 0, s>>>(a, da, c, V);
+  if (c % 8 != 0) return hipErrorInvalidValue;
+  k_leaky_dgrad<<<blocks_for(static_cast<int64_t>(V) * (c / 8)), kNT, 0, s>>>(a, da, c, V);
   return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct NetWs {
   double* loss_part = nullptr;
   bf16* wf[kNumLayers] = {};
   bf16* wb[kNumLayers] = {};
+  float* wt[kNumLayers] = {};  // 2^3 layers: transposed FP32 weights of the data gradient
   size_t total = 0;
 };
 
@@ -131,7 +132,10 @@ NetWs layout(void* base, int D) {
   w.loss_part = reinterpret_cast<double*>(take(static_cast<size_t>(net::loss_blocks(static_cast<int>(V))) * 8));
   w.partial = reinterpret_cast<float*>(take(static_cast<size_t>(partial_floats(D)) * sizeof(float)));
   for (int l = 0; l < kNumLayers; ++l) {
-    if (kLayers[l].kind != kConv3) continue;
+    if (kLayers[l].kind != kConv3) {
+      w.wt[l] = reinterpret_cast<float*>(take(static_cast<size_t>(weight_count(kLayers[l])) * sizeof(float)));
+      continue;
+    }
     const ConvShape c = conv_shape(kLayers[l]);
     w.wf[l] = reinterpret_cast<bf16*>(take(static_cast<size_t>(16 * c.nbo) * c.kpad * sizeof(bf16)));
     w.wb[l] = reinterpret_cast<bf16*>(take(static_cast<size_t>(16 * c.nbi) * c.kpadb * sizeof(bf16)));
@@ -167,7 +171,10 @@ View v(bf16* p, int ld, int off = 0) { return View{p, ld, off}; }
 void convert_weights(const NetWs& w, const float* params, hipStream_t s) {
   for (int l = 0; l < kNumLayers; ++l) {
     const LayerDef& L = kLayers[l];
-    if (L.kind != kConv3) continue;
+    if (L.kind != kConv3) {
+      check(net::transpose2(Wp(params, l), L.cout, L.cin, w.wt[l], s), "transpose weights");
+      continue;
+    }
     const ConvShape c = conv_shape(L);
     check(net::convert_conv3(Wp(params, l), L.cout, L.cin, w.wf[l], c.cinp, c.nbo, c.kpad, w.wb[l], c.coutp, c.nbi,
                              c.kpadb, s),
@@ -233,7 +240,7 @@ void backward(const NetWs& w, const float* params, const float* target, float* g
   // u0 = leaky(up2(c1))
   check(net::leaky_dgrad(v(w.cat0, 32, 0), v(w.dcat0, 32, 0), 16, V, s), "leaky grad");
   weight_grad(w, UP0, v(w.c1, 32), 32, v(w.dcat0, 32, 0), Dh, grad, s);
-  check(net::up2_dgrad(v(w.dcat0, 32, 0), 16, Wp(params, UP0), 32, v(w.dc1, 32), Dh, s), "up2 grad");
+  check(net::up2_dgrad(v(w.dcat0, 32, 0), 16, w.wt[UP0], 32, v(w.dc1, 32), Dh, s), "up2 grad");
   // c1 = leaky(conv3([u1, s1]))
   check(net::leaky_dgrad(v(w.c1, 32), v(w.dc1, 32), 32, Vh, s), "leaky grad");
   weight_grad(w, C1, v(w.cat1, 64), 64, v(w.dc1, 32), Dh, grad, s);
@@ -241,7 +248,7 @@ void backward(const NetWs& w, const float* params, const float* target, float* g
   // u1 = leaky(up2(b2))
   check(net::leaky_dgrad(v(w.cat1, 64, 0), v(w.dcat1, 64, 0), 32, Vh, s), "leaky grad");
   weight_grad(w, UP1, v(w.b2, 64), 64, v(w.dcat1, 64, 0), Dq, grad, s);
-  check(net::up2_dgrad(v(w.dcat1, 64, 0), 32, Wp(params, UP1), 64, v(w.db2, 64), Dq, s), "up2 grad");
+  check(net::up2_dgrad(v(w.dcat1, 64, 0), 32, w.wt[UP1], 64, v(w.db2, 64), Dq, s), "up2 grad");
   // b2 = leaky(conv3(a2))
   check(net::leaky_dgrad(v(w.b2, 64), v(w.db2, 64), 64, Vq, s), "leaky grad");
   weight_grad(w, B2, v(w.a2, 64), 64, v(w.db2, 64), Dq, grad, s);
@@ -249,7 +256,7 @@ void backward(const NetWs& w, const float* params, const float* target, float* g
   // a2 = leaky(down2(s1)); s1 also feeds c1, so its gradient accumulates
   check(net::leaky_dgrad(v(w.a2, 64), v(w.da2, 64), 64, Vq, s), "leaky grad");
   weight_grad(w, DOWN2, v(w.cat1, 64, 32), 32, v(w.da2, 64), Dh, grad, s);
-  check(net::down2_dgrad(v(w.da2, 64), 64, Wp(params, DOWN2), 32, v(w.dcat1, 64, 32), Dh, 1, s), "down2 grad");
+  check(net::down2_dgrad(v(w.da2, 64), 64, w.wt[DOWN2], 32, v(w.dcat1, 64, 32), Dh, 1, s), "down2 grad");
   // s1 = leaky(conv3(a1))
   check(net::leaky_dgrad(v(w.cat1, 64, 32), v(w.dcat1, 64, 32), 32, Vh, s), "leaky grad");
   weight_grad(w, E1, v(w.a1, 32), 32, v(w.dcat1, 64, 32), Dh, grad, s);
@@ -257,7 +264,7 @@ void backward(const NetWs& w, const float* params, const float* target, float* g
   // a1 = leaky(down2(s0)); s0 also feeds c0
   check(net::leaky_dgrad(v(w.a1, 32), v(w.da1, 32), 32, Vh, s), "leaky grad");
   weight_grad(w, DOWN1, v(w.cat0, 32, 16), 16, v(w.da1, 32), D, grad, s);
-  check(net::down2_dgrad(v(w.da1, 32), 32, Wp(params, DOWN1), 16, v(w.dcat0, 32, 16), D, 1, s), "down2 grad");
+  check(net::down2_dgrad(v(w.da1, 32), 32, w.wt[DOWN1], 16, v(w.dcat0, 32, 16), D, 1, s), "down2 grad");
   // s0 = leaky(conv3(a0))
   check(net::leaky_dgrad(v(w.cat0, 32, 16), v(w.dcat0, 32, 16), 16, V, s), "leaky grad");
   weight_grad(w, E0B, v(w.a0, 16), 16, v(w.dcat0, 32, 16), D, grad, s);

@@ -36,9 +36,14 @@ hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float*
 //   up:   out[2y + t][o] = b[o] + sum_i W[o][t][i] x[y][i]          (x on D^3, out on (2D)^3)
 hipError_t down2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s);
 hipError_t up2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s);
-// Data gradients: dx (+)= ... ; accumulate adds into dx instead of overwriting it.
-hipError_t down2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D, int accumulate, hipStream_t s);
-hipError_t up2_dgrad(View dz, int cout, const float* W, int cin, View dx, int D, hipStream_t s);
+// Data gradients on the same MFMA kernels, from the transposed weights Wt[i][t][o] (transpose2), shapes (cin, cout)
+// (16, 32) and (32, 64) for down, (32, 16) and (64, 32) for up; accumulate adds into dx instead of overwriting it.
+//   down: dx[2y + t][i] (+)= sum_o Wt[i][t][o] dz[y][o]       (dx on D^3, dz on (D/2)^3)
+//   up:   dx[y][i] = sum_{t, o} Wt[i][t][o] dz[2y + t][o]      (dx on D^3, dz on (2D)^3)
+hipError_t down2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, int accumulate, hipStream_t s);
+hipError_t up2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, hipStream_t s);
+// Wt[i][t][o] = W[o][t][i] (FP32, cout x 8 x cin values)
+hipError_t transpose2(const float* W, int cout, int cin, float* Wt, hipStream_t s);
 
 // Weight gradients as per-chunk partial sums (deterministic): partial[chunk][W (canonical, cin_real input channels),
 // then nslot bias slots of cout] with nslot = 8 for up2 (one per tap) and 1 otherwise. x has cin (a multiple of 8)
