@@ -320,7 +320,8 @@ __global__ __launch_bounds__(kNT) void k_transpose2(const float* __restrict__ W,
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Weight gradients. Workgroup (chunk, tap) sums dz[zv(b, tap)][o] x[xv(b, tap)][i] over the base voxels b of its
+// Weight gradients on the vector ALUs, used for 3^3 layers on grids that are not a multiple of 32 per side (the
+// MFMA kernels below take the rest). Workgroup (chunk, tap) sums dz[zv(b, tap)][o] x[xv(b, tap)][i] over the base voxels b of its
 // chunk, for every (o, i); tap 0 also sums dz[..][o] for the bias. Base voxels, tiles of kTV, are staged in LDS as
 // FP32; thread groups take interleaved voxels of a tile and are reduced in LDS at the end.
 constexpr int kTV = 64;
@@ -557,6 +558,118 @@ __global__ __launch_bounds__(kNT, 2) void k_wgrad3(View x, int cin, int cin_real
   }
 }
 
+// Weight gradient of a 2^3 layer on v_mfma_f32_16x16x32_bf16: dW[o][t][i] = sum_y dz[.][o] x[.][i] over the coarse
+// voxels y, with dz at y and x at 2 y + t (down layer) or dz at 2 y + t and x at y (up layer). A workgroup takes one
+// 16 (o) x 16 (i) tile of all 8 taps over a range of blocks of 128 coarse voxels. Per block it stages the operand that
+// depends on the tap (8 taps x 16 channels) and the one that does not (16 channels) in LDS channel-major, two BF16 of
+// neighbouring y per dword, zero past the last voxel. Wave w takes the K step of voxels 32 w .. 32 w + 31 of the block.
+// The bias (per tap for the up layer) is summed from the dz operand; waves and lane groups are summed in a fixed order.
+constexpr int kW2Y = 128;                // coarse voxels per block
+constexpr int kW2P = kW2Y / 2 + 4;       // channel pitch in dwords, = 4 mod 32
+
+__global__ __launch_bounds__(kNT, 2) void k_wgrad2(int kind, View x, int cin, int cin_real, View dz, int cout, int D,
+                                                   int nchunk, float* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) unsigned st[8 * 16 * kW2P];  // the operand at 2 y + t
+  __shared__ __attribute__((aligned(16))) unsigned su[16 * kW2P];      // the operand at y
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c16 = lane & 15, g = lane >> 4;
+  const int nib = (cin + 15) / 16;
+  const int ob = blockIdx.y / nib, ib = blockIdx.y % nib;
+  const int coutp = (cout + 7) & ~7;
+  const bool down = kind == 1;
+  const int Dc = down ? D / 2 : D;  // coarse grid side
+  const int nbase = Dc * Dc * Dc;
+  const int nblk = (nbase + kW2Y - 1) / kW2Y;
+  const int per = (nblk + nchunk - 1) / nchunk;
+  const int k0 = per * blockIdx.x, k1 = min(nblk, k0 + per);
+  const View vt = down ? x : dz, vu = down ? dz : x;
+  const int cht = down ? 16 * ib : 16 * ob, chu = down ? 16 * ob : 16 * ib;
+  const int mt = down ? cin : coutp, mu = down ? coutp : cin;
+  const bool do_bias = ib == 0;
+  f32x4 acc[8];
+  float bs[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bs[t] = 0.f;
+  }
+  for (int k = k0; k < k1; ++k) {
+    const int y0 = k * kW2Y;
+    __syncthreads();  // the previous block's reads are done
+    for (int e = tid; e < 8 * 2 * (kW2Y / 2); e += kNT) {  // (tap t, group q, voxel pair p)
+      const int t = e >> 7, q = (e >> 6) & 1, p = e & 63;
+      const int ch = cht + 8 * q, y = y0 + 2 * p;
+      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
+      if (ch < mt) {
+        if (y < nbase)
+          u0 = *reinterpret_cast<const u32x4*>(vt.p + static_cast<size_t>(fine_voxel(y, Dc, t)) * vt.ld + vt.off + ch);
+        if (y + 1 < nbase)
+          u1 = *reinterpret_cast<const u32x4*>(vt.p + static_cast<size_t>(fine_voxel(y + 1, Dc, t)) * vt.ld + vt.off +
+                                               ch);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) st[(t * 16 + 8 * q + j) * kW2P + p] = half16(u0, j) | (half16(u1, j) << 16);
+    }
+    if (tid < 2 * (kW2Y / 2)) {  // (group q, voxel pair p)
+      const int q = tid >> 6, p = tid & 63;
+      const int ch = chu + 8 * q, y = y0 + 2 * p;
+      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
+      if (ch < mu) {
+        if (y < nbase) u0 = *reinterpret_cast<const u32x4*>(vu.p + static_cast<size_t>(y) * vu.ld + vu.off + ch);
+        if (y + 1 < nbase)
+          u1 = *reinterpret_cast<const u32x4*>(vu.p + static_cast<size_t>(y + 1) * vu.ld + vu.off + ch);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) su[(8 * q + j) * kW2P + p] = half16(u0, j) | (half16(u1, j) << 16);
+    }
+    __syncthreads();
+    const int dw = 16 * wave + 4 * g;
+    const u32x4 fu = *reinterpret_cast<const u32x4*>(su + c16 * kW2P + dw);
+    if (down && do_bias) {
+#pragma unroll
+      for (int d = 0; d < 4; ++d) bs[0] += bf16_bits(fu[d] & 0xffffu) + bf16_bits(fu[d] >> 16);
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const u32x4 ft = *reinterpret_cast<const u32x4*>(st + (t * 16 + c16) * kW2P + dw);
+      if (!down && do_bias) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) bs[t] += bf16_bits(ft[d] & 0xffffu) + bf16_bits(ft[d] >> 16);
+      }
+      // A is dz (rows o), B is x (columns i)
+      const bf16x8 A = __builtin_bit_cast(bf16x8, down ? fu : ft), B = __builtin_bit_cast(bf16x8, down ? ft : fu);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[t], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(st);
+  float* rb = reinterpret_cast<float*>(su);
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        f32x4* cell = reinterpret_cast<f32x4*>(red + (t * 64 + lane) * 4);
+        *cell = (w == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : *cell) + acc[t];
+        rb[t * 64 + lane] = (w == 0 ? 0.f : rb[t * 64 + lane]) + bs[t];
+      }
+    }
+    __syncthreads();
+  }
+  const int nslot = down ? 1 : 8;
+  const int nW = cout * 8 * cin_real;
+  float* dst = partial + static_cast<size_t>(blockIdx.x) * (nW + nslot * cout);
+  for (int e = tid; e < 8 * 256; e += kNT) {
+    const int t = e >> 8, ln = (e >> 2) & 63, j = e & 3;
+    const int o = 16 * ob + 4 * (ln >> 4) + j, i = 16 * ib + (ln & 15);
+    if (o < cout && i < cin_real) dst[(o * 8 + t) * cin_real + i] = red[e];
+  }
+  if (do_bias && tid < 16 * nslot) {
+    const int t = tid >> 4, c = tid & 15, o = 16 * ob + c;
+    const float* b = rb + t * 64;
+    if (o < cout) dst[nW + t * cout + o] = ((b[c] + b[16 + c]) + b[32 + c]) + b[48 + c];
+  }
+}
+
 // grad[j] = sum over chunks (and, for the bias, over its nslot slots) of the partial sums, in a fixed order: a block
 // takes 64 outputs, wave q sums the chunks c = q mod 4, and the four wave sums are added in order.
 __global__ __launch_bounds__(kNT) void k_reduce(const float* __restrict__ partial, int nchunk, int nW, int cout,
@@ -769,23 +882,26 @@ hipError_t transpose2(const float* W, int cout, int cin, float* Wt, hipStream_t 
 }
 
 int wgrad_chunks(int kind, int cin, int cout, int D) {
-  if (wgrad3_mfma(kind, D)) {  // about 512 workgroups over the chunks and the (o, i) tiles
-    const int ntile = ((cout + 15) / 16) * ((cin + 15) / 16);
-    const int nbrick = (D / 4) * (D / 4) * (D / kWB);
-    const int c = std::max(1, 512 / ntile);
-    return std::min(c, nbrick);
+  const int ntile = ((cout + 15) / 16) * ((cin + 15) / 16);
+  const int c512 = std::max(1, 512 / ntile);  // about 512 workgroups over the chunks and the (o, i) tiles
+  if (wgrad3_mfma(kind, D)) return std::min(c512, (D / 4) * (D / 4) * (D / kWB));
+  if (kind != 0) {
+    const int Dc = (kind == 1) ? D / 2 : D;
+    return std::min(c512, (Dc * Dc * Dc + kW2Y - 1) / kW2Y);
   }
-  const int nbase = (kind == 1) ? (D / 2) * (D / 2) * (D / 2) : D * D * D;
-  const int c = nbase / 4096;
+  const int c = D * D * D / 4096;  // 3^3 layer on the VALU kernel
   return c < 1 ? 1 : (c > 64 ? 64 : c);
 }
 
 hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int D, float* partial, hipStream_t s) {
   if (cin > kMaxC || cout > kMaxC || (cin % 8) != 0) return hipErrorInvalidValue;
-  if (wgrad3_mfma(kind, D)) {
+  if (wgrad3_mfma(kind, D) || kind != 0) {
     const int nchunk = wgrad_chunks(kind, cin, cout, D);
     const dim3 grid(static_cast<unsigned>(nchunk), static_cast<unsigned>(((cout + 15) / 16) * ((cin + 15) / 16)));
-    k_wgrad3<<<grid, kNT, 0, s>>>(x, cin, cin_real, dz, cout, D, nchunk, partial);
+    if (kind == 0)
+      k_wgrad3<<<grid, kNT, 0, s>>>(x, cin, cin_real, dz, cout, D, nchunk, partial);
+    else
+      k_wgrad2<<<grid, kNT, 0, s>>>(kind, x, cin, cin_real, dz, cout, D, nchunk, partial);
     return hipGetLastError();
   }
   const int ntap = (kind == 0) ? 27 : 8;
