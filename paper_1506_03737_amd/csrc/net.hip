@@ -471,39 +471,66 @@ __global__ __launch_bounds__(kNT, 2) void k_wgrad3(View x, int cin, int cin_real
   for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;
   const bool do_bias = ib == 0;
-  for (int k = k0; k < k1; ++k) {
+  // Staging items of a thread: dz (8-channel group q, row r, z pair p), items tid and tid + 256; x halo (group q,
+  // halo row hr = 6 hx + hy, z pair p; halo z 2 p, 2 p + 1 is voxel z0 - 1 + halo z), items tid + 256 m < 1224.
+  // The next brick's items are loaded into registers before the current brick's MFMAs and written to LDS after them.
+  constexpr int kHI = 2 * 36 * 17, kHM = (kHI + kNT - 1) / kNT;
+  u32x4 rz[2][2], rh[kHM][2];
+  auto load = [&](int k) {
     const int bzi = k % nbz, byi = (k / nbz) % nb4, bxi = k / (nbz * nb4);
     const int x0 = 4 * bxi, y0 = 4 * byi, z0 = kWB * bzi;
-    __syncthreads();  // the previous brick's reads are done
-    // dz rows: (8-channel group q, row r, z pair p); channels at or past coutp are zero
-    for (int e = tid; e < 2 * 16 * 16; e += kNT) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int e = tid + m * kNT;
       const int q = e >> 8, r = (e >> 4) & 15, p = e & 15;
       const int ch = 16 * ob + 8 * q;
-      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
-      if (ch < coutp) {
+      rz[m][0] = rz[m][1] = u32x4{0u, 0u, 0u, 0u};
+      if (ch < coutp) {  // channels at or past coutp stay zero
         const size_t vox = (static_cast<size_t>(x0 + (r >> 2)) * D + (y0 + (r & 3))) * D + z0 + 2 * p;
-        u0 = *reinterpret_cast<const u32x4*>(dz.p + vox * dz.ld + dz.off + ch);
-        u1 = *reinterpret_cast<const u32x4*>(dz.p + (vox + 1) * dz.ld + dz.off + ch);
+        rz[m][0] = *reinterpret_cast<const u32x4*>(dz.p + vox * dz.ld + dz.off + ch);
+        rz[m][1] = *reinterpret_cast<const u32x4*>(dz.p + (vox + 1) * dz.ld + dz.off + ch);
       }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) sz[(8 * q + j) * kWZC + r * 16 + p] = half16(u0, j) | (half16(u1, j) << 16);
     }
-    // x halo rows: (group q, halo row hr = 6 hx + hy, z pair p) for halo z 2 p, 2 p + 1 (voxel z0 - 1 + halo z)
-    for (int e = tid; e < 2 * 36 * 17; e += kNT) {
-      const int q = e / (36 * 17), rem = e - q * (36 * 17), hr = rem / 17, p = rem - hr * 17;
-      const int ch = 16 * ib + 8 * q;
-      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
-      if (ch < cin) {
-        const int gx = wrapi(x0 - 1 + hr / 6, D), gy = wrapi(y0 - 1 + hr % 6, D);
-        const size_t row = (static_cast<size_t>(gx) * D + gy) * D;
-        const size_t v0 = row + wrapi(z0 - 1 + 2 * p, D), v1 = row + wrapi(z0 + 2 * p, D);
-        u0 = *reinterpret_cast<const u32x4*>(x.p + v0 * x.ld + x.off + ch);
-        u1 = *reinterpret_cast<const u32x4*>(x.p + v1 * x.ld + x.off + ch);
-      }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sx[(8 * q + j) * kWXC + hr * kWRow + p] = half16(u0, j) | (half16(u1, j) << 16);
+    for (int m = 0; m < kHM; ++m) {
+      const int e = tid + m * kNT;
+      rh[m][0] = rh[m][1] = u32x4{0u, 0u, 0u, 0u};
+      if (e < kHI) {
+        const int q = e / (36 * 17), rem = e - q * (36 * 17), hr = rem / 17, p = rem - hr * 17;
+        const int ch = 16 * ib + 8 * q;
+        if (ch < cin) {
+          const int gx = wrapi(x0 - 1 + hr / 6, D), gy = wrapi(y0 - 1 + hr % 6, D);
+          const size_t row = (static_cast<size_t>(gx) * D + gy) * D;
+          const size_t v0 = row + wrapi(z0 - 1 + 2 * p, D), v1 = row + wrapi(z0 + 2 * p, D);
+          rh[m][0] = *reinterpret_cast<const u32x4*>(x.p + v0 * x.ld + x.off + ch);
+          rh[m][1] = *reinterpret_cast<const u32x4*>(x.p + v1 * x.ld + x.off + ch);
+        }
+      }
+    }
+  };
+  if (k0 < k1) load(k0);
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();  // the previous brick's reads are done
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int e = tid + m * kNT;
+      const int q = e >> 8, r = (e >> 4) & 15, p = e & 15;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        sz[(8 * q + j) * kWZC + r * 16 + p] = half16(rz[m][0], j) | (half16(rz[m][1], j) << 16);
+    }
+#pragma unroll
+    for (int m = 0; m < kHM; ++m) {
+      const int e = tid + m * kNT;
+      if (e < kHI) {
+        const int q = e / (36 * 17), rem = e - q * (36 * 17), hr = rem / 17, p = rem - hr * 17;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          sx[(8 * q + j) * kWXC + hr * kWRow + p] = half16(rh[m][0], j) | (half16(rh[m][1], j) << 16);
+      }
     }
     __syncthreads();
+    if (k + 1 < k1) load(k + 1);
     for (int ry = 0; ry < 4; ++ry) {
       const int r = wave * 4 + ry;
       const u32x4 a = *reinterpret_cast<const u32x4*>(sz + c16 * kWZC + r * 16 + 4 * g);
