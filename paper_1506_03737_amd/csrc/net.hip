@@ -150,6 +150,39 @@ __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(V
       }
     }
   }
+  // BF16 outputs with whole 8-channel groups: each wave stages its 4 x 16 voxels x 16 NB channels in the (now free)
+  // halo buffer and writes them as 16-byte rows; every wave takes both barriers.
+  constexpr int CO = 16 * NB;
+  constexpr bool kStage = 4 * 64 * CO <= kHalo * VS;
+  if (kStage && outf == nullptr && (cout & 7) == 0) {
+    __syncthreads();  // every wave is done reading the halo
+    bf16* st = halo + wave * (64 * CO);
+    if (wave_on) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + r;
+        const float b = (bias && co < cout) ? bias[co] : 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float val = acc[mt][nb][j] + b;
+            st[(mt * 16 + g * 4 + j) * CO + co] = static_cast<bf16>(act ? leaky(val) : val);
+          }
+      }
+    }
+    __syncthreads();
+    if (!wave_on) return;
+    const int x = x0 + wave, ng = cout / 8;
+    for (int c = lane; c < 64 * ng; c += 64) {
+      const int row = c / ng, q = c - row * ng;
+      const int y = y0 + row / 16, z = z0 + row % 16;
+      if (y < D && z < D)
+        *reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>((x * D + y) * D + z) * out.ld + out.off + 8 * q) =
+            *reinterpret_cast<const bf16x8*>(st + row * CO + 8 * q);
+    }
+    return;
+  }
   if (!wave_on) return;
   const int x = x0 + wave;
 #pragma unroll
