@@ -837,10 +837,14 @@ __global__ __launch_bounds__(kNT) void k_adam(float* __restrict__ p, float* __re
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// PACK: write the six features of the apply path (ref == NULL, psi1 given) straight into the network's BF16 input
+// row x[id][0..8) (channels 6, 7 zero), rounded as the FP32 grid would be by pack_input.
+template <bool PACK>
 __global__ __launch_bounds__(kNT) void k_features(const float* __restrict__ pos, const int32_t* __restrict__ id,
                                                   int64_t n, const float* __restrict__ ref,
                                                   const float* __restrict__ psi1, int N, double box,
-                                                  float* __restrict__ out, int ld, int* __restrict__ flags) {
+                                                  float* __restrict__ out, int ld, bf16* __restrict__ xpack,
+                                                  int* __restrict__ flags) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
   if (p >= n) return;
   const int64_t q = id[p];
@@ -851,12 +855,26 @@ __global__ __launch_bounds__(kNT) void k_features(const float* __restrict__ pos,
   }
   const double dp = box / N;
   const int64_t ijk[3] = {q / (static_cast<int64_t>(N) * N), (q / N) % N, q % N};
+  float fv[6];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double base = ref ? static_cast<double>(ref[d * n + p]) : (static_cast<double>(ijk[d]) + 0.5) * dp;
     double dd = static_cast<double>(pos[d * n + p]) - base;
     dd -= box * rint(dd / box);
-    out[q * ld + d] = static_cast<float>(dd / dp);
-    if (psi1) out[q * ld + 3 + d] = static_cast<float>(static_cast<double>(psi1[d * n + p]) / dp);
+    fv[d] = static_cast<float>(dd / dp);
+    fv[3 + d] = psi1 ? static_cast<float>(static_cast<double>(psi1[d * n + p]) / dp) : 0.f;
+  }
+  if constexpr (PACK) {
+    bf16x8 u;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) u[c] = static_cast<bf16>(c < kInputChannels ? fv[c] : 0.f);
+    *reinterpret_cast<bf16x8*>(xpack + q * 8) = u;
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      out[q * ld + d] = fv[d];
+      if (psi1) out[q * ld + 3 + d] = fv[3 + d];
+    }
   }
 }
 
@@ -1019,7 +1037,15 @@ hipError_t adam(float* p, float* m, float* v, const float* g, int64_t count, flo
 
 hipError_t features(const float* pos, const int32_t* id, int64_t n, const float* ref, const float* psi1, int N,
                     double box, float* out, int* flags, hipStream_t s) {
-  k_features<<<blocks_for(n), kNT, 0, s>>>(pos, id, n, ref, psi1, N, box, out, psi1 ? kInputChannels : 3, flags);
+  k_features<false><<<blocks_for(n), kNT, 0, s>>>(pos, id, n, ref, psi1, N, box, out, psi1 ? kInputChannels : 3,
+                                                  nullptr, flags);
+  return hipGetLastError();
+}
+
+hipError_t features_packed(const float* pos, const int32_t* id, int64_t n, const float* psi1, int N, double box,
+                           bf16* x, int* flags, hipStream_t s) {
+  if (!psi1) return hipErrorInvalidValue;
+  k_features<true><<<blocks_for(n), kNT, 0, s>>>(pos, id, n, nullptr, psi1, N, box, nullptr, 0, x, flags);
   return hipGetLastError();
 }
 

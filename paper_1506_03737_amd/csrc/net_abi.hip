@@ -206,12 +206,13 @@ void weight_grad(const NetWs& w, int l, View x, int cin, View dz, int D, float* 
         "reduce weight grad");
 }
 
-// Forward pass of the feature grid w.feat (FP32 [V][3]) into w.out (FP32 [V][3]).
-void forward(const NetWs& w, const float* params, hipStream_t s) {
+// Forward pass of the feature grid w.feat (FP32 [V][6]) into w.out (FP32 [V][3]); with input_packed the BF16 network
+// input w.x is already written (features_packed) and w.feat is not read.
+void forward(const NetWs& w, const float* params, hipStream_t s, bool input_packed = false) {
   const int D = w.D, Dh = D / 2, Dq = D / 4;
   const int V = D * D * D;
   convert_weights(w, params, s);
-  check(net::pack_input(w.feat, w.x, V, s), "pack input");
+  if (!input_packed) check(net::pack_input(w.feat, w.x, V, s), "pack input");
   conv_fwd(w, params, E0A, v(w.x, 8), v(w.a0, 16), nullptr, D, s);
   conv_fwd(w, params, E0B, v(w.a0, 16), v(w.cat0, 32, 16), nullptr, D, s);                       // s0
   check(net::down2(v(w.cat0, 32, 16), 16, Wp(params, DOWN1), Bp(params, DOWN1), 32, v(w.a1, 32), D, s), "down2");
@@ -399,11 +400,10 @@ lpc_status lpc_net_apply(const lpc_geometry* geom, const float* params, const lp
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() {
     check(hipMemsetAsync(w.flags, 0, 4 * sizeof(int), s), "hipMemsetAsync");
-    check(hipMemsetAsync(w.feat, 0, static_cast<size_t>(V) * net::kInputChannels * sizeof(float), s),
-          "hipMemsetAsync");
-    check(net::features(inout->pos, inout->id, inout->n, nullptr, inout->psi1, N, geom->box, w.feat, w.flags, s),
+    check(hipMemsetAsync(w.x, 0, static_cast<size_t>(V) * 8 * sizeof(bf16), s), "hipMemsetAsync");
+    check(net::features_packed(inout->pos, inout->id, inout->n, inout->psi1, N, geom->box, w.x, w.flags, s),
           "features");
-    forward(w, params, s);
+    forward(w, params, s, true);
     check(net::apply_residual(inout->pos, inout->id, inout->n, w.out, N, geom->box, w.flags, s), "apply");
     return sync_flags(w.flags, s);
   });

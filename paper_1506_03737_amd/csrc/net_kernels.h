@@ -80,6 +80,10 @@ hipError_t adam(float* p, float* m, float* v, const float* g, int64_t count, flo
 // stride 6, else 3). flags[0] is set if an id is out of range.
 hipError_t features(const float* pos, const int32_t* id, int64_t n, const float* ref, const float* psi1, int N,
                     double box, float* out, int* flags, hipStream_t s);
+// The same six features (lattice base, psi1 required) written as the network input x[id] = BF16 [8] (channels 6, 7
+// zero): what features followed by pack_input gives, in one pass.
+hipError_t features_packed(const float* pos, const int32_t* id, int64_t n, const float* psi1, int N, double box,
+                           bf16* x, int* flags, hipStream_t s);
 // pos = wrap(pos + r[id] L / N) for every particle.
 hipError_t apply_residual(float* pos, const int32_t* id, int64_t n, const float* r, int N, double box, int* flags,
                           hipStream_t s);
