@@ -353,35 +353,24 @@ __global__ __launch_bounds__(kNT) void k_transpose2(const float* __restrict__ W,
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Weight gradients on the vector ALUs, used for 3^3 layers on grids that are not a multiple of 32 per side (the
-// MFMA kernels below take the rest). Workgroup (chunk, tap) sums dz[zv(b, tap)][o] x[xv(b, tap)][i] over the base voxels b of its
-// chunk, for every (o, i); tap 0 also sums dz[..][o] for the bias. Base voxels, tiles of kTV, are staged in LDS as
-// FP32; thread groups take interleaved voxels of a tile and are reduced in LDS at the end.
+// Weight gradient of a 3^3 layer on the vector ALUs, for grids that are not a multiple of 32 per side (the MFMA
+// kernels below take the rest). Workgroup (chunk, tap) sums dz[p][o] x[p + d_tap][i] over the output voxels p of its
+// chunk, for every (o, i); tap 0 also sums dz[p][o] for the bias. Voxels, tiles of kTV, are staged in LDS as FP32;
+// thread groups take interleaved voxels of a tile and are reduced in LDS at the end.
 constexpr int kTV = 64;
 constexpr int kMaxC = 64;
 
-__device__ __forceinline__ void wgrad_voxels(int kind, int b, int tap, int D, int* xv, int* zv) {
-  if (kind == 0) {  // conv3: base = output voxel p on D^3; x at p + tap - 1
-    const int px = b / (D * D), py = (b / D) % D, pz = b % D;
-    const int x = wrapi(px + tap / 9 - 1, D), y = wrapi(py + (tap / 3) % 3 - 1, D), z = wrapi(pz + tap % 3 - 1, D);
-    *xv = (x * D + y) * D + z;
-    *zv = b;
-  } else if (kind == 1) {  // down2: base = output voxel y on (D/2)^3; x at 2y + t on D^3
-    const int Dc = D / 2;
-    const int yx = b / (Dc * Dc), yy = (b / Dc) % Dc, yz = b % Dc;
-    *xv = ((2 * yx + (tap >> 2)) * D + 2 * yy + ((tap >> 1) & 1)) * D + 2 * yz + (tap & 1);
-    *zv = b;
-  } else {  // up2: base = input voxel y on D^3; dz at 2y + t on (2D)^3
-    const int Df = 2 * D;
-    const int yx = b / (D * D), yy = (b / D) % D, yz = b % D;
-    *xv = b;
-    *zv = ((2 * yx + (tap >> 2)) * Df + 2 * yy + ((tap >> 1) & 1)) * Df + 2 * yz + (tap & 1);
-  }
+__device__ __forceinline__ int conv3_neighbour(int p, int tap, int D) {  // periodic voxel p + d_tap
+  const int px = p / (D * D), py = (p / D) % D, pz = p % D;
+  const int x = wrapi(px + tap / 9 - 1, D), y = wrapi(py + (tap / 3) % 3 - 1, D), z = wrapi(pz + tap % 3 - 1, D);
+  return (x * D + y) * D + z;
 }
 
 template <int CI>
-__global__ __launch_bounds__(kNT) void k_wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int D,
-                                               int ntap, int nbase, float* __restrict__ partial) {
+__global__ __launch_bounds__(kNT) void k_wgrad(View x, int cin, int cin_real, View dz, int cout, int D,
+                                               float* __restrict__ partial) {
+  constexpr int ntap = 27;
+  const int nbase = D * D * D;
   __shared__ float sdz[kTV * kMaxC];
   __shared__ float sx[kTV * kMaxC];
   __shared__ int sxv[kTV], szv[kTV];
@@ -405,10 +394,8 @@ __global__ __launch_bounds__(kNT) void k_wgrad(int kind, View x, int cin, int ci
     const int nv = min(kTV, b1 - t0);
     __syncthreads();
     if (tid < nv) {
-      int xv, zv;
-      wgrad_voxels(kind, t0 + tid, tap, D, &xv, &zv);
-      sxv[tid] = xv;
-      szv[tid] = zv;
+      sxv[tid] = conv3_neighbour(t0 + tid, tap, D);
+      szv[tid] = t0 + tid;
     }
     __syncthreads();
     for (int e = tid; e < nv * (gz + gx); e += kNT) {
@@ -448,17 +435,16 @@ __global__ __launch_bounds__(kNT) void k_wgrad(int kind, View x, int cin, int ci
     __syncthreads();
   }
   // canonical layout W[o][t][i] over the real input channels, then the bias (each (o, cb) pair summed dz[o]; take
-  // the cb == 0 one). For up2 every tap sees a different set of dz voxels, so each tap has its own bias slot.
+  // the cb == 0 one)
   const int nW = cout * ntap * cin_real;
-  const int nslot = (kind == 2) ? ntap : 1;
-  float* dst = partial + static_cast<size_t>(chunk) * (nW + nslot * cout);
+  float* dst = partial + static_cast<size_t>(chunk) * (nW + cout);
   for (int e = tid; e < slice; e += kNT) {
     const int p = e / CI, c = e % CI;
     const int oo = p / ncb, ci = (p % ncb) * CI + c;
     if (ci < cin_real) dst[(oo * ntap + tap) * cin_real + ci] = red[e];
   }
-  if (kind == 2 || tap == 0)
-    for (int e = tid; e < cout; e += kNT) dst[nW + (kind == 2 ? tap : 0) * cout + e] = sdz[e * ncb];
+  if (tap == 0)
+    for (int e = tid; e < cout; e += kNT) dst[nW + e] = sdz[e * ncb];
 }
 
 // Weight gradient of a 3^3 layer on v_mfma_f32_16x16x32_bf16, for D a multiple of 32: dW[o][t][i] =
@@ -982,13 +968,11 @@ hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int
       k_wgrad2<<<grid, kNT, 0, s>>>(kind, x, cin, cin_real, dz, cout, D, nchunk, partial);
     return hipGetLastError();
   }
-  const int ntap = (kind == 0) ? 27 : 8;
-  const int nbase = (kind == 1) ? (D / 2) * (D / 2) * (D / 2) : D * D * D;
-  const dim3 grid(static_cast<unsigned>(wgrad_chunks(kind, cin, cout, D)), static_cast<unsigned>(ntap));
+  const dim3 grid(static_cast<unsigned>(wgrad_chunks(kind, cin, cout, D)), 27u);  // a 3^3 layer on a small grid
   if (cin == 8)
-    k_wgrad<8><<<grid, kNT, 0, s>>>(kind, x, cin, cin_real, dz, cout, D, ntap, nbase, partial);
+    k_wgrad<8><<<grid, kNT, 0, s>>>(x, cin, cin_real, dz, cout, D, partial);
   else if ((cin % 16) == 0 && cout * (cin / 16) <= kNT)
-    k_wgrad<16><<<grid, kNT, 0, s>>>(kind, x, cin, cin_real, dz, cout, D, ntap, nbase, partial);
+    k_wgrad<16><<<grid, kNT, 0, s>>>(x, cin, cin_real, dz, cout, D, partial);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
