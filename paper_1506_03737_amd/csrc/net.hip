@@ -46,7 +46,7 @@ __device__ __forceinline__ int modi(int a, int D) {
 template <int CIN, int NB>
 __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(View in, const bf16* __restrict__ w, int kpad,
                                                const float* __restrict__ bias, int act, View out,
-                                               float* __restrict__ outf, int cout, int D) {
+                                               float* __restrict__ outf, int cout, int D, View mask, int mask_ch) {
   constexpr int CC = CIN < 32 ? CIN : 32;   // channels per staged chunk
   constexpr int NCH = CIN / CC;             // chunks
   constexpr int VS = CC + 8;                // LDS voxel stride (bf16), padded against bank conflicts
@@ -177,9 +177,17 @@ __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(V
     for (int c = lane; c < 64 * ng; c += 64) {
       const int row = c / ng, q = c - row * ng;
       const int y = y0 + row / 16, z = z0 + row % 16;
-      if (y < D && z < D)
-        *reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>((x * D + y) * D + z) * out.ld + out.off + 8 * q) =
-            *reinterpret_cast<const bf16x8*>(st + row * CO + 8 * q);
+      if (y < D && z < D) {
+        const size_t v = static_cast<size_t>((x * D + y) * D + z);
+        bf16x8 val = *reinterpret_cast<const bf16x8*>(st + row * CO + 8 * q);
+        if (8 * q < mask_ch) {  // leaky-ReLU gradient, rounded as a separate pass over the stored values would be
+          const bf16x8 a = *reinterpret_cast<const bf16x8*>(mask.p + v * mask.ld + mask.off + 8 * q);
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (!(f(a[j]) > 0.f)) val[j] = static_cast<bf16>(kSlope * f(val[j]));
+        }
+        *reinterpret_cast<bf16x8*>(out.p + v * out.ld + out.off + 8 * q) = val;
+      }
     }
     return;
   }
@@ -200,10 +208,13 @@ __global__ __launch_bounds__(kNT, (CIN >= 64 && NB >= 4) ? 2 : 3) void k_conv3(V
         if (z >= D) continue;
         const size_t v = static_cast<size_t>((x * D + y) * D + z);
         const float val = acc[mt][nb][j] + b;
-        if (outf)
+        if (outf) {
           outf[v * cout + co] = val;
-        else
-          out.p[v * out.ld + out.off + co] = static_cast<bf16>(act ? leaky(val) : val);
+        } else {
+          bf16 o = static_cast<bf16>(act ? leaky(val) : val);
+          if (co < mask_ch && !(f(mask.p[v * mask.ld + mask.off + co]) > 0.f)) o = static_cast<bf16>(kSlope * f(o));
+          out.p[v * out.ld + out.off + co] = o;
+        }
       }
     }
   }
@@ -240,7 +251,7 @@ __device__ __forceinline__ int fine_voxel(int y, int Dc, int t) {  // voxel 2 y 
 // DG: the data gradient of a 2^3 up layer, the same product without bias and activation (W its weights transposed).
 template <int CIN, int COUT, bool DG>
 __global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__ W, const float* __restrict__ b,
-                                               View out, int D) {
+                                               View out, int D, View mask, int mask_ch) {
   static_assert(CIN % 8 == 0 && COUT % 16 == 0, "fragment shapes");
   constexpr int KS = 8 * CIN / 32, NBLK = COUT / 16;
   __shared__ bf16 stage[4][16 * COUT];
@@ -282,9 +293,16 @@ __global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__
   for (int c = lane; c < NCH; c += 64) {
     const int row = c / (COUT / 8), q8 = c % (COUT / 8);
     const int yr = y0 + row;
-    if (yr < Vc)
-      *reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>(yr) * out.ld + out.off + 8 * q8) =
-          *reinterpret_cast<const bf16x8*>(st + row * COUT + 8 * q8);
+    if (yr < Vc) {
+      bf16x8 val = *reinterpret_cast<const bf16x8*>(st + row * COUT + 8 * q8);
+      if (DG && 8 * q8 < mask_ch) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(mask.p + static_cast<size_t>(yr) * mask.ld + mask.off + 8 * q8);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (!(f(a[j]) > 0.f)) val[j] = static_cast<bf16>(kSlope * f(val[j]));
+      }
+      *reinterpret_cast<bf16x8*>(out.p + static_cast<size_t>(yr) * out.ld + out.off + 8 * q8) = val;
+    }
   }
 }
 
@@ -293,7 +311,7 @@ __global__ __launch_bounds__(kNT) void k_down2(View x, const float* __restrict__
 // added to what out holds when accumulate is set.
 template <int CIN, int COUT, bool DG>
 __global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ W, const float* __restrict__ b,
-                                             View out, int D, int accumulate) {
+                                             View out, int D, int accumulate, View mask, int mask_ch) {
   static_assert(CIN % 32 == 0 && COUT % 16 == 0, "fragment shapes");
   constexpr int KS = CIN / 32, NBLK = 8 * COUT / 16;
   __shared__ bf16 stage[4][16 * 8 * COUT];  // [coarse row][tap][channel] per wave
@@ -337,6 +355,13 @@ __global__ __launch_bounds__(kNT) void k_up2(View x, const float* __restrict__ W
         const bf16x8 old = *dst;
 #pragma unroll
         for (int j = 0; j < 8; ++j) val[j] = static_cast<bf16>(f(old[j]) + f(val[j]));
+      }
+      if (DG && 8 * q8 < mask_ch) {
+        const size_t fv = static_cast<size_t>(fine_voxel(yr, D, t));
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(mask.p + fv * mask.ld + mask.off + 8 * q8);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (!(f(a[j]) > 0.f)) val[j] = static_cast<bf16>(kSlope * f(val[j]));
       }
       *dst = val;
     }
@@ -737,21 +762,6 @@ __global__ __launch_bounds__(kNT) void k_reduce(const float* __restrict__ partia
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// one thread per 8 channels of a voxel (16-byte loads and store; c, ld and off are multiples of 8)
-__global__ __launch_bounds__(kNT) void k_leaky_dgrad(View a, View da, int c, int V) {
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
-  const int c8 = c / 8;
-  if (idx >= static_cast<int64_t>(V) * c8) return;
-  const int v = static_cast<int>(idx / c8), ch = 8 * static_cast<int>(idx % c8);
-  bf16x8* d = reinterpret_cast<bf16x8*>(da.p + static_cast<size_t>(v) * da.ld + da.off + ch);
-  const bf16x8 av = *reinterpret_cast<const bf16x8*>(a.p + static_cast<size_t>(v) * a.ld + a.off + ch);
-  bf16x8 dv = *d;
-#pragma unroll
-  for (int j = 0; j < 8; ++j)
-    if (!(f(av[j]) > 0.f)) dv[j] = static_cast<bf16>(kSlope * f(dv[j]));
-  *d = dv;
-}
-
 __global__ __launch_bounds__(kNT) void k_convert_conv3(const float* __restrict__ W, int cout, int cin,
                                                        bf16* __restrict__ wf, int cinp, int nbo, int kpad,
                                                        bf16* __restrict__ wb, int coutp, int nbi, int kpadb) {
@@ -885,9 +895,11 @@ __global__ __launch_bounds__(kNT) void k_apply(float* __restrict__ pos, const in
 }  // namespace
 
 hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float* bias, int leaky_act, View out,
-                 float* outf, int cout, int D, hipStream_t s) {
+                 float* outf, int cout, int D, hipStream_t s, View mask, int mask_ch) {
+  if (mask_ch > 0 && (outf || !mask.p || (mask_ch & 7) != 0)) return hipErrorInvalidValue;
   const unsigned grid = static_cast<unsigned>(((D + 3) / 4) * ((D + 3) / 4) * ((D + 15) / 16));
-#define LPC_CONV(CI, NBV) k_conv3<CI, NBV><<<grid, kNT, 0, s>>>(in, w, kpad, bias, leaky_act, out, outf, cout, D)
+#define LPC_CONV(CI, NBV) \
+  k_conv3<CI, NBV><<<grid, kNT, 0, s>>>(in, w, kpad, bias, leaky_act, out, outf, cout, D, mask, mask_ch)
   if (cin == 8 && nb == 1) LPC_CONV(8, 1);
   else if (cin == 8 && nb == 2) LPC_CONV(8, 2);
   else if (cin == 8 && nb == 4) LPC_CONV(8, 4);
@@ -907,35 +919,44 @@ hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float*
 
 hipError_t down2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
   const unsigned grid = blocks_for(static_cast<int64_t>(D / 2) * (D / 2) * (D / 2), 64);  // 64 coarse voxels per block
-  if (cin == 16 && cout == 32) k_down2<16, 32, false><<<grid, kNT, 0, s>>>(x, W, b, out, D);
-  else if (cin == 32 && cout == 64) k_down2<32, 64, false><<<grid, kNT, 0, s>>>(x, W, b, out, D);
+  const View none{nullptr, 0, 0};
+  if (cin == 16 && cout == 32) k_down2<16, 32, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, none, 0);
+  else if (cin == 32 && cout == 64) k_down2<32, 64, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, none, 0);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t up2(View x, int cin, const float* W, const float* b, int cout, View out, int D, hipStream_t s) {
   const unsigned grid = blocks_for(static_cast<int64_t>(D) * D * D, 64);  // 64 coarse voxels per block
-  if (cin == 64 && cout == 32) k_up2<64, 32, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, 0);
-  else if (cin == 32 && cout == 16) k_up2<32, 16, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, 0);
+  const View none{nullptr, 0, 0};
+  if (cin == 64 && cout == 32) k_up2<64, 32, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, 0, none, 0);
+  else if (cin == 32 && cout == 16) k_up2<32, 16, false><<<grid, kNT, 0, s>>>(x, W, b, out, D, 0, none, 0);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 // The data gradient of a 2^3 down layer has the form of an up layer from dz's grid, and that of an up layer the
 // form of a down layer onto dx's grid, both with the transposed weights Wt[i][t][o].
-hipError_t down2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, int accumulate, hipStream_t s) {
+hipError_t down2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, int accumulate, hipStream_t s,
+                       View mask, int mask_ch) {
+  if (mask_ch > 0 && (!mask.p || (mask_ch & 7) != 0)) return hipErrorInvalidValue;
   const int Dc = D / 2;
   const unsigned grid = blocks_for(static_cast<int64_t>(Dc) * Dc * Dc, 64);
-  if (cin == 16 && cout == 32) k_up2<32, 16, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, Dc, accumulate);
-  else if (cin == 32 && cout == 64) k_up2<64, 32, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, Dc, accumulate);
+  if (cin == 16 && cout == 32)
+    k_up2<32, 16, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, Dc, accumulate, mask, mask_ch);
+  else if (cin == 32 && cout == 64)
+    k_up2<64, 32, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, Dc, accumulate, mask, mask_ch);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t up2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, hipStream_t s) {
+hipError_t up2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, hipStream_t s, View mask,
+                     int mask_ch) {
+  if (mask_ch > 0 && (!mask.p || (mask_ch & 7) != 0)) return hipErrorInvalidValue;
   const unsigned grid = blocks_for(static_cast<int64_t>(D) * D * D, 64);
-  if (cin == 32 && cout == 16) k_down2<16, 32, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, 2 * D);
-  else if (cin == 64 && cout == 32) k_down2<32, 64, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, 2 * D);
+  if (cin == 32 && cout == 16) k_down2<16, 32, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, 2 * D, mask, mask_ch);
+  else if (cin == 64 && cout == 32)
+    k_down2<32, 64, true><<<grid, kNT, 0, s>>>(dz, Wt, nullptr, dx, 2 * D, mask, mask_ch);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -981,12 +1002,6 @@ hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int
 hipError_t reduce_partials(const float* partial, int nchunk, int nW, int cout, int nslot, float* grad,
                            hipStream_t s) {
   k_reduce<<<blocks_for(nW + cout, 64), kNT, 0, s>>>(partial, nchunk, nW, cout, nslot, grad);
-  return hipGetLastError();
-}
-
-hipError_t leaky_dgrad(View a, View da, int c, int V, hipStream_t s) {
-  if (c % 8 != 0) return hipErrorInvalidValue;
-  k_leaky_dgrad<<<blocks_for(static_cast<int64_t>(V) * (c / 8)), kNT, 0, s>>>(a, da, c, V);
   return hipGetLastError();
 }
 

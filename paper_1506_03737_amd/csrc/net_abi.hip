@@ -190,10 +190,12 @@ void conv_fwd(const NetWs& w, const float* params, int l, View in, View out, flo
 }
 
 // data gradient of 3^3 layer l: dx[.][cin] = conv3(dz[.][coutp], flipped weights)
-void conv_dgrad(const NetWs& w, int l, View dz, View dx, int D, hipStream_t s) {
+// (channels below mask_ch then get the leaky-ReLU gradient of the activation view mask)
+void conv_dgrad(const NetWs& w, int l, View dz, View dx, int D, hipStream_t s, View mask, int mask_ch) {
   const LayerDef& L = kLayers[l];
   const ConvShape c = conv_shape(L);
-  check(net::conv3(dz, c.coutp, w.wb[l], c.kpadb, c.nbi, nullptr, 0, dx, nullptr, L.cin, D, s), "conv3 data grad");
+  check(net::conv3(dz, c.coutp, w.wb[l], c.kpadb, c.nbi, nullptr, 0, dx, nullptr, L.cin, D, s, mask, mask_ch),
+        "conv3 data grad");
 }
 
 void weight_grad(const NetWs& w, int l, View x, int cin, View dz, int D, float* grad, hipStream_t s) {
@@ -231,47 +233,39 @@ void backward(const NetWs& w, const float* params, const float* target, float* g
   const int D = w.D, Dh = D / 2, Dq = D / 4;
   const int V = D * D * D, Vh = V / 8, Vq = V / 64;
   check(net::loss_grad(w.out, target, w.dout, w.loss_part, V, s), "loss grad");
+  // Each data gradient applies the leaky-ReLU gradient of the activation it flows into as it is written.
   // out = conv3(c0)
   weight_grad(w, OUT, v(w.c0, 16), 16, v(w.dout, 8), D, grad, s);
-  conv_dgrad(w, OUT, v(w.dout, 8), v(w.dc0, 16), D, s);
-  // c0 = leaky(conv3([u0, s0]))
-  check(net::leaky_dgrad(v(w.c0, 16), v(w.dc0, 16), 16, V, s), "leaky grad");
+  conv_dgrad(w, OUT, v(w.dout, 8), v(w.dc0, 16), D, s, v(w.c0, 16), 16);  // c0 = leaky(conv3([u0, s0]))
   weight_grad(w, C0, v(w.cat0, 32), 32, v(w.dc0, 16), D, grad, s);
-  conv_dgrad(w, C0, v(w.dc0, 16), v(w.dcat0, 32), D, s);
-  // u0 = leaky(up2(c1))
-  check(net::leaky_dgrad(v(w.cat0, 32, 0), v(w.dcat0, 32, 0), 16, V, s), "leaky grad");
+  // u0 = leaky(up2(c1)) takes channels 0..15; s0's gradient is complete only after the down layer's part below
+  conv_dgrad(w, C0, v(w.dc0, 16), v(w.dcat0, 32), D, s, v(w.cat0, 32, 0), 16);
   weight_grad(w, UP0, v(w.c1, 32), 32, v(w.dcat0, 32, 0), Dh, grad, s);
-  check(net::up2_dgrad(v(w.dcat0, 32, 0), 16, w.wt[UP0], 32, v(w.dc1, 32), Dh, s), "up2 grad");
   // c1 = leaky(conv3([u1, s1]))
-  check(net::leaky_dgrad(v(w.c1, 32), v(w.dc1, 32), 32, Vh, s), "leaky grad");
+  check(net::up2_dgrad(v(w.dcat0, 32, 0), 16, w.wt[UP0], 32, v(w.dc1, 32), Dh, s, v(w.c1, 32), 32), "up2 grad");
   weight_grad(w, C1, v(w.cat1, 64), 64, v(w.dc1, 32), Dh, grad, s);
-  conv_dgrad(w, C1, v(w.dc1, 32), v(w.dcat1, 64), Dh, s);
-  // u1 = leaky(up2(b2))
-  check(net::leaky_dgrad(v(w.cat1, 64, 0), v(w.dcat1, 64, 0), 32, Vh, s), "leaky grad");
+  // u1 = leaky(up2(b2)) takes channels 0..31
+  conv_dgrad(w, C1, v(w.dc1, 32), v(w.dcat1, 64), Dh, s, v(w.cat1, 64, 0), 32);
   weight_grad(w, UP1, v(w.b2, 64), 64, v(w.dcat1, 64, 0), Dq, grad, s);
-  check(net::up2_dgrad(v(w.dcat1, 64, 0), 32, w.wt[UP1], 64, v(w.db2, 64), Dq, s), "up2 grad");
   // b2 = leaky(conv3(a2))
-  check(net::leaky_dgrad(v(w.b2, 64), v(w.db2, 64), 64, Vq, s), "leaky grad");
+  check(net::up2_dgrad(v(w.dcat1, 64, 0), 32, w.wt[UP1], 64, v(w.db2, 64), Dq, s, v(w.b2, 64), 64), "up2 grad");
   weight_grad(w, B2, v(w.a2, 64), 64, v(w.db2, 64), Dq, grad, s);
-  conv_dgrad(w, B2, v(w.db2, 64), v(w.da2, 64), Dq, s);
-  // a2 = leaky(down2(s1)); s1 also feeds c1, so its gradient accumulates
-  check(net::leaky_dgrad(v(w.a2, 64), v(w.da2, 64), 64, Vq, s), "leaky grad");
+  // a2 = leaky(down2(s1))
+  conv_dgrad(w, B2, v(w.db2, 64), v(w.da2, 64), Dq, s, v(w.a2, 64), 64);
   weight_grad(w, DOWN2, v(w.cat1, 64, 32), 32, v(w.da2, 64), Dh, grad, s);
-  check(net::down2_dgrad(v(w.da2, 64), 64, w.wt[DOWN2], 32, v(w.dcat1, 64, 32), Dh, 1, s), "down2 grad");
-  // s1 = leaky(conv3(a1))
-  check(net::leaky_dgrad(v(w.cat1, 64, 32), v(w.dcat1, 64, 32), 32, Vh, s), "leaky grad");
+  // s1 = leaky(conv3(a1)) also feeds c1, so its gradient accumulates before the activation's gradient
+  check(net::down2_dgrad(v(w.da2, 64), 64, w.wt[DOWN2], 32, v(w.dcat1, 64, 32), Dh, 1, s, v(w.cat1, 64, 32), 32),
+        "down2 grad");
   weight_grad(w, E1, v(w.a1, 32), 32, v(w.dcat1, 64, 32), Dh, grad, s);
-  conv_dgrad(w, E1, v(w.dcat1, 64, 32), v(w.da1, 32), Dh, s);
-  // a1 = leaky(down2(s0)); s0 also feeds c0
-  check(net::leaky_dgrad(v(w.a1, 32), v(w.da1, 32), 32, Vh, s), "leaky grad");
+  // a1 = leaky(down2(s0))
+  conv_dgrad(w, E1, v(w.dcat1, 64, 32), v(w.da1, 32), Dh, s, v(w.a1, 32), 32);
   weight_grad(w, DOWN1, v(w.cat0, 32, 16), 16, v(w.da1, 32), D, grad, s);
-  check(net::down2_dgrad(v(w.da1, 32), 32, w.wt[DOWN1], 16, v(w.dcat0, 32, 16), D, 1, s), "down2 grad");
-  // s0 = leaky(conv3(a0))
-  check(net::leaky_dgrad(v(w.cat0, 32, 16), v(w.dcat0, 32, 16), 16, V, s), "leaky grad");
+  // s0 = leaky(conv3(a0)) also feeds c0
+  check(net::down2_dgrad(v(w.da1, 32), 32, w.wt[DOWN1], 16, v(w.dcat0, 32, 16), D, 1, s, v(w.cat0, 32, 16), 16),
+        "down2 grad");
   weight_grad(w, E0B, v(w.a0, 16), 16, v(w.dcat0, 32, 16), D, grad, s);
-  conv_dgrad(w, E0B, v(w.dcat0, 32, 16), v(w.da0, 16), D, s);
   // a0 = leaky(conv3(x))
-  check(net::leaky_dgrad(v(w.a0, 16), v(w.da0, 16), 16, V, s), "leaky grad");
+  conv_dgrad(w, E0B, v(w.dcat0, 32, 16), v(w.da0, 16), D, s, v(w.a0, 16), 16);
   weight_grad(w, E0A, v(w.x, 8), 8, v(w.da0, 16), D, grad, s);
 }
 

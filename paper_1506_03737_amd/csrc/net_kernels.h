@@ -27,9 +27,11 @@ struct View {        // a BF16 tensor view: base[v * ld + off + c]
 //   w: BF16 [16 nb][kpad] (kpad = 27 cin rounded up to 32; padding rows / columns zero)
 //   bias: FP32 [cout] or NULL; leaky: apply leaky ReLU (slope 0.1)
 //   out: BF16 view, or outf (FP32 [V][cout]) when outf != NULL. Only channels < cout are written.
+//   mask, mask_ch (BF16 out only; mask_ch a multiple of 8): out channels c < mask_ch are multiplied by the leaky-ReLU
+//   slope where the activation mask[v][c] is not positive, after rounding (the leaky-ReLU gradient, fused).
 // The same kernel computes the data gradient of a convolution with the flipped, transposed weights.
 hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float* bias, int leaky, View out,
-                 float* outf, int cout, int D, hipStream_t s);
+                 float* outf, int cout, int D, hipStream_t s, View mask = View{nullptr, 0, 0}, int mask_ch = 0);
 
 // 2^3 stride-2 convolution (down) and transposed convolution (up), FP32 weights in the canonical layout.
 //   down: out[y][o] = b[o] + sum_{t, i} W[o][t][i] x[2y + t][i]     (x on D^3, out on (D/2)^3)
@@ -40,8 +42,11 @@ hipError_t up2(View x, int cin, const float* W, const float* b, int cout, View o
 // (16, 32) and (32, 64) for down, (32, 16) and (64, 32) for up; accumulate adds into dx instead of overwriting it.
 //   down: dx[2y + t][i] (+)= sum_o Wt[i][t][o] dz[y][o]       (dx on D^3, dz on (D/2)^3)
 //   up:   dx[y][i] = sum_{t, o} Wt[i][t][o] dz[2y + t][o]      (dx on D^3, dz on (2D)^3)
-hipError_t down2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, int accumulate, hipStream_t s);
-hipError_t up2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, hipStream_t s);
+// mask, mask_ch: the fused leaky-ReLU gradient as for conv3 (applied after the accumulation).
+hipError_t down2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, int accumulate, hipStream_t s,
+                       View mask = View{nullptr, 0, 0}, int mask_ch = 0);
+hipError_t up2_dgrad(View dz, int cout, const float* Wt, int cin, View dx, int D, hipStream_t s,
+                     View mask = View{nullptr, 0, 0}, int mask_ch = 0);
 // Wt[i][t][o] = W[o][t][i] (FP32, cout x 8 x cin values)
 hipError_t transpose2(const float* W, int cout, int cin, float* Wt, hipStream_t s);
 
@@ -55,9 +60,6 @@ hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int
 // grad[0..nW) = sum over chunks; grad[nW + o] = sum over chunks and slots (over wgrad_chunks(...) chunks)
 hipError_t reduce_partials(const float* partial, int nchunk, int nW, int cout, int nslot, float* grad,
                            hipStream_t s);
-
-// dz = da * (a > 0 ? 1 : 0.1) in place on da (a: the layer's stored output)
-hipError_t leaky_dgrad(View a, View da, int c, int V, hipStream_t s);
 
 // Canonical FP32 weights of a 3^3 conv -> BF16 MFMA layouts: forward [16 nbo][kpad] with k = t cinp + ci, and
 // flipped [16 nbi][kpadb] with k = t' coutp + o holding W[o][26 - t'][i] (the data-gradient convolution).
