@@ -742,23 +742,29 @@ __global__ __launch_bounds__(kNT, 2) void k_wgrad2(int kind, View x, int cin, in
 }
 
 // grad[j] = sum over chunks (and, for the bias, over its nslot slots) of the partial sums, in a fixed order: a block
-// takes 64 outputs, wave q sums the chunks c = q mod 4, and the four wave sums are added in order.
-__global__ __launch_bounds__(kNT) void k_reduce(const float* __restrict__ partial, int nchunk, int nW, int cout,
-                                                int nslot, float* __restrict__ grad) {
-  __shared__ float part[4][64];
+// of kRW waves takes 64 outputs, wave q sums the chunks c = q mod kRW, and the wave sums are added in order.
+constexpr int kRW = 16;
+__global__ __launch_bounds__(64 * kRW) void k_reduce(const float* __restrict__ partial, int nchunk, int nW, int cout,
+                                                     int nslot, float* __restrict__ grad) {
+  __shared__ float part[kRW][64];
   const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
   const int j = blockIdx.x * 64 + lane;
   const size_t stride = static_cast<size_t>(nW) + static_cast<size_t>(nslot) * cout;
   float s = 0.f;
   if (j < nW) {
-    for (int c = q; c < nchunk; c += 4) s += partial[c * stride + j];
+    for (int c = q; c < nchunk; c += kRW) s += partial[c * stride + j];
   } else if (j < nW + cout) {
-    for (int c = q; c < nchunk; c += 4)
+    for (int c = q; c < nchunk; c += kRW)
       for (int k = 0; k < nslot; ++k) s += partial[c * stride + nW + k * cout + (j - nW)];
   }
   part[q][lane] = s;
   __syncthreads();
-  if (q == 0 && j < nW + cout) grad[j] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+  if (q == 0 && j < nW + cout) {
+    float t = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < kRW; ++w) t += part[w][lane];
+    grad[j] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -1001,7 +1007,7 @@ hipError_t wgrad(int kind, View x, int cin, int cin_real, View dz, int cout, int
 
 hipError_t reduce_partials(const float* partial, int nchunk, int nW, int cout, int nslot, float* grad,
                            hipStream_t s) {
-  k_reduce<<<blocks_for(nW + cout, 64), kNT, 0, s>>>(partial, nchunk, nW, cout, nslot, grad);
+  k_reduce<<<blocks_for(nW + cout, 64), 64 * kRW, 0, s>>>(partial, nchunk, nW, cout, nslot, grad);
   return hipGetLastError();
 }
 
