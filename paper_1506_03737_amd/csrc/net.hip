@@ -664,36 +664,57 @@ __global__ __launch_bounds__(kNT, 2) void k_wgrad2(int kind, View x, int cin, in
     acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     bs[t] = 0.f;
   }
-  for (int k = k0; k < k1; ++k) {
+  // Staging items of a thread: the tap operand (tap t, group q, voxel pair p) for items tid + 256 m, m < 4; the other
+  // operand (group q, voxel pair p) for item tid < 128. The next block's items are loaded into registers before the
+  // current block's MFMAs and written to LDS after them.
+  constexpr int kTM = 8 * 2 * (kW2Y / 2) / kNT;
+  u32x4 rt[kTM][2], ru[2];
+  auto load = [&](int k) {
     const int y0 = k * kW2Y;
-    __syncthreads();  // the previous block's reads are done
-    for (int e = tid; e < 8 * 2 * (kW2Y / 2); e += kNT) {  // (tap t, group q, voxel pair p)
+#pragma unroll
+    for (int m = 0; m < kTM; ++m) {
+      const int e = tid + m * kNT;
       const int t = e >> 7, q = (e >> 6) & 1, p = e & 63;
       const int ch = cht + 8 * q, y = y0 + 2 * p;
-      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
+      rt[m][0] = rt[m][1] = u32x4{0u, 0u, 0u, 0u};
       if (ch < mt) {
         if (y < nbase)
-          u0 = *reinterpret_cast<const u32x4*>(vt.p + static_cast<size_t>(fine_voxel(y, Dc, t)) * vt.ld + vt.off + ch);
+          rt[m][0] =
+              *reinterpret_cast<const u32x4*>(vt.p + static_cast<size_t>(fine_voxel(y, Dc, t)) * vt.ld + vt.off + ch);
         if (y + 1 < nbase)
-          u1 = *reinterpret_cast<const u32x4*>(vt.p + static_cast<size_t>(fine_voxel(y + 1, Dc, t)) * vt.ld + vt.off +
-                                               ch);
+          rt[m][1] = *reinterpret_cast<const u32x4*>(vt.p + static_cast<size_t>(fine_voxel(y + 1, Dc, t)) * vt.ld +
+                                                     vt.off + ch);
       }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) st[(t * 16 + 8 * q + j) * kW2P + p] = half16(u0, j) | (half16(u1, j) << 16);
     }
-    if (tid < 2 * (kW2Y / 2)) {  // (group q, voxel pair p)
+    ru[0] = ru[1] = u32x4{0u, 0u, 0u, 0u};
+    if (tid < 2 * (kW2Y / 2)) {
       const int q = tid >> 6, p = tid & 63;
       const int ch = chu + 8 * q, y = y0 + 2 * p;
-      u32x4 u0 = u32x4{0u, 0u, 0u, 0u}, u1 = u0;
       if (ch < mu) {
-        if (y < nbase) u0 = *reinterpret_cast<const u32x4*>(vu.p + static_cast<size_t>(y) * vu.ld + vu.off + ch);
+        if (y < nbase) ru[0] = *reinterpret_cast<const u32x4*>(vu.p + static_cast<size_t>(y) * vu.ld + vu.off + ch);
         if (y + 1 < nbase)
-          u1 = *reinterpret_cast<const u32x4*>(vu.p + static_cast<size_t>(y + 1) * vu.ld + vu.off + ch);
+          ru[1] = *reinterpret_cast<const u32x4*>(vu.p + static_cast<size_t>(y + 1) * vu.ld + vu.off + ch);
       }
+    }
+  };
+  if (k0 < k1) load(k0);
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();  // the previous block's reads are done
 #pragma unroll
-      for (int j = 0; j < 8; ++j) su[(8 * q + j) * kW2P + p] = half16(u0, j) | (half16(u1, j) << 16);
+    for (int m = 0; m < kTM; ++m) {
+      const int e = tid + m * kNT;
+      const int t = e >> 7, q = (e >> 6) & 1, p = e & 63;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        st[(t * 16 + 8 * q + j) * kW2P + p] = half16(rt[m][0], j) | (half16(rt[m][1], j) << 16);
+    }
+    if (tid < 2 * (kW2Y / 2)) {
+      const int q = tid >> 6, p = tid & 63;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) su[(8 * q + j) * kW2P + p] = half16(ru[0], j) | (half16(ru[1], j) << 16);
     }
     __syncthreads();
+    if (k + 1 < k1) load(k + 1);
     const int dw = 16 * wave + 4 * g;
     const u32x4 fu = *reinterpret_cast<const u32x4*>(su + c16 * kW2P + dw);
     if (down && do_bias) {
