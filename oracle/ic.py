@@ -130,16 +130,23 @@ def lattice_positions(n_side, box):
     return np.stack([qx.ravel(), qy.ravel(), qz.ravel()])
 
 
-def initial_conditions(seed, n_side, box, a_init, omega_m, h, n_s, sigma8):
-    """2LPT particles at a_init. Returns dict of float64 arrays pos, vel, psi1, psi2 (each (3, N^3)) and id (N^3,)."""
-    delta_hat = gaussian_field_hat(seed, n_side, box, omega_m, h, n_s, sigma8)
-    psi1, psi2 = lpt_displacements(delta_hat, n_side, box)
+def particles_from_displacements(psi1, psi2, n_side, box, a_init, omega_m):
+    """The particles at a_init from the z = 0 displacement fields (each (3, N, N, N) or (3, N^3)), Sec. 2.1 Eq. 5 and
+    Sec. 2.2: x = q + D1(a) Psi1 + D2(a) Psi2 wrapped into [0, L), and the momentum of the 2LPT trajectory,
+    p = a^2 dx/dt / H0 = a^3 E(a) (D1'(a) Psi1 + D2'(a) Psi2). Returns the dict of initial_conditions."""
     npart = n_side**3
-    psi1 = psi1.reshape(3, npart)
-    psi2 = psi2.reshape(3, npart)
+    psi1 = np.asarray(psi1, dtype=np.float64).reshape(3, npart)
+    psi2 = np.asarray(psi2, dtype=np.float64).reshape(3, npart)
     d1 = cosmo.growth_D1(a_init, omega_m)
     d2 = cosmo.growth_D2(a_init, omega_m)
     f1, f2 = cosmo.frame_momentum_factors(a_init, omega_m)
     pos = np.mod(lattice_positions(n_side, box) + d1 * psi1 + d2 * psi2, box)
     vel = f1 * psi1 + f2 * psi2
     return {"pos": pos, "vel": vel, "psi1": psi1, "psi2": psi2, "id": np.arange(npart, dtype=np.int64)}
+
+
+def initial_conditions(seed, n_side, box, a_init, omega_m, h, n_s, sigma8):
+    """2LPT particles at a_init. Returns dict of float64 arrays pos, vel, psi1, psi2 (each (3, N^3)) and id (N^3,)."""
+    delta_hat = gaussian_field_hat(seed, n_side, box, omega_m, h, n_s, sigma8)
+    psi1, psi2 = lpt_displacements(delta_hat, n_side, box)
+    return particles_from_displacements(psi1, psi2, n_side, box, a_init, omega_m)

@@ -4,7 +4,7 @@ This module holds workload parameters and random-input recipes only. It contains
 (no cosmology, no deposit, no FFT, no integrator), so both the GPU path's tests and the CPU oracle may draw from it.
 
 Workloads (flat LCDM, BBKS spectrum with ns = 0.96, sigma8 = 0.8, Om = 0.31, h = 0.68, 2LPT ICs at z = 9, ten steps
-uniform in a from 0.1 to 1.0, modified COLA stepping with nLPT = -2.5, CIC window deconvolved twice):
+uniform in a from 0.1 to 1.0, modified COLA stepping with nLPT = -2.5, CIC window deconvolved once in the force):
   small  : 32^3 particles, 64^3 mesh, 256 Mpc/h box    (the size the oracle finishes in seconds)
   single : 256^3 particles, 768^3 mesh, 1000 Mpc/h box
   large  : 512^3 particles, 1024^3 mesh, 2000 Mpc/h box

@@ -100,3 +100,58 @@ def test_initial_conditions_layout():
     q = ic.lattice_positions(8, 64.0)
     assert np.array_equal(q[:, 1], [4.0, 4.0, 12.0]) and np.array_equal(q[:, 8], [4.0, 12.0, 4.0])
     assert np.all((out["pos"] >= 0) & (out["pos"] <= 64.0))
+
+
+def _two_wave_fields(n, box, A, B):
+    """Psi1, Psi2 of the two-wave potential phi1 = A cos(kx x) + B cos(ky y), from lpt_displacements (pinned above
+    by its closed form), on the cell-centred lattice the particles start from."""
+    kx, ky = 2 * np.pi * 2 / box, 2 * np.pi * 3 / box
+    x = (np.arange(n) + 0.5) * (box / n)
+    X, Y, _ = np.meshgrid(x, x, x, indexing="ij")
+    delta = -A * kx**2 * np.cos(kx * X) - B * ky**2 * np.cos(ky * Y)
+    return ic.lpt_displacements(np.fft.rfftn(delta), n, box)
+
+
+@pytest.mark.parametrize("a0", [0.1, 0.37])
+def test_ic_assembly_einstein_de_sitter_closed_form(a0):
+    """Omega_m = 1: D1 = a, D2 = -3/7 a^2, E = a^-3/2, so x = q + a Psi1 - (3/7) a^2 Psi2 and
+    p = a^3 E (D1' Psi1 + D2' Psi2) = a^(3/2) Psi1 - (6/7) a^(5/2) Psi2, element by element."""
+    n, box = 16, 100.0
+    psi1, psi2 = _two_wave_fields(n, box, 3.0, -2.0)
+    out = ic.particles_from_displacements(psi1, psi2, n, box, a0, 1.0)
+    p1, p2 = psi1.reshape(3, -1), psi2.reshape(3, -1)
+    assert np.abs(p2).max() > 1e-3  # the second-order field is not trivially zero
+    q = ic.lattice_positions(n, box)
+    x_ref = np.mod(q + a0 * p1 - 3.0 / 7.0 * a0**2 * p2, box)
+    d = out["pos"] - x_ref
+    d -= box * np.round(d / box)
+    assert np.abs(d).max() < 1e-10
+    v_ref = a0**1.5 * p1 - 6.0 / 7.0 * a0**2.5 * p2
+    assert np.allclose(out["vel"], v_ref, rtol=0, atol=1e-10 * np.abs(v_ref).max())
+    assert np.array_equal(out["psi1"], p1) and np.array_equal(out["psi2"], p2)
+
+
+def test_ic_momentum_is_the_cola_frame_momentum():
+    """With the force that the 2LPT trajectory itself feels, g = -(D1 Psi1 + (D2 - D1^2) Psi2), the COLA residual
+    acceleration vanishes. The IC momentum minus the frame momentum the integrator removes must then be exactly zero,
+    so the run follows x(a) = q + D1(a) Psi1 + D2(a) Psi2 and ends with the frame momentum of its last time. A sign
+    slip on the D2 term, or a frame momentum at the wrong time, moves x by Q p_res and fails this."""
+    from oracle import cola as ocola
+    from oracle import cosmology as oc
+    n, box, om = 8, 64.0, 1.0
+    psi1, psi2 = _two_wave_fields(n, box, 4.0, 2.5)
+    a_list = [0.1, 0.3, 0.55, 1.0]
+    out = ic.particles_from_displacements(psi1, psi2, n, box, a_list[0], om)
+    p1, p2 = out["psi1"], out["psi2"]
+
+    def lpt_force(x, a):
+        d1, d2 = oc.growth_D1(a, om), oc.growth_D2(a, om)
+        return -(d1 * p1 + (d2 - d1 * d1) * p2)
+
+    x, p = ocola.cola_run(out["pos"], out["vel"], p1, p2, a_list, om, n, box, force_fn=lpt_force)
+    aN = a_list[-1]
+    q = ic.lattice_positions(n, box)
+    d = x - np.mod(q + aN * p1 - 3.0 / 7.0 * aN**2 * p2, box)
+    d -= box * np.round(d / box)
+    assert np.abs(d).max() < 1e-9
+    assert np.allclose(p, aN**1.5 * p1 - 6.0 / 7.0 * aN**2.5 * p2, rtol=0, atol=1e-9)
