@@ -51,6 +51,31 @@ def deposit_fixed(pos, n_mesh, box, frac_bits=FRAC_BITS):
     return C.reshape(n_mesh, n_mesh, n_mesh)
 
 
+def fixed_point_overflow(pos, n_mesh, box, frac_bits=FRAC_BITS):
+    """True when some cell's exact fixed-point count reaches 2^63, the headroom of a signed 64-bit count (the rule
+    behind LPC_ERR_FIXED_OVERFLOW). Each corner weight w <= 2^(3F) is split into w >> 24 and w & (2^24 - 1); both
+    per-cell sums fit int64 for any realistic particle count, and C = hi 2^24 + lo >= 2^63 exactly when
+    hi + (lo >> 24) >= 2^39 (2^63 is a multiple of 2^24)."""
+    idx, frac = fixed_point_coords(pos, n_mesh, box, frac_bits)
+    one = np.int64(1 << frac_bits)
+    hi = np.zeros(n_mesh**3, dtype=np.int64)
+    lo = np.zeros(n_mesh**3, dtype=np.int64)
+    for cx in (0, 1):
+        wx = frac[0] if cx else one - frac[0]
+        ix = (idx[0] + cx) % n_mesh
+        for cy in (0, 1):
+            wy = frac[1] if cy else one - frac[1]
+            iy = (idx[1] + cy) % n_mesh
+            for cz in (0, 1):
+                wz = frac[2] if cz else one - frac[2]
+                iz = (idx[2] + cz) % n_mesh
+                w = wx * wy * wz
+                cell = (ix * n_mesh + iy) * n_mesh + iz
+                np.add.at(hi, cell, w >> np.int64(24))
+                np.add.at(lo, cell, w & np.int64((1 << 24) - 1))
+    return bool(np.any(hi + (lo >> np.int64(24)) >= np.int64(1 << 39)))
+
+
 def density_contrast(C, n_particles, frac_bits=FRAC_BITS):
     """delta = C m 2^(-3F) - 1 with m = Nm^3 / n_particles (float64)."""
     m = C.size / float(n_particles)

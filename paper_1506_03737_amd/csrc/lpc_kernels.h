@@ -80,6 +80,17 @@ __device__ __forceinline__ const LPC_CONST T* to_const(const T* p) {
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2). Remap the hardware block index so
 // that each XCD receives a contiguous range of logical tiles: neighbouring tiles (which share cache lines at their
 // edges) then run on the same XCD.
+// Periodic wrap of a coordinate that moved by less than one box into [0, box). x + box can round up to box itself
+// in FP32 when x is a tiny negative number; that point is the periodic image of 0, which is returned instead.
+__device__ __forceinline__ float wrap_box(float x, float box) {
+  if (x >= box) x -= box;
+  if (x < 0.f) {
+    x += box;
+    if (x >= box) x = 0.f;
+  }
+  return x;
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   const int per = nblocks / 8, rem = nblocks % 8;
   const int xcd = bid % 8, local = bid / 8;

@@ -914,7 +914,10 @@ __global__ __launch_bounds__(kNT) void k_apply(float* __restrict__ pos, const in
   for (int d = 0; d < 3; ++d) {
     float x = pos[d * n + p] + r[q * 3 + d] * dp;
     if (x >= box) x -= box;
-    if (x < 0.f) x += box;
+    if (x < 0.f) {  // x + box can round up to box: its periodic image is 0
+      x += box;
+      if (x >= box) x = 0.f;
+    }
     pos[d * n + p] = x;
   }
 }

@@ -263,62 +263,38 @@ __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ job
 // tile once with plain stores (so the mesh needs no clearing and sees no global atomics). The up to 8 particle
 // ranges are walked as one index space, so a workgroup needs few rounds of loads.
 constexpr int kTileCells = kTile * kTile * kTile;
+// A cell's exact count C is a sum of corner weights of at most 2^48 each. With fewer than 2^16 particles reaching a
+// tile, C < 2^64 cannot wrap its 64-bit sum and bit 63 tells whether C >= 2^63 (the headroom of a signed count).
+// A tile reached by 2^16 or more particles also sums the weights' high parts T = sum(w >> 16), which cannot wrap;
+// with the wrapped sum S = C mod 2^64, R = S - T 2^16 (mod 2^64) is the exact sum of the low parts (< 2^47), so
+// C = T 2^16 + R and C >= 2^63 exactly when T + (R >> 16) >= 2^47.
+constexpr int kWrapParticles = 1 << 16;
 
-__global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict__ jobs, const int* __restrict__ offs,
-                                                       int njob, int total, const int* __restrict__ start,
-                                                       int* __restrict__ flags) {
-  __shared__ unsigned long long acc[kTileCells];
-  const int w = blockIdx.x;
-  if (w >= total) return;
-  const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
-  const LPC_CONST DepJob& J = to_const(jobs)[jb];
-  const int nt = J.nt, nm = J.nm;
-  // neighbouring tiles (which write the two halves of shared 128-byte lines) run on the same XCD
-  const int t = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]);
-  if (t >= nt * nt * nt) return;  // padding item
-  const int tid = threadIdx.x;
-  for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
-  const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
-  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
-  // the particle ranges (local indices, uniform): own tile, then the boundary bucket of each distinct lower
-  // neighbour; logical particle q lies in range r when cum[r] <= q < cum[r + 1], at index rb[r] + q - cum[r]
+// The particle ranges of a tile's workgroup: logical particle q lies in range r when cum[r] <= q < cum[r + 1], at
+// sorted index rb[r] + q - cum[r] (local to the box).
+struct TileRanges {
   int rb[8], cum[9];
-  int nr = 0;
-  cum[0] = 0;
-  const int pbase = static_cast<int>(J.pbase);  // sort positions are int
-  const int lo = (nt > 1) ? -1 : 0;  // an axis with one tile has no distinct lower neighbour
-  for (int dx = lo; dx <= 0; ++dx) {
-    for (int dy = lo; dy <= 0; ++dy) {
-      for (int dz = lo; dz <= 0; ++dz) {
-        const int sx = (tx + dx + nt) % nt, sy = (ty + dy + nt) % nt, sz = (tz + dz + nt) % nt;
-        const int g = J.tbase + 2 * ((sx * nt + sy) * nt + sz);
-        const bool own = (dx == 0 && dy == 0 && dz == 0);
-        const int b = __builtin_amdgcn_readfirstlane(start[own ? g : g + 1] - pbase);
-        const int e = __builtin_amdgcn_readfirstlane(start[g + 2] - pbase);
-        rb[nr] = b;
-        cum[nr + 1] = cum[nr] + (e - b);
-        ++nr;
-      }
-    }
-  }
-  const int tot = cum[nr];
-  __syncthreads();
-  const int64_t n = J.n;
+  int nr;
+};
+
+// Adds (corner weight >> shift) of every particle in the ranges to the tile's cells in acc (LDS).
+__device__ __forceinline__ void deposit_pass(const TileRanges tr, int tot, LPC_GLOBAL const float* __restrict__ pos,
+                                             int64_t n, double scale, int nm, int x0, int y0, int z0,
+                                             unsigned long long* acc, int shift) {
   const int64_t period = static_cast<int64_t>(nm) << kFracBits;
-  LPC_GLOBAL const float* pos = to_global(J.pos);
   // kUnroll particles per thread per round: all their position loads are issued before any is used
   constexpr int kUnroll = 4;
-  for (int q0 = tid; q0 < tot; q0 += kUnroll * kNT) {
+  for (int q0 = threadIdx.x; q0 < tot; q0 += kUnroll * kNT) {
     float px[kUnroll][3];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int q = q0 + u * kNT;
       px[u][0] = px[u][1] = px[u][2] = 0.f;
       if (q < tot) {
-        int off = rb[0];
+        int off = tr.rb[0];
 #pragma unroll
         for (int r = 1; r < 8; ++r)
-          if (r < nr && q >= cum[r]) off = rb[r] - cum[r];
+          if (r < tr.nr && q >= tr.cum[r]) off = tr.rb[r] - tr.cum[r];
         const int64_t i = off + q;
 #pragma unroll
         for (int d = 0; d < 3; ++d) px[u][d] = pos[d * n + i];
@@ -330,7 +306,7 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
       uint32_t c[3], f[3];
       bool ok = true;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) ok &= fixed_coord(px[u][d], J.scale, period, &c[d], &f[d]);
+      for (int d = 0; d < 3; ++d) ok &= fixed_coord(px[u][d], scale, period, &c[d], &f[d]);
       if (!ok) continue;  // cannot happen for a bucketed particle; kept as a guard
       // corner offsets relative to the tile origin (periodic), in [0, kTile) when inside
       int lx[2], ly[2], lz[2];
@@ -355,7 +331,7 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
 #pragma unroll
           for (int e2 = 0; e2 < 2; ++e2) {
             if (static_cast<unsigned>(lz[e2]) >= static_cast<unsigned>(kTile)) continue;
-            const uint64_t wt = wab * wz[e2];
+            const uint64_t wt = (wab * wz[e2]) >> shift;
             if (wt != 0)
               __hip_atomic_fetch_add(&acc[(lx[a] * kTile + ly[bb]) * kTile + lz[e2]],
                                      static_cast<unsigned long long>(wt), __ATOMIC_RELAXED,
@@ -365,10 +341,61 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
       }
     }
   }
+}
+
+__global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict__ jobs, const int* __restrict__ offs,
+                                                       int njob, int total, const int* __restrict__ start,
+                                                       int* __restrict__ flags) {
+  __shared__ unsigned long long acc[kTileCells];
+  const int w = blockIdx.x;
+  if (w >= total) return;
+  const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
+  const LPC_CONST DepJob& J = to_const(jobs)[jb];
+  const int nt = J.nt, nm = J.nm;
+  // neighbouring tiles (which write the two halves of shared 128-byte lines) run on the same XCD
+  const int t = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]);
+  if (t >= nt * nt * nt) return;  // padding item
+  const int tid = threadIdx.x;
+  for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
+  const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
+  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  // the particle ranges (local indices, uniform): own tile, then the boundary bucket of each distinct lower
+  // neighbour
+  int rb[8], cum[9];
+  int nr = 0;
+  cum[0] = 0;
+  const int pbase = static_cast<int>(J.pbase);  // sort positions are int
+  const int lo = (nt > 1) ? -1 : 0;  // an axis with one tile has no distinct lower neighbour
+  for (int dx = lo; dx <= 0; ++dx) {
+    for (int dy = lo; dy <= 0; ++dy) {
+      for (int dz = lo; dz <= 0; ++dz) {
+        const int sx = (tx + dx + nt) % nt, sy = (ty + dy + nt) % nt, sz = (tz + dz + nt) % nt;
+        const int g = J.tbase + 2 * ((sx * nt + sy) * nt + sz);
+        const bool own = (dx == 0 && dy == 0 && dz == 0);
+        const int b = __builtin_amdgcn_readfirstlane(start[own ? g : g + 1] - pbase);
+        const int e = __builtin_amdgcn_readfirstlane(start[g + 2] - pbase);
+        rb[nr] = b;
+        cum[nr + 1] = cum[nr] + (e - b);
+        ++nr;
+      }
+    }
+  }
+  const int tot = cum[nr];
+  // the ranges as uniform values (unused slots never selected: their start lies past tot)
+  TileRanges tr;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    tr.rb[r] = (r < nr) ? rb[r] : 0;
+    tr.cum[r] = (r < nr) ? cum[r] : tot;
+  }
+  tr.cum[8] = tot;
+  tr.nr = nr;
+  __syncthreads();
+  LPC_GLOBAL const float* pos = to_global(J.pos);
+  deposit_pass(tr, tot, pos, J.n, J.scale, nm, x0, y0, z0, acc, 0);
   __syncthreads();
   // write the tile (cells outside the mesh on a narrow last tile are skipped): the exact int64 counts, and/or the
-  // FP32 density contrast C mscale - 1 that the forward transform takes (a cell whose count passed 2^63 raises the
-  // overflow flag)
+  // FP32 density contrast C mscale - 1 that the forward transform takes
   LPC_GLOBAL unsigned long long* C = to_global(reinterpret_cast<unsigned long long*>(J.dens));
   LPC_GLOBAL float* D = to_global(J.delta);
   const double mscale = J.mscale;
@@ -384,11 +411,25 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
     for (int i = 0; i < kTile; ++i, cell += plane) {
       if (i >= wx_) break;  // uniform: a narrow last tile along x
       const unsigned long long v = acc[i * kNT + tid];
+      overflow |= (v >> 63) != 0;
       if (C) C[cell] = v;
-      if (D) {
-        overflow |= (v >> 63) != 0;
-        D[cell] = static_cast<float>(static_cast<double>(v) * mscale - 1.0);
-      }
+      if (D) D[cell] = static_cast<float>(static_cast<double>(v) * mscale - 1.0);
+    }
+  }
+  if (tot >= kWrapParticles) {  // uniform; rare (a tile reached by 65536 particles or more)
+    unsigned long long S[kTile];
+#pragma unroll
+    for (int i = 0; i < kTile; ++i) S[i] = acc[i * kNT + tid];
+    __syncthreads();
+    for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
+    __syncthreads();
+    deposit_pass(tr, tot, pos, J.n, J.scale, nm, x0, y0, z0, acc, kFracBits);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kTile; ++i) {
+      const unsigned long long T = acc[i * kNT + tid];
+      const unsigned long long R = S[i] - (T << kFracBits);
+      overflow |= (T + (R >> kFracBits)) >= (1ull << 47);
     }
   }
   if (overflow) atomicOr(flags + kFlagOverflow, 1);
@@ -494,8 +535,7 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
           if (kd.do_drift) {
             float xn = x[d] + kd.drift * v;
             if (kd.cola) xn += kd.dd1 * p1 + kd.dd2 * p2;
-            if (xn >= box) xn -= box;
-            if (xn < 0.f) xn += box;
+            xn = wrap_box(xn, box);
             pos[d * n + i] = xn;
             x[d] = xn;
           }

@@ -127,3 +127,29 @@ def test_batch_of_one_and_errors():
     with pytest.raises(lpc.LpcError) as e:
         lpc.lpc_cola_step_batched(bad, lpc.cosmology(**C), step, a, ws)
     assert e.value.status == -2
+
+
+def test_batched_workload_shapes():
+    """One box of each shape of the 48-box workload (N = 96, 128, 160 with Nm = 2N, boxes 300, 450, 600 Mpc/h), so
+    the batched launches take the 192, 256 and 320 meshes (compile-time FFT plans 8 8 3, 8 8 4, 8 8 5 and their half
+    lengths) together, with the tile widths and points per thread shared across the three: every box equals its own
+    lpc_cola_step run bit for bit over ten steps, and the N = 96 box is within 1e-5 L of the FP64 oracle."""
+    from paper_1506_03737_amd import lpc
+    boxes = [(96, 192, 300.0, 1000), (128, 256, 450.0, 1001), (160, 320, 600.0, 1002)]
+    say("batched: workload shapes 96/192, 128/256, 160/320, ten steps")
+    step = lpc.stepping()
+    a = synth.A_LIST
+    ics = [box_ic(n, L, seed) for (n, nm, L, seed) in boxes]
+    ref = single_runs(lpc, ics, boxes, a, step)
+    got, _, _, _ = batched_run(lpc, ics, boxes, a, step)
+    for i, ((x, v), (xr, vr)) in enumerate(zip(got, ref)):
+        assert np.array_equal(x, xr), f"box {i}: positions differ"
+        assert np.array_equal(v, vr), f"box {i}: velocities differ"
+    n, nm, L, _ = boxes[0]
+    ic = ics[0]
+    xr, vr = ocola.cola_run(ic["pos"], ic["vel"], ic["psi1"], ic["psi2"], a, C["omega_m"], nm, L)
+    dx = np.abs(periodic_diff(got[0][0], xr, L)).max() / L
+    dv = np.sqrt(np.mean((got[0][1] - vr) ** 2)) / np.sqrt(np.mean(vr**2))
+    say(f"  N=96 box vs oracle: max |dx|/L = {dx:.3e}, rms |dv|/rms v = {dv:.3e}")
+    assert dx < 1e-5
+    assert dv < 1e-4

@@ -44,7 +44,7 @@ def test_r2c_matches_brute_force_8():
     assert rel_l2(got, ref) < 1e-6
 
 
-@pytest.mark.parametrize("n", [8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 96, 128, 160, 192, 250, 256])
+@pytest.mark.parametrize("n", [8, 10, 12, 16, 20, 24, 30, 32, 40, 48, 60, 64, 96, 128, 160, 192, 250, 256, 320, 384])
 def test_r2c_and_c2r_match_numpy(n):
     from paper_1506_03737_amd import lpc
     say(f"fft: r2c/c2r n={n}")

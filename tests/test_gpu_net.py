@@ -1,10 +1,12 @@
 """GPU parity of the learned correction (lpc_net_*) against the FP64 oracle in oracle/net.py.
 
-Bars (derived from the precision stated in include/lpc.h): activations, their gradients and the MFMA operands are
-BF16 (relative rounding 2^-9 ~ 2e-3 per value). Eleven layers each round their weights and outputs once, so the
-network output carries ~ sqrt(22) x 2e-3 ~ 1e-2 relative error: the bar is 3e-2 (relative L2 over the grid). The
-parameter gradient passes through the same roundings twice (forward activations, BF16 gradients): bar 6e-2
-relative L2 over the whole vector and 1.5e-1 for each layer's block. Adam is FP32 element-wise: 1e-5 relative.
+Precision (include/lpc.h): activations, their gradients and the MFMA operands are BF16 (relative rounding 2^-9 ~ 2e-3
+per value). Eleven layers each round their weights and outputs once, so the network output carries ~ sqrt(22) x 2e-3
+~ 1e-2 relative error at most; measured: 5.7e-3. The parameter gradient passes through the same roundings twice.
+The bars sit at about three times the measured errors, per grid size and per layer block (FWD_*, GRAD_*). Every
+output value and every weight and bias gradient is held element by element as well as in norm: max |GPU - oracle|
+against the largest reference value of its block, so an error confined to one face's wrap, one tile edge or one
+layer's bias cannot hide in a norm over the whole grid. Adam is FP32 element-wise: 1e-5 relative.
 """
 import numpy as np
 import pytest
@@ -13,6 +15,41 @@ from oracle import net as onet
 from tests.gpu_util import rel_l2, requires_gpu, say, to_dev, to_np, torch
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
+
+# Bars at about three times the errors measured on these inputs (the GPU results are bitwise repeatable and the
+# oracle is deterministic). Forward: rel L2 5.7e-3, max 5.8e-3 to 6.7e-3 of max at D = 8..64.
+FWD_L2, FWD_MAX = 1.8e-2, 2.1e-2
+# Gradient over the whole vector (measured 7.1e-3, 3.0e-3, 2.5e-3, 2.5e-3) and the loss (1.8e-3 relative).
+GRAD_L2 = {8: 2.2e-2, 16: 9.1e-3, 32: 7.6e-3, 64: 7.4e-3}
+LOSS_REL = 5e-3
+# Per layer block: (W rel L2, W max of max, b rel L2, b max of max). The errors fall with D: the weight gradients sum
+# BF16 products over more voxels, and the bottleneck layers (at D / 4 per side) sum over the fewest.
+GRAD_BARS = {
+    8: {"e0a": (0.15, 0.075, 0.026, 0.018), "e0b": (0.027, 0.052, 0.017, 0.015), "d1": (0.11, 0.11, 0.073, 0.085),
+        "e1": (0.096, 0.12, 0.067, 0.073), "d2": (0.37, 0.65, 0.31, 0.4),
+        # not measured at D = 8 yet: 2.5 x the D = 16 bars
+        "b2": (0.3, 0.35, 0.22, 0.2), "u1": (0.22, 0.33, 0.085, 0.063), "c1": (0.073, 0.063, 0.06, 0.045),
+        "u0": (0.05, 0.04, 0.033, 0.03), "c0": (0.023, 0.033, 0.018, 0.018), "out": (0.017, 0.025, 0.01, 0.014)},
+    16: {"e0a": (0.065, 0.045, 0.0095, 0.0056), "e0b": (0.0092, 0.016, 0.0073, 0.0088), "d1": (0.056, 0.044, 0.031, 0.025),
+         "e1": (0.048, 0.061, 0.035, 0.031), "d2": (0.16, 0.17, 0.12, 0.091), "b2": (0.12, 0.14, 0.089, 0.079),
+         "u1": (0.089, 0.13, 0.034, 0.025), "c1": (0.029, 0.025, 0.024, 0.018), "u0": (0.02, 0.016, 0.013, 0.012),
+         "c0": (0.009, 0.013, 0.007, 0.0072), "out": (0.0066, 0.0099, 0.004, 0.0055)},
+    32: {"e0a": (0.026, 0.025, 0.009, 0.006), "e0b": (0.0068, 0.0089, 0.0065, 0.0075), "d1": (0.021, 0.021, 0.015, 0.015),
+         "e1": (0.02, 0.025, 0.017, 0.021), "d2": (0.065, 0.063, 0.047, 0.039), "b2": (0.04, 0.033, 0.031, 0.029),
+         "u1": (0.034, 0.021, 0.015, 0.0097), "c1": (0.015, 0.013, 0.014, 0.011), "u0": (0.013, 0.012, 0.012, 0.011),
+         "c0": (0.0084, 0.011, 0.007, 0.0075), "out": (0.0066, 0.011, 0.004, 0.0055)},
+    64: {"e0a": (0.012, 0.018, 0.008, 0.0054), "e0b": (0.0065, 0.0088, 0.0065, 0.0079), "d1": (0.018, 0.017, 0.016, 0.014),
+         "e1": (0.017, 0.022, 0.016, 0.02), "d2": (0.031, 0.028, 0.027, 0.025), "b2": (0.022, 0.022, 0.02, 0.021),
+         "u1": (0.02, 0.015, 0.017, 0.012), "c1": (0.014, 0.012, 0.014, 0.012), "u0": (0.012, 0.0095, 0.012, 0.011),
+         "c0": (0.0083, 0.011, 0.0069, 0.0076), "out": (0.0066, 0.011, 0.004, 0.0056)},
+}
+
+
+def max_rel(a, b):
+    """max |a - b| over the block, relative to max |b|."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 def grid_to_cf(a, D):
@@ -33,7 +70,7 @@ def sample(D, seed):
     return feat, target
 
 
-@pytest.mark.parametrize("D", [8, 16])
+@pytest.mark.parametrize("D", [8, 16, 32, 64])
 def test_forward_matches_oracle(D):
     from paper_1506_03737_amd import lpc
     say(f"net: forward D={D}")
@@ -44,9 +81,12 @@ def test_forward_matches_oracle(D):
     out = torch.empty((D**3, 3), dtype=torch.float32, device="cuda")
     lpc.lpc_net_forward(D, to_dev(params), to_dev(cf_to_grid(feat)), out, ws)  # feat: 6 channels
     ref, _ = onet.forward(params.astype(np.float64), feat.astype(np.float64))
-    err = rel_l2(grid_to_cf(to_np(out), D), ref)
-    say(f"  rel L2 = {err:.3e}")
-    assert err < 3e-2
+    got = grid_to_cf(to_np(out), D)
+    err = rel_l2(got, ref)
+    emax = max_rel(got, ref)
+    say(f"  rel L2 = {err:.3e}, max = {emax:.3e} of max")
+    assert err < FWD_L2
+    assert emax < FWD_MAX
 
 
 # D = 8, 16: every weight gradient on the vector-ALU kernels; D = 32, 64: the 3^3 layers on grids of 32 and 64 per
@@ -66,13 +106,16 @@ def test_gradient_matches_oracle(D):
     L, g = onet.loss_and_grad(params.astype(np.float64), feat.astype(np.float64), target.astype(np.float64))
     gg = to_np(grad).astype(np.float64)
     say(f"  loss {loss:.6e} vs {L:.6e}; grad rel L2 {rel_l2(gg, g):.3e}")
-    assert abs(loss - L) < 3e-2 * L
-    assert rel_l2(gg, g) < 6e-2
+    errs = {}
     for name, (ws_, bs, kind, cin, cout) in onet.layer_slices().items():
-        e = rel_l2(gg[ws_], g[ws_])
-        eb = rel_l2(gg[bs], g[bs])
-        say(f"  {name:4s} W {e:.3e} b {eb:.3e}")
-        assert e < 1.5e-1 and eb < 1.5e-1, name
+        errs[name] = (rel_l2(gg[ws_], g[ws_]), max_rel(gg[ws_], g[ws_]), rel_l2(gg[bs], g[bs]), max_rel(gg[bs], g[bs]))
+        say(f"  {name:4s} W {errs[name][0]:.3e} (max {errs[name][1]:.3e}) b {errs[name][2]:.3e} "
+            f"(max {errs[name][3]:.3e})")
+    assert abs(loss - L) < LOSS_REL * L
+    assert rel_l2(gg, g) < GRAD_L2[D]
+    for name, e in errs.items():
+        bar = GRAD_BARS[D][name]
+        assert all(v < b for v, b in zip(e, bar)), (name, e, bar)
     # deterministic: a second call gives the same bits
     grad2 = torch.empty_like(grad)
     loss2 = lpc.lpc_net_loss_grad(D, pd, to_dev(cf_to_grid(feat)), to_dev(cf_to_grid(target)), grad2, ws)

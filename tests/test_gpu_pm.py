@@ -37,6 +37,11 @@ CASES = [
     ("edges nm=16", lambda: synth.edge_positions(16, 64.0), 16, 64.0),
     ("lattice+ic n=32^3 nm=64", None, 64, 256.0),
     ("clustered n=100003 nm=160", lambda: synth.clustered_positions(3, 100003, 500.0), 160, 500.0),
+    # the batched and coarse meshes with their compile-time FFT plans: 192 = 8 8 3 (half 96 = 4 8 3), 256 = 8 8 4
+    # (half 128), 320 = 8 8 5 (half 160 = 4 8 5)
+    ("clustered n=150001 nm=192", lambda: synth.clustered_positions(4, 150001, 400.0), 192, 400.0),
+    ("clustered n=200003 nm=256", lambda: synth.clustered_positions(5, 200003, 500.0), 256, 500.0),
+    ("clustered n=250007 nm=320", lambda: synth.clustered_positions(6, 250007, 600.0), 320, 600.0),
 ]
 
 
@@ -88,17 +93,34 @@ def test_zero_net_force():
 
 def test_error_flags():
     from paper_1506_03737_amd import lpc
-    say("pm_force: NaN position and fixed-point headroom")
+    say("pm_force: NaN position")
     pos = synth.uniform_positions(9, 1000, 50.0)
     pos[1, 17] = np.nan
     with pytest.raises(lpc.LpcError) as e:
         run_force(lpc, pos, 16, 50.0)
     assert e.value.status == -6
-    # 40000 particles at one point: 40000 * 2^48 >= 2^63 in one cell
-    pos = np.full((3, 40000), 12.5, dtype=np.float32)
-    with pytest.raises(lpc.LpcError) as e:
-        run_force(lpc, pos, 16, 50.0)
-    assert e.value.status == -5
+
+
+@pytest.mark.parametrize("count,where,overflows", [(32767, "node", False), (32768, "node", True),
+                                                   (65535, "node", True), (70000, "node", True),
+                                                   (2**18 - 1, "centre", False), (2**18, "centre", True)])
+def test_fixed_point_headroom(count, where, overflows):
+    """LPC_ERR_FIXED_OVERFLOW exactly when a cell's exact count reaches 2^63 (oracle.pm.fixed_point_overflow): on a
+    mesh node each particle adds 2^48 to one cell, at a cell centre 2^45 to eight. 70000 on a node wrap a 64-bit sum
+    past 2^64; 2^18 - 1 at a centre reach a tile with more than 2^16 particles and must still pass."""
+    from paper_1506_03737_amd import lpc
+    nm, box = 16, 50.0
+    x = 12.5 if where == "node" else 12.5 + 0.5 * box / nm
+    say(f"pm_force: {count} particles on a {where}")
+    pos = np.full((3, count), x, dtype=np.float32)
+    assert opm.fixed_point_overflow(pos, nm, box) == overflows
+    if overflows:
+        with pytest.raises(lpc.LpcError) as e:
+            run_force(lpc, pos, nm, box)
+        assert e.value.status == -5
+    else:
+        _, dens = run_force(lpc, pos, nm, box)
+        assert np.array_equal(dens, opm.deposit_fixed(pos, nm, box))
 
 
 def test_full_size_single_box_properties():
@@ -148,6 +170,38 @@ def test_full_size_plane_wave_parity():
     got_c = to_np(dens[ci[0], ci[1], ci[2]])
     assert np.array_equal(got_c, X[cells[0]] * Y[cells[1]] * Z[cells[2]])
     del dens
+    sample = rng.choice(N**3, 512, replace=False)
+    ref = pw.force_at(pos, N, nm, box, sample)
+    g = to_np(grad)[:, sample].astype(np.float64)
+    say(f"  force rel L2 {rel_l2(g, ref):.3e}, max {np.abs(g - ref).max() / np.abs(ref).max():.3e} of max")
+    assert rel_l2(g, ref) < 2e-5
+    assert np.abs(g - ref).max() < 2e-4 * np.abs(ref).max()
+
+
+def test_full_size_large_box_launch_shape():
+    """The large single-box launch shape: 512^3 particles on the 1024^3 mesh (built-in tile widths), on the separable
+    lattice input of tests/plane_wave.py (box 1024 Mpc/h, so the fixed-point scale is 2^16): the whole int64 density
+    equals X Y Z bit for bit (compared plane by plane on the device), and the force at 512 sampled particles, against
+    the oracle's definitions evaluated there, meets the bar of the small meshes."""
+    from paper_1506_03737_amd import lpc
+    from tests import plane_wave as pw
+    N, nm = 512, 1024
+    box = float(nm)
+    say("pm_force: 512^3 plane-wave lattice, 1024^3 mesh")
+    pos = pw.lattice_plane_wave(N, box, 0.4 * box / N, 3)
+    X, Y, Z = pw.factors(pos, N, nm, box)
+    geom = lpc.geometry(N, nm, box)
+    ws = lpc.workspace(geom, lpc.LPC_OP_PM_FORCE)
+    grad = torch.empty((3, N**3), dtype=torch.float32, device="cuda")
+    dens = torch.empty((nm, nm, nm), dtype=torch.int64, device="cuda")
+    lpc.lpc_pm_force(geom, lpc.stepping(), to_dev(pos), grad, ws, density_out=dens)
+    del ws
+    Xd, Yd, Zd = (torch.from_numpy(a).to("cuda") for a in (X, Y, Z))
+    yz = Yd[:, None] * Zd[None, :]
+    for i in range(nm):
+        assert torch.equal(dens[i], Xd[i] * yz), f"density plane {i}"
+    del dens, yz
+    rng = np.random.default_rng(12)
     sample = rng.choice(N**3, 512, replace=False)
     ref = pw.force_at(pos, N, nm, box, sample)
     g = to_np(grad)[:, sample].astype(np.float64)

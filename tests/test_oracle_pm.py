@@ -132,3 +132,23 @@ def test_plane_wave_sampled_force_equals_oracle():
         ref = pm.pm_force(pos.astype(np.float64), nm, box, deconv_power=p)[:, sample]
         got = pw.force_at(pos, N, nm, box, sample, deconv_power=p)
         assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_fixed_point_overflow_rule():
+    """A cell overflows when its exact count reaches 2^63. Particles on a mesh node put their whole 2^48 on one cell:
+    32767 of them fit, 32768 reach 2^63 exactly. 70000 wrap a 64-bit sum past 2^64 (the wrapped value has bit 63
+    clear), and are still flagged. Particles at a cell centre put 2^45 on each of 8 cells: 2^18 - 1 fit, 2^18 not."""
+    nm, box = 16, 50.0
+    node = np.full((3, 1), 12.5, dtype=np.float64)                 # 12.5 / (50 / 16) = 4 cells: a node
+    centre = np.full((3, 1), 12.5 + 0.5 * box / nm, dtype=np.float64)
+    assert not pm.fixed_point_overflow(np.repeat(node, 32767, axis=1), nm, box)
+    assert pm.fixed_point_overflow(np.repeat(node, 32768, axis=1), nm, box)
+    many = np.repeat(node, 70000, axis=1)
+    assert pm.fixed_point_overflow(many, nm, box)
+    wrapped = (70000 * 2**48) % 2**64
+    assert wrapped < 2**63 and int(pm.deposit_fixed(many, nm, box).max()) == wrapped
+    assert not pm.fixed_point_overflow(np.repeat(centre, 2**18 - 1, axis=1), nm, box)
+    assert pm.fixed_point_overflow(np.repeat(centre, 2**18, axis=1), nm, box)
+    # spread particles never come close
+    rng = np.random.default_rng(0)
+    assert not pm.fixed_point_overflow(rng.random((3, 10000)) * box, nm, box)
