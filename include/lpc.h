@@ -122,6 +122,22 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
 lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, const float* pos, int64_t n,
                         float* grad_out, int64_t* density_fixed_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Bytes of the static device scratch behind lpc_pm_force_noalloc (64 MiB per GPU, held from the library's load until
+ * the process ends). */
+#define LPC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* lpc_pm_force without a workspace argument and without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, serving loops that must not call hipMalloc, harnesses that forbid it. The workspace
+ * is a static device array of LPC_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, looked up for the current
+ * device (the stream must belong to it). Arguments, outputs and results are those of lpc_pm_force (same kernels, the
+ * same bits). A geometry and count whose lpc_workspace_bytes(geom, LPC_OP_PM_FORCE, n) exceeds the scratch (for
+ * example a 128^3 mesh with more than about 400k particles, or a 96^3 mesh with more than about 1.8M) is rejected with
+ * LPC_ERR_WORKSPACE before anything is enqueued. Every call on one GPU shares that GPU's scratch: calls that overlap
+ * on one GPU (two streams, two threads) race and must be serialised by the caller. The scratch keeps the last
+ * call's contents; everything a call needs cleared it clears itself. */
+lpc_status lpc_pm_force_noalloc(const lpc_geometry* geom, const lpc_stepping* step, const float* pos, int64_t n,
+                                float* grad_out, int64_t* density_fixed_out, void* stream);
+
 /* Advance particles from a_list[0] to a_list[n_a - 1] with the kick-drift-kick COLA integrator (Sec. 2.3):
  * frame momentum removed at a_0 (Sec. 2.3), then for i = 0..n_a-1: force at a_i, kick a_{i-1/2} -> a_{i+1/2}
  * (midpoints; a_{-1/2} = a_0, a_{N+1/2} = a_N), drift a_i -> a_{i+1} for i < n_a - 1; frame momentum added back at

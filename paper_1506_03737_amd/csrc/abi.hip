@@ -872,6 +872,66 @@ lpc_status check_stepping(const lpc_stepping* step) {
   return LPC_OK;
 }
 
+// Argument checks of lpc_pm_force and lpc_pm_force_noalloc (nothing is enqueued when they fail).
+lpc_status check_pm_force_args(const lpc_geometry* geom, const lpc_stepping* step, const float* pos, int64_t n,
+                               const float* grad_out) {
+  if (lpc_status st = check_geom_mesh(geom)) return st;
+  if (!step) return fail(LPC_ERR_INVALID_ARG, "stepping is NULL");
+  if (step->deconv_power < 0 || step->deconv_power > 2) return fail(LPC_ERR_INVALID_ARG, "deconv_power not in 0..2");
+  if (n <= 0 || n > (int64_t(1) << 31) - 1) return fail(LPC_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
+  if (!pos || !grad_out) return fail(LPC_ERR_INVALID_ARG, "pos/grad_out is NULL");
+  return LPC_OK;
+}
+
+// The PM force of one box on workspace ws (arguments already checked).
+lpc_status pm_force_impl(const lpc_geometry* geom, const lpc_stepping* step, const float* pos, int64_t n,
+                         float* grad_out, int64_t* density_fixed_out, void* ws, size_t ws_bytes, void* stream) {
+  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_PM_FORCE, n);
+  if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() {
+    int* flags = reinterpret_cast<int*>(ws);
+    stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
+    JobPack jp(at(ws, p.jobs));
+    const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, n, const_cast<float*>(pos), nullptr, nullptr, nullptr,
+                                 grad_out, reinterpret_cast<uint64_t*>(density_fixed_out));
+    const ForceProgram f = add_force(jp, {b}, sort_space(ws, p, geom->n_mesh, LPC_OP_PM_FORCE, n), step->deconv_power,
+                                     false);
+    jp.upload(s);
+    run_sort(jp, f.ss, f.sort_user, flags, s);
+    run_force_mesh(jp, f, 0, flags, s);
+    stage("gather", s, [&] { return kern::launch_gather(jp.jobs<kern::PartJob>(f.parts[0]), jp.table(f.parts[0]), flags, s); });
+    return finish(flags, s);
+  });
+}
+
+// Static scratch of lpc_pm_force_noalloc: device memory that the library never allocates at run time. Each GPU
+// holds its own copy from the library's load until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (the array's name in host code is not a device address).
+constexpr size_t kScratchBytes = LPC_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch, looked up once per device.
+lpc_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(LPC_ERR_HIP, "lpc_pm_force_noalloc: no current HIP device (or device index >= %d)", kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LPC_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LPC_OK;
+}
+
 // Cached hipGraph of one batched run: replayed while the call's arguments stay the same.
 struct GraphCache {
   std::vector<char> key;
@@ -1006,28 +1066,22 @@ lpc_status lpc_linear_power(const lpc_cosmology* cosmo, const double* k, int32_t
 
 lpc_status lpc_pm_force(const lpc_geometry* geom, const lpc_stepping* step, const float* pos, int64_t n,
                         float* grad_out, int64_t* density_fixed_out, void* ws, size_t ws_bytes, void* stream) {
-  if (lpc_status st = check_geom_mesh(geom)) return st;
-  if (!step) return fail(LPC_ERR_INVALID_ARG, "stepping is NULL");
-  if (step->deconv_power < 0 || step->deconv_power > 2) return fail(LPC_ERR_INVALID_ARG, "deconv_power not in 0..2");
-  if (n <= 0 || n > (int64_t(1) << 31) - 1) return fail(LPC_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
-  if (!pos || !grad_out) return fail(LPC_ERR_INVALID_ARG, "pos/grad_out is NULL");
-  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_PM_FORCE, n);
-  if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  return guarded([&]() {
-    int* flags = reinterpret_cast<int*>(ws);
-    stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
-    JobPack jp(at(ws, p.jobs));
-    const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, n, const_cast<float*>(pos), nullptr, nullptr, nullptr,
-                                 grad_out, reinterpret_cast<uint64_t*>(density_fixed_out));
-    const ForceProgram f = add_force(jp, {b}, sort_space(ws, p, geom->n_mesh, LPC_OP_PM_FORCE, n), step->deconv_power,
-                                     false);
-    jp.upload(s);
-    run_sort(jp, f.ss, f.sort_user, flags, s);
-    run_force_mesh(jp, f, 0, flags, s);
-    stage("gather", s, [&] { return kern::launch_gather(jp.jobs<kern::PartJob>(f.parts[0]), jp.table(f.parts[0]), flags, s); });
-    return finish(flags, s);
-  });
+  if (lpc_status st = check_pm_force_args(geom, step, pos, n, grad_out)) return st;
+  return pm_force_impl(geom, step, pos, n, grad_out, density_fixed_out, ws, ws_bytes, stream);
+}
+
+lpc_status lpc_pm_force_noalloc(const lpc_geometry* geom, const lpc_stepping* step, const float* pos, int64_t n,
+                                float* grad_out, int64_t* density_fixed_out, void* stream) {
+  if (lpc_status st = check_pm_force_args(geom, step, pos, n, grad_out)) return st;
+  const size_t need = make_ws_plan(geom->n_mesh, LPC_OP_PM_FORCE, n).total;
+  if (need > kScratchBytes)
+    return fail(LPC_ERR_WORKSPACE,
+                "lpc_pm_force_noalloc: a %d^3 mesh with %lld particles needs %zu bytes of scratch; the static scratch "
+                "holds %zu (LPC_NOALLOC_SCRATCH_BYTES)",
+                geom->n_mesh, static_cast<long long>(n), need, kScratchBytes);
+  void* ws = nullptr;
+  if (lpc_status st = scratch_of_current_device(&ws)) return st;
+  return pm_force_impl(geom, step, pos, n, grad_out, density_fixed_out, ws, kScratchBytes, stream);
 }
 
 lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, const lpc_stepping* step,

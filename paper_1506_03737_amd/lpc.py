@@ -71,6 +71,7 @@ def _load():
         "lpc_workspace_bytes": (sz, [P(Geometry), i32, i64]),
         "lpc_init_ic": (i32, [P(Geometry), P(Cosmology), ctypes.c_uint64, dbl, P(Particles), vp, sz, vp]),
         "lpc_pm_force": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp, sz, vp]),
+        "lpc_pm_force_noalloc": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp]),
         "lpc_cola_step": (i32, [P(Geometry), P(Cosmology), P(Stepping), P(dbl), i32, P(Particles), vp, sz, vp]),
         "lpc_workspace_bytes_batched": (sz, [P(BatchEntry), i32]),
         "lpc_cola_step_batched": (i32, [P(BatchEntry), i32, P(Cosmology), P(Stepping), P(dbl), i32, vp, sz, vp]),
@@ -108,7 +109,8 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_cola_step", "lpc_workspace_bytes_batched",
+EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_pm_force_noalloc", "lpc_cola_step",
+            "lpc_workspace_bytes_batched",
             "lpc_cola_step_batched", "lpc_graph_enable", "lpc_power_spectrum",
             "lpc_net_param_count", "lpc_net_init", "lpc_net_workspace_bytes", "lpc_net_features", "lpc_net_forward",
             "lpc_net_loss_grad", "lpc_net_adam", "lpc_net_apply",
@@ -193,6 +195,15 @@ def lpc_init_ic(geom, cosmo, seed, a_init, particles, ws, stream=None):
 def lpc_pm_force(geom, step, pos, grad_out, ws, density_out=None, stream=None):
     _check(LIB.lpc_pm_force(ctypes.byref(geom), ctypes.byref(step), _ptr(pos), int(pos.shape[1]), _ptr(grad_out),
                             _ptr(density_out), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # LPC_NOALLOC_SCRATCH_BYTES
+
+
+def lpc_pm_force_noalloc(geom, step, pos, grad_out, density_out=None, stream=None):
+    """lpc_pm_force on the library's static per-GPU scratch (no workspace argument, no allocation)."""
+    _check(LIB.lpc_pm_force_noalloc(ctypes.byref(geom), ctypes.byref(step), _ptr(pos), int(pos.shape[1]),
+                                    _ptr(grad_out), _ptr(density_out), _stream(stream)))
 
 
 def lpc_cola_step(geom, cosmo, step, a_list, particles, ws, stream=None):
