@@ -26,10 +26,9 @@ LOSS_REL = 5e-3
 # BF16 products over more voxels, and the bottleneck layers (at D / 4 per side) sum over the fewest.
 GRAD_BARS = {
     8: {"e0a": (0.15, 0.075, 0.026, 0.018), "e0b": (0.027, 0.052, 0.017, 0.015), "d1": (0.11, 0.11, 0.073, 0.085),
-        "e1": (0.096, 0.12, 0.067, 0.073), "d2": (0.37, 0.65, 0.31, 0.4),
-        # not measured at D = 8 yet: 2.5 x the D = 16 bars
-        "b2": (0.3, 0.35, 0.22, 0.2), "u1": (0.22, 0.33, 0.085, 0.063), "c1": (0.073, 0.063, 0.06, 0.045),
-        "u0": (0.05, 0.04, 0.033, 0.03), "c0": (0.023, 0.033, 0.018, 0.018), "out": (0.017, 0.025, 0.01, 0.014)},
+        "e1": (0.096, 0.12, 0.067, 0.073), "d2": (0.37, 0.65, 0.31, 0.4), "b2": (0.22, 0.42, 0.19, 0.33),
+        "u1": (0.19, 0.4, 0.064, 0.044), "c1": (0.071, 0.055, 0.054, 0.046), "u0": (0.071, 0.11, 0.026, 0.03),
+        "c0": (0.019, 0.041, 0.013, 0.018), "out": (0.0067, 0.011, 0.0043, 0.0058)},
     16: {"e0a": (0.065, 0.045, 0.0095, 0.0056), "e0b": (0.0092, 0.016, 0.0073, 0.0088), "d1": (0.056, 0.044, 0.031, 0.025),
          "e1": (0.048, 0.061, 0.035, 0.031), "d2": (0.16, 0.17, 0.12, 0.091), "b2": (0.12, 0.14, 0.089, 0.079),
          "u1": (0.089, 0.13, 0.034, 0.025), "c1": (0.029, 0.025, 0.024, 0.018), "u0": (0.02, 0.016, 0.013, 0.012),
