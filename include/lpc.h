@@ -39,7 +39,8 @@ typedef enum {
   LPC_ERR_WORKSPACE = -3,        /* workspace too small or misaligned */
   LPC_ERR_HIP = -4,              /* a HIP runtime call failed (detail in lpc_last_error) */
   LPC_ERR_FIXED_OVERFLOW = -5,   /* a density cell exceeded the 64-bit fixed-point headroom (>= 2^63) */
-  LPC_ERR_NONFINITE = -6         /* a particle coordinate was NaN/Inf or absurdly far outside the box */
+  LPC_ERR_NONFINITE = -6,        /* a particle coordinate was NaN/Inf or absurdly far outside the box */
+  LPC_ERR_CAPACITY = -7          /* an output buffer was too small (the count needed is reported) */
 } lpc_status;
 
 /* Flat LCDM cosmology: Omega_Lambda = 1 - omega_m. The linear spectrum is A k^n_s T_BBKS(k)^2 with shape
@@ -148,6 +149,55 @@ lpc_status lpc_pm_force_noalloc(const lpc_geometry* geom, const lpc_stepping* st
 lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, const lpc_stepping* step,
                          const double* a_list, int32_t n_a, const lpc_particles* inout, void* ws, size_t ws_bytes,
                          void* stream);
+
+/* ---------------------------------------------------------------------------------------------------------------
+ * On-the-fly lightcone (Sec. 6.1) with box replicates (Sec. 6.2).
+ *
+ * Speed of light over H0 in Mpc/h (H0 = 100 h km/s/Mpc): the unit of comoving distance. */
+#define LPC_C_OVER_H0 2997.92458
+
+/* Comoving distance R_L(a) = (c / H0) int_a^1 da' / (a'^2 E(a')) in Mpc/h, the radius of the past lightcone of an
+ * observer at a = 1 (Sec. 6), at host scale factors a[m] in (0, 1] into host r[m] (host only). */
+lpc_status lpc_comoving_distance(const lpc_cosmology* cosmo, const double* a, int32_t m, double* r);
+
+/* One particle image leaving the lightcone. */
+typedef struct {
+  float pos[3];      /* comoving position at a (Mpc/h) in the replicated volume: box position + L (i, j, k) */
+  float vel[3];      /* momentum p = a^2 dx/dt / H0 (Mpc/h) at the drift's midpoint a_{i+1/2} (not interpolated) */
+  float a;           /* the scale factor at which the image left the lightcone */
+  int32_t index;     /* the particle's index in the caller's arrays */
+  int32_t replicate; /* ((i - rep_lo[0]) n_y + (j - rep_lo[1])) n_z + (k - rep_lo[2]), n_d = rep_hi[d] - rep_lo[d] + 1 */
+  int32_t reserved;  /* 0 */
+} lpc_lightcone_record;
+
+/* The lightcone of a run: an observer at `origin` (Mpc/h, in the box frame), active on every drift that starts at
+ * a >= a_start; the box repeated on the offsets L (i, j, k), rep_lo[d] <= i, j, k <= rep_hi[d] (all 0: the box
+ * alone; at most 32768 replicates, each index within +-1024); `records` is a DEVICE array of `capacity` records
+ * (caller-owned; NULL allowed when capacity is 0). */
+typedef struct {
+  double origin[3];
+  double a_start;
+  int32_t rep_lo[3];
+  int32_t rep_hi[3];
+  lpc_lightcone_record* records;
+  int64_t capacity;
+} lpc_lightcone;
+
+/* lpc_cola_step (same arguments, workspace lpc_workspace_bytes(geom, LPC_OP_COLA_STEP, n), same final particles) with
+ * the lightcone drift of Sec. 6.1. In each lightcone drift a_i -> a_{i+1} every particle image (the wrapped position
+ * plus a replicate offset, drifted without wrapping) is tested: it leaves the lightcone when R_p(a_i) <= R_L(a_i)
+ * and R_p(a_{i+1}) > R_L(a_{i+1}), R_p being its distance to the observer. Its crossing time comes from the linear
+ * interpolation of R_p and R_L between a_i and a_{i+1} (the interpolation equation of Sec. 6.1), its position from
+ * the drift (Sec. 2.3) from a_i to that time, its momentum is the one at a_{i+1/2} plus, for COLA, the frame momentum
+ * a^3 E (D1' psi1 + D2' psi2) there. Replicates whose closest point lies beyond R_L(a_i) are skipped for that drift and
+ * all later ones (Sec. 6.2.3); each workgroup also skips images its particles' bounding boxes cannot cross. Records
+ * are appended in no fixed order; *n_records (host) receives their number. When it exceeds lc->capacity the records
+ * past the capacity are dropped and LPC_ERR_CAPACITY is returned (the particles are still advanced). a_list ends at
+ * a <= 1 and holds at most 1000 times. */
+lpc_status lpc_cola_step_lightcone(const lpc_geometry* geom, const lpc_cosmology* cosmo, const lpc_stepping* step,
+                                   const double* a_list, int32_t n_a, const lpc_particles* inout,
+                                   const lpc_lightcone* lc, int64_t* n_records, void* ws, size_t ws_bytes,
+                                   void* stream);
 
 /* One box of a batched run: its geometry (n_side unused) and its device particles (pos, vel, psi1, psi2). */
 typedef struct {

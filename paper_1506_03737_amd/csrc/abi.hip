@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -21,6 +22,11 @@
 namespace {
 thread_local std::string g_error;
 }  // namespace
+
+static_assert(sizeof(lpc_lightcone_record) == sizeof(lpc::kern::LcRecord), "lightcone record layout");
+static_assert(offsetof(lpc_lightcone_record, a) == offsetof(lpc::kern::LcRecord, a), "lightcone record layout");
+static_assert(offsetof(lpc_lightcone_record, replicate) == offsetof(lpc::kern::LcRecord, replicate),
+              "lightcone record layout");
 
 namespace lpc {
 namespace abi {
@@ -405,6 +411,8 @@ class JobPack {
     }
     return reinterpret_cast<const float*>(dev_ + it->second);
   }
+  // Device copy of n bytes of host data (uploaded with the tables).
+  const void* data(const void* p, size_t n) { return dev_ + append(p, n); }
   template <class J>
   const J* jobs(const Section& s) const {
     return reinterpret_cast<const J*>(dev_ + s.jobs_off);
@@ -788,8 +796,9 @@ void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags,
 // The whole COLA run over a_list for every box (all boxes share cosmology, stepping and time list). Particles are
 // tile-sorted into workspace copy 0 first, re-sorted into the other copy before every later force evaluation, and
 // copied back to the caller's order at the end.
+// lc (optional): per drift i, the lightcone step (active when its table pointer is set).
 void run_cola(const JobPack& jp, const ForceProgram& f, const std::vector<double>& tab, int n_a, double om, bool cola,
-              int* flags, hipStream_t s) {
+              int* flags, hipStream_t s, const std::vector<kern::LightconeStep>* lc = nullptr) {
   auto row = [&tab](int i) { return tab.data() + static_cast<size_t>(i) * host::kCoefColumns; };
   int c = 0;
   run_sort(jp, f.ss, f.sort_user, flags, s);
@@ -816,6 +825,14 @@ void run_cola(const JobPack& jp, const ForceProgram& f, const std::vector<double
     // a drift is followed by a re-sort: its key pass runs inside this kernel, on zeroed bucket counts
     const bool keys = kd.do_drift != 0;
     if (keys) stage("sort keys", s, [&] { return kern::fill_i32(f.ss.cnt, static_cast<size_t>(f.ss.G), 0, s); });
+    if (lc && kd.do_drift && (*lc)[static_cast<size_t>(i)].tab) {
+      stage("gather kick drift lightcone", s, [&] {
+        return kern::launch_gather_kick_drift_lc(jp.jobs<kern::PartJob>(f.parts[c]), jp.table(f.parts[c]), kd,
+                                                 (*lc)[static_cast<size_t>(i)], flags, f.ss.cnt, f.ss.key, f.ss.rank,
+                                                 s);
+      });
+      continue;
+    }
     stage("gather kick drift", s, [&] {
       return kern::launch_gather_kick_drift(jp.jobs<kern::PartJob>(f.parts[c]), jp.table(f.parts[c]), kd, flags,
                                             keys ? f.ss.cnt : nullptr, keys ? f.ss.key : nullptr,
@@ -1030,6 +1047,7 @@ const char* lpc_status_string(lpc_status s) {
     case LPC_ERR_HIP: return "LPC_ERR_HIP";
     case LPC_ERR_FIXED_OVERFLOW: return "LPC_ERR_FIXED_OVERFLOW";
     case LPC_ERR_NONFINITE: return "LPC_ERR_NONFINITE";
+    case LPC_ERR_CAPACITY: return "LPC_ERR_CAPACITY";
   }
   return "unknown lpc_status";
 }
@@ -1108,6 +1126,135 @@ lpc_status lpc_cola_step(const lpc_geometry* geom, const lpc_cosmology* cosmo, c
     jp.upload(s);
     run_cola(jp, f, tab, n_a, cosmo->omega_m, step->cola != 0, flags, s);
     return finish(flags, s);
+  });
+}
+
+lpc_status lpc_comoving_distance(const lpc_cosmology* cosmo, const double* a, int32_t m, double* r) {
+  if (lpc_status st = check_cosmo(cosmo)) return st;
+  if (m < 0 || (m > 0 && (!a || !r))) return fail(LPC_ERR_INVALID_ARG, "bad a/r arrays");
+  for (int i = 0; i < m; ++i)
+    if (!(a[i] > 0.0 && a[i] <= 1.0)) return fail(LPC_ERR_INVALID_ARG, "a[%d] must be in (0, 1]", i);
+  return guarded([&]() {
+    const host::Cosmo c = to_host(cosmo);
+    for (int i = 0; i < m; ++i) r[i] = host::comoving_distance(c, a[i]);
+    return LPC_OK;
+  });
+}
+
+lpc_status lpc_cola_step_lightcone(const lpc_geometry* geom, const lpc_cosmology* cosmo, const lpc_stepping* step,
+                                   const double* a_list, int32_t n_a, const lpc_particles* inout,
+                                   const lpc_lightcone* lc, int64_t* n_records, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  if (lpc_status st = check_geom_mesh(geom)) return st;
+  if (lpc_status st = check_cosmo(cosmo)) return st;
+  if (lpc_status st = check_stepping(step)) return st;
+  if (lpc_status st = check_particles(inout, step->cola != 0)) return st;
+  if (inout->n == 0) return fail(LPC_ERR_INVALID_ARG, "no particles");
+  if (!lc || !n_records) return fail(LPC_ERR_INVALID_ARG, "lightcone or n_records is NULL");
+  if (lc->capacity < 0 || (lc->capacity > 0 && !lc->records))
+    return fail(LPC_ERR_INVALID_ARG, "lightcone capacity < 0, or records NULL with capacity > 0");
+  int64_t nrep = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (!std::isfinite(lc->origin[d])) return fail(LPC_ERR_INVALID_ARG, "origin not finite");
+    if (lc->rep_lo[d] > lc->rep_hi[d]) return fail(LPC_ERR_INVALID_ARG, "rep_lo[%d] > rep_hi[%d]", d, d);
+    if (lc->rep_lo[d] < -1024 || lc->rep_hi[d] > 1024) return fail(LPC_ERR_INVALID_ARG, "replicate range beyond +-1024");
+    nrep *= static_cast<int64_t>(lc->rep_hi[d]) - lc->rep_lo[d] + 1;
+  }
+  if (nrep > 32768) return fail(LPC_ERR_INVALID_ARG, "more than 32768 replicates");
+  if (!(lc->a_start > 0.0) || !std::isfinite(lc->a_start)) return fail(LPC_ERR_INVALID_ARG, "a_start must be positive");
+  if (n_a > 1000) return fail(LPC_ERR_INVALID_ARG, "a lightcone run takes at most 1000 times");
+  std::vector<double> tab(static_cast<size_t>(n_a > 0 ? n_a : 0) * host::kCoefColumns);
+  if (lpc_status st = lpc_cola_coefficients(cosmo, step, a_list, n_a, tab.data())) return st;
+  if (a_list[n_a - 1] > 1.0) return fail(LPC_ERR_INVALID_ARG, "a lightcone run ends at a <= 1");
+  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_COLA_STEP, inout->n);
+  if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  *n_records = 0;
+  return guarded([&]() {
+    const host::Cosmo c = to_host(cosmo);
+    int* flags = reinterpret_cast<int*>(ws);
+    // the record counter sits in the flag region (64 bytes in, 8 bytes)
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(at(ws, 64));
+    stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
+    stage("clear flags", s, [&] { return kern::fill_i32(reinterpret_cast<int*>(counter), 2, 0, s); });
+    JobPack jp(at(ws, p.jobs));
+    const ForceBox b = force_box(ws, p, geom->n_mesh, geom->box, inout->n, inout->pos, inout->vel, inout->psi1,
+                                 inout->psi2, nullptr, nullptr);
+    const ForceProgram f = add_force(jp, {b}, sort_space(ws, p, geom->n_mesh, LPC_OP_COLA_STEP, inout->n),
+                                     step->deconv_power, true);
+    // Replicates sorted by their closest distance to the observer: the ones a drift still needs (closest point
+    // within R_L(a_i), Sec. 6.2.3) are then a prefix of the list.
+    struct Rep {
+      double dmin;
+      int v[4];
+    };
+    std::vector<Rep> reps;
+    const int ny = lc->rep_hi[1] - lc->rep_lo[1] + 1, nz = lc->rep_hi[2] - lc->rep_lo[2] + 1;
+    for (int ix = lc->rep_lo[0]; ix <= lc->rep_hi[0]; ++ix)
+      for (int iy = lc->rep_lo[1]; iy <= lc->rep_hi[1]; ++iy)
+        for (int iz = lc->rep_lo[2]; iz <= lc->rep_hi[2]; ++iz) {
+          const int ijk[3] = {ix, iy, iz};
+          double d2 = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            const double lo = ijk[d] * geom->box, hi = lo + geom->box, o = lc->origin[d];
+            const double e = std::max(0.0, std::max(lo - o, o - hi));
+            d2 += e * e;
+          }
+          const int flat = ((ix - lc->rep_lo[0]) * ny + (iy - lc->rep_lo[1])) * nz + (iz - lc->rep_lo[2]);
+          reps.push_back(Rep{std::sqrt(d2), {ix, iy, iz, flat}});
+        }
+    std::stable_sort(reps.begin(), reps.end(), [](const Rep& x, const Rep& y) { return x.dmin < y.dmin; });
+    std::vector<int> rep_ints;
+    for (const Rep& r : reps) rep_ints.insert(rep_ints.end(), r.v, r.v + 4);
+    const int* reps_dev = static_cast<const int*>(jp.data(rep_ints.data(), rep_ints.size() * sizeof(int)));
+    const bool modified = step->modified != 0, cola = step->cola != 0;
+    std::vector<kern::LightconeStep> lcs(static_cast<size_t>(n_a));
+    for (int i = 0; i + 1 < n_a; ++i) {
+      const double ai = a_list[i], an = a_list[i + 1];
+      if (ai < lc->a_start) continue;
+      kern::LightconeStep& L = lcs[static_cast<size_t>(i)];
+      const double rli = host::comoving_distance(c, ai), rln = host::comoving_distance(c, an);
+      int nact = 0;
+      while (nact < static_cast<int>(reps.size()) && reps[static_cast<size_t>(nact)].dmin <= rli) ++nact;
+      // partial drift from a_i to a = a_i + t (a_{i+1} - a_i) at t = k / (kLcTab - 1)
+      std::vector<float> tb(3 * kern::kLcTab);
+      const double d1i = host::growth_D1(c, ai), d2i = host::growth_D2(c, ai);
+      for (int k = 0; k < kern::kLcTab; ++k) {
+        const double a = (k == kern::kLcTab - 1) ? an : ai + (an - ai) * k / (kern::kLcTab - 1.0);
+        tb[3 * k] = static_cast<float>(host::partial_drift_factor(c, ai, a, an, modified, step->n_lpt));
+        tb[3 * k + 1] = static_cast<float>(host::growth_D1(c, a) - d1i);
+        tb[3 * k + 2] = static_cast<float>(host::growth_D2(c, a) - d2i);
+      }
+      L.ai = static_cast<float>(ai);
+      L.aip1 = static_cast<float>(an);
+      L.rli = static_cast<float>(rli);
+      L.rln = static_cast<float>(rln);
+      L.ox = static_cast<float>(lc->origin[0]);
+      L.oy = static_cast<float>(lc->origin[1]);
+      L.oz = static_cast<float>(lc->origin[2]);
+      if (cola) {
+        const double am = 0.5 * (ai + an), pref = am * am * am * host::hubble_E(c, am);
+        L.f1h = static_cast<float>(pref * host::growth_dD1(c, am));
+        L.f2h = static_cast<float>(pref * host::growth_dD2(c, am));
+      }
+      L.tab = static_cast<const float*>(jp.data(tb.data(), tb.size() * sizeof(float)));
+      L.reps = reps_dev;
+      L.nrep = nact;
+      L.out = reinterpret_cast<kern::LcRecord*>(lc->records);
+      L.count = counter;
+      L.capacity = lc->capacity;
+    }
+    jp.upload(s);
+    run_cola(jp, f, tab, n_a, cosmo->omega_m, cola, flags, s, &lcs);
+    unsigned long long cnt = 0;
+    check(hipMemcpyAsync(&cnt, counter, sizeof(cnt), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(count)");
+    lpc_status st = finish(flags, s);
+    *n_records = static_cast<int64_t>(cnt);
+    if (st != LPC_OK) return st;
+    if (static_cast<long long>(cnt) > lc->capacity)
+      return fail(LPC_ERR_CAPACITY, "%llu lightcone records, capacity %lld: the records past the capacity were dropped",
+                  cnt, static_cast<long long>(lc->capacity));
+    return LPC_OK;
   });
 }
 

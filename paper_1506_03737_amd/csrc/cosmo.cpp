@@ -111,14 +111,30 @@ double kick_factor(const Cosmo& c, double a_lo, double a_i, double a_hi, bool mo
   return integrate([&c](double a) { return 1.0 / (a * a * hubble_E(c, a)); }, a_lo, a_hi);
 }
 
-double drift_factor(const Cosmo& c, double a_i, double a_ip1, bool modified, double n_lpt) {
+double partial_drift_factor(const Cosmo& c, double a_i, double a_end, double a_ip1, bool modified, double n_lpt) {
+  if (a_end == a_i) return 0.0;
   if (modified) {
     const double mid = 0.5 * (a_i + a_ip1);
     const double v =
-        integrate([&c, n_lpt](double a) { return std::pow(a, n_lpt) / (a * a * a * hubble_E(c, a)); }, a_i, a_ip1);
+        integrate([&c, n_lpt](double a) { return std::pow(a, n_lpt) / (a * a * a * hubble_E(c, a)); }, a_i, a_end);
     return v / std::pow(mid, n_lpt);
   }
-  return integrate([&c](double a) { return 1.0 / (a * a * a * hubble_E(c, a)); }, a_i, a_ip1);
+  return integrate([&c](double a) { return 1.0 / (a * a * a * hubble_E(c, a)); }, a_i, a_end);
+}
+
+double drift_factor(const Cosmo& c, double a_i, double a_ip1, bool modified, double n_lpt) {
+  return partial_drift_factor(c, a_i, a_ip1, a_ip1, modified, n_lpt);
+}
+
+// 1 / (a^2 E) = a^(-1/2) / sqrt(Om + OL a^3); with a = s^2 (da = 2 s ds) the integrand becomes
+// 2 / sqrt(Om + OL s^6), smooth down to a = 0.
+double comoving_distance(const Cosmo& c, double a) {
+  const double om = c.omega_m, ol = 1.0 - c.omega_m;
+  auto f = [om, ol](double s) {
+    const double s2 = s * s;
+    return 2.0 / std::sqrt(om + ol * s2 * s2 * s2);
+  };
+  return kCOverH0 * integrate(f, std::sqrt(a), 1.0, 4);
 }
 
 void coefficient_table(const Cosmo& c, bool modified, double n_lpt, const double* a, int n, double* out) {

@@ -21,6 +21,12 @@ double growth_D2(const Cosmo& c, double a);
 double growth_dD2(const Cosmo& c, double a);
 double kick_factor(const Cosmo& c, double a_lo, double a_i, double a_hi, bool modified, double n_lpt);
 double drift_factor(const Cosmo& c, double a_i, double a_ip1, bool modified, double n_lpt);
+// The drift factor from a_i to a within the step a_i -> a_{i+1} (the modified form keeps the step's normalisation
+// u(a_{i+1/2})); drift_factor(a_i, a_{i+1}) is the case a = a_{i+1}.
+double partial_drift_factor(const Cosmo& c, double a_i, double a, double a_ip1, bool modified, double n_lpt);
+// Comoving distance to scale factor a, (c / H0) int_a^1 da / (a^2 E), in Mpc/h.
+constexpr double kCOverH0 = 2997.92458;
+double comoving_distance(const Cosmo& c, double a);
 void coefficient_table(const Cosmo& c, bool modified, double n_lpt, const double* a, int n, double* out);
 double pk_amplitude(const Cosmo& c);
 double linear_pk(const Cosmo& c, double amplitude, double k);

@@ -48,6 +48,31 @@ struct KickDrift {
   int cola;
 };
 
+// On-the-fly lightcone of one drift a_i -> a_{i+1} (Sec. 6.1, 6.2). Particle images that leave the lightcone in the
+// drift are appended to `out` (the count in *count, records past `capacity` dropped).
+constexpr int kLcTab = 65;       // nodes of the partial-drift table over t = (a - a_i) / (a_{i+1} - a_i) in [0, 1]
+constexpr int kLcList = 512;     // replicate images a workgroup keeps after its own culling (more: test them all)
+struct LcRecord {                // layout of lpc_lightcone_record
+  float pos[3];
+  float vel[3];
+  float a;
+  int index;
+  int replicate;
+  int reserved;
+};
+struct LightconeStep {
+  float ai, aip1;                // a_i, a_{i+1}
+  float rli, rln;                // R_L(a_i), R_L(a_{i+1}) (Mpc/h)
+  float ox, oy, oz;              // observer (Mpc/h)
+  float f1h, f2h;                // frame momentum factors at a_{i+1/2} (0 for plain PM)
+  const float* tab;              // [kLcTab][3]: Q(a_i, a), D1(a) - D1(a_i), D2(a) - D2(a_i) at the nodes
+  const int* reps;               // [nrep][4]: replicate (i, j, k) and its flat index
+  int nrep;
+  LcRecord* out;
+  unsigned long long* count;
+  long long capacity;
+};
+
 hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s);
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -232,6 +257,9 @@ hipError_t launch_unsort(const UnsortJob* jobs, WorkTable wt, hipStream_t s);
 // which must be zero): the key pass of k_tile_key folded into the drift.
 hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift kd, int* flags, int* cnt, int* key,
                                     int* rank, hipStream_t s);
+// The same kernel with the lightcone test of Sec. 6.1 in its drift (kd.do_drift must be 1).
+hipError_t launch_gather_kick_drift_lc(const PartJob* jobs, WorkTable wt, KickDrift kd, const LightconeStep& lc,
+                                       int* flags, int* cnt, int* key, int* rank, hipStream_t s);
 hipError_t launch_gather(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s);
 hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, hipStream_t s);
 // B: tile columns (rows for z passes); lds: dynamic LDS bytes (the max over the jobs).

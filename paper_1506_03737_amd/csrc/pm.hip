@@ -496,10 +496,139 @@ __device__ __forceinline__ bool cic_gather(LPC_GLOBAL const float* __restrict__ 
   return true;
 }
 
+// Lightcone test of one workgroup's particles (Sec. 6.1, 6.2): xs = wrapped positions at a_i, xe = unwrapped
+// positions at a_{i+1}, v = momentum after the kick (the one at a_{i+1/2}), p1 / p2 = 2LPT displacements, ok = the
+// thread holds a particle. Called by every thread of the workgroup (it has barriers).
+//  1. Culling on the workgroup's bounding boxes (the rule of Sec. 6.2.3 applied to a tile of sorted particles
+//     rather than to a whole replicate): an image can hold a crossing only if its start box comes within R_L(a_i)
+//     of the observer and its end box reaches beyond R_L(a_{i+1}); the others are skipped.
+//  2. Each particle tests each kept image: R_p,i <= R_L,i and R_p,i+1 > R_L,i+1; the crossing time comes from the
+//     linear interpolation of R_p and R_L, the position from the drift to a_L (partial-drift table), the velocity is
+//     the momentum at a_{i+1/2} (plus the frame momentum there for COLA). Records are appended with one counter atomic
+//     per wave and image.
+struct LcShared {
+  float bb[kNT / 64][12];
+  int list[kLcList];
+  int nlist;
+};
+
+__device__ void lightcone_test(const LightconeStep& lc, const KickDrift& kd, float box, bool ok, const float xs[3],
+                               const float xe[3], const float v[3], const float p1[3], const float p2[3], int index,
+                               LcShared& sm) {
+  const int tid = threadIdx.x, lane = __lane_id(), wave = tid / 64;
+  const float inf = __builtin_inff();
+  float b[12];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    b[d] = ok ? xs[d] : inf;
+    b[3 + d] = ok ? xs[d] : -inf;
+    b[6 + d] = ok ? xe[d] : inf;
+    b[9 + d] = ok ? xe[d] : -inf;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      b[d] = fminf(b[d], __shfl_xor(b[d], off));
+      b[3 + d] = fmaxf(b[3 + d], __shfl_xor(b[3 + d], off));
+      b[6 + d] = fminf(b[6 + d], __shfl_xor(b[6 + d], off));
+      b[9 + d] = fmaxf(b[9 + d], __shfl_xor(b[9 + d], off));
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) sm.bb[wave][k] = b[k];
+  }
+  if (tid == 0) sm.nlist = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    float m = sm.bb[0][k];
+#pragma unroll
+    for (int wv = 1; wv < kNT / 64; ++wv) m = (k % 6 < 3) ? fminf(m, sm.bb[wv][k]) : fmaxf(m, sm.bb[wv][k]);
+    b[k] = m;
+  }
+  const float o[3] = {lc.ox, lc.oy, lc.oz};
+  const float rli2 = lc.rli * lc.rli, rln2 = lc.rln * lc.rln;
+  const int* __restrict__ reps = lc.reps;
+  for (int r = tid; r < lc.nrep; r += kNT) {
+    float dmin2 = 0.f, dmax2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float off = static_cast<float>(reps[4 * r + d]) * box;
+      const float c = fmaxf(0.f, fmaxf(b[d] + off - o[d], o[d] - (b[3 + d] + off)));
+      const float f = fmaxf(fabsf(b[6 + d] + off - o[d]), fabsf(b[9 + d] + off - o[d]));
+      dmin2 += c * c;
+      dmax2 += f * f;
+    }
+    if (dmin2 <= rli2 && dmax2 > rln2) {
+      const int slot = atomicAdd(&sm.nlist, 1);
+      if (slot < kLcList) sm.list[slot] = r;
+    }
+  }
+  __syncthreads();
+  const int nl = sm.nlist;
+  const bool all = nl > kLcList;  // uniform
+  const int count = all ? lc.nrep : nl;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int e = 0; e < count; ++e) {
+    const int r = __builtin_amdgcn_readfirstlane(all ? e : sm.list[e]);
+    float off[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) off[d] = static_cast<float>(reps[4 * r + d]) * box;
+    float ri2 = 0.f, rn2 = 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float ds = xs[d] + off[d] - o[d], de = xe[d] + off[d] - o[d];
+      ri2 += ds * ds;
+      rn2 += de * de;
+    }
+    const bool hit = ok && ri2 <= rli2 && rn2 > rln2;
+    const unsigned long long mask = __ballot(hit);
+    if (mask == 0ull) continue;
+    unsigned long long base = 0;
+    const int leader = __ffsll(static_cast<long long>(mask)) - 1;
+    if (lane == leader) base = atomicAdd(lc.count, static_cast<unsigned long long>(__popcll(mask)));
+    base = __shfl(base, leader);
+    if (!hit) continue;
+    const unsigned long long slot = base + __popcll(mask & below);
+    if (slot >= static_cast<unsigned long long>(lc.capacity)) continue;
+    const float rpi = sqrtf(ri2), rpn = sqrtf(rn2);
+    float t = (lc.rli - rpi) / ((rpn - rpi) - (lc.rln - lc.rli));
+    t = fminf(fmaxf(t, 0.f), 1.f);
+    const float u = t * static_cast<float>(kLcTab - 1);
+    const int k = min(static_cast<int>(u), kLcTab - 2);
+    const float fr = u - static_cast<float>(k);
+    const float* __restrict__ tb = lc.tab + 3 * k;
+    const float q = tb[0] + fr * (tb[3] - tb[0]);
+    const float e1 = tb[1] + fr * (tb[4] - tb[1]);
+    const float e2 = tb[2] + fr * (tb[5] - tb[2]);
+    LcRecord* rec = lc.out + slot;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      float xl = xs[d] + off[d] + q * v[d];
+      float vl = v[d];
+      if (kd.cola) {
+        xl += e1 * p1[d] + e2 * p2[d];
+        vl += lc.f1h * p1[d] + lc.f2h * p2[d];
+      }
+      rec->pos[d] = xl;
+      rec->vel[d] = vl;
+    }
+    rec->a = lc.ai + t * (lc.aip1 - lc.ai);
+    rec->index = index;
+    rec->replicate = reps[4 * r + 3];
+    rec->reserved = 0;
+  }
+  __syncthreads();  // sm is reused by the next item
+}
+
+template <bool LC>
 __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __restrict__ jobs,
                                                            const int* __restrict__ offs, int njob, int total,
-                                                           KickDrift kd, int* __restrict__ flags, int* __restrict__ cnt,
-                                                           int* __restrict__ key, int* __restrict__ rank) {
+                                                           KickDrift kd, LightconeStep lc, int* __restrict__ flags,
+                                                           int* __restrict__ cnt, int* __restrict__ key,
+                                                           int* __restrict__ rank) {
   __shared__ int sh[3 * kRankSlots];  // block_rank, when key != NULL
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
@@ -508,6 +637,10 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
     const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
     const bool active = i < n;
     float x[3] = {0.f, 0.f, 0.f};
+    // the lightcone's view of the drift: start, unwrapped end, momentum, displacements
+    float xs[3] = {0.f, 0.f, 0.f}, xe[3] = {0.f, 0.f, 0.f}, vv[3] = {0.f, 0.f, 0.f};
+    float q1[3] = {0.f, 0.f, 0.f}, q2[3] = {0.f, 0.f, 0.f};
+    bool lc_ok = false;
     if (active) {
       LPC_GLOBAL float* pos = to_global(J.pos);
       LPC_GLOBAL float* vel = to_global(J.vel);
@@ -521,6 +654,7 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
         atomicOr(flags + kFlagNonfinite, 1);  // the particle is left as it is
       } else {
         const float box = J.box;
+        lc_ok = true;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           float acc = g[d];
@@ -535,12 +669,24 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
           if (kd.do_drift) {
             float xn = x[d] + kd.drift * v;
             if (kd.cola) xn += kd.dd1 * p1 + kd.dd2 * p2;
+            if constexpr (LC) {
+              xs[d] = x[d];
+              xe[d] = xn;
+              vv[d] = v;
+              q1[d] = p1;
+              q2[d] = p2;
+            }
             xn = wrap_box(xn, box);
             pos[d * n + i] = xn;
             x[d] = xn;
           }
         }
       }
+    }
+    if constexpr (LC) {
+      __shared__ LcShared lsm;
+      const int index = active ? (J.orig ? to_global(J.orig)[i] : static_cast<int>(i)) : -1;
+      lightcone_test(lc, kd, J.box, lc_ok, xs, xe, vv, q1, q2, index, lsm);
     }
     if (key) {  // uniform: the next sort's key pass on the positions as stored (k_tile_key's arithmetic)
       int g = 0;
@@ -656,8 +802,19 @@ hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift
                                     int* rank, hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
   if (key && (!cnt || !rank)) return hipErrorInvalidValue;
-  k_gather_kick_drift<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd, flags, cnt, key,
-                                                                 rank);
+  k_gather_kick_drift<false><<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd,
+                                                                        LightconeStep{}, flags, cnt, key, rank);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_kick_drift_lc(const PartJob* jobs, WorkTable wt, KickDrift kd, const LightconeStep& lc,
+                                       int* flags, int* cnt, int* key, int* rank, hipStream_t s) {
+  if (wt.total <= 0) return hipSuccess;
+  if ((key && (!cnt || !rank)) || !kd.do_drift || !lc.tab || (lc.nrep > 0 && !lc.reps) || !lc.count ||
+      (lc.capacity > 0 && !lc.out))
+    return hipErrorInvalidValue;
+  k_gather_kick_drift<true><<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd, lc, flags,
+                                                                       cnt, key, rank);
   return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ LPC_OP_FFT = 5
 COEF_COLUMNS = ("a", "D1", "D2", "dD1", "dD2", "E", "K", "Q", "dDD1", "dDD2", "f1", "f2")
 
 STATUS = {0: "LPC_OK", -1: "LPC_ERR_INVALID_ARG", -2: "LPC_ERR_UNSUPPORTED_SIZE", -3: "LPC_ERR_WORKSPACE",
-          -4: "LPC_ERR_HIP", -5: "LPC_ERR_FIXED_OVERFLOW", -6: "LPC_ERR_NONFINITE"}
+          -4: "LPC_ERR_HIP", -5: "LPC_ERR_FIXED_OVERFLOW", -6: "LPC_ERR_NONFINITE", -7: "LPC_ERR_CAPACITY"}
 
 
 class LpcError(RuntimeError):
@@ -49,6 +49,14 @@ class Particles(ctypes.Structure):
                 ("psi2", ctypes.c_void_p), ("id", ctypes.c_void_p), ("n", ctypes.c_int64)]
 
 
+class Lightcone(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("a_start", ctypes.c_double), ("rep_lo", ctypes.c_int32 * 3),
+                ("rep_hi", ctypes.c_int32 * 3), ("records", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+LIGHTCONE_RECORD_FIELDS = 10  # lpc_lightcone_record: 6 floats + a + index + replicate + reserved (4 bytes each)
+
+
 class BatchEntry(ctypes.Structure):
     _fields_ = [("geom", Geometry), ("particles", Particles)]
 
@@ -73,6 +81,9 @@ def _load():
         "lpc_pm_force": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp, sz, vp]),
         "lpc_pm_force_noalloc": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp]),
         "lpc_cola_step": (i32, [P(Geometry), P(Cosmology), P(Stepping), P(dbl), i32, P(Particles), vp, sz, vp]),
+        "lpc_cola_step_lightcone": (i32, [P(Geometry), P(Cosmology), P(Stepping), P(dbl), i32, P(Particles),
+                                          P(Lightcone), P(i64), vp, sz, vp]),
+        "lpc_comoving_distance": (i32, [P(Cosmology), P(dbl), i32, P(dbl)]),
         "lpc_workspace_bytes_batched": (sz, [P(BatchEntry), i32]),
         "lpc_cola_step_batched": (i32, [P(BatchEntry), i32, P(Cosmology), P(Stepping), P(dbl), i32, vp, sz, vp]),
         "lpc_graph_enable": (i32, [i32]),
@@ -110,6 +121,7 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_pm_force_noalloc", "lpc_cola_step",
+            "lpc_cola_step_lightcone", "lpc_comoving_distance",
             "lpc_workspace_bytes_batched",
             "lpc_cola_step_batched", "lpc_graph_enable", "lpc_power_spectrum",
             "lpc_net_param_count", "lpc_net_init", "lpc_net_workspace_bytes", "lpc_net_features", "lpc_net_forward",
@@ -212,6 +224,42 @@ def lpc_cola_step(geom, cosmo, step, a_list, particles, ws, stream=None):
     _check(LIB.lpc_cola_step(ctypes.byref(geom), ctypes.byref(cosmo), ctypes.byref(step),
                              a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(a.size), ctypes.byref(p),
                              _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def lightcone(origin, a_start, records=None, rep_lo=(0, 0, 0), rep_hi=(0, 0, 0)):
+    """An lpc_lightcone; `records` is a device tensor of shape (capacity, 10) with 4-byte elements (float32 or int32
+    view of lpc_lightcone_record), or None for capacity 0. Keep the tensor referenced while the struct is used."""
+    cap = 0 if records is None else int(records.shape[0])
+    if records is not None and (records.element_size() != 4 or records.shape[1] != LIGHTCONE_RECORD_FIELDS
+                                or not records.is_contiguous()):
+        raise ValueError("records must be a contiguous (capacity, 10) tensor of 4-byte elements")
+    return Lightcone((ctypes.c_double * 3)(*origin), float(a_start), (ctypes.c_int32 * 3)(*rep_lo),
+                     (ctypes.c_int32 * 3)(*rep_hi), _ptr(records).value, cap)
+
+
+def lpc_cola_step_lightcone(geom, cosmo, step, a_list, particles, lc, ws, stream=None):
+    """lpc_cola_step with the lightcone drift; returns the number of records (raises LpcError with status -7 when it
+    exceeds the capacity)."""
+    a = np.ascontiguousarray(a_list, dtype=np.float64)
+    p = particles.c_struct()
+    count = ctypes.c_int64(0)
+    status = LIB.lpc_cola_step_lightcone(ctypes.byref(geom), ctypes.byref(cosmo), ctypes.byref(step),
+                                         a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(a.size),
+                                         ctypes.byref(p), ctypes.byref(lc), ctypes.byref(count), _ptr(ws), ws.numel(),
+                                         _stream(stream))
+    if status != 0:
+        err = LpcError(status, LIB.lpc_last_error().decode())
+        err.count = int(count.value)
+        raise err
+    return int(count.value)
+
+
+def lpc_comoving_distance(cosmo, a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.empty_like(a)
+    D = ctypes.POINTER(ctypes.c_double)
+    _check(LIB.lpc_comoving_distance(ctypes.byref(cosmo), a.ctypes.data_as(D), int(a.size), out.ctypes.data_as(D)))
+    return out
 
 
 def _entries(boxes):

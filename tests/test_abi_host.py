@@ -55,6 +55,18 @@ def test_coefficients_eds_closed_form():
     assert got[2, 1] == pytest.approx(1.0, rel=1e-13)                               # D1(1)
 
 
+def test_comoving_distance_matches_oracle():
+    from oracle import lightcone as olc
+    from paper_1506_03737_amd import lpc
+    c = synth.COSMOLOGY
+    a = np.array([0.1, 0.55, 0.82, 0.91, 0.999, 1.0])
+    got = lpc.lpc_comoving_distance(lpc.cosmology(**c), a)
+    ref = np.array([olc.comoving_distance(x, c["omega_m"]) for x in a])
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-9)
+    with pytest.raises(lpc.LpcError):
+        lpc.lpc_comoving_distance(lpc.cosmology(**c), [1.5])
+
+
 def test_linear_power_matches_oracle():
     from paper_1506_03737_amd import lpc
     c = synth.COSMOLOGY
