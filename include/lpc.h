@@ -111,6 +111,41 @@ size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op, int64_t n_parti
 lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
                        const lpc_particles* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Primordial non-Gaussianity in the initial conditions (Sec. 5: local, equilateral, orthogonal or a generic kernel).
+ * The Gaussian primordial potential phi is drawn from the same white noise as lpc_init_ic, with power
+ * A k^(ns - 4) / alpha0^2 (A the sigma8 amplitude of the linear spectrum, alpha0 = (2/3) (c/H0)^2 g0 / Om, g0 the
+ * growth suppression D1(1) / lim_{a->0} D1(a) / a). The non-Gaussian potential is
+ *   Phi = phi + f_nl (NL - <NL>),  NL = sum_t c_t D^g_t[(D^a_t phi) (D^b_t phi)],
+ * where D^s multiplies Fourier mode k by k^(s (4 - ns) / 3) (k in h/Mpc; |k|^s for a scale-invariant spectrum), so a
+ * kernel whose exponents sum to zero per term has the bispectrum of the matching shape in fractional powers of P.
+ * The linear density is delta_L(k) = alpha0 k^2 T(k) Phi(k) (f_nl = 0 gives lpc_init_ic's field, to rounding;
+ * positive f_nl skews the density positively); the 2LPT construction then proceeds as in lpc_init_ic. */
+typedef struct {
+  double c; /* coefficient */
+  double a; /* D exponents (each within [-4, 4]): inner a and b, outer g */
+  double b;
+  double g;
+} lpc_png_term;
+
+typedef struct {
+  double f_nl;
+  int32_t n_terms;  /* 1..4 (at most 5 distinct inner exponents in all) */
+  int32_t reserved; /* must be 0 */
+  lpc_png_term terms[4];
+} lpc_png;
+
+enum { LPC_PNG_LOCAL = 0, LPC_PNG_EQUILATERAL = 1, LPC_PNG_ORTHOGONAL = 2 };
+
+/* The kernels of the standard shapes (host only): local NL = phi^2; equilateral (Creminelli et al. 2006)
+ * -3 phi^2 + 6 D^-1[(D phi) phi] - 2 D^-2[(D phi)^2]; orthogonal (Senatore et al. 2010)
+ * -9 phi^2 + 18 D^-1[(D phi) phi] - 8 D^-2[(D phi)^2]. */
+lpc_status lpc_png_preset(int32_t kind, double f_nl, lpc_png* out);
+
+/* lpc_init_ic with the non-Gaussian linear field of `png` (host struct). Workspace: lpc_workspace_bytes(geom,
+ * LPC_OP_INIT_IC, 0), as for lpc_init_ic. */
+lpc_status lpc_init_ic_png(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
+                           const lpc_png* png, const lpc_particles* out, void* ws, size_t ws_bytes, void* stream);
+
 /* The particle-mesh force of Sec. 2.4 (Eqs. 20-21) at positions pos[3][n]:
  *   particles sorted by mesh tile (16^3 cells) into the workspace (the single-GPU counterpart of moving particles
  *   to the process that owns their slab, Sec. 4.4), fixed-point CIC deposit by one workgroup per tile

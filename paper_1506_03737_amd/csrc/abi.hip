@@ -218,6 +218,7 @@ Plan make_ws_plan(int n, int op, int64_t np) {
     case LPC_OP_INIT_IC:
       p.A = take(cbytes);
       p.B = take(cbytes);
+      p.C = take(cbytes);  // the non-linear term's spectrum of a non-Gaussian field
       break;
     case LPC_OP_POWER_SPECTRUM:
       p.dens = take(M * 8);
@@ -1394,8 +1395,56 @@ lpc_status lpc_cola_step_batched(const lpc_batch_entry* entries, int32_t n_real,
   });
 }
 
-lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
-                       const lpc_particles* out, void* ws, size_t ws_bytes, void* stream) {
+lpc_status lpc_png_preset(int32_t kind, double f_nl, lpc_png* out) {
+  if (!out) return fail(LPC_ERR_INVALID_ARG, "out is NULL");
+  if (!std::isfinite(f_nl)) return fail(LPC_ERR_INVALID_ARG, "f_nl not finite");
+  lpc_png p{};
+  p.f_nl = f_nl;
+  // (c, a, b, g) of NL = sum c D^g[(D^a phi)(D^b phi)]: the kernels whose bispectra are the published templates
+  switch (kind) {
+    case LPC_PNG_LOCAL:
+      p.n_terms = 1;
+      p.terms[0] = lpc_png_term{1.0, 0.0, 0.0, 0.0};
+      break;
+    case LPC_PNG_EQUILATERAL:
+      p.n_terms = 3;
+      p.terms[0] = lpc_png_term{-3.0, 0.0, 0.0, 0.0};
+      p.terms[1] = lpc_png_term{6.0, 1.0, 0.0, -1.0};
+      p.terms[2] = lpc_png_term{-2.0, 1.0, 1.0, -2.0};
+      break;
+    case LPC_PNG_ORTHOGONAL:
+      p.n_terms = 3;
+      p.terms[0] = lpc_png_term{-9.0, 0.0, 0.0, 0.0};
+      p.terms[1] = lpc_png_term{18.0, 1.0, 0.0, -1.0};
+      p.terms[2] = lpc_png_term{-8.0, 1.0, 1.0, -2.0};
+      break;
+    default:
+      return fail(LPC_ERR_INVALID_ARG, "unknown non-Gaussianity kind %d", kind);
+  }
+  *out = p;
+  return LPC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+lpc_status check_png(const lpc_png* png) {
+  if (!std::isfinite(png->f_nl)) return fail(LPC_ERR_INVALID_ARG, "f_nl not finite");
+  if (png->n_terms < 1 || png->n_terms > kern::kPngMaxTerms)
+    return fail(LPC_ERR_INVALID_ARG, "n_terms must be in [1, %d]", kern::kPngMaxTerms);
+  if (png->reserved != 0) return fail(LPC_ERR_INVALID_ARG, "png.reserved must be 0");
+  for (int t = 0; t < png->n_terms; ++t) {
+    const lpc_png_term& q = png->terms[t];
+    if (!std::isfinite(q.c) || !(std::fabs(q.a) <= 4.0) || !(std::fabs(q.b) <= 4.0) || !(std::fabs(q.g) <= 4.0))
+      return fail(LPC_ERR_INVALID_ARG, "term %d: c must be finite and a, b, g within [-4, 4]", t);
+  }
+  return LPC_OK;
+}
+
+// 2LPT initial conditions; png (nullable) adds primordial non-Gaussianity to the linear field.
+lpc_status init_ic_impl(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
+                        const lpc_png* png, const lpc_particles* out, void* ws, size_t ws_bytes, void* stream) {
   if (!geom) return fail(LPC_ERR_INVALID_ARG, "geometry is NULL");
   if (!(geom->box > 0.0) || !std::isfinite(geom->box)) return fail(LPC_ERR_INVALID_ARG, "box must be positive");
   if (lpc_status st = check_mesh(geom->n_side, "n_side")) return st;
@@ -1403,10 +1452,22 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
   if (!(a_init > 0.0) || !std::isfinite(a_init)) return fail(LPC_ERR_INVALID_ARG, "a_init must be positive");
   if (lpc_status st = check_particles(out, true)) return st;
   if (!out->id) return fail(LPC_ERR_INVALID_ARG, "id is NULL");
+  if (png)
+    if (lpc_status st = check_png(png)) return st;
   const int N = geom->n_side;
   const int64_t n = static_cast<int64_t>(N) * N * N;
   if (out->n != n) return fail(LPC_ERR_INVALID_ARG, "particles.n = %lld but n_side^3 = %lld",
                                static_cast<long long>(out->n), static_cast<long long>(n));
+  // the distinct D exponents of the non-Gaussian terms (each needs one real field; five slots are free)
+  std::vector<double> alphas, gammas;
+  if (png) {
+    for (int t = 0; t < png->n_terms; ++t) {
+      for (double v : {png->terms[t].a, png->terms[t].b})
+        if (std::find(alphas.begin(), alphas.end(), v) == alphas.end()) alphas.push_back(v);
+      if (std::find(gammas.begin(), gammas.end(), png->terms[t].g) == gammas.end()) gammas.push_back(png->terms[t].g);
+    }
+    if (alphas.size() > 5) return fail(LPC_ERR_INVALID_ARG, "more than 5 distinct inner exponents a, b");
+  }
   const Plan p = make_ws_plan(N, LPC_OP_INIT_IC, 0);
   if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1418,6 +1479,7 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
     const int pitch = kern::mesh_pitch(N);
     float2* dhat = reinterpret_cast<float2*>(at(ws, p.A));
     float2* spec = reinterpret_cast<float2*>(at(ws, p.B));
+    float2* nlhat = reinterpret_cast<float2*>(at(ws, p.C));
     float* r0 = out->psi2;
     float* r1 = out->psi2 + n;
     float* r2 = out->psi2 + 2 * n;
@@ -1430,6 +1492,12 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
     C2RSections der[12];
     for (int k = 0; k < 12; ++k) der[k] = add_c2r(jp, spec, N, dst[k], inv_n3);
     const R2CSections source = add_r2c(jp, r0, false, 0.0, N, dhat);
+    // non-Gaussian stage: real fields D^a phi in the five slots psi1[0..2], psi2[1..2]; products in psi2[0]
+    float* slot[5] = {out->psi1, out->psi1 + n, out->psi1 + 2 * n, r1, r2};
+    std::vector<C2RSections> to_real;
+    std::vector<R2CSections> prod_r2c;
+    for (size_t v = 0; v < alphas.size(); ++v) to_real.push_back(add_c2r(jp, spec, N, slot[v], inv_n3));
+    for (size_t v = 0; v < gammas.size(); ++v) prod_r2c.push_back(add_r2c(jp, r0, false, 0.0, N, spec));
     jp.upload(s);
     auto derived = [&](int kind) {
       stage("spectral factor", s, [&] { return kern::ic_spectral_factor(dhat, spec, N, pitch, geom->box, kind, s); });
@@ -1437,7 +1505,44 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
     };
     stage("noise", s, [&] { return kern::ic_noise(seed, N, r0, s); });
     run_r2c(jp, noise, false, flags, s);
-    stage("scale spectrum", s, [&] { return kern::ic_scale_spectrum(dhat, N, pitch, geom->box, A, c.omega_m, c.h, c.n_s, s); });
+    if (!png) {
+      stage("scale spectrum", s, [&] { return kern::ic_scale_spectrum(dhat, N, pitch, geom->box, A, c.omega_m, c.h, c.n_s, s); });
+    } else {
+      // Phi = phi + fNL sum_j c_j D^g[(D^a phi)(D^b phi)], D^s = k^(s (4 - ns) / 3); delta_L = alpha0 k^2 T Phi
+      const double g0 = host::growth_suppression(c);
+      const double alpha0 = (2.0 / 3.0) * host::kCOverH0 * host::kCOverH0 * g0 / c.omega_m;
+      const double a_phi = A / (alpha0 * alpha0);
+      const double tilt = (4.0 - c.n_s) / 3.0;
+      stage("png potential", s, [&] { return kern::png_potential(dhat, N, pitch, geom->box, a_phi, c.n_s, s); });
+      for (size_t v = 0; v < alphas.size(); ++v) {
+        stage("png power", s, [&] {
+          return kern::png_power(dhat, spec, N, pitch, geom->box, alphas[v] * tilt, 1.0, false, s);
+        });
+        run_c2r(jp, to_real[v], s);
+      }
+      auto field = [&](double e) {
+        return slot[std::find(alphas.begin(), alphas.end(), e) - alphas.begin()];
+      };
+      for (size_t gi = 0; gi < gammas.size(); ++gi) {
+        kern::PngProducts pp{};
+        pp.out = r0;
+        for (int t = 0; t < png->n_terms; ++t) {
+          if (png->terms[t].g != gammas[gi]) continue;
+          pp.fa[pp.n] = field(png->terms[t].a);
+          pp.fb[pp.n] = field(png->terms[t].b);
+          pp.c[pp.n] = static_cast<float>(png->terms[t].c);
+          ++pp.n;
+        }
+        stage("png products", s, [&] { return kern::png_products(pp, n, s); });
+        run_r2c(jp, prod_r2c[gi], false, flags, s);
+        stage("png power", s, [&] {
+          return kern::png_power(spec, nlhat, N, pitch, geom->box, gammas[gi] * tilt, 1.0, gi > 0, s);
+        });
+      }
+      stage("png to delta", s, [&] {
+        return kern::png_to_delta(dhat, nlhat, N, pitch, geom->box, png->f_nl, alpha0, c.omega_m, c.h, s);
+      });
+    }
     for (int k = 0; k < 3; ++k) derived(k);  // Psi1
     for (int k = 3; k < 6; ++k) derived(k);  // phi_xx, phi_yy, phi_zz
     stage("source", s, [&] { return kern::ic_source_init(r0, r1, r2, n, s); });
@@ -1460,6 +1565,21 @@ lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uin
     });
     return finish(flags, s);
   });
+}
+
+}  // namespace
+
+extern "C" {
+
+lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
+                       const lpc_particles* out, void* ws, size_t ws_bytes, void* stream) {
+  return init_ic_impl(geom, cosmo, seed, a_init, nullptr, out, ws, ws_bytes, stream);
+}
+
+lpc_status lpc_init_ic_png(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
+                           const lpc_png* png, const lpc_particles* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!png) return fail(LPC_ERR_INVALID_ARG, "png is NULL");
+  return init_ic_impl(geom, cosmo, seed, a_init, png, out, ws, ws_bytes, stream);
 }
 
 lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_t n, double k_max, int32_t n_bins,

@@ -79,6 +79,9 @@ static double d1_norm(const Cosmo& c) { return hubble_E(c, 1.0) * heath(c, 1.0);
 
 double growth_D1(const Cosmo& c, double a) { return hubble_E(c, a) * heath(c, a) / d1_norm(c); }
 
+// Early on E ~ sqrt(Om) a^(-3/2) and the integral ~ (2/5) a^(5/2) / Om^(3/2), so D1(a) -> (2/5) a / (Om norm).
+double growth_suppression(const Cosmo& c) { return 2.5 * c.omega_m * d1_norm(c); }
+
 double growth_dD1(const Cosmo& c, double a) {
   const double E = hubble_E(c, a);
   const double dE = -1.5 * c.omega_m / (a * a * a * a * E);

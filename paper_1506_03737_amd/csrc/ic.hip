@@ -156,6 +156,81 @@ __global__ __launch_bounds__(kNT) void k_ic_assemble(float* __restrict__ pos, fl
   id[i] = static_cast<int32_t>(i);
 }
 
+// Primordial non-Gaussianity (Sec. 5). Phi_hat = phi_hat + fNL NL_hat with phi the Gaussian primordial potential and
+// NL = sum_j c_j D^g[(D^a phi)(D^b phi)], D^s multiplying mode k by k^(s (4 - ns) / 3); delta_L_hat = alpha(k) Phi_hat.
+
+// phi_hat = noise_hat sqrt(A_phi k^(ns - 4) N^3 / V) in place; zero at k = 0 and on the Nyquist planes.
+__global__ __launch_bounds__(kNT) void k_png_potential(float2* __restrict__ spec, int N, int pitch, double kf,
+                                                       double amp_norm, double a_phi, double n_s) {
+  const int nh = N / 2 + 1;
+  const int64_t count = static_cast<int64_t>(N) * N * nh;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (e >= count) return;
+  Mode m;
+  mode_of(e, N, nh, &m);
+  const int64_t idx = spec_index(e, nh, pitch);
+  if (m.zero) {
+    spec[idx] = make_float2(0.f, 0.f);
+    return;
+  }
+  const double k = kf * sqrt(static_cast<double>(m.nx * m.nx + m.ny * m.ny + m.nz * m.nz));
+  const double amp = sqrt(a_phi * pow(k, n_s - 4.0) * amp_norm);
+  const float2 v = spec[idx];
+  spec[idx] = make_float2(static_cast<float>(v.x * amp), static_cast<float>(v.y * amp));
+}
+
+// out = coef k^expo in (accumulate = 0) or out += coef k^expo in (accumulate = 1); zero at k = 0 and Nyquist.
+__global__ __launch_bounds__(kNT) void k_png_power(const float2* __restrict__ in, float2* __restrict__ out, int N,
+                                                   int pitch, double kf, double expo, double coef, int accumulate) {
+  const int nh = N / 2 + 1;
+  const int64_t count = static_cast<int64_t>(N) * N * nh;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (e >= count) return;
+  Mode m;
+  mode_of(e, N, nh, &m);
+  const int64_t idx = spec_index(e, nh, pitch);
+  float2 o = make_float2(0.f, 0.f);
+  if (!m.zero) {
+    const double k = kf * sqrt(static_cast<double>(m.nx * m.nx + m.ny * m.ny + m.nz * m.nz));
+    const double f = coef * (expo == 0.0 ? 1.0 : pow(k, expo));
+    const float2 v = in[idx];
+    o = make_float2(static_cast<float>(v.x * f), static_cast<float>(v.y * f));
+  }
+  if (accumulate) {
+    const float2 prev = out[idx];
+    o = make_float2(prev.x + o.x, prev.y + o.y);
+  }
+  out[idx] = o;
+}
+
+__global__ __launch_bounds__(kNT) void k_png_products(PngProducts pp, int64_t count) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (i >= count) return;
+  float acc = 0.f;
+  for (int t = 0; t < pp.n; ++t) acc += pp.c[t] * (pp.fa[t][i] * pp.fb[t][i]);
+  pp.out[i] = acc;
+}
+
+// delta_L_hat = alpha0 k^2 T(k) (phi_hat + fNL NL_hat) into phi_hat's place; zero at k = 0 and Nyquist.
+__global__ __launch_bounds__(kNT) void k_png_to_delta(float2* __restrict__ phi, const float2* __restrict__ nl, int N,
+                                                      int pitch, double kf, double f_nl, double alpha0, double om_h) {
+  const int nh = N / 2 + 1;
+  const int64_t count = static_cast<int64_t>(N) * N * nh;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (e >= count) return;
+  Mode m;
+  mode_of(e, N, nh, &m);
+  const int64_t idx = spec_index(e, nh, pitch);
+  if (m.zero) {
+    phi[idx] = make_float2(0.f, 0.f);
+    return;
+  }
+  const double k = kf * sqrt(static_cast<double>(m.nx * m.nx + m.ny * m.ny + m.nz * m.nz));
+  const double a = alpha0 * k * k * bbks(k, om_h);
+  const float2 p = phi[idx], q = nl[idx];
+  phi[idx] = make_float2(static_cast<float>(a * (p.x + f_nl * q.x)), static_cast<float>(a * (p.y + f_nl * q.y)));
+}
+
 unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kNT - 1) / kNT); }
 
 }  // namespace
@@ -188,6 +263,33 @@ hipError_t ic_source_init(float* a, const float* b, const float* c, int64_t coun
 
 hipError_t ic_sub_square(float* S, const float* d, int64_t count, hipStream_t s) {
   k_ic_sub_square<<<grid_for(count), kNT, 0, s>>>(S, d, count);
+  return hipGetLastError();
+}
+
+hipError_t png_potential(float2* spec, int N, int pitch, double box, double a_phi, double n_s, hipStream_t s) {
+  const int64_t count = static_cast<int64_t>(N) * N * (N / 2 + 1);
+  const double amp_norm = static_cast<double>(N) * N * N / (box * box * box);
+  k_png_potential<<<grid_for(count), kNT, 0, s>>>(spec, N, pitch, 2.0 * M_PI / box, amp_norm, a_phi, n_s);
+  return hipGetLastError();
+}
+
+hipError_t png_power(const float2* in, float2* out, int N, int pitch, double box, double expo, double coef,
+                     bool accumulate, hipStream_t s) {
+  const int64_t count = static_cast<int64_t>(N) * N * (N / 2 + 1);
+  k_png_power<<<grid_for(count), kNT, 0, s>>>(in, out, N, pitch, 2.0 * M_PI / box, expo, coef, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t png_products(const PngProducts& pp, int64_t count, hipStream_t s) {
+  if (pp.n < 1 || pp.n > kPngMaxTerms) return hipErrorInvalidValue;
+  k_png_products<<<grid_for(count), kNT, 0, s>>>(pp, count);
+  return hipGetLastError();
+}
+
+hipError_t png_to_delta(float2* phi, const float2* nl, int N, int pitch, double box, double f_nl, double alpha0,
+                        double omega_m, double h, hipStream_t s) {
+  const int64_t count = static_cast<int64_t>(N) * N * (N / 2 + 1);
+  k_png_to_delta<<<grid_for(count), kNT, 0, s>>>(phi, nl, N, pitch, 2.0 * M_PI / box, f_nl, alpha0, omega_m * h);
   return hipGetLastError();
 }
 

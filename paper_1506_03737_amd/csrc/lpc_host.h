@@ -27,6 +27,8 @@ double partial_drift_factor(const Cosmo& c, double a_i, double a, double a_ip1, 
 // Comoving distance to scale factor a, (c / H0) int_a^1 da / (a^2 E), in Mpc/h.
 constexpr double kCOverH0 = 2997.92458;
 double comoving_distance(const Cosmo& c, double a);
+// g0 = D1(1) / lim_{a->0} D1(a) / a = (5/2) Om int_0^1 da / (a E)^3: the growth suppression of D1(1) = 1.
+double growth_suppression(const Cosmo& c);
 void coefficient_table(const Cosmo& c, bool modified, double n_lpt, const double* a, int n, double* out);
 double pk_amplitude(const Cosmo& c);
 double linear_pk(const Cosmo& c, double amplitude, double k);

@@ -283,6 +283,22 @@ hipError_t ic_spectral_factor(const float2* in, float2* out, int N, int pitch, d
 // S = a*b + a*c + b*c (written into a), then S -= d^2 via ic_sub_square
 hipError_t ic_source_init(float* a, const float* b, const float* c, int64_t count, hipStream_t s);
 hipError_t ic_sub_square(float* S, const float* d, int64_t count, hipStream_t s);
+// Primordial non-Gaussianity (Sec. 5): phi_hat from the noise spectrum; D^s spectral multipliers; the real-space sum
+// of the products of a group of terms; delta_L_hat = alpha0 k^2 T(k) (phi_hat + fNL NL_hat).
+constexpr int kPngMaxTerms = 4;
+struct PngProducts {  // out[i] = sum_t c[t] fa[t][i] fb[t][i]
+  float* out;
+  const float* fa[kPngMaxTerms];
+  const float* fb[kPngMaxTerms];
+  float c[kPngMaxTerms];
+  int n;
+};
+hipError_t png_potential(float2* spec, int N, int pitch, double box, double a_phi, double n_s, hipStream_t s);
+hipError_t png_power(const float2* in, float2* out, int N, int pitch, double box, double expo, double coef,
+                     bool accumulate, hipStream_t s);
+hipError_t png_products(const PngProducts& pp, int64_t count, hipStream_t s);
+hipError_t png_to_delta(float2* phi, const float2* nl, int N, int pitch, double box, double f_nl, double alpha0,
+                        double omega_m, double h, hipStream_t s);
 hipError_t ic_assemble(float* pos, float* vel, int32_t* id, const float* psi1, const float* psi2, int N, double box,
                        float d1, float d2, float f1, float f2, hipStream_t s);
 

@@ -57,6 +57,18 @@ class Lightcone(ctypes.Structure):
 LIGHTCONE_RECORD_FIELDS = 10  # lpc_lightcone_record: 6 floats + a + index + replicate + reserved (4 bytes each)
 
 
+class PngTerm(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double), ("g", ctypes.c_double)]
+
+
+class Png(ctypes.Structure):
+    _fields_ = [("f_nl", ctypes.c_double), ("n_terms", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("terms", PngTerm * 4)]
+
+
+PNG_KINDS = {"local": 0, "equilateral": 1, "orthogonal": 2}
+
+
 class BatchEntry(ctypes.Structure):
     _fields_ = [("geom", Geometry), ("particles", Particles)]
 
@@ -78,6 +90,8 @@ def _load():
     sig = {
         "lpc_workspace_bytes": (sz, [P(Geometry), i32, i64]),
         "lpc_init_ic": (i32, [P(Geometry), P(Cosmology), ctypes.c_uint64, dbl, P(Particles), vp, sz, vp]),
+        "lpc_init_ic_png": (i32, [P(Geometry), P(Cosmology), ctypes.c_uint64, dbl, P(Png), P(Particles), vp, sz, vp]),
+        "lpc_png_preset": (i32, [i32, dbl, P(Png)]),
         "lpc_pm_force": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp, sz, vp]),
         "lpc_pm_force_noalloc": (i32, [P(Geometry), P(Stepping), vp, i64, vp, vp, vp]),
         "lpc_cola_step": (i32, [P(Geometry), P(Cosmology), P(Stepping), P(dbl), i32, P(Particles), vp, sz, vp]),
@@ -120,7 +134,8 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_pm_force", "lpc_pm_force_noalloc", "lpc_cola_step",
+EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_init_ic_png", "lpc_png_preset", "lpc_pm_force",
+            "lpc_pm_force_noalloc", "lpc_cola_step",
             "lpc_cola_step_lightcone", "lpc_comoving_distance",
             "lpc_workspace_bytes_batched",
             "lpc_cola_step_batched", "lpc_graph_enable", "lpc_power_spectrum",
@@ -202,6 +217,25 @@ def lpc_init_ic(geom, cosmo, seed, a_init, particles, ws, stream=None):
     p = particles.c_struct()
     _check(LIB.lpc_init_ic(ctypes.byref(geom), ctypes.byref(cosmo), ctypes.c_uint64(seed), float(a_init),
                            ctypes.byref(p), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def png(f_nl, kind=None, terms=None):
+    """An lpc_png: a preset kind ("local", "equilateral", "orthogonal") or explicit terms [(c, a, b, g), ...]."""
+    p = Png()
+    if kind is not None:
+        _check(LIB.lpc_png_preset(PNG_KINDS[kind], float(f_nl), ctypes.byref(p)))
+        return p
+    p.f_nl = float(f_nl)
+    p.n_terms = len(terms)
+    for t, (c, a, b, g) in enumerate(terms):
+        p.terms[t] = PngTerm(float(c), float(a), float(b), float(g))
+    return p
+
+
+def lpc_init_ic_png(geom, cosmo, seed, a_init, png_params, particles, ws, stream=None):
+    p = particles.c_struct()
+    _check(LIB.lpc_init_ic_png(ctypes.byref(geom), ctypes.byref(cosmo), ctypes.c_uint64(seed), float(a_init),
+                               ctypes.byref(png_params), ctypes.byref(p), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def lpc_pm_force(geom, step, pos, grad_out, ws, density_out=None, stream=None):

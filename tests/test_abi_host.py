@@ -269,3 +269,15 @@ def test_net_entry_points_reject_misaligned_params():
     assert st == -1 and b"16-byte" in lib.lpc_last_error()
     st = lib.lpc_net_loss_grad(16, bad, ok, ok, ok, ctypes.byref(loss), ok, 1 << 20, None)
     assert st == -1 and b"16-byte" in lib.lpc_last_error()
+
+
+def test_png_presets_match_oracle():
+    from oracle import png as opng
+    from paper_1506_03737_amd import lpc
+    for kind, terms in opng.PRESETS.items():
+        p = lpc.png(12.5, kind=kind)
+        assert p.f_nl == 12.5 and p.n_terms == len(terms) and p.reserved == 0
+        got = [(p.terms[t].c, p.terms[t].a, p.terms[t].b, p.terms[t].g) for t in range(p.n_terms)]
+        assert got == [tuple(map(float, t)) for t in terms]
+    with pytest.raises(lpc.LpcError):
+        lpc._check(lpc.LIB.lpc_png_preset(7, 1.0, ctypes.byref(lpc.Png())))
