@@ -1,25 +1,32 @@
 """Throughput benchmark of the PM-COLA time step on one MI355X.
 
 Workload (the single-box configuration): 256^3 particles, 768^3 mesh, 1000 Mpc/h box, 2LPT initial conditions at
-z = 9 from a seeded BBKS Gaussian field (generated on the GPU by lpc_init_ic, untimed), modified COLA stepping with
-nLPT = -2.5, CIC window deconvolved once.
+z = 9 from a seeded BBKS Gaussian field (generated on the GPU by lpc_init_ic, untimed), ten modified-COLA steps
+uniform in a from 0.1 to 1.0 (nLPT = -2.5), CIC window deconvolved once.
 
-A "step" is one COLA time step: drift + full PM force (deposit, r2c FFT, Poisson/gradient, 3 c2r, gather) + kick.
-The timed region is ONE lpc_cola_step call over K + 1 scale factors spaced uniformly from a = 0.1 to 1.0: the opening
-force and half kick, K drift/force/kick iterations and the frame-velocity conversions (K + 1 force evaluations in
-all). value = N^3 * K / wall time (particle-steps/s), inputs resident in HBM before the clock starts.
+A "step" is one COLA time step of that ten-step schedule: drift + full PM force (deposit, r2c FFT, Poisson/gradient,
+3 c2r, gather) + kick. `--steps K` times K steps as repetitions of the schedule: K // 10 full lpc_cola_step calls
+over the 11 scale factors, and, if K is not a multiple of 10, one call over the first K % 10 steps, each started from
+the initial conditions (reset untimed) and bracketed by device synchronisations. value = N^3 K / (sum of the call
+times) in particle-steps/s, inputs resident in HBM. The timed calls record HIP events around every launch on the
+call's stream; those give the per-stage table and the dominant kernel's roofline.
 
-Also reported: the dominant kernel's achieved HBM bandwidth from HIP events recorded on the call's stream
-(roofline), the FP64 CPU oracle's rate on a bounded sample (cpu_baseline), and the batched form on 48 uneven boxes
-(96^3/128^3/160^3 particles, Nm = 2N, L = 300..600 Mpc/h, one lpc_cola_step_batched call replaying its recorded HIP
-graph; aggregate particle-steps/s, in "batched"), and the learned form (a coarse Nm = N run plus the trained
-correction network against the fine Nm = 3N run, with its P(k) error, in "learned").
-
-Before the clock starts, the FFT tile widths of every mesh size measured here are autotuned (paper_1506_03737_amd/
-autotune.py; --no-tune keeps the built-in widths); the widths used are reported in config.fft_tiling.
+Extras in the same JSON line:
+  roofline     the dominant kernel: algorithmic bytes per launch / mean launch time, against the 8 TB/s HBM peak
+               and against a device-to-device copy measured here (copy_peak);
+  batched      48 uneven boxes (96^3/128^3/160^3 particles, Nm = 2N, L = 300..600 Mpc/h), one recorded HIP graph of
+               the ten-step run replayed (aggregate particle-steps/s);
+  learned      coarse Nm = N run plus the trained correction network against the fine Nm = 3N run (ten steps);
+  large        the large single box (512^3 particles, 1024^3 mesh, 2000 Mpc/h), one ten-step call;
+  lightcone    the single box with the on-the-fly lightcone on its last two drifts (observer at a box corner,
+               2 x 2 x 2 replicates) against the same run without it;
+  cpu_baseline the FP64 oracle on the host: the 32^3 / 64^3 / 256 Mpc/h configuration in full on one core and in one
+               process per core, and a two-step sample of the single box at 1/8 volume corrected to the ten-step
+               schedule's force evaluations per step;
+  precision    the GPU against the oracle on that small configuration after ten steps: positions, momenta, P(k).
 
 Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--workload single|small|large] [--no-cpu] [--no-batched]
-                      [--no-learned] [--no-tune] [--tiling-cache PATH]
+                      [--no-learned] [--no-large] [--no-lightcone] [--no-tune] [--tiling-cache PATH]
 """
 import argparse
 import json
@@ -41,7 +48,7 @@ MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 9.25
                     ("fft y", 768, 8): 3.713e9, ("fft z r2c", 768, 16): 3.643e9}
 
 
-def stage_bytes(stage, n_part, nm, ncomp_y=3):
+def stage_bytes(stage, n_part, nm):
     """Algorithmic HBM bytes of one launch of each force-path stage (FP32 mesh, int64 density, SoA particles).
 
     Half spectra are counted at nm * nm * (nm/2 + 1) complex values (8 B each)."""
@@ -61,39 +68,91 @@ def stage_bytes(stage, n_part, nm, ncomp_y=3):
     }.get(stage)
 
 
-def stage_table(stats, n_part, nm, wall_ms):
+def stage_table(stats, n_part, nm, wall_ms, copy_gbs=None):
     stages = {}
     for name, (launches, ms) in stats.items():
         b = stage_bytes(name, n_part, nm)
         avg = ms / launches
         entry = {"launches": launches, "avg_ms": round(avg, 4), "share": round(ms / wall_ms, 4)}
         if b is not None:
-            entry["GB_per_s"] = round(b / (avg * 1e-3) / 1e9, 1)
+            gbs = b / (avg * 1e-3) / 1e9
+            entry["GB_per_s"] = round(gbs, 1)
+            entry["frac_of_8TBs"] = round(gbs / HBM_PEAK_GBS, 4)
+            if copy_gbs:
+                entry["frac_of_copy"] = round(gbs / copy_gbs, 4)
         stages[name] = entry
     return stages
 
 
-def batched_bench(lpc, synth, torch, steps):
-    """The 48-box batched form: ICs per box (untimed), one recording call, then one timed replay of the graph over
-    steps + 1 scale factors. Returns the "batched" object of the JSON line."""
-    import numpy as np
-    dev = torch.device("cuda:0")
+def schedule_runs(k):
+    """Step counts of the calls that make up k steps of the ten-step schedule."""
+    return [10] * (k // 10) + ([k % 10] if k % 10 else [])
+
+
+def timed_schedule(lpc, torch, geom, cosmo, step, a_list, ps, ws, reset, k, profile):
+    """k steps as calls over the ten-step schedule, each reset (untimed) and bracketed by synchronisations; returns
+    the summed call time (s) and, with profile, the per-stage event statistics of the timed calls."""
+    total = 0.0
+    if profile:
+        lpc.lpc_profile_reset()
+        lpc.lpc_profile_enable(True)
+    try:
+        for m in schedule_runs(k):
+            reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lpc.lpc_cola_step(geom, cosmo, step, a_list[: m + 1], ps, ws)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+    finally:
+        if profile:
+            lpc.lpc_profile_enable(False)
+    return total, (lpc.lpc_profile_stats() if profile else None)
+
+
+def copy_peak(torch, nbytes=2 << 30, reps=5):
+    """Device-to-device copy bandwidth (bytes read + written / time), best of `reps` copies of nbytes."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
+def make_ic(lpc, torch, n_side, box, seed, cosmo):
+    n = n_side**3
+    geom = lpc.geometry(n_side, n_side, box)
+    ic = lpc.ParticleSet.empty(n, "cuda")
+    ws = lpc.workspace(geom, lpc.LPC_OP_INIT_IC, "cuda")
+    lpc.lpc_init_ic(geom, cosmo, seed, 0.1, ic, ws)
+    del ws
+    return ic
+
+
+def batched_bench(lpc, synth, torch):
+    """The 48-box batched form over the ten-step schedule: ICs per box (untimed), one recording call, then one timed
+    replay of the graph; per-stage times from one more direct-launch run."""
     cosmo = lpc.cosmology(**synth.COSMOLOGY)
     step = lpc.stepping(**synth.STEPPING)
     boxes = synth.batch_workload()
     ics, sets, entries = [], [], []
     for b in boxes:
-        n = b["n_side"] ** 3
-        geom = lpc.geometry(b["n_side"], b["n_mesh"], b["box"])
-        ic = lpc.ParticleSet.empty(n, dev)
-        ws_ic = lpc.workspace(geom, lpc.LPC_OP_INIT_IC, dev)
-        lpc.lpc_init_ic(geom, cosmo, b["seed"], 0.1, ic, ws_ic)
-        del ws_ic
-        ps = lpc.ParticleSet.empty(n, dev)
+        ic = make_ic(lpc, torch, b["n_side"], b["box"], b["seed"], cosmo)
+        ps = lpc.ParticleSet.empty(b["n_side"] ** 3, "cuda")
         ics.append(ic)
         sets.append(ps)
-        entries.append((geom, ps))
-    ws = lpc.workspace_batched(entries, dev)
+        entries.append((lpc.geometry(b["n_side"], b["n_mesh"], b["box"]), ps))
+    ws = lpc.workspace_batched(entries, "cuda")
     n_total = sum(b["n_side"] ** 3 for b in boxes)
 
     def reset():
@@ -101,7 +160,8 @@ def batched_bench(lpc, synth, torch, steps):
             for k in ("pos", "vel", "psi1", "psi2", "id"):
                 getattr(ps, k).copy_(getattr(ic, k))
 
-    a_list = np.linspace(0.1, 1.0, steps + 1)
+    a_list = synth.A_LIST
+    steps = len(a_list) - 1
     reset()
     lpc.lpc_cola_step_batched(entries, cosmo, step, a_list, ws)  # records the graph (untimed)
     reset()
@@ -110,7 +170,6 @@ def batched_bench(lpc, synth, torch, steps):
     lpc.lpc_cola_step_batched(entries, cosmo, step, a_list, ws)  # replays it
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # per-stage times from one more (direct-launch, event-bracketed) run
     reset()
     lpc.lpc_profile_reset()
     lpc.lpc_profile_enable(True)
@@ -121,7 +180,6 @@ def batched_bench(lpc, synth, torch, steps):
     dt_prof = time.perf_counter() - t1
     lpc.lpc_profile_enable(False)
     stats = lpc.lpc_profile_stats()
-    # algorithmic bytes of a batched launch: the sum over boxes of each box's bytes
     stages = {}
     for name, (launches, ms) in stats.items():
         per = [stage_bytes(name, b["n_side"] ** 3, b["n_mesh"]) for b in boxes]
@@ -133,23 +191,25 @@ def batched_bench(lpc, synth, torch, steps):
     return {"value": n_total * steps / dt, "unit": "particle-steps/s", "ms_per_step": dt * 1e3 / steps,
             "steps": steps, "boxes": len(boxes), "particles": n_total,
             "workload": "48 boxes, N in {96,128,160} cycling, Nm = 2N, L = 300 + 300 j/47 Mpc/h, seeds 1000 + j, "
-                        "2LPT ICs at z=9, modified COLA nLPT=-2.5; one graph replay (graph recorded by an untimed "
-                        "identical call)",
+                        "2LPT ICs at z=9, ten modified-COLA steps nLPT=-2.5; one graph replay (graph recorded by an "
+                        "untimed identical call)",
             "stages_direct_launch": stages}
 
 
-def learned_bench(lpc, synth, torch, steps):
-    """The learned form: a coarse run (Nm = N) plus one network pass, against the fine run (Nm = 3N) it stands in
-    for. Training data: 64 coarse/fine pairs of 128^3 particles in 500 Mpc/h boxes (seeds 5000..5063) made by
-    lpc_cola_step, 8 more held out; 12 epochs of Adam (lr 1e-3 -> 5e-5, cosine), random cube symmetries. Applied to
-    the single-box workload (256^3 particles, 1000 Mpc/h, seed 2015): coarse Nm = 256 + network vs fine Nm = 768.
-    Throughput counts the coarse run and the network pass; P(k) errors are against the fine run, k <= 0.5 h/Mpc."""
+def learned_bench(lpc, synth, torch):
+    """The learned form over the ten-step schedule: a coarse run (Nm = N) plus one network pass, against the fine run
+    (Nm = 3N) it stands in for. Training data: 64 coarse/fine pairs of 128^3 particles in 500 Mpc/h boxes (seeds
+    5000..5063) made by lpc_cola_step, 8 more held out; 12 epochs of Adam (lr 1e-3 -> 5e-5, cosine), random cube
+    symmetries. Applied to the single-box workload (256^3 particles, 1000 Mpc/h, seed 2015): coarse Nm = 256 +
+    network vs fine Nm = 768. Throughput counts the coarse run and the network pass; P(k) errors are against the fine
+    run, k <= 0.5 h/Mpc; Q is the reduced bispectrum error of each against the fine run."""
     import numpy as np
     from paper_1506_03737_amd import learned
     dev = torch.device("cuda:0")
     cosmo = lpc.cosmology(**synth.COSMOLOGY)
     step = lpc.stepping(**synth.STEPPING)
-    a_list = np.linspace(0.1, 1.0, steps + 1)
+    a_list = synth.A_LIST
+    steps = len(a_list) - 1
     n_tr, box_tr = 128, 500.0
     ws = lpc.net_workspace(n_tr, dev)
     t0 = time.perf_counter()
@@ -164,14 +224,9 @@ def learned_bench(lpc, synth, torch, steps):
         lambda: learned.train(train_s, n_tr, epochs=12, lr=1e-3, lr_final=5e-5, seed=3, device=dev))
     net_loss, zero_loss = learned.validation_loss(params, val_s, n_tr, dev)
     del train_s, val_s, ws
-    # apply to the single-box workload
     N, box = 256, 1000.0
     n = N**3
-    geom_ic = lpc.geometry(N, N, box)
-    ic = lpc.ParticleSet.empty(n, dev)
-    ws_ic = lpc.workspace(geom_ic, lpc.LPC_OP_INIT_IC, dev)
-    lpc.lpc_init_ic(geom_ic, cosmo, 2015, 0.1, ic, ws_ic)
-    del ws_ic
+    ic = make_ic(lpc, torch, N, box, 2015, cosmo)
     runs = {}
     for name, nm in (("coarse", N), ("fine", 3 * N)):
         ps = lpc.ParticleSet(*(torch.clone(getattr(ic, k)) for k in ("pos", "vel", "psi1", "psi2", "id")))
@@ -190,32 +245,176 @@ def learned_bench(lpc, synth, torch, steps):
     err = lambda p: float(np.max(np.abs(p[sel] / p_fine[sel] - 1.0)))
     t_learned = runs["coarse"][1] + t_apply
     return {"value": n * steps / t_learned, "unit": "particle-steps/s", "ms_per_step": t_learned * 1e3 / steps,
-            "fine_value": n * steps / runs["fine"][1], "speedup_vs_fine": runs["fine"][1] / t_learned,
+            "steps": steps, "fine_value": n * steps / runs["fine"][1], "speedup_vs_fine": runs["fine"][1] / t_learned,
             "coarse_run_ms": runs["coarse"][1] * 1e3, "net_apply_ms": t_apply * 1e3, "fine_run_ms": runs["fine"][1] * 1e3,
             "pk_max_rel_err_k_le_0.5": {"coarse": err(p_coarse), "coarse+net": err(p_corr)},
             "validation_loss_ratio": net_loss / zero_loss, "train_s": t_train, "pairs_s": t_gen,
-            "workload": "256^3 particles, 1000 Mpc/h, seed 2015: coarse Nm=256 + network vs fine Nm=768; network "
-                        "trained on 64 pairs of 128^3 / 500 Mpc/h (coarse Nm=128, fine Nm=384), 12 epochs"}
+            "workload": "256^3 particles, 1000 Mpc/h, seed 2015, ten steps: coarse Nm=256 + network vs fine Nm=768; "
+                        "network trained on 64 pairs of 128^3 / 500 Mpc/h (coarse Nm=128, fine Nm=384), 12 epochs"}
 
 
-def cpu_baseline_sample():
-    """The FP64 oracle, untuned, on two COLA steps of the single-box workload at 1/8 of its volume: 128^3 particles,
-    384^3 mesh, 500 Mpc/h (same Nm/N = 3 and particle density). Returns particle-steps/s for that sample."""
+def large_bench(lpc, synth, torch, copy_gbs):
+    """The large single box: 512^3 particles, 1024^3 mesh, 2000 Mpc/h, one ten-step call (untimed warm-up call first),
+    with per-stage events."""
+    w = synth.WORKLOADS["large"]
+    cosmo = lpc.cosmology(**synth.COSMOLOGY)
+    step = lpc.stepping(**synth.STEPPING)
+    N, nm, box = w["n_side"], w["n_mesh"], w["box"]
+    n = N**3
+    ic = make_ic(lpc, torch, N, box, w["seed"], cosmo)
+    geom = lpc.geometry(N, nm, box)
+    ps = lpc.ParticleSet.empty(n, "cuda")
+    ws = lpc.workspace(geom, lpc.LPC_OP_COLA_STEP, "cuda")
+
+    def reset():
+        for k in ("pos", "vel", "psi1", "psi2", "id"):
+            getattr(ps, k).copy_(getattr(ic, k))
+
+    timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, 1, False)
+    dt, stats = timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, 10, True)
+    stages = stage_table(stats, n, nm, dt * 1e3, copy_gbs)
+    del ps, ws, ic
+    torch.cuda.empty_cache()
+    return {"value": n * 10 / dt, "unit": "particle-steps/s", "ms_per_step": dt * 1e3 / 10, "steps": 10,
+            "workload": f"large: {N}^3 particles, {nm}^3 mesh, {box:g} Mpc/h, 2LPT ICs at z=9, ten modified-COLA steps",
+            "stages": stages}
+
+
+def lightcone_bench(lpc, synth, torch, ic, geom, ws, n):
+    """The single box with the lightcone on its last two drifts (from a = 0.82, R_L = 623 Mpc/h), observer at a box
+    corner, replicates covering the sphere (2 x 2 x 2): one ten-step call against a plain one."""
+    cosmo = lpc.cosmology(**synth.COSMOLOGY)
+    step = lpc.stepping(**synth.STEPPING)
+    ps = lpc.ParticleSet(*(torch.clone(getattr(ic, k)) for k in ("pos", "vel", "psi1", "psi2", "id")))
+    cap = 24_000_000
+    rec = torch.empty((cap, lpc.LIGHTCONE_RECORD_FIELDS), dtype=torch.float32, device="cuda")
+    lc = lpc.lightcone((0.0, 0.0, 0.0), synth.A_LIST[8], rec, (-1, -1, -1), (0, 0, 0))
+
+    def reset():
+        for k in ("pos", "vel", "psi1", "psi2", "id"):
+            getattr(ps, k).copy_(getattr(ic, k))
+
+    times = {}
+    for name in ("lightcone", "plain"):
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if name == "lightcone":
+            count = lpc.lpc_cola_step_lightcone(geom, cosmo, step, synth.A_LIST, ps, lc, ws)
+        else:
+            lpc.lpc_cola_step(geom, cosmo, step, synth.A_LIST, ps, ws)
+        torch.cuda.synchronize()
+        times[name] = time.perf_counter() - t0
+    del rec, ps
+    torch.cuda.empty_cache()
+    return {"value": n * 10 / times["lightcone"], "unit": "particle-steps/s", "records": count,
+            "run_ms": times["lightcone"] * 1e3, "plain_run_ms": times["plain"] * 1e3,
+            "overhead": times["lightcone"] / times["plain"] - 1.0,
+            "workload": "single box, lightcone on the last two drifts (a >= 0.82), observer at (0, 0, 0), "
+                        "replicates -1..0 per axis"}
+
+
+def _oracle_small_run(_=None):
+    """The oracle's ten-step run of the small configuration (seed 1) from its FP32 initial conditions; returns
+    (seconds, pos, vel, ic32)."""
     import numpy as np
 
     import synth
     from oracle import cola as ocola
     from oracle import ic as oic
+    w = synth.WORKLOADS["small"]
+    init = oic.initial_conditions(w["seed"], w["n_side"], w["box"], synth.A_LIST[0], **synth.COSMOLOGY)
+    ic32 = {k: init[k].astype(np.float32) for k in ("pos", "vel", "psi1", "psi2")}
+    t0 = time.perf_counter()
+    x, v = ocola.cola_run(ic32["pos"], ic32["vel"], ic32["psi1"], ic32["psi2"], synth.A_LIST,
+                          synth.COSMOLOGY["omega_m"], w["n_mesh"], w["box"])
+    return time.perf_counter() - t0, x, v, ic32
+
+
+def cpu_baseline(workers):
+    """The FP64 oracle, untuned, on the host (run before the GPU is touched, so the worker processes are plain forks
+    of a process without a GPU context). Returns (cpu_baseline object, oracle results for the precision object)."""
+    import concurrent.futures
+    import multiprocessing
+    import platform
+
+    import synth
+    from oracle import cola as ocola
+    from oracle import ic as oic
+    from oracle import pm as opm
+    from oracle import spectrum as ospec
+    w = synth.WORKLOADS["small"]
+    n_small = w["n_side"] ** 3
+    t1, x_ref, v_ref, ic32 = _oracle_small_run()
+    ctx = multiprocessing.get_context("fork")
+    t_all0 = time.perf_counter()
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        per = [r[0] for r in ex.map(_oracle_small_run, range(workers))]
+    t_all = time.perf_counter() - t_all0
+    # the single box at 1/8 volume (128^3 particles, 384^3 mesh, 500 Mpc/h): two steps (3 force evaluations, 2 drifts)
+    # and one more force evaluation timed alone, to re-weight to the ten-step schedule's 1.1 forces per step
     n_side, nm, box = 128, 384, 500.0
     init = oic.initial_conditions(7, n_side, box, 0.1, **synth.COSMOLOGY)
     t0 = time.perf_counter()
-    ocola.cola_run(init["pos"], init["vel"], init["psi1"], init["psi2"], [0.1, 0.19, 0.28],
+    ocola.cola_run(init["pos"], init["vel"], init["psi1"], init["psi2"], synth.A_LIST[:3],
                    synth.COSMOLOGY["omega_m"], nm, box)
-    dt = time.perf_counter() - t0
-    # the run above is 2 drifts and 3 force evaluations (the GPU run: 10 drifts, 11 force evaluations)
-    return {"value": 2 * n_side**3 / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"two COLA steps (3 force evaluations + 2 drifts) of the FP64 NumPy oracle, 128^3 particles, "
-                      f"384^3 mesh, 500 Mpc/h (single-box workload at 1/8 volume), {dt:.1f} s, single thread"}
+    t_two = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    opm.pm_force(init["pos"], nm, box, 1)
+    t_force = time.perf_counter() - t0
+    t_rest = max(0.0, (t_two - 3 * t_force) / 2)          # kick + drift per step
+    t_step = 1.1 * t_force + t_rest                         # a step of the ten-step schedule
+    k_ref, p_ref, _ = ospec.power_spectrum(x_ref, w["n_mesh"], w["box"], 0.5, 20)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        model = platform.processor() or "unknown"
+    out = {"value": n_small * 10 / t1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"FP64 NumPy oracle, the small configuration (32^3 particles, 64^3 mesh, 256 Mpc/h) in full: ten "
+                     f"modified-COLA steps in {t1:.2f} s on one core",
+           "all_cores": {"value": n_small * 10 * workers / max(per), "unit": "particle-steps/s",
+                         "processes": workers, "pool_seconds": round(t_all, 2),
+                         "per_process_s": [round(p, 2) for p in per],
+                         "sample": "the same ten-step run in one process per core at once (independent realisations); "
+                                   "rate over the slowest process's stepping time"},
+           "single_box_sample": {"value": n_side**3 / t_step, "unit": "particle-steps/s", "cores": 1,
+                                 "two_step_s": round(t_two, 2), "force_s": round(t_force, 2),
+                                 "sample": "128^3 particles, 384^3 mesh, 500 Mpc/h (the single box at 1/8 volume): two "
+                                           "steps and one force evaluation, re-weighted to 1.1 force evaluations "
+                                           "per step (11 per ten-step run)"},
+           "os_cpu_count": os.cpu_count(), "cpu_model": model}
+    return out, {"x": x_ref, "v": v_ref, "ic32": ic32, "k": k_ref, "pk": p_ref}
+
+
+def precision(lpc, synth, torch, oracle_small):
+    """The GPU's ten-step run of the small configuration against the oracle's, from the same FP32 ICs."""
+    import numpy as np
+    w = synth.WORKLOADS["small"]
+    ic = oracle_small["ic32"]
+    dev = torch.device("cuda:0")
+    ps = lpc.ParticleSet(*(torch.from_numpy(ic[k]).to(dev) for k in ("pos", "vel", "psi1", "psi2")),
+                         id=torch.arange(w["n_side"] ** 3, dtype=torch.int32, device=dev))
+    geom = lpc.geometry(w["n_side"], w["n_mesh"], w["box"])
+    ws = lpc.workspace(geom, lpc.LPC_OP_COLA_STEP, dev)
+    lpc.lpc_cola_step(geom, lpc.cosmology(**synth.COSMOLOGY), lpc.stepping(**synth.STEPPING), synth.A_LIST, ps, ws)
+    x = ps.pos.cpu().numpy().astype(np.float64)
+    v = ps.vel.cpu().numpy().astype(np.float64)
+    box = w["box"]
+    d = x - oracle_small["x"]
+    d -= box * np.round(d / box)
+    dv = v - oracle_small["v"]
+    wsp = lpc.workspace(geom, lpc.LPC_OP_POWER_SPECTRUM, dev, n_particles=w["n_side"] ** 3)
+    _, pk, cnt = lpc.lpc_power_spectrum(geom, ps.pos, 0.5, 20, wsp)
+    sel = cnt > 0
+    return {"workload": "32^3 particles, 64^3 mesh, 256 Mpc/h, seed 1, ten modified-COLA steps from the same FP32 "
+                        "ICs; P(k) in 20 bins to k = 0.5 h/Mpc on the 64^3 mesh",
+            "pos_max_abs_over_L": float(np.abs(d).max() / box), "pos_rms_over_L": float(np.sqrt(np.mean(d**2)) / box),
+            "vel_rms_rel": float(np.sqrt(np.mean(dv**2)) / np.sqrt(np.mean(oracle_small["v"] ** 2))),
+            "pk_max_rel": float(np.abs(pk[sel] / oracle_small["pk"][sel] - 1.0).max())}
 
 
 def main():
@@ -224,9 +423,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single", choices=["single", "small", "large"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and the precision object")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-box batched measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-correction measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the large single-box measurement")
+    ap.add_argument("--no-lightcone", action="store_true", help="skip the lightcone measurement")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT tile widths (no autotuning)")
     ap.add_argument("--tiling-cache", default=None,
                     help="JSON cache of tuned FFT tile widths: applied if present, written with new results")
@@ -236,17 +437,23 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path has no multi-GPU form (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
+    if args.steps < 1:
+        print("--steps must be at least 1", file=sys.stderr)
+        sys.exit(2)
 
     import synth
+    # the CPU baseline first: its worker processes fork a process that has not touched the GPU
+    cpu, oracle_small = None, None
+    if not args.no_cpu:
+        cpu, oracle_small = cpu_baseline(workers=min(os.cpu_count() or 1, 16))
+
+    import torch
+
     from paper_1506_03737_amd import autotune, lpc
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.WORKLOADS[args.workload]
     n_side, nm, box = w["n_side"], w["n_mesh"], w["box"]
-    # FFT tile widths: tuned (untimed) for the single-box mesh and the batched form's meshes
     tune_sizes = [nm]
     if not args.no_batched and args.workload == "single":
         tune_sizes += sorted({b["n_mesh"] for b in synth.batch_workload()})
@@ -268,11 +475,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = copy_peak(torch)
 
-    ic = lpc.ParticleSet.empty(n, dev)
-    ws_ic = lpc.workspace(geom, lpc.LPC_OP_INIT_IC, dev)
-    lpc.lpc_init_ic(geom, cosmo, w["seed"], 0.1, ic, ws_ic)
-    del ws_ic
+    ic = make_ic(lpc, torch, n_side, box, w["seed"], cosmo)
     ps = lpc.ParticleSet.empty(n, dev)
     ws = lpc.workspace(geom, lpc.LPC_OP_COLA_STEP, dev)
 
@@ -281,30 +486,11 @@ def main():
             getattr(ps, k).copy_(getattr(ic, k))
 
     if args.warmup > 0:
-        reset()
-        lpc.lpc_cola_step(geom, cosmo, step, np.linspace(0.1, 1.0, args.warmup + 1), ps, ws)
-    reset()
-    a_list = np.linspace(0.1, 1.0, args.steps + 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lpc.lpc_cola_step(geom, cosmo, step, a_list, ps, ws)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    # the same run again with per-stage HIP events (they add a record between launches, so they stay out of the
-    # timed run above)
-    reset()
-    lpc.lpc_profile_reset()
-    lpc.lpc_profile_enable(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lpc.lpc_cola_step(geom, cosmo, step, a_list, ps, ws)
-    torch.cuda.synchronize()
-    dt_prof = time.perf_counter() - t1
-    lpc.lpc_profile_enable(False)
-    stats = lpc.lpc_profile_stats()
+        timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, args.warmup, False)
+    dt, stats = timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, args.steps, True)
 
     value = n * args.steps / dt
-    stages = stage_table(stats, n, nm, dt_prof * 1e3)
+    stages = stage_table(stats, n, nm, dt * 1e3, copy_gbs)
     dom = max((k for k in stats if stage_bytes(k, n, nm) is not None), key=lambda k: stats[k][1])
     dl, dms = stats[dom]
     dbytes = stage_bytes(dom, n, nm)
@@ -312,29 +498,37 @@ def main():
     width = next((tilings[str(nm)][f] for f, (st, _) in autotune.FIELDS.items() if dom in st), None)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": MEASURED_TRAFFIC.get((dom, nm, width)),
-                "algorithmic_bytes_per_launch": dbytes, "tile_width": width}
+                "algorithmic_bytes_per_launch": dbytes, "tile_width": width, "launches": dl,
+                "mean_launch_ms": round(dms / dl, 4), "copy_peak": round(copy_gbs, 1),
+                "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {n_side}^3 particles, {nm}^3 mesh, {box:g} Mpc/h, 2LPT ICs at z=9, "
-                               f"modified COLA nLPT=-2.5, plain form", "n_side": n_side, "n_mesh": nm, "box": box,
-                   "form": "plain", "force_evaluations": args.steps + 1, "fft_tiling": tilings,
-                   "fft_tiling_source": "built-in" if args.no_tune else "autotuned",
-                   "autotune_s": round(t_tune, 2)},
+                               f"ten modified-COLA steps nLPT=-2.5, plain form", "n_side": n_side, "n_mesh": nm,
+                   "box": box, "form": "plain", "schedule_calls": schedule_runs(args.steps),
+                   "force_evaluations": sum(m + 1 for m in schedule_runs(args.steps)), "fft_tiling": tilings,
+                   "fft_tiling_source": "built-in" if args.no_tune else "autotuned", "autotune_s": round(t_tune, 2)},
         "roofline": roofline,
         "stages": stages,
     }
+    if not args.no_lightcone and args.workload == "single":
+        out["lightcone"] = lightcone_bench(lpc, synth, torch, ic, geom, ws, n)
+    del ps, ws, ic
+    torch.cuda.empty_cache()
     if not args.no_batched and args.workload == "single":
-        del ps, ic, ws
+        out["batched"] = batched_bench(lpc, synth, torch)
         torch.cuda.empty_cache()
-        out["batched"] = batched_bench(lpc, synth, torch, args.steps)
     if not args.no_learned and args.workload == "single":
+        out["learned"] = learned_bench(lpc, synth, torch)
         torch.cuda.empty_cache()
-        out["learned"] = learned_bench(lpc, synth, torch, args.steps)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_sample()
+    if not args.no_large and args.workload == "single":
+        out["large"] = large_bench(lpc, synth, torch, copy_gbs)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        out["precision"] = precision(lpc, synth, torch, oracle_small)
     print(json.dumps(out), flush=True)
 
 
