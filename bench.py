@@ -49,12 +49,29 @@ MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 9.25
 
 
 def stage_bytes(stage, n_part, nm):
-    """Algorithmic HBM bytes of one launch of each force-path stage (FP32 mesh, int64 density, SoA particles).
+    """Algorithmic HBM bytes of one launch of each force-path stage, from per-unit figures: a 1-D transform pass over
+    the mesh moves 8 B per cell (read and write of the half spectrum),
+    and a launch counts each transform it performs; the CIC deposit moves 12 B per particle and 8 B per cell; the
+    gather + kick + drift reads the force mesh (12 B per cell) and 48 B of particle state and writes 24 B (plus the
+    next sort's key and rank, 8 B) per particle."""
+    M = nm**3
+    return {
+        "deposit": 12 * n_part + 8 * M,
+        "fft z r2c": 8 * M,                 # one transform
+        "fft y": 8 * M,                     # one transform
+        "fft x + poisson": 3 * 8 * M,       # forward x, inverse x of the x gradient, inverse x of the potential
+        "fft y inv": 3 * 8 * M,             # x gradient, i k_y psi, psi
+        "fft z c2r": 3 * 8 * M,             # three components
+        "gather kick drift": 80 * n_part + 12 * M,
+        "frame velocity": 48 * n_part,      # read vel, psi1, psi2; write vel
+    }.get(stage)
 
-    Half spectra are counted at nm * nm * (nm/2 + 1) complex values (8 B each)."""
+
+def moved_bytes(stage, n_part, nm):
+    """The bytes each fused kernel must move at least (FP32 mesh and contrast, half spectra of nm nm (nm/2 + 1)
+    complex values): less than stage_bytes where a launch shares loads between transforms."""
     M = nm**3
     H = nm * nm * (nm // 2 + 1) * 8        # bytes of one half-spectrum complex mesh
-    corners = min(M, 8 * n_part)
     return {
         "deposit": 12 * n_part + 4 * M,     # read positions, the FP32 density contrast written once
         "fft z r2c": 4 * M + H,             # read the FP32 contrast, write half spectrum
@@ -62,9 +79,8 @@ def stage_bytes(stage, n_part, nm):
         "fft x + poisson": H + 2 * H,       # read delta_hat, write the x gradient and the potential
         "fft y inv": 2 * H + 3 * H,         # x gradient in place; read the potential, write its y gradient and itself
         "fft z c2r": 3 * H + 12 * M,        # read three spectra, write the AoS float3 force mesh
-        # pos, vel, psi1, psi2 in, vel and pos out, the next sort's key and rank out (on the launches that drift)
-        "gather kick drift": 80 * n_part + 12 * corners,
-        "frame velocity": 48 * n_part,      # read vel, psi1, psi2; write vel
+        "gather kick drift": 80 * n_part + 12 * M,
+        "frame velocity": 48 * n_part,
     }.get(stage)
 
 
@@ -80,6 +96,8 @@ def stage_table(stats, n_part, nm, wall_ms, copy_gbs=None):
             entry["frac_of_8TBs"] = round(gbs / HBM_PEAK_GBS, 4)
             if copy_gbs:
                 entry["frac_of_copy"] = round(gbs / copy_gbs, 4)
+            mb = moved_bytes(name, n_part, nm)
+            entry["moved_GB_per_s"] = round(mb / (avg * 1e-3) / 1e9, 1)
         stages[name] = entry
     return stages
 
@@ -498,7 +516,8 @@ def main():
     width = next((tilings[str(nm)][f] for f, (st, _) in autotune.FIELDS.items() if dom in st), None)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": MEASURED_TRAFFIC.get((dom, nm, width)),
-                "algorithmic_bytes_per_launch": dbytes, "tile_width": width, "launches": dl,
+                "algorithmic_bytes_per_launch": dbytes, "moved_bytes_per_launch": moved_bytes(dom, n, nm),
+                "tile_width": width, "launches": dl,
                 "mean_launch_ms": round(dms / dl, 4), "copy_peak": round(copy_gbs, 1),
                 "frac_of_copy": round(achieved / copy_gbs, 4)}
 

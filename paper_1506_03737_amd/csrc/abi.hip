@@ -140,9 +140,10 @@ struct BoxParts {
 struct SortSpace {
   std::vector<BoxParts> copy[2];
   std::vector<int64_t> pbase;
-  std::vector<int> tbase, nt;
+  std::vector<int> tbase;
+  std::vector<kern::TileGrid> nt;
   int *key = nullptr, *rank = nullptr, *cnt = nullptr, *start = nullptr, *block_sums = nullptr;
-  int G = 0;  // buckets over all boxes (2 nt^3 + 1 each)
+  int G = 0;  // buckets over all boxes (2 tiles + 1 each)
 };
 
 // Lays out the sort space of boxes with particle counts n[] and meshes nm[] from workspace offset `off` (base NULL:
@@ -161,10 +162,10 @@ size_t layout_sort(char* base, size_t off, const std::vector<int64_t>& n, const 
   for (size_t b = 0; b < n.size(); ++b) {
     ss.pbase.push_back(ptot);
     ss.tbase.push_back(G);
-    const int nt = kern::tiles_per_side(nm[b]);
+    const kern::TileGrid nt = kern::tile_grid(nm[b]);
     ss.nt.push_back(nt);
     ptot += n[b];
-    G += 2 * nt * nt * nt + 1;
+    G += 2 * nt.count() + 1;
   }
   for (int c = 0; c < (cola ? 2 : 1); ++c) {
     for (size_t b = 0; b < n.size(); ++b) {
@@ -607,10 +608,10 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     const int nm = b.nm, pitch = kern::mesh_pitch(nm), nh = nm / 2 + 1;
     const int64_t M = static_cast<int64_t>(nm) * nm * nm;
     const double scale = (static_cast<double>(nm) * 65536.0) / b.box;
-    const int nt = ss.nt[ib];
+    const kern::TileGrid nt = ss.nt[ib];
     i_part.push_back(static_cast<int>((b.n + kern::kNT - 1) / kern::kNT));
     i_frame.push_back(static_cast<int>((3 * b.n + kern::kNT - 1) / kern::kNT));
-    i_tile.push_back(nt * nt * nt);
+    i_tile.push_back(nt.count());
     auto sort_job = [&](const BoxParts* src, const BoxParts& dst) {
       kern::SortJob j{};
       if (src) {
@@ -633,7 +634,9 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
       j.n = b.n;
       j.pbase = ss.pbase[ib];
       j.tbase = ss.tbase[ib];
-      j.nt = nt;
+      j.ntx = nt.x;
+      j.nty = nt.y;
+      j.ntz = nt.z;
       j.nm = nm;
       j.scale = scale;
       return j;
@@ -647,7 +650,9 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
       d.n = b.n;
       d.pbase = ss.pbase[ib];
       d.tbase = ss.tbase[ib];
-      d.nt = nt;
+      d.ntx = nt.x;
+      d.nty = nt.y;
+      d.ntz = nt.z;
       d.nm = nm;
       d.scale = scale;
       d.mscale = (static_cast<double>(M) / static_cast<double>(b.n)) * 0x1.0p-48;
@@ -668,7 +673,9 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
       p.scale = scale;
       p.pbase = ss.pbase[ib];
       p.tbase = ss.tbase[ib];
-      p.nt = nt;
+      p.ntx = nt.x;
+      p.nty = nt.y;
+      p.ntz = nt.z;
       pj[c].push_back(p);
       kern::UnsortJob u{};
       u.spos = cp.pos;
@@ -1602,25 +1609,29 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(sums + 2 * n_bins);
     JobPack jp(at(ws, p.jobs));
     const SortSpace ss = sort_space(ws, p, nm, LPC_OP_POWER_SPECTRUM, n);
-    const int nt = ss.nt[0];
+    const kern::TileGrid nt = ss.nt[0];
     kern::SortJob sj{};
     sj.pos = pos;
     sj.dpos = ss.copy[0][0].pos;
     sj.dorig = ss.copy[0][0].orig;
     sj.n = n;
-    sj.nt = nt;
+    sj.ntx = nt.x;
+    sj.nty = nt.y;
+    sj.ntz = nt.z;
     sj.nm = nm;
     sj.scale = (static_cast<double>(nm) * 65536.0) / geom->box;
     const Section sort = jp.add1(sj, static_cast<int>((n + kern::kNT - 1) / kern::kNT));
     kern::DepJob dj{};
     dj.pos = sj.dpos;
     dj.n = n;
-    dj.nt = nt;
+    dj.ntx = nt.x;
+    dj.nty = nt.y;
+    dj.ntz = nt.z;
     dj.nm = nm;
     dj.scale = sj.scale;
     dj.delta = reinterpret_cast<float*>(dens);  // the FP32 contrast, in the density region
     dj.mscale = (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48;
-    const Section dep = jp.add1(dj, nt * nt * nt);
+    const Section dep = jp.add1(dj, nt.count());
     const R2CSections r = add_r2c(jp, dj.delta, false, 0.0, nm, A);
     jp.upload(s);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });

@@ -128,12 +128,18 @@ struct WorkTable {
   int total;
 };
 
-// Mesh tiles of the particle sort and of the tiled deposit: kTile^3 cells (narrower at the end of an axis when
-// kTile does not divide Nm); a box has nt = ceil(Nm / kTile) tiles per side, tile (tx, ty, tz) has index
-// t = (tx nt + ty) nt + tz and two buckets, 2 t (interior) and 2 t + 1 (boundary: the particle's cell is in the
-// tile's last layer along some axis); one extra bucket (2 nt^3) collects particles whose position is unusable.
-constexpr int kTile = 16;
-inline int tiles_per_side(int nm) { return (nm + kTile - 1) / kTile; }
+// Mesh tiles of the particle sort and of the tiled deposit: kTX x kTY x kTZ cells (x, y, z; narrower at the end of
+// an axis they do not divide). 32 cells along z make every row of a tile one 128-byte line of the FP32 density, and
+// kTY kTZ = kNT puts one thread on each (y, z) cell of a tile plane. A box has ntx ny nz = ceil(Nm / kTX),
+// ceil(Nm / kTY), ceil(Nm / kTZ) tiles; tile (tx, ty, tz) has index t = (tx nty + ty) ntz + tz and two buckets, 2 t
+// (interior) and 2 t + 1 (boundary: the particle's cell is in the tile's last layer along some axis); one extra bucket
+// (2 ntx nty ntz) collects particles whose position is unusable.
+constexpr int kTX = 16, kTY = 8, kTZ = 32;
+struct TileGrid {
+  int x, y, z;
+  int count() const { return x * y * z; }
+};
+inline TileGrid tile_grid(int nm) { return TileGrid{(nm + kTX - 1) / kTX, (nm + kTY - 1) / kTY, (nm + kTZ - 1) / kTZ}; }
 
 struct SortJob {        // key pass and scatter of one box: src (SoA [3][n]) -> dst in tile order
   const float* pos;
@@ -147,13 +153,15 @@ struct SortJob {        // key pass and scatter of one box: src (SoA [3][n]) -> 
   float* dpsi2;
   int* dorig;
   int64_t n, pbase;     // particles; first global particle index of the box (key / rank arrays)
-  int tbase, nt, nm;    // first global tile index; tiles per side; mesh size
+  int tbase, nm;        // first global tile index; mesh size
+  int ntx, nty, ntz;    // tiles along x, y, z
   double scale;         // nm 2^16 / box
 };
 struct DepJob {         // tiled deposit of one box from its tile-sorted positions
   const float* pos;
   int64_t n, pbase;
-  int tbase, nt, nm;
+  int tbase, nm;
+  int ntx, nty, ntz;
   double scale;
   uint64_t* dens;       // int64 counts, or NULL
   float* delta;         // FP32 density contrast C mscale - 1, or NULL
@@ -181,7 +189,8 @@ struct PartJob {        // one box's particles and meshes
   float box;
   double scale;         // nm 2^16 / box
   int64_t pbase;        // first global particle index of the box (key / rank arrays of the next sort)
-  int tbase, nt;        // first global tile index of the box; tiles per side
+  int tbase;            // first global tile index of the box
+  int ntx, nty, ntz;    // tiles along x, y, z
 };
 // FFT tables (device, built once per call on the host in FP64 and rounded to FP32): tw = the plan's stage twiddles
 // (Plan1D), roots[k] = exp(-2 pi i k / n) for k <= n / 2 (real-transform split), win[m] = sinc^2(pi m / n) for

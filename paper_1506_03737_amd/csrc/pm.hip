@@ -24,17 +24,29 @@ constexpr uint32_t kOne = 1u << kFracBits;
 constexpr uint32_t kMask = kOne - 1u;
 
 // Fixed-point coordinate of one axis; false if x is not finite or too far outside the box to convert.
+// For a wrapped position, 0 <= x scale < Nm 2^16 <= 2^31, so floor is a 32-bit truncation (one conversion); the
+// 64-bit floor and remainder are only taken for positions outside the box.
 __device__ __forceinline__ bool fixed_coord(float x, double scale, int64_t period, uint32_t* cell, uint32_t* frac) {
   const double xs = static_cast<double>(x) * scale;
-  if (!(fabs(xs) < 4.0e18)) return false;  // also catches NaN
-  int64_t u = static_cast<int64_t>(floor(xs));
-  if (u < 0 || u >= period) {  // positions are normally wrapped already: the 64-bit remainder is rarely needed
-    u %= period;
+  uint32_t u32;
+  if (xs >= 0.0 && xs < static_cast<double>(period)) {
+    u32 = static_cast<uint32_t>(xs);
+  } else {
+    if (!(fabs(xs) < 4.0e18)) return false;  // also catches NaN
+    int64_t u = static_cast<int64_t>(floor(xs)) % period;
     if (u < 0) u += period;
+    u32 = static_cast<uint32_t>(u);
   }
-  *cell = static_cast<uint32_t>(u >> kFracBits);
-  *frac = static_cast<uint32_t>(u) & kMask;
+  *cell = u32 >> kFracBits;
+  *frac = u32 & kMask;
   return true;
+}
+
+// a b for a < 2^33 and b <= 2^16 (a product of two axis weights times a third): one 32 x 32 -> 64 multiply-add for
+// the low word and a 32-bit multiply for the high one.
+__device__ __forceinline__ uint64_t mul_weight(uint64_t a, uint32_t b) {
+  return static_cast<uint64_t>(static_cast<uint32_t>(a)) * b +
+         (static_cast<uint64_t>(static_cast<uint32_t>(a >> 32) * b) << 32);
 }
 
 __device__ __forceinline__ int find_job(const LPC_CONST int* __restrict__ offs, int njob, int w) {
@@ -55,18 +67,22 @@ __global__ __launch_bounds__(kNT) void k_fill_i32(int* __restrict__ p, size_t co
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// Tile sort. A box's mesh is cut into tiles of kTile^3 cells (the last tile of an axis may be narrower); a particle
-// belongs to the tile of its floor cell, and within it to one of two buckets: interior, or boundary when its cell is
-// in the last layer of the tile along any axis (only boundary particles can reach the next tile's cells). Bucket
-// 2 t + boundary; the box's last bucket (2 nt^3) holds particles whose position is unusable.
+// Tile sort. A box's mesh is cut into tiles of kTX x kTY x kTZ cells (the last tile of an axis may be narrower); a
+// particle belongs to the tile of its floor cell, and within it to one of two buckets: interior, or boundary when its
+// cell is in the last layer of the tile along any axis (only boundary particles can reach the next tile's cells).
+// Bucket 2 t + boundary; the box's last bucket (2 ntx nty ntz) holds particles whose position is unusable.
 // Key pass: bucket and rank among the bucket's particles. Scan: bucket starts. Scatter: copy each record to
 // start[bucket] + rank. The order within a bucket is not deterministic, but nothing downstream depends on it: the
 // deposit is integer and the other particle stages act per particle.
 
-__device__ __forceinline__ int bucket_of(uint32_t cx, uint32_t cy, uint32_t cz, int nt, int nm) {
-  const int t = (static_cast<int>(cx / kTile) * nt + static_cast<int>(cy / kTile)) * nt + static_cast<int>(cz / kTile);
-  auto last = [nm](uint32_t c) { return (c % kTile == kTile - 1) || (static_cast<int>(c) == nm - 1); };
-  return 2 * t + ((last(cx) || last(cy) || last(cz)) ? 1 : 0);
+template <class J>
+__device__ __forceinline__ int bucket_of(uint32_t cx, uint32_t cy, uint32_t cz, const J& job) {
+  const int t = (static_cast<int>(cx / kTX) * job.nty + static_cast<int>(cy / kTY)) * job.ntz + static_cast<int>(cz / kTZ);
+  const int nm = job.nm;
+  const bool last = (cx % kTX == kTX - 1) || (cy % kTY == kTY - 1) || (cz % kTZ == kTZ - 1) ||
+                    (static_cast<int>(cx) == nm - 1) || (static_cast<int>(cy) == nm - 1) ||
+                    (static_cast<int>(cz) == nm - 1);
+  return 2 * t + (last ? 1 : 0);
 }
 
 // Rank of each active thread among the threads of its workgroup with the same bucket g, with one counter atomic per
@@ -138,9 +154,9 @@ __global__ __launch_bounds__(kNT) void k_tile_key(const SortJob* __restrict__ jo
       bool ok = true;
 #pragma unroll
       for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], J.scale, period, &c[d], &f[d]);
-      int b = 2 * J.nt * J.nt * J.nt;
+      int b = 2 * J.ntx * J.nty * J.ntz;
       if (ok)
-        b = bucket_of(c[0], c[1], c[2], J.nt, J.nm);
+        b = bucket_of(c[0], c[1], c[2], J);
       else
         atomicOr(flags + kFlagNonfinite, 1);
       g = J.tbase + b;
@@ -262,7 +278,7 @@ __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ job
 // integer weights of the corners that fall inside its tile with 64-bit LDS atomics; and writes every cell of the
 // tile once with plain stores (so the mesh needs no clearing and sees no global atomics). The up to 8 particle
 // ranges are walked as one index space, so a workgroup needs few rounds of loads.
-constexpr int kTileCells = kTile * kTile * kTile;
+constexpr int kTileCells = kTX * kTY * kTZ;
 // A cell's exact count C is a sum of corner weights of at most 2^48 each. With fewer than 2^16 particles reaching a
 // tile, C < 2^64 cannot wrap its 64-bit sum and bit 63 tells whether C >= 2^63 (the headroom of a signed count).
 // A tile reached by 2^16 or more particles also sums the weights' high parts T = sum(w >> 16), which cannot wrap;
@@ -285,20 +301,19 @@ __device__ __forceinline__ void deposit_pass(const TileRanges tr, int tot, LPC_G
   // kUnroll particles per thread per round: all their position loads are issued before any is used
   constexpr int kUnroll = 4;
   for (int q0 = threadIdx.x; q0 < tot; q0 += kUnroll * kNT) {
+    // every load is issued unconditionally (a thread past the end reloads the last particle and skips it below), so
+    // the 3 kUnroll loads go out together instead of one conditional group at a time
     float px[kUnroll][3];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int q = q0 + u * kNT;
-      px[u][0] = px[u][1] = px[u][2] = 0.f;
-      if (q < tot) {
-        int off = tr.rb[0];
+      const int q = min(q0 + u * kNT, tot - 1);
+      int off = tr.rb[0];
 #pragma unroll
-        for (int r = 1; r < 8; ++r)
-          if (r < tr.nr && q >= tr.cum[r]) off = tr.rb[r] - tr.cum[r];
-        const int64_t i = off + q;
+      for (int r = 1; r < 8; ++r)
+        if (r < tr.nr && q >= tr.cum[r]) off = tr.rb[r] - tr.cum[r];
+      const int64_t i = off + q;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) px[u][d] = pos[d * n + i];
-      }
+      for (int d = 0; d < 3; ++d) px[u][d] = pos[d * n + i];
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -308,7 +323,7 @@ __device__ __forceinline__ void deposit_pass(const TileRanges tr, int tot, LPC_G
 #pragma unroll
       for (int d = 0; d < 3; ++d) ok &= fixed_coord(px[u][d], scale, period, &c[d], &f[d]);
       if (!ok) continue;  // cannot happen for a bucketed particle; kept as a guard
-      // corner offsets relative to the tile origin (periodic), in [0, kTile) when inside
+      // corner offsets relative to the tile origin (periodic), in [0, kT*) when inside
       int lx[2], ly[2], lz[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
@@ -320,20 +335,20 @@ __device__ __forceinline__ void deposit_pass(const TileRanges tr, int tot, LPC_G
         ly[a] = cy - y0;
         lz[a] = cz - z0;
       }
-      const uint64_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
+      const uint32_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        if (static_cast<unsigned>(lx[a]) >= static_cast<unsigned>(kTile)) continue;
+        if (static_cast<unsigned>(lx[a]) >= static_cast<unsigned>(kTX)) continue;
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb) {
-          if (static_cast<unsigned>(ly[bb]) >= static_cast<unsigned>(kTile)) continue;
-          const uint64_t wab = wx[a] * wy[bb];
+          if (static_cast<unsigned>(ly[bb]) >= static_cast<unsigned>(kTY)) continue;
+          const uint64_t wab = static_cast<uint64_t>(wx[a]) * wy[bb];  // <= 2^32
 #pragma unroll
           for (int e2 = 0; e2 < 2; ++e2) {
-            if (static_cast<unsigned>(lz[e2]) >= static_cast<unsigned>(kTile)) continue;
-            const uint64_t wt = (wab * wz[e2]) >> shift;
+            if (static_cast<unsigned>(lz[e2]) >= static_cast<unsigned>(kTZ)) continue;
+            const uint64_t wt = mul_weight(wab, wz[e2]) >> shift;
             if (wt != 0)
-              __hip_atomic_fetch_add(&acc[(lx[a] * kTile + ly[bb]) * kTile + lz[e2]],
+              __hip_atomic_fetch_add(&acc[(lx[a] * kTY + ly[bb]) * kTZ + lz[e2]],
                                      static_cast<unsigned long long>(wt), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
           }
@@ -351,33 +366,41 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   if (w >= total) return;
   const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
   const LPC_CONST DepJob& J = to_const(jobs)[jb];
-  const int nt = J.nt, nm = J.nm;
-  // neighbouring tiles (which write the two halves of shared 128-byte lines) run on the same XCD
+  const int ntx = J.ntx, nty = J.nty, ntz = J.ntz, nm = J.nm;
+  // neighbouring tiles (which share the particles of their boundary buckets) run on the same XCD
   const int t = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]);
-  if (t >= nt * nt * nt) return;  // padding item
+  if (t >= ntx * nty * ntz) return;  // padding item
   const int tid = threadIdx.x;
   for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
-  const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
-  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  const int tx = t / (nty * ntz), ty = (t / ntz) % nty, tz = t % ntz;
+  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
   // the particle ranges (local indices, uniform): own tile, then the boundary bucket of each distinct lower
-  // neighbour
+  // neighbour. All sixteen bucket bounds are loaded before any is used (one memory round trip, not eight).
+  const int pbase = static_cast<int>(J.pbase);  // sort positions are int
+  // an axis with one tile has no distinct lower neighbour
+  const bool mx = ntx > 1, my = nty > 1, mz = ntz > 1;
+  int bs[8], es[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int dx = (q >> 2) & 1, dy = (q >> 1) & 1, dz = q & 1;  // 1 = the lower neighbour along that axis
+    const bool use = (mx || !dx) && (my || !dy) && (mz || !dz);
+    const int sx = dx ? (tx + ntx - 1) % ntx : tx, sy = dy ? (ty + nty - 1) % nty : ty, sz = dz ? (tz + ntz - 1) % ntz : tz;
+    const int g = J.tbase + 2 * ((sx * nty + sy) * ntz + sz);
+    bs[q] = use ? start[q == 0 ? g : g + 1] : 0;
+    es[q] = use ? start[g + 2] : 0;
+  }
   int rb[8], cum[9];
   int nr = 0;
   cum[0] = 0;
-  const int pbase = static_cast<int>(J.pbase);  // sort positions are int
-  const int lo = (nt > 1) ? -1 : 0;  // an axis with one tile has no distinct lower neighbour
-  for (int dx = lo; dx <= 0; ++dx) {
-    for (int dy = lo; dy <= 0; ++dy) {
-      for (int dz = lo; dz <= 0; ++dz) {
-        const int sx = (tx + dx + nt) % nt, sy = (ty + dy + nt) % nt, sz = (tz + dz + nt) % nt;
-        const int g = J.tbase + 2 * ((sx * nt + sy) * nt + sz);
-        const bool own = (dx == 0 && dy == 0 && dz == 0);
-        const int b = __builtin_amdgcn_readfirstlane(start[own ? g : g + 1] - pbase);
-        const int e = __builtin_amdgcn_readfirstlane(start[g + 2] - pbase);
-        rb[nr] = b;
-        cum[nr + 1] = cum[nr] + (e - b);
-        ++nr;
-      }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int dx = (q >> 2) & 1, dy = (q >> 1) & 1, dz = q & 1;
+    if ((mx || !dx) && (my || !dy) && (mz || !dz)) {
+      const int b = __builtin_amdgcn_readfirstlane(bs[q] - pbase);
+      const int e = __builtin_amdgcn_readfirstlane(es[q] - pbase);
+      rb[nr] = b;
+      cum[nr + 1] = cum[nr] + (e - b);
+      ++nr;
     }
   }
   const int tot = cum[nr];
@@ -399,34 +422,39 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   LPC_GLOBAL unsigned long long* C = to_global(reinterpret_cast<unsigned long long*>(J.dens));
   LPC_GLOBAL float* D = to_global(J.delta);
   const double mscale = J.mscale;
-  const int wx_ = min(kTile, nm - x0), wy_ = min(kTile, nm - y0), wz_ = min(kTile, nm - z0);
+  const int wx_ = min(kTX, nm - x0), wy_ = min(kTY, nm - y0), wz_ = min(kTZ, nm - z0);
   bool overflow = false;
-  // kNT = kTile^2 threads: thread (j, k) writes its cell of every x-plane i, stepping one plane (nm^2 cells) at a time
-  static_assert(kNT == kTile * kTile, "one thread per (y, z) cell of a tile plane");
-  const int j = tid / kTile, k = tid % kTile;
+  // kNT = kTY kTZ threads: thread (j, k) writes its cell of every x-plane i, stepping one plane (nm^2 cells) at a
+  // time; a wave's store covers two whole 128-byte rows
+  static_assert(kNT == kTY * kTZ, "one thread per (y, z) cell of a tile plane");
+  const int j = tid / kTZ, k = tid % kTZ;
   if (j < wy_ && k < wz_) {
     const size_t plane = static_cast<size_t>(nm) * nm;
     size_t cell = (static_cast<size_t>(x0) * nm + (y0 + j)) * nm + (z0 + k);
 #pragma unroll
-    for (int i = 0; i < kTile; ++i, cell += plane) {
+    for (int i = 0; i < kTX; ++i, cell += plane) {
       if (i >= wx_) break;  // uniform: a narrow last tile along x
       const unsigned long long v = acc[i * kNT + tid];
       overflow |= (v >> 63) != 0;
       if (C) C[cell] = v;
-      if (D) D[cell] = static_cast<float>(static_cast<double>(v) * mscale - 1.0);
+      if (D) {  // v in FP64 (hi 2^32 + lo, rounded once: the correctly rounded conversion), then C mscale - 1
+        const double cv = fma(static_cast<double>(static_cast<uint32_t>(v >> 32)), 4294967296.0,
+                              static_cast<double>(static_cast<uint32_t>(v)));
+        D[cell] = static_cast<float>(cv * mscale - 1.0);
+      }
     }
   }
   if (tot >= kWrapParticles) {  // uniform; rare (a tile reached by 65536 particles or more)
-    unsigned long long S[kTile];
+    unsigned long long S[kTX];
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) S[i] = acc[i * kNT + tid];
+    for (int i = 0; i < kTX; ++i) S[i] = acc[i * kNT + tid];
     __syncthreads();
     for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
     __syncthreads();
     deposit_pass(tr, tot, pos, J.n, J.scale, nm, x0, y0, z0, acc, kFracBits);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kTile; ++i) {
+    for (int i = 0; i < kTX; ++i) {
       const unsigned long long T = acc[i * kNT + tid];
       const unsigned long long R = S[i] - (T << kFracBits);
       overflow |= (T + (R >> kFracBits)) >= (1ull << 47);
@@ -696,9 +724,9 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
         bool ok = true;
 #pragma unroll
         for (int d = 0; d < 3; ++d) ok &= fixed_coord(x[d], J.scale, period, &c[d], &f[d]);
-        int b = 2 * J.nt * J.nt * J.nt;
+        int b = 2 * J.ntx * J.nty * J.ntz;
         if (ok)
-          b = bucket_of(c[0], c[1], c[2], J.nt, J.nm);
+          b = bucket_of(c[0], c[1], c[2], J);
         else
           atomicOr(flags + kFlagNonfinite, 1);
         g = J.tbase + b;
