@@ -47,6 +47,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 9.255e9, ("fft x + poisson", 768, 8): 5.664e9,
                     ("fft y", 768, 8): 3.713e9, ("fft z r2c", 768, 16): 3.643e9}
 
+# Stages run once per force evaluation: their algorithmic bytes are counted per evaluation and spread over its launches
+PER_EVALUATION = ("deposit", "fft z r2c", "fft y", "fft x + poisson", "fft y inv", "fft z c2r", "gather kick drift")
+
 
 def stage_bytes(stage, n_part, nm):
     """Algorithmic HBM bytes of one launch of each force-path stage, from per-unit figures: a 1-D transform pass over
@@ -84,20 +87,28 @@ def moved_bytes(stage, n_part, nm):
     }.get(stage)
 
 
-def stage_table(stats, n_part, nm, wall_ms, copy_gbs=None):
+def launch_share(name, launches, evals):
+    """The fraction of one evaluation's bytes that one launch of a stage moves (1 for a stage launched per call)."""
+    return evals / launches if name in PER_EVALUATION else 1.0
+
+
+def stage_table(stats, n_part, nm, wall_ms, evals, copy_gbs=None):
     stages = {}
     for name, (launches, ms) in stats.items():
         b = stage_bytes(name, n_part, nm)
         avg = ms / launches
         entry = {"launches": launches, "avg_ms": round(avg, 4), "share": round(ms / wall_ms, 4)}
+        if name in PER_EVALUATION:
+            entry["ms_per_evaluation"] = round(ms / evals, 4)
         if b is not None:
-            gbs = b / (avg * 1e-3) / 1e9
+            f = launch_share(name, launches, evals)
+            gbs = b * f / (avg * 1e-3) / 1e9
             entry["GB_per_s"] = round(gbs, 1)
             entry["frac_of_8TBs"] = round(gbs / HBM_PEAK_GBS, 4)
             if copy_gbs:
                 entry["frac_of_copy"] = round(gbs / copy_gbs, 4)
             mb = moved_bytes(name, n_part, nm)
-            entry["moved_GB_per_s"] = round(mb / (avg * 1e-3) / 1e9, 1)
+            entry["moved_GB_per_s"] = round(mb * f / (avg * 1e-3) / 1e9, 1)
         stages[name] = entry
     return stages
 
@@ -290,7 +301,7 @@ def large_bench(lpc, synth, torch, copy_gbs):
 
     timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, 1, False)
     dt, stats = timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, 10, True)
-    stages = stage_table(stats, n, nm, dt * 1e3, copy_gbs)
+    stages = stage_table(stats, n, nm, dt * 1e3, sum(m + 1 for m in schedule_runs(10)), copy_gbs)
     del ps, ws, ic
     torch.cuda.empty_cache()
     return {"value": n * 10 / dt, "unit": "particle-steps/s", "ms_per_step": dt * 1e3 / 10, "steps": 10,
@@ -508,16 +519,18 @@ def main():
     dt, stats = timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, args.steps, True)
 
     value = n * args.steps / dt
-    stages = stage_table(stats, n, nm, dt * 1e3, copy_gbs)
+    evals = sum(m + 1 for m in schedule_runs(args.steps))
+    stages = stage_table(stats, n, nm, dt * 1e3, evals, copy_gbs)
     dom = max((k for k in stats if stage_bytes(k, n, nm) is not None), key=lambda k: stats[k][1])
     dl, dms = stats[dom]
-    dbytes = stage_bytes(dom, n, nm)
+    share = launch_share(dom, dl, evals)
+    dbytes = stage_bytes(dom, n, nm) * share  # per launch
     achieved = dbytes / (dms / dl * 1e-3) / 1e9
     width = next((tilings[str(nm)][f] for f, (st, _) in autotune.FIELDS.items() if dom in st), None)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": MEASURED_TRAFFIC.get((dom, nm, width)),
-                "algorithmic_bytes_per_launch": dbytes, "moved_bytes_per_launch": moved_bytes(dom, n, nm),
-                "tile_width": width, "launches": dl,
+                "algorithmic_bytes_per_launch": round(dbytes), "moved_bytes_per_launch": round(moved_bytes(dom, n, nm) * share),
+                "tile_width": width, "launches": dl, "launches_per_evaluation": round(dl / evals, 3),
                 "mean_launch_ms": round(dms / dl, 4), "copy_peak": round(copy_gbs, 1),
                 "frac_of_copy": round(achieved / copy_gbs, 4)}
 
