@@ -227,11 +227,11 @@ def batched_bench(lpc, synth, torch):
 
 def learned_bench(lpc, synth, torch):
     """The learned form over the ten-step schedule: a coarse run (Nm = N) plus one network pass, against the fine run
-    (Nm = 3N) it stands in for. Training data: 64 coarse/fine pairs of 128^3 particles in 500 Mpc/h boxes (seeds
-    5000..5063) made by lpc_cola_step, 8 more held out; 12 epochs of Adam (lr 1e-3 -> 5e-5, cosine), random cube
-    symmetries. Applied to the single-box workload (256^3 particles, 1000 Mpc/h, seed 2015): coarse Nm = 256 +
-    network vs fine Nm = 768. Throughput counts the coarse run and the network pass; P(k) errors are against the fine
-    run, k <= 0.5 h/Mpc; Q is the reduced bispectrum error of each against the fine run."""
+    (Nm = 3N) it stands in for. Training data: 256 coarse/fine pairs of 128^3 particles in 500 Mpc/h boxes (seeds
+    5000..5255) made by lpc_cola_step, 8 more held out (seeds 6000..6007); 24 epochs of Adam (lr 1e-3 -> 5e-5,
+    cosine), random cube symmetries; the output gain calibrated on the held-out pairs' P(k). Applied to the single-box
+    workload (256^3 particles, 1000 Mpc/h, seed 2015): coarse Nm = 256 + network vs fine Nm = 768. Throughput counts
+    the coarse run and the network pass; P(k) errors are against the fine run, k <= 0.5 h/Mpc."""
     import numpy as np
     from paper_1506_03737_amd import learned
     dev = torch.device("cuda:0")
@@ -239,20 +239,9 @@ def learned_bench(lpc, synth, torch):
     step = lpc.stepping(**synth.STEPPING)
     a_list = synth.A_LIST
     steps = len(a_list) - 1
-    n_tr, box_tr = 128, 500.0
-    ws = lpc.net_workspace(n_tr, dev)
-    t0 = time.perf_counter()
-    train_s, val_s = [], []
-    for seed in range(5000, 5072):
-        c, f = learned.run_pair(seed, n_tr, box_tr, a_list, cosmo, step, dev)
-        (train_s if seed < 5064 else val_s).append(learned.pair_grids(c, f, n_tr, box_tr, ws, dev))
-        del c, f
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t0
-    (params, hist), t_train = learned.timed(
-        lambda: learned.train(train_s, n_tr, epochs=12, lr=1e-3, lr_final=5e-5, seed=3, device=dev))
-    net_loss, zero_loss = learned.validation_loss(params, val_s, n_tr, dev)
-    del train_s, val_s, ws
+    fit = learned.fit_correction(range(5000, 5256), range(6000, 6008), 128, 500.0, a_list, cosmo, step, dev,
+                                 epochs=24)
+    params = fit["params"]
     N, box = 256, 1000.0
     n = N**3
     ic = make_ic(lpc, torch, N, box, 2015, cosmo)
@@ -267,19 +256,29 @@ def learned_bench(lpc, synth, torch):
     corrected = lpc.ParticleSet(torch.clone(runs["coarse"][0].pos), None, ic.psi1, None, ic.id)
     ws_net = lpc.net_workspace(N, dev)
     _, t_apply = learned.timed(lambda: lpc.lpc_net_apply(lpc.geometry(N, N, box), params, corrected, ws_net))
-    k, p_fine, cnt = learned.power_spectrum(runs["fine"][0].pos, n, box, dev)
-    _, p_coarse, _ = learned.power_spectrum(runs["coarse"][0].pos, n, box, dev)
-    _, p_corr, _ = learned.power_spectrum(corrected.pos, n, box, dev)
-    sel = (k <= 0.5) & (cnt > 0)
-    err = lambda p: float(np.max(np.abs(p[sel] / p_fine[sel] - 1.0)))
+    fine = runs["fine"][0].pos
     t_learned = runs["coarse"][1] + t_apply
+    # reduced bispectrum (128^3 estimator mesh, shells of 3 kf): equilateral and k2 = 2 k1 triangles
+    tri = [(0.05, 0.05, 0.05), (0.1, 0.1, 0.1), (0.2, 0.2, 0.2), (0.3, 0.3, 0.3), (0.1, 0.2, 0.15), (0.1, 0.2, 0.25)]
+    gq = lpc.geometry(0, 128, box)
+    wsq = lpc.workspace(gq, lpc.LPC_OP_BISPECTRUM, dev, n_particles=n)
+    q = {name: lpc.lpc_bispectrum(gq, pos, tri, 3 * 2 * np.pi / box, wsq)[1]
+         for name, pos in (("fine", fine), ("coarse", runs["coarse"][0].pos), ("coarse+net", corrected.pos))}
+    del wsq
     return {"value": n * steps / t_learned, "unit": "particle-steps/s", "ms_per_step": t_learned * 1e3 / steps,
             "steps": steps, "fine_value": n * steps / runs["fine"][1], "speedup_vs_fine": runs["fine"][1] / t_learned,
             "coarse_run_ms": runs["coarse"][1] * 1e3, "net_apply_ms": t_apply * 1e3, "fine_run_ms": runs["fine"][1] * 1e3,
-            "pk_max_rel_err_k_le_0.5": {"coarse": err(p_coarse), "coarse+net": err(p_corr)},
-            "validation_loss_ratio": net_loss / zero_loss, "train_s": t_train, "pairs_s": t_gen,
+            "pk_max_rel_err_k_le_0.5": {"coarse": learned.pk_max_error(runs["coarse"][0].pos, fine, n, box, dev),
+                                        "coarse+net": learned.pk_max_error(corrected.pos, fine, n, box, dev)},
+            "q_rel_err": {name: [round(float(abs(a / b - 1.0)), 5) for a, b in zip(q[name], q["fine"])]
+                          for name in ("coarse", "coarse+net")},
+            "q_triangles": tri, "q_fine": [round(float(x), 5) for x in q["fine"]],
+            "output_gain": fit["gain"], "held_out_pk_err_by_gain": fit["gain_errors"],
+            "validation_loss_ratio": fit["validation_loss_ratio"], "train_s": fit["train_s"],
+            "pairs_s": fit["pairs_s"], "calibrate_s": fit["calibrate_s"],
             "workload": "256^3 particles, 1000 Mpc/h, seed 2015, ten steps: coarse Nm=256 + network vs fine Nm=768; "
-                        "network trained on 64 pairs of 128^3 / 500 Mpc/h (coarse Nm=128, fine Nm=384), 12 epochs"}
+                        "network trained on 256 pairs of 128^3 / 500 Mpc/h (coarse Nm=128, fine Nm=384), 24 epochs, "
+                        "output gain calibrated on 8 held-out pairs"}
 
 
 def large_bench(lpc, synth, torch, copy_gbs):

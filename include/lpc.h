@@ -86,14 +86,15 @@ enum {
   LPC_OP_PM_FORCE = 2,
   LPC_OP_COLA_STEP = 3,
   LPC_OP_POWER_SPECTRUM = 4,
-  LPC_OP_FFT = 5
+  LPC_OP_FFT = 5,
+  LPC_OP_BISPECTRUM = 6
 };
 
 /* Number of columns of the per-time coefficient table written by lpc_cola_coefficients. */
 #define LPC_COEF_COLUMNS 12
 
 /* Workspace bytes needed by operation `op` for this geometry and n_particles particles (0 on an invalid geometry,
- * op or count). PM_FORCE, COLA_STEP and POWER_SPECTRUM need 1 <= n_particles <= 2^31 - 1: their workspace holds
+ * op or count). PM_FORCE, COLA_STEP, POWER_SPECTRUM and BISPECTRUM need 1 <= n_particles <= 2^31 - 1: their workspace holds
  * tile-sorted copies of the particles (about 16 B per particle for a force or spectrum, 112 B for a COLA run) next
  * to the meshes; INIT_IC and FFT ignore n_particles. */
 size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op, int64_t n_particles);
@@ -269,6 +270,21 @@ lpc_status lpc_graph_enable(int32_t on);
 lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_t n, double k_max, int32_t n_bins,
                               double* k_mean, double* pk, int64_t* n_modes, void* ws, size_t ws_bytes, void* stream);
 
+/* Reduced bispectrum Q(k1, k2, k3) of the particles (periodic box; the three-point statistic of Sec. 7.2), by the
+ * FFT shell estimator: the density spectrum of lpc_power_spectrum with one CIC window removed (delta_hat / W); shell
+ * b = {modes with k_b - dk/2 <= |k| < k_b + dk/2}; for each triangle, F_i(x) = sum over shell i of delta_hat e^{ikx}
+ * and I_i(x) = sum over shell i of e^{ikx} (inverse transforms), then
+ *   B = L^6 / Nm^9 * sum_x F1 F2 F3 / sum_x I1 I2 I3   (the mean of delta_hat1 delta_hat2 delta_hat3 over the closed
+ *       triangles n1 + n2 + n3 = 0 with n_i in shell i, in continuous normalisation),
+ *   P_i = L^3 / Nm^6 * mean over shell i of |delta_hat / W|^2,   Q = B / (P1 P2 + P2 P3 + P3 P1).
+ * No shot-noise subtraction. k123 (HOST, [m][3], h/Mpc, each > 0) are the shell centres of m <= 256 triangles;
+ * B and Q (HOST, [m]) receive the results (NaN where no triangle closes: sum_x I1 I2 I3, which is Nm^3 times the
+ * number of closed triangles, below Nm^3 / 2), P (HOST, [m][3], or NULL) the shell
+ * powers. Sums are FP64, reduced in a fixed order (bitwise repeatable). Workspace: lpc_workspace_bytes(geom,
+ * LPC_OP_BISPECTRUM, n), geom->n_mesh the estimator mesh. */
+lpc_status lpc_bispectrum(const lpc_geometry* geom, const float* pos, int64_t n, const double* k123, int32_t m,
+                          double dk, double* B, double* Q, double* P, void* ws, size_t ws_bytes, void* stream);
+
 /* The FP64 per-time coefficient table of one lpc_cola_step call (host only; for checking and inspection).
  * out[n_a][LPC_COEF_COLUMNS] row i: a_i, D1, D2, dD1/da, dD2/da, E, K_i (kick factor), Q_i (drift factor, 0 in the
  * last row), D1(a_{i+1}) - D1(a_i), D2(a_{i+1}) - D2(a_i) (0 in the last row), a^3 E D1', a^3 E D2'. */
@@ -368,6 +384,22 @@ lpc_status lpc_net_loss_grad(int32_t n_side, const float* params, const float* f
 /* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step counts from 1) on the
  * device vectors params, m, v with gradient grad. */
 lpc_status lpc_net_adam(float* params, float* m, float* v, const float* grad, int64_t step, float lr, void* stream);
+
+/* Scales the network's output in place: the output layer (the last, linear layer: its weights and biases) of the
+ * device parameter vector params is multiplied by gain, so network(x) becomes gain network(x) up to the BF16 rounding
+ * of the scaled weights. Used to calibrate a trained correction against the statistic it is judged by (the trainer
+ * picks gain on held-out pairs). Asynchronous on `stream`; LPC_ERR_INVALID_ARG for a NULL or misaligned params or a
+ * non-finite gain. */
+lpc_status lpc_net_scale_output(float* params, float gain, void* stream);
+
+/* Training-data augmentation: out = the k-th (0..47) symmetry of the periodic cube applied to a lattice field of
+ * 3-vectors, in and out FP32 [n_side^3][channels] (channels = 3 m: m vectors per site, e.g. 6 for an input grid, 3
+ * for a target grid; device pointers that must not overlap). k = 8 p + f maps space by x'_d = x_{perm[d]} with perm
+ * the p-th of (0 1 2), (0 2 1), (1 0 2), (1 2 0), (2 0 1), (2 1 0), then reflects axis d (x'_d -> L - x'_d, lattice
+ * site i -> n_side - 1 - i) for each bit d of f; a vector v at site u moves to the image site as v'_d = +-v_{perm[d]}
+ * (minus on a reflected axis). The equations of motion are invariant under these maps, so a pair of runs maps to
+ * a valid pair. Asynchronous on `stream`; LPC_ERR_INVALID_ARG for k, channels or n_side out of range, or overlap. */
+lpc_status lpc_net_symmetry(int32_t n_side, int32_t k, int32_t channels, const float* in, float* out, void* stream);
 
 /* Corrects a coarse run in place: pos += network(input grid(pos, psi1, id)) L / N, wrapped into [0, L). inout->n must
  * be n_side^3 (one particle per lattice site); only pos, psi1 and id are used. */

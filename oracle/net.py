@@ -255,3 +255,29 @@ def displacement_grid(pos, ids, n_side, box, ref=None):
     grid = np.zeros((3, n_side**3))
     grid[:, ids] = d / dp
     return grid.reshape(3, n_side, n_side, n_side)
+
+
+# --- training-data augmentation -------------------------------------------------------------------------------------
+
+# Axis permutations of the cube's symmetries: symmetry k = 8 p + f takes permutation PERMS[p] and reflection bits f
+PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def cube_symmetry(grid, k):
+    """The k-th (0..47) symmetry of the periodic cube applied to a lattice field of 3-vectors, channels-first
+    (3 m, N, N, N). The map of space: x'_d = x_{perm[d]}, then for each bit d of f the reflection x'_d -> L - x'_d
+    about the box centre, which takes lattice site i (point (i + 1/2) L / N) to N - 1 - i. A vector v at site u goes to
+    site T(u) as v'_d = +-v_{perm[d]} (minus for a reflected axis d)."""
+    grid = np.asarray(grid)
+    perm, f = PERMS[k // 8], k % 8
+    n = grid.shape[1]
+    out = np.empty_like(grid)
+    o = np.indices((n, n, n))                      # output site coordinates o_d
+    src = [None] * 3
+    for d in range(3):
+        src[perm[d]] = (n - 1 - o[d]) if (f >> d) & 1 else o[d]   # input coordinate along axis perm[d]
+    for c in range(grid.shape[0]):
+        d = c % 3
+        sign = -1.0 if (f >> d) & 1 else 1.0
+        out[c] = sign * grid[3 * (c // 3) + perm[d]][src[0], src[1], src[2]]
+    return out

@@ -195,7 +195,13 @@ size_t layout_sort(char* base, size_t off, const std::vector<int64_t>& n, const 
 // the sort space, every region 256-byte aligned.
 struct Plan {
   size_t flags = 0, jobs = 0, dens = 0, A = 0, B = 0, C = 0, bins = 0, sort = 0, total = 0;
+  size_t fields = 0;  // three real meshes (bispectrum)
 };
+
+// Triangles per lpc_bispectrum call (their partial sums share one workspace region)
+constexpr int kMaxTriangles = 256;
+// FP64 partial sums per triangle: the filtered and indicator triple sums, the three shells' power and mode counts
+constexpr int kPartsPerTriangle = 8;
 
 Plan make_ws_plan(int n, int op, int64_t np) {
   Plan p;
@@ -226,12 +232,19 @@ Plan make_ws_plan(int n, int op, int64_t np) {
       p.A = take(cbytes);
       p.bins = take(static_cast<size_t>(2048) * 3 * sizeof(double));
       break;
+    case LPC_OP_BISPECTRUM:
+      p.dens = take(M * 8);
+      p.A = take(cbytes);  // delta_hat
+      p.B = take(cbytes);  // a shell-filtered spectrum, consumed by its inverse transform
+      p.fields = take(M * 3 * sizeof(float));
+      p.bins = take(static_cast<size_t>(kMaxTriangles) * kPartsPerTriangle * kern::sum_blocks() * sizeof(double));
+      break;
     case LPC_OP_FFT:
       break;
     default:
       return Plan{};
   }
-  if (op == LPC_OP_PM_FORCE || op == LPC_OP_COLA_STEP || op == LPC_OP_POWER_SPECTRUM) {
+  if (op == LPC_OP_PM_FORCE || op == LPC_OP_COLA_STEP || op == LPC_OP_POWER_SPECTRUM || op == LPC_OP_BISPECTRUM) {
     p.sort = off;
     off = layout_sort(nullptr, off, {np}, {n}, op == LPC_OP_COLA_STEP, nullptr);
   }
@@ -983,7 +996,8 @@ size_t lpc_workspace_bytes(const lpc_geometry* geom, int32_t op, int64_t n_parti
   if (!geom) return 0;
   const int n = (op == LPC_OP_INIT_IC) ? geom->n_side : geom->n_mesh;
   if (!fft_size_ok(n)) return 0;
-  const bool takes_particles = (op == LPC_OP_PM_FORCE || op == LPC_OP_COLA_STEP || op == LPC_OP_POWER_SPECTRUM);
+  const bool takes_particles = (op == LPC_OP_PM_FORCE || op == LPC_OP_COLA_STEP || op == LPC_OP_POWER_SPECTRUM ||
+                                op == LPC_OP_BISPECTRUM);
   if (takes_particles && (n_particles < 1 || n_particles > (int64_t(1) << 31) - 1)) return 0;
   return make_ws_plan(n, op, n_particles).total;
 }
@@ -1576,6 +1590,59 @@ lpc_status init_ic_impl(const lpc_geometry* geom, const lpc_cosmology* cosmo, ui
 
 }  // namespace
 
+namespace {
+
+// Tile sort, fixed-point deposit (FP32 contrast in the density region) and forward r2c into A: the density
+// spectrum of a statistic's particles, on workspace plan p of operation op.
+struct DensitySpectrum {
+  SortSpace ss;
+  Section sort, dep;
+  R2CSections r;
+};
+
+DensitySpectrum add_density_spectrum(JobPack& jp, void* ws, const Plan& p, const lpc_geometry* geom, const float* pos,
+                                     int64_t n, int op, float2* A) {
+  DensitySpectrum d;
+  const int nm = geom->n_mesh;
+  const int64_t M = static_cast<int64_t>(nm) * nm * nm;
+  d.ss = sort_space(ws, p, nm, op, n);
+  const kern::TileGrid nt = d.ss.nt[0];
+  kern::SortJob sj{};
+  sj.pos = pos;
+  sj.dpos = d.ss.copy[0][0].pos;
+  sj.dorig = d.ss.copy[0][0].orig;
+  sj.n = n;
+  sj.ntx = nt.x;
+  sj.nty = nt.y;
+  sj.ntz = nt.z;
+  sj.nm = nm;
+  sj.scale = (static_cast<double>(nm) * 65536.0) / geom->box;
+  d.sort = jp.add1(sj, static_cast<int>((n + kern::kNT - 1) / kern::kNT));
+  kern::DepJob dj{};
+  dj.pos = sj.dpos;
+  dj.n = n;
+  dj.ntx = nt.x;
+  dj.nty = nt.y;
+  dj.ntz = nt.z;
+  dj.nm = nm;
+  dj.scale = sj.scale;
+  dj.delta = reinterpret_cast<float*>(at(ws, p.dens));  // the FP32 contrast, in the density region
+  dj.mscale = (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48;
+  d.dep = jp.add1(dj, nt.count());
+  d.r = add_r2c(jp, dj.delta, false, 0.0, nm, A);
+  return d;
+}
+
+void run_density_spectrum(const JobPack& jp, const DensitySpectrum& d, int* flags, hipStream_t s) {
+  run_sort(jp, d.ss, d.sort, flags, s);
+  stage("deposit", s, [&] {
+    return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(d.dep), jp.table(d.dep), d.ss.start, flags, s);
+  });
+  run_r2c(jp, d.r, false, flags, s);
+}
+
+}  // namespace
+
 extern "C" {
 
 lpc_status lpc_init_ic(const lpc_geometry* geom, const lpc_cosmology* cosmo, uint64_t seed, double a_init,
@@ -1603,46 +1670,17 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
     const int nm = geom->n_mesh, pitch = kern::mesh_pitch(nm);
     const int64_t M = static_cast<int64_t>(nm) * nm * nm;
     int* flags = reinterpret_cast<int*>(ws);
-    uint64_t* dens = reinterpret_cast<uint64_t*>(at(ws, p.dens));
     float2* A = reinterpret_cast<float2*>(at(ws, p.A));
     double* sums = reinterpret_cast<double*>(at(ws, p.bins));
     unsigned long long* counts = reinterpret_cast<unsigned long long*>(sums + 2 * n_bins);
     JobPack jp(at(ws, p.jobs));
-    const SortSpace ss = sort_space(ws, p, nm, LPC_OP_POWER_SPECTRUM, n);
-    const kern::TileGrid nt = ss.nt[0];
-    kern::SortJob sj{};
-    sj.pos = pos;
-    sj.dpos = ss.copy[0][0].pos;
-    sj.dorig = ss.copy[0][0].orig;
-    sj.n = n;
-    sj.ntx = nt.x;
-    sj.nty = nt.y;
-    sj.ntz = nt.z;
-    sj.nm = nm;
-    sj.scale = (static_cast<double>(nm) * 65536.0) / geom->box;
-    const Section sort = jp.add1(sj, static_cast<int>((n + kern::kNT - 1) / kern::kNT));
-    kern::DepJob dj{};
-    dj.pos = sj.dpos;
-    dj.n = n;
-    dj.ntx = nt.x;
-    dj.nty = nt.y;
-    dj.ntz = nt.z;
-    dj.nm = nm;
-    dj.scale = sj.scale;
-    dj.delta = reinterpret_cast<float*>(dens);  // the FP32 contrast, in the density region
-    dj.mscale = (static_cast<double>(M) / static_cast<double>(n)) * 0x1.0p-48;
-    const Section dep = jp.add1(dj, nt.count());
-    const R2CSections r = add_r2c(jp, dj.delta, false, 0.0, nm, A);
+    const DensitySpectrum ds = add_density_spectrum(jp, ws, p, geom, pos, n, LPC_OP_POWER_SPECTRUM, A);
     jp.upload(s);
     stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
     stage("clear bins", s, [&] {
       return kern::fill_i32(reinterpret_cast<int*>(sums), static_cast<size_t>(6) * n_bins, 0, s);
     });
-    run_sort(jp, ss, sort, flags, s);
-    stage("deposit", s, [&] {
-      return kern::launch_deposit_tiles(jp.jobs<kern::DepJob>(dep), jp.table(dep), ss.start, flags, s);
-    });
-    run_r2c(jp, r, false, flags, s);
+    run_density_spectrum(jp, ds, flags, s);
     const double V = geom->box * geom->box * geom->box;
     const double pscale = V / (static_cast<double>(M) * static_cast<double>(M));
     stage("pk bin", s, [&] { return kern::pk_bin(A, nm, pitch, geom->box, k_max, n_bins, pscale, sums, counts, s); });
@@ -1659,6 +1697,78 @@ lpc_status lpc_power_spectrum(const lpc_geometry* geom, const float* pos, int64_
         k_mean[b] = hs[2 * b] / static_cast<double>(hc[b]);
         pk[b] = hs[2 * b + 1] / static_cast<double>(hc[b]);
       }
+    }
+    return LPC_OK;
+  });
+}
+
+lpc_status lpc_bispectrum(const lpc_geometry* geom, const float* pos, int64_t n, const double* k123, int32_t m,
+                          double dk, double* B, double* Q, double* P, void* ws, size_t ws_bytes, void* stream) {
+  if (lpc_status st = check_geom_mesh(geom)) return st;
+  if (n <= 0 || n > (int64_t(1) << 31) - 1) return fail(LPC_ERR_INVALID_ARG, "n must be in [1, 2^31 - 1]");
+  if (!pos || !k123 || !B || !Q) return fail(LPC_ERR_INVALID_ARG, "NULL array");
+  if (m < 1 || m > kMaxTriangles) return fail(LPC_ERR_INVALID_ARG, "m must be in [1, %d]", kMaxTriangles);
+  if (!(dk > 0.0) || !std::isfinite(dk)) return fail(LPC_ERR_INVALID_ARG, "dk must be positive");
+  for (int t = 0; t < 3 * m; ++t)
+    if (!(k123[t] > 0.0) || !std::isfinite(k123[t])) return fail(LPC_ERR_INVALID_ARG, "shell centres must be positive");
+  const Plan p = make_ws_plan(geom->n_mesh, LPC_OP_BISPECTRUM, n);
+  if (lpc_status st = check_ws(ws, ws_bytes, p.total)) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() {
+    const int nm = geom->n_mesh, pitch = kern::mesh_pitch(nm);
+    const int64_t M = static_cast<int64_t>(nm) * nm * nm;
+    const double box = geom->box;
+    int* flags = reinterpret_cast<int*>(ws);
+    float2* A = reinterpret_cast<float2*>(at(ws, p.A));
+    float2* H = reinterpret_cast<float2*>(at(ws, p.B));
+    float* F[3];
+    for (int i = 0; i < 3; ++i) F[i] = reinterpret_cast<float*>(at(ws, p.fields)) + i * M;
+    double* parts = reinterpret_cast<double*>(at(ws, p.bins));
+    const int nb = kern::sum_blocks();
+    JobPack jp(at(ws, p.jobs));
+    const DensitySpectrum ds = add_density_spectrum(jp, ws, p, geom, pos, n, LPC_OP_BISPECTRUM, A);
+    // the unnormalised inverse transform of H into each of the three real meshes (H is consumed each time)
+    const C2RSections inv[3] = {add_c2r(jp, H, nm, F[0], 1.f), add_c2r(jp, H, nm, F[1], 1.f),
+                                add_c2r(jp, H, nm, F[2], 1.f)};
+    jp.upload(s);
+    stage("clear flags", s, [&] { return kern::fill_i32(flags, kern::kNumFlags, 0, s); });
+    run_density_spectrum(jp, ds, flags, s);
+    for (int t = 0; t < m; ++t) {
+      double* pt = parts + static_cast<size_t>(t) * kPartsPerTriangle * nb;
+      for (int ind = 0; ind < 2; ++ind) {  // shell-filtered fields, then the shell indicators
+        for (int i = 0; i < 3; ++i) {
+          const double kc = k123[3 * t + i];
+          stage("shell fill", s, [&] {
+            return kern::shell_fill(A, H, nm, pitch, box, kc - 0.5 * dk, kc + 0.5 * dk, ind == 1, s);
+          });
+          run_c2r(jp, inv[i], s);
+        }
+        stage("triple sum", s, [&] { return kern::triple_sum(F[0], F[1], F[2], M, pt + ind * nb, s); });
+      }
+      for (int i = 0; i < 3; ++i) {
+        const double kc = k123[3 * t + i];
+        stage("shell power", s, [&] {
+          return kern::shell_power(A, nm, pitch, box, kc - 0.5 * dk, kc + 0.5 * dk, pt + (2 + 2 * i) * nb,
+                                   pt + (3 + 2 * i) * nb, s);
+        });
+      }
+    }
+    std::vector<double> hp(static_cast<size_t>(m) * kPartsPerTriangle * nb);
+    check(hipMemcpyAsync(hp.data(), parts, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s), "copy sums");
+    lpc_status st = finish(flags, s);
+    if (st != LPC_OK) return st;
+    const double V = box * box * box, Md = static_cast<double>(M);
+    for (int t = 0; t < m; ++t) {
+      double sum[kPartsPerTriangle] = {};
+      for (int q = 0; q < kPartsPerTriangle; ++q)
+        for (int b = 0; b < nb; ++b) sum[q] += hp[(static_cast<size_t>(t) * kPartsPerTriangle + q) * nb + b];
+      double pw[3];
+      for (int i = 0; i < 3; ++i) pw[i] = (sum[3 + 2 * i] > 0.0) ? V / (Md * Md) * sum[2 + 2 * i] / sum[3 + 2 * i] : std::nan("");
+      // sum_x I1 I2 I3 is Nm^3 times the number of closed triangles (exact up to FP32 rounding of the fields)
+      B[t] = (sum[1] >= 0.5 * Md) ? V * V / (Md * Md * Md) * sum[0] / sum[1] : std::nan("");
+      Q[t] = B[t] / (pw[0] * pw[1] + pw[1] * pw[2] + pw[2] * pw[0]);
+      if (P)
+        for (int i = 0; i < 3; ++i) P[3 * t + i] = pw[i];
     }
     return LPC_OK;
   });

@@ -312,6 +312,16 @@ hipError_t ic_assemble(float* pos, float* vel, int32_t* id, const float* psi1, c
                        float d1, float d2, float f1, float f2, hipStream_t s);
 
 // Power-spectrum binning of a half spectrum: sums[b] += (k, P) per mode, counts[b] += multiplicity.
+// Reduced-bispectrum pieces (FFT shell estimator). A shell is klo <= |k| < khi. shell_fill writes a whole half
+// spectrum (pitch included): delta_hat / W in the shell (or 1 with indicator), 0 elsewhere. triple_sum and
+// shell_power write sum_blocks() FP64 partial sums each: sum a b c over M cells; sum of mult |delta_hat|^2 / W^2 and
+// of mult over the shell's modes (mult 2 off the kz = 0 and Nyquist planes).
+hipError_t shell_fill(const float2* spec, float2* out, int nm, int pitch, double box, double klo, double khi,
+                      bool indicator, hipStream_t s);
+hipError_t triple_sum(const float* a, const float* b, const float* c, int64_t M, double* part, hipStream_t s);
+hipError_t shell_power(const float2* spec, int nm, int pitch, double box, double klo, double khi, double* part_p,
+                       double* part_n, hipStream_t s);
+int sum_blocks();
 hipError_t pk_bin(const float2* spec, int nm, int pitch, double box, double k_max, int n_bins, double pscale,
                   double* sums, unsigned long long* counts, hipStream_t s);
 

@@ -922,6 +922,36 @@ __global__ __launch_bounds__(kNT) void k_apply(float* __restrict__ pos, const in
   }
 }
 
+__global__ __launch_bounds__(kNT) void k_scale(float* __restrict__ p, int64_t count, float g) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  if (i < count) p[i] *= g;
+}
+
+// The cube symmetry (perm, f) of a channels-last lattice field [N^3][C] of 3-vectors: output site o takes input site
+// u with u[perm[d]] = f_d ? N - 1 - o_d : o_d, and its channel c = 3 m + d takes the input channel 3 m + perm[d],
+// negated when f_d is set. One thread per output site; its C values are contiguous in both fields.
+__global__ __launch_bounds__(kNT) void k_symmetry(const float* __restrict__ in, float* __restrict__ out, int N, int C,
+                                                  int p0, int p1, int p2, int f) {
+  const int64_t v = static_cast<int64_t>(blockIdx.x) * kNT + threadIdx.x;
+  const int64_t V = static_cast<int64_t>(N) * N * N;
+  if (v >= V) return;
+  const int o[3] = {static_cast<int>(v / (static_cast<int64_t>(N) * N)), static_cast<int>((v / N) % N),
+                    static_cast<int>(v % N)};
+  const int perm[3] = {p0, p1, p2};
+  int u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) u[perm[d]] = ((f >> d) & 1) ? N - 1 - o[d] : o[d];
+  const int64_t src = ((static_cast<int64_t>(u[0]) * N + u[1]) * N + u[2]) * C;
+  const int64_t dst = v * C;
+  for (int m = 0; m < C; m += 3) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float x = in[src + m + perm[d]];
+      out[dst + m + d] = ((f >> d) & 1) ? -x : x;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t conv3(View in, int cin, const bf16* w, int kpad, int nb, const float* bias, int leaky_act, View out,
@@ -1075,6 +1105,21 @@ hipError_t features_packed(const float* pos, const int32_t* id, int64_t n, const
                            bf16* x, int* flags, hipStream_t s) {
   if (!psi1) return hipErrorInvalidValue;
   k_features<true><<<blocks_for(n), kNT, 0, s>>>(pos, id, n, nullptr, psi1, N, box, nullptr, 0, x, flags);
+  return hipGetLastError();
+}
+
+hipError_t scale(float* p, int64_t count, float g, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  k_scale<<<blocks_for(count), kNT, 0, s>>>(p, count, g);
+  return hipGetLastError();
+}
+
+hipError_t symmetry(const float* in, float* out, int N, int C, int k, hipStream_t s) {
+  static constexpr int kPerms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  if (k < 0 || k >= 48 || C < 3 || C % 3 != 0 || N < 1) return hipErrorInvalidValue;
+  const int* p = kPerms[k / 8];
+  const int64_t V = static_cast<int64_t>(N) * N * N;
+  k_symmetry<<<blocks_for(V), kNT, 0, s>>>(in, out, N, C, p[0], p[1], p[2], k % 8);
   return hipGetLastError();
 }
 

@@ -380,6 +380,34 @@ lpc_status lpc_net_adam(float* params, float* m, float* v, const float* grad, in
   });
 }
 
+lpc_status lpc_net_scale_output(float* params, float gain, void* stream) {
+  if (!params) return fail(LPC_ERR_INVALID_ARG, "NULL argument");
+  if (lpc_status st = check_params(params)) return st;
+  if (!std::isfinite(gain)) return fail(LPC_ERR_INVALID_ARG, "gain must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() {
+    // the output layer's weights and biases are the last block of the parameter vector
+    check(net::scale(params + layer_offset(OUT), param_count() - layer_offset(OUT), gain, s), "scale");
+    return LPC_OK;
+  });
+}
+
+lpc_status lpc_net_symmetry(int32_t n_side, int32_t k, int32_t channels, const float* in, float* out, void* stream) {
+  if (!in || !out) return fail(LPC_ERR_INVALID_ARG, "NULL argument");
+  if (n_side < 1 || n_side > 1024) return fail(LPC_ERR_INVALID_ARG, "n_side must be in [1, 1024]");
+  if (k < 0 || k >= 48) return fail(LPC_ERR_INVALID_ARG, "k must be in [0, 48)");
+  if (channels < 3 || channels > 48 || channels % 3 != 0)
+    return fail(LPC_ERR_INVALID_ARG, "channels must be a multiple of 3 in [3, 48]");
+  const size_t bytes = static_cast<size_t>(n_side) * n_side * n_side * channels * sizeof(float);
+  const char *a = reinterpret_cast<const char*>(in), *b = reinterpret_cast<const char*>(out);
+  if (a < b + bytes && b < a + bytes) return fail(LPC_ERR_INVALID_ARG, "out overlaps in");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() {
+    check(net::symmetry(in, out, n_side, channels, k, s), "symmetry");
+    return LPC_OK;
+  });
+}
+
 lpc_status lpc_net_apply(const lpc_geometry* geom, const float* params, const lpc_particles* inout, void* ws,
                          size_t ws_bytes, void* stream) {
   if (!geom || !params || !inout || !inout->pos || !inout->psi1 || !inout->id)

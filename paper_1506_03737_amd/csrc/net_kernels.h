@@ -86,6 +86,11 @@ hipError_t features(const float* pos, const int32_t* id, int64_t n, const float*
 // zero): what features followed by pack_input gives, in one pass.
 hipError_t features_packed(const float* pos, const int32_t* id, int64_t n, const float* psi1, int N, double box,
                            bf16* x, int* flags, hipStream_t s);
+// p[i] *= g for i < count.
+hipError_t scale(float* p, int64_t count, float g, hipStream_t s);
+// out = the k-th (0..47) symmetry of the cube applied to the lattice field in[N^3][C] of C / 3 vectors per site (k =
+// 8 p + f: axis permutation p, reflection bits f; see lpc_net_symmetry). out must not overlap in.
+hipError_t symmetry(const float* in, float* out, int N, int C, int k, hipStream_t s);
 // pos = wrap(pos + r[id] L / N) for every particle.
 hipError_t apply_residual(float* pos, const int32_t* id, int64_t n, const float* r, int N, double box, int* flags,
                           hipStream_t s);

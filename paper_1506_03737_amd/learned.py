@@ -47,20 +47,9 @@ def pair_grids(coarse, fine, n_side, box, ws, device):
 
 def symmetry(grid, n_side, k):
     """The k-th (0..47) symmetry of the cube applied to a field of 3-vectors [N^3][3 m] (m vectors per site): an axis
-    permutation with sign flips, acting on both the grid positions and every vector's components (the equations of
-    motion are invariant under it)."""
-    import torch
-    perms = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
-    perm, flips = perms[k // 8], k % 8
-    c = grid.shape[1]
-    comp = [3 * (j // 3) + perm[j % 3] for j in range(c)]
-    g = grid.reshape(n_side, n_side, n_side, c).permute(*perm, 3)[..., comp]
-    for ax in range(3):
-        if flips >> ax & 1:
-            # reflection x -> -x of a periodic, cell-centred lattice maps site i to N - 1 - i
-            g = torch.flip(g, dims=(ax,))
-            g[..., ax::3] = -g[..., ax::3]
-    return g.reshape(-1, c).contiguous()
+    permutation with reflections, acting on both the grid positions and every vector's components (the equations of
+    motion are invariant under it). Runs in liblpc (lpc_net_symmetry)."""
+    return lpc.lpc_net_symmetry(n_side, k, grid)
 
 
 def train(samples, n_side, epochs, lr, seed=1, device="cuda", augment=True, lr_final=None, log=None):
@@ -97,14 +86,16 @@ def train(samples, n_side, epochs, lr, seed=1, device="cuda", augment=True, lr_f
 
 
 def validation_loss(params, samples, n_side, device="cuda"):
-    """Mean loss of the network and of the zero correction (target^2) over held-out samples."""
+    """Mean loss of the network and of the zero correction (mean target^2) over held-out samples. The zero
+    correction's loss is the library's loss at all-zero parameters: every layer's output is then exactly zero."""
     import torch
     ws = lpc.net_workspace(n_side, device)
     grad = torch.empty_like(params)
+    zeros = torch.zeros_like(params)
     net, zero = [], []
     for feat, target in samples:
         net.append(lpc.lpc_net_loss_grad(n_side, params, feat, target, grad, ws))
-        zero.append(float(torch.mean(target.double() ** 2)))
+        zero.append(lpc.lpc_net_loss_grad(n_side, zeros, feat, target, grad, ws))
     return float(np.mean(net)), float(np.mean(zero))
 
 
@@ -113,6 +104,80 @@ def power_spectrum(pos, n, box, device, nm_est=512, k_max=1.0, n_bins=100):
     g = lpc.geometry(0, nm_est, box)
     ws = lpc.workspace(g, lpc.LPC_OP_POWER_SPECTRUM, device, n_particles=n)
     return lpc.lpc_power_spectrum(g, pos, k_max, n_bins, ws)
+
+
+def pk_max_error(pos, ref_pos, n, box, device, k_judge=0.5, nm_est=512, n_bins=100):
+    """max over k <= k_judge of |P(pos) / P(ref_pos) - 1| (binned P(k), empty bins skipped)."""
+    k, p_ref, cnt = power_spectrum(ref_pos, n, box, device, nm_est=nm_est, n_bins=n_bins)
+    _, p, _ = power_spectrum(pos, n, box, device, nm_est=nm_est, n_bins=n_bins)
+    sel = (k <= k_judge) & (cnt > 0)
+    return float(np.max(np.abs(p[sel] / p_ref[sel] - 1.0)))
+
+
+def corrected(params, coarse, n_side, box, device, ws=None):
+    """A copy of a coarse run's particles moved by the network (lpc_net_apply)."""
+    import torch
+    out = lpc.ParticleSet(torch.clone(coarse.pos), None, coarse.psi1, None, coarse.id)
+    lpc.lpc_net_apply(lpc.geometry(n_side, n_side, box), params, out, ws if ws is not None else lpc.net_workspace(n_side, device))
+    return out
+
+
+# Output gains tried by calibrate_gain
+GAINS = tuple(round(0.40 + 0.05 * i, 2) for i in range(13))
+
+
+def calibrate_gain(params, runs, n_side, box, device, gains=GAINS, nm_est=None, n_bins=50, k_judge=0.5):
+    """The output gain that makes the corrected held-out runs' P(k) match their fine runs' best.
+
+    A network trained on the mean squared displacement error returns, at each site, the mean residual given its
+    inputs; moved by it, particles cluster more than the fine run's at k ~ 0.3-0.5 h/Mpc. One scalar on the output
+    layer (lpc_net_scale_output) trades that back: for every g in gains the held-out coarse runs are corrected with
+    g network(x) and judged by the mean over runs of max_{k <= k_judge} |P_corr / P_fine - 1|. runs: [(coarse, fine)]
+    particle sets that were not trained on. Returns (best g, params scaled by it (a copy), {g: error})."""
+    import torch
+    nm_est = nm_est or 2 * n_side
+    ws = lpc.net_workspace(n_side, device)
+    errors = {}
+    for g in gains:
+        pg = torch.clone(params)
+        lpc.lpc_net_scale_output(pg, g)
+        errs = [pk_max_error(corrected(pg, c, n_side, box, device, ws).pos, f.pos, n_side**3, box, device,
+                             k_judge, nm_est, n_bins) for c, f in runs]
+        errors[g] = float(np.mean(errs))
+    best = min(errors, key=errors.get)
+    pb = torch.clone(params)
+    lpc.lpc_net_scale_output(pb, best)
+    return best, pb, errors
+
+
+def fit_correction(train_seeds, val_seeds, n_side, box, a_list, cosmo, step, device, epochs, lr=1e-3, lr_final=5e-5,
+                   seed=3, log=None):
+    """The whole recipe: coarse/fine pairs of the train and held-out seeds, Adam over the training pairs with random
+    cube symmetries, the held-out loss against no correction, then the output gain calibrated on the held-out runs.
+    Returns a dict: params (gain applied), gain, gain_errors, history, validation_loss_ratio (before the gain),
+    pairs_s, train_s, calibrate_s."""
+    import torch
+    ws = lpc.net_workspace(n_side, device)
+    t0 = time.perf_counter()
+    train_s = []
+    for sd in train_seeds:
+        c, f = run_pair(sd, n_side, box, a_list, cosmo, step, device)
+        train_s.append(pair_grids(c, f, n_side, box, ws, device))
+        del c, f
+    val_runs = [run_pair(sd, n_side, box, a_list, cosmo, step, device) for sd in val_seeds]
+    val_s = [pair_grids(c, f, n_side, box, ws, device) for c, f in val_runs]
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    (params, hist), t_train = timed(lambda: train(train_s, n_side, epochs=epochs, lr=lr, lr_final=lr_final, seed=seed,
+                                                  device=device, log=log))
+    del train_s
+    net_loss, zero_loss = validation_loss(params, val_s, n_side, device)
+    (gain, scaled, errors), t_cal = timed(lambda: calibrate_gain(params, val_runs, n_side, box, device))
+    if log:
+        log(f"held-out loss ratio {net_loss / zero_loss:.4f}; gain {gain} (held-out P(k) errors {errors})")
+    return {"params": scaled, "gain": gain, "gain_errors": errors, "history": hist,
+            "validation_loss_ratio": net_loss / zero_loss, "pairs_s": t_pairs, "train_s": t_train,
+            "calibrate_s": t_cal}
 
 
 def timed(fn):

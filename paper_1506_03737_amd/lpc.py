@@ -18,6 +18,7 @@ LPC_OP_PM_FORCE = 2
 LPC_OP_COLA_STEP = 3
 LPC_OP_POWER_SPECTRUM = 4
 LPC_OP_FFT = 5
+LPC_OP_BISPECTRUM = 6
 COEF_COLUMNS = ("a", "D1", "D2", "dD1", "dD2", "E", "K", "Q", "dDD1", "dDD2", "f1", "f2")
 
 STATUS = {0: "LPC_OK", -1: "LPC_ERR_INVALID_ARG", -2: "LPC_ERR_UNSUPPORTED_SIZE", -3: "LPC_ERR_WORKSPACE",
@@ -107,9 +108,12 @@ def _load():
         "lpc_net_features": (i32, [P(Geometry), vp, vp, i64, vp, vp, vp, vp, sz, vp]),
         "lpc_net_forward": (i32, [i32, vp, vp, vp, vp, sz, vp]),
         "lpc_net_loss_grad": (i32, [i32, vp, vp, vp, vp, P(dbl), vp, sz, vp]),
+        "lpc_net_symmetry": (i32, [i32, i32, i32, vp, vp, vp]),
+        "lpc_net_scale_output": (i32, [vp, ctypes.c_float, vp]),
         "lpc_net_adam": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, vp]),
         "lpc_net_apply": (i32, [P(Geometry), vp, P(Particles), vp, sz, vp]),
         "lpc_power_spectrum": (i32, [P(Geometry), vp, i64, dbl, i32, P(dbl), P(dbl), P(i64), vp, sz, vp]),
+        "lpc_bispectrum": (i32, [P(Geometry), vp, i64, P(dbl), i32, dbl, P(dbl), P(dbl), P(dbl), vp, sz, vp]),
         "lpc_cola_coefficients": (i32, [P(Cosmology), P(Stepping), P(dbl), i32, P(dbl)]),
         "lpc_linear_power": (i32, [P(Cosmology), P(dbl), i32, P(dbl)]),
         "lpc_fft_r2c": (i32, [i32, vp, vp, vp, sz, vp]),
@@ -138,9 +142,9 @@ EXPORTED = ("lpc_workspace_bytes", "lpc_init_ic", "lpc_init_ic_png", "lpc_png_pr
             "lpc_pm_force_noalloc", "lpc_cola_step",
             "lpc_cola_step_lightcone", "lpc_comoving_distance",
             "lpc_workspace_bytes_batched",
-            "lpc_cola_step_batched", "lpc_graph_enable", "lpc_power_spectrum",
+            "lpc_cola_step_batched", "lpc_graph_enable", "lpc_power_spectrum", "lpc_bispectrum",
             "lpc_net_param_count", "lpc_net_init", "lpc_net_workspace_bytes", "lpc_net_features", "lpc_net_forward",
-            "lpc_net_loss_grad", "lpc_net_adam", "lpc_net_apply",
+            "lpc_net_loss_grad", "lpc_net_symmetry", "lpc_net_scale_output", "lpc_net_adam", "lpc_net_apply",
             "lpc_cola_coefficients", "lpc_linear_power", "lpc_fft_r2c", "lpc_fft_c2r", "lpc_fft_pitch",
             "lpc_fft_tiling_default", "lpc_fft_tiling_get", "lpc_fft_tiling_set", "lpc_fft_tiling_reset",
             "lpc_profile_enable", "lpc_profile_reset", "lpc_profile_count", "lpc_profile_get",
@@ -343,6 +347,21 @@ def lpc_power_spectrum(geom, pos, k_max, n_bins, ws, stream=None):
     return k, pk, cnt
 
 
+def lpc_bispectrum(geom, pos, triangles, dk, ws, stream=None):
+    """Reduced bispectrum of particles pos[3][n] on the geom.n_mesh estimator mesh: triangles is a sequence of
+    (k1, k2, k3) shell centres (h/Mpc), dk the shell width. Returns (B, Q, P) numpy arrays ([m], [m], [m][3])."""
+    k123 = np.ascontiguousarray(np.asarray(triangles, dtype=np.float64).reshape(-1, 3))
+    m = k123.shape[0]
+    B = np.empty(m, dtype=np.float64)
+    Q = np.empty(m, dtype=np.float64)
+    P = np.empty((m, 3), dtype=np.float64)
+    D = ctypes.POINTER(ctypes.c_double)
+    _check(LIB.lpc_bispectrum(ctypes.byref(geom), _ptr(pos), int(pos.shape[1]), k123.ctypes.data_as(D), int(m),
+                              float(dk), B.ctypes.data_as(D), Q.ctypes.data_as(D), P.ctypes.data_as(D), _ptr(ws),
+                              ws.numel(), _stream(stream)))
+    return B, Q, P
+
+
 def lpc_cola_coefficients(cosmo, step, a_list):
     a = np.ascontiguousarray(a_list, dtype=np.float64)
     out = np.empty((a.size, len(COEF_COLUMNS)), dtype=np.float64)
@@ -446,6 +465,27 @@ def lpc_net_loss_grad(n_side, params, feat, target, grad, ws, stream=None):
     _check(LIB.lpc_net_loss_grad(int(n_side), _ptr(params), _ptr(feat), _ptr(target), _ptr(grad),
                                  ctypes.byref(loss), _ptr(ws), ws.numel(), _stream(stream)))
     return float(loss.value)
+
+
+def lpc_net_symmetry(n_side, k, grid, out=None, stream=None):
+    """The k-th cube symmetry of a lattice field grid [n_side^3][channels] (FP32, contiguous); returns out (a new
+    tensor unless given)."""
+    import torch
+    if grid.dtype != torch.float32 or not grid.is_contiguous() or grid.dim() != 2:
+        raise ValueError("grid must be a contiguous FP32 [n_side^3][channels] tensor")
+    if out is None:
+        out = torch.empty_like(grid)
+    elif out.shape != grid.shape or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous FP32 tensor of the grid's shape")
+    if grid.shape[0] != int(n_side) ** 3:
+        raise ValueError("grid must have n_side^3 rows")
+    _check(LIB.lpc_net_symmetry(int(n_side), int(k), int(grid.shape[1]), _ptr(grid), _ptr(out), _stream(stream)))
+    return out
+
+
+def lpc_net_scale_output(params, gain, stream=None):
+    """Multiply the output layer of params (device, in place) by gain."""
+    _check(LIB.lpc_net_scale_output(_ptr(params), ctypes.c_float(gain), _stream(stream)))
 
 
 def lpc_net_adam(params, m, v, grad, step, lr, stream=None):

@@ -281,3 +281,38 @@ def test_png_presets_match_oracle():
         assert got == [tuple(map(float, t)) for t in terms]
     with pytest.raises(lpc.LpcError):
         lpc._check(lpc.LIB.lpc_png_preset(7, 1.0, ctypes.byref(lpc.Png())))
+
+
+def test_net_symmetry_rejects_bad_arguments():
+    """Argument checks of lpc_net_symmetry run before any device work: k and channels out of range, aliasing."""
+    import ctypes
+    from paper_1506_03737_amd import lpc
+    n, C = 4, 6
+    a = ctypes.create_string_buffer(n**3 * C * 4 * 2)
+    base = ctypes.addressof(a)
+    other = base + n**3 * C * 4
+    for args in ((n, 48, C, base, other), (n, -1, C, base, other), (n, 0, 4, base, other), (n, 0, 51, base, other),
+                 (0, 0, C, base, other), (n, 0, C, base, base + 8), (n, 0, C, None, other)):
+        st = lpc.LIB.lpc_net_symmetry(*args, None)
+        assert st == -1, args  # LPC_ERR_INVALID_ARG
+
+
+def test_bispectrum_arguments_and_workspace():
+    """lpc_bispectrum's checks run before any device work; its workspace holds the P(k) path's plus three real
+    meshes and a spectrum."""
+    from paper_1506_03737_amd import lpc
+    g = lpc.geometry(0, 64, 500.0)
+    wb = lpc.lpc_workspace_bytes(g, lpc.LPC_OP_BISPECTRUM, 1000)
+    wp = lpc.lpc_workspace_bytes(g, lpc.LPC_OP_POWER_SPECTRUM, 1000)
+    assert wb >= wp + 3 * 64**3 * 4 + 64 * 64 * lpc.lpc_fft_pitch(64) * 8
+    assert lpc.lpc_workspace_bytes(g, lpc.LPC_OP_BISPECTRUM, 0) == 0
+    D = ctypes.POINTER(ctypes.c_double)
+    k = (ctypes.c_double * 6)(0.1, 0.1, 0.1, 0.1, 0.2, 0.0)
+    out = (ctypes.c_double * 8)()
+    fake = ctypes.c_void_p(0x100000)
+    lib = lpc.LIB
+    for args in ((fake, 1000, k, 1, 0.0), (fake, 1000, k, 0, 0.01), (fake, 1000, k, 257, 0.01),
+                 (fake, 1000, k, 2, 0.01), (fake, 0, k, 1, 0.01), (None, 1000, k, 1, 0.01)):
+        st = lib.lpc_bispectrum(ctypes.byref(g), args[0], args[1], ctypes.cast(args[2], D), args[3], args[4],
+                                ctypes.cast(out, D), ctypes.cast(out, D), None, fake, 1 << 30, None)
+        assert st == -1, args

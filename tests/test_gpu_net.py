@@ -206,3 +206,72 @@ def test_training_reduces_loss():
         lpc.lpc_net_adam(params, m, v, grad, t, 3e-3)
     say(f"  loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert losses[-1] < 0.5 * losses[0]
+
+
+@pytest.mark.parametrize("N,C", [(8, 6), (8, 3), (12, 9)])
+def test_symmetry_matches_oracle_all_48(N, C):
+    """lpc_net_symmetry moves and negates values only: every one of the 48 cube symmetries equals the oracle's bit for
+    bit (odd and even lattice sizes, one to three vectors per site)."""
+    from paper_1506_03737_amd import lpc
+    rng = np.random.default_rng(N * 100 + C)
+    cf = rng.standard_normal((C, N, N, N)).astype(np.float32)
+    g = to_dev(cf_to_grid(cf))
+    for k in range(48):
+        got = to_np(lpc.lpc_net_symmetry(N, k, g))
+        ref = cf_to_grid(onet.cube_symmetry(cf, k))
+        assert np.array_equal(got, ref), k
+
+
+def test_symmetry_training_size_and_round_trip():
+    """At the training lattice (128^3, input grids of 6 channels) sampled symmetries equal the oracle bit for bit, and
+    applying a symmetry and then its inverse (found among the 48) gives the field back."""
+    from paper_1506_03737_amd import lpc
+    N, C = 128, 6
+    cf = np.random.default_rng(9).standard_normal((C, N, N, N)).astype(np.float32)
+    g = to_dev(cf_to_grid(cf))
+    for k in (5, 19, 30, 47):
+        got = to_np(lpc.lpc_net_symmetry(N, k, g))
+        assert np.array_equal(got, cf_to_grid(onet.cube_symmetry(cf, k))), k
+    small = np.random.default_rng(1).standard_normal((3, 4, 4, 4))
+    for k in range(48):
+        inv = next(j for j in range(48) if np.array_equal(onet.cube_symmetry(onet.cube_symmetry(small, k), j), small))
+        back = lpc.lpc_net_symmetry(N, inv, lpc.lpc_net_symmetry(N, k, g))
+        assert torch.equal(back, g), k
+
+
+def test_zero_parameters_give_the_zero_correction_loss():
+    """With all-zero parameters every layer outputs zero, so the library's loss is mean(target^2) (FP64 sums)."""
+    from paper_1506_03737_amd import lpc
+    D = 16
+    feat, target = sample(D, 4)
+    ws = lpc.net_workspace(D)
+    params = torch.zeros(lpc.lpc_net_param_count(), dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(params)
+    loss = lpc.lpc_net_loss_grad(D, params, to_dev(cf_to_grid(feat)), to_dev(cf_to_grid(target)), grad, ws)
+    assert loss == pytest.approx(float(np.mean(target.astype(np.float64) ** 2)), rel=1e-12)
+
+
+def test_scale_output_scales_the_network_output():
+    """lpc_net_scale_output multiplies the last (linear) layer: a gain of 1/2 is exact in BF16 and FP32, so the output
+    halves bit for bit; a gain of 0.65 scales it to within the BF16 rounding of the scaled weights. The other layers'
+    parameters are untouched."""
+    from paper_1506_03737_amd import lpc
+    D = 16
+    feat, _ = sample(D, 6)
+    ws = lpc.net_workspace(D)
+    params = to_dev(lpc.lpc_net_init(11))
+    x = to_dev(cf_to_grid(feat))
+    out = torch.empty((D**3, 3), dtype=torch.float32, device="cuda")
+    lpc.lpc_net_forward(D, params, x, out, ws)
+    base = to_np(out).copy()
+    n_out = onet.layer_slices()["out"][0].start
+    for g, exact in ((0.5, True), (0.65, False)):
+        p = torch.clone(params)
+        lpc.lpc_net_scale_output(p, g)
+        assert torch.equal(p[:n_out], params[:n_out])
+        lpc.lpc_net_forward(D, p, x, out, ws)
+        got = to_np(out)
+        if exact:
+            assert np.array_equal(got, 0.5 * base)
+        else:
+            assert max_rel(got, g * base) < 1e-2

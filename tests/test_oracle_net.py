@@ -164,3 +164,42 @@ def test_bispectrum_of_three_plane_waves_closed_form():
     P = [V * A**2 / (2 * len(sh[kc])) for kc in (3, 4, 5)]
     assert np.isclose(obs.power_in_shell(dhat, box, 3 * kf, kf), P[0], rtol=1e-9)
     assert np.isclose(Q, B / (P[0] * P[1] + P[1] * P[2] + P[2] * P[0]), rtol=1e-9)
+
+
+def _transform_points(x, k, box):
+    """The cube symmetry k as a map of positions x[3][n] (independent of cube_symmetry's index arithmetic)."""
+    perm, f = net.PERMS[k // 8], k % 8
+    y = np.stack([x[perm[d]] for d in range(3)])
+    for d in range(3):
+        if (f >> d) & 1:
+            y[d] = box - y[d]
+    return y
+
+
+def test_cube_symmetry_is_the_geometric_map():
+    """Moving the particles by symmetry k (positions and the lattice points their ids name, recomputed from scratch)
+    and taking their displacement field equals cube_symmetry of the original displacement field, for all 48 k; the
+    map is a group action: k = 0 is the identity and the 48 images of a generic field are distinct."""
+    n_side, box = 6, 60.0
+    dp = box / n_side
+    rng = np.random.default_rng(5)
+    ids = np.arange(n_side**3)
+    ijk = np.stack([ids // (n_side * n_side), (ids // n_side) % n_side, ids % n_side]).astype(np.float64)
+    q = (ijk + 0.5) * dp
+    x = q + rng.uniform(-0.4, 0.4, q.shape) * dp
+    psi = rng.standard_normal(q.shape) * dp
+    grid = net.input_grid(x, psi, ids, n_side, box)
+    seen = set()
+    for k in range(48):
+        xt, qt, pt = _transform_points(x, k, box), _transform_points(q, k, box), _transform_points(psi + box, k, box)
+        # psi is a vector: transform it as a difference of two points so that reflections flip its sign
+        pt = pt - _transform_points(np.full_like(psi, box), k, box)
+        t_ijk = np.rint(qt / dp - 0.5).astype(np.int64)
+        t_ids = (t_ijk[0] * n_side + t_ijk[1]) * n_side + t_ijk[2]
+        assert np.array_equal(np.sort(t_ids), ids)  # the lattice maps onto itself
+        ref = net.input_grid(xt % box, pt, t_ids, n_side, box)
+        got = net.cube_symmetry(grid, k)
+        assert np.allclose(got, ref, rtol=0, atol=1e-12), k
+        seen.add(got.tobytes())
+    assert np.array_equal(net.cube_symmetry(grid, 0), grid)
+    assert len(seen) == 48
