@@ -41,6 +41,11 @@ if ROOT not in sys.path:
 METRIC = "particle-steps/s (COLA PM step), plain vs batched/learned at P(k) err <2%"
 HBM_PEAK_GBS = 8000.0
 
+
+def note(msg):
+    """A progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes (read scaled by 2.0, write by 1.0, from
 # a 1 GiB copy), by (stage, mesh size, tile width of the stage); profiles/force_path_768_hbm_traffic.md. Must be
 # re-measured (or removed) when the kernel changes.
@@ -473,6 +478,7 @@ def main():
     # the CPU baseline first: its worker processes fork a process that has not touched the GPU
     cpu, oracle_small = None, None
     if not args.no_cpu:
+        note("cpu baseline (FP64 oracle on the host)")
         cpu, oracle_small = cpu_baseline(workers=min(os.cpu_count() or 1, 16))
 
     import torch
@@ -515,7 +521,9 @@ def main():
 
     if args.warmup > 0:
         timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, args.warmup, False)
+    note(f"single box: {args.steps} timed steps")
     dt, stats = timed_schedule(lpc, torch, geom, cosmo, step, synth.A_LIST, ps, ws, reset, args.steps, True)
+    note(f"single box: {dt * 1e3 / args.steps:.2f} ms per step")
 
     value = n * args.steps / dt
     evals = sum(m + 1 for m in schedule_runs(args.steps))
@@ -546,19 +554,24 @@ def main():
         "stages": stages,
     }
     if not args.no_lightcone and args.workload == "single":
+        note("lightcone")
         out["lightcone"] = lightcone_bench(lpc, synth, torch, ic, geom, ws, n)
     del ps, ws, ic
     torch.cuda.empty_cache()
     if not args.no_batched and args.workload == "single":
+        note("batched (48 boxes)")
         out["batched"] = batched_bench(lpc, synth, torch)
         torch.cuda.empty_cache()
     if not args.no_learned and args.workload == "single":
+        note("learned (pairs, training, calibration, runs)")
         out["learned"] = learned_bench(lpc, synth, torch)
         torch.cuda.empty_cache()
     if not args.no_large and args.workload == "single":
+        note("large box")
         out["large"] = large_bench(lpc, synth, torch, copy_gbs)
     if cpu is not None:
         out["cpu_baseline"] = cpu
+        note("precision")
         out["precision"] = precision(lpc, synth, torch, oracle_small)
     print(json.dumps(out), flush=True)
 
