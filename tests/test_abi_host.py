@@ -112,7 +112,8 @@ def test_batched_workspace_layout():
 
     def sort_space(nms, ns):
         copies = 2 * sum(4 * r256(12 * n) + r256(4 * n) for n in ns)
-        G = sum(2 * (-(-nm // 16)) ** 3 + 1 for nm in nms)
+        # two buckets per tile of 16 x 8 x 32 cells, plus one per box
+        G = sum(2 * (-(-nm // 16)) * (-(-nm // 8)) * (-(-nm // 32)) + 1 for nm in nms)
         return copies + 2 * r256(4 * sum(ns)) + r256(4 * G) + r256(4 * (G + 1)) + r256(4 * -(-G // 2048))
 
     one = (lpc.BatchEntry * 1)(entry(64, 1000))
