@@ -123,6 +123,53 @@ __device__ __forceinline__ void fft_tile_fast(float2* tile, const float2* tw, co
   fft_tile<INV, EPT, R12>(tile, tw, pl, B, BP, tid);
 }
 
+// fft_tile_fast with the tile's fill and drain folded into the first and last stages: with GIN the input comes from
+// load(row, col) (the tile is not filled first; mid() runs while the first loads are in flight), with GOUT the
+// output goes to store(row, col, value). Full-length transforms; plans other than the compiled ones fill the tile,
+// run fft_tile and store from it. The twiddles in tw must be in LDS by the first barrier (mid() may write them).
+template <class F, class PL, bool GIN, bool GOUT, bool PAIRS, class Load, class Pair, class Mid, class Store>
+__device__ __forceinline__ bool try_fixed_io(float2* tile, const float2* tw, const PL& pl, int tid, Load load,
+                                             Pair pair, Mid mid, Store store) {
+  if (!F::matches(pl)) return false;
+  F::template run_io<GIN, GOUT, PAIRS>(tile, tw, tid, load, pair, mid, store);
+  return true;
+}
+
+// PAIRS: tile column b < B / 2 is pair(row, x) and column b + B / 2 is x itself, for x = load(row, b) of a B / 2
+// column source (load takes source columns only).
+template <bool INV, int EPT, int B, int BP, bool GIN, bool GOUT, bool PAIRS = false, class PL, class Load, class Pair,
+          class Mid, class Store>
+__device__ __forceinline__ void fft_io_fast(float2* tile, const float2* tw, const PL& pl, int tid, Load load, Pair pair,
+                                            Mid mid, Store store) {
+#define LPC_TRY_IO(...)                                                                                          \
+  if (try_fixed_io<FixedFFT<INV, EPT, B, BP, __VA_ARGS__>, PL, GIN, GOUT, PAIRS>(tile, tw, pl, tid, load, pair, mid, \
+                                                                             store))                             \
+    return;
+  LPC_TRY_IO(8, 8, 12)
+  LPC_TRY_IO(8, 8, 5)
+  LPC_TRY_IO(8, 8, 4)
+  LPC_TRY_IO(8, 8, 3)
+#undef LPC_TRY_IO
+  const int n = pl.n;
+  if constexpr (GIN) {
+    for (int e = tid; e < n * B; e += kFftNT) {
+      const int j = e / B, b = e % B;
+      if constexpr (PAIRS) {
+        const float2 x = load(j, b % (B / 2));
+        tile[j * BP + b] = (b < B / 2) ? pair(j, x) : x;
+      } else {
+        tile[j * BP + b] = load(j, b);
+      }
+    }
+    mid();
+    __syncthreads();
+  }
+  fft_tile<INV, EPT, true>(tile, tw, pl, B, BP, tid);
+  if constexpr (GOUT) {
+    for (int e = tid; e < n * B; e += kFftNT) store(e / B, e % B, tile[(e / B) * BP + (e % B)]);
+  }
+}
+
 // Job of work item w: the last j with offs[j] <= w (binary search; offs is uniform, so scalar loads).
 __device__ __forceinline__ int find_job(const LPC_CONST int* __restrict__ offs, int njob, int w) {
   int lo = 0, hi = njob - 1;
@@ -339,19 +386,16 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : 4) void k_fft_axis(const A
     float2* tile = smem;
     float2* tw = smem + n * strided_pitch(B);
     LPC_GLOBAL float2* ptr = to_global(J.base + comp * J.cstr + outer * J.ostr + c0);
-    {
-      constexpr int H = EPT / 2;
-      float2 v[H];
-      const TableRegs<float2> t = table_load(J.tw, n, tid);
-      strided_issue<B, H>(v, ptr, J.astr, n, bw, tid, 0);
-      table_store(tw, t, n, tid);
-      strided_put<B, H>(tile, v, n, tid, 0);
-      strided_issue<B, H>(v, ptr, J.astr, n, bw, tid, 1);
-      strided_put<B, H>(tile, v, n, tid, 1);
-    }
-    __syncthreads();
-    fft_tile_fast<INV, EPT, B, strided_pitch(B), false>(tile, tw, J.pl, tid);
-    store_strided<B, EPT>(tile, ptr, J.astr, n, bw, tid);
+    const int64_t astr = J.astr;
+    // the first stage reads the columns from HBM and the last writes them back: the tile holds only the stages between
+    const TableRegs<float2> twr = table_load(J.tw, n, tid);
+    auto load = [&](int j, int b) { return b < bw ? ptr[j * astr + b] : make_float2(0.f, 0.f); };
+    auto mid = [&]() { table_store(tw, twr, n, tid); };
+    auto store = [&](int j, int b, float2 v) {
+      if (b < bw) ptr[j * astr + b] = v;
+    };
+    auto none = [](int, float2 x) { return x; };
+    fft_io_fast<INV, EPT, B, strided_pitch(B), true, true>(tile, tw, J.pl, tid, load, none, mid, store);
   }
 }
 
@@ -375,25 +419,21 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
   const int n = J.n;
   float2* tile = smem;
   float2* tw = smem + n * BP;
+  const TableRegs<float2> twr = table_load(J.tw, n, tid);
+  auto mid = [&]() { table_store(tw, twr, n, tid); };
   if (local < J.per_comp) {  // component 0 (uniform)
     const int t = xcd_remap(local, J.per_comp);
     const int outer = t / J.ntc, ct = t - outer * J.ntc;
     if (outer >= n) return;  // padding item
     const int c0 = ct * B, bw = min(B, J.ncols - c0);
-    const int64_t off = static_cast<int64_t>(outer) * J.ostr + c0;
-    {
-      LPC_GLOBAL const float2* src = to_global(J.A + off);
-      float2 v[H];
-      const TableRegs<float2> tt = table_load(J.tw, n, tid);
-      strided_issue<B, H>(v, src, J.astr, n, bw, tid, 0);
-      table_store(tw, tt, n, tid);
-      strided_put<B, H>(tile, v, n, tid, 0);
-      strided_issue<B, H>(v, src, J.astr, n, bw, tid, 1);
-      strided_put<B, H>(tile, v, n, tid, 1);
-    }
-    __syncthreads();
-    fft_tile_fast<true, EPT, B, BP, false>(tile, tw, J.pl, tid);
-    store_strided<B, EPT>(tile, to_global(J.A + off), J.astr, n, bw, tid);
+    LPC_GLOBAL float2* ptr = to_global(J.A + static_cast<int64_t>(outer) * J.ostr + c0);
+    const int64_t astr = J.astr;
+    auto load = [&](int j, int b) { return b < bw ? ptr[j * astr + b] : make_float2(0.f, 0.f); };
+    auto store = [&](int j, int b, float2 v) {
+      if (b < bw) ptr[j * astr + b] = v;
+    };
+    auto none = [](int, float2 x) { return x; };
+    fft_io_fast<true, EPT, B, BP, true, true>(tile, tw, J.pl, tid, load, none, mid, store);
     return;
   }
   const int t = xcd_remap(local - J.per_comp, J.per_comp1);
@@ -401,45 +441,28 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
   if (outer >= n) return;  // padding item
   const int c0 = ct * BH, bw = min(BH, J.ncols - c0);
   const int64_t off = static_cast<int64_t>(outer) * J.ostr + c0;
-  {
-    // n BH <= H kFftNT values, H per thread; column bh = tid % BH is the same for all of a thread's values
-    constexpr int SH = kFftNT / BH;
-    const int bh = tid % BH, j0 = tid / BH;
-    LPC_GLOBAL const float2* src = to_global(J.C + off) + bh;
-    const TableRegs<float2> tt = table_load(J.tw, n, tid);
-    float2 v[H];
-#pragma unroll
-    for (int m = 0; m < H; ++m) {
-      const int j = j0 + m * SH;
-      v[m] = make_float2(0.f, 0.f);
-      if (j < n && bh < bw) v[m] = src[j * J.astr];
-    }
-    table_store(tw, tt, n, tid);
-    const int half = n / 2;
-    const float kf = J.kf;
-#pragma unroll
-    for (int m = 0; m < H; ++m) {
-      const int j = j0 + m * SH;
-      if (j < n) {
-        const float ky = (j == half) ? 0.f : kf * static_cast<float>(j <= half ? j : j - n);
-        tile[j * BP + bh] = make_float2(-ky * v[m].y, ky * v[m].x);  // i k_y psi
-        tile[j * BP + BH + bh] = v[m];                               // psi
-      }
-    }
-  }
-  __syncthreads();
-  fft_tile_fast<true, EPT, B, BP, false>(tile, tw, J.pl, tid);
-  {
-    // tile column b: b < BH -> B (y gradient), else C (psi); b = tid % B is fixed per thread
-    constexpr int S = kFftNT / B;
-    const int b = tid % B, j0 = tid / B, bh = b % BH;
-    LPC_GLOBAL float2* dst = to_global((b < BH ? J.B : J.C) + off) + bh;
-#pragma unroll
-    for (int m = 0; m < EPT; ++m) {
-      const int j = j0 + m * S;
-      if (j < n && bh < bw) dst[j * J.astr] = tile[j * BP + b];
-    }
-  }
+  LPC_GLOBAL const float2* src = to_global(J.C + off);
+  LPC_GLOBAL float2* dB = to_global(J.B + off);
+  LPC_GLOBAL float2* dC = to_global(J.C + off);
+  const int64_t astr = J.astr;
+  const int half = n / 2;
+  const float kf = J.kf;
+  // tile column b < BH holds i k_y psi of psi's column b, column BH + b psi itself; they go to B and back to C.
+  // Each psi value is loaded once and feeds both columns.
+  auto load = [&](int j, int bh) {
+    float2 v = make_float2(0.f, 0.f);
+    if (bh < bw) v = src[j * astr + bh];
+    return v;
+  };
+  auto iky = [&](int j, float2 v) {
+    const float ky = (j == half) ? 0.f : kf * static_cast<float>(j <= half ? j : j - n);
+    return make_float2(-ky * v.y, ky * v.x);
+  };
+  auto store = [&](int j, int b, float2 v) {
+    const int bh = b % BH;
+    if (bh < bw) (b < BH ? dB : dC)[j * astr + bh] = v;
+  };
+  fft_io_fast<true, EPT, B, BP, true, true, true>(tile, tw, J.pl, tid, load, iky, mid, store);
 }
 
 // ---------------------------------------------------------------------------------------------------------------

@@ -226,6 +226,112 @@ __device__ __forceinline__ void fft_stage_c(float2* tile, const float2* tws, int
   __syncthreads();
 }
 
+// The first stage of a compile-time plan fed straight from global memory (sub-transform length 1: no twiddles).
+// Butterfly i of column b takes rows i + r T (r < R) through load(row, b) and writes its outputs to the tile at rows
+// i R + r. All of a thread's loads are issued before mid() runs and before the first butterfly, so a caller can use
+// mid() for work that overlaps them. No barrier: the caller synchronises before the next stage reads the tile.
+template <int R, bool INV, int EPT, int N, int B, int BP, class Load, class Mid>
+__device__ __forceinline__ void fft_stage_from_global(float2* tile, Load load, Mid mid, int tid) {
+  constexpr int MB = (EPT + R - 1) / R, T = N / R, S = kFftNT / B;
+  const int b = tid % B;
+  const int i0 = (tid < S * B) ? tid / B : (1 << 30);
+  float2 v[MB][R];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[m][r] = load(i + r * T, b);
+    }
+  }
+  mid();
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      Dft<R, INV>::run(v[m]);
+      float2* dst = tile + i * R * BP + b;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * BP] = v[m][r];
+    }
+  }
+}
+
+// The same first stage for a tile whose columns come in pairs (b, b + B / 2) built from one source column: thread
+// (i, bh) loads rows i + r T of source column bh once through load(row, bh), and pair(row, x) gives the value of
+// column bh (column bh + B / 2 takes x itself). The loads of 16 rows x B / 2 columns per wave are each read once.
+template <int R, bool INV, int N, int B, int BP, class Load, class Pair, class Mid>
+__device__ __forceinline__ void fft_stage_from_global_pairs(float2* tile, Load load, Pair pair, Mid mid, int tid) {
+  constexpr int BH = B / 2, T = N / R, S = kFftNT / BH, MB = (T + S - 1) / S;
+  const int bh = tid % BH, i0 = tid / BH;
+  float2 x[MB][R];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[m][r] = load(i + r * T, bh);
+    }
+  }
+  mid();
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      float2 a[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] = pair(i + r * T, x[m][r]);
+      Dft<R, INV>::run(a);
+      Dft<R, INV>::run(x[m]);
+      float2* dst = tile + i * R * BP + bh;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        dst[r * BP] = a[r];
+        dst[r * BP + BH] = x[m][r];
+      }
+    }
+  }
+}
+
+// The last stage of a compile-time plan written straight to global memory: fft_stage_c with output row
+// (i - k) R + k + r P going to store(row, b, value) instead of the tile. There is no barrier after the tile reads:
+// nothing writes the tile again before the caller's next barrier.
+template <int R, bool INV, int EPT, int N, int P, int B, int BP, class Store>
+__device__ __forceinline__ void fft_stage_to_global(const float2* tile, const float2* tws, Store store, int tid) {
+  constexpr int MB = (EPT + R - 1) / R, T = N / R, S = kFftNT / B;
+  const int b = tid % B;
+  const int i0 = (tid < S * B) ? tid / B : (1 << 30);
+  float2 v[MB][R];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      const float2* src = tile + i * BP + b;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[m][r] = src[r * T * BP];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    if (i < T) {
+      const int k = ((P & (P - 1)) == 0) ? (i & (P - 1)) : (i % P);
+      if (P > 1) {
+        const float2* w = tws + k * (R - 1) - 1;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const float2 t = w[r];
+          v[m][r] = INV ? cmulc(v[m][r], t) : cmul(v[m][r], t);
+        }
+      }
+      Dft<R, INV>::run(v[m]);
+      const int row = (i - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(row + r * P, b, v[m][r]);
+    }
+  }
+}
+
 // A transform whose plan (radices Rs..., applied in order) and tile geometry are fixed at compile time. matches()
 // tells whether a job's run-time plan is this one (then run() computes exactly what fft_tile computes, with the same
 // twiddle table) and whether the tile geometry can hold it; kernels use it for the mesh sizes they are tuned for and
@@ -256,6 +362,32 @@ struct FixedFFT {
   // The caller has synchronised after filling the tile.
   static __device__ __forceinline__ void run(float2* tile, const float2* tw, int tid) {
     if constexpr (kFits) stages<1, Rs...>(tile, tw, tid);
+  }
+  // With GIN the first stage reads global memory through load (the tile is not filled first; mid runs while the
+  // loads are in flight); with GOUT the last stage writes global memory through store (the tile keeps the last
+  // stage's input). Without them the stage works in the tile as in run(). Plans of two stages or more.
+  template <bool GIN, bool GOUT, bool PAIRS, int P, int R, int... More, class Load, class Pair, class Mid, class Store>
+  static __device__ __forceinline__ void io_stages(float2* tile, const float2* tw, int tid, Load load, Pair pair,
+                                                   Mid mid, Store store) {
+    if constexpr (P == 1 && GIN) {
+      if constexpr (PAIRS)
+        fft_stage_from_global_pairs<R, INV, kN, B, BP>(tile, load, pair, mid, tid);
+      else
+        fft_stage_from_global<R, INV, EPT, kN, B, BP>(tile, load, mid, tid);
+      __syncthreads();
+    } else if constexpr (sizeof...(More) == 0 && GOUT) {
+      fft_stage_to_global<R, INV, EPT, kN, P, B, BP>(tile, tw, store, tid);
+    } else {
+      fft_stage_c<R, INV, EPT, kN, P, B, BP>(tile, tw, tid);
+    }
+    if constexpr (sizeof...(More) > 0)
+      io_stages<GIN, GOUT, PAIRS, P * R, More...>(tile, tw + P * (R - 1), tid, load, pair, mid, store);
+  }
+  // PAIRS: the tile's columns come in pairs built from one loaded column (fft_stage_from_global_pairs)
+  template <bool GIN, bool GOUT, bool PAIRS, class Load, class Pair, class Mid, class Store>
+  static __device__ __forceinline__ void run_io(float2* tile, const float2* tw, int tid, Load load, Pair pair, Mid mid,
+                                                Store store) {
+    if constexpr (kFits && kNst >= 2) io_stages<GIN, GOUT, PAIRS, 1, Rs...>(tile, tw, tid, load, pair, mid, store);
   }
 };
 
