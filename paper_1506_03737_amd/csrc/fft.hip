@@ -498,19 +498,22 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
     const int c0 = ct * B, bw = min(B, nh - c0);
     const int64_t astr = static_cast<int64_t>(nm) * pitch;
     const int64_t off = static_cast<int64_t>(y) * pitch + c0;
+    LPC_GLOBAL float2* gA = to_global(J.A + off);
+    LPC_GLOBAL float2* gC = to_global(J.C + off);
+    auto none = [](int, float2 x) { return x; };
+    auto nothing = []() {};
+    auto no_load = [](int, int) { return make_float2(0.f, 0.f); };
+    auto no_store = [](int, int, float2) {};
     {
-      constexpr int H = M / 2;
-      float2 v[H];
-      strided_issue<B, H>(v, to_global(J.A + off), astr, n, bw, tid, 0);
-      // the tables are copied while the first batch is in flight
-      copy_table(tw, J.tw, n, tid);
-      copy_table(win, J.win, n / 2 + 1, tid);
-      strided_put<B, H>(tile, v, n, tid, 0);
-      strided_issue<B, H>(v, to_global(J.A + off), astr, n, bw, tid, 1);
-      strided_put<B, H>(tile, v, n, tid, 1);
+      // forward transform: the first stage reads delta_hat from HBM; the tables are copied while its loads are in
+      // flight; the result stays in the tile (natural order)
+      auto load = [&](int j, int b) { return b < bw ? gA[j * astr + b] : make_float2(0.f, 0.f); };
+      auto mid = [&]() {
+        copy_table(tw, J.tw, n, tid);
+        copy_table(win, J.win, n / 2 + 1, tid);
+      };
+      fft_io_fast<false, M, B, BP, true, false>(tile, tw, J.pl, tid, load, none, mid, no_store);
     }
-    __syncthreads();
-    fft_tile_fast<false, M, B, BP, false>(tile, tw, J.pl, tid);
 
     // Each thread touches only its own points between the barriers that bracket the inverse transforms.
     const int half = nm / 2;
@@ -547,8 +550,13 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
       }
     }
     __syncthreads();
-    fft_tile_fast<true, M, B, BP, false>(tile, tw, J.pl, tid);
-    store_strided<B, M>(tile, to_global(J.A + off), astr, n, bw, tid);
+    {
+      // first inverse transform: the last stage writes the x gradient to A
+      auto store = [&](int j, int b, float2 v) {
+        if (b < bw) gA[j * astr + b] = v;
+      };
+      fft_io_fast<true, M, B, BP, false, true>(tile, tw, J.pl, tid, no_load, none, nothing, store);
+    }
     __syncthreads();
     {
       // (the empty asm keeps the comp-invariant indices of the first inverse transform from staying live)
@@ -561,9 +569,12 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
         if (j < n) tile[j * BP + b] = kRegs ? ph[kRegs ? m : 0] : ph_lds[j * BP + b];
       }
       __syncthreads();
-      fft_tile_fast<true, M, B, BP, false>(tile, tw, J.pl, ltid);
-      // the x-transformed potential: the y and z gradients are i k_y and i k_z times it (applied by the y and z passes)
-      store_strided<B, M>(tile, to_global(J.C + off), astr, n, bw, ltid);
+      // the x-transformed potential: the y and z gradients are i k_y and i k_z times it (applied by the y and z
+      // passes); the last stage writes it to C
+      auto store = [&](int j, int b, float2 v) {
+        if (b < bw) gC[j * astr + b] = v;
+      };
+      fft_io_fast<true, M, B, BP, false, true>(tile, tw, J.pl, ltid, no_load, none, nothing, store);
     }
   }
 }
