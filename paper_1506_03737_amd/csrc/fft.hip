@@ -149,10 +149,15 @@ __device__ __forceinline__ void fft_io_fast(float2* tile, const float2* tw, cons
   LPC_TRY_IO(8, 8, 5)
   LPC_TRY_IO(8, 8, 4)
   LPC_TRY_IO(8, 8, 3)
+  LPC_TRY_IO(4, 4, 8, 8)  // 1024: the large box
+  LPC_TRY_IO(4, 8, 12)    // 384: the learned form's fine training runs
 #undef LPC_TRY_IO
-  const int n = pl.n;
-  if constexpr (GIN) {
-    for (int e = tid; e < n * B; e += kFftNT) {
+  // other plans: fill the tile (n B <= EPT kFftNT values), transform it in place, store it. With 12 or more points per
+  // thread (the largest meshes) the loads go out in unrolled batches of four per thread, so that each batch's loads
+  // are in flight together; the 80-register instances keep a plain loop (the batches would spill them).
+  const int n = pl.n, count = n * B;
+  if constexpr (GIN && EPT < 12) {
+    for (int e = tid; e < count; e += kFftNT) {
       const int j = e / B, b = e % B;
       if constexpr (PAIRS) {
         const float2 x = load(j, b % (B / 2));
@@ -163,10 +168,41 @@ __device__ __forceinline__ void fft_io_fast(float2* tile, const float2* tw, cons
     }
     mid();
     __syncthreads();
+  } else if constexpr (GIN) {
+    constexpr int H = 4, NH = (EPT + H - 1) / H;
+#pragma unroll
+    for (int half = 0; half < NH; ++half) {
+      float2 v[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const int e = tid + (half * H + m) * kFftNT;
+        v[m] = make_float2(0.f, 0.f);
+        if (e < count) {
+          const int j = e / B, b = e % B;
+          if constexpr (PAIRS) {
+            const float2 x = load(j, b % (B / 2));
+            v[m] = (b < B / 2) ? pair(j, x) : x;
+          } else {
+            v[m] = load(j, b);
+          }
+        }
+      }
+      if (half == 0) mid();
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        const int e = tid + (half * H + m) * kFftNT;
+        if (e < count) tile[(e / B) * BP + (e % B)] = v[m];
+      }
+    }
+    __syncthreads();
   }
   fft_tile<INV, EPT, true>(tile, tw, pl, B, BP, tid);
   if constexpr (GOUT) {
-    for (int e = tid; e < n * B; e += kFftNT) store(e / B, e % B, tile[(e / B) * BP + (e % B)]);
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+      const int e = tid + m * kFftNT;
+      if (e < count) store(e / B, e % B, tile[(e / B) * BP + (e % B)]);
+    }
   }
 }
 
