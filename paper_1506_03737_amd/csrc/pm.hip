@@ -42,6 +42,32 @@ __device__ __forceinline__ bool fixed_coord(float x, double scale, int64_t perio
   return true;
 }
 
+// The three axes of a position at once: one branch for the common case (every axis inside the box) instead of one
+// per axis; each branch a wave takes divergently costs the scalar unit an exec-mask save and restore.
+__device__ __forceinline__ bool fixed_coord3(const float x[3], double scale, int64_t period, uint32_t c[3],
+                                             uint32_t f[3]) {
+  double xs[3];
+  bool in = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xs[d] = static_cast<double>(x[d]) * scale;
+    in = in && xs[d] >= 0.0 && xs[d] < static_cast<double>(period);
+  }
+  if (in) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const uint32_t u = static_cast<uint32_t>(xs[d]);
+      c[d] = u >> kFracBits;
+      f[d] = u & kMask;
+    }
+    return true;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ok &= fixed_coord(x[d], scale, period, &c[d], &f[d]);
+  return ok;
+}
+
 // a b for a < 2^33 and b <= 2^16 (a product of two axis weights times a third): one 32 x 32 -> 64 multiply-add for
 // the low word and a 32-bit multiply for the high one.
 __device__ __forceinline__ uint64_t mul_weight(uint64_t a, uint32_t b) {
@@ -319,10 +345,7 @@ __device__ __forceinline__ void deposit_pass(const TileRanges tr, int tot, LPC_G
     for (int u = 0; u < kUnroll; ++u) {
       if (q0 + u * kNT >= tot) continue;
       uint32_t c[3], f[3];
-      bool ok = true;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) ok &= fixed_coord(px[u][d], scale, period, &c[d], &f[d]);
-      if (!ok) continue;  // cannot happen for a bucketed particle; kept as a guard
+      if (!fixed_coord3(px[u], scale, period, c, f)) continue;  // cannot happen for a bucketed particle
       // corner offsets relative to the tile origin (periodic), in [0, kT*) when inside
       int lx[2], ly[2], lz[2];
 #pragma unroll
@@ -336,18 +359,19 @@ __device__ __forceinline__ void deposit_pass(const TileRanges tr, int tot, LPC_G
         lz[a] = cz - z0;
       }
       const uint32_t wx[2] = {kOne - f[0], f[0]}, wy[2] = {kOne - f[1], f[1]}, wz[2] = {kOne - f[2], f[2]};
+      // one predicate per corner (inside the tile and a non-zero weight) instead of nested per-axis branches: each
+      // divergent branch costs the scalar unit an exec-mask save and restore
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        if (static_cast<unsigned>(lx[a]) >= static_cast<unsigned>(kTX)) continue;
+        const bool in_x = static_cast<unsigned>(lx[a]) < static_cast<unsigned>(kTX);
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb) {
-          if (static_cast<unsigned>(ly[bb]) >= static_cast<unsigned>(kTY)) continue;
+          const bool in_xy = in_x && static_cast<unsigned>(ly[bb]) < static_cast<unsigned>(kTY);
           const uint64_t wab = static_cast<uint64_t>(wx[a]) * wy[bb];  // <= 2^32
 #pragma unroll
           for (int e2 = 0; e2 < 2; ++e2) {
-            if (static_cast<unsigned>(lz[e2]) >= static_cast<unsigned>(kTZ)) continue;
             const uint64_t wt = mul_weight(wab, wz[e2]) >> shift;
-            if (wt != 0)
+            if (in_xy && static_cast<unsigned>(lz[e2]) < static_cast<unsigned>(kTZ) && wt != 0)
               __hip_atomic_fetch_add(&acc[(lx[a] * kTY + ly[bb]) * kTZ + lz[e2]],
                                      static_cast<unsigned long long>(wt), __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -358,10 +382,46 @@ __device__ __forceinline__ void deposit_pass(const TileRanges tr, int tot, LPC_G
   }
 }
 
+// Zeroes the tile's counts with 16-byte LDS stores, fully unrolled (no loop control on the scalar unit).
+__device__ __forceinline__ void clear_tile(unsigned long long* acc, int tid) {
+  static_assert(kTileCells % (2 * kNT) == 0, "whole 16-byte rounds");
+  ulonglong2* a2 = reinterpret_cast<ulonglong2*>(acc);
+#pragma unroll
+  for (int m = 0; m < kTileCells / (2 * kNT); ++m) a2[tid + m * kNT] = make_ulonglong2(0ull, 0ull);
+}
+
+// Writes cell (j, k) of the x-planes 0 .. wx - 1 of the tile from acc: the int64 counts (TO_D false) or the FP32
+// contrast v mscale - 1 (TO_D true). cell is the cell's index in plane 0, plane the cells of one x-plane. Returns
+// whether a count has bit 63 set. Full-width tiles run the unrolled loop with no per-plane test.
+template <bool TO_D>
+__device__ __forceinline__ bool write_tile_column(const unsigned long long* acc, int tid, int wx, size_t cell,
+                                                  size_t plane, LPC_GLOBAL unsigned long long* C, LPC_GLOBAL float* D,
+                                                  double mscale) {
+  bool overflow = false;
+  auto put = [&](int i, size_t at) {
+    const unsigned long long v = acc[i * kNT + tid];
+    overflow |= (v >> 63) != 0;
+    if constexpr (TO_D) {  // v in FP64 (hi 2^32 + lo, rounded once: the correctly rounded conversion), then C mscale - 1
+      const double cv = fma(static_cast<double>(static_cast<uint32_t>(v >> 32)), 4294967296.0,
+                            static_cast<double>(static_cast<uint32_t>(v)));
+      D[at] = static_cast<float>(cv * mscale - 1.0);
+    } else {
+      C[at] = v;
+    }
+  };
+  if (wx == kTX) {
+#pragma unroll
+    for (int i = 0; i < kTX; ++i, cell += plane) put(i, cell);
+  } else {
+    for (int i = 0; i < wx; ++i, cell += plane) put(i, cell);
+  }
+  return overflow;
+}
+
 __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict__ jobs, const int* __restrict__ offs,
                                                        int njob, int total, const int* __restrict__ start,
                                                        int* __restrict__ flags) {
-  __shared__ unsigned long long acc[kTileCells];
+  __shared__ __align__(16) unsigned long long acc[kTileCells];
   const int w = blockIdx.x;
   if (w >= total) return;
   const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
@@ -371,7 +431,7 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   const int t = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]);
   if (t >= ntx * nty * ntz) return;  // padding item
   const int tid = threadIdx.x;
-  for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
+  clear_tile(acc, tid);
   const int tx = t / (nty * ntz), ty = (t / ntz) % nty, tz = t % ntz;
   const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
   // the particle ranges (local indices, uniform): own tile, then the boundary bucket of each distinct lower
@@ -384,7 +444,8 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   for (int q = 0; q < 8; ++q) {
     const int dx = (q >> 2) & 1, dy = (q >> 1) & 1, dz = q & 1;  // 1 = the lower neighbour along that axis
     const bool use = (mx || !dx) && (my || !dy) && (mz || !dz);
-    const int sx = dx ? (tx + ntx - 1) % ntx : tx, sy = dy ? (ty + nty - 1) % nty : ty, sz = dz ? (tz + ntz - 1) % ntz : tz;
+    const int sx = dx ? (tx == 0 ? ntx - 1 : tx - 1) : tx, sy = dy ? (ty == 0 ? nty - 1 : ty - 1) : ty,
+              sz = dz ? (tz == 0 ? ntz - 1 : tz - 1) : tz;
     const int g = J.tbase + 2 * ((sx * nty + sy) * ntz + sz);
     bs[q] = use ? start[q == 0 ? g : g + 1] : 0;
     es[q] = use ? start[g + 2] : 0;
@@ -430,26 +491,17 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   const int j = tid / kTZ, k = tid % kTZ;
   if (j < wy_ && k < wz_) {
     const size_t plane = static_cast<size_t>(nm) * nm;
-    size_t cell = (static_cast<size_t>(x0) * nm + (y0 + j)) * nm + (z0 + k);
-#pragma unroll
-    for (int i = 0; i < kTX; ++i, cell += plane) {
-      if (i >= wx_) break;  // uniform: a narrow last tile along x
-      const unsigned long long v = acc[i * kNT + tid];
-      overflow |= (v >> 63) != 0;
-      if (C) C[cell] = v;
-      if (D) {  // v in FP64 (hi 2^32 + lo, rounded once: the correctly rounded conversion), then C mscale - 1
-        const double cv = fma(static_cast<double>(static_cast<uint32_t>(v >> 32)), 4294967296.0,
-                              static_cast<double>(static_cast<uint32_t>(v)));
-        D[cell] = static_cast<float>(cv * mscale - 1.0);
-      }
-    }
+    const size_t cell = (static_cast<size_t>(x0) * nm + (y0 + j)) * nm + (z0 + k);
+    // (a job writes the contrast or the counts, not both; both pointers set would write both)
+    if (D) overflow |= write_tile_column<true>(acc, tid, wx_, cell, plane, C, D, mscale);
+    if (C) overflow |= write_tile_column<false>(acc, tid, wx_, cell, plane, C, D, mscale);
   }
   if (tot >= kWrapParticles) {  // uniform; rare (a tile reached by 65536 particles or more)
     unsigned long long S[kTX];
 #pragma unroll
     for (int i = 0; i < kTX; ++i) S[i] = acc[i * kNT + tid];
     __syncthreads();
-    for (int c = tid; c < kTileCells; c += kNT) acc[c] = 0ull;
+    clear_tile(acc, tid);
     __syncthreads();
     deposit_pass(tr, tot, pos, J.n, J.scale, nm, x0, y0, z0, acc, kFracBits);
     __syncthreads();
