@@ -666,6 +666,8 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
       d.ntx = nt.x;
       d.nty = nt.y;
       d.ntz = nt.z;
+      d.inv_yz = kern::div_inverse(nt.y * nt.z);
+      d.inv_z = kern::div_inverse(nt.z);
       d.nm = nm;
       d.scale = scale;
       d.mscale = (static_cast<double>(M) / static_cast<double>(b.n)) * 0x1.0p-48;
@@ -1624,6 +1626,8 @@ DensitySpectrum add_density_spectrum(JobPack& jp, void* ws, const Plan& p, const
   dj.ntx = nt.x;
   dj.nty = nt.y;
   dj.ntz = nt.z;
+  dj.inv_yz = kern::div_inverse(nt.y * nt.z);
+  dj.inv_z = kern::div_inverse(nt.z);
   dj.nm = nm;
   dj.scale = sj.scale;
   dj.delta = reinterpret_cast<float*>(at(ws, p.dens));  // the FP32 contrast, in the density region

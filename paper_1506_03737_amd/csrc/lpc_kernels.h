@@ -157,11 +157,17 @@ struct SortJob {        // key pass and scatter of one box: src (SoA [3][n]) -> 
   int ntx, nty, ntz;    // tiles along x, y, z
   double scale;         // nm 2^16 / box
 };
+// ceil(2^32 / d) for d > 1, 0 for d = 1: the reciprocal with which t / d = mulhi(t, inv) for t < 2^32 / d
+inline uint32_t div_inverse(int d) {
+  return d <= 1 ? 0u : static_cast<uint32_t>(((uint64_t(1) << 32) + static_cast<uint64_t>(d) - 1) / static_cast<uint64_t>(d));
+}
+
 struct DepJob {         // tiled deposit of one box from its tile-sorted positions
   const float* pos;
   int64_t n, pbase;
   int tbase, nm;
   int ntx, nty, ntz;
+  uint32_t inv_yz, inv_z;  // div_inverse(nty ntz), div_inverse(ntz): tiles number fewer than 2^32 / (nty ntz)
   double scale;
   uint64_t* dens;       // int64 counts, or NULL
   float* delta;         // FP32 density contrast C mscale - 1, or NULL

@@ -75,6 +75,11 @@ __device__ __forceinline__ uint64_t mul_weight(uint64_t a, uint32_t b) {
          (static_cast<uint64_t>(static_cast<uint32_t>(a >> 32) * b) << 32);
 }
 
+// t / d for t < 2^32 / d, with inv = ceil(2^32 / d) computed on the host (0 for d = 1): one high multiply.
+__device__ __forceinline__ uint32_t fast_div(int t, uint32_t inv) {
+  return inv ? __umulhi(static_cast<uint32_t>(t), inv) : static_cast<uint32_t>(t);
+}
+
 __device__ __forceinline__ int find_job(const LPC_CONST int* __restrict__ offs, int njob, int w) {
   int lo = 0, hi = njob - 1;
   while (lo < hi) {
@@ -432,7 +437,11 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   if (t >= ntx * nty * ntz) return;  // padding item
   const int tid = threadIdx.x;
   clear_tile(acc, tid);
-  const int tx = t / (nty * ntz), ty = (t / ntz) % nty, tz = t % ntz;
+  // t = (tx nty + ty) ntz + tz, split with the job's reciprocals instead of runtime divisions (exact: t < ntx nty ntz
+  // and ntx (nty ntz)^2 < 2^32 for every mesh up to 1024)
+  const int txy = static_cast<int>(fast_div(t, J.inv_z));  // tx nty + ty
+  const int tx = static_cast<int>(fast_div(t, J.inv_yz));
+  const int ty = txy - tx * nty, tz = t - txy * ntz;
   const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
   // the particle ranges (local indices, uniform): own tile, then the boundary bucket of each distinct lower
   // neighbour. All sixteen bucket bounds are loaded before any is used (one memory round trip, not eight).
@@ -446,9 +455,12 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
     const bool use = (mx || !dx) && (my || !dy) && (mz || !dz);
     const int sx = dx ? (tx == 0 ? ntx - 1 : tx - 1) : tx, sy = dy ? (ty == 0 ? nty - 1 : ty - 1) : ty,
               sz = dz ? (tz == 0 ? ntz - 1 : tz - 1) : tz;
+    // always in range (an axis with one tile names the tile itself), so loaded without a branch; unused ones are
+    // skipped below
     const int g = J.tbase + 2 * ((sx * nty + sy) * ntz + sz);
-    bs[q] = use ? start[q == 0 ? g : g + 1] : 0;
-    es[q] = use ? start[g + 2] : 0;
+    (void)use;
+    bs[q] = start[q == 0 ? g : g + 1];
+    es[q] = start[g + 2];
   }
   int rb[8], cum[9];
   int nr = 0;
