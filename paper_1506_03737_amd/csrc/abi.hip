@@ -576,6 +576,7 @@ struct ForceProgram {
   Section zr2c, yfwd, pois, yinv, zc2r;
   int Bz = 32, Bax = 32, Bp = 16, R3 = 16;
   int Mp = 8;  // points per thread of the fused x + Poisson tiles: the largest over the boxes
+  bool chain_p = false;  // the fused x pass chains its transforms through registers (every plan 8 x 8 x R, 8 columns)
   int P3 = 8;  // points per thread of the three-spectrum c2r tiles: the largest over the boxes
   int Pax = 8;  // points per thread of the strided y tiles: the largest over the boxes
   int Pz = 8;   // points per thread of the forward z tiles: the largest over the boxes
@@ -605,6 +606,8 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     f.Pax = std::max(f.Pax, kern::axis_points(b.nm, f.Bax));
     f.Pz = std::max(f.Pz, kern::r2c_points(b.nm, f.Bz));
   }
+  f.chain_p = f.Bp == 8 && f.Mp <= 12;
+  for (const ForceBox& b : boxes) f.chain_p = f.chain_p && kern::poisson_chainable(plan_of(b.nm));
   const int ncopy = cola_run ? 2 : 1;
   std::vector<kern::SortJob> su, sn[2];
   std::vector<kern::DepJob> dj[2];
@@ -745,6 +748,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     p.inv_m3 = static_cast<float>(1.0 / static_cast<double>(M));
     p.pl = plan_of(nm);
     p.tw = jp.twiddles(p.pl);
+    p.tw_rev = jp.twiddles(kern::reversed_plan(p.pl));
     p.win = jp.sinc2(nm);
     ps.push_back(p);
     i_p.push_back(nm * p.ntc);
@@ -811,7 +815,7 @@ void run_force_mesh(const JobPack& jp, const ForceProgram& f, int c, int* flags,
                               s);
   });
   stage("fft y", s, [&] { return kern::launch_axis(jp.jobs<kern::AxisJob>(f.yfwd), jp.table(f.yfwd), false, f.Bax, f.Pax, f.lds_ax, s); });
-  stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.Mp, f.lds_p, s); });
+  stage("fft x + poisson", s, [&] { return kern::launch_poisson(jp.jobs<kern::PoissonJob>(f.pois), jp.table(f.pois), f.Bp, f.Mp, f.chain_p, f.lds_p, s); });
   stage("fft y inv", s, [&] { return kern::launch_y_grad(jp.jobs<kern::YGradJob>(f.yinv), jp.table(f.yinv), f.Bax, f.Pax, f.lds_ax, s); });
   stage("fft z c2r", s, [&] { return kern::launch_z_c2r(jp.jobs<kern::ZC2RJob>(f.zc2r), jp.table(f.zc2r), 3, f.R3, f.P3, f.lds_c, s); });
 }

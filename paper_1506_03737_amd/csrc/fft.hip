@@ -21,6 +21,9 @@
 namespace lpc {
 namespace kern {
 
+// p[s], pmask[s] and tw_off[s] of a plan whose radices are set
+static void set_strides(Plan1D* p);
+
 bool make_plan(int n, Plan1D* p, bool radix12) {
   if (n < 1) return false;
   int m = n, ns = 0;
@@ -65,6 +68,18 @@ bool make_plan(int n, Plan1D* p, bool radix12) {
   if (r12) p->radix[p->nst++] = 12;
   for (int i = 0; i < ns; ++i)
     if (!(r12 && i == i3)) p->radix[p->nst++] = odd[i];
+  set_strides(p);
+  return true;
+}
+
+Plan1D reversed_plan(const Plan1D& p) {
+  Plan1D r = p;
+  for (int s = 0; s < p.nst; ++s) r.radix[s] = p.radix[p.nst - 1 - s];
+  set_strides(&r);
+  return r;
+}
+
+static void set_strides(Plan1D* p) {
   int prod = 1, off = 0;
   for (int s = 0; s < p->nst; ++s) {
     p->p[s] = prod;
@@ -73,7 +88,6 @@ bool make_plan(int n, Plan1D* p, bool radix12) {
     off += prod * (p->radix[s] - 1);
     prod *= p->radix[s];
   }
-  return true;
 }
 
 int mesh_pitch(int n) { return ((n / 2 + 1) + 7) / 8 * 8; }
@@ -249,10 +263,11 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     // of kFftNT = dq h + dr.
     const int dq = kFftNT / h, dr = kFftNT - dq * h;
     const int b0 = tid / h, j0 = tid - b0 * h;
-    // The global loads are issued before the twiddle tables are computed, so the tables overlap their latency.
     // The item's rows are contiguous in the input, so element e is at offset row0 h + e (in complex values); rows past
     // the last are not read.
     const int valid = min(count, (nrows - row0) * h);
+    // the tables' loads go out first, so that writing them to LDS waits for them only
+    const TableRegs<float2> r_tw = table_load(J.tw, h, tid), r_roots = table_load(J.roots, h + 1, tid);
     if (FIXED) {
       LPC_GLOBAL const ulonglong2* in =
           reinterpret_cast<LPC_GLOBAL const ulonglong2*>(to_global(static_cast<const uint64_t*>(J.in))) +
@@ -270,8 +285,8 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
           if (e < valid) raw[m] = in[e];
         }
         if (half == 0) {
-          copy_table(tw, J.tw, h, tid);
-          copy_table(roots, J.roots, h + 1, tid);
+          table_store(tw, r_tw, h, tid);
+          table_store(roots, r_roots, h + 1, tid);
         }
         bool overflow = false;
         b = bb;
@@ -308,8 +323,8 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
         v[m] = make_float2(0.f, 0.f);
         if (e < valid) v[m] = in[e];
       }
-      copy_table(tw, J.tw, h, tid);
-      copy_table(roots, J.roots, h + 1, tid);
+      table_store(tw, r_tw, h, tid);
+      table_store(roots, r_roots, h + 1, tid);
       int b = b0, j = j0;
 #pragma unroll
       for (int m = 0; m < EPT; ++m) {
@@ -502,15 +517,61 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
 }
 
 // ---------------------------------------------------------------------------------------------------------------
+// The fused x pass for the plans 8 x 8 x R (R = 12, 5, 4, 3: meshes 768, 320, 256, 192) on 8-column tiles, with its
+// three transforms chained through registers. The forward transform's last stage has one radix-R butterfly per thread:
+// thread (i, b) = (tid / 8, tid % 8) ends with rows i + 64 r (r < R) of column b in its registers, in natural order.
+// factor(row, g, ph) turns each into psi_hat (ph) and i k_x psi_hat (g) there. Both inverse transforms run the plan
+// in reverse order (R x 8 x 8, stage twiddles twr), whose first stage takes exactly those rows, so neither spectrum
+// goes back through the tile between the transforms: per tile 12 LDS passes and 9 barriers instead of 18 and 15.
+template <int R, int M, class PL, class Load, class Mid, class MakeFactor, class StoreA, class StoreC>
+__device__ __forceinline__ bool x_poisson_chained(float2* tile, const float2* tw, const float2* twr, const PL& pl,
+                                                  int tid, Load load, Mid mid, MakeFactor make_factor,
+                                                  StoreA store_a, StoreC store_c) {
+  constexpr int B = 8, BP = strided_pitch(B), N = 64 * R;
+  using Fwd = FixedFFT<false, M, B, BP, 8, 8, R>;
+  if constexpr (!Fwd::kFits) return false;
+  else {
+  if (!Fwd::matches(pl)) return false;
+  // forward: radix 8 from HBM, radix 8, radix R into registers
+  fft_stage_from_global<8, false, M, N, B, BP>(tile, load, mid, tid);
+  __syncthreads();
+  fft_stage_c<8, false, M, N, 8, B, BP>(tile, tw + 7, tid);
+  float2 g[R], ph[R];
+  fft_stage_to_regs<R, false, N, 64, B, BP>(tile, tw + 7 + 8 * 7, tid, g);
+  {
+    const auto factor = make_factor();
+    const int i = tid / B;
+#pragma unroll
+    for (int r = 0; r < R; ++r) factor(i + 64 * r, g[r], ph[r]);
+  }
+  __syncthreads();  // the tile has been read
+  // first inverse: i k_x psi_hat -> the x gradient in A
+  fft_stage_from_regs<R, true, N, B, BP>(tile, g, tid);
+  __syncthreads();
+  fft_stage_c<8, true, M, N, R, B, BP>(tile, twr + (R - 1), tid);
+  fft_stage_to_global<8, true, M, N, 8 * R, B, BP>(tile, twr + (R - 1) + R * 7, store_a, tid);
+  __syncthreads();
+  // second inverse: psi_hat -> the x-transformed potential in C
+  fft_stage_from_regs<R, true, N, B, BP>(tile, ph, tid);
+  __syncthreads();
+  fft_stage_c<8, true, M, N, R, B, BP>(tile, twr + (R - 1), tid);
+  fft_stage_to_global<8, true, M, N, 8 * R, B, BP>(tile, twr + (R - 1) + R * 7, store_c, tid);
+  return true;
+  }
+}
+
 // Fused x pass of the force. With psi_hat = -delta_hat / (k^2 W^p Nm^3) (zero at k = 0; W = prod_d sinc^2(pi n_d /
 // Nm); the 1/Nm^3 of the inverse transform folded in), the gradient spectra are g_hat_j = i k_j psi_hat, zero on the
 // Nyquist plane of axis j. Along the x transform k_y and k_z are constant (per tile and per column), so
 //   IFFT_x(g_hat_x) = IFFT_x(i k_x psi_hat) -> A,   IFFT_x(g_hat_{y,z}) = i k_{y,z} IFFT_x(psi_hat), IFFT_x(psi_hat) -> C:
-// one forward and two inverse transforms per tile, two spectra written. psi_hat is kept between them. Each thread owns the points of column
-// b at rows j0 + m S, at most M of them (M = n B / kFftNT rounded up to 8, 12 or 16): with M <= 12 they stay in the
-// thread's registers, so the workgroup needs one LDS tile and two workgroups fit on a CU; with M = 16 a second LDS
-// tile holds them (the registers would spill).
-template <int B, int M>
+// one forward and two inverse transforms per tile, two spectra written. psi_hat is kept between them. The CHAIN
+// instances (B = 8, M <= 12) run every job's transforms chained through registers (x_poisson_chained): the host
+// launches them only when every job's plan is 8 x 8 x R (poisson_chainable). Otherwise each thread owns the points of
+// column b at rows j0 + m S, at most M of them (M = n B / kFftNT rounded up to 8, 12 or 16): with M <= 12 they stay
+// in the thread's registers, so the workgroup needs one LDS tile and two workgroups fit on a CU; with M = 16 a second
+// LDS tile holds them (the registers would spill). The two forms are separate instances because the generic form's
+// register allocation would otherwise cover the chained form's too (and spill).
+template <int B, int M, bool CHAIN>
 __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(const PoissonJob* __restrict__ jobs,
                                                                             const int* __restrict__ offs, int njob,
                                                                             int total) {
@@ -530,43 +591,25 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
     float2* tile = smem;
     float2* ph_lds = tile + n * BP;  // psi_hat when !kRegs
     float2* tw = tile + (kRegs ? 1 : 2) * n * BP;
-    float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
+    float2* twr = tw + n;                           // twiddles of the reversed plan (chained form)
+    float* win = reinterpret_cast<float*>(twr + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
     const int c0 = ct * B, bw = min(B, nh - c0);
     const int64_t astr = static_cast<int64_t>(nm) * pitch;
     const int64_t off = static_cast<int64_t>(y) * pitch + c0;
     LPC_GLOBAL float2* gA = to_global(J.A + off);
     LPC_GLOBAL float2* gC = to_global(J.C + off);
-    auto none = [](int, float2 x) { return x; };
-    auto nothing = []() {};
-    auto no_load = [](int, int) { return make_float2(0.f, 0.f); };
-    auto no_store = [](int, int, float2) {};
-    {
-      // forward transform: the first stage reads delta_hat from HBM; the tables are copied while its loads are in
-      // flight; the result stays in the tile (natural order)
-      auto load = [&](int j, int b) { return b < bw ? gA[j * astr + b] : make_float2(0.f, 0.f); };
-      auto mid = [&]() {
-        copy_table(tw, J.tw, n, tid);
-        copy_table(win, J.win, n / 2 + 1, tid);
-      };
-      fft_io_fast<false, M, B, BP, true, false>(tile, tw, J.pl, tid, load, none, mid, no_store);
-    }
-
-    // Each thread touches only its own points between the barriers that bracket the inverse transforms.
     const int half = nm / 2;
     const int ny = (y <= half) ? y : y - nm;
     const float kf = J.kf, inv_m3 = J.inv_m3;
     const int deconv = J.deconv;
-    float2 ph[kRegs ? M : 1];
-    {
-      const int b = tid % B, j0 = tid / B;
-      const int nz = c0 + b;
+    // The Poisson factor of this thread's column b = tid % B (read once the window table is in LDS):
+    // factor(j, g, ph) takes the forward spectrum at row j in g and leaves psi_hat in ph and i k_x psi_hat in g.
+    auto make_factor = [&]() {
+      const int b = tid % B, nz = c0 + b;
       const bool col_ok = b < bw;
       const float wyz = win[min(y, n - y)] * win[min(nz, half)];
       const int nyz2 = ny * ny + nz * nz;
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const int j = j0 + m * S;
-        if (j >= n) continue;
+      return [=](int j, float2& g, float2& ph) {
         const int nx = (j <= half) ? j : j - nm;
         const float k2 = kf * kf * static_cast<float>(nx * nx + nyz2);
         float sc = 0.f;
@@ -575,42 +618,87 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
           const float wp = (deconv == 0) ? 1.f : (deconv == 1 ? W : W * W);
           sc = -inv_m3 * __builtin_amdgcn_rcpf(k2 * wp);  // hardware reciprocal (1 ulp) instead of a division
         }
-        const float2 d = tile[j * BP + b];
-        const float2 psi = make_float2(sc * d.x, sc * d.y);
-        if (kRegs)
-          ph[kRegs ? m : 0] = psi;
-        else
-          ph_lds[j * BP + b] = psi;
+        ph = make_float2(sc * g.x, sc * g.y);
         const float kx = (nx == half) ? 0.f : kf * static_cast<float>(nx);
-        tile[j * BP + b] = make_float2(-kx * psi.y, kx * psi.x);  // i k_x psi_hat
-      }
-    }
-    __syncthreads();
-    {
-      // first inverse transform: the last stage writes the x gradient to A
-      auto store = [&](int j, int b, float2 v) {
-        if (b < bw) gA[j * astr + b] = v;
+        g = make_float2(-kx * ph.y, kx * ph.x);
       };
-      fft_io_fast<true, M, B, BP, false, true>(tile, tw, J.pl, tid, no_load, none, nothing, store);
-    }
-    __syncthreads();
-    {
-      // (the empty asm keeps the comp-invariant indices of the first inverse transform from staying live)
-      int ltid = tid;
-      asm volatile("" : "+v"(ltid));
-      const int b = ltid % B, j0 = ltid / B;
+    };
+    auto load = [&](int j, int b) { return b < bw ? gA[j * astr + b] : make_float2(0.f, 0.f); };
+    auto store_a = [&](int j, int b, float2 v) {
+      if (b < bw) gA[j * astr + b] = v;
+    };
+    auto store_c = [&](int j, int b, float2 v) {
+      if (b < bw) gC[j * astr + b] = v;
+    };
+    if constexpr (CHAIN) {
+      static_assert(B == 8 && kRegs, "the chained form takes 8-column tiles held in registers");
+      // the tables' loads go out first; mid() writes them to LDS while the first stage's loads are in flight
+      const TableRegs<float2> r_tw = table_load(J.tw, n, tid), r_twr = table_load(J.tw_rev, n, tid);
+      const TableRegs<float> r_win = table_load(J.win, n / 2 + 1, tid);
+      auto mid = [&]() {
+        table_store(tw, r_tw, n, tid);
+        table_store(twr, r_twr, n, tid);
+        table_store(win, r_win, n / 2 + 1, tid);
+      };
+      if (x_poisson_chained<12, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c)) return;
+      if (x_poisson_chained<5, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c)) return;
+      if (x_poisson_chained<4, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c)) return;
+      x_poisson_chained<3, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c);
+      return;
+    } else {
+      auto none = [](int, float2 x) { return x; };
+      auto nothing = []() {};
+      auto no_load = [](int, int) { return make_float2(0.f, 0.f); };
+      auto no_store = [](int, int, float2) {};
+      {
+        // forward transform: the first stage reads delta_hat from HBM; the tables are copied while its loads are in
+        // flight; the result stays in the tile (natural order)
+        const TableRegs<float2> r_tw = table_load(J.tw, n, tid);
+        const TableRegs<float> r_win = table_load(J.win, n / 2 + 1, tid);
+        auto mid = [&]() {
+          table_store(tw, r_tw, n, tid);
+          table_store(win, r_win, n / 2 + 1, tid);
+        };
+        fft_io_fast<false, M, B, BP, true, false>(tile, tw, J.pl, tid, load, none, mid, no_store);
+      }
+
+      // Each thread touches only its own points between the barriers that bracket the inverse transforms.
+      float2 ph[kRegs ? M : 1];
+      {
+        const auto factor = make_factor();
+        const int b = tid % B, j0 = tid / B;
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        const int j = j0 + m * S;
-        if (j < n) tile[j * BP + b] = kRegs ? ph[kRegs ? m : 0] : ph_lds[j * BP + b];
+        for (int m = 0; m < M; ++m) {
+          const int j = j0 + m * S;
+          if (j >= n) continue;
+          float2 g = tile[j * BP + b], psi;
+          factor(j, g, psi);
+          if (kRegs)
+            ph[kRegs ? m : 0] = psi;
+          else
+            ph_lds[j * BP + b] = psi;
+          tile[j * BP + b] = g;  // i k_x psi_hat
+        }
       }
       __syncthreads();
-      // the x-transformed potential: the y and z gradients are i k_y and i k_z times it (applied by the y and z
-      // passes); the last stage writes it to C
-      auto store = [&](int j, int b, float2 v) {
-        if (b < bw) gC[j * astr + b] = v;
-      };
-      fft_io_fast<true, M, B, BP, false, true>(tile, tw, J.pl, ltid, no_load, none, nothing, store);
+      // first inverse transform: the last stage writes the x gradient to A
+      fft_io_fast<true, M, B, BP, false, true>(tile, tw, J.pl, tid, no_load, none, nothing, store_a);
+      __syncthreads();
+      {
+        // (the empty asm keeps the comp-invariant indices of the first inverse transform from staying live)
+        int ltid = tid;
+        asm volatile("" : "+v"(ltid));
+        const int b = ltid % B, j0 = ltid / B;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          const int j = j0 + m * S;
+          if (j < n) tile[j * BP + b] = kRegs ? ph[kRegs ? m : 0] : ph_lds[j * BP + b];
+        }
+        __syncthreads();
+        // the x-transformed potential: the y and z gradients are i k_y and i k_z times it (applied by the y and z
+        // passes); the last stage writes it to C
+        fft_io_fast<true, M, B, BP, false, true>(tile, tw, J.pl, ltid, no_load, none, nothing, store_c);
+      }
     }
   }
 }
@@ -651,6 +739,8 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     constexpr int MC = (EPT + NC - 1) / NC;
     const int per = R * h;
     const int dq = kFftNT / h, dr = kFftNT - dq * h;
+    // the tables' loads go out first, so that writing them to LDS waits for them only
+    const TableRegs<float2> r_tw = table_load(J.tw, h, tid), r_roots = table_load(J.roots, h + 1, tid);
     {
       int64_t goff[MC];  // global element offset (row0 + r) pitch + k, or -1 for no element
       int loff[MC];      // tile offset k BP + r NC
@@ -687,9 +777,9 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
         LPC_GLOBAL const float2* src = (nyq_c == 0) ? in0 : (nyq_c == 1 ? in1 : in2);
         nyq = src[static_cast<size_t>(row0 + nyq_r) * pitch + h];
       }
-      // the tables are copied while the loads are in flight
-      copy_table(tw, J.tw, h, tid);
-      copy_table(roots, J.roots, h + 1, tid);
+      // the tables are written while the loads are in flight
+      table_store(tw, r_tw, h, tid);
+      table_store(roots, r_roots, h + 1, tid);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
 #pragma unroll
@@ -826,13 +916,15 @@ struct Init {
     allow_big_lds(k_fft_y_grad<32, 8>);
     allow_big_lds(k_fft_y_grad<32, 12>);
     allow_big_lds(k_fft_y_grad<32, 16>);
-    allow_big_lds(k_fft_x_poisson<4, 8>);
-    allow_big_lds(k_fft_x_poisson<8, 8>);
-    allow_big_lds(k_fft_x_poisson<8, 12>);
-    allow_big_lds(k_fft_x_poisson<8, 16>);
-    allow_big_lds(k_fft_x_poisson<16, 8>);
-    allow_big_lds(k_fft_x_poisson<16, 12>);
-    allow_big_lds(k_fft_x_poisson<16, 16>);
+    allow_big_lds(k_fft_x_poisson<8, 8, true>);
+    allow_big_lds(k_fft_x_poisson<8, 12, true>);
+    allow_big_lds(k_fft_x_poisson<4, 8, false>);
+    allow_big_lds(k_fft_x_poisson<8, 8, false>);
+    allow_big_lds(k_fft_x_poisson<8, 12, false>);
+    allow_big_lds(k_fft_x_poisson<8, 16, false>);
+    allow_big_lds(k_fft_x_poisson<16, 8, false>);
+    allow_big_lds(k_fft_x_poisson<16, 12, false>);
+    allow_big_lds(k_fft_x_poisson<16, 16, false>);
     allow_big_lds(k_fft_z_c2r<1, 8, kEPT>);
     allow_big_lds(k_fft_z_c2r<1, 16, kEPT>);
     allow_big_lds(k_fft_z_c2r<1, 32, kEPT>);
@@ -884,9 +976,16 @@ int poisson_points(int n, int B) {
   return pts <= 8 ? 8 : (pts <= 12 ? 12 : 16);
 }
 
+bool poisson_chainable(const Plan1D& pl) {
+  if (pl.nst != 3 || pl.radix[0] != 8 || pl.radix[1] != 8) return false;
+  const int r = pl.radix[2];
+  return r == 12 || r == 5 || r == 4 || r == 3;
+}
+
 size_t lds_x_poisson(int n, int B, int M) {
   const size_t tiles = M <= 12 ? 1 : 2;
-  return sizeof(float2) * (tiles * static_cast<size_t>(n) * strided_pitch(B) + n) + sizeof(float) * (n / 2 + 1);
+  // tile(s), the plan's twiddles and those of the reversed plan, the window
+  return sizeof(float2) * (tiles * static_cast<size_t>(n) * strided_pitch(B) + 2 * n) + sizeof(float) * (n / 2 + 1);
 }
 size_t lds_z_c2r(int n, int B) {
   return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (B + 1) + n / 2 + n / 2 + 1);
@@ -995,18 +1094,23 @@ hipError_t launch_y_grad(const YGradJob* jobs, WorkTable wt, int B, int P, size_
   return hipGetLastError();
 }
 
-hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, size_t lds, hipStream_t s) {
+hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, bool chained, size_t lds, hipStream_t s) {
   ensure_init();
   const unsigned g = item_grid(wt.total);
   if (g == 0) return hipSuccess;
-#define LPC_POIS(BB, MM) k_fft_x_poisson<BB, MM><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
-  if (B == 4 && M == 8) LPC_POIS(4, 8);
-  else if (B == 8 && M == 8) LPC_POIS(8, 8);
-  else if (B == 8 && M == 12) LPC_POIS(8, 12);
-  else if (B == 8 && M == 16) LPC_POIS(8, 16);
-  else if (B == 16 && M == 8) LPC_POIS(16, 8);
-  else if (B == 16 && M == 12) LPC_POIS(16, 12);
-  else if (B == 16 && M == 16) LPC_POIS(16, 16);
+#define LPC_POIS(BB, MM, CC) k_fft_x_poisson<BB, MM, CC><<<g, kFftNT, lds, s>>>(jobs, wt.offs, wt.njob, wt.total)
+  if (chained) {
+    if (B == 8 && M == 8) LPC_POIS(8, 8, true);
+    else if (B == 8 && M == 12) LPC_POIS(8, 12, true);
+    else return hipErrorInvalidValue;
+  }
+  else if (B == 4 && M == 8) LPC_POIS(4, 8, false);
+  else if (B == 8 && M == 8) LPC_POIS(8, 8, false);
+  else if (B == 8 && M == 12) LPC_POIS(8, 12, false);
+  else if (B == 8 && M == 16) LPC_POIS(8, 16, false);
+  else if (B == 16 && M == 8) LPC_POIS(16, 8, false);
+  else if (B == 16 && M == 12) LPC_POIS(16, 12, false);
+  else if (B == 16 && M == 16) LPC_POIS(16, 16, false);
   else return hipErrorInvalidValue;
 #undef LPC_POIS
   return hipGetLastError();

@@ -293,6 +293,40 @@ __device__ __forceinline__ void fft_stage_from_global_pairs(float2* tile, Load l
   }
 }
 
+// The last stage of a compile-time plan into registers: as fft_stage_c, but butterfly i of column b keeps its R
+// outputs (rows (i - k) R + k + r P) in v instead of writing the tile. For stages with one butterfly per thread
+// (T B = kFftNT): thread tid holds b = tid % B, i = tid / B. No barrier after the tile reads.
+template <int R, bool INV, int N, int P, int B, int BP>
+__device__ __forceinline__ void fft_stage_to_regs(const float2* tile, const float2* tws, int tid, float2 (&v)[R]) {
+  constexpr int T = N / R;
+  static_assert(T * B == kFftNT, "one butterfly per thread");
+  const int b = tid % B, i = tid / B;
+  const float2* src = tile + i * BP + b;
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[r * T * BP];
+  const int k = ((P & (P - 1)) == 0) ? (i & (P - 1)) : (i % P);
+  if (P > 1) {
+    const float2* w = tws + k * (R - 1) - 1;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
+  }
+  Dft<R, INV>::run(v);
+}
+
+// The first stage of a compile-time plan from registers (sub-transform length 1): butterfly i of column b takes its
+// R inputs (rows i + r T) from v, and writes its DFT to the tile at rows i R + r. The same thread mapping as
+// fft_stage_to_regs, so a stage that ends in registers can feed a transform whose first radix matches its last.
+template <int R, bool INV, int N, int B, int BP>
+__device__ __forceinline__ void fft_stage_from_regs(float2* tile, float2 (&v)[R], int tid) {
+  constexpr int T = N / R;
+  static_assert(T * B == kFftNT, "one butterfly per thread");
+  const int b = tid % B, i = tid / B;
+  Dft<R, INV>::run(v);
+  float2* dst = tile + i * R * BP + b;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[r * BP] = v[r];
+}
+
 // The last stage of a compile-time plan written straight to global memory: fft_stage_c with output row
 // (i - k) R + k + r P going to store(row, b, value) instead of the tile. There is no barrier after the tile reads:
 // nothing writes the tile again before the caller's next barrier.
@@ -414,20 +448,16 @@ __device__ __forceinline__ void fft_tile(float2* tile, const float2* tw, const P
   }
 }
 
-// Copy `count` entries of a precomputed table from global memory to LDS. No barrier.
-template <class T>
-__device__ __forceinline__ void copy_table(T* dst, const T* __restrict__ src, int count, int tid) {
-  LPC_GLOBAL const T* g = to_global(src);
-  for (int i = tid; i < count; i += kFftNT) dst[i] = g[i];
-}
 
-// The same in two steps, for count <= 2 kFftNT (tables of lengths up to 1024): table_load issues the loads into
-// registers, table_store writes them, so other loads can be issued in between.
 // Row pitch of a strided tile of B columns, whose lanes run along the columns: 8-column tiles are left unpadded
 // (with a pitch of 9, two rows met in one 16-lane group of a 64-bit LDS access share banks; a model of the stage
 // accesses gives 1.9x the conflict-free cycles for pitch 9 and 1.1x for pitch 8), wider tiles take B + 1.
 __host__ __device__ constexpr int strided_pitch(int B) { return B == 8 ? 8 : B + 1; }
 
+// Copy `count` <= 2 kFftNT entries (tables of lengths up to 1024, the largest mesh side) of a precomputed table from
+// global memory to LDS in two steps: table_load issues the loads into registers, table_store writes them (no
+// barrier). A kernel issues its tables' loads before its data loads, so that writing the tables waits for them only
+// (a load-then-store loop would wait out one memory latency per table, behind every load issued before it).
 template <class T>
 struct TableRegs {
   T v[2];

@@ -35,6 +35,8 @@ struct Plan1D {
 // Stages of a length-n transform: radix 8 (2, 4 for the rest of the power of two), 3 and 5; with radix12 a radix-4
 // and a radix-3 stage become one radix-12 stage. False if n has a prime factor > 5 or n < 1.
 bool make_plan(int n, Plan1D* p, bool radix12 = true);
+// The plan of the same length with the radices applied in reverse order (p, pmask and tw_off recomputed).
+Plan1D reversed_plan(const Plan1D& p);
 int mesh_pitch(int n);                   // complex row pitch of the half-spectrum layout, >= n/2 + 1
 
 // Per-kick scalars (FP64 table rows reduced to FP32 products).
@@ -219,6 +221,7 @@ struct AxisJob {        // complex FFT along a strided axis, ncomp meshes
 struct PoissonJob {     // fused forward x / Poisson-gradient / inverse x of one box
   float2 *A, *B, *C;
   const float2* tw;
+  const float2* tw_rev;  // stage twiddles of the plan with its radices in reverse order (reversed_plan)
   const float* win;
   int nm, pitch, ntc, deconv;
   float kf, inv_m3;
@@ -284,7 +287,10 @@ hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, in
                         hipStream_t s);
 hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, int P, size_t lds, hipStream_t s);
 hipError_t launch_y_grad(const YGradJob* jobs, WorkTable wt, int B, int P, size_t lds, hipStream_t s);
-hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, size_t lds, hipStream_t s);
+// chained: every job's plan is poisson_chainable, B = 8 and M <= 12 (the transforms chained through registers)
+hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, bool chained, size_t lds, hipStream_t s);
+// Plans 8 x 8 x R with R in {12, 5, 4, 3}: the fused x pass can chain its transforms through registers.
+bool poisson_chainable(const Plan1D& pl);
 hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, int P, size_t lds, hipStream_t s);
 
 // Initial conditions on an N^3 lattice.
