@@ -5,6 +5,8 @@ Bar: bit-for-bit equality with separate lpc_cola_step calls on each box (the bat
 per-element arithmetic and the same integer deposit), on the first call (graph recorded), on a replay of the
 recorded graph, and with graphs switched off; and for one box, positions within 1e-5 L of the FP64 oracle.
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -129,25 +131,40 @@ def test_batch_of_one_and_errors():
     assert e.value.status == -2
 
 
-def test_batched_workload_shapes():
+@functools.lru_cache(maxsize=None)
+def oracle_run(n_side, nm, box, seed):
+    """The FP64 oracle's ten-step modified-COLA run of one box (cached across the tests that use it)."""
+    ic = box_ic(n_side, box, seed)
+    return ocola.cola_run(ic["pos"], ic["vel"], ic["psi1"], ic["psi2"], synth.A_LIST, C["omega_m"], nm, box)
+
+
+@pytest.mark.parametrize("poisson_cols", [None, 8], ids=["builtin-widths", "poisson-8-chained"])
+def test_batched_workload_shapes(poisson_cols):
     """One box of each shape of the 48-box workload (N = 96, 128, 160 with Nm = 2N, boxes 300, 450, 600 Mpc/h), so
     the batched launches take the 192, 256 and 320 meshes (compile-time FFT plans 8 8 3, 8 8 4, 8 8 5 and their half
     lengths) together, with the tile widths and points per thread shared across the three: every box equals its own
-    lpc_cola_step run bit for bit over ten steps, and the N = 96 box is within 1e-5 L of the FP64 oracle."""
+    lpc_cola_step run bit for bit over ten steps, and the N = 96 box is within 1e-5 L of the FP64 oracle. With the
+    built-in widths the fused x pass takes 16-column tiles (its unchained form); with 8-column tiles, the width the
+    autotuner picks at these meshes, it chains its three transforms through registers."""
     from paper_1506_03737_amd import lpc
     boxes = [(96, 192, 300.0, 1000), (128, 256, 450.0, 1001), (160, 320, 600.0, 1002)]
-    say("batched: workload shapes 96/192, 128/256, 160/320, ten steps")
+    say(f"batched: workload shapes 96/192, 128/256, 160/320, ten steps, poisson_cols={poisson_cols}")
     step = lpc.stepping()
     a = synth.A_LIST
     ics = [box_ic(n, L, seed) for (n, nm, L, seed) in boxes]
-    ref = single_runs(lpc, ics, boxes, a, step)
-    got, _, _, _ = batched_run(lpc, ics, boxes, a, step)
+    try:
+        if poisson_cols is not None:
+            for _, nm, _, _ in boxes:
+                lpc.lpc_fft_tiling_set(nm, dict(lpc.lpc_fft_tiling_default(nm), poisson_cols=poisson_cols))
+        ref = single_runs(lpc, ics, boxes, a, step)
+        got, _, _, _ = batched_run(lpc, ics, boxes, a, step)
+    finally:
+        lpc.lpc_fft_tiling_reset()
     for i, ((x, v), (xr, vr)) in enumerate(zip(got, ref)):
         assert np.array_equal(x, xr), f"box {i}: positions differ"
         assert np.array_equal(v, vr), f"box {i}: velocities differ"
-    n, nm, L, _ = boxes[0]
-    ic = ics[0]
-    xr, vr = ocola.cola_run(ic["pos"], ic["vel"], ic["psi1"], ic["psi2"], a, C["omega_m"], nm, L)
+    n, nm, L, seed = boxes[0]
+    xr, vr = oracle_run(n, nm, L, seed)
     dx = np.abs(periodic_diff(got[0][0], xr, L)).max() / L
     dv = np.sqrt(np.mean((got[0][1] - vr) ** 2)) / np.sqrt(np.mean(vr**2))
     say(f"  N=96 box vs oracle: max |dx|/L = {dx:.3e}, rms |dv|/rms v = {dv:.3e}")

@@ -85,6 +85,30 @@ def test_every_tiling_matches_builtin(nm):
         assert np.abs(g - g_ref).max() < 2e-5 * np.abs(g_ref).max(), t
 
 
+@pytest.mark.parametrize("nm", [192, 256, 320])
+def test_chained_x_pass_matches_oracle(nm):
+    """At the x plans 8 8 R (192, 256, 320) the fused x pass chains its three transforms through registers when its
+    tiles are 8 columns wide (the width the autotuner picks there); the built-in 16-column tiles take the unchained
+    form. Both against the FP64 oracle (density bit for bit, force at the standard bars) and against each other."""
+    from paper_1506_03737_amd import lpc
+    box = 400.0
+    pos = synth.clustered_positions(7, 150001, box)
+    ref_C = opm.deposit_fixed(pos, nm, box)
+    ref = opm.pm_force(pos.astype(np.float64), nm, box, deconv_power=1)
+    pos_d = to_dev(pos)
+    say(f"tiling: chained and unchained fused x pass at nm={nm}")
+    out = {}
+    for w in (16, 8):
+        lpc.lpc_fft_tiling_set(nm, dict(lpc.lpc_fft_tiling_default(nm), poisson_cols=w))
+        g, d = force(lpc, pos_d, nm, box)
+        assert np.array_equal(d, ref_C), w
+        assert rel_l2(g, ref) < 2e-5, w
+        assert np.abs(g - ref).max() < 2e-4 * np.abs(ref).max(), w
+        out[w] = g
+    assert rel_l2(out[8], out[16]) < 2e-6
+    assert np.abs(out[8] - out[16]).max() < 2e-5 * np.abs(out[16]).max()
+
+
 def test_fft_round_trip_under_other_tilings():
     """lpc_fft_r2c / lpc_fft_c2r use z_rows and axis_cols: every fitting pair against numpy.fft."""
     from paper_1506_03737_amd import autotune, lpc
