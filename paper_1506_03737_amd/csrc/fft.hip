@@ -150,7 +150,9 @@ __device__ __forceinline__ bool try_fixed_io(float2* tile, const float2* tw, con
 }
 
 // PAIRS: tile column b < B / 2 is pair(row, x) and column b + B / 2 is x itself, for x = load(row, b) of a B / 2
-// column source (load takes source columns only).
+// column source (load takes source columns only). Columns transform independently, so for a column that store skips
+// (past the mesh edge) load may return any finite value: the kernels reload the item's last column there instead of
+// predicating the load and clearing its register.
 template <bool INV, int EPT, int B, int BP, bool GIN, bool GOUT, bool PAIRS = false, class PL, class Load, class Pair,
           class Mid, class Store>
 __device__ __forceinline__ void fft_io_fast(float2* tile, const float2* tw, const PL& pl, int tid, Load load, Pair pair,
@@ -437,13 +439,13 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : 4) void k_fft_axis(const A
     float2* tile = smem;
     float2* tw = smem + n * strided_pitch(B);
     LPC_GLOBAL float2* ptr = to_global(J.base + comp * J.cstr + outer * J.ostr + c0);
-    const int64_t astr = J.astr;
+    const uint32_t astr = static_cast<uint32_t>(J.astr);  // j astr < 2^32 for every mesh up to 1024
     // the first stage reads the columns from HBM and the last writes them back: the tile holds only the stages between
     const TableRegs<float2> twr = table_load(J.tw, n, tid);
-    auto load = [&](int j, int b) { return b < bw ? ptr[j * astr + b] : make_float2(0.f, 0.f); };
+    auto load = [&](int j, int b) { return ptr[static_cast<uint32_t>(j) * astr + min(b, bw - 1)]; };
     auto mid = [&]() { table_store(tw, twr, n, tid); };
     auto store = [&](int j, int b, float2 v) {
-      if (b < bw) ptr[j * astr + b] = v;
+      if (b < bw) ptr[static_cast<uint32_t>(j) * astr + b] = v;
     };
     auto none = [](int, float2 x) { return x; };
     fft_io_fast<INV, EPT, B, strided_pitch(B), true, true>(tile, tw, J.pl, tid, load, none, mid, store);
@@ -478,10 +480,10 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
     if (outer >= n) return;  // padding item
     const int c0 = ct * B, bw = min(B, J.ncols - c0);
     LPC_GLOBAL float2* ptr = to_global(J.A + static_cast<int64_t>(outer) * J.ostr + c0);
-    const int64_t astr = J.astr;
-    auto load = [&](int j, int b) { return b < bw ? ptr[j * astr + b] : make_float2(0.f, 0.f); };
+    const uint32_t astr = static_cast<uint32_t>(J.astr);
+    auto load = [&](int j, int b) { return ptr[static_cast<uint32_t>(j) * astr + min(b, bw - 1)]; };
     auto store = [&](int j, int b, float2 v) {
-      if (b < bw) ptr[j * astr + b] = v;
+      if (b < bw) ptr[static_cast<uint32_t>(j) * astr + b] = v;
     };
     auto none = [](int, float2 x) { return x; };
     fft_io_fast<true, EPT, B, BP, true, true>(tile, tw, J.pl, tid, load, none, mid, store);
@@ -495,23 +497,19 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
   LPC_GLOBAL const float2* src = to_global(J.C + off);
   LPC_GLOBAL float2* dB = to_global(J.B + off);
   LPC_GLOBAL float2* dC = to_global(J.C + off);
-  const int64_t astr = J.astr;
+  const uint32_t astr = static_cast<uint32_t>(J.astr);
   const int half = n / 2;
   const float kf = J.kf;
   // tile column b < BH holds i k_y psi of psi's column b, column BH + b psi itself; they go to B and back to C.
   // Each psi value is loaded once and feeds both columns.
-  auto load = [&](int j, int bh) {
-    float2 v = make_float2(0.f, 0.f);
-    if (bh < bw) v = src[j * astr + bh];
-    return v;
-  };
+  auto load = [&](int j, int bh) { return src[static_cast<uint32_t>(j) * astr + min(bh, bw - 1)]; };
   auto iky = [&](int j, float2 v) {
     const float ky = (j == half) ? 0.f : kf * static_cast<float>(j <= half ? j : j - n);
     return make_float2(-ky * v.y, ky * v.x);
   };
   auto store = [&](int j, int b, float2 v) {
     const int bh = b % BH;
-    if (bh < bw) (b < BH ? dB : dC)[j * astr + bh] = v;
+    if (bh < bw) (b < BH ? dB : dC)[static_cast<uint32_t>(j) * astr + bh] = v;
   };
   fft_io_fast<true, EPT, B, BP, true, true, true>(tile, tw, J.pl, tid, load, iky, mid, store);
 }
@@ -594,7 +592,7 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
     float2* twr = tw + n;                           // twiddles of the reversed plan (chained form)
     float* win = reinterpret_cast<float*>(twr + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
     const int c0 = ct * B, bw = min(B, nh - c0);
-    const int64_t astr = static_cast<int64_t>(nm) * pitch;
+    const uint32_t astr = static_cast<uint32_t>(nm) * static_cast<uint32_t>(pitch);  // j astr < 2^32 (Nm <= 1024)
     const int64_t off = static_cast<int64_t>(y) * pitch + c0;
     LPC_GLOBAL float2* gA = to_global(J.A + off);
     LPC_GLOBAL float2* gC = to_global(J.C + off);
@@ -623,12 +621,12 @@ __global__ __launch_bounds__(kFftNT, (M <= 12) ? 4 : 2) void k_fft_x_poisson(con
         g = make_float2(-kx * ph.y, kx * ph.x);
       };
     };
-    auto load = [&](int j, int b) { return b < bw ? gA[j * astr + b] : make_float2(0.f, 0.f); };
+    auto load = [&](int j, int b) { return gA[static_cast<uint32_t>(j) * astr + min(b, bw - 1)]; };
     auto store_a = [&](int j, int b, float2 v) {
-      if (b < bw) gA[j * astr + b] = v;
+      if (b < bw) gA[static_cast<uint32_t>(j) * astr + b] = v;
     };
     auto store_c = [&](int j, int b, float2 v) {
-      if (b < bw) gC[j * astr + b] = v;
+      if (b < bw) gC[static_cast<uint32_t>(j) * astr + b] = v;
     };
     if constexpr (CHAIN) {
       static_assert(B == 8 && kRegs, "the chained form takes 8-column tiles held in registers");

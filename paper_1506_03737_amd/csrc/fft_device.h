@@ -226,29 +226,38 @@ __device__ __forceinline__ void fft_stage_c(float2* tile, const float2* tws, int
   __syncthreads();
 }
 
-// The first stage of a compile-time plan fed straight from global memory (sub-transform length 1: no twiddles).
-// Butterfly i of column b takes rows i + r T (r < R) through load(row, b) and writes its outputs to the tile at rows
-// i R + r. All of a thread's loads are issued before mid() runs and before the first butterfly, so a caller can use
-// mid() for work that overlaps them. No barrier: the caller synchronises before the next stage reads the tile.
-template <int R, bool INV, int EPT, int N, int B, int BP, class Load, class Mid>
-__device__ __forceinline__ void fft_stage_from_global(float2* tile, Load load, Mid mid, int tid) {
-  constexpr int MB = (EPT + R - 1) / R, T = N / R, S = kFftNT / B;
+// The first stage of a compile-time plan fed straight from global memory (sub-transform length 1: no twiddles), in
+// two steps. first_stage_load issues the loads: butterfly i of column b takes rows i + r T (r < R) through load(row, b)
+// into v. first_stage_store transforms them and writes the outputs to the tile at rows i R + r. No barrier: the caller
+// synchronises before the next stage reads the tile.
+template <int R, int EPT, int N, int B>
+struct FirstStage {
+  static constexpr int MB = (EPT + R - 1) / R, T = N / R, S = kFftNT / B;
+  using Regs = float2[MB][R];
+};
+template <int R, int EPT, int N, int B, class Load>
+__device__ __forceinline__ void first_stage_load(typename FirstStage<R, EPT, N, B>::Regs& v, Load load, int tid) {
+  using F = FirstStage<R, EPT, N, B>;
   const int b = tid % B;
-  const int i0 = (tid < S * B) ? tid / B : (1 << 30);
-  float2 v[MB][R];
+  const int i0 = (tid < F::S * B) ? tid / B : (1 << 30);
 #pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int i = i0 + m * S;
-    if (i < T) {
+  for (int m = 0; m < F::MB; ++m) {
+    const int i = i0 + m * F::S;
+    if (i < F::T) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[m][r] = load(i + r * T, b);
+      for (int r = 0; r < R; ++r) v[m][r] = load(i + r * F::T, b);
     }
   }
-  mid();
+}
+template <int R, bool INV, int EPT, int N, int B, int BP>
+__device__ __forceinline__ void first_stage_store(float2* tile, typename FirstStage<R, EPT, N, B>::Regs& v, int tid) {
+  using F = FirstStage<R, EPT, N, B>;
+  const int b = tid % B;
+  const int i0 = (tid < F::S * B) ? tid / B : (1 << 30);
 #pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int i = i0 + m * S;
-    if (i < T) {
+  for (int m = 0; m < F::MB; ++m) {
+    const int i = i0 + m * F::S;
+    if (i < F::T) {
       Dft<R, INV>::run(v[m]);
       float2* dst = tile + i * R * BP + b;
 #pragma unroll
@@ -257,40 +266,67 @@ __device__ __forceinline__ void fft_stage_from_global(float2* tile, Load load, M
   }
 }
 
+// Both steps, with mid() between them: all of a thread's loads are issued before mid() runs and before the first
+// butterfly, so a caller can use mid() for work that overlaps them.
+template <int R, bool INV, int EPT, int N, int B, int BP, class Load, class Mid>
+__device__ __forceinline__ void fft_stage_from_global(float2* tile, Load load, Mid mid, int tid) {
+  typename FirstStage<R, EPT, N, B>::Regs v;
+  first_stage_load<R, EPT, N, B>(v, load, tid);
+  mid();
+  first_stage_store<R, INV, EPT, N, B, BP>(tile, v, tid);
+}
+
 // The same first stage for a tile whose columns come in pairs (b, b + B / 2) built from one source column: thread
 // (i, bh) loads rows i + r T of source column bh once through load(row, bh), and pair(row, x) gives the value of
 // column bh (column bh + B / 2 takes x itself). The loads of 16 rows x B / 2 columns per wave are each read once.
-template <int R, bool INV, int N, int B, int BP, class Load, class Pair, class Mid>
-__device__ __forceinline__ void fft_stage_from_global_pairs(float2* tile, Load load, Pair pair, Mid mid, int tid) {
-  constexpr int BH = B / 2, T = N / R, S = kFftNT / BH, MB = (T + S - 1) / S;
-  const int bh = tid % BH, i0 = tid / BH;
-  float2 x[MB][R];
+template <int R, int N, int B>
+struct FirstStagePairs {
+  static constexpr int BH = B / 2, T = N / R, S = kFftNT / BH, MB = (T + S - 1) / S;
+  using Regs = float2[MB][R];
+};
+template <int R, int N, int B, class Load>
+__device__ __forceinline__ void first_stage_pairs_load(typename FirstStagePairs<R, N, B>::Regs& x, Load load,
+                                                       int tid) {
+  using F = FirstStagePairs<R, N, B>;
+  const int bh = tid % F::BH, i0 = tid / F::BH;
 #pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int i = i0 + m * S;
-    if (i < T) {
+  for (int m = 0; m < F::MB; ++m) {
+    const int i = i0 + m * F::S;
+    if (i < F::T) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[m][r] = load(i + r * T, bh);
+      for (int r = 0; r < R; ++r) x[m][r] = load(i + r * F::T, bh);
     }
   }
-  mid();
+}
+template <int R, bool INV, int N, int B, int BP, class Pair>
+__device__ __forceinline__ void first_stage_pairs_store(float2* tile, typename FirstStagePairs<R, N, B>::Regs& x,
+                                                        Pair pair, int tid) {
+  using F = FirstStagePairs<R, N, B>;
+  const int bh = tid % F::BH, i0 = tid / F::BH;
 #pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int i = i0 + m * S;
-    if (i < T) {
+  for (int m = 0; m < F::MB; ++m) {
+    const int i = i0 + m * F::S;
+    if (i < F::T) {
       float2 a[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) a[r] = pair(i + r * T, x[m][r]);
+      for (int r = 0; r < R; ++r) a[r] = pair(i + r * F::T, x[m][r]);
       Dft<R, INV>::run(a);
       Dft<R, INV>::run(x[m]);
       float2* dst = tile + i * R * BP + bh;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         dst[r * BP] = a[r];
-        dst[r * BP + BH] = x[m][r];
+        dst[r * BP + F::BH] = x[m][r];
       }
     }
   }
+}
+template <int R, bool INV, int N, int B, int BP, class Load, class Pair, class Mid>
+__device__ __forceinline__ void fft_stage_from_global_pairs(float2* tile, Load load, Pair pair, Mid mid, int tid) {
+  typename FirstStagePairs<R, N, B>::Regs x;
+  first_stage_pairs_load<R, N, B>(x, load, tid);
+  mid();
+  first_stage_pairs_store<R, INV, N, B, BP>(tile, x, pair, tid);
 }
 
 // The last stage of a compile-time plan into registers: as fft_stage_c, but butterfly i of column b keeps its R
