@@ -606,7 +606,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     f.Pax = std::max(f.Pax, kern::axis_points(b.nm, f.Bax));
     f.Pz = std::max(f.Pz, kern::r2c_points(b.nm, f.Bz));
   }
-  f.chain_p = f.Bp == 8 && f.Mp <= 12;
+  f.chain_p = f.Bp == 8;
   for (const ForceBox& b : boxes) f.chain_p = f.chain_p && kern::poisson_chainable(plan_of(b.nm));
   const int ncopy = cola_run ? 2 : 1;
   std::vector<kern::SortJob> su, sn[2];
@@ -770,7 +770,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     i_c.push_back((c.nrows + f.R3 - 1) / f.R3);
     f.lds_z = std::max(f.lds_z, kern::lds_z_r2c(nm, f.Bz));
     f.lds_ax = std::max(f.lds_ax, kern::lds_axis(nm, f.Bax));
-    f.lds_p = std::max(f.lds_p, kern::lds_x_poisson(nm, f.Bp, f.Mp));
+    f.lds_p = std::max(f.lds_p, kern::lds_x_poisson(nm, f.Bp, f.Mp, f.chain_p));
     f.lds_c = std::max(f.lds_c, kern::lds_z_c2r(nm, 3 * f.R3));
   }
   f.sort_user = jp.add(su, i_part);

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 
 #include "fft_device.h"
@@ -515,46 +516,87 @@ __global__ __launch_bounds__(kFftNT, EPT <= 8 ? 6 : 4) void k_fft_y_grad(
 }
 
 // ---------------------------------------------------------------------------------------------------------------
-// The fused x pass for the plans 8 x 8 x R (R = 12, 5, 4, 3: meshes 768, 320, 256, 192) on 8-column tiles, with its
-// three transforms chained through registers. The forward transform's last stage has one radix-R butterfly per thread:
-// thread (i, b) = (tid / 8, tid % 8) ends with rows i + 64 r (r < R) of column b in its registers, in natural order.
-// factor(row, g, ph) turns each into psi_hat (ph) and i k_x psi_hat (g) there. Both inverse transforms run the plan
-// in reverse order (R x 8 x 8, stage twiddles twr), whose first stage takes exactly those rows, so neither spectrum
-// goes back through the tile between the transforms: per tile 12 LDS passes and 9 barriers instead of 18 and 15.
-template <int R, int M, class PL, class Load, class Mid, class MakeFactor, class StoreA, class StoreC>
-__device__ __forceinline__ bool x_poisson_chained(float2* tile, const float2* tw, const float2* twr, const PL& pl,
-                                                  int tid, Load load, Mid mid, MakeFactor make_factor,
-                                                  StoreA store_a, StoreC store_c) {
-  constexpr int B = 8, BP = strided_pitch(B), N = 64 * R;
-  using Fwd = FixedFFT<false, M, B, BP, 8, 8, R>;
-  if constexpr (!Fwd::kFits) return false;
-  else {
-  if (!Fwd::matches(pl)) return false;
-  // forward: radix 8 from HBM, radix 8, radix R into registers
-  fft_stage_from_global<8, false, M, N, B, BP>(tile, load, mid, tid);
-  __syncthreads();
-  fft_stage_c<8, false, M, N, 8, B, BP>(tile, tw + 7, tid);
-  float2 g[R], ph[R];
-  fft_stage_to_regs<R, false, N, 64, B, BP>(tile, tw + 7 + 8 * 7, tid, g);
-  {
-    const auto factor = make_factor();
-    const int i = tid / B;
-#pragma unroll
-    for (int r = 0; r < R; ++r) factor(i + 64 * r, g[r], ph[r]);
+// A compile-time plan (radices Rs in order, or reversed with REV): stage s has radix r(s), sub-transform length p(s)
+// and its twiddles at off(s) of the plan's table (the layout make_plan gives it).
+template <bool REV, int... Rs>
+struct ChainPlan {
+  static constexpr int K = sizeof...(Rs);
+  static constexpr int N = (Rs * ...);
+  static constexpr int fwd[K] = {Rs...};
+  static constexpr int r(int s) { return REV ? fwd[K - 1 - s] : fwd[s]; }
+  static constexpr int p(int s) {
+    int q = 1;
+    for (int t = 0; t < s; ++t) q *= r(t);
+    return q;
   }
-  __syncthreads();  // the tile has been read
-  // first inverse: i k_x psi_hat -> the x gradient in A
-  fft_stage_from_regs<R, true, N, B, BP>(tile, g, tid);
-  __syncthreads();
-  fft_stage_c<8, true, M, N, R, B, BP>(tile, twr + (R - 1), tid);
-  fft_stage_to_global<8, true, M, N, 8 * R, B, BP>(tile, twr + (R - 1) + R * 7, store_a, tid);
-  __syncthreads();
-  // second inverse: psi_hat -> the x-transformed potential in C
-  fft_stage_from_regs<R, true, N, B, BP>(tile, ph, tid);
-  __syncthreads();
-  fft_stage_c<8, true, M, N, R, B, BP>(tile, twr + (R - 1), tid);
-  fft_stage_to_global<8, true, M, N, 8 * R, B, BP>(tile, twr + (R - 1) + R * 7, store_c, tid);
-  return true;
+  static constexpr int off(int s) {
+    int o = 0;
+    for (int t = 0; t < s; ++t) o += p(t) * (r(t) - 1);
+    return o;
+  }
+};
+
+// Stages 1 .. K - 2 of plan CP in the tile.
+template <class CP, bool INV, int EPT, int B, int BP, int... S>
+__device__ __forceinline__ void chain_mid_stages(float2* tile, const float2* tw, int tid,
+                                                 std::integer_sequence<int, S...>) {
+  (fft_stage_c<CP::r(S + 1), INV, EPT, CP::N, CP::p(S + 1), B, BP>(tile, tw + CP::off(S + 1), tid), ...);
+}
+
+// The fused x pass on 8-column tiles with its three transforms chained through registers, for the plans 8 x 8 x R
+// (R = 12, 5, 4, 3: meshes 768, 320, 256, 192) and 4 x 4 x 8 x 8 (1024). The forward transform's last stage (radix
+// RL) leaves each thread's MB butterflies in its registers: thread (i, b) = (tid / 8, tid % 8) holds rows
+// i + m 64 + r N / RL of column b, in natural order (MB = 1 for 8 x 8 x R, 2 for 1024). factor(row, g, ph) turns each
+// into psi_hat (ph) and i k_x psi_hat (g) there. Both inverse transforms run the plan in reverse order, whose first
+// stage (radix RL) takes exactly those rows, so neither spectrum goes back through the tile between the transforms:
+// for 768, 12 LDS passes and 9 barriers per tile instead of 18 and 15. The reversed plan's twiddles wait in registers
+// (r_twr) and replace the forward ones in LDS once the forward transform has read them, so one table's worth of LDS
+// serves both (at 1024 that lets two workgroups share a CU).
+template <int M, int... Rs, class PL, class Load, class Mid, class MakeFactor, class StoreA, class StoreC>
+__device__ __forceinline__ bool x_poisson_chained(float2* tile, float2* tw, const TableRegs<float2>& r_twr,
+                                                  const PL& pl, int tid, Load load, Mid mid, MakeFactor make_factor,
+                                                  StoreA store_a, StoreC store_c) {
+  constexpr int B = 8, BP = strided_pitch(B);
+  using Fwd = FixedFFT<false, M, B, BP, Rs...>;
+  if constexpr (!Fwd::kFits) {
+    return false;
+  } else {
+    if (!Fwd::matches(pl)) return false;
+    using F = ChainPlan<false, Rs...>;
+    using V = ChainPlan<true, Rs...>;
+    constexpr int N = F::N, K = F::K, RF = F::r(0), RL = F::r(K - 1);
+    constexpr int MB = (N / RL) * B / kFftNT;
+    static_assert(MB * kFftNT == (N / RL) * B, "the last stage's butterflies split evenly over the threads");
+    using Mids = std::make_integer_sequence<int, K - 2>;
+    // forward: the first stage from HBM, the middle stages in the tile, the last into registers
+    fft_stage_from_global<RF, false, M, N, B, BP>(tile, load, mid, tid);
+    __syncthreads();
+    chain_mid_stages<F, false, M, B, BP>(tile, tw, tid, Mids{});
+    float2 g[MB][RL], ph[MB][RL];
+    fft_stage_to_regs<RL, false, N, F::p(K - 1), B, BP, MB>(tile, tw + F::off(K - 1), tid, g);
+    {
+      const auto factor = make_factor();
+      const int i0 = tid / B;
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+#pragma unroll
+        for (int r = 0; r < RL; ++r) factor(i0 + m * (kFftNT / B) + r * (N / RL), g[m][r], ph[m][r]);
+      }
+    }
+    __syncthreads();  // the tile and the forward twiddles have been read
+    table_store(tw, r_twr, N, tid);
+    // first inverse: i k_x psi_hat -> the x gradient in A
+    fft_stage_from_regs<RL, true, N, B, BP, MB>(tile, g, tid);
+    __syncthreads();
+    chain_mid_stages<V, true, M, B, BP>(tile, tw, tid, Mids{});
+    fft_stage_to_global<RF, true, M, N, V::p(K - 1), B, BP>(tile, tw + V::off(K - 1), store_a, tid);
+    __syncthreads();
+    // second inverse: psi_hat -> the x-transformed potential in C
+    fft_stage_from_regs<RL, true, N, B, BP, MB>(tile, ph, tid);
+    __syncthreads();
+    chain_mid_stages<V, true, M, B, BP>(tile, tw, tid, Mids{});
+    fft_stage_to_global<RF, true, M, N, V::p(K - 1), B, BP>(tile, tw + V::off(K - 1), store_c, tid);
+    return true;
   }
 }
 
@@ -572,11 +614,10 @@ __device__ __forceinline__ bool x_poisson_chained(float2* tile, const float2* tw
 // 192-320 meshes) is capped at 80 VGPRs, so that three workgroups fit on a CU (one register spills; 48-box step
 // 30.86 -> 30.25 ms).
 template <int B, int M, bool CHAIN>
-__global__ __launch_bounds__(kFftNT, (CHAIN && M <= 8) ? 6 : ((M <= 12) ? 4 : 2)) void k_fft_x_poisson(const PoissonJob* __restrict__ jobs,
-                                                                            const int* __restrict__ offs, int njob,
-                                                                            int total) {
+__global__ __launch_bounds__(kFftNT, (CHAIN && M <= 8) ? 6 : ((CHAIN || M <= 12) ? 4 : 2)) void k_fft_x_poisson(
+    const PoissonJob* __restrict__ jobs, const int* __restrict__ offs, int njob, int total) {
   constexpr int BP = strided_pitch(B), S = kFftNT / B;
-  constexpr bool kRegs = M <= 12;
+  constexpr bool kRegs = CHAIN || M <= 12;  // psi_hat in registers (else a second LDS tile)
   extern __shared__ float2 smem[];
   {
     const int w = blockIdx.x;
@@ -591,8 +632,7 @@ __global__ __launch_bounds__(kFftNT, (CHAIN && M <= 8) ? 6 : ((M <= 12) ? 4 : 2)
     float2* tile = smem;
     float2* ph_lds = tile + n * BP;  // psi_hat when !kRegs
     float2* tw = tile + (kRegs ? 1 : 2) * n * BP;
-    float2* twr = tw + n;                           // twiddles of the reversed plan (chained form)
-    float* win = reinterpret_cast<float*>(twr + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
+    float* win = reinterpret_cast<float*>(tw + n);  // sinc^2(pi m / n), m <= n / 2 (even in m)
     const int c0 = ct * B, bw = min(B, nh - c0);
     const uint32_t astr = static_cast<uint32_t>(nm) * static_cast<uint32_t>(pitch);  // j astr < 2^32 (Nm <= 1024)
     const int64_t off = static_cast<int64_t>(y) * pitch + c0;
@@ -631,19 +671,23 @@ __global__ __launch_bounds__(kFftNT, (CHAIN && M <= 8) ? 6 : ((M <= 12) ? 4 : 2)
       if (b < bw) gC[static_cast<uint32_t>(j) * astr + b] = v;
     };
     if constexpr (CHAIN) {
-      static_assert(B == 8 && kRegs, "the chained form takes 8-column tiles held in registers");
-      // the tables' loads go out first; mid() writes them to LDS while the first stage's loads are in flight
+      static_assert(B == 8, "the chained form takes 8-column tiles");
+      // the tables' loads go out first; mid() writes the forward twiddles and the window to LDS while the first
+      // stage's loads are in flight, the reversed plan's twiddles stay in registers until the forward pass is done
       const TableRegs<float2> r_tw = table_load(J.tw, n, tid), r_twr = table_load(J.tw_rev, n, tid);
       const TableRegs<float> r_win = table_load(J.win, n / 2 + 1, tid);
       auto mid = [&]() {
         table_store(tw, r_tw, n, tid);
-        table_store(twr, r_twr, n, tid);
         table_store(win, r_win, n / 2 + 1, tid);
       };
-      if (x_poisson_chained<12, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c)) return;
-      if (x_poisson_chained<5, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c)) return;
-      if (x_poisson_chained<4, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c)) return;
-      x_poisson_chained<3, M>(tile, tw, twr, J.pl, tid, load, mid, make_factor, store_a, store_c);
+#define LPC_CHAIN(...) \
+  if (x_poisson_chained<M, __VA_ARGS__>(tile, tw, r_twr, J.pl, tid, load, mid, make_factor, store_a, store_c)) return;
+      LPC_CHAIN(8, 8, 12)
+      LPC_CHAIN(8, 8, 5)
+      LPC_CHAIN(8, 8, 4)
+      LPC_CHAIN(8, 8, 3)
+      LPC_CHAIN(4, 4, 8, 8)
+#undef LPC_CHAIN
       return;
     } else {
       auto none = [](int, float2 x) { return x; };
@@ -918,6 +962,7 @@ struct Init {
     allow_big_lds(k_fft_y_grad<32, 16>);
     allow_big_lds(k_fft_x_poisson<8, 8, true>);
     allow_big_lds(k_fft_x_poisson<8, 12, true>);
+    allow_big_lds(k_fft_x_poisson<8, 16, true>);
     allow_big_lds(k_fft_x_poisson<4, 8, false>);
     allow_big_lds(k_fft_x_poisson<8, 8, false>);
     allow_big_lds(k_fft_x_poisson<8, 12, false>);
@@ -977,15 +1022,16 @@ int poisson_points(int n, int B) {
 }
 
 bool poisson_chainable(const Plan1D& pl) {
+  if (pl.nst == 4) return pl.radix[0] == 4 && pl.radix[1] == 4 && pl.radix[2] == 8 && pl.radix[3] == 8;
   if (pl.nst != 3 || pl.radix[0] != 8 || pl.radix[1] != 8) return false;
   const int r = pl.radix[2];
   return r == 12 || r == 5 || r == 4 || r == 3;
 }
 
-size_t lds_x_poisson(int n, int B, int M) {
-  const size_t tiles = M <= 12 ? 1 : 2;
-  // tile(s), the plan's twiddles and those of the reversed plan, the window
-  return sizeof(float2) * (tiles * static_cast<size_t>(n) * strided_pitch(B) + 2 * n) + sizeof(float) * (n / 2 + 1);
+size_t lds_x_poisson(int n, int B, int M, bool chained) {
+  const size_t tiles = (chained || M <= 12) ? 1 : 2;
+  // tile(s), the stage twiddles (the chained form's two tables take turns), the window
+  return sizeof(float2) * (tiles * static_cast<size_t>(n) * strided_pitch(B) + n) + sizeof(float) * (n / 2 + 1);
 }
 size_t lds_z_c2r(int n, int B) {
   return sizeof(float2) * (static_cast<size_t>(n / 2 + 1) * (B + 1) + n / 2 + n / 2 + 1);
@@ -1031,7 +1077,8 @@ bool tile_ok(TileKind kind, int n, int w) {
     case TileKind::kAxisCols:  // strided y / x passes (instances 8, 16, 32)
       return (w == 8 || w == 16 || w == 32) && cols_fit(n, w) && lds_axis(n, w) <= kMaxLds;
     case TileKind::kPoissonCols:  // fused x + Poisson pass (instances 4, 8, 16)
-      return (w == 4 || w == 8 || w == 16) && cols_fit(n, w) && lds_x_poisson(n, w, poisson_points(n, w)) <= kMaxLds;
+      return (w == 4 || w == 8 || w == 16) && cols_fit(n, w) &&
+             lds_x_poisson(n, w, poisson_points(n, w), false) <= kMaxLds;
     case TileKind::kForceC2RRows:  // three-component c2r z pass (instances 4, 8, 16)
       return (w == 4 || w == 8 || w == 16) && rows_fit(n, 3 * w) && lds_z_c2r(n, 3 * w) <= kMaxLds;
   }
@@ -1102,6 +1149,7 @@ hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, bo
   if (chained) {
     if (B == 8 && M == 8) LPC_POIS(8, 8, true);
     else if (B == 8 && M == 12) LPC_POIS(8, 12, true);
+    else if (B == 8 && M == 16) LPC_POIS(8, 16, true);
     else return hipErrorInvalidValue;
   }
   else if (B == 4 && M == 8) LPC_POIS(4, 8, false);

@@ -330,37 +330,49 @@ __device__ __forceinline__ void fft_stage_from_global_pairs(float2* tile, Load l
 }
 
 // The last stage of a compile-time plan into registers: as fft_stage_c, but butterfly i of column b keeps its R
-// outputs (rows (i - k) R + k + r P) in v instead of writing the tile. For stages with one butterfly per thread
-// (T B = kFftNT): thread tid holds b = tid % B, i = tid / B. No barrier after the tile reads.
-template <int R, bool INV, int N, int P, int B, int BP>
-__device__ __forceinline__ void fft_stage_to_regs(const float2* tile, const float2* tws, int tid, float2 (&v)[R]) {
-  constexpr int T = N / R;
-  static_assert(T * B == kFftNT, "one butterfly per thread");
-  const int b = tid % B, i = tid / B;
-  const float2* src = tile + i * BP + b;
+// outputs (rows (i - k) R + k + r P) in v instead of writing the tile. Each thread owns MB butterflies of one column,
+// b = tid % B and i = tid / B + m kFftNT / B (m < MB), and they cover the stage exactly. No barrier after the tile
+// reads.
+template <int R, bool INV, int N, int P, int B, int BP, int MB>
+__device__ __forceinline__ void fft_stage_to_regs(const float2* tile, const float2* tws, int tid,
+                                                  float2 (&v)[MB][R]) {
+  constexpr int T = N / R, S = kFftNT / B;
+  static_assert(T == MB * S, "MB butterflies per thread cover the stage");
+  const int b = tid % B, i0 = tid / B;
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = src[r * T * BP];
-  const int k = ((P & (P - 1)) == 0) ? (i & (P - 1)) : (i % P);
-  if (P > 1) {
-    const float2* w = tws + k * (R - 1) - 1;
+  for (int m = 0; m < MB; ++m) {
+    const float2* src = tile + (i0 + m * S) * BP + b;
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
+    for (int r = 0; r < R; ++r) v[m][r] = src[r * T * BP];
   }
-  Dft<R, INV>::run(v);
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const int i = i0 + m * S;
+    const int k = ((P & (P - 1)) == 0) ? (i & (P - 1)) : (i % P);
+    if (P > 1) {
+      const float2* w = tws + k * (R - 1) - 1;
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[m][r] = INV ? cmulc(v[m][r], w[r]) : cmul(v[m][r], w[r]);
+    }
+    Dft<R, INV>::run(v[m]);
+  }
 }
 
 // The first stage of a compile-time plan from registers (sub-transform length 1): butterfly i of column b takes its
 // R inputs (rows i + r T) from v, and writes its DFT to the tile at rows i R + r. The same thread mapping as
 // fft_stage_to_regs, so a stage that ends in registers can feed a transform whose first radix matches its last.
-template <int R, bool INV, int N, int B, int BP>
-__device__ __forceinline__ void fft_stage_from_regs(float2* tile, float2 (&v)[R], int tid) {
-  constexpr int T = N / R;
-  static_assert(T * B == kFftNT, "one butterfly per thread");
-  const int b = tid % B, i = tid / B;
-  Dft<R, INV>::run(v);
-  float2* dst = tile + i * R * BP + b;
+template <int R, bool INV, int N, int B, int BP, int MB>
+__device__ __forceinline__ void fft_stage_from_regs(float2* tile, float2 (&v)[MB][R], int tid) {
+  constexpr int T = N / R, S = kFftNT / B;
+  static_assert(T == MB * S, "MB butterflies per thread cover the stage");
+  const int b = tid % B, i0 = tid / B;
 #pragma unroll
-  for (int r = 0; r < R; ++r) dst[r * BP] = v[r];
+  for (int m = 0; m < MB; ++m) {
+    Dft<R, INV>::run(v[m]);
+    float2* dst = tile + (i0 + m * S) * R * BP + b;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[r * BP] = v[m][r];
+  }
 }
 
 // The last stage of a compile-time plan written straight to global memory: fft_stage_c with output row

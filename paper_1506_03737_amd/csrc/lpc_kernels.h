@@ -260,7 +260,7 @@ int axis_points(int n, int B);     // points per thread of a strided tile of B c
 int r2c_points(int n, int B);      // points per thread of a forward r2c z tile of B rows (8, 12 or 16)
 int c2r_points(int n, int R);      // points per thread of a three-spectrum c2r z tile of R rows (8, 12 or 16)
 int poisson_points(int n, int B);  // points per thread of a fused x + Poisson tile (8, 12 or 16)
-size_t lds_x_poisson(int n, int B, int M);
+size_t lds_x_poisson(int n, int B, int M, bool chained);
 size_t lds_z_c2r(int n, int B);
 
 hipError_t launch_tile_key(const SortJob* jobs, WorkTable wt, int* cnt, int* key, int* rank, int* flags,
@@ -287,9 +287,10 @@ hipError_t launch_z_r2c(const ZR2CJob* jobs, WorkTable wt, bool fixed, int B, in
                         hipStream_t s);
 hipError_t launch_axis(const AxisJob* jobs, WorkTable wt, bool inverse, int B, int P, size_t lds, hipStream_t s);
 hipError_t launch_y_grad(const YGradJob* jobs, WorkTable wt, int B, int P, size_t lds, hipStream_t s);
-// chained: every job's plan is poisson_chainable, B = 8 and M <= 12 (the transforms chained through registers)
+// chained: every job's plan is poisson_chainable and B = 8 (the transforms chained through registers)
 hipError_t launch_poisson(const PoissonJob* jobs, WorkTable wt, int B, int M, bool chained, size_t lds, hipStream_t s);
-// Plans 8 x 8 x R with R in {12, 5, 4, 3}: the fused x pass can chain its transforms through registers.
+// Plans 8 x 8 x R with R in {12, 5, 4, 3}, and 4 x 4 x 8 x 8: the fused x pass can chain its transforms through
+// registers.
 bool poisson_chainable(const Plan1D& pl);
 hipError_t launch_z_c2r(const ZC2RJob* jobs, WorkTable wt, int nc, int R, int P, size_t lds, hipStream_t s);
 

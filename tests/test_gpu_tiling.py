@@ -109,6 +109,27 @@ def test_chained_x_pass_matches_oracle(nm):
     assert np.abs(out[8] - out[16]).max() < 2e-5 * np.abs(out[16]).max()
 
 
+@pytest.mark.parametrize("nm", [768, 1024])
+def test_chained_x_pass_matches_unchained_full_size(nm):
+    """At the full meshes the fused x pass runs chained through registers on 8-column tiles (plans 8 8 12 and
+    4 4 8 8, the latter with two butterflies per thread in its register stages) and unchained on 4-column tiles.
+    The two forms share no transform code beyond the butterflies: forces on 2M clustered particles agree to FP32
+    rounding, and the density is the same bits."""
+    from paper_1506_03737_amd import lpc
+    box = 1000.0 if nm == 768 else 2000.0
+    pos_d = to_dev(synth.clustered_positions(8, 2000003, box))
+    say(f"tiling: chained (8 columns) and unchained (4 columns) fused x pass at nm={nm}")
+    out = {}
+    for w in (4, 8):
+        lpc.lpc_fft_tiling_set(nm, dict(lpc.lpc_fft_tiling_default(nm), poisson_cols=w))
+        out[w] = force(lpc, pos_d, nm, box)
+    assert np.array_equal(out[4][1], out[8][1])
+    g4, g8 = out[4][0], out[8][0]
+    say(f"  rel L2 {rel_l2(g8, g4):.3e}, max {np.abs(g8 - g4).max() / np.abs(g4).max():.3e} of max")
+    assert rel_l2(g8, g4) < 2e-6
+    assert np.abs(g8 - g4).max() < 2e-5 * np.abs(g4).max()
+
+
 def test_fft_round_trip_under_other_tilings():
     """lpc_fft_r2c / lpc_fft_c2r use z_rows and axis_cols: every fitting pair against numpy.fft."""
     from paper_1506_03737_amd import autotune, lpc
