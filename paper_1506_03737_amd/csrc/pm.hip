@@ -741,6 +741,16 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
       x[0] = pos[i];
       x[1] = pos[n + i];
       x[2] = pos[2 * n + i];
+      // the momentum and displacements are loaded with the position, so that their latency overlaps the gather's
+      float v0[3], p1v[3] = {0.f, 0.f, 0.f}, p2v[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        v0[d] = vel[d * n + i];
+        if (kd.cola) {
+          p1v[d] = psi1[d * n + i];
+          p2v[d] = psi2[d * n + i];
+        }
+      }
       float g[3];
       if (!cic_gather(to_global(J.force), J.nm, J.scale, x[0], x[1], x[2], g)) {
         atomicOr(flags + kFlagNonfinite, 1);  // the particle is left as it is
@@ -750,13 +760,9 @@ __global__ __launch_bounds__(kNT) void k_gather_kick_drift(const PartJob* __rest
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           float acc = g[d];
-          float p1 = 0.f, p2 = 0.f;
-          if (kd.cola) {
-            p1 = psi1[d * n + i];
-            p2 = psi2[d * n + i];
-            acc += kd.d1 * p1 + kd.d2m * p2;
-          }
-          const float v = vel[d * n + i] + kd.kick * acc;
+          const float p1 = p1v[d], p2 = p2v[d];
+          if (kd.cola) acc += kd.d1 * p1 + kd.d2m * p2;
+          const float v = v0[d] + kd.kick * acc;
           vel[d * n + i] = v;
           if (kd.do_drift) {
             float xn = x[d] + kd.drift * v;
