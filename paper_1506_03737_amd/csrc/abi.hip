@@ -455,6 +455,16 @@ Plan1D plan_of(int n, bool radix12 = true) {
   return p;
 }
 
+// The plan of the force's y passes: 8 x 8 x 12 runs in reverse order, 12 x 8 x 8. On 8-column tiles its radix-12
+// stage has one butterfly per thread, so as the first stage it spreads the column loads evenly over the waves (a
+// radix-8 stage gives half the waves two butterflies and half one). Measured at 768^3: inverse y 2.33 -> 2.26 ms,
+// forward y 0.792 -> 0.786 ms.
+Plan1D y_plan_of(int n) {
+  const Plan1D p = plan_of(n);
+  const bool r12_last = p.nst == 3 && p.radix[0] == 8 && p.radix[1] == 8 && p.radix[2] == 12;
+  return r12_last ? kern::reversed_plan(p) : p;
+}
+
 // One 3-D transform on an n^3 mesh: the jobs of its passes.
 struct R2CSections {
   Section z, y, x;
@@ -717,6 +727,8 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     zs.push_back(z);
     i_z.push_back((z.nrows + f.Bz - 1) / f.Bz);
     kern::AxisJob y = axis_job(jp, b.A, nm, pitch, static_cast<int64_t>(nm) * pitch, 0, f.Bax);
+    y.pl = y_plan_of(nm);
+    y.tw = jp.twiddles(y.pl);
     ys.push_back(y);
     i_y.push_back(y.per_comp);
     kern::YGradJob yi{};
@@ -732,7 +744,7 @@ ForceProgram add_force(JobPack& jp, const std::vector<ForceBox>& boxes, const So
     yi.ntc1 = (nh + f.Bax / 2 - 1) / (f.Bax / 2);
     yi.per_comp1 = round8(nm * yi.ntc1);
     yi.kf = static_cast<float>(2.0 * M_PI / b.box);
-    yi.pl = plan_of(nm);
+    yi.pl = y_plan_of(nm);
     yi.tw = jp.twiddles(yi.pl);
     yis.push_back(yi);
     i_yi.push_back(yi.per_comp + yi.per_comp1);  // component 0: the x gradient; 1: the potential (y and z gradients)

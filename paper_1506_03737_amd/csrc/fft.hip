@@ -163,6 +163,7 @@ __device__ __forceinline__ void fft_io_fast(float2* tile, const float2* tw, cons
                                                                              store))                             \
     return;
   LPC_TRY_IO(8, 8, 12)
+  LPC_TRY_IO(12, 8, 8)    // 768 in the force's y passes
   LPC_TRY_IO(8, 8, 5)
   LPC_TRY_IO(8, 8, 4)
   LPC_TRY_IO(8, 8, 3)
