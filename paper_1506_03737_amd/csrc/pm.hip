@@ -843,11 +843,10 @@ __global__ __launch_bounds__(kNT) void k_frame_velocity(const PartJob* __restric
   }
 }
 
-constexpr int kPartGridCap = 256 * 8 * 4;
-
-unsigned grid_of(const WorkTable& wt, int cap) {
-  return static_cast<unsigned>(wt.total < cap ? wt.total : cap);
-}
+// One workgroup per item of kNT particles. (The kernels keep their grid-stride loops, so any grid is correct; a grid
+// capped at 8192 workgroups left the last round of resident workgroups part-full: at 768^3 the scatter took 0.60
+// against 0.53 ms and the gather/kick/drift 1.19 against 1.11 ms.)
+unsigned grid_of(const WorkTable& wt) { return static_cast<unsigned>(wt.total); }
 
 }  // namespace
 
@@ -862,7 +861,7 @@ hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s) {
 hipError_t launch_tile_key(const SortJob* jobs, WorkTable wt, int* cnt, int* key, int* rank, int* flags,
                            hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_tile_key<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, cnt, key, rank, flags);
+  k_tile_key<<<grid_of(wt), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, cnt, key, rank, flags);
   return hipGetLastError();
 }
 
@@ -880,7 +879,7 @@ hipError_t launch_scan(const int* cnt, int* start, int count, int* block_sums, h
 hipError_t launch_scatter(const SortJob* jobs, WorkTable wt, const int* key, const int* rank, const int* start,
                           hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_scatter<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, key, rank, start);
+  k_scatter<<<grid_of(wt), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, key, rank, start);
   return hipGetLastError();
 }
 
@@ -892,7 +891,7 @@ hipError_t launch_deposit_tiles(const DepJob* jobs, WorkTable wt, const int* sta
 
 hipError_t launch_unsort(const UnsortJob* jobs, WorkTable wt, hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_unsort<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total);
+  k_unsort<<<grid_of(wt), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total);
   return hipGetLastError();
 }
 
@@ -900,7 +899,7 @@ hipError_t launch_gather_kick_drift(const PartJob* jobs, WorkTable wt, KickDrift
                                     int* rank, hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
   if (key && (!cnt || !rank)) return hipErrorInvalidValue;
-  k_gather_kick_drift<false><<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd,
+  k_gather_kick_drift<false><<<grid_of(wt), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd,
                                                                         LightconeStep{}, flags, cnt, key, rank);
   return hipGetLastError();
 }
@@ -911,20 +910,20 @@ hipError_t launch_gather_kick_drift_lc(const PartJob* jobs, WorkTable wt, KickDr
   if ((key && (!cnt || !rank)) || !kd.do_drift || !lc.tab || (lc.nrep > 0 && !lc.reps) || !lc.count ||
       (lc.capacity > 0 && !lc.out))
     return hipErrorInvalidValue;
-  k_gather_kick_drift<true><<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd, lc, flags,
+  k_gather_kick_drift<true><<<grid_of(wt), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, kd, lc, flags,
                                                                        cnt, key, rank);
   return hipGetLastError();
 }
 
 hipError_t launch_gather(const PartJob* jobs, WorkTable wt, int* flags, hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_gather<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, flags);
+  k_gather<<<grid_of(wt), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_frame(const PartJob* jobs, WorkTable wt, float f1, float f2, hipStream_t s) {
   if (wt.total <= 0) return hipSuccess;
-  k_frame_velocity<<<grid_of(wt, kPartGridCap), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, f1, f2);
+  k_frame_velocity<<<grid_of(wt), kNT, 0, s>>>(jobs, wt.offs, wt.njob, wt.total, f1, f2);
   return hipGetLastError();
 }
 
