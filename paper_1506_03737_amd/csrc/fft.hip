@@ -257,7 +257,8 @@ __global__ __launch_bounds__(kFftNT, 4) void k_fft_z_r2c(const ZR2CJob* __restri
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST ZR2CJob& J = to_const(jobs)[jb];
     const int n = J.n, h = n / 2, nrows = J.nrows;
-    const int row0 = (w - offs[jb]) * B;
+    // each XCD takes a contiguous range of row blocks (r2c 0.72 -> 0.68 ms, c2r 2.25 -> 2.20 ms at 768^3)
+    const int row0 = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]) * B;
     if (row0 >= nrows) return;  // padding item (uniform; no LDS touched)
     float2* tile = smem;
     float2* tw = tile + h * BP;
@@ -767,7 +768,7 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 12) ? 6 : 4) void k_fft_z_c2r(const
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST ZC2RJob& J = to_const(jobs)[jb];
     const int n = J.n, h = n / 2, nrows = J.nrows, pitch = J.pitch;
-    const int row0 = (w - offs[jb]) * R;
+    const int row0 = xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb]) * R;  // as in the r2c: XCD-contiguous rows
     if (row0 >= nrows) return;  // padding item
     float2* tile = smem;                 // (h + 1) x BP
     float2* tw = tile + (h + 1) * BP;    // stage twiddles (h)

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kNT) void k_tile_key(const SortJob* __restrict__ jo
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST SortJob& J = to_const(jobs)[jb];
     const int64_t n = J.n;
-    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    const int64_t i = static_cast<int64_t>(xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb])) * kNT + threadIdx.x;
     const bool active = i < n;
     int g = 0;
     if (active) {
@@ -267,6 +267,10 @@ __global__ __launch_bounds__(kNT) void k_scan_add(int* __restrict__ start, int c
     if (base + k < count) start[base + k] += add;
 }
 
+// The sort's kernels (keys, scatter, unsort) give each XCD a contiguous range of particles (xcd_remap), so that the
+// runs they write into one bucket mostly come from one XCD's L2: scatter 0.53 -> 0.52 ms, unsort 0.55 -> 0.46 ms at
+// 768^3. The gather/kick/drift and the frame momentum measured slower that way (1.11 -> 1.15 and 0.15 -> 0.17 ms) and
+// keep consecutive items on consecutive XCDs.
 __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ jobs, const int* __restrict__ offs,
                                                  int njob, int total, const int* __restrict__ key,
                                                  const int* __restrict__ rank, const int* __restrict__ start) {
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ job
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST SortJob& J = to_const(jobs)[jb];
     const int64_t n = J.n;
-    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    const int64_t i = static_cast<int64_t>(xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb])) * kNT + threadIdx.x;
     if (i >= n) continue;
     const int64_t gi = J.pbase + i;
     const int64_t dst = static_cast<int64_t>(start[key[gi]]) + rank[gi] - J.pbase;
@@ -534,7 +538,7 @@ __global__ __launch_bounds__(kNT) void k_unsort(const UnsortJob* __restrict__ jo
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST UnsortJob& J = to_const(jobs)[jb];
     const int64_t n = J.n;
-    const int64_t i = static_cast<int64_t>(w - offs[jb]) * kNT + threadIdx.x;
+    const int64_t i = static_cast<int64_t>(xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb])) * kNT + threadIdx.x;
     if (i >= n) continue;
     const int64_t o = to_global(J.orig)[i];
     LPC_GLOBAL const float* sp = to_global(J.spos);
