@@ -434,7 +434,9 @@ __global__ __launch_bounds__(kFftNT, (EPT <= 8) ? 6 : 4) void k_fft_axis(const A
     const LPC_CONST AxisJob& J = to_const(jobs)[jb];
     const int local = w - offs[jb];
     const int comp = local / J.per_comp;
-    const int t = xcd_remap(local - comp * J.per_comp, J.per_comp);
+    // XCD-contiguous chunks of 32 items rather than eighths (forward y 0.785 -> 0.759 ms at 768^3; the other strided
+    // passes and the z passes measured no better that way)
+    const int t = xcd_chunk_remap(local - comp * J.per_comp, J.per_comp, 32);
     const int outer = t / J.ntc, ct = t - outer * J.ntc;
     const int n = J.n;
     if (outer >= n) return;  // padding item

@@ -124,6 +124,16 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return xcd * per + min(xcd, rem) + local;
 }
 
+// XCD-contiguous chunks of C items: XCD x (which takes the blocks b = x mod 8) processes the chunks 8 c + x, c = 0,
+// 1, ..., so at any time the eight XCDs work on eight adjacent chunks rather than on eight distant eighths of the
+// items. Items past the last whole group of 8 C take xcd_remap's order. A permutation of [0, n) for n a multiple of 8.
+__device__ __forceinline__ int xcd_chunk_remap(int bid, int n, int C) {
+  const int full = n / (8 * C) * (8 * C);
+  if (bid >= full) return full + xcd_remap(bid - full, n - full);
+  const int x = bid % 8, k = bid / 8;
+  return ((k / C) * 8 + x) * C + k % C;
+}
+
 struct WorkTable {
   const int* offs;
   int njob;
