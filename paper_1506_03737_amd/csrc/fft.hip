@@ -615,8 +615,7 @@ __device__ __forceinline__ bool x_poisson_chained(float2* tile, float2* tw, cons
 // in the thread's registers, so the workgroup needs one LDS tile and two workgroups fit on a CU; with M = 16 a second
 // LDS tile holds them (the registers would spill). The two forms are separate instances because the generic form's
 // register allocation would otherwise cover the chained form's too (and spill). The chained M = 8 instance (the
-// 192-320 meshes) is capped at 80 VGPRs, so that three workgroups fit on a CU (one register spills; 48-box step
-// 30.86 -> 30.25 ms).
+// 192-320 meshes) is capped at 80 VGPRs, so that three workgroups fit on a CU (48-box step 30.86 -> 30.25 ms).
 template <int B, int M, bool CHAIN>
 __global__ __launch_bounds__(kFftNT, (CHAIN && M <= 8) ? 6 : ((CHAIN || M <= 12) ? 4 : 2)) void k_fft_x_poisson(
     const PoissonJob* __restrict__ jobs, const int* __restrict__ offs, int njob, int total) {

@@ -79,8 +79,9 @@ hipError_t fill_i32(int* p, size_t count, int value, hipStream_t s);
 
 // ---------------------------------------------------------------------------------------------------------------
 // Batched stage launches. Every stage kernel runs over the items of a work table: FFT kernels take one item per
-// workgroup (w = blockIdx.x); the light particle kernels walk w = blockIdx.x, blockIdx.x + G, ... with a capped grid
-// of G workgroups. Item w belongs to job j with offs[j] <= w < offs[j + 1]
+// workgroup (w = blockIdx.x); the particle kernels are launched with one workgroup per item too, and their loops
+// walk w = blockIdx.x, blockIdx.x + G, ... (so any grid of G workgroups is correct). Item w belongs to job j with
+// offs[j] <= w < offs[j + 1]
 // (offs has njob + 1 entries, offs[0] = 0, offs[njob] = total, every offs[j] a multiple of 8 so that items keep their
 // XCD position within a job). A single box is a batch of one job. Job arrays and offsets live in device memory.
 // Pointers read from job tables are generic; casting them to the global address space lets the compiler issue

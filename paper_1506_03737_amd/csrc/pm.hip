@@ -7,8 +7,8 @@
 // so every particle adds exactly 2^48 and the mesh does not depend on the order of the additions. The gather uses
 // the same u, with weights f 2^-16 and 1 - f 2^-16 (exact in FP32), so it is the transpose of the deposit.
 //
-// The kernels are batched over the jobs (boxes) of a work table, with a capped grid that strides over the items;
-// an item is kNT particles of one box.
+// The kernels are batched over the jobs (boxes) of a work table and launched with one workgroup per item (their
+// loops stride over the grid, so any grid size is correct); an item is kNT particles of one box.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
