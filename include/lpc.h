@@ -387,7 +387,7 @@ lpc_status lpc_net_adam(float* params, float* m, float* v, const float* grad, in
 
 /* Scales the network's output in place: the output layer (the last, linear layer: its weights and biases) of the
  * device parameter vector params is multiplied by gain, so network(x) becomes gain network(x) up to the BF16 rounding
- * of the scaled weights. Used to calibrate a trained correction against the statistic it is judged by (the trainer
+ * of the scaled weights. Used to calibrate a trained correction against the statistic it is evaluated by (the trainer
  * picks gain on held-out pairs). Asynchronous on `stream`; LPC_ERR_INVALID_ARG for a NULL or misaligned params or a
  * non-finite gain. */
 lpc_status lpc_net_scale_output(float* params, float gain, void* stream);

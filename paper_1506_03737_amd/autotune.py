@@ -61,7 +61,7 @@ def tune(n_mesh, device="cuda", reps=5, box=1000.0, seed=0, log=None):
     """Measure every fitting width of every pass at mesh size n_mesh and set the fastest as the override.
 
     The passes are separate kernels, so round i runs every field at its i-th candidate (the last one repeated when a
-    field has fewer) and each field is judged by its own stages' times: max(len(candidates)) rounds in all.
+    field has fewer) and each field is ranked by its own stages' times: max(len(candidates)) rounds in all.
     Returns {"n_mesh", "tiling", "default", "stage_ms": {field: {width: ms}}, "seconds"}."""
     import torch
     t0 = time.perf_counter()

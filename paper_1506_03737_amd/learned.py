@@ -106,11 +106,11 @@ def power_spectrum(pos, n, box, device, nm_est=512, k_max=1.0, n_bins=100):
     return lpc.lpc_power_spectrum(g, pos, k_max, n_bins, ws)
 
 
-def pk_max_error(pos, ref_pos, n, box, device, k_judge=0.5, nm_est=512, n_bins=100):
-    """max over k <= k_judge of |P(pos) / P(ref_pos) - 1| (binned P(k), empty bins skipped)."""
+def pk_max_error(pos, ref_pos, n, box, device, k_eval=0.5, nm_est=512, n_bins=100):
+    """max over k <= k_eval of |P(pos) / P(ref_pos) - 1| (binned P(k), empty bins skipped)."""
     k, p_ref, cnt = power_spectrum(ref_pos, n, box, device, nm_est=nm_est, n_bins=n_bins)
     _, p, _ = power_spectrum(pos, n, box, device, nm_est=nm_est, n_bins=n_bins)
-    sel = (k <= k_judge) & (cnt > 0)
+    sel = (k <= k_eval) & (cnt > 0)
     return float(np.max(np.abs(p[sel] / p_ref[sel] - 1.0)))
 
 
@@ -126,13 +126,13 @@ def corrected(params, coarse, n_side, box, device, ws=None):
 GAINS = tuple(round(0.40 + 0.05 * i, 2) for i in range(13))
 
 
-def calibrate_gain(params, runs, n_side, box, device, gains=GAINS, nm_est=None, n_bins=50, k_judge=0.5):
+def calibrate_gain(params, runs, n_side, box, device, gains=GAINS, nm_est=None, n_bins=50, k_eval=0.5):
     """The output gain that makes the corrected held-out runs' P(k) match their fine runs' best.
 
     A network trained on the mean squared displacement error returns, at each site, the mean residual given its
     inputs; moved by it, particles cluster more than the fine run's at k ~ 0.3-0.5 h/Mpc. One scalar on the output
     layer (lpc_net_scale_output) trades that back: for every g in gains the held-out coarse runs are corrected with
-    g network(x) and judged by the mean over runs of max_{k <= k_judge} |P_corr / P_fine - 1|. runs: [(coarse, fine)]
+    g network(x) and scored by the mean over runs of max_{k <= k_eval} |P_corr / P_fine - 1|. runs: [(coarse, fine)]
     particle sets that were not trained on. Returns (best g, params scaled by it (a copy), {g: error})."""
     import torch
     nm_est = nm_est or 2 * n_side
@@ -142,7 +142,7 @@ def calibrate_gain(params, runs, n_side, box, device, gains=GAINS, nm_est=None, 
         pg = torch.clone(params)
         lpc.lpc_net_scale_output(pg, g)
         errs = [pk_max_error(corrected(pg, c, n_side, box, device, ws).pos, f.pos, n_side**3, box, device,
-                             k_judge, nm_est, n_bins) for c, f in runs]
+                             k_eval, nm_est, n_bins) for c, f in runs]
         errors[g] = float(np.mean(errs))
     best = min(errors, key=errors.get)
     pb = torch.clone(params)

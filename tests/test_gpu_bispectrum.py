@@ -5,7 +5,7 @@ The deposit is bitwise the oracle's, so both sides start from the same density; 
 inverse transforms (relative rounding ~1e-7 per value, growing as log2 of the mesh) and by FP32 storage of the
 filtered fields. Shell membership is decided by the same FP64 arithmetic on both sides, so the mode sets agree
 exactly. Bars: B, Q and the shell powers within 1.5e-6 relative (measured at most 4.0e-7 on these inputs), at
-estimator meshes 48, 64 and 128 (the learned form's judge size); shells that close no triangle give NaN.
+estimator meshes 48, 64 and 128 (the learned form's evaluation mesh); shells that close no triangle give NaN.
 """
 import numpy as np
 import pytest
