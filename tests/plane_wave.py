@@ -1,28 +1,30 @@
-"""Sampled evaluation of the oracle's PM force (oracle/pm.py) for a lattice displaced along x only.
+"""Sampled evaluation of the oracle's PM force (oracle/pm.py) for a lattice displaced along one axis only.
 
 Test infrastructure: it applies the oracle's own definitions (fixed-point CIC deposit, CIC window W^p, Green's function
 -1/k^2, spectral derivative i k_j, Nyquist and k = 0 zeroing, 1/Nm^3 inverse normalisation, fixed-point CIC gather)
 to a special input on which they can be evaluated particle by particle at full size.
 
-The input: N^3 particles at lattice cell centres q = (i + 1/2) L / N, displaced along x only by a function of q_x, in a
-box with L = Nm (so the fixed-point scale Nm 2^16 / L is 2^16 and every y and z coordinate, 3 j + 3/2 for Nm = 3 N,
-is exact). A particle's deposit weights are a product of per-axis weights, and its x weights depend on i alone, its
-y weights on j alone, its z weights on l alone, so the counts factor exactly: C = X (x) Y (x) Z with X, Y, Z the
-summed per-axis weights of one lattice line. Y and Z repeat with the lattice period, so their DFTs vanish except at
-multiples of N: the density spectrum, and with it each gradient spectrum, lives on Nm x (few) x (few) modes, and the
-force mesh at any node is a direct sum over those modes.
+The input: N^3 particles at lattice cell centres q = (i + 1/2) L / N, displaced along one axis (x unless stated) by a
+function of that axis's q, in a box with L = Nm (so the fixed-point scale Nm 2^16 / L is 2^16 and every undisplaced
+coordinate, 3 j + 3/2 for Nm = 3 N, is exact). A particle's deposit weights are a product of per-axis weights, and its
+x weights depend on i alone, its y weights on j alone, its z weights on l alone, so the counts factor exactly:
+C = X (x) Y (x) Z with X, Y, Z the summed per-axis weights of one lattice line. The two undisplaced factors repeat
+with the lattice period, so their DFTs vanish except at multiples of N: the density spectrum, and with it each
+gradient spectrum, lives on Nm x (few) x (few) modes (the displaced axis taking all Nm), and the force mesh at any
+node is a direct sum over those modes.
 """
 import numpy as np
 
 from oracle import pm
 
 
-def lattice_plane_wave(N, box, amp, mode):
-    """FP32 positions (3, N^3) in lattice order: x = q_x + amp sin(2 pi mode q_x / L), y = q_y, z = q_z."""
+def lattice_plane_wave(N, box, amp, mode, axis=0):
+    """FP32 positions (3, N^3) in lattice order (i, j, l): coordinate `axis` is q + amp sin(2 pi mode q / L) of its own
+    lattice index, the other two are q."""
     q = (np.arange(N, dtype=np.float64) + 0.5) * (box / N)
-    qx = q + amp * np.sin(2.0 * np.pi * mode * q / box)
-    i, j, l = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
-    pos = np.stack([qx[i.ravel()], q[j.ravel()], q[l.ravel()]]).astype(np.float32)
+    qd = q + amp * np.sin(2.0 * np.pi * mode * q / box)
+    idx = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    pos = np.stack([(qd if a == axis else q)[idx[a].ravel()] for a in range(3)]).astype(np.float32)
     return pos
 
 
@@ -51,14 +53,17 @@ def force_at(pos, N, n_mesh, box, sample, deconv_power=1):
     X, Y, Z = factors(pos, N, n_mesh, box)
     n = N**3
     m = n_mesh**3 / float(n)
-    Xh, Yh, Zh = (np.fft.fft(a.astype(np.float64)) for a in (X, Y, Z))
-    sy = np.flatnonzero(np.abs(Yh) > 1e-9 * np.abs(Yh).max())
-    sz = np.flatnonzero(np.abs(Zh) > 1e-9 * np.abs(Zh).max())
-    assert len(sy) <= 8 and len(sz) <= 8, "Y and Z are not lattice-periodic"
+    hats = [np.fft.fft(a.astype(np.float64)) for a in (X, Y, Z)]
+    # the displaced axis keeps all Nm modes; the two lattice-periodic factors have a few
+    sparse = [np.flatnonzero(np.abs(h) > 1e-9 * np.abs(h).max()) for h in hats]
+    full = int(np.argmax([len(s) for s in sparse]))
+    supp = [np.arange(n_mesh) if a == full else sparse[a] for a in range(3)]
+    assert all(len(supp[a]) <= 8 for a in range(3) if a != full), "two factors are not lattice-periodic"
     nf = np.fft.fftfreq(n_mesh, d=1.0 / n_mesh)  # signed mode numbers
-    kx, ky, kz = np.meshgrid(nf, nf[sy], nf[sz], indexing="ij")
+    kx, ky, kz = np.meshgrid(nf[supp[0]], nf[supp[1]], nf[supp[2]], indexing="ij")
     # full-spectrum density contrast on the support: (m 2^-3F) X^ Y^ Z^ - Nm^3 [k = 0]
-    dh = (m * 2.0 ** (-3 * pm.FRAC_BITS)) * (Xh[:, None, None] * Yh[sy][None, :, None] * Zh[sz][None, None, :])
+    dh = (m * 2.0 ** (-3 * pm.FRAC_BITS)) * (hats[0][supp[0]][:, None, None] * hats[1][supp[1]][None, :, None] *
+                                              hats[2][supp[2]][None, None, :])
     zero = (kx == 0) & (ky == 0) & (kz == 0)
     dh = np.where(zero, dh - n_mesh**3, dh)
     kf = 2.0 * np.pi / box

@@ -147,17 +147,19 @@ def test_full_size_single_box_properties():
     assert torch.equal(grad, grad2)
 
 
-def test_full_size_plane_wave_parity():
+@pytest.mark.parametrize("axis", [0, 1, 2], ids=["x", "y", "z"])
+def test_full_size_plane_wave_parity(axis):
     """The single-box launch shape (256^3 particles, 768^3 mesh, built-in tile widths) on the separable lattice input
-    of tests/plane_wave.py (box 768 Mpc/h, so the fixed-point scale is 2^16; x displaced by a sine of mode 5): the int64
-    density at 4096 sampled cells equals X Y Z bit for bit, and the force at 512 sampled particles, against the oracle's
-    definitions evaluated there, meets the bar of the small meshes."""
+    of tests/plane_wave.py (box 768 Mpc/h, so the fixed-point scale is 2^16; one axis displaced by a sine of mode 5, so
+    that the signal runs through that axis's transforms: the fused x pass, the y passes with their 12 8 8 plan, or
+    the z passes): the int64 density at 4096 sampled cells equals X Y Z bit for bit, and the force at 512 sampled
+    particles, against the oracle's definitions evaluated there, meets the bar of the small meshes."""
     from paper_1506_03737_amd import lpc
     from tests import plane_wave as pw
     N, nm = 256, 768
     box = float(nm)
-    say("pm_force: 256^3 plane-wave lattice, 768^3 mesh, sampled parity")
-    pos = pw.lattice_plane_wave(N, box, 0.4 * box / N, 5)
+    say(f"pm_force: 256^3 plane-wave lattice displaced along axis {axis}, 768^3 mesh, sampled parity")
+    pos = pw.lattice_plane_wave(N, box, 0.4 * box / N, 5, axis)
     X, Y, Z = pw.factors(pos, N, nm, box)
     geom = lpc.geometry(N, nm, box)
     ws = lpc.workspace(geom, lpc.LPC_OP_PM_FORCE)

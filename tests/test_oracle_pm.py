@@ -117,13 +117,15 @@ def test_gather_of_linear_ramp_is_exact_inside():
     assert np.allclose(out[0], frac_pos, atol=1e-12)
 
 
-def test_plane_wave_sampled_force_equals_oracle():
-    """The separable lattice input of tests/plane_wave.py: its factored counts equal deposit_fixed bit for bit, and the
-    mode sum over the density's support equals pm.pm_force (full FFTs) at every sampled particle (N = 32, Nm = 96)."""
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_plane_wave_sampled_force_equals_oracle(axis):
+    """The separable lattice input of tests/plane_wave.py, displaced along each axis in turn: its factored counts equal
+    deposit_fixed bit for bit, and the mode sum over the density's support equals pm.pm_force (full FFTs) at every
+    sampled particle (N = 32, Nm = 96)."""
     from tests import plane_wave as pw
     N, nm = 32, 96
     box = float(nm)
-    pos = pw.lattice_plane_wave(N, box, 0.4 * box / N, 3)
+    pos = pw.lattice_plane_wave(N, box, 0.4 * box / N, 3, axis)
     X, Y, Z = pw.factors(pos, N, nm, box)
     C = pm.deposit_fixed(pos.astype(np.float64), nm, box)
     assert np.array_equal(C, X[:, None, None] * Y[None, :, None] * Z[None, None, :])
