@@ -210,3 +210,34 @@ def test_full_size_large_box_launch_shape():
     say(f"  force rel L2 {rel_l2(g, ref):.3e}, max {np.abs(g - ref).max() / np.abs(ref).max():.3e} of max")
     assert rel_l2(g, ref) < 2e-5
     assert np.abs(g - ref).max() < 2e-4 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("axis", [1, 2], ids=["y", "z"])
+def test_full_size_large_box_plane_wave_axes(axis):
+    """The large launch shape (512^3 particles, 1024^3 mesh, built-in tile widths) on the separable lattice input
+    displaced along y or z (mode 3), so the y or z passes of the 1024 transforms carry the signal: the int64 density at
+    4096 sampled cells equals X Y Z bit for bit and the force at 512 sampled particles meets the small meshes' bar."""
+    from paper_1506_03737_amd import lpc
+    from tests import plane_wave as pw
+    N, nm = 512, 1024
+    box = float(nm)
+    say(f"pm_force: 512^3 plane-wave lattice displaced along axis {axis}, 1024^3 mesh, sampled parity")
+    pos = pw.lattice_plane_wave(N, box, 0.4 * box / N, 3, axis)
+    X, Y, Z = pw.factors(pos, N, nm, box)
+    geom = lpc.geometry(N, nm, box)
+    ws = lpc.workspace(geom, lpc.LPC_OP_PM_FORCE)
+    grad = torch.empty((3, N**3), dtype=torch.float32, device="cuda")
+    dens = torch.empty((nm, nm, nm), dtype=torch.int64, device="cuda")
+    lpc.lpc_pm_force(geom, lpc.stepping(), to_dev(pos), grad, ws, density_out=dens)
+    del ws
+    rng = np.random.default_rng(13 + axis)
+    cells = rng.integers(0, nm, size=(3, 4096))
+    ci = torch.as_tensor(cells, device="cuda")
+    assert np.array_equal(to_np(dens[ci[0], ci[1], ci[2]]), X[cells[0]] * Y[cells[1]] * Z[cells[2]])
+    del dens
+    sample = rng.choice(N**3, 512, replace=False)
+    ref = pw.force_at(pos, N, nm, box, sample)
+    g = to_np(grad)[:, sample].astype(np.float64)
+    say(f"  force rel L2 {rel_l2(g, ref):.3e}, max {np.abs(g - ref).max() / np.abs(ref).max():.3e} of max")
+    assert rel_l2(g, ref) < 2e-5
+    assert np.abs(g - ref).max() < 2e-4 * np.abs(ref).max()
