@@ -148,8 +148,9 @@ lpc_status lpc_init_ic_png(const lpc_geometry* geom, const lpc_cosmology* cosmo,
                            const lpc_png* png, const lpc_particles* out, void* ws, size_t ws_bytes, void* stream);
 
 /* The particle-mesh force of Sec. 2.4 (Eqs. 20-21) at positions pos[3][n]:
- *   particles sorted by mesh tile (16^3 cells) into the workspace (the single-GPU counterpart of moving particles
- *   to the process that owns their slab, Sec. 4.4), fixed-point CIC deposit by one workgroup per tile
+ *   particles sorted by mesh tile (16 x 8 x 32 cells along x, y, z) into the workspace (the single-GPU counterpart
+ *   of moving particles to the process that owns their slab, Sec. 4.4), fixed-point CIC deposit by one workgroup
+ *   per tile
  *   (16 fractional bits per axis, int64 counts, each particle adds exactly 2^48),
  *   delta = C (Nm^3 / n) 2^-48 - 1, forward r2c FFT, g_hat_j = i k_j (-1/k^2) delta_hat / W^p
  *   (W = prod sinc^2(pi n_d / Nm), p = step->deconv_power, zero at k = 0 and on the Nyquist plane of axis j),
