@@ -181,10 +181,13 @@ __global__ __launch_bounds__(kNT) void k_tile_key(const SortJob* __restrict__ jo
     if (active) {
       LPC_GLOBAL const float* pos = to_global(J.pos);
       const int64_t period = static_cast<int64_t>(J.nm) << kFracBits;
+      float x[3];  // the three loads go out together
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = pos[d * n + i];
       uint32_t c[3], f[3];
       bool ok = true;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) ok &= fixed_coord(pos[d * n + i], J.scale, period, &c[d], &f[d]);
+      for (int d = 0; d < 3; ++d) ok &= fixed_coord(x[d], J.scale, period, &c[d], &f[d]);
       int b = 2 * J.ntx * J.nty * J.ntz;
       if (ok)
         b = bucket_of(c[0], c[1], c[2], J);
@@ -271,6 +274,8 @@ __global__ __launch_bounds__(kNT) void k_scan_add(int* __restrict__ start, int c
 // runs they write into one bucket mostly come from one XCD's L2: scatter 0.53 -> 0.52 ms, unsort 0.55 -> 0.46 ms at
 // 768^3. The gather/kick/drift and the frame momentum measured slower that way (1.11 -> 1.15 and 0.15 -> 0.17 ms; the
 // gather 1.22 ms with XCD-contiguous chunks of 32) and keep consecutive items on consecutive XCDs.
+// The scatter copies one array at a time (each load next to its store); issuing all of a particle's loads first
+// measured slower (0.51 -> 0.54 ms).
 __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ jobs, const int* __restrict__ offs,
                                                  int njob, int total, const int* __restrict__ key,
                                                  const int* __restrict__ rank, const int* __restrict__ start) {
