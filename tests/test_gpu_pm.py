@@ -42,6 +42,12 @@ CASES = [
     ("clustered n=150001 nm=192", lambda: synth.clustered_positions(4, 150001, 400.0), 192, 400.0),
     ("clustered n=200003 nm=256", lambda: synth.clustered_positions(5, 200003, 500.0), 256, 500.0),
     ("clustered n=250007 nm=320", lambda: synth.clustered_positions(6, 250007, 600.0), 320, 600.0),
+    # meshes that are not multiples of the 16 x 8 x 32-cell sort tile, so the last tile along every axis is narrow
+    # and the lower neighbour of tile 0 is a narrow tile: 20 = 16 + 4 (x), 2 x 8 + 4 (y); 36 = 2 x 16 + 4,
+    # 4 x 8 + 4, 32 + 4; 90 = 5 x 16 + 10, 11 x 8 + 2, 2 x 32 + 26 (with radix-3 and radix-5 FFT plans)
+    ("uniform n=2999 nm=20", lambda: synth.uniform_positions(10, 2999, 40.0), 20, 40.0),
+    ("clustered n=40009 nm=36", lambda: synth.clustered_positions(11, 40009, 150.0), 36, 150.0),
+    ("clustered n=90001 nm=90", lambda: synth.clustered_positions(12, 90001, 300.0), 90, 300.0),
 ]
 
 
