@@ -19,8 +19,10 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 
 C = synth.COSMOLOGY
 
-# (n_side, n_mesh, box, seed): ragged mesh sizes (40 = 8 x 5, 48 = 16 x 3, 96) and unequal particle counts
-BOXES = [(16, 32, 128.0, 11), (20, 40, 160.0, 12), (24, 48, 200.0, 13), (32, 96, 256.0, 14), (16, 48, 100.0, 15)]
+# (n_side, n_mesh, box, seed): ragged mesh sizes (40 = 8 x 5, 48 = 16 x 3, 96; 36, whose last 16 x 8 x 32-cell sort
+# tile is narrow along every axis) and unequal particle counts
+BOXES = [(16, 32, 128.0, 11), (20, 40, 160.0, 12), (24, 48, 200.0, 13), (32, 96, 256.0, 14), (16, 48, 100.0, 15),
+         (18, 36, 120.0, 16)]
 
 
 def box_ic(n_side, box, seed):

@@ -73,15 +73,17 @@ def test_stepping_variants(step):
         assert d.max() < 1e-5
 
 
-def test_ragged_mesh_and_count():
-    """A mesh that is not a power of two (Nm = 96 = 3 x 32) and Nm = 3N, with the 48^3 lattice."""
+@pytest.mark.parametrize("n_side,nm", [(32, 96), (30, 90), (18, 36)])
+def test_ragged_mesh_and_count(n_side, nm):
+    """Meshes that are not powers of two, with Nm = 3N: 96 = 3 x 32, and 90 and 36, which are not multiples of the
+    16 x 8 x 32-cell sort tile, so the sort key computed in the drift kernel sees a narrow last tile along every axis."""
     from paper_1506_03737_amd import lpc
-    say("cola: N=32, Nm=96")
-    box = 256.0
-    ic32 = small_ic(4)
+    say(f"cola: N={n_side}, Nm={nm}")
+    box = 8.0 * n_side
+    ic32 = small_ic(4, n_side, box)
     a = synth.A_LIST[:6]
-    x, v = gpu_run(lpc, ic32, a, 32, 96, box)
-    xr, vr = oracle_run(ic32, a, 96, box)
+    x, v = gpu_run(lpc, ic32, a, n_side, nm, box)
+    xr, vr = oracle_run(ic32, a, nm, box)
     assert np.abs(periodic_diff(x, xr, box)).max() / box < 1e-5
 
 
