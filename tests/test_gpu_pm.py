@@ -88,6 +88,28 @@ def test_order_invariance_and_run_to_run_determinism():
     assert np.array_equal(g1[:, perm], g3)        # each particle's force does not depend on the order
 
 
+@pytest.mark.parametrize("ratio", [1, 2, 3])
+def test_unperturbed_lattice_feels_no_force(ratio):
+    """An unperturbed lattice (Sec. 2.4: the force of a uniform distribution vanishes). With Nm = N every node holds
+    one particle, the contrast is exactly zero and so is the force, bit for bit. With Nm = 2N or 3N the particles sit
+    on every second or third node: the density is periodic with the lattice and symmetric about each particle, so the
+    mesh force is odd about each particle and vanishes there (for 2N its modes lie on Nyquist planes, where the
+    derivative is zero); in FP32 it is rounding noise, far below the forces of a perturbed field (~1-1000)."""
+    from paper_1506_03737_amd import lpc
+    n_side, box = 32, 256.0
+    nm = ratio * n_side
+    say(f"pm_force: unperturbed lattice N={n_side}, Nm={nm}")
+    q = (np.arange(n_side) * (box / n_side)).astype(np.float32)
+    pos = np.stack([g.ravel() for g in np.meshgrid(q, q, q, indexing="ij")]).astype(np.float32)
+    assert np.abs(opm.pm_force(pos.astype(np.float64), nm, box)).max() < 1e-9
+    grad, dens = run_force(lpc, pos, nm, box)
+    assert np.array_equal(dens, opm.deposit_fixed(pos, nm, box))
+    if ratio == 1:
+        assert not grad.any()
+    else:
+        assert np.abs(grad).max() < 1e-4
+
+
 def test_zero_net_force():
     from paper_1506_03737_amd import lpc
     say("pm_force: zero net force")
