@@ -442,8 +442,9 @@ __global__ __launch_bounds__(kNT) void k_deposit_tiles(const DepJob* __restrict_
   const LPC_CONST DepJob& J = to_const(jobs)[jb];
   const int ntx = J.ntx, nty = J.nty, ntz = J.ntz, nm = J.nm;
   // neighbouring tiles (which share the particles of their boundary buckets) run on the same XCD
-  // tiles in XCD-contiguous chunks of 32 (0.748 -> 0.736 ms at 768^3 against eighths of the tiles per XCD)
-  const int t = xcd_chunk_remap(w - offs[jb], offs[jb + 1] - offs[jb], 32);
+  // tiles in XCD-contiguous chunks of 64 (at 768^3: 0.748 ms with eighths of the tiles per XCD, 0.736 ms with chunks
+  // of 32, 0.70 ms with 64; 48, 72, 96, 128 and 256 measured 0.71-0.75 ms)
+  const int t = xcd_chunk_remap(w - offs[jb], offs[jb + 1] - offs[jb], 64);
   if (t >= ntx * nty * ntz) return;  // padding item
   const int tid = threadIdx.x;
   clear_tile(acc, tid);
