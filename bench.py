@@ -49,8 +49,8 @@ def note(msg):
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes (read scaled by 2.0, write by 1.0, from
 # a 1 GiB copy), by (stage, mesh size, tile width of the stage); profiles/force_path_768_hbm_traffic.md. Must be
 # re-measured (or removed) when the kernel changes.
-MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 9.290e9, ("fft x + poisson", 768, 8): 5.665e9,
-                    ("fft y", 768, 8): 3.795e9, ("fft z r2c", 768, 16): 3.643e9}
+MEASURED_TRAFFIC = {("fft z c2r", 768, 4): 10.985e9, ("fft y inv", 768, 8): 9.292e9, ("fft x + poisson", 768, 8): 5.657e9,
+                    ("fft y", 768, 8): 3.796e9, ("fft z r2c", 768, 16): 3.643e9}
 
 # Stages run once per force evaluation: their algorithmic bytes are counted per evaluation and spread over its launches
 PER_EVALUATION = ("deposit", "fft z r2c", "fft y", "fft x + poisson", "fft y inv", "fft z c2r", "gather kick drift")
