@@ -270,10 +270,12 @@ __global__ __launch_bounds__(kNT) void k_scan_add(int* __restrict__ start, int c
     if (base + k < count) start[base + k] += add;
 }
 
-// The sort's kernels (keys, scatter, unsort) give each XCD a contiguous range of particles (xcd_remap), so that the
-// runs they write into one bucket mostly come from one XCD's L2: scatter 0.53 -> 0.52 ms, unsort 0.55 -> 0.46 ms at
-// 768^3. The gather/kick/drift and the frame momentum measured slower that way (1.11 -> 1.15 and 0.15 -> 0.17 ms; the
-// gather 1.22 ms with XCD-contiguous chunks of 32) and keep consecutive items on consecutive XCDs.
+// The sort's kernels (keys, scatter, unsort) give each XCD contiguous ranges of particles, so that the runs they
+// write into one bucket mostly come from one XCD's L2: eighths of the range per XCD (xcd_remap) took the scatter from
+// 0.53 to 0.52 ms and the unsort from 0.55 to 0.46 ms at 768^3; the scatter then takes XCD-contiguous chunks of 64
+// items in turn (xcd_chunk_remap: 0.52 -> 0.48 ms; chunks of 256 the same, the key pass and the unsort no different).
+// The gather/kick/drift and the frame momentum measured slower with eighths (1.11 -> 1.15 and 0.15 -> 0.17 ms; the
+// gather 1.22 ms with chunks of 32) and keep consecutive items on consecutive XCDs.
 // The scatter copies one array at a time (each load next to its store); issuing all of a particle's loads first
 // measured slower (0.51 -> 0.54 ms).
 __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ jobs, const int* __restrict__ offs,
@@ -283,7 +285,8 @@ __global__ __launch_bounds__(kNT) void k_scatter(const SortJob* __restrict__ job
     const int jb = __builtin_amdgcn_readfirstlane(find_job(to_const(offs), njob, w));
     const LPC_CONST SortJob& J = to_const(jobs)[jb];
     const int64_t n = J.n;
-    const int64_t i = static_cast<int64_t>(xcd_remap(w - offs[jb], offs[jb + 1] - offs[jb])) * kNT + threadIdx.x;
+    const int64_t i =
+        static_cast<int64_t>(xcd_chunk_remap(w - offs[jb], offs[jb + 1] - offs[jb], 64)) * kNT + threadIdx.x;
     if (i >= n) continue;
     const int64_t gi = J.pbase + i;
     const int64_t dst = static_cast<int64_t>(start[key[gi]]) + rank[gi] - J.pbase;
