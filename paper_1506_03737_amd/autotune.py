@@ -57,8 +57,19 @@ def _stage_ms(run, reps):
     return {k: ms / max(1, n) for k, (n, ms) in stats.items()}
 
 
+TIE = 0.03  # widths timed within 3 % of the fastest count as tied
+
+
+def pick(times, tie=TIE):
+    """The width to use from {width: ms}: the widest one within `tie` of the fastest. Widths that close are within
+    the timing noise of one tuning round, and the wider tile is kept because a batched launch runs every box at the
+    narrowest width any of its mesh sizes was given."""
+    fastest = min(times.values())
+    return max(w for w, t in times.items() if t <= fastest * (1.0 + tie))
+
+
 def tune(n_mesh, device="cuda", reps=5, box=1000.0, seed=0, log=None):
-    """Measure every fitting width of every pass at mesh size n_mesh and set the fastest as the override.
+    """Measure every fitting width of every pass at mesh size n_mesh and set the fastest (see pick) as the override.
 
     The passes are separate kernels, so round i runs every field at its i-th candidate (the last one repeated when a
     field has fewer) and each field is ranked by its own stages' times: max(len(candidates)) rounds in all.
@@ -92,7 +103,7 @@ def tune(n_mesh, device="cuda", reps=5, box=1000.0, seed=0, log=None):
     except BaseException:
         lpc.lpc_fft_tiling_set(n_mesh, None if saved == base else saved)
         raise
-    best = {f: min(timings[f], key=timings[f].get) for f in FIELDS}
+    best = {f: pick(timings[f]) for f in FIELDS}
     lpc.lpc_fft_tiling_set(n_mesh, best)
     res = {"n_mesh": n_mesh, "tiling": best, "default": base,
            "stage_ms": {f: {str(w): round(v, 4) for w, v in timings[f].items()} for f in FIELDS},

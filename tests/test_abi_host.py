@@ -317,3 +317,14 @@ def test_bispectrum_arguments_and_workspace():
         st = lib.lpc_bispectrum(ctypes.byref(g), args[0], args[1], ctypes.cast(args[2], D), args[3], args[4],
                                 ctypes.cast(out, D), ctypes.cast(out, D), None, fake, 1 << 30, None)
         assert st == -1, args
+
+
+def test_autotune_pick_prefers_the_wider_of_tied_widths():
+    """The tuner's choice from one round of timings: the fastest width, unless a wider one is within 3 % of it."""
+    from paper_1506_03737_amd import autotune
+    assert autotune.pick({8: 0.100, 16: 0.200, 32: 0.300}) == 8
+    assert autotune.pick({4: 0.178, 8: 0.1799, 16: 0.1846}) == 8      # 8 within 1.1 %, 16 at 3.7 %
+    assert autotune.pick({8: 0.0805, 16: 0.0578, 32: 0.058}) == 32     # 16 and 32 tied
+    assert autotune.pick({4: 0.190, 8: 0.092, 16: 0.111}) == 8         # a narrower fastest width still wins
+    assert autotune.pick({8: 1.0}) == 8
+    assert autotune.pick({8: 0.1, 16: 0.1, 32: 0.1}, tie=0.0) == 32
